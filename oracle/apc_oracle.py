@@ -1,0 +1,299 @@
+"""Plain FP64 CPU oracle for Accelerated Projection-based Consensus (APC).
+
+TEST INFRASTRUCTURE ONLY.  This module exists to check the HIP implementation.
+Only the test suite, the smoke check and the CPU-baseline leg of the benchmark
+may import it.  The product path (the C-ABI library and its Python binding)
+never imports, calls or links anything here, and this module imports nothing
+from the product package.
+
+Everything is NumPy in float64, written for clarity rather than speed: one
+Python loop over the row blocks ("machines"), library primitives (QR,
+triangular solve, symmetric eigenvalues, matrix products) as single steps, and
+no fusion or reordering beyond what the paper writes down.
+
+Paper: Azizan-Ruhi, Lahouti, Avestimehr, Hassibi, "Distributed Solution of
+Large-Scale Linear Systems via Accelerated Projection-Based Consensus"
+(arXiv 1708.01413).  Citations below name the section / equation / algorithm.
+
+Readings taken where the paper is silent or ambiguous (each is repeated in the
+design notes):
+  R1 partition   -- the paper assumes m divides N (Sec. 2).  When it does not,
+                    the first (N mod m) blocks get one extra row.
+  R2 init        -- Alg. 1 lets each machine pick any solution of A_i x = b_i;
+                    we take the minimum-norm one A_i^T (A_i A_i^T)^{-1} b_i.
+                    Alg. 1 never initialises x_bar; we take the mean of the
+                    x_i(0).
+  R3 iteration   -- Alg. 1 loops "t = 1 to T" starting from x_i(0); we read it
+                    as T updates, with the trajectory indexed by the number of
+                    updates applied (t = 0 is the initial average).
+  R4 optimum     -- Theorem 1's two equations are symmetric in (gamma, eta);
+                    gamma* is the smaller root (it must satisfy |1-gamma| <= rho,
+                    from the (m-1)n eigenvalues equal to 1-gamma in App. A, and
+                    gamma in [0, 2] from the definition of S, eq. (6)).
+  R5 metric      -- relative l2 error ||x_bar - x*|| / ||x*|| (Sec. 5); with k
+                    right-hand sides, per column, and the maximum over columns.
+  R6 rank        -- a block is rank deficient when min|diag R_i| <=
+                    n * eps * max|diag R_i| (thin QR of A_i^T).
+  R7 singular    -- no unique solution when mu_min <= n * eps (App. A, steady
+                    state: the error vanishes iff mu_min != 0).
+
+Parity note: every function here is pinned by tests that do not reuse its
+arithmetic (definitions written differently, brute force, closed forms, the
+paper's invariants).
+"""
+
+from __future__ import annotations
+
+import numpy as np
+from scipy.linalg import solve_triangular
+
+EPS = np.finfo(np.float64).eps
+
+
+class OracleError(ValueError):
+    """Raised for inputs the method rejects (rank-deficient block, singular X)."""
+
+
+# ----------------------------------------------------------------------------
+# Sec. 2: the row partition [A_i, b_i]
+# ----------------------------------------------------------------------------
+
+def partition(N: int, m: int) -> np.ndarray:
+    """Contiguous row blocks, block i = rows off[i]:off[i+1] (Sec. 2).
+
+    p = N/m when m divides N; otherwise reading R1 (first N mod m blocks get
+    one extra row).
+    """
+    if m < 1 or N < m:
+        raise OracleError("need 1 <= m <= N")
+    base, extra = divmod(N, m)
+    sizes = [base + (1 if i < extra else 0) for i in range(m)]
+    return np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+
+
+def blocks(M: np.ndarray, off: np.ndarray) -> list[np.ndarray]:
+    """Row blocks M_i = M[off[i]:off[i+1]] (Sec. 2)."""
+    return [M[off[i]:off[i + 1]] for i in range(len(off) - 1)]
+
+
+def _as_cols(B: np.ndarray) -> np.ndarray:
+    B = np.asarray(B, dtype=np.float64)
+    return B[:, None] if B.ndim == 1 else B
+
+
+# ----------------------------------------------------------------------------
+# Sec. 3.1: projections
+# ----------------------------------------------------------------------------
+
+def projector(Ai: np.ndarray) -> np.ndarray:
+    """Dense nullspace projector P_i = I - A_i^T (A_i A_i^T)^{-1} A_i (Sec. 3.1).
+
+    Written straight from the definition; used only for small dense checks.
+    """
+    Ai = np.asarray(Ai, dtype=np.float64)
+    n = Ai.shape[1]
+    return np.eye(n) - Ai.T @ np.linalg.solve(Ai @ Ai.T, Ai)
+
+
+def factor(A: np.ndarray, off: np.ndarray):
+    """Thin QR of every A_i^T = Q_i R_i (Sec. 3.3, "e.g. using QR").
+
+    Returns (Qt, R): Qt[i] = Q_i^T (p_i x n, orthonormal rows spanning the row
+    space of A_i) and R[i] (p_i x p_i, upper triangular).  Then
+    P_i v = v - Q_i (Q_i^T v).  Rank check: reading R6.
+    """
+    A = np.asarray(A, dtype=np.float64)
+    n = A.shape[1]
+    Qt, R = [], []
+    for i, Ai in enumerate(blocks(A, off)):
+        if Ai.shape[0] > n:
+            raise OracleError(f"block {i}: p_i > n")
+        Q, Ri = np.linalg.qr(Ai.T, mode="reduced")
+        dg = np.abs(np.diag(Ri))
+        if dg.min() <= n * EPS * dg.max():
+            raise OracleError(f"block {i} is rank deficient")
+        Qt.append(Q.T.copy())
+        R.append(Ri)
+    return Qt, R
+
+
+def project(Qti: np.ndarray, v: np.ndarray) -> np.ndarray:
+    """P_i v = v - Q_i Q_i^T v, the two mat-vecs of Sec. 3.3."""
+    return v - Qti.T @ (Qti @ v)
+
+
+# ----------------------------------------------------------------------------
+# Alg. 1, initialisation
+# ----------------------------------------------------------------------------
+
+def init_local(Qt, R, B: np.ndarray, off: np.ndarray) -> np.ndarray:
+    """x_i(0) = A_i^T (A_i A_i^T)^{-1} b_i for every block (Alg. 1 init, R2).
+
+    With A_i^T = Q_i R_i this is Q_i R_i^{-T} b_i.  Returns (m, n, k).
+    """
+    B = _as_cols(B)
+    xs = []
+    for Qti, Ri, bi in zip(Qt, R, blocks(B, off)):
+        ci = solve_triangular(Ri, bi, trans="T", lower=False)
+        xs.append(Qti.T @ ci)
+    return np.stack(xs)
+
+
+def initial_average(x0: np.ndarray) -> np.ndarray:
+    """x_bar(0) = (1/m) sum_i x_i(0) (reading R2)."""
+    return x0.mean(axis=0)
+
+
+# ----------------------------------------------------------------------------
+# Sec. 3.2: the matrix X and its spectrum; Theorem 1
+# ----------------------------------------------------------------------------
+
+def X_matrix(A: np.ndarray, off: np.ndarray) -> np.ndarray:
+    """X = (1/m) sum_i A_i^T (A_i A_i^T)^{-1} A_i, eq. (3), formed densely."""
+    A = np.asarray(A, dtype=np.float64)
+    m = len(off) - 1
+    X = np.zeros((A.shape[1], A.shape[1]))
+    for Ai in blocks(A, off):
+        X += Ai.T @ np.linalg.solve(Ai @ Ai.T, Ai)
+    return X / m
+
+
+def spectrum(A: np.ndarray, off: np.ndarray):
+    """(mu_min, mu_max) of X, eq. (4); raises for a singular X (reading R7)."""
+    mu = np.linalg.eigvalsh(X_matrix(A, off))
+    n = A.shape[1]
+    if mu[0] <= n * EPS:
+        raise OracleError("mu_min ~ 0: the system has no unique solution")
+    return float(mu[0]), float(mu[-1])
+
+
+def optimal_params(mu_min: float, mu_max: float):
+    """Optimal (gamma*, eta*, rho*) of Theorem 1.
+
+    Theorem 1 fixes gamma, eta by
+        mu_max * eta*gamma = (1 + r)^2,   mu_min * eta*gamma = (1 - r)^2,
+    with r = sqrt((gamma-1)(eta-1)) = rho.  Taking square roots and adding
+    gives s = eta*gamma = 4/(sqrt(mu_max)+sqrt(mu_min))^2; subtracting gives
+    r = (sqrt(mu_max)-sqrt(mu_min))/(sqrt(mu_max)+sqrt(mu_min)), which is
+    (sqrt(kappa)-1)/(sqrt(kappa)+1), eq. (7).  From s and r,
+    gamma + eta = s + 1 - r^2, so gamma and eta are the roots of
+    z^2 - (s + 1 - r^2) z + s = 0; gamma is the smaller root (reading R4).
+    """
+    if not (0.0 < mu_min <= mu_max <= 1.0 + 1e-12):
+        raise OracleError("need 0 < mu_min <= mu_max <= 1")
+    a, c = np.sqrt(mu_max), np.sqrt(mu_min)
+    s = 4.0 / (a + c) ** 2
+    r = (a - c) / (a + c)
+    tr = s + 1.0 - r * r
+    disc = max(tr * tr - 4.0 * s, 0.0)
+    gamma = (tr - np.sqrt(disc)) / 2.0
+    eta = (tr + np.sqrt(disc)) / 2.0
+    return float(gamma), float(eta), float(r)
+
+
+def char_poly_roots(mu: float, gamma: float, eta: float) -> np.ndarray:
+    """Roots of p_i(lambda; gamma, eta), eq. (5)."""
+    b1 = -eta * gamma * (1.0 - mu) + gamma - 1.0 + eta - 1.0
+    b0 = (gamma - 1.0) * (eta - 1.0)
+    return np.roots([1.0, b1, b0])
+
+
+def predicted_rate(mus: np.ndarray, gamma: float, eta: float) -> float:
+    """Spectral radius predicted by App. A: max of |1-gamma| (when m > 1) and
+    the magnitudes of the roots of every p_i, eq. (5)."""
+    rad = abs(1.0 - gamma)
+    for mu in np.atleast_1d(mus):
+        rad = max(rad, float(np.max(np.abs(char_poly_roots(mu, gamma, eta)))))
+    return rad
+
+
+# ----------------------------------------------------------------------------
+# Eq. (2a)-(2b), Alg. 1: the iteration
+# ----------------------------------------------------------------------------
+
+def apc_step(Qt, x: np.ndarray, xbar: np.ndarray, gamma: float, eta: float):
+    """One APC update (eq. (2a) for every block, then eq. (2b)).
+
+    x: (m, n, k) local solutions x_i(t); xbar: (n, k).  Block i computes
+    d = x_bar - x_i, w = Q_i^T d, x_i <- x_i + gamma (d - Q_i w); the master
+    then forms x_bar <- (eta/m) sum_i x_i + (1-eta) x_bar, summing in block
+    order.
+    """
+    m = x.shape[0]
+    xn = np.empty_like(x)
+    for i in range(m):
+        d = xbar - x[i]
+        w = Qt[i] @ d
+        xn[i] = x[i] + gamma * (d - Qt[i].T @ w)
+    acc = np.zeros_like(xbar)
+    for i in range(m):
+        acc = acc + xn[i]
+    xbar_n = (eta / m) * acc + (1.0 - eta) * xbar
+    return xn, xbar_n
+
+
+def rel_error(xbar: np.ndarray, xstar: np.ndarray) -> float:
+    """Relative l2 error ||x_bar - x*|| / ||x*|| (Sec. 5), max over columns (R5)."""
+    xb, xs = _as_cols(xbar), _as_cols(xstar)
+    return float(np.max(np.linalg.norm(xb - xs, axis=0) / np.linalg.norm(xs, axis=0)))
+
+
+def residual(A: np.ndarray, B: np.ndarray, X: np.ndarray) -> float:
+    """||B - A X||_F / ||B||_F, the residual of eq. (1)."""
+    B = _as_cols(B)
+    return float(np.linalg.norm(B - np.asarray(A) @ _as_cols(X)) / np.linalg.norm(B))
+
+
+def apc_run(A, B, off, T: int, gamma: float | None = None, eta: float | None = None,
+            xstar=None, keep_traj: bool = False, keep_state: bool = False):
+    """Algorithm 1: factor, initialise, then T updates (reading R3).
+
+    gamma/eta default to Theorem 1's optimum.  Returns a dict with the
+    parameters, x_bar(T), the relative-error curve err[t] for t = 0..T when
+    x* is given, and optionally the whole x_bar trajectory (T+1, n, k).
+    """
+    A = np.asarray(A, dtype=np.float64)
+    B = _as_cols(B)
+    Qt, R = factor(A, off)
+    x = init_local(Qt, R, B, off)
+    xbar = initial_average(x)
+    out = {}
+    if gamma is None or eta is None:
+        mu_min, mu_max = spectrum(A, off)
+        g, e, rho = optimal_params(mu_min, mu_max)
+        gamma = g if gamma is None else gamma
+        eta = e if eta is None else eta
+        out.update(mu_min=mu_min, mu_max=mu_max, rho=rho)
+    out.update(gamma=gamma, eta=eta)
+    errs, traj = [], []
+    if xstar is not None:
+        errs.append(rel_error(xbar, xstar))
+    if keep_traj:
+        traj.append(xbar.copy())
+    for _ in range(T):
+        x, xbar = apc_step(Qt, x, xbar, gamma, eta)
+        if xstar is not None:
+            errs.append(rel_error(xbar, xstar))
+        if keep_traj:
+            traj.append(xbar.copy())
+    out["xbar"] = xbar
+    out["err"] = np.array(errs)
+    if keep_traj:
+        out["traj"] = np.stack(traj)
+    if keep_state:
+        out["x"] = x
+        out["Qt"] = Qt
+    return out
+
+
+# ----------------------------------------------------------------------------
+# Sec. 4.5: block Cimmino (used only to check Proposition 2)
+# ----------------------------------------------------------------------------
+
+def cimmino_step(A, B, off, xbar: np.ndarray, nu: float) -> np.ndarray:
+    """x_bar <- x_bar + nu sum_i A_i^+ (b_i - A_i x_bar), eqs. (15a)-(15b)."""
+    B = _as_cols(B)
+    upd = np.zeros_like(xbar)
+    for Ai, bi in zip(blocks(np.asarray(A, dtype=np.float64), off), blocks(B, off)):
+        upd = upd + Ai.T @ np.linalg.solve(Ai @ Ai.T, bi - Ai @ xbar)
+    return xbar + nu * upd

@@ -1,0 +1,112 @@
+"""Plant plausible mistakes in the oracle (on the CPU) and check that the pins in
+test_oracle.py catch each one.  This guards the pins themselves: a pin that
+passes on a wrong oracle is no pin."""
+
+import numpy as np
+import pytest
+
+from oracle import apc_oracle as O
+from tests import test_oracle as P
+
+
+def _step_wrong_sign(Qt, x, xbar, gamma, eta):
+    m = x.shape[0]
+    xn = np.empty_like(x)
+    for i in range(m):
+        d = xbar - x[i]
+        xn[i] = x[i] + gamma * (d + Qt[i].T @ (Qt[i] @ d))      # sign of Q Q^T d flipped
+    return xn, (eta / m) * xn.sum(0) + (1 - eta) * xbar
+
+
+def _step_dropped_memory(Qt, x, xbar, gamma, eta):
+    m = x.shape[0]
+    xn = np.empty_like(x)
+    for i in range(m):
+        d = xbar - x[i]
+        xn[i] = x[i] + gamma * (d - Qt[i].T @ (Qt[i] @ d))
+    return xn, (eta / m) * xn.sum(0)                             # (1 - eta) x_bar dropped
+
+
+def _step_stale_average(Qt, x, xbar, gamma, eta):
+    m = x.shape[0]
+    xn = np.empty_like(x)
+    for i in range(m):
+        d = xbar - x[i]
+        xn[i] = x[i] + gamma * (d - Qt[i].T @ (Qt[i] @ d))
+    return xn, (eta / m) * x.sum(0) + (1 - eta) * xbar           # averages x_i(t), not x_i(t+1)
+
+
+def _step_wrong_direction(Qt, x, xbar, gamma, eta):
+    m = x.shape[0]
+    xn = np.empty_like(x)
+    for i in range(m):
+        d = x[i] - xbar                                          # d sign flipped
+        xn[i] = x[i] + gamma * (d - Qt[i].T @ (Qt[i] @ d))
+    return xn, (eta / m) * xn.sum(0) + (1 - eta) * xbar
+
+
+def _params_swapped(mu_min, mu_max):
+    g, e, r = _orig_params(mu_min, mu_max)
+    return e, g, r                                               # gamma/eta roots swapped
+
+
+def _params_plain_kappa(mu_min, mu_max):
+    g, e, r = _orig_params(mu_min, mu_max)
+    k = mu_max / mu_min
+    return g, e, (k - 1) / (k + 1)                               # Cimmino rate instead of APC's
+
+
+def _init_transposed(Qt, R, B, off):
+    from scipy.linalg import solve_triangular
+    B = B[:, None] if B.ndim == 1 else B
+    xs = []
+    for Qti, Ri, bi in zip(Qt, R, O.blocks(B, off)):
+        ci = solve_triangular(Ri, bi, trans="N", lower=False)    # R^{-1} instead of R^{-T}
+        xs.append(Qti.T @ ci)
+    return np.stack(xs)
+
+
+def _X_missing_inverse(A, off):
+    A = np.asarray(A, dtype=np.float64)
+    m = len(off) - 1
+    return sum(Ai.T @ Ai for Ai in O.blocks(A, off)) / m        # (A_i A_i^T)^{-1} dropped
+
+
+_orig_params = O.optimal_params
+
+MUTANTS = [
+    ("apc_step", _step_wrong_sign, ["test_single_update_solves_the_constrained_problem",
+                                    "test_one_step_matches_stacked_error_recursion"]),
+    ("apc_step", _step_dropped_memory, ["test_one_step_matches_stacked_error_recursion",
+                                        "test_gamma_one_is_block_cimmino"]),
+    ("apc_step", _step_stale_average, ["test_one_step_matches_stacked_error_recursion"]),
+    ("apc_step", _step_wrong_direction, ["test_single_update_solves_the_constrained_problem",
+                                         "test_converges_to_direct_solve"]),
+    ("optimal_params", _params_swapped, ["test_optimal_params_satisfy_theorem1",
+                                         "test_stacked_radius_at_optimum_is_rho_star"]),
+    ("optimal_params", _params_plain_kappa, ["test_optimal_params_satisfy_theorem1"]),
+    ("init_local", _init_transposed, ["test_init_is_min_norm_solution"]),
+    ("X_matrix", _X_missing_inverse, ["test_X_matrix_properties"]),
+]
+
+
+def _run_pin(name):
+    fn = getattr(P, name)
+    if name == "test_optimal_params_satisfy_theorem1":
+        for seed in range(5):
+            fn(seed)
+    else:
+        fn()
+
+
+@pytest.mark.parametrize("attr,mutant,pins", MUTANTS,
+                         ids=[f"{a}-{m.__name__}" for a, m, _ in MUTANTS])
+def test_pins_catch_planted_mistake(monkeypatch, attr, mutant, pins):
+    monkeypatch.setattr(O, attr, mutant)
+    caught = 0
+    for name in pins:
+        try:
+            _run_pin(name)
+        except (AssertionError, O.OracleError, np.linalg.LinAlgError):
+            caught += 1
+    assert caught == len(pins), f"{mutant.__name__}: only {caught}/{len(pins)} pins failed"
