@@ -1,0 +1,168 @@
+/*
+ * apc.h -- C ABI of the MI355X (gfx950) Accelerated Projection-based Consensus
+ * solver (Azizan-Ruhi, Lahouti, Avestimehr, Hassibi, arXiv 1708.01413).
+ *
+ * Problem (Sec. 2, eq. (1)): solve A x = b, A in R^{N x n}, N >= n, with a
+ * unique solution.  The rows are split into m contiguous blocks
+ * [A_i, b_i] = rows off[i] .. off[i+1]-1 ("machines", Sec. 2); all m blocks
+ * live on one GPU and are processed as a batch.
+ *
+ * Method (Sec. 3.1, eq. (2a)-(2b), Alg. 1):
+ *     x_i   <- x_i + gamma * P_i (x_bar - x_i),        i = 1..m
+ *     x_bar <- (eta/m) * sum_i x_i + (1 - eta) * x_bar
+ * with P_i = I - A_i^T (A_i A_i^T)^{-1} A_i applied as v - Q_i (Q_i^T v)
+ * from a thin QR A_i^T = Q_i R_i computed once at setup (Sec. 3.3).
+ *
+ * Conventions for every entry point:
+ *   - Matrices are row-major.  "device" pointers point to GPU memory, "host"
+ *     pointers to CPU memory.
+ *   - The library never allocates device memory.  The caller owns A, B, the
+ *     outputs and the workspace; sizes come from apc_workspace_bytes.
+ *   - All GPU work is enqueued on the stream given to apc_setup (a
+ *     hipStream_t passed as void*, NULL = default stream).  Entry points that
+ *     return host values synchronise that stream; they say so below.
+ *   - No C++ exception crosses this boundary.  A non-OK status leaves a
+ *     message for apc_last_error() (thread-local).  Argument errors are
+ *     detected on the host before any GPU work is enqueued.
+ *   - k (number of right-hand sides) must be 1 in this version; B is then a
+ *     length-N vector with stride ldb between consecutive entries.
+ */
+#ifndef APC_H
+#define APC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct apc_plan_s* apc_plan; /* opaque, host-side, owned by the library */
+
+typedef enum {
+  APC_F64 = 0, /* Q_i and all arithmetic in FP64                                  */
+  APC_F32 = 1  /* Q_i stored in FP32, projections (both mat-vecs) in FP32 with     */
+               /* FP32 accumulation; x_i, x_bar and the update/average in FP64     */
+} apc_precision;
+
+typedef enum {
+  APC_OK = 0,
+  APC_EINVAL = 1,       /* invalid argument (sizes, offsets, strides, pointers)     */
+  APC_ERANK = 2,        /* some A_i is not of full row rank (setup QR)              */
+  APC_ESINGULAR = 3,    /* mu_min(X) ~ 0: no unique solution (App. A)               */
+  APC_EDIVERGED = 4,    /* residual became non-finite or grew without bound        */
+  APC_ENOCONV = 5,      /* tolerance not reached within the iteration budget       */
+  APC_ENODEV = 6,       /* no usable GPU                                            */
+  APC_EHIP = 7,         /* a HIP runtime call failed                                */
+  APC_EUNSUPPORTED = 8  /* valid request this version does not implement           */
+} apc_status;
+
+/* Bytes of device workspace apc_setup needs for this problem.
+ * off: host array of m+1 increasing row offsets, off[0] = 0, off[m] = N,
+ * 1 <= off[i+1]-off[i] <= min(n, 2048).  Returns 0 for invalid arguments. */
+size_t apc_workspace_bytes(int64_t N, int64_t n, const int64_t* off, int32_t m, int32_t k,
+                           int32_t precision);
+
+/* Factor every block, initialise the iterates and choose (gamma, eta).
+ *
+ *   A      device, N x n FP64, row stride lda >= n.  Read during setup, and
+ *          again by apc_residual / apc_solve: keep it alive and unchanged
+ *          until apc_destroy.
+ *   B      device, FP64 right-hand side b (k = 1), entry r at B[r * ldb].
+ *          Read during setup and by apc_residual / apc_solve (keep alive).
+ *   off    host, m+1 block offsets as in apc_workspace_bytes (copied).
+ *   gamma, eta  the parameters of eq. (2).  If either is NaN, both are set to
+ *          Theorem 1's optimum from the extreme eigenvalues of
+ *          X = (1/m) sum_i A_i^T (A_i A_i^T)^{-1} A_i (eq. (3)), estimated on
+ *          the GPU in FP64 by Lanczos on X v = (1/m) sum_i Q_i Q_i^T v and
+ *          widened to an interval that encloses the spectrum.
+ *   workspace  device, >= apc_workspace_bytes(...) bytes, 256-byte aligned,
+ *          owned by the caller, used exclusively by this plan until destroy.
+ *
+ * Setup steps (Sec. 3.1, Sec. 3.3, Alg. 1 initialisation): thin QR of each
+ * A_i^T in FP64 (CholeskyQR2), c_i = R_i^{-T} b_i, the minimum-norm local
+ * solutions x_i(0) = Q_i c_i and x_bar(0) = (1/m) sum_i x_i(0).
+ * Synchronises the stream (rank check, eigenvalue estimate).
+ * Errors: APC_EINVAL, APC_ERANK, APC_ESINGULAR, APC_ENOCONV (eigenvalue
+ * estimate did not converge), APC_ENODEV, APC_EHIP.  *out is NULL on error. */
+apc_status apc_setup(apc_plan* out, const double* A, int64_t lda, const double* B, int64_t ldb,
+                     int64_t N, int64_t n, const int64_t* off, int32_t m, int32_t k,
+                     int32_t precision, double gamma, double eta, void* workspace,
+                     size_t ws_bytes, void* stream);
+
+/* Apply T updates of eq. (2a)-(2b) (T >= 0).  Asynchronous: enqueues two
+ * kernels per update (projection pass A: w_i = Q_i^T (x_bar - x_i); pass B:
+ * x_i += gamma (x_bar - x_i - Q_i w_i) with the momentum average fused into
+ * its epilogue) and returns. */
+apc_status apc_iterate(apc_plan p, int32_t T);
+
+/* As apc_iterate, and also measures the two passes with HIP events on the
+ * plan's stream: *ms_pass_a / *ms_pass_b (host) receive the summed durations
+ * of all T pass-A / pass-B launches.  Synchronises the stream. */
+apc_status apc_iterate_timed(apc_plan p, int32_t T, float* ms_pass_a, float* ms_pass_b);
+
+/* Relative residual ||b - A x_bar||_2 / ||b||_2 in FP64 on the GPU (the
+ * solver's convergence monitor).  *relres is host.  Synchronises. */
+apc_status apc_residual(apc_plan p, double* relres);
+
+/* Iterate until apc_residual <= rtol, checking every 8 updates, for at most
+ * max_iters updates; then copy x_bar (n doubles, device, stride ldx >= 1
+ * between entries) to Xbar.  *iters_out, *relres_out are host (may be NULL).
+ * Returns APC_ENOCONV if rtol was not reached (Xbar is still written),
+ * APC_EDIVERGED if the residual became non-finite.  Synchronises. */
+apc_status apc_solve(apc_plan p, double rtol, int32_t max_iters, double* Xbar, int64_t ldx,
+                     int32_t* iters_out, double* relres_out);
+
+/* Copy the master estimate x_bar (n doubles) to device memory Xbar with stride
+ * ldx.  Asynchronous (stream-ordered). */
+apc_status apc_get_xbar(apc_plan p, double* Xbar, int64_t ldx);
+
+/* Copy every local solution x_i (m rows of n doubles, row i at X + i*ldx,
+ * ldx >= n) to device memory.  Asynchronous. */
+apc_status apc_get_local(apc_plan p, double* X, int64_t ldx);
+
+/* Apply every block's FP64 projector to its own row: out_i = P_i v_i =
+ * v_i - Q_i (Q_i^T v_i) (Sec. 3.1), for m device rows of n doubles (stride
+ * ldv >= n for both V and Out; V and Out must not overlap).  Uses the FP64
+ * factor in every precision mode.  Asynchronous. */
+apc_status apc_project(apc_plan p, const double* V, double* Out, int64_t ldv);
+
+/* Host copies of the parameters in use and of the eigenvalue estimate
+ * (mu_min, mu_max, rho are NaN when gamma and eta were given by the caller).
+ * Any pointer may be NULL. */
+apc_status apc_get_params(apc_plan p, double* gamma, double* eta, double* mu_min, double* mu_max,
+                          double* rho);
+
+/* Host-only helper (no GPU needed): Theorem 1's optimal parameters for a
+ * spectrum of X enclosed in [mu_min, mu_max], 0 < mu_min <= mu_max <= 1.
+ * gamma* is the smaller of the two roots (it must satisfy |1 - gamma| <= rho
+ * because of the (m-1)n eigenvalues 1 - gamma of the error recursion, App. A);
+ * rho* = (sqrt(kappa) - 1)/(sqrt(kappa) + 1), eq. (7).  Outputs are host
+ * pointers (any may be NULL).  APC_EINVAL for an invalid interval. */
+apc_status apc_optimal_params(double mu_min, double mu_max, double* gamma, double* eta,
+                              double* rho);
+
+/* Host-only helper used by the eigenvalue estimate: extreme eigenvalues of
+ * the k x k symmetric tridiagonal matrix with diagonal alpha[0..k-1] and
+ * off-diagonal beta[0..k-2] (bisection on Sturm counts), and the Lanczos
+ * residual bounds |beta[k-1] * s_k| of the two extreme Ritz pairs (s = unit
+ * eigenvector; beta[k-1] is read only when with_bounds != 0).  Host pointers.
+ * APC_EINVAL when k < 1 or a pointer is NULL. */
+apc_status apc_tridiag_extremes(const double* alpha, const double* beta, int32_t k,
+                                int32_t with_bounds, double* lo, double* hi, double* bound_lo,
+                                double* bound_hi);
+
+/* Number of updates applied since setup (host). */
+int64_t apc_iterations(apc_plan p);
+
+/* Release the host-side plan.  Does not touch the caller's device memory. */
+void apc_destroy(apc_plan p);
+
+/* Message describing the last non-OK status returned on this thread. */
+const char* apc_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* APC_H */

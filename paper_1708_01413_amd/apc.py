@@ -1,0 +1,283 @@
+"""Thin Python binding of libapc (``include/apc.h``).
+
+Argument marshalling only: every step of the solver runs in the HIP kernels of
+``libapc.so``.  PyTorch supplies device memory and the stream; this module
+passes raw pointers through ctypes.  Importing it fails loudly when the
+library has not been built.
+
+The functions ``apc_workspace_bytes``, ``apc_setup``, ``apc_iterate``, ... carry
+the names and argument order of the C ABI.  ``Plan`` wraps them for torch
+tensors.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libapc.so")
+
+APC_F64, APC_F32 = 0, 1
+PRECISIONS = {"f64": APC_F64, "f32": APC_F32}
+
+STATUS_NAMES = {
+    0: "APC_OK", 1: "APC_EINVAL", 2: "APC_ERANK", 3: "APC_ESINGULAR", 4: "APC_EDIVERGED",
+    5: "APC_ENOCONV", 6: "APC_ENODEV", 7: "APC_EHIP", 8: "APC_EUNSUPPORTED",
+}
+APC_OK, APC_EINVAL, APC_ERANK, APC_ESINGULAR, APC_EDIVERGED, APC_ENOCONV, APC_ENODEV, \
+    APC_EHIP, APC_EUNSUPPORTED = range(9)
+
+EXPORTED = (
+    "apc_workspace_bytes", "apc_setup", "apc_iterate", "apc_iterate_timed", "apc_residual",
+    "apc_solve", "apc_get_xbar", "apc_get_local", "apc_project", "apc_get_params",
+    "apc_iterations", "apc_destroy", "apc_last_error", "apc_optimal_params",
+    "apc_tridiag_extremes",
+)
+
+
+class ApcError(RuntimeError):
+    """A non-OK status from libapc."""
+
+    def __init__(self, status: int, message: str):
+        self.status = status
+        self.name = STATUS_NAMES.get(status, str(status))
+        super().__init__(f"{self.name}: {message}")
+
+
+def _load() -> ctypes.CDLL:
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                          "(hipcc --offload-arch=gfx950); there is no fallback path")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, i64, i32, f64 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_double
+    P64 = ctypes.POINTER(ctypes.c_int64)
+    Pd = ctypes.POINTER(ctypes.c_double)
+    Pf = ctypes.POINTER(ctypes.c_float)
+    Pi = ctypes.POINTER(ctypes.c_int32)
+    sig = {
+        "apc_workspace_bytes": (ctypes.c_size_t, [i64, i64, P64, i32, i32, i32]),
+        "apc_setup": (i32, [ctypes.POINTER(vp), vp, i64, vp, i64, i64, i64, P64, i32, i32, i32,
+                            f64, f64, vp, ctypes.c_size_t, vp]),
+        "apc_iterate": (i32, [vp, i32]),
+        "apc_iterate_timed": (i32, [vp, i32, Pf, Pf]),
+        "apc_residual": (i32, [vp, Pd]),
+        "apc_solve": (i32, [vp, f64, i32, vp, i64, Pi, Pd]),
+        "apc_get_xbar": (i32, [vp, vp, i64]),
+        "apc_get_local": (i32, [vp, vp, i64]),
+        "apc_project": (i32, [vp, vp, vp, i64]),
+        "apc_get_params": (i32, [vp, Pd, Pd, Pd, Pd, Pd]),
+        "apc_iterations": (i64, [vp]),
+        "apc_optimal_params": (i32, [f64, f64, Pd, Pd, Pd]),
+        "apc_tridiag_extremes": (i32, [Pd, Pd, i32, i32, Pd, Pd, Pd, Pd]),
+        "apc_destroy": (None, [vp]),
+        "apc_last_error": (ctypes.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    return lib
+
+
+lib = _load()
+
+
+def _check(status: int):
+    if status != APC_OK:
+        raise ApcError(status, lib.apc_last_error().decode(errors="replace"))
+
+
+def _off_array(off) -> ctypes.Array:
+    off = np.ascontiguousarray(np.asarray(off, dtype=np.int64))
+    return (ctypes.c_int64 * len(off))(*off.tolist())
+
+
+# ---------------------------------------------------------------- C-named calls
+
+
+def apc_workspace_bytes(N: int, n: int, off, m: int, k: int = 1, precision: int = APC_F64) -> int:
+    return int(lib.apc_workspace_bytes(N, n, _off_array(off), m, k, precision))
+
+
+def apc_setup(A: int, lda: int, B: int, ldb: int, N: int, n: int, off, m: int, k: int,
+              precision: int, gamma: float, eta: float, workspace: int, ws_bytes: int,
+              stream: int) -> ctypes.c_void_p:
+    h = ctypes.c_void_p()
+    _check(lib.apc_setup(ctypes.byref(h), A, lda, B, ldb, N, n, _off_array(off), m, k,
+                         precision, gamma, eta, workspace, ws_bytes, stream))
+    return h
+
+
+def apc_iterate(plan, T: int):
+    _check(lib.apc_iterate(plan, T))
+
+
+def apc_iterate_timed(plan, T: int):
+    a, b = ctypes.c_float(), ctypes.c_float()
+    _check(lib.apc_iterate_timed(plan, T, ctypes.byref(a), ctypes.byref(b)))
+    return a.value, b.value
+
+
+def apc_residual(plan) -> float:
+    r = ctypes.c_double()
+    _check(lib.apc_residual(plan, ctypes.byref(r)))
+    return r.value
+
+
+def apc_solve(plan, rtol: float, max_iters: int, Xbar: int, ldx: int = 1):
+    it, rr = ctypes.c_int32(), ctypes.c_double()
+    st = lib.apc_solve(plan, rtol, max_iters, Xbar, ldx, ctypes.byref(it), ctypes.byref(rr))
+    return st, it.value, rr.value
+
+
+def apc_get_xbar(plan, Xbar: int, ldx: int = 1):
+    _check(lib.apc_get_xbar(plan, Xbar, ldx))
+
+
+def apc_get_local(plan, X: int, ldx: int):
+    _check(lib.apc_get_local(plan, X, ldx))
+
+
+def apc_project(plan, V: int, Out: int, ldv: int):
+    _check(lib.apc_project(plan, V, Out, ldv))
+
+
+def apc_get_params(plan) -> dict:
+    vals = [ctypes.c_double() for _ in range(5)]
+    _check(lib.apc_get_params(plan, *[ctypes.byref(v) for v in vals]))
+    return dict(zip(("gamma", "eta", "mu_min", "mu_max", "rho"), (v.value for v in vals)))
+
+
+def apc_iterations(plan) -> int:
+    return int(lib.apc_iterations(plan))
+
+
+def apc_optimal_params(mu_min: float, mu_max: float):
+    g, e, r = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+    _check(lib.apc_optimal_params(mu_min, mu_max, ctypes.byref(g), ctypes.byref(e), ctypes.byref(r)))
+    return g.value, e.value, r.value
+
+
+def apc_tridiag_extremes(alpha, beta, with_bounds: bool = False):
+    a = np.ascontiguousarray(np.asarray(alpha, dtype=np.float64))
+    b = np.ascontiguousarray(np.asarray(beta, dtype=np.float64))
+    k = len(a)
+    if len(b) < (k if with_bounds else k - 1):
+        raise ValueError("beta too short")
+    if len(b) == 0:
+        b = np.zeros(1)
+    Pd = ctypes.POINTER(ctypes.c_double)
+    out = [ctypes.c_double() for _ in range(4)]
+    _check(lib.apc_tridiag_extremes(a.ctypes.data_as(Pd), b.ctypes.data_as(Pd), k,
+                                    1 if with_bounds else 0, *[ctypes.byref(v) for v in out]))
+    return tuple(v.value for v in out)
+
+
+def apc_destroy(plan):
+    lib.apc_destroy(plan)
+
+
+def apc_last_error() -> str:
+    return lib.apc_last_error().decode(errors="replace")
+
+
+# ---------------------------------------------------------------- torch wrapper
+
+
+class Plan:
+    """An APC solver instance on one GPU.
+
+    A: (N, n) float64 CUDA tensor (row stride may exceed n); b: (N,) float64
+    CUDA tensor; off: m+1 block offsets.  gamma/eta None selects Theorem 1's
+    optimum.  The plan keeps references to A, b and its workspace.
+    """
+
+    def __init__(self, A, b, off, precision: str = "f64", gamma=None, eta=None, stream=None):
+        import torch
+
+        if A.dtype != torch.float64 or b.dtype != torch.float64:
+            raise TypeError("A and b must be float64")
+        if not (A.is_cuda and b.is_cuda):
+            raise TypeError("A and b must be device tensors")
+        if A.dim() != 2 or A.stride(1) != 1:
+            raise ValueError("A must be a row-major matrix")
+        if b.dim() != 1:
+            raise ValueError("b must be a vector (k = 1)")
+        self._torch = torch
+        self.device = A.device
+        self.N, self.n = A.shape
+        self.off = np.asarray(off, dtype=np.int64)
+        self.m = len(self.off) - 1
+        self.precision = PRECISIONS[precision]
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        ws = apc_workspace_bytes(self.N, self.n, self.off, self.m, 1, self.precision)
+        if ws == 0:
+            raise ApcError(APC_EINVAL, apc_last_error())
+        self.ws_bytes = ws
+        self.workspace = torch.empty(ws + 256, dtype=torch.uint8, device=self.device)
+        base = self.workspace.data_ptr()
+        self._ws_ptr = (base + 255) // 256 * 256
+        self.A, self.b = A, b
+        g = math.nan if gamma is None else float(gamma)
+        e = math.nan if eta is None else float(eta)
+        self.handle = apc_setup(A.data_ptr(), A.stride(0), b.data_ptr(), b.stride(0), self.N,
+                                self.n, self.off, self.m, 1, self.precision, g, e, self._ws_ptr,
+                                ws, self.stream.cuda_stream)
+
+    # -- iteration
+    def iterate(self, T: int):
+        apc_iterate(self.handle, T)
+
+    def iterate_timed(self, T: int):
+        return apc_iterate_timed(self.handle, T)
+
+    def residual(self) -> float:
+        return apc_residual(self.handle)
+
+    def solve(self, rtol: float, max_iters: int):
+        x = self._torch.empty(self.n, dtype=self._torch.float64, device=self.device)
+        st, it, rr = apc_solve(self.handle, rtol, max_iters, x.data_ptr(), 1)
+        if st not in (APC_OK, APC_ENOCONV):
+            _check(st)
+        return x, it, rr, st
+
+    # -- state access
+    def xbar(self):
+        x = self._torch.empty(self.n, dtype=self._torch.float64, device=self.device)
+        apc_get_xbar(self.handle, x.data_ptr(), 1)
+        return x
+
+    def local(self):
+        X = self._torch.empty((self.m, self.n), dtype=self._torch.float64, device=self.device)
+        apc_get_local(self.handle, X.data_ptr(), self.n)
+        return X
+
+    def project(self, V):
+        if V.shape != (self.m, self.n) or V.dtype != self._torch.float64 or not V.is_contiguous():
+            raise ValueError("V must be a contiguous (m, n) float64 tensor")
+        out = self._torch.empty_like(V)
+        apc_project(self.handle, V.data_ptr(), out.data_ptr(), self.n)
+        return out
+
+    def params(self) -> dict:
+        return apc_get_params(self.handle)
+
+    @property
+    def iterations(self) -> int:
+        return apc_iterations(self.handle)
+
+    def close(self):
+        if getattr(self, "handle", None) is not None:
+            self.stream.synchronize()
+            apc_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

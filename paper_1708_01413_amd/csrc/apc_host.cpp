@@ -1,0 +1,755 @@
+// Host side of libapc: argument validation, workspace layout, setup and
+// iteration orchestration, the Lanczos eigenvalue estimate and the C ABI.
+//
+// The library never allocates device memory: every device buffer is a slice
+// of the caller's workspace.  The plan itself is a small host object.
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <limits>
+#include <string>
+#include <vector>
+
+#include "apc.h"
+#include "apc_internal.h"
+
+using namespace apc;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+apc_status fail(apc_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return st;
+}
+
+#define HIP_TRY(expr)                                                                     \
+  do {                                                                                    \
+    hipError_t e_ = (expr);                                                               \
+    if (e_ != hipSuccess)                                                                 \
+      return fail(APC_EHIP, "%s failed: %s (%s:%d)", #expr, hipGetErrorString(e_), __FILE__, \
+                  __LINE__);                                                              \
+  } while (0)
+
+constexpr int64_t kAlign = 256;
+constexpr int kLanczosMax = 1024;   // Lanczos steps cap (full reorthogonalisation)
+constexpr int kLanczosCheck = 8;    // steps between convergence checks (host syncs)
+
+int64_t round_up(int64_t v, int64_t a) { return (v + a - 1) / a * a; }
+
+// ------------------------------------------------------------------ layout
+
+struct Layout {
+  int64_t ldc = 0, kmax = 0, S = 0;
+  int32_t ntiles_a = 0, ntiles_g = 0, ntiles_t = 0, nslab = 0, nparts = 0;
+  size_t C64a, C64b, C32, x, xbar, w, ca, cb, Y, vtmp, V, h, h2, alpha, beta, G, Linv, counters,
+      flags, scal, partial, tiles_a, tiles_g, tiles_t, doff, goff, total;
+};
+
+struct Tiles {
+  std::vector<int32_t> a_row0, a_nrows, a_blk;  // pass-A row tiles, aligned to block starts
+  std::vector<int32_t> g;                        // Gram tiles (blk, ta, tb), ta >= tb
+  std::vector<int32_t> t;                        // TRMM tiles (blk, ta, tc)
+  std::vector<int64_t> goff;                     // offset of G_i in the packed Gram storage
+};
+
+void build_tiles(const int64_t* off, int32_t m, int64_t ldc, Tiles* T) {
+  int64_t g = 0;
+  const int64_t ctiles = (ldc + kGramTile - 1) / kGramTile;
+  for (int i = 0; i < m; ++i) {
+    const int64_t p = off[i + 1] - off[i];
+    for (int64_t r = 0; r < p; r += kRowTile) {
+      T->a_row0.push_back(static_cast<int32_t>(off[i] + r));
+      T->a_nrows.push_back(static_cast<int32_t>(std::min<int64_t>(kRowTile, p - r)));
+      T->a_blk.push_back(i);
+    }
+    const int64_t pt = (p + kGramTile - 1) / kGramTile;
+    for (int64_t a = 0; a < pt; ++a) {
+      for (int64_t b = 0; b <= a; ++b) {
+        T->g.push_back(i);
+        T->g.push_back(static_cast<int32_t>(a));
+        T->g.push_back(static_cast<int32_t>(b));
+      }
+      for (int64_t c = 0; c < ctiles; ++c) {
+        T->t.push_back(i);
+        T->t.push_back(static_cast<int32_t>(a));
+        T->t.push_back(static_cast<int32_t>(c));
+      }
+    }
+    T->goff.push_back(g);
+    g += p * p;
+  }
+}
+
+Layout make_layout(int64_t N, int64_t n, const int64_t* off, int32_t m, int32_t prec,
+                   const Tiles& T) {
+  Layout L;
+  L.ldc = round_up(n, kLdAlign);
+  L.kmax = std::min<int64_t>(n, kLanczosMax);
+  for (int i = 0; i < m; ++i) L.S += (off[i + 1] - off[i]) * (off[i + 1] - off[i]);
+  L.ntiles_a = static_cast<int32_t>(T.a_row0.size());
+  L.ntiles_g = static_cast<int32_t>(T.g.size() / 3);
+  L.ntiles_t = static_cast<int32_t>(T.t.size() / 3);
+  L.nslab = static_cast<int32_t>((L.ldc + 127) / 128);  // enough for both slab widths
+  L.nparts = residual_parts(N);
+  size_t cur = 0;
+  auto take = [&](int64_t bytes) {
+    const size_t at = cur;
+    cur += static_cast<size_t>(round_up(std::max<int64_t>(bytes, 1), kAlign));
+    return at;
+  };
+  const int64_t d = sizeof(double);
+  L.C64a = take(N * L.ldc * d);
+  L.C64b = take(N * L.ldc * d);
+  L.C32 = take(prec == APC_F32 ? N * L.ldc * 4 : 0);
+  L.x = take(m * L.ldc * d);
+  L.xbar = take(L.ldc * d);
+  L.w = take(N * d);
+  L.ca = take(N * d);
+  L.cb = take(N * d);
+  L.Y = take(m * L.ldc * d);
+  L.vtmp = take(L.ldc * d);
+  L.V = take((L.kmax + 1) * L.ldc * d);
+  L.h = take((L.kmax + 1) * d);
+  L.h2 = take((L.kmax + 1) * d);
+  L.alpha = take((L.kmax + 1) * d);
+  L.beta = take((L.kmax + 1) * d);
+  L.G = take(L.S * d);
+  L.Linv = take(L.S * d);
+  L.counters = take(L.nslab * 4);
+  L.flags = take(4 * 4);
+  L.scal = take(8 * d);
+  L.partial = take(L.nparts * d);
+  L.tiles_a = take(3 * static_cast<int64_t>(L.ntiles_a) * 4);
+  L.tiles_g = take(3 * static_cast<int64_t>(L.ntiles_g) * 4);
+  L.tiles_t = take(3 * static_cast<int64_t>(L.ntiles_t) * 4);
+  L.doff = take((m + 1) * 8);
+  L.goff = take(m * 8);
+  L.total = cur;
+  return L;
+}
+
+apc_status validate(int64_t N, int64_t n, const int64_t* off, int32_t m, int32_t k,
+                    int32_t prec) {
+  if (n < 1 || N < n) return fail(APC_EINVAL, "need N >= n >= 1 (got N=%lld n=%lld)", (long long)N, (long long)n);
+  if (m < 1 || m > N) return fail(APC_EINVAL, "need 1 <= m <= N (got m=%d)", m);
+  if (!off) return fail(APC_EINVAL, "off is NULL");
+  if (k != 1) return fail(APC_EUNSUPPORTED, "only k = 1 right-hand side is supported (got %d)", k);
+  if (prec != APC_F64 && prec != APC_F32) return fail(APC_EINVAL, "unknown precision %d", prec);
+  if (off[0] != 0 || off[m] != N) return fail(APC_EINVAL, "off[0] must be 0 and off[m] must be N");
+  const int64_t pmax = std::min<int64_t>(n, kMaxBlockRows);
+  for (int i = 0; i < m; ++i) {
+    const int64_t p = off[i + 1] - off[i];
+    if (p < 1) return fail(APC_EINVAL, "block %d is empty or offsets decrease", i);
+    if (p > n) return fail(APC_EINVAL, "block %d has p_i=%lld > n=%lld rows", i, (long long)p, (long long)n);
+    if (p > pmax) return fail(APC_EUNSUPPORTED, "block %d has p_i=%lld > %d rows", i, (long long)p, kMaxBlockRows);
+  }
+  if (N > std::numeric_limits<int32_t>::max() / 2) return fail(APC_EINVAL, "N too large");
+  return APC_OK;
+}
+
+// ------------------------------------------------------------------ tridiagonal eigen
+
+// Number of eigenvalues of the symmetric tridiagonal (a, b) smaller than x.
+int sturm_count(const std::vector<double>& a, const std::vector<double>& b, int k, double x) {
+  int cnt = 0;
+  double q = a[0] - x;
+  if (q < 0) ++cnt;
+  for (int i = 1; i < k; ++i) {
+    if (q == 0.0) q = std::numeric_limits<double>::min();
+    q = a[i] - x - b[i - 1] * b[i - 1] / q;
+    if (q < 0) ++cnt;
+  }
+  return cnt;
+}
+
+// The idx-th smallest eigenvalue (0-based) by bisection on the Sturm count.
+double tridiag_eig(const std::vector<double>& a, const std::vector<double>& b, int k, int idx) {
+  double lo = a[0], hi = a[0];
+  for (int i = 0; i < k; ++i) {
+    const double r = (i > 0 ? std::fabs(b[i - 1]) : 0.0) + (i + 1 < k ? std::fabs(b[i]) : 0.0);
+    lo = std::min(lo, a[i] - r);
+    hi = std::max(hi, a[i] + r);
+  }
+  for (int it = 0; it < 200; ++it) {
+    const double mid = 0.5 * (lo + hi);
+    if (mid <= lo || mid >= hi) break;
+    if (sturm_count(a, b, k, mid) > idx) hi = mid; else lo = mid;
+  }
+  return 0.5 * (lo + hi);
+}
+
+// Last component of the unit eigenvector of T for an extreme eigenvalue theta,
+// by inverse iteration with a shift just outside the spectrum (the shifted
+// matrix is definite, so elimination without pivoting is stable).
+double last_component(const std::vector<double>& a, const std::vector<double>& b, int k,
+                      double theta, bool top) {
+  const double scale = std::max(std::fabs(theta), 1e-300);
+  const double sigma = top ? theta + 1e-12 * scale + 1e-300 : theta - 1e-12 * scale - 1e-300;
+  std::vector<double> s(k, 1.0 / std::sqrt(static_cast<double>(k))), dd(k), rr(k);
+  for (int it = 0; it < 4; ++it) {
+    // Thomas algorithm on (T - sigma I) z = s.
+    dd[0] = a[0] - sigma;
+    rr[0] = s[0];
+    for (int i = 1; i < k; ++i) {
+      const double l = b[i - 1] / dd[i - 1];
+      dd[i] = a[i] - sigma - l * b[i - 1];
+      rr[i] = s[i] - l * rr[i - 1];
+    }
+    s[k - 1] = rr[k - 1] / dd[k - 1];
+    for (int i = k - 2; i >= 0; --i) s[i] = (rr[i] - b[i] * s[i + 1]) / dd[i];
+    double nrm = 0.0;
+    for (int i = 0; i < k; ++i) nrm += s[i] * s[i];
+    nrm = std::sqrt(nrm);
+    if (!(nrm > 0.0) || !std::isfinite(nrm)) return 1.0;  // unusable: report a loose bound
+    for (int i = 0; i < k; ++i) s[i] /= nrm;
+  }
+  return s[k - 1];
+}
+
+// Theorem 1's optimum for a spectrum enclosed in [lo, hi].  With
+// s = eta*gamma = 4/(sqrt(hi)+sqrt(lo))^2 and rho = (sqrt(hi)-sqrt(lo))/
+// (sqrt(hi)+sqrt(lo)), u = gamma-1 and v = eta-1 satisfy u v = rho^2 and
+// u + v = s - 1 - rho^2; u is the smaller root, formed without cancellation.
+void optimum(double lo, double hi, double* gamma, double* eta, double* rho) {
+  const double a = std::sqrt(hi), c = std::sqrt(lo);
+  const double r = (a - c) / (a + c);
+  const double s = 4.0 / ((a + c) * (a + c));
+  const double sum = s - 1.0 - r * r;  // u + v >= 2 r >= 0
+  const double disc = std::sqrt(std::max(sum * sum - 4.0 * r * r, 0.0));
+  const double v = 0.5 * (sum + disc);
+  const double u = v > 0.0 ? (r * r) / v : 0.0;
+  *gamma = 1.0 + u;
+  *eta = 1.0 + v;
+  *rho = r;
+}
+
+uint64_t splitmix64(uint64_t x) {
+  x += 0x9E3779B97F4A7C15ull;
+  x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ull;
+  x = (x ^ (x >> 27)) * 0x94D049BB133111EBull;
+  return x ^ (x >> 31);
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ the plan
+
+struct apc_plan_s {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  int64_t N = 0, n = 0;
+  int32_t m = 0, k = 1, prec = APC_F64;
+  std::vector<int64_t> off;
+  Layout L;
+  char* ws = nullptr;
+  const double* A = nullptr;
+  int64_t lda = 0;
+  const double* B = nullptr;
+  int64_t ldb = 0;
+  double gamma = 0, eta = 0;
+  double mu_min = NAN, mu_max = NAN, rho = NAN;
+  int64_t iters = 0;
+  double bnorm = 0;
+  int32_t xcd_remap = 1, passb_order = 0;
+  hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
+
+  template <typename T>
+  T* at(size_t o) const { return reinterpret_cast<T*>(ws + o); }
+  double* C64() const { return at<double>(L.C64a); }
+  double* x() const { return at<double>(L.x); }
+  double* xbar() const { return at<double>(L.xbar); }
+  int64_t* doff() const { return at<int64_t>(L.doff); }
+  int32_t* ta(int which) const { return at<int32_t>(L.tiles_a) + which * L.ntiles_a; }
+};
+
+namespace {
+
+apc_status pass_a(apc_plan_s* P, const double* va, const double* vb, int64_t ldvb) {
+  if (P->prec == APC_F32) {
+    RowdotArgs<float> a{P->at<float>(P->L.C32), P->L.ldc, P->ta(0), P->ta(1), P->ta(2),
+                        P->L.ntiles_a, 0, va, vb, ldvb, P->at<float>(P->L.w), P->xcd_remap};
+    HIP_TRY(launch_rowdot_f32(a, P->stream));
+  } else {
+    RowdotArgs<double> a{P->C64(), P->L.ldc, P->ta(0), P->ta(1), P->ta(2), P->L.ntiles_a, 0, va,
+                         vb, ldvb, P->at<double>(P->L.w), P->xcd_remap};
+    HIP_TRY(launch_rowdot_f64(a, P->stream));
+  }
+  return APC_OK;
+}
+
+apc_status pass_b(apc_plan_s* P) {
+  if (P->prec == APC_F32) {
+    const int32_t nslab = static_cast<int32_t>((P->L.ldc + 255) / 256);
+    PassBArgs<float> a{P->at<float>(P->L.C32), P->L.ldc, P->doff(), P->m, nslab,
+                       P->at<float>(P->L.w), P->x(), P->L.ldc, P->xbar(), P->gamma, P->eta,
+                       P->at<unsigned>(P->L.counters), P->passb_order};
+    HIP_TRY(launch_pass_b_f32(a, P->stream));
+  } else {
+    const int32_t nslab = static_cast<int32_t>((P->L.ldc + 127) / 128);
+    PassBArgs<double> a{P->C64(), P->L.ldc, P->doff(), P->m, nslab, P->at<double>(P->L.w),
+                        P->x(), P->L.ldc, P->xbar(), P->gamma, P->eta,
+                        P->at<unsigned>(P->L.counters), P->passb_order};
+    HIP_TRY(launch_pass_b_f64(a, P->stream));
+  }
+  return APC_OK;
+}
+
+// y_i = alpha * Q_i w_i + beta * y_i over all blocks of the FP64 factor.
+apc_status expand_blocks(apc_plan_s* P, const double* w, double* y, double alpha, double beta) {
+  ExpandArgs e{P->C64(), P->L.ldc, P->doff(), P->m, static_cast<int32_t>((P->L.ldc + 127) / 128),
+               P->N, w, y, P->L.ldc, alpha, beta};
+  HIP_TRY(launch_expand(e, P->stream));
+  return APC_OK;
+}
+
+// FP64 u = C v (all rows), uniform or block tiling.
+apc_status rowdot64(apc_plan_s* P, const double* C, int32_t rows, const double* va,
+                    const double* vb, int64_t ldvb, bool block_tiles, double* out) {
+  RowdotArgs<double> a{};
+  a.C = C;
+  a.ldc = P->L.ldc;
+  if (block_tiles) {
+    a.tile_row0 = P->ta(0);
+    a.tile_nrows = P->ta(1);
+    a.tile_blk = P->ta(2);
+    a.ntiles = P->L.ntiles_a;
+  } else {
+    a.ntiles = (rows + kRowTile - 1) / kRowTile;
+    a.rows_total = rows;
+  }
+  a.va = va;
+  a.vb = vb;
+  a.ldvb = ldvb;
+  a.out = out;
+  a.xcd_remap = 0;
+  HIP_TRY(launch_rowdot_f64(a, P->stream));
+  return APC_OK;
+}
+
+#define ST_TRY(expr)              \
+  do {                            \
+    apc_status s_ = (expr);       \
+    if (s_ != APC_OK) return s_;  \
+  } while (0)
+
+// Lanczos with full (twice classical Gram-Schmidt) reorthogonalisation on
+// X v = (1/m) sum_i Q_i (Q_i^T v), in FP64 on the GPU.  Returns an interval
+// [lo, hi] that encloses the spectrum of X up to the Ritz residual bounds.
+apc_status lanczos(apc_plan_s* P, double* lo_out, double* hi_out, double* theta_lo,
+                   double* theta_hi) {
+  const int64_t ldc = P->L.ldc, n = P->n;
+  const int kmax = static_cast<int>(P->L.kmax);
+  double* V = P->at<double>(P->L.V);
+  double* vt = P->at<double>(P->L.vtmp);
+  double* Y = P->at<double>(P->L.Y);
+  double* u = P->at<double>(P->L.w);
+  double* h = P->at<double>(P->L.h);
+  double* h2 = P->at<double>(P->L.h2);
+  double* al = P->at<double>(P->L.alpha);
+  double* be = P->at<double>(P->L.beta);
+
+  std::vector<double> v0(ldc, 0.0);
+  double nrm = 0.0;
+  for (int64_t j = 0; j < n; ++j) {
+    const uint64_t r = splitmix64(0x5eedull * 1000003ull + static_cast<uint64_t>(j));
+    v0[j] = (static_cast<double>(r >> 11) * (1.0 / 9007199254740992.0)) - 0.5;
+    nrm += v0[j] * v0[j];
+  }
+  nrm = std::sqrt(nrm);
+  for (int64_t j = 0; j < n; ++j) v0[j] /= nrm;
+  HIP_TRY(hipMemcpyAsync(V, v0.data(), ldc * sizeof(double), hipMemcpyHostToDevice, P->stream));
+  HIP_TRY(hipStreamSynchronize(P->stream));
+
+  const int32_t nslab = static_cast<int32_t>((ldc + 127) / 128);
+  std::vector<double> a, b;
+  double th_lo = 0, th_hi = 0, bd_lo = INFINITY, bd_hi = INFINITY;
+  bool done = false;
+  for (int j = 0; j < kmax && !done; ++j) {
+    double* vj = V + static_cast<int64_t>(j) * ldc;
+    ST_TRY(rowdot64(P, P->C64(), static_cast<int32_t>(P->N), vj, nullptr, 0, true, u));
+    ST_TRY(expand_blocks(P, u, Y, 1.0, 0.0));
+    HIP_TRY(launch_block_sum(Y, ldc, P->m, ldc, 1.0 / P->m, vt, P->stream));
+    for (int pass = 0; pass < 2; ++pass) {
+      double* hh = pass == 0 ? h : h2;
+      ST_TRY(rowdot64(P, V, j + 1, vt, nullptr, 0, false, hh));
+      ExpandArgs e{V, ldc, nullptr, 1, nslab, j + 1, hh, vt, 0, -1.0, 1.0};
+      HIP_TRY(launch_expand(e, P->stream));
+    }
+    HIP_TRY(launch_lanczos_normalize(vt, ldc, h, h2, j, al, be, V + static_cast<int64_t>(j + 1) * ldc,
+                                     P->stream));
+    const int k = j + 1;
+    if (k % kLanczosCheck != 0 && k != kmax) continue;
+    a.resize(k);
+    b.resize(k);
+    HIP_TRY(hipMemcpyAsync(a.data(), al, k * sizeof(double), hipMemcpyDeviceToHost, P->stream));
+    HIP_TRY(hipMemcpyAsync(b.data(), be, k * sizeof(double), hipMemcpyDeviceToHost, P->stream));
+    HIP_TRY(hipStreamSynchronize(P->stream));
+    for (int i = 0; i < k; ++i)
+      if (!std::isfinite(a[i]) || !std::isfinite(b[i]))
+        return fail(APC_EDIVERGED, "non-finite value in the Lanczos recurrence");
+    // A (numerically) zero beta_i means the Krylov space became invariant at
+    // step i+1: T's leading block then holds exact eigenvalues of X, and with
+    // a generic start vector it holds every distinct one.
+    double scale = 0.0;
+    for (int i = 0; i < k; ++i) scale = std::max(scale, std::fabs(a[i]));
+    int kk = k;
+    for (int i = 0; i < k; ++i)
+      if (b[i] <= 1e-13 * scale) { kk = i + 1; break; }
+    th_lo = tridiag_eig(a, b, kk, 0);
+    th_hi = tridiag_eig(a, b, kk, kk - 1);
+    const double bk = b[kk - 1];
+    bd_hi = std::fabs(bk * last_component(a, b, kk, th_hi, true));
+    bd_lo = std::fabs(bk * last_component(a, b, kk, th_lo, false));
+    const bool exhausted = (kk < k) || (k == n) || (bk <= 1e-13 * std::max(th_hi, 1e-300));
+    if (exhausted) {
+      bd_lo = std::min(bd_lo, 1e-13 * th_hi);
+      bd_hi = std::min(bd_hi, 1e-13 * th_hi);
+    }
+    const bool hi_ok = bd_hi <= 1e-12 * th_hi;
+    const bool lo_ok = bd_lo <= 1e-6 * th_lo || bd_lo <= 1e-14 * th_hi;
+    done = exhausted || (hi_ok && lo_ok);
+  }
+  *theta_lo = th_lo;
+  *theta_hi = th_hi;
+  if (!done)
+    return fail(APC_ENOCONV, "eigenvalue estimate did not converge in %d Lanczos steps "
+                "(theta in [%g, %g], bounds %g, %g); pass gamma and eta explicitly", kmax,
+                th_lo, th_hi, bd_lo, bd_hi);
+  if (!(th_lo > n * std::numeric_limits<double>::epsilon() * th_hi) || th_lo - bd_lo <= 0.0)
+    return fail(APC_ESINGULAR, "mu_min(X) ~ 0 (Ritz value %g, mu_max %g): no unique solution",
+                th_lo, th_hi);
+  *lo_out = th_lo - bd_lo;
+  *hi_out = std::min(th_hi + bd_hi, 1.0);
+  return APC_OK;
+}
+
+apc_status residual_norm2(apc_plan_s* P, const double* x, double* out_dev) {
+  int32_t parts = 0;
+  HIP_TRY(launch_residual_partial(P->A, P->lda, P->B, P->ldb, P->N, P->n, x,
+                                  P->at<double>(P->L.partial), &parts, P->stream));
+  HIP_TRY(launch_sum_partials(P->at<double>(P->L.partial), parts, out_dev, P->stream));
+  return APC_OK;
+}
+
+apc_status check_device(int* dev) {
+  int count = 0;
+  if (hipGetDeviceCount(&count) != hipSuccess || count < 1)
+    return fail(APC_ENODEV, "no HIP device available");
+  HIP_TRY(hipGetDevice(dev));
+  hipDeviceProp_t prop;
+  HIP_TRY(hipGetDeviceProperties(&prop, *dev));
+  if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+    return fail(APC_ENODEV, "libapc is built for gfx950 only (device is %s)", prop.gcnArchName);
+  return APC_OK;
+}
+
+apc_status setup_impl(apc_plan_s* P, const Tiles& T) {
+  const Layout& L = P->L;
+  hipStream_t st = P->stream;
+  const int64_t N = P->N, n = P->n, ldc = L.ldc;
+  const int m = P->m;
+
+  // Device copies of the block structure and tile lists.
+  std::vector<int32_t> ta;
+  ta.insert(ta.end(), T.a_row0.begin(), T.a_row0.end());
+  ta.insert(ta.end(), T.a_nrows.begin(), T.a_nrows.end());
+  ta.insert(ta.end(), T.a_blk.begin(), T.a_blk.end());
+  HIP_TRY(hipMemcpyAsync(P->at<int32_t>(L.tiles_a), ta.data(), ta.size() * 4, hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(P->at<int32_t>(L.tiles_g), T.g.data(), T.g.size() * 4, hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(P->at<int32_t>(L.tiles_t), T.t.data(), T.t.size() * 4, hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(P->doff(), P->off.data(), (m + 1) * 8, hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(P->at<int64_t>(L.goff), T.goff.data(), m * 8, hipMemcpyHostToDevice, st));
+  HIP_TRY(launch_fill_u32(P->at<unsigned>(L.counters), L.nslab, 0u, st));
+  HIP_TRY(launch_fill_u32(P->at<unsigned>(L.flags), 4, 0u, st));
+
+  // ||b||^2 for the residual monitor.
+  ST_TRY(residual_norm2(P, nullptr, P->at<double>(L.scal) + 1));
+
+  // CholeskyQR2 of every A_i^T: C <- L^{-1} C twice, c <- L^{-1} c alongside.
+  double* Ca = P->at<double>(L.C64a);
+  double* Cb = P->at<double>(L.C64b);
+  double* ca = P->at<double>(L.ca);
+  double* cb = P->at<double>(L.cb);
+  HIP_TRY(launch_copy_pad(P->A, P->lda, P->B, P->ldb, N, n, Ca, ldc, ca, st));
+  int64_t pmax = 1;
+  for (int i = 0; i < m; ++i) pmax = std::max(pmax, P->off[i + 1] - P->off[i]);
+  const double rank_tol = 32.0 * std::numeric_limits<double>::epsilon() *
+                          static_cast<double>(std::max<int64_t>(pmax, 32));
+  for (int pass = 0; pass < 2; ++pass) {
+    double* src = pass == 0 ? Ca : Cb;
+    double* dst = pass == 0 ? Cb : Ca;
+    const double* cs = pass == 0 ? ca : cb;
+    double* cd = pass == 0 ? cb : ca;
+    HIP_TRY(launch_gram(src, ldc, P->doff(), P->at<int32_t>(L.tiles_g), L.ntiles_g,
+                        P->at<int64_t>(L.goff), P->at<double>(L.G), st));
+    HIP_TRY(launch_chol_inv(P->doff(), P->at<int64_t>(L.goff), m, P->at<double>(L.G),
+                            P->at<double>(L.Linv), cs, cd, P->at<int>(L.flags), rank_tol, st));
+    HIP_TRY(launch_trmm(src, dst, ldc, P->doff(), P->at<int32_t>(L.tiles_t), L.ntiles_t,
+                        P->at<int64_t>(L.goff), P->at<double>(L.Linv), st));
+  }
+  int flags[4] = {0, 0, 0, 0};
+  HIP_TRY(hipMemcpyAsync(flags, P->at<int>(L.flags), sizeof flags, hipMemcpyDeviceToHost, st));
+  double scal[2] = {0, 0};
+  HIP_TRY(hipMemcpyAsync(scal, P->at<double>(L.scal), sizeof scal, hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  if (flags[0] != 0)
+    return fail(APC_ERANK, "block %d is not of full row rank (Cholesky pivot below %g of the largest)",
+                flags[0] - 1, rank_tol);
+  P->bnorm = std::sqrt(scal[1]);
+
+  // Alg. 1 initialisation: x_i(0) = Q_i c_i (minimum-norm local solutions),
+  // x_bar(0) = (1/m) sum_i x_i(0).
+  ST_TRY(expand_blocks(P, ca, P->x(), 1.0, 0.0));
+  HIP_TRY(launch_block_sum(P->x(), ldc, m, ldc, 1.0 / m, P->xbar(), st));
+  if (P->prec == APC_F32) HIP_TRY(launch_cast_f32(Ca, P->at<float>(L.C32), N * ldc, st));
+
+  // Parameters: caller's, or Theorem 1's optimum from the estimated spectrum.
+  if (std::isnan(P->gamma) || std::isnan(P->eta)) {
+    double lo = 0, hi = 0, tl = 0, th = 0;
+    ST_TRY(lanczos(P, &lo, &hi, &tl, &th));
+    P->mu_min = lo;
+    P->mu_max = hi;
+    optimum(lo, hi, &P->gamma, &P->eta, &P->rho);
+  }
+  HIP_TRY(hipStreamSynchronize(st));
+  return APC_OK;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ C ABI
+
+extern "C" {
+
+size_t apc_workspace_bytes(int64_t N, int64_t n, const int64_t* off, int32_t m, int32_t k,
+                           int32_t precision) {
+  if (validate(N, n, off, m, k, precision) != APC_OK) return 0;
+  Tiles T;
+  build_tiles(off, m, round_up(n, kLdAlign), &T);
+  return make_layout(N, n, off, m, precision, T).total;
+}
+
+apc_status apc_setup(apc_plan* out, const double* A, int64_t lda, const double* B, int64_t ldb,
+                     int64_t N, int64_t n, const int64_t* off, int32_t m, int32_t k,
+                     int32_t precision, double gamma, double eta, void* workspace,
+                     size_t ws_bytes, void* stream) {
+  if (!out) return fail(APC_EINVAL, "out is NULL");
+  *out = nullptr;
+  apc_status st = validate(N, n, off, m, k, precision);
+  if (st != APC_OK) return st;
+  if (!A || !B) return fail(APC_EINVAL, "A and B must be device pointers");
+  if (lda < n) return fail(APC_EINVAL, "lda=%lld < n=%lld", (long long)lda, (long long)n);
+  if (ldb < 1) return fail(APC_EINVAL, "ldb must be >= 1");
+  if (!workspace) return fail(APC_EINVAL, "workspace is NULL");
+  if (reinterpret_cast<uintptr_t>(workspace) % kAlign != 0)
+    return fail(APC_EINVAL, "workspace must be 256-byte aligned");
+  const bool given = !std::isnan(gamma) && !std::isnan(eta);
+  if (given && (!std::isfinite(gamma) || !std::isfinite(eta)))
+    return fail(APC_EINVAL, "gamma and eta must be finite (or NaN for the optimum)");
+  Tiles T;
+  build_tiles(off, m, round_up(n, kLdAlign), &T);
+  const Layout L = make_layout(N, n, off, m, precision, T);
+  if (ws_bytes < L.total)
+    return fail(APC_EINVAL, "workspace has %zu bytes, needs %zu", ws_bytes, L.total);
+
+  int dev = 0;
+  st = check_device(&dev);
+  if (st != APC_OK) return st;
+
+  apc_plan_s* P = new (std::nothrow) apc_plan_s();
+  if (!P) return fail(APC_EINVAL, "out of host memory");
+  P->device = dev;
+  P->stream = static_cast<hipStream_t>(stream);
+  P->N = N;
+  P->n = n;
+  P->m = m;
+  P->k = k;
+  P->prec = precision;
+  P->off.assign(off, off + m + 1);
+  P->L = L;
+  P->ws = static_cast<char*>(workspace);
+  P->A = A;
+  P->lda = lda;
+  P->B = B;
+  P->ldb = ldb;
+  P->gamma = given ? gamma : NAN;
+  P->eta = given ? eta : NAN;
+  if (const char* e = std::getenv("APC_XCD_REMAP")) P->xcd_remap = std::atoi(e) != 0;
+  if (const char* e = std::getenv("APC_PASSB_ORDER")) P->passb_order = std::atoi(e) != 0;
+  st = setup_impl(P, T);
+  if (st != APC_OK) {
+    (void)hipStreamSynchronize(P->stream);
+    delete P;
+    return st;
+  }
+  *out = P;
+  return APC_OK;
+}
+
+apc_status apc_iterate(apc_plan p, int32_t T) {
+  if (!p) return fail(APC_EINVAL, "plan is NULL");
+  if (T < 0) return fail(APC_EINVAL, "T must be >= 0");
+  for (int32_t t = 0; t < T; ++t) {
+    ST_TRY(pass_a(p, p->xbar(), p->x(), p->L.ldc));
+    ST_TRY(pass_b(p));
+  }
+  p->iters += T;
+  return APC_OK;
+}
+
+apc_status apc_iterate_timed(apc_plan p, int32_t T, float* ms_pass_a, float* ms_pass_b) {
+  if (!p) return fail(APC_EINVAL, "plan is NULL");
+  if (T < 0) return fail(APC_EINVAL, "T must be >= 0");
+  for (auto& e : p->ev)
+    if (!e) HIP_TRY(hipEventCreate(&e));
+  float sa = 0.f, sb = 0.f;
+  for (int32_t t = 0; t < T; ++t) {
+    HIP_TRY(hipEventRecord(p->ev[0], p->stream));
+    ST_TRY(pass_a(p, p->xbar(), p->x(), p->L.ldc));
+    HIP_TRY(hipEventRecord(p->ev[1], p->stream));
+    ST_TRY(pass_b(p));
+    HIP_TRY(hipEventRecord(p->ev[2], p->stream));
+    HIP_TRY(hipEventSynchronize(p->ev[2]));
+    float a = 0.f, b = 0.f;
+    HIP_TRY(hipEventElapsedTime(&a, p->ev[0], p->ev[1]));
+    HIP_TRY(hipEventElapsedTime(&b, p->ev[1], p->ev[2]));
+    sa += a;
+    sb += b;
+  }
+  p->iters += T;
+  if (ms_pass_a) *ms_pass_a = sa;
+  if (ms_pass_b) *ms_pass_b = sb;
+  return APC_OK;
+}
+
+apc_status apc_residual(apc_plan p, double* relres) {
+  if (!p || !relres) return fail(APC_EINVAL, "NULL argument");
+  double* dst = p->at<double>(p->L.scal);
+  ST_TRY(residual_norm2(p, p->xbar(), dst));
+  double r2 = 0;
+  HIP_TRY(hipMemcpyAsync(&r2, dst, sizeof r2, hipMemcpyDeviceToHost, p->stream));
+  HIP_TRY(hipStreamSynchronize(p->stream));
+  *relres = p->bnorm > 0 ? std::sqrt(r2) / p->bnorm : std::sqrt(r2);
+  return APC_OK;
+}
+
+apc_status apc_solve(apc_plan p, double rtol, int32_t max_iters, double* Xbar, int64_t ldx,
+                     int32_t* iters_out, double* relres_out) {
+  if (!p || !Xbar) return fail(APC_EINVAL, "NULL argument");
+  if (ldx < 1 || max_iters < 0 || !(rtol >= 0)) return fail(APC_EINVAL, "bad ldx/max_iters/rtol");
+  double rr = 0;
+  ST_TRY(apc_residual(p, &rr));
+  int32_t done = 0;
+  apc_status st = APC_OK;
+  while (rr > rtol && done < max_iters) {
+    const int32_t T = std::min(8, max_iters - done);
+    ST_TRY(apc_iterate(p, T));
+    done += T;
+    ST_TRY(apc_residual(p, &rr));
+    if (!std::isfinite(rr)) {
+      st = fail(APC_EDIVERGED, "residual became non-finite after %d updates", done);
+      break;
+    }
+  }
+  if (st == APC_OK && rr > rtol)
+    st = fail(APC_ENOCONV, "relative residual %g > %g after %d updates", rr, rtol, done);
+  apc_status cs = apc_get_xbar(p, Xbar, ldx);
+  if (cs != APC_OK) return cs;
+  HIP_TRY(hipStreamSynchronize(p->stream));
+  if (iters_out) *iters_out = done;
+  if (relres_out) *relres_out = rr;
+  return st;
+}
+
+apc_status apc_get_xbar(apc_plan p, double* Xbar, int64_t ldx) {
+  if (!p || !Xbar || ldx < 1) return fail(APC_EINVAL, "bad argument");
+  HIP_TRY(launch_copy_strided(p->xbar(), 1, Xbar, ldx, p->n, 1, p->stream));
+  return APC_OK;
+}
+
+apc_status apc_get_local(apc_plan p, double* X, int64_t ldx) {
+  if (!p || !X || ldx < p->n) return fail(APC_EINVAL, "bad argument");
+  HIP_TRY(launch_copy_strided(p->x(), p->L.ldc, X, ldx, p->m, p->n, p->stream));
+  return APC_OK;
+}
+
+apc_status apc_project(apc_plan p, const double* V, double* Out, int64_t ldv) {
+  if (!p || !V || !Out || ldv < p->n) return fail(APC_EINVAL, "bad argument");
+  const Layout& L = p->L;
+  double* Y = p->at<double>(L.Y);
+  // Y_i <- V_i zero-padded to ldc; w = Q_i^T (0 - Y_i) = -Q_i^T V_i; Y_i += Q_i w.
+  HIP_TRY(launch_fill_u32(reinterpret_cast<unsigned*>(Y), 2 * p->m * L.ldc, 0u, p->stream));
+  HIP_TRY(launch_copy_strided(V, ldv, Y, L.ldc, p->m, p->n, p->stream));
+  HIP_TRY(launch_fill_u32(p->at<unsigned>(L.vtmp), 2 * L.ldc, 0u, p->stream));
+  ST_TRY(rowdot64(p, p->C64(), static_cast<int32_t>(p->N), p->at<double>(L.vtmp), Y, L.ldc, true,
+                  p->at<double>(L.w)));
+  ST_TRY(expand_blocks(p, p->at<double>(L.w), Y, 1.0, 1.0));
+  HIP_TRY(launch_copy_strided(Y, L.ldc, Out, ldv, p->m, p->n, p->stream));
+  return APC_OK;
+}
+
+apc_status apc_get_params(apc_plan p, double* gamma, double* eta, double* mu_min, double* mu_max,
+                          double* rho) {
+  if (!p) return fail(APC_EINVAL, "plan is NULL");
+  if (gamma) *gamma = p->gamma;
+  if (eta) *eta = p->eta;
+  if (mu_min) *mu_min = p->mu_min;
+  if (mu_max) *mu_max = p->mu_max;
+  if (rho) *rho = p->rho;
+  return APC_OK;
+}
+
+apc_status apc_optimal_params(double mu_min, double mu_max, double* gamma, double* eta,
+                              double* rho) {
+  if (!(mu_min > 0.0) || !(mu_max >= mu_min) || !(mu_max <= 1.0 + 1e-12))
+    return fail(APC_EINVAL, "need 0 < mu_min <= mu_max <= 1 (got %g, %g)", mu_min, mu_max);
+  double g = 0, e = 0, r = 0;
+  optimum(mu_min, std::min(mu_max, 1.0), &g, &e, &r);
+  if (gamma) *gamma = g;
+  if (eta) *eta = e;
+  if (rho) *rho = r;
+  return APC_OK;
+}
+
+apc_status apc_tridiag_extremes(const double* alpha, const double* beta, int32_t k,
+                                int32_t with_bounds, double* lo, double* hi, double* bound_lo,
+                                double* bound_hi) {
+  if (k < 1 || !alpha || (k > 1 && !beta) || (with_bounds && !beta))
+    return fail(APC_EINVAL, "bad tridiagonal arguments");
+  std::vector<double> a(alpha, alpha + k), b(k, 0.0);
+  for (int i = 0; i + 1 < k; ++i) b[i] = beta[i];
+  if (with_bounds) b[k - 1] = beta[k - 1];
+  const double tl = tridiag_eig(a, b, k, 0);
+  const double th = tridiag_eig(a, b, k, k - 1);
+  if (lo) *lo = tl;
+  if (hi) *hi = th;
+  if (bound_lo) *bound_lo = with_bounds ? std::fabs(b[k - 1] * last_component(a, b, k, tl, false)) : 0.0;
+  if (bound_hi) *bound_hi = with_bounds ? std::fabs(b[k - 1] * last_component(a, b, k, th, true)) : 0.0;
+  return APC_OK;
+}
+
+int64_t apc_iterations(apc_plan p) { return p ? p->iters : -1; }
+
+void apc_destroy(apc_plan p) {
+  if (!p) return;
+  for (auto& e : p->ev)
+    if (e) (void)hipEventDestroy(e);
+  delete p;
+}
+
+const char* apc_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

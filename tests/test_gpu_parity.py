@@ -1,0 +1,358 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle.
+
+Tolerances (written per test): FP64 mode 1e-10 and FP32 mode 1e-5, both as
+||x_bar_gpu(t) - x_bar_oracle(t)||_2 / ||x*||_2 at every checked t.
+"""
+
+import math
+import os
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import apc_oracle as O
+from paper_1708_01413_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+TOL = {"f64": 1e-10, "f32": 1e-5}
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _apc():
+    from paper_1708_01413_amd import apc
+    return apc
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def upload(S):
+    torch = _torch()
+    return torch.from_numpy(np.ascontiguousarray(S.A)).cuda(), torch.from_numpy(S.B).cuda()
+
+
+def oracle_traj(S, T, gamma, eta):
+    Qt, R = O.factor(S.A, S.off)
+    x = O.init_local(Qt, R, S.B, S.off)
+    xbar = O.initial_average(x)
+    traj = [xbar[:, 0].copy()]
+    for _ in range(T):
+        x, xbar = O.apc_step(Qt, x, xbar, gamma, eta)
+        traj.append(xbar[:, 0].copy())
+    return np.stack(traj), x
+
+
+def gpu_traj(plan, T):
+    torch = _torch()
+    snaps = [plan.xbar()]
+    for _ in range(T):
+        plan.iterate(1)
+        snaps.append(plan.xbar())
+    torch.cuda.synchronize()
+    return torch.stack(snaps).cpu().numpy()
+
+
+def rel_dev(a, b, xstar):
+    return float(np.max(np.linalg.norm(a - b, axis=-1)) / np.linalg.norm(xstar))
+
+
+# ---------------------------------------------------------------- the FP64 workload
+
+
+@pytest.fixture(scope="module")
+def square512():
+    S = synth.square_gaussian_512()
+    mn, mx = O.spectrum(S.A, S.off)
+    g, e, rho = O.optimal_params(mn, mx)
+    traj, _ = oracle_traj(S, 2000, g, e)
+    return S, dict(mu_min=mn, mu_max=mx, gamma=g, eta=e, rho=rho), traj
+
+
+def test_fp64_square512_trajectory_2000(square512):
+    """N = n = 512, m = 8, FP64, optimal (gamma, eta) from the oracle: the whole
+    2000-update x_bar trajectory (through its transient growth) within 1e-10."""
+    apc = _apc()
+    S, prm, ref = square512
+    say("case: square512 f64 trajectory T=2000")
+    A, b = upload(S)
+    plan = apc.Plan(A, b, S.off, "f64", gamma=prm["gamma"], eta=prm["eta"])
+    got = gpu_traj(plan, 2000)
+    dev = rel_dev(got, ref, S.xstar)
+    err = np.linalg.norm(got - S.xstar, axis=1) / np.linalg.norm(S.xstar)
+    say(f"max dev {dev:.3e}; err(1)={err[1]:.3f} peak={err.max():.2f} err(2000)={err[-1]:.2f}")
+    assert dev <= TOL["f64"]
+    assert plan.iterations == 2000
+
+
+def test_fp64_square512_invariants(square512):
+    """App. A: A_i x_i(t) = b_i at every iterate (checked at t = 0, 700, 1400)."""
+    apc = _apc()
+    S, prm, _ = square512
+    say("case: square512 f64 invariants")
+    A, b = upload(S)
+    plan = apc.Plan(A, b, S.off, "f64", gamma=prm["gamma"], eta=prm["eta"])
+    for t in (0, 700, 1400):
+        if t:
+            plan.iterate(700)
+        X = plan.local().cpu().numpy()
+        for i, (Ai, bi) in enumerate(zip(O.blocks(S.A, S.off), O.blocks(S.B, S.off))):
+            r = np.linalg.norm(Ai @ X[i] - bi) / np.linalg.norm(bi)
+            assert r < 1e-11, (t, i, r)
+
+
+def test_fp64_square512_eigen_estimate(square512):
+    """Setup's Lanczos estimate of mu_min, mu_max (eq. (4)) and Theorem 1's optimum."""
+    apc = _apc()
+    S, prm, _ = square512
+    say("case: square512 eigen estimate")
+    A, b = upload(S)
+    plan = apc.Plan(A, b, S.off, "f64")
+    p = plan.params()
+    say(p, prm)
+    assert p["mu_max"] >= prm["mu_max"] * (1 - 1e-12)           # encloses the spectrum
+    assert p["mu_max"] == pytest.approx(prm["mu_max"], rel=1e-9)
+    assert p["mu_min"] <= prm["mu_min"] * (1 + 1e-9)
+    assert p["mu_min"] == pytest.approx(prm["mu_min"], rel=1e-4)
+    assert p["gamma"] == pytest.approx(prm["gamma"], rel=1e-5)
+    assert p["eta"] == pytest.approx(prm["eta"], rel=1e-5)
+    assert p["rho"] == pytest.approx(prm["rho"], rel=1e-6)
+
+
+def test_setup_init_and_projectors_match_oracle():
+    """Alg. 1 init (min-norm x_i(0), mean x_bar(0)) and P_i = I - Q_i Q_i^T on device:
+    compare P_i v with the dense definition, and check P_i^2 = P_i and A_i P_i = 0."""
+    apc = _apc()
+    torch = _torch()
+    S = synth.gaussian_system(300, 200, 7, seed=3,
+                              sizes=synth.renormalised_sizes(np.random.default_rng(3), 7, 300, 20, 60))
+    say("case: init/projectors N=300 n=200 m=7 uneven", np.diff(S.off))
+    A, b = upload(S)
+    plan = apc.Plan(A, b, S.off, "f64", gamma=1.0, eta=1.0)
+    Qt, R = O.factor(S.A, S.off)
+    x0 = O.init_local(Qt, R, S.B, S.off)[:, :, 0]
+    np.testing.assert_allclose(plan.local().cpu().numpy(), x0, atol=1e-12)
+    np.testing.assert_allclose(plan.xbar().cpu().numpy(), O.initial_average(x0[:, :, None])[:, 0],
+                               atol=1e-12)
+    V = torch.from_numpy(np.random.default_rng(0).standard_normal((7, 200))).cuda()
+    PV = plan.project(V)
+    PPV = plan.project(PV)
+    PVn, PPVn, Vn = PV.cpu().numpy(), PPV.cpu().numpy(), V.cpu().numpy()
+    for i, Ai in enumerate(O.blocks(S.A, S.off)):
+        np.testing.assert_allclose(PVn[i], O.projector(Ai) @ Vn[i], atol=1e-12)
+        np.testing.assert_allclose(PPVn[i], PVn[i], atol=1e-12)
+        assert np.abs(Ai @ PVn[i]).max() < 1e-11
+
+
+# ---------------------------------------------------------------- ragged / edge shapes
+
+
+RAGGED = [
+    # (N, n, m, size range or None, seed, shift)
+    (300, 200, 7, (20, 60), 1, 0.0),       # n not a multiple of the tile/slab widths
+    (1000, 1000, 13, (40, 120), 2, 2.0),   # several tiles per block, ragged tails
+    (517, 333, 5, None, 4, 0.0),           # odd sizes, N mod m != 0
+    (2048, 1536, 16, None, 5, 0.0),        # slab count > 1 in both precisions
+]
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("N,n,m,rng_sizes,seed,shift", RAGGED)
+def test_ragged_trajectory(prec, N, n, m, rng_sizes, seed, shift):
+    apc = _apc()
+    sizes = None
+    if rng_sizes:
+        sizes = synth.renormalised_sizes(np.random.default_rng(seed), m, N, *rng_sizes)
+    S = synth.gaussian_system(N, n, m, seed=seed, shift=shift, sizes=sizes,
+                              scale=1.0 / math.sqrt(n))
+    say(f"case: ragged {prec} N={N} n={n} m={m} sizes={np.diff(S.off).tolist()}")
+    g, e, _ = O.optimal_params(*O.spectrum(S.A, S.off))
+    T = 60
+    ref, _ = oracle_traj(S, T, g, e)
+    A, b = upload(S)
+    plan = apc.Plan(A, b, S.off, prec, gamma=g, eta=e)
+    got = gpu_traj(plan, T)
+    dev = rel_dev(got, ref, S.xstar)
+    say(f"max dev {dev:.3e} (tol {TOL[prec]})")
+    assert dev <= TOL[prec]
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_single_row_blocks(prec):
+    """p_i = 1 for every block (m = N = n = 96)."""
+    apc = _apc()
+    S = synth.gaussian_system(96, 96, 96, seed=7, shift=3.0, scale=1 / math.sqrt(96))
+    say(f"case: single-row blocks {prec}")
+    g, e, _ = O.optimal_params(*O.spectrum(S.A, S.off))
+    ref, _ = oracle_traj(S, 40, g, e)
+    A, b = upload(S)
+    plan = apc.Plan(A, b, S.off, prec, gamma=g, eta=e)
+    assert rel_dev(gpu_traj(plan, 40), ref, S.xstar) <= TOL[prec]
+
+
+@pytest.mark.parametrize("N,n,m", [(64, 64, 1), (128, 64, 2), (3, 1, 3)])
+def test_full_blocks_converge_in_one_step(N, n, m):
+    """Every p_i = n: X = I, so gamma* = eta* = 1 and x_bar(1) = x* (Theorem 1).  Also
+    runs the on-device eigenvalue estimate on an X with a single distinct eigenvalue."""
+    apc = _apc()
+    S = synth.gaussian_system(N, n, m, seed=8, shift=2.0 if N == n else 0.0)
+    say(f"case: full blocks N={N} n={n} m={m}")
+    A, b = upload(S)
+    plan = apc.Plan(A, b, S.off, "f64")
+    p = plan.params()
+    assert p["gamma"] == pytest.approx(1.0, abs=1e-6) and p["eta"] == pytest.approx(1.0, abs=1e-6)
+    plan.iterate(1)
+    x = plan.xbar().cpu().numpy()
+    assert np.linalg.norm(x - S.xstar) / np.linalg.norm(S.xstar) < 1e-10
+
+
+def test_zero_updates_is_a_no_op():
+    apc = _apc()
+    S = synth.gaussian_system(64, 64, 4, seed=9, shift=2.0)
+    A, b = upload(S)
+    plan = apc.Plan(A, b, S.off, "f64", gamma=1.1, eta=1.5)
+    x0 = plan.xbar().cpu().numpy()
+    plan.iterate(0)
+    np.testing.assert_array_equal(plan.xbar().cpu().numpy(), x0)
+    assert plan.iterations == 0
+
+
+def test_fp64_is_deterministic():
+    apc = _apc()
+    S = synth.gaussian_system(1024, 768, 12, seed=10, scale=1 / math.sqrt(768))
+    say("case: determinism")
+    A, b = upload(S)
+    outs = []
+    for _ in range(2):
+        plan = apc.Plan(A, b, S.off, "f64", gamma=1.05, eta=3.0)
+        plan.iterate(50)
+        outs.append(plan.xbar().cpu().numpy())
+        plan.close()
+    np.testing.assert_array_equal(outs[0], outs[1])
+
+
+# ---------------------------------------------------------------- error paths
+
+
+def test_rank_deficient_block_is_reported():
+    apc = _apc()
+    S = synth.gaussian_system(64, 64, 4, seed=11)
+    S.A[5] = S.A[4]
+    say("case: rank-deficient block")
+    A, b = upload(S)
+    with pytest.raises(apc.ApcError) as ei:
+        apc.Plan(A, b, S.off, "f64")
+    assert ei.value.status == apc.APC_ERANK
+
+
+def test_singular_system_is_reported():
+    apc = _apc()
+    S = synth.gaussian_system(80, 40, 4, seed=12)
+    S.A[:, 3] = S.A[:, 4]
+    say("case: singular X")
+    A, b = upload(S)
+    with pytest.raises(apc.ApcError) as ei:
+        apc.Plan(A, b, S.off, "f64")
+    assert ei.value.status == apc.APC_ESINGULAR
+
+
+def test_solve_reports_divergence():
+    """gamma = 1 and eta * mu_max = 3 put the root 1 - eta*mu_max = -2 of p_i outside the
+    unit disc (eq. (6)): the residual blows up and apc_solve returns APC_EDIVERGED."""
+    apc = _apc()
+    S = synth.gaussian_system(64, 64, 4, seed=13, shift=2.0)
+    _, mx = O.spectrum(S.A, S.off)
+    A, b = upload(S)
+    plan = apc.Plan(A, b, S.off, "f64", gamma=1.0, eta=3.0 / mx)
+    say("case: divergence")
+    with pytest.raises(apc.ApcError) as ei:
+        plan.solve(1e-12, 5000)
+    assert ei.value.status == apc.APC_EDIVERGED
+
+
+@pytest.mark.parametrize("prec,rtol,xtol", [("f64", 1e-13, 1e-11), ("f32", 1e-6, 1e-5)])
+def test_solve_reaches_direct_solution(prec, rtol, xtol):
+    apc = _apc()
+    S = synth.shifted_square(1024, 8, seed=14)
+    say(f"case: solve {prec}")
+    A, b = upload(S)
+    plan = apc.Plan(A, b, S.off, prec)
+    x, it, rr, st = plan.solve(rtol, 500)
+    assert st == apc.APC_OK and rr <= rtol
+    ref = np.linalg.solve(S.A, S.B)
+    assert np.linalg.norm(x.cpu().numpy() - ref) / np.linalg.norm(ref) < xtol
+    assert it == plan.iterations and it % 8 == 0
+
+
+# ---------------------------------------------------------------- full size
+
+
+@pytest.fixture(scope="module")
+def tall16k():
+    torch = _torch()
+    g = np.load(os.path.join(GOLDEN, "tall_gauss_16384x8192_m64.npz"), allow_pickle=False)
+    S = synth.tall_gaussian_16k()
+    A, b = upload(S)
+    xs = torch.from_numpy(S.xstar).cuda()
+    off = S.off
+    del S
+    return A, b, xs, off, g
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_full_size_tall16k_trajectory(tall16k, prec):
+    """N = 16384, n = 8192, m = 64 (the benchmark workload) in the launch configuration
+    the benchmark times: relative-error curve and every-8th-coordinate samples of x_bar(t)
+    against the oracle's stored values (tests/golden/make_golden.py)."""
+    torch = _torch()
+    apc = _apc()
+    A, b, xs, off, g = tall16k
+    say(f"case: full-size tall16k {prec}")
+    plan = apc.Plan(A, b, off, prec, gamma=float(g["gamma"]), eta=float(g["eta"]))
+    idx = torch.from_numpy(g["idx"]).cuda()
+    check = list(g["check_t"])
+    xn = float(g["xstar_norm"])
+    errs, samples = [], {}
+    for t in range(int(check[-1]) + 1):
+        if t:
+            plan.iterate(1)
+        xb = plan.xbar()
+        errs.append(float(torch.linalg.norm(xb - xs)) / xn)
+        if t in check:
+            samples[t] = xb[idx].cpu().numpy()
+    errs = np.array(errs)
+    ref_err = g["err"]
+    say("err gpu ", " ".join(f"{e:.3e}" for e in errs[[10, 20, 30, 40, 60]]))
+    say("err orc ", " ".join(f"{e:.3e}" for e in ref_err[[10, 20, 30, 40, 60]]))
+    assert np.max(np.abs(errs - ref_err)) <= TOL[prec]
+    n = 8192
+    for k, t in enumerate(check):
+        d = samples[t] - g["samples"][k]
+        est = math.sqrt(n / d.size * float(np.sum(d * d))) / xn   # sampled estimate of ||dx||/||x*||
+        assert est <= TOL[prec], (t, est)
+    first = lambda e, lvl: int(np.argmax(e <= lvl))
+    assert abs(first(errs, 1e-5) - first(ref_err, 1e-5)) <= 1
+    assert errs[-1] <= (1e-6 if prec == "f32" else 1e-9)
+
+
+def test_full_size_tall16k_eigen_estimate(tall16k):
+    apc = _apc()
+    A, b, xs, off, g = tall16k
+    say("case: full-size eigen estimate")
+    plan = apc.Plan(A, b, off, "f32")
+    p = plan.params()
+    say(p, {k: float(g[k]) for k in ("mu_min", "mu_max", "gamma", "eta", "rho")})
+    assert p["mu_max"] == pytest.approx(float(g["mu_max"]), rel=1e-9)
+    assert p["mu_min"] == pytest.approx(float(g["mu_min"]), rel=1e-5)
+    assert p["gamma"] == pytest.approx(float(g["gamma"]), rel=1e-6)
+    assert p["eta"] == pytest.approx(float(g["eta"]), rel=1e-5)
