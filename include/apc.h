@@ -90,16 +90,19 @@ apc_status apc_setup(apc_plan* out, const double* A, int64_t lda, const double* 
                      int32_t precision, double gamma, double eta, void* workspace,
                      size_t ws_bytes, void* stream);
 
-/* Apply T updates of eq. (2a)-(2b) (T >= 0).  Asynchronous: enqueues two
- * kernels per update (projection pass A: w_i = Q_i^T (x_bar - x_i); pass B:
- * x_i += gamma (x_bar - x_i - Q_i w_i) with the momentum average fused into
- * its epilogue) and returns. */
+/* Apply T updates of eq. (2a)-(2b) (T >= 0).  Asynchronous: per update it
+ * enqueues, for each group of blocks, projection pass A (w_i = Q_i^T (x_bar -
+ * x_i)) and pass B (x_i += gamma (x_bar - x_i - Q_i w_i)), then the momentum
+ * average x_bar <- (eta/m) sum_i x_i + (1 - eta) x_bar, and returns. */
 apc_status apc_iterate(apc_plan p, int32_t T);
 
-/* As apc_iterate, and also measures the two passes with HIP events on the
- * plan's stream: *ms_pass_a / *ms_pass_b (host) receive the summed durations
- * of all T pass-A / pass-B launches.  Synchronises the stream. */
-apc_status apc_iterate_timed(apc_plan p, int32_t T, float* ms_pass_a, float* ms_pass_b);
+/* As apc_iterate, and also times the launches with HIP events recorded on the
+ * plan's stream after every launch: *ms_total receives the span of the T
+ * updates (launch gaps included); *ms_pass_a, *ms_pass_b and *ms_average the
+ * summed durations of the pass-A, pass-B and averaging launches (host
+ * pointers, any may be NULL).  Synchronises the stream once, at the end. */
+apc_status apc_iterate_timed(apc_plan p, int32_t T, float* ms_total, float* ms_pass_a,
+                             float* ms_pass_b, float* ms_average);
 
 /* Relative residual ||b - A x_bar||_2 / ||b||_2 in FP64 on the GPU (the
  * solver's convergence monitor).  *relres is host.  Synchronises. */
@@ -151,6 +154,14 @@ apc_status apc_optimal_params(double mu_min, double mu_max, double* gamma, doubl
 apc_status apc_tridiag_extremes(const double* alpha, const double* beta, int32_t k,
                                 int32_t with_bounds, double* lo, double* hi, double* bound_lo,
                                 double* bound_hi);
+
+/* Host copies of setup diagnostics: the number of Lanczos steps the
+ * eigenvalue estimate took (0 when gamma and eta were given), and the launch
+ * shape chosen for this problem: pass-A rows per workgroup and column splits,
+ * and the number of block groups each update runs pass A and pass B over.
+ * Any pointer may be NULL. */
+apc_status apc_get_info(apc_plan p, int32_t* lanczos_steps, int32_t* rows_per_tile,
+                        int32_t* column_splits, int32_t* block_groups);
 
 /* Number of updates applied since setup (host). */
 int64_t apc_iterations(apc_plan p);

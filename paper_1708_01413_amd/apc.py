@@ -35,7 +35,7 @@ EXPORTED = (
     "apc_workspace_bytes", "apc_setup", "apc_iterate", "apc_iterate_timed", "apc_residual",
     "apc_solve", "apc_get_xbar", "apc_get_local", "apc_project", "apc_get_params",
     "apc_iterations", "apc_destroy", "apc_last_error", "apc_optimal_params",
-    "apc_tridiag_extremes",
+    "apc_tridiag_extremes", "apc_get_info",
 )
 
 
@@ -48,11 +48,27 @@ class ApcError(RuntimeError):
         super().__init__(f"{self.name}: {message}")
 
 
+def _hip_runtimes() -> set:
+    """Distinct libamdhip64 files mapped into this process."""
+    try:
+        with open("/proc/self/maps") as f:
+            return {line.split()[-1] for line in f if "libamdhip64" in line}
+    except OSError:
+        return set()
+
+
 def _load() -> ctypes.CDLL:
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
                           "(hipcc --offload-arch=gfx950); there is no fallback path")
+    # torch ships its own HIP runtime with the same soname as the system one.
+    # Load it first so libapc binds to it: two HIP runtimes in one process
+    # cannot share the device (HIP then reports no device to one of them).
+    import torch  # noqa: F401
+
     lib = ctypes.CDLL(LIB_PATH)
+    if len(_hip_runtimes()) > 1:
+        raise ImportError(f"two HIP runtimes are loaded: {sorted(_hip_runtimes())}")
     vp, i64, i32, f64 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_double
     P64 = ctypes.POINTER(ctypes.c_int64)
     Pd = ctypes.POINTER(ctypes.c_double)
@@ -63,7 +79,7 @@ def _load() -> ctypes.CDLL:
         "apc_setup": (i32, [ctypes.POINTER(vp), vp, i64, vp, i64, i64, i64, P64, i32, i32, i32,
                             f64, f64, vp, ctypes.c_size_t, vp]),
         "apc_iterate": (i32, [vp, i32]),
-        "apc_iterate_timed": (i32, [vp, i32, Pf, Pf]),
+        "apc_iterate_timed": (i32, [vp, i32, Pf, Pf, Pf, Pf]),
         "apc_residual": (i32, [vp, Pd]),
         "apc_solve": (i32, [vp, f64, i32, vp, i64, Pi, Pd]),
         "apc_get_xbar": (i32, [vp, vp, i64]),
@@ -71,6 +87,7 @@ def _load() -> ctypes.CDLL:
         "apc_project": (i32, [vp, vp, vp, i64]),
         "apc_get_params": (i32, [vp, Pd, Pd, Pd, Pd, Pd]),
         "apc_iterations": (i64, [vp]),
+        "apc_get_info": (i32, [vp, Pi, Pi, Pi, Pi]),
         "apc_optimal_params": (i32, [f64, f64, Pd, Pd, Pd]),
         "apc_tridiag_extremes": (i32, [Pd, Pd, i32, i32, Pd, Pd, Pd, Pd]),
         "apc_destroy": (None, [vp]),
@@ -117,9 +134,10 @@ def apc_iterate(plan, T: int):
 
 
 def apc_iterate_timed(plan, T: int):
-    a, b = ctypes.c_float(), ctypes.c_float()
-    _check(lib.apc_iterate_timed(plan, T, ctypes.byref(a), ctypes.byref(b)))
-    return a.value, b.value
+    """Returns (ms_total, ms_pass_a, ms_pass_b, ms_average)."""
+    v = [ctypes.c_float() for _ in range(4)]
+    _check(lib.apc_iterate_timed(plan, T, *[ctypes.byref(x) for x in v]))
+    return tuple(x.value for x in v)
 
 
 def apc_residual(plan) -> float:
@@ -150,6 +168,13 @@ def apc_get_params(plan) -> dict:
     vals = [ctypes.c_double() for _ in range(5)]
     _check(lib.apc_get_params(plan, *[ctypes.byref(v) for v in vals]))
     return dict(zip(("gamma", "eta", "mu_min", "mu_max", "rho"), (v.value for v in vals)))
+
+
+def apc_get_info(plan) -> dict:
+    vals = [ctypes.c_int32() for _ in range(4)]
+    _check(lib.apc_get_info(plan, *[ctypes.byref(v) for v in vals]))
+    return dict(zip(("lanczos_steps", "rows_per_tile", "column_splits", "block_groups"),
+                    (v.value for v in vals)))
 
 
 def apc_iterations(plan) -> int:
@@ -196,7 +221,8 @@ class Plan:
     optimum.  The plan keeps references to A, b and its workspace.
     """
 
-    def __init__(self, A, b, off, precision: str = "f64", gamma=None, eta=None, stream=None):
+    def __init__(self, A, b, off, precision: str = "f64", gamma=None, eta=None, stream=None,
+                 workspace=None):
         import torch
 
         if A.dtype != torch.float64 or b.dtype != torch.float64:
@@ -218,7 +244,11 @@ class Plan:
         if ws == 0:
             raise ApcError(APC_EINVAL, apc_last_error())
         self.ws_bytes = ws
-        self.workspace = torch.empty(ws + 256, dtype=torch.uint8, device=self.device)
+        if workspace is None:
+            workspace = torch.empty(ws + 256, dtype=torch.uint8, device=self.device)
+        elif workspace.numel() < ws + 256 or workspace.dtype != torch.uint8:
+            raise ValueError(f"workspace needs {ws + 256} bytes (uint8)")
+        self.workspace = workspace
         base = self.workspace.data_ptr()
         self._ws_ptr = (base + 255) // 256 * 256
         self.A, self.b = A, b
@@ -233,7 +263,14 @@ class Plan:
         apc_iterate(self.handle, T)
 
     def iterate_timed(self, T: int):
+        """(ms_total, ms_pass_a, ms_pass_b, ms_average) of T updates, timed with HIP events."""
         return apc_iterate_timed(self.handle, T)
+
+    @staticmethod
+    def workspace_bytes(N, n, off, precision="f64") -> int:
+        """Bytes to pass as a preallocated ``workspace`` (uint8) tensor."""
+        off = np.asarray(off, dtype=np.int64)
+        return apc_workspace_bytes(N, n, off, len(off) - 1, 1, PRECISIONS[precision]) + 256
 
     def residual(self) -> float:
         return apc_residual(self.handle)
@@ -265,6 +302,9 @@ class Plan:
 
     def params(self) -> dict:
         return apc_get_params(self.handle)
+
+    def info(self) -> dict:
+        return apc_get_info(self.handle)
 
     @property
     def iterations(self) -> int:

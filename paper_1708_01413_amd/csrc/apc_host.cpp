@@ -43,9 +43,15 @@ apc_status fail(apc_status st, const char* fmt, ...) {
                   __LINE__);                                                              \
   } while (0)
 
+#define ST_TRY(expr)              \
+  do {                            \
+    apc_status s_ = (expr);       \
+    if (s_ != APC_OK) return s_;  \
+  } while (0)
+
 constexpr int64_t kAlign = 256;
 constexpr int kLanczosMax = 1024;   // Lanczos steps cap (full reorthogonalisation)
-constexpr int kLanczosCheck = 8;    // steps between convergence checks (host syncs)
+constexpr int kLanczosCheck = 4;    // steps between convergence checks (host syncs)
 
 int64_t round_up(int64_t v, int64_t a) { return (v + a - 1) / a * a; }
 
@@ -53,9 +59,8 @@ int64_t round_up(int64_t v, int64_t a) { return (v + a - 1) / a * a; }
 
 struct Layout {
   int64_t ldc = 0, kmax = 0, S = 0;
-  int32_t ntiles_a = 0, ntiles_g = 0, ntiles_t = 0, nslab = 0, nparts = 0;
-  size_t C64a, C64b, C32, x, xbar, w, ca, cb, Y, vtmp, V, h, h2, alpha, beta, G, Linv, counters,
-      flags, scal, partial, tiles_a, tiles_g, tiles_t, doff, goff, total;
+  int32_t ntiles_a = 0, ntiles_g = 0, ntiles_t = 0, nparts = 0;
+  size_t C64a, C64b, C32, x, xbar, dv, w, ca, cb, Y, vtmp, V, h, h2, alpha, beta, G, Linv, flags, scal, partial, tiles_a, tiles_g, tiles_t, doff, goff, total;
 };
 
 struct Tiles {
@@ -65,14 +70,18 @@ struct Tiles {
   std::vector<int64_t> goff;                     // offset of G_i in the packed Gram storage
 };
 
-void build_tiles(const int64_t* off, int32_t m, int64_t ldc, Tiles* T) {
+constexpr int kMinRowTile = 8;  // the workspace holds pass-A tile lists of this height or more
+constexpr int kPassARows = 8;   // default rows per pass-A workgroup
+constexpr int kMaxSplit = 8;    // pass-A column splits the workspace holds partials for
+
+void build_tiles(const int64_t* off, int32_t m, int64_t ldc, int rows_per_tile, Tiles* T) {
   int64_t g = 0;
   const int64_t ctiles = (ldc + kGramTile - 1) / kGramTile;
   for (int i = 0; i < m; ++i) {
     const int64_t p = off[i + 1] - off[i];
-    for (int64_t r = 0; r < p; r += kRowTile) {
+    for (int64_t r = 0; r < p; r += rows_per_tile) {
       T->a_row0.push_back(static_cast<int32_t>(off[i] + r));
-      T->a_nrows.push_back(static_cast<int32_t>(std::min<int64_t>(kRowTile, p - r)));
+      T->a_nrows.push_back(static_cast<int32_t>(std::min<int64_t>(rows_per_tile, p - r)));
       T->a_blk.push_back(i);
     }
     const int64_t pt = (p + kGramTile - 1) / kGramTile;
@@ -99,10 +108,11 @@ Layout make_layout(int64_t N, int64_t n, const int64_t* off, int32_t m, int32_t 
   L.ldc = round_up(n, kLdAlign);
   L.kmax = std::min<int64_t>(n, kLanczosMax);
   for (int i = 0; i < m; ++i) L.S += (off[i + 1] - off[i]) * (off[i + 1] - off[i]);
+  int64_t max_tiles_a = 0;  // tile lists of the smallest height
+  for (int i = 0; i < m; ++i) max_tiles_a += (off[i + 1] - off[i] + kMinRowTile - 1) / kMinRowTile;
   L.ntiles_a = static_cast<int32_t>(T.a_row0.size());
   L.ntiles_g = static_cast<int32_t>(T.g.size() / 3);
   L.ntiles_t = static_cast<int32_t>(T.t.size() / 3);
-  L.nslab = static_cast<int32_t>((L.ldc + 127) / 128);  // enough for both slab widths
   L.nparts = residual_parts(N);
   size_t cur = 0;
   auto take = [&](int64_t bytes) {
@@ -116,23 +126,23 @@ Layout make_layout(int64_t N, int64_t n, const int64_t* off, int32_t m, int32_t 
   L.C32 = take(prec == APC_F32 ? N * L.ldc * 4 : 0);
   L.x = take(m * L.ldc * d);
   L.xbar = take(L.ldc * d);
-  L.w = take(N * d);
+  L.dv = take(m * L.ldc * d);
+  L.w = take(kMaxSplit * N * d);
   L.ca = take(N * d);
   L.cb = take(N * d);
   L.Y = take(m * L.ldc * d);
   L.vtmp = take(L.ldc * d);
   L.V = take((L.kmax + 1) * L.ldc * d);
-  L.h = take((L.kmax + 1) * d);
-  L.h2 = take((L.kmax + 1) * d);
+  L.h = take(kMaxSplit * (L.kmax + 1) * d);
+  L.h2 = take(kMaxSplit * (L.kmax + 1) * d);
   L.alpha = take((L.kmax + 1) * d);
   L.beta = take((L.kmax + 1) * d);
   L.G = take(L.S * d);
   L.Linv = take(L.S * d);
-  L.counters = take(L.nslab * 4);
   L.flags = take(4 * 4);
   L.scal = take(8 * d);
   L.partial = take(L.nparts * d);
-  L.tiles_a = take(3 * static_cast<int64_t>(L.ntiles_a) * 4);
+  L.tiles_a = take(3 * max_tiles_a * 4);
   L.tiles_g = take(3 * static_cast<int64_t>(L.ntiles_g) * 4);
   L.tiles_t = take(3 * static_cast<int64_t>(L.ntiles_t) * 4);
   L.doff = take((m + 1) * 8);
@@ -263,8 +273,12 @@ struct apc_plan_s {
   double mu_min = NAN, mu_max = NAN, rho = NAN;
   int64_t iters = 0;
   double bnorm = 0;
-  int32_t xcd_remap = 1, passb_order = 0;
-  hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
+  int lanczos_steps = 0;
+  int32_t xcd_remap = 1, passa_rows = kRowTile, nsplit = 1;
+  int64_t split_cols = 0;
+  int32_t group_blocks = 0;            // blocks per pass-A/pass-B group (MALL reuse)
+  std::vector<int32_t> tile_start;     // first pass-A tile of every block (m+1)
+  std::vector<hipEvent_t> events;
 
   template <typename T>
   T* at(size_t o) const { return reinterpret_cast<T*>(ws + o); }
@@ -273,89 +287,149 @@ struct apc_plan_s {
   double* xbar() const { return at<double>(L.xbar); }
   int64_t* doff() const { return at<int64_t>(L.doff); }
   int32_t* ta(int which) const { return at<int32_t>(L.tiles_a) + which * L.ntiles_a; }
+  int32_t slab_cols() const { return pass_b_slab(prec == APC_F32 ? 4 : 8); }
 };
 
 namespace {
 
-apc_status pass_a(apc_plan_s* P, const double* va, const double* vb, int64_t ldvb) {
+// Pass A over blocks [i0, i1): w = C d with d_i = x_bar - x_i precomputed by
+// the previous average (or by setup).
+apc_status pass_a(apc_plan_s* P, int i0, int i1) {
+  const int32_t t0 = P->tile_start[i0], nt = P->tile_start[i1] - t0;
   if (P->prec == APC_F32) {
-    RowdotArgs<float> a{P->at<float>(P->L.C32), P->L.ldc, P->ta(0), P->ta(1), P->ta(2),
-                        P->L.ntiles_a, 0, va, vb, ldvb, P->at<float>(P->L.w), P->xcd_remap};
+    RowdotArgs<float> a{P->at<float>(P->L.C32), P->L.ldc, P->ta(0), P->ta(1), P->ta(2), nt, 0,
+                        nullptr, nullptr, 0, P->at<float>(P->L.dv), P->L.ldc,
+                        P->at<float>(P->L.w), P->N, P->nsplit, P->split_cols, P->xcd_remap,
+                        P->passa_rows, t0};
     HIP_TRY(launch_rowdot_f32(a, P->stream));
   } else {
-    RowdotArgs<double> a{P->C64(), P->L.ldc, P->ta(0), P->ta(1), P->ta(2), P->L.ntiles_a, 0, va,
-                         vb, ldvb, P->at<double>(P->L.w), P->xcd_remap};
+    RowdotArgs<double> a{P->C64(), P->L.ldc, P->ta(0), P->ta(1), P->ta(2), nt, 0, nullptr,
+                         nullptr, 0, P->at<double>(P->L.dv), P->L.ldc, P->at<double>(P->L.w),
+                         P->N, P->nsplit, P->split_cols, P->xcd_remap, P->passa_rows, t0};
     HIP_TRY(launch_rowdot_f64(a, P->stream));
   }
   return APC_OK;
 }
 
-apc_status pass_b(apc_plan_s* P) {
+// x_bar <- alpha sum_i x_i + beta x_bar, and the differences d_i for pass A.
+apc_status average(apc_plan_s* P, double alpha, double beta) {
+  if (P->prec == APC_F32)
+    HIP_TRY(launch_combine_f32(P->x(), P->L.ldc, P->m, P->L.ldc, alpha, beta, P->xbar(),
+                               P->at<float>(P->L.dv), P->L.ldc, P->stream));
+  else
+    HIP_TRY(launch_combine_f64(P->x(), P->L.ldc, P->m, P->L.ldc, alpha, beta, P->xbar(),
+                               P->at<double>(P->L.dv), P->L.ldc, P->stream));
+  return APC_OK;
+}
+
+// Pass B over blocks [i0, i1): x_i += gamma (x_bar - x_i - Q_i w_i).
+apc_status pass_b(apc_plan_s* P, int i0, int i1) {
+  const int32_t nslab = static_cast<int32_t>((P->L.ldc + P->slab_cols() - 1) / P->slab_cols());
   if (P->prec == APC_F32) {
-    const int32_t nslab = static_cast<int32_t>((P->L.ldc + 255) / 256);
-    PassBArgs<float> a{P->at<float>(P->L.C32), P->L.ldc, P->doff(), P->m, nslab,
-                       P->at<float>(P->L.w), P->x(), P->L.ldc, P->xbar(), P->gamma, P->eta,
-                       P->at<unsigned>(P->L.counters), P->passb_order};
+    PassBArgs<float> a{P->at<float>(P->L.C32), P->L.ldc, P->doff(), i1 - i0, nslab,
+                       P->at<float>(P->L.w), P->nsplit, P->N, P->x(), P->L.ldc, P->xbar(),
+                       P->gamma, i0};
     HIP_TRY(launch_pass_b_f32(a, P->stream));
   } else {
-    const int32_t nslab = static_cast<int32_t>((P->L.ldc + 127) / 128);
-    PassBArgs<double> a{P->C64(), P->L.ldc, P->doff(), P->m, nslab, P->at<double>(P->L.w),
-                        P->x(), P->L.ldc, P->xbar(), P->gamma, P->eta,
-                        P->at<unsigned>(P->L.counters), P->passb_order};
+    PassBArgs<double> a{P->C64(), P->L.ldc, P->doff(), i1 - i0, nslab, P->at<double>(P->L.w),
+                        P->nsplit, P->N, P->x(), P->L.ldc, P->xbar(), P->gamma, i0};
     HIP_TRY(launch_pass_b_f64(a, P->stream));
   }
   return APC_OK;
 }
 
-// y_i = alpha * Q_i w_i + beta * y_i over all blocks of the FP64 factor.
-apc_status expand_blocks(apc_plan_s* P, const double* w, double* y, double alpha, double beta) {
-  ExpandArgs e{P->C64(), P->L.ldc, P->doff(), P->m, static_cast<int32_t>((P->L.ldc + 127) / 128),
-               P->N, w, y, P->L.ldc, alpha, beta};
-  HIP_TRY(launch_expand(e, P->stream));
+// One update of eq. (2a)-(2b): for each group of blocks, pass A then pass B
+// (pass B of a block needs only that block's w, so a group's rows of C are
+// re-read while they are still in the Infinity Cache), then the average.
+// With ev non-null, an event is recorded after every launch and the launch
+// kinds (0 pass A, 1 pass B, 2 average) are appended to kinds.
+apc_status update(apc_plan_s* P, hipEvent_t* ev, int* kinds) {
+  const int g = P->group_blocks > 0 ? P->group_blocks : P->m;
+  int e = 0;
+  for (int i0 = 0; i0 < P->m; i0 += g) {
+    const int i1 = std::min(P->m, i0 + g);
+    ST_TRY(pass_a(P, i0, i1));
+    if (ev) { HIP_TRY(hipEventRecord(ev[e], P->stream)); kinds[e++] = 0; }
+    ST_TRY(pass_b(P, i0, i1));
+    if (ev) { HIP_TRY(hipEventRecord(ev[e], P->stream)); kinds[e++] = 1; }
+  }
+  ST_TRY(average(P, P->eta / P->m, 1.0 - P->eta));
+  if (ev) { HIP_TRY(hipEventRecord(ev[e], P->stream)); kinds[e++] = 2; }
   return APC_OK;
 }
 
-// FP64 u = C v (all rows), uniform or block tiling.
-apc_status rowdot64(apc_plan_s* P, const double* C, int32_t rows, const double* va,
-                    const double* vb, int64_t ldvb, bool block_tiles, double* out) {
-  RowdotArgs<double> a{};
-  a.C = C;
-  a.ldc = P->L.ldc;
-  if (block_tiles) {
-    a.tile_row0 = P->ta(0);
-    a.tile_nrows = P->ta(1);
-    a.tile_blk = P->ta(2);
-    a.ntiles = P->L.ntiles_a;
-  } else {
-    a.ntiles = (rows + kRowTile - 1) / kRowTile;
-    a.rows_total = rows;
-  }
-  a.va = va;
-  a.vb = vb;
-  a.ldvb = ldvb;
-  a.out = out;
-  a.xcd_remap = 0;
+int launches_per_update(const apc_plan_s* P) {
+  const int g = P->group_blocks > 0 ? P->group_blocks : P->m;
+  return 2 * ((P->m + g - 1) / g) + 1;
+}
+
+// y_i = alpha * Q_i w_i + beta * y_i over all blocks of the FP64 factor.
+apc_status expand_blocks(apc_plan_s* P, const double* w, double* y, double alpha, double beta) {
+  ExpandArgs<double> e{P->C64(), P->L.ldc, P->doff(), P->m,
+                       static_cast<int32_t>((P->L.ldc + expand_slab(8) - 1) / expand_slab(8)),
+                       P->N, w, 1, 0, y, P->L.ldc, alpha, beta, 0};
+  HIP_TRY(launch_expand_f64(e, P->stream));
+  return APC_OK;
+}
+
+// FP64 out = C d over the block tiles, d_i = va - vb_i (va or vb may be null).
+apc_status rowdot64(apc_plan_s* P, const double* va, const double* vb, int64_t ldvb,
+                    double* out) {
+  RowdotArgs<double> a{P->C64(), P->L.ldc, P->ta(0), P->ta(1), P->ta(2), P->L.ntiles_a, 0, va,
+                       vb, ldvb, nullptr, 0, out, 0, 1, P->L.ldc, 0, P->passa_rows, 0};
   HIP_TRY(launch_rowdot_f64(a, P->stream));
   return APC_OK;
 }
 
-#define ST_TRY(expr)              \
-  do {                            \
-    apc_status s_ = (expr);       \
-    if (s_ != APC_OK) return s_;  \
-  } while (0)
+// X v for the eigenvalue estimate, through the factor the iteration uses
+// (FP64, or FP32 storage with FP64 accumulation): u = C v, Y_i = Q_i u_i,
+// out = (1/m) sum_i Y_i.
+apc_status x_matvec(apc_plan_s* P, const double* v, double* out) {
+  const Layout& L = P->L;
+  double* u = P->at<double>(L.w);
+  double* Y = P->at<double>(L.Y);
+  const int g = P->group_blocks > 0 ? P->group_blocks : P->m;
+  for (int i0 = 0; i0 < P->m; i0 += g) {
+    const int i1 = std::min(P->m, i0 + g);
+    const int32_t t0 = P->tile_start[i0], nt = P->tile_start[i1] - t0;
+    if (P->prec == APC_F32) {
+      RowdotArgs<float, double> a{P->at<float>(L.C32), L.ldc, P->ta(0), P->ta(1), P->ta(2), nt, 0,
+                                  v, nullptr, 0, nullptr, 0, u, 0, 1, L.ldc, P->xcd_remap,
+                                  P->passa_rows, t0};
+      HIP_TRY(launch_rowdot_f32x64(a, P->stream));
+      ExpandArgs<float> e{P->at<float>(L.C32), L.ldc, P->doff(), i1 - i0,
+                          static_cast<int32_t>((L.ldc + expand_slab(4) - 1) / expand_slab(4)),
+                          P->N, u, 1, 0, Y, L.ldc, 1.0, 0.0, i0};
+      HIP_TRY(launch_expand_f32(e, P->stream));
+    } else {
+      RowdotArgs<double, double> a{P->C64(), L.ldc, P->ta(0), P->ta(1), P->ta(2), nt, 0, v,
+                                   nullptr, 0, nullptr, 0, u, 0, 1, L.ldc, P->xcd_remap,
+                                   P->passa_rows, t0};
+      HIP_TRY(launch_rowdot_f64(a, P->stream));
+      ExpandArgs<double> e{P->C64(), L.ldc, P->doff(), i1 - i0,
+                           static_cast<int32_t>((L.ldc + expand_slab(8) - 1) / expand_slab(8)),
+                           P->N, u, 1, 0, Y, L.ldc, 1.0, 0.0, i0};
+      HIP_TRY(launch_expand_f64(e, P->stream));
+    }
+  }
+  HIP_TRY(launch_combine_f64(Y, L.ldc, P->m, L.ldc, 1.0 / P->m, 0.0, out, nullptr, 0, P->stream));
+  return APC_OK;
+}
 
 // Lanczos with full (twice classical Gram-Schmidt) reorthogonalisation on
-// X v = (1/m) sum_i Q_i (Q_i^T v), in FP64 on the GPU.  Returns an interval
-// [lo, hi] that encloses the spectrum of X up to the Ritz residual bounds.
-apc_status lanczos(apc_plan_s* P, double* lo_out, double* hi_out, double* theta_lo,
-                   double* theta_hi) {
+// X v = (1/m) sum_i Q_i (Q_i^T v), on the GPU in FP64 arithmetic.  Returns an
+// interval [lo, hi] for Theorem 1's closed form.  Ritz values lie inside the
+// spectrum: hi gets a margin above the converged largest Ritz value
+// (underestimating mu_max can make the iteration diverge); lo is the smallest
+// Ritz value, an estimate from above (overestimating mu_min only slows
+// convergence: for any mu in (0, lo) the roots of p_i stay inside the unit
+// disc).
+apc_status lanczos(apc_plan_s* P, double* lo_out, double* hi_out, int* steps_out) {
   const int64_t ldc = P->L.ldc, n = P->n;
   const int kmax = static_cast<int>(P->L.kmax);
+  const int64_t hstride = P->L.kmax + 1;
   double* V = P->at<double>(P->L.V);
   double* vt = P->at<double>(P->L.vtmp);
-  double* Y = P->at<double>(P->L.Y);
-  double* u = P->at<double>(P->L.w);
   double* h = P->at<double>(P->L.h);
   double* h2 = P->at<double>(P->L.h2);
   double* al = P->at<double>(P->L.alpha);
@@ -373,24 +447,33 @@ apc_status lanczos(apc_plan_s* P, double* lo_out, double* hi_out, double* theta_
   HIP_TRY(hipMemcpyAsync(V, v0.data(), ldc * sizeof(double), hipMemcpyHostToDevice, P->stream));
   HIP_TRY(hipStreamSynchronize(P->stream));
 
-  const int32_t nslab = static_cast<int32_t>((ldc + 127) / 128);
+  // Reorthogonalisation GEMVs against V (j+1 rows) use column splits so that
+  // enough workgroups run even for a few rows.
+  const int64_t chunk = rowdot_chunk<double>();
+  const int64_t want = std::min<int64_t>(kMaxSplit, std::max<int64_t>(1, (ldc + chunk - 1) / chunk));
+  const int64_t scols = round_up((ldc + want - 1) / want, chunk);
+  const int32_t ns = static_cast<int32_t>((ldc + scols - 1) / scols);
+  const int32_t nslab = static_cast<int32_t>((ldc + expand_slab(8) - 1) / expand_slab(8));
+
   std::vector<double> a, b;
   double th_lo = 0, th_hi = 0, bd_lo = INFINITY, bd_hi = INFINITY;
+  double prev_lo = NAN, prev_hi = NAN;
   bool done = false;
+  int steps = 0;
   for (int j = 0; j < kmax && !done; ++j) {
-    double* vj = V + static_cast<int64_t>(j) * ldc;
-    ST_TRY(rowdot64(P, P->C64(), static_cast<int32_t>(P->N), vj, nullptr, 0, true, u));
-    ST_TRY(expand_blocks(P, u, Y, 1.0, 0.0));
-    HIP_TRY(launch_block_sum(Y, ldc, P->m, ldc, 1.0 / P->m, vt, P->stream));
+    ST_TRY(x_matvec(P, V + static_cast<int64_t>(j) * ldc, vt));
     for (int pass = 0; pass < 2; ++pass) {
       double* hh = pass == 0 ? h : h2;
-      ST_TRY(rowdot64(P, V, j + 1, vt, nullptr, 0, false, hh));
-      ExpandArgs e{V, ldc, nullptr, 1, nslab, j + 1, hh, vt, 0, -1.0, 1.0};
-      HIP_TRY(launch_expand(e, P->stream));
+      RowdotArgs<double> r{V, ldc, nullptr, nullptr, nullptr, (j + 1 + 7) / 8, j + 1, vt, nullptr,
+                           0, nullptr, 0, hh, hstride, ns, scols, 0, 8, 0};
+      HIP_TRY(launch_rowdot_f64(r, P->stream));
+      ExpandArgs<double> e{V, ldc, nullptr, 1, nslab, j + 1, hh, ns, hstride, vt, 0, -1.0, 1.0, 0};
+      HIP_TRY(launch_expand_f64(e, P->stream));
     }
-    HIP_TRY(launch_lanczos_normalize(vt, ldc, h, h2, j, al, be, V + static_cast<int64_t>(j + 1) * ldc,
-                                     P->stream));
+    HIP_TRY(launch_lanczos_normalize(vt, ldc, h, h2, ns, hstride, j, al, be,
+                                     V + static_cast<int64_t>(j + 1) * ldc, P->stream));
     const int k = j + 1;
+    steps = k;
     if (k % kLanczosCheck != 0 && k != kmax) continue;
     a.resize(k);
     b.resize(k);
@@ -418,21 +501,27 @@ apc_status lanczos(apc_plan_s* P, double* lo_out, double* hi_out, double* theta_
       bd_lo = std::min(bd_lo, 1e-13 * th_hi);
       bd_hi = std::min(bd_hi, 1e-13 * th_hi);
     }
-    const bool hi_ok = bd_hi <= 1e-12 * th_hi;
-    const bool lo_ok = bd_lo <= 1e-6 * th_lo || bd_lo <= 1e-14 * th_hi;
+    // Converged ends: a small residual bound, or a Ritz value that has
+    // stopped moving since the previous check (with a loose bound as a guard
+    // against an early plateau).
+    const bool hi_ok = bd_hi <= 1e-10 * th_hi ||
+                       (std::fabs(th_hi - prev_hi) <= 1e-9 * th_hi && bd_hi <= 1e-3 * th_hi);
+    const bool lo_ok = bd_lo <= 1e-6 * th_lo ||
+                       (std::fabs(th_lo - prev_lo) <= 1e-4 * th_lo && bd_lo <= 0.1 * th_lo);
+    prev_lo = th_lo;
+    prev_hi = th_hi;
     done = exhausted || (hi_ok && lo_ok);
   }
-  *theta_lo = th_lo;
-  *theta_hi = th_hi;
+  *steps_out = steps;
   if (!done)
     return fail(APC_ENOCONV, "eigenvalue estimate did not converge in %d Lanczos steps "
                 "(theta in [%g, %g], bounds %g, %g); pass gamma and eta explicitly", kmax,
                 th_lo, th_hi, bd_lo, bd_hi);
-  if (!(th_lo > n * std::numeric_limits<double>::epsilon() * th_hi) || th_lo - bd_lo <= 0.0)
+  if (!(th_lo > n * std::numeric_limits<double>::epsilon() * th_hi))
     return fail(APC_ESINGULAR, "mu_min(X) ~ 0 (Ritz value %g, mu_max %g): no unique solution",
                 th_lo, th_hi);
-  *lo_out = th_lo - bd_lo;
-  *hi_out = std::min(th_hi + bd_hi, 1.0);
+  *lo_out = bd_lo <= 1e-6 * th_lo ? th_lo - bd_lo : th_lo;
+  *hi_out = std::min(th_hi + std::max(std::min(bd_hi, 1e-8 * th_hi), 1e-13 * th_hi), 1.0);
   return APC_OK;
 }
 
@@ -472,7 +561,6 @@ apc_status setup_impl(apc_plan_s* P, const Tiles& T) {
   HIP_TRY(hipMemcpyAsync(P->at<int32_t>(L.tiles_t), T.t.data(), T.t.size() * 4, hipMemcpyHostToDevice, st));
   HIP_TRY(hipMemcpyAsync(P->doff(), P->off.data(), (m + 1) * 8, hipMemcpyHostToDevice, st));
   HIP_TRY(hipMemcpyAsync(P->at<int64_t>(L.goff), T.goff.data(), m * 8, hipMemcpyHostToDevice, st));
-  HIP_TRY(launch_fill_u32(P->at<unsigned>(L.counters), L.nslab, 0u, st));
   HIP_TRY(launch_fill_u32(P->at<unsigned>(L.flags), 4, 0u, st));
 
   // ||b||^2 for the residual monitor.
@@ -513,13 +601,13 @@ apc_status setup_impl(apc_plan_s* P, const Tiles& T) {
   // Alg. 1 initialisation: x_i(0) = Q_i c_i (minimum-norm local solutions),
   // x_bar(0) = (1/m) sum_i x_i(0).
   ST_TRY(expand_blocks(P, ca, P->x(), 1.0, 0.0));
-  HIP_TRY(launch_block_sum(P->x(), ldc, m, ldc, 1.0 / m, P->xbar(), st));
+  ST_TRY(average(P, 1.0 / m, 0.0));
   if (P->prec == APC_F32) HIP_TRY(launch_cast_f32(Ca, P->at<float>(L.C32), N * ldc, st));
 
   // Parameters: caller's, or Theorem 1's optimum from the estimated spectrum.
   if (std::isnan(P->gamma) || std::isnan(P->eta)) {
-    double lo = 0, hi = 0, tl = 0, th = 0;
-    ST_TRY(lanczos(P, &lo, &hi, &tl, &th));
+    double lo = 0, hi = 0;
+    ST_TRY(lanczos(P, &lo, &hi, &P->lanczos_steps));
     P->mu_min = lo;
     P->mu_max = hi;
     optimum(lo, hi, &P->gamma, &P->eta, &P->rho);
@@ -538,7 +626,7 @@ size_t apc_workspace_bytes(int64_t N, int64_t n, const int64_t* off, int32_t m, 
                            int32_t precision) {
   if (validate(N, n, off, m, k, precision) != APC_OK) return 0;
   Tiles T;
-  build_tiles(off, m, round_up(n, kLdAlign), &T);
+  build_tiles(off, m, round_up(n, kLdAlign), kPassARows, &T);
   return make_layout(N, n, off, m, precision, T).total;
 }
 
@@ -559,8 +647,17 @@ apc_status apc_setup(apc_plan* out, const double* A, int64_t lda, const double* 
   const bool given = !std::isnan(gamma) && !std::isnan(eta);
   if (given && (!std::isfinite(gamma) || !std::isfinite(eta)))
     return fail(APC_EINVAL, "gamma and eta must be finite (or NaN for the optimum)");
+  // Launch-shape knobs (defaults are the tuned ones; the environment may override).
+  int32_t xcd_remap = 1, passa_rows = kPassARows, nsplit_req = 0, group_blocks = -1;
+  if (const char* e = std::getenv("APC_XCD_REMAP")) xcd_remap = std::atoi(e) != 0;
+  if (const char* e = std::getenv("APC_PASSA_SPLIT")) nsplit_req = std::atoi(e);
+  if (const char* e = std::getenv("APC_GROUP_BLOCKS")) group_blocks = std::atoi(e);
+  if (const char* e = std::getenv("APC_PASSA_ROWS")) {
+    const int r = std::atoi(e);
+    if (r == 8 || r == 16 || r == 32) passa_rows = r;
+  }
   Tiles T;
-  build_tiles(off, m, round_up(n, kLdAlign), &T);
+  build_tiles(off, m, round_up(n, kLdAlign), passa_rows, &T);
   const Layout L = make_layout(N, n, off, m, precision, T);
   if (ws_bytes < L.total)
     return fail(APC_EINVAL, "workspace has %zu bytes, needs %zu", ws_bytes, L.total);
@@ -587,8 +684,25 @@ apc_status apc_setup(apc_plan* out, const double* A, int64_t lda, const double* 
   P->ldb = ldb;
   P->gamma = given ? gamma : NAN;
   P->eta = given ? eta : NAN;
-  if (const char* e = std::getenv("APC_XCD_REMAP")) P->xcd_remap = std::atoi(e) != 0;
-  if (const char* e = std::getenv("APC_PASSB_ORDER")) P->passb_order = std::atoi(e) != 0;
+  P->xcd_remap = xcd_remap;
+  P->passa_rows = passa_rows;
+  P->tile_start.assign(1, 0);
+  for (int i = 0; i < m; ++i)
+    P->tile_start.push_back(P->tile_start.back() +
+                            static_cast<int32_t>((off[i + 1] - off[i] + passa_rows - 1) / passa_rows));
+  P->group_blocks = group_blocks >= 0 ? group_blocks : 0;
+  {
+    // Column splits of pass A: about 4096 workgroups (16 per CU, measured best
+    // for streaming at the 16384 x 8192 shape), each split at least one
+    // register chunk wide.
+    const int64_t chunk = precision == APC_F32 ? rowdot_chunk<float>() : rowdot_chunk<double>();
+    const int64_t max_split = std::max<int64_t>(1, (L.ldc + chunk - 1) / chunk);
+    int64_t want = nsplit_req > 0 ? nsplit_req
+                                  : (4096 + L.ntiles_a - 1) / std::max<int32_t>(L.ntiles_a, 1);
+    want = std::max<int64_t>(1, std::min<int64_t>({want, max_split, kMaxSplit}));
+    P->split_cols = round_up((L.ldc + want - 1) / want, chunk);
+    P->nsplit = static_cast<int32_t>((L.ldc + P->split_cols - 1) / P->split_cols);
+  }
   st = setup_impl(P, T);
   if (st != APC_OK) {
     (void)hipStreamSynchronize(P->stream);
@@ -602,36 +716,42 @@ apc_status apc_setup(apc_plan* out, const double* A, int64_t lda, const double* 
 apc_status apc_iterate(apc_plan p, int32_t T) {
   if (!p) return fail(APC_EINVAL, "plan is NULL");
   if (T < 0) return fail(APC_EINVAL, "T must be >= 0");
-  for (int32_t t = 0; t < T; ++t) {
-    ST_TRY(pass_a(p, p->xbar(), p->x(), p->L.ldc));
-    ST_TRY(pass_b(p));
-  }
+  for (int32_t t = 0; t < T; ++t) ST_TRY(update(p, nullptr, nullptr));
   p->iters += T;
   return APC_OK;
 }
 
-apc_status apc_iterate_timed(apc_plan p, int32_t T, float* ms_pass_a, float* ms_pass_b) {
+apc_status apc_iterate_timed(apc_plan p, int32_t T, float* ms_total, float* ms_pass_a,
+                             float* ms_pass_b, float* ms_average) {
   if (!p) return fail(APC_EINVAL, "plan is NULL");
   if (T < 0) return fail(APC_EINVAL, "T must be >= 0");
-  for (auto& e : p->ev)
-    if (!e) HIP_TRY(hipEventCreate(&e));
-  float sa = 0.f, sb = 0.f;
-  for (int32_t t = 0; t < T; ++t) {
-    HIP_TRY(hipEventRecord(p->ev[0], p->stream));
-    ST_TRY(pass_a(p, p->xbar(), p->x(), p->L.ldc));
-    HIP_TRY(hipEventRecord(p->ev[1], p->stream));
-    ST_TRY(pass_b(p));
-    HIP_TRY(hipEventRecord(p->ev[2], p->stream));
-    HIP_TRY(hipEventSynchronize(p->ev[2]));
-    float a = 0.f, b = 0.f;
-    HIP_TRY(hipEventElapsedTime(&a, p->ev[0], p->ev[1]));
-    HIP_TRY(hipEventElapsedTime(&b, p->ev[1], p->ev[2]));
-    sa += a;
-    sb += b;
+  const int per = launches_per_update(p);
+  const size_t need = static_cast<size_t>(T) * per + 1;
+  while (p->events.size() < need) {
+    hipEvent_t e = nullptr;
+    HIP_TRY(hipEventCreate(&e));
+    p->events.push_back(e);
   }
+  std::vector<int> kinds(need, -1);
+  if (T > 0) HIP_TRY(hipEventRecord(p->events[0], p->stream));
+  for (int32_t t = 0; t < T; ++t)
+    ST_TRY(update(p, p->events.data() + 1 + static_cast<size_t>(t) * per,
+                  kinds.data() + 1 + static_cast<size_t>(t) * per));
   p->iters += T;
-  if (ms_pass_a) *ms_pass_a = sa;
-  if (ms_pass_b) *ms_pass_b = sb;
+  float sums[3] = {0.f, 0.f, 0.f}, tot = 0.f;
+  if (T > 0) {
+    HIP_TRY(hipEventSynchronize(p->events[need - 1]));
+    for (size_t e = 1; e < need; ++e) {
+      float ms = 0.f;
+      HIP_TRY(hipEventElapsedTime(&ms, p->events[e - 1], p->events[e]));
+      sums[kinds[e]] += ms;
+    }
+    HIP_TRY(hipEventElapsedTime(&tot, p->events[0], p->events[need - 1]));
+  }
+  if (ms_total) *ms_total = tot;
+  if (ms_pass_a) *ms_pass_a = sums[0];
+  if (ms_pass_b) *ms_pass_b = sums[1];
+  if (ms_average) *ms_average = sums[2];
   return APC_OK;
 }
 
@@ -693,9 +813,7 @@ apc_status apc_project(apc_plan p, const double* V, double* Out, int64_t ldv) {
   // Y_i <- V_i zero-padded to ldc; w = Q_i^T (0 - Y_i) = -Q_i^T V_i; Y_i += Q_i w.
   HIP_TRY(launch_fill_u32(reinterpret_cast<unsigned*>(Y), 2 * p->m * L.ldc, 0u, p->stream));
   HIP_TRY(launch_copy_strided(V, ldv, Y, L.ldc, p->m, p->n, p->stream));
-  HIP_TRY(launch_fill_u32(p->at<unsigned>(L.vtmp), 2 * L.ldc, 0u, p->stream));
-  ST_TRY(rowdot64(p, p->C64(), static_cast<int32_t>(p->N), p->at<double>(L.vtmp), Y, L.ldc, true,
-                  p->at<double>(L.w)));
+  ST_TRY(rowdot64(p, nullptr, Y, L.ldc, p->at<double>(L.w)));
   ST_TRY(expand_blocks(p, p->at<double>(L.w), Y, 1.0, 1.0));
   HIP_TRY(launch_copy_strided(Y, L.ldc, Out, ldv, p->m, p->n, p->stream));
   return APC_OK;
@@ -741,12 +859,21 @@ apc_status apc_tridiag_extremes(const double* alpha, const double* beta, int32_t
   return APC_OK;
 }
 
+apc_status apc_get_info(apc_plan p, int32_t* lanczos_steps, int32_t* rows_per_tile,
+                        int32_t* column_splits, int32_t* block_groups) {
+  if (!p) return fail(APC_EINVAL, "plan is NULL");
+  if (lanczos_steps) *lanczos_steps = p->lanczos_steps;
+  if (rows_per_tile) *rows_per_tile = p->passa_rows;
+  if (column_splits) *column_splits = p->nsplit;
+  if (block_groups) *block_groups = (launches_per_update(p) - 1) / 2;
+  return APC_OK;
+}
+
 int64_t apc_iterations(apc_plan p) { return p ? p->iters : -1; }
 
 void apc_destroy(apc_plan p) {
   if (!p) return;
-  for (auto& e : p->ev)
-    if (e) (void)hipEventDestroy(e);
+  for (hipEvent_t e : p->events) (void)hipEventDestroy(e);
   delete p;
 }
 

@@ -18,69 +18,101 @@ constexpr int kXcds = 8;            // XCDs per MI355X; workgroups are dealt rou
 // Streaming kernels (hot path)
 // ---------------------------------------------------------------------------
 
-// out[row] = sum_j C[row][j] * d_blk[j] for every row of every tile, with
-// d_blk = va - vb[blk] (vb may be null: d = va), rounded to TQ.
-template <typename TQ>
+// out[split * out_stride + row] = sum_{j in split} C[row][j] * d_blk[j] for
+// every row of every tile, accumulated in TA, where d_blk is d + blk*ldd when
+// d is given, else va - vb[blk] (either may be null: 0) rounded to TA.
+// Columns are split into nsplit ranges of split_cols (a multiple of the
+// register chunk, rowdot_chunk<TQ>()).
+template <typename TQ, typename TA = TQ>
 struct RowdotArgs {
   const TQ* C;
   int64_t ldc;
   const int32_t* tile_row0;   // null: uniform tiling of rows_total rows
   const int32_t* tile_nrows;
   const int32_t* tile_blk;
-  int32_t ntiles;
+  int32_t ntiles;              // tiles in this launch, starting at tile_begin
   int32_t rows_total;
   const double* va;
   const double* vb;
   int64_t ldvb;
-  TQ* out;
+  const TA* d;
+  int64_t ldd;
+  TA* out;
+  int64_t out_stride;
+  int32_t nsplit;
+  int64_t split_cols;
   int32_t xcd_remap;          // 1: give each XCD a contiguous range of tiles
+  int32_t rows_per_tile;      // 8, 16 or 32 (must match the tile lists)
+  int32_t tile_begin;         // first tile of this launch (block-tile lists only)
 };
 
-// Pass B of eq. (2a)-(2b): x_i += gamma (x_bar - x_i - Q_i w_i), then the
-// last workgroup of each column slab forms x_bar <- (eta/m) sum_i x_i +
-// (1 - eta) x_bar for that slab.
+template <typename TQ>
+constexpr int rowdot_unroll() { return 2; }
+// Columns covered by one register chunk of pass A.
+template <typename TQ>
+constexpr int64_t rowdot_chunk() { return static_cast<int64_t>(kThreads) * (16 / sizeof(TQ)) * rowdot_unroll<TQ>(); }
+
+// Pass B of eq. (2a): x_i += gamma (x_bar - x_i - Q_i w_i), with
+// w = sum over pass A's nsplit partials (w + s * w_stride).
 template <typename TQ>
 struct PassBArgs {
   const TQ* C;
   int64_t ldc;
   const int64_t* off;
-  int32_t m;
+  int32_t m;                  // blocks in this launch, starting at blk_begin
   int32_t nslab;
   const TQ* w;
+  int32_t nsplit;
+  int64_t w_stride;
   double* x;
   int64_t ldx;
   double* xbar;
   double gamma;
-  double eta;
-  unsigned* counters;
-  int32_t order;              // 0: slab-major workgroup order, 1: reversed block-major
+  int32_t blk_begin;
 };
 
-// y_i = beta * y_i + alpha * sum_{r in block i} w[r] C[r][:]  (FP64).
-// off == null: a single block of rows_total rows.
+// Columns per pass-B slab for an element size.
+inline int pass_b_slab(int elem_bytes) { return kThreads * (16 / elem_bytes); }
+
+// y_i = beta * y_i + alpha * sum_{r in block i} w_r C[r][:], FP64 accumulation,
+// w_r = sum over nsplit partials (w + s * w_stride).  off == null: a single
+// block of rows_total rows.
+template <typename TQ>
 struct ExpandArgs {
-  const double* C;
+  const TQ* C;
   int64_t ldc;
   const int64_t* off;
   int32_t m;
-  int32_t nslab;
+  int32_t nslab;              // ceil(ldc / (64 * 16 / sizeof(TQ)))
   int64_t rows_total;
   const double* w;
+  int32_t nsplit;
+  int64_t w_stride;
   double* y;
   int64_t ldy;
   double alpha;
   double beta;
+  int32_t blk_begin;          // first block of this launch (off != null)
 };
 
-hipError_t launch_rowdot_f64(const RowdotArgs<double>& a, hipStream_t s);
-hipError_t launch_rowdot_f32(const RowdotArgs<float>& a, hipStream_t s);
+inline int expand_slab(int elem_bytes) { return 64 * (16 / elem_bytes); }
+
+hipError_t launch_rowdot_f64(const RowdotArgs<double, double>& a, hipStream_t s);
+hipError_t launch_rowdot_f32(const RowdotArgs<float, float>& a, hipStream_t s);
+hipError_t launch_rowdot_f32x64(const RowdotArgs<float, double>& a, hipStream_t s);
 hipError_t launch_pass_b_f64(const PassBArgs<double>& a, hipStream_t s);
 hipError_t launch_pass_b_f32(const PassBArgs<float>& a, hipStream_t s);
-hipError_t launch_expand(const ExpandArgs& a, hipStream_t s);
+hipError_t launch_expand_f64(const ExpandArgs<double>& a, hipStream_t s);
+hipError_t launch_expand_f32(const ExpandArgs<float>& a, hipStream_t s);
 
-// out[j] = scale * sum_{i<m} y[i*ldy + j] for j < n (fixed block order).
-hipError_t launch_block_sum(const double* y, int64_t ldy, int32_t m, int64_t n, double scale,
-                            double* out, hipStream_t s);
+// Eq. (2b) and the next differences: xbar[j] = alpha * sum_{i<m} x[i*ldx + j]
+// + beta * xbar[j] for j < n in a fixed order (wave w sums i = w, w+4, ...;
+// then (s0 + s1) + (s2 + s3)); beta == 0 does not read xbar.  If d is not
+// null, also d[i*ldd + j] = xbar[j] - x[i*ldx + j] rounded to its type.
+hipError_t launch_combine_f64(const double* x, int64_t ldx, int32_t m, int64_t n, double alpha,
+                              double beta, double* xbar, double* d, int64_t ldd, hipStream_t s);
+hipError_t launch_combine_f32(const double* x, int64_t ldx, int32_t m, int64_t n, double alpha,
+                              double beta, double* xbar, float* d, int64_t ldd, hipStream_t s);
 
 // ---------------------------------------------------------------------------
 // Setup kernels (FP64)
@@ -106,10 +138,11 @@ hipError_t launch_fill_u32(unsigned* p, int64_t count, unsigned v, hipStream_t s
 hipError_t launch_copy_strided(const double* src, int64_t lds, double* dst, int64_t ldd,
                                int64_t rows, int64_t cols, hipStream_t s);
 
-// Lanczos helpers: alpha[j] = h[j] + h2[j]; beta[j] = ||y||; V[j+1] = y / beta[j].
+// Lanczos helper: alpha[j] = sum_s h[s*hstride + j] + sum_s h2[s*hstride + j];
+// beta[j] = ||y||; V[j+1] = y / beta[j].
 hipError_t launch_lanczos_normalize(const double* y, int64_t n, const double* h, const double* h2,
-                                    int32_t j, double* alpha, double* beta, double* vnext,
-                                    hipStream_t s);
+                                    int32_t nsplit, int64_t hstride, int32_t j, double* alpha,
+                                    double* beta, double* vnext, hipStream_t s);
 
 // ---------------------------------------------------------------------------
 // Residual monitor (FP64)

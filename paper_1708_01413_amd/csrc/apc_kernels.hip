@@ -1,17 +1,20 @@
 // HIP kernels (gfx950, wave64) for Accelerated Projection-based Consensus.
 //
 // Hot path, per update of eq. (2a)-(2b):
-//   pass A  (k_rowdot)  w_i = Q_i^T (x_bar - x_i): one dot product per row of
-//           the stacked factor C = [Q_1^T; ...; Q_m^T] (N x ldc, row-major),
-//           streamed once with 16-byte loads, the difference vector held in
-//           registers, one wave-level reduction per row.
+//   pass A  (k_rowdot)  w_i = Q_i^T d_i, d_i = x_bar - x_i: one dot product
+//           per row of the stacked factor C = [Q_1^T; ...; Q_m^T] (N x ldc,
+//           row-major), streamed once with 16-byte loads, the difference
+//           vector held in registers, one wave-level reduction per row.
 //   pass B  (k_pass_b)  x_i += gamma (x_bar - x_i - Q_i w_i): each workgroup
-//           owns one column slab of one block and streams that block's rows
-//           once; the momentum average of eq. (2b) is fused into the
-//           epilogue: the last workgroup to finish a slab (atomic ticket)
-//           sums the m new x_i of that slab in block order and writes x_bar.
+//           owns a 4 KB column slab of one block and streams that block's
+//           rows once.
+//   average (k_combine) x_bar <- (eta/m) sum_i x_i + (1 - eta) x_bar in a
+//           fixed summation order, and d_i = x_bar - x_i for the next pass A.
 // Both passes are HBM-bound (one FMA per streamed element), so they are
-// written for coalescing and memory-level parallelism, not for MFMA.
+// written for coalescing and memory-level parallelism, not for MFMA.  The
+// average is a launch of its own: folding it into pass B's epilogue needs a
+// device-scope release per workgroup, which on a multi-XCD part writes back
+// L2 and measured slower than the extra launch.
 //
 // Setup (FP64): CholeskyQR2 of every A_i^T -- Gram G_i = C_i C_i^T (LDS-tiled),
 // per-block Cholesky + triangular inverse, C_i <- L_i^{-1} C_i -- applied
@@ -61,48 +64,63 @@ inline unsigned grid_for(int64_t work, int per) {
 
 // ------------------------------------------------------------------ pass A
 
-template <typename TQ, int ROWS, int U>
-__global__ __launch_bounds__(kThreads) void k_rowdot(RowdotArgs<TQ> a) {
+// One workgroup per (row tile, column split).  The difference vector d of the
+// tile's block is held in registers one chunk (U sweeps of 256 x 16 B) at a
+// time; every row of the tile is streamed with 16-byte loads against it.
+template <typename TQ, typename TA, int ROWS, int U>
+__global__ __launch_bounds__(kThreads) void k_rowdot(RowdotArgs<TQ, TA> a) {
   constexpr int W = V16<TQ>::W;
   constexpr int SWEEP = kThreads * W;
   constexpr int CH = SWEEP * U;
 
-  int L = blockIdx.x;
+  const int total = a.ntiles * a.nsplit;
+  int q = blockIdx.x;
   if (a.xcd_remap) {
-    const int per = (a.ntiles + kXcds - 1) / kXcds;
-    L = (blockIdx.x % kXcds) * per + blockIdx.x / kXcds;
+    const int per = (total + kXcds - 1) / kXcds;
+    q = (blockIdx.x % kXcds) * per + blockIdx.x / kXcds;
   }
-  if (L >= a.ntiles) return;
+  if (q >= total) return;
+  const int Lrel = q / a.nsplit;
+  const int split = q - Lrel * a.nsplit;
+  const int L = a.tile_begin + Lrel;
   int row0, nrows, blk;
   if (a.tile_row0) {
     row0 = a.tile_row0[L];
     nrows = a.tile_nrows[L];
     blk = a.tile_blk[L];
   } else {
-    row0 = L * ROWS;
+    row0 = Lrel * ROWS;
     nrows = min(ROWS, a.rows_total - row0);
     blk = 0;
   }
+  const int64_t c0 = static_cast<int64_t>(split) * a.split_cols;
+  const int64_t c1 = min(a.ldc, c0 + a.split_cols);
   const double* vb = a.vb ? a.vb + static_cast<int64_t>(blk) * a.ldvb : nullptr;
+  const TA* dblk = a.d ? a.d + static_cast<int64_t>(blk) * a.ldd : nullptr;
   const int tcol = threadIdx.x * W;
 
-  TQ acc[ROWS];
+  TA acc[ROWS];
 #pragma unroll
-  for (int r = 0; r < ROWS; ++r) acc[r] = TQ(0);
+  for (int r = 0; r < ROWS; ++r) acc[r] = TA(0);
 
-  for (int64_t base = 0; base < a.ldc; base += CH) {
-    TQ d[U][W];
+  for (int64_t base = c0; base < c1; base += CH) {
+    TA d[U][W];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int64_t j = base + u * SWEEP + tcol;
+      if (dblk) {
 #pragma unroll
-      for (int e = 0; e < W; ++e) {
-        double v = 0.0;
-        if (j < a.ldc) {
-          v = a.va[j + e];
-          if (vb) v -= vb[j + e];
+        for (int e = 0; e < W; ++e) d[u][e] = j < c1 ? dblk[j + e] : TA(0);
+      } else {
+#pragma unroll
+        for (int e = 0; e < W; ++e) {
+          double v = 0.0;
+          if (j < c1) {
+            v = a.va ? a.va[j + e] : 0.0;
+            if (vb) v -= vb[j + e];
+          }
+          d[u][e] = static_cast<TA>(v);
         }
-        d[u][e] = static_cast<TQ>(v);
       }
     }
 #pragma unroll
@@ -112,156 +130,164 @@ __global__ __launch_bounds__(kThreads) void k_rowdot(RowdotArgs<TQ> a) {
 #pragma unroll
         for (int u = 0; u < U; ++u) {
           const int64_t j = base + u * SWEEP + tcol;
-          if (j < a.ldc) {
-            TQ q[W];
-            V16<TQ>::load(crow + j, q);
+          if (j < c1) {
+            TQ qv[W];
+            V16<TQ>::load(crow + j, qv);
 #pragma unroll
-            for (int e = 0; e < W; ++e) acc[r] = fma(q[e], d[u][e], acc[r]);
+            for (int e = 0; e < W; ++e) acc[r] = fma(static_cast<TA>(qv[e]), d[u][e], acc[r]);
           }
         }
       }
     }
   }
 
-  __shared__ TQ red[kThreads / 64][ROWS];
+  __shared__ TA red[kThreads / 64][ROWS];
   const int lane = threadIdx.x & 63;
   const int wv = threadIdx.x >> 6;
 #pragma unroll
   for (int r = 0; r < ROWS; ++r) {
-    const TQ v = wave_sum(acc[r]);
+    const TA v = wave_sum(acc[r]);
     if (lane == 0) red[wv][r] = v;
   }
   __syncthreads();
   if (static_cast<int>(threadIdx.x) < nrows) {
     const int r = threadIdx.x;
-    a.out[row0 + r] = (red[0][r] + red[1][r]) + (red[2][r] + red[3][r]);
+    a.out[static_cast<int64_t>(split) * a.out_stride + row0 + r] =
+        (red[0][r] + red[1][r]) + (red[2][r] + red[3][r]);
   }
 }
 
 // ------------------------------------------------------------------ pass B
 
+// One workgroup per (block i, 256 x 16-byte column slab): every wave streams
+// all rows of the block over its own 64 x 16 B of the slab, so each row read
+// by the workgroup is 4 KB contiguous and no cross-wave combine is needed.
+// w_r is the sum of pass A's column-split partials, added in split order.
 template <typename TQ, int RU>
 __global__ __launch_bounds__(kThreads) void k_pass_b(PassBArgs<TQ> a) {
   constexpr int W = V16<TQ>::W;
-  constexpr int SW = 64 * W;  // columns per slab
-  int s, i;
-  if (a.order == 0) {
-    s = blockIdx.x / a.m;
-    i = blockIdx.x % a.m;
-  } else {
-    i = a.m - 1 - static_cast<int>(blockIdx.x / a.nslab);
-    s = blockIdx.x % a.nslab;
-  }
-  const int lane = threadIdx.x & 63;
-  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  constexpr int SW = kThreads * W;  // columns per slab
+  const int s = blockIdx.x % a.nslab;
+  const int i = a.blk_begin + static_cast<int>(blockIdx.x / a.nslab);
   const int64_t r0 = a.off[i];
   const int64_t r1 = a.off[i + 1];
-  const int64_t col = static_cast<int64_t>(s) * SW + lane * W;
+  const int64_t col = static_cast<int64_t>(s) * SW + threadIdx.x * W;
+  if (col >= a.ldc) return;
 
+  auto coef = [&](int64_t r) {
+    TQ v = a.w[r];
+    for (int sp = 1; sp < a.nsplit; ++sp) v += a.w[sp * a.w_stride + r];
+    return v;
+  };
   TQ acc[W];
 #pragma unroll
   for (int e = 0; e < W; ++e) acc[e] = TQ(0);
-  if (col < a.ldc) {
-    int64_t r = r0 + wv;
-    for (; r + 4 * (RU - 1) < r1; r += 4 * RU) {
-      TQ q[RU][W];
-      TQ wr[RU];
+  int64_t r = r0;
+  for (; r + RU - 1 < r1; r += RU) {
+    TQ qv[RU][W];
+    TQ wr[RU];
 #pragma unroll
-      for (int u = 0; u < RU; ++u) {
-        wr[u] = a.w[r + 4 * u];
-        V16<TQ>::load(a.C + (r + 4 * u) * a.ldc + col, q[u]);
-      }
-#pragma unroll
-      for (int u = 0; u < RU; ++u)
-#pragma unroll
-        for (int e = 0; e < W; ++e) acc[e] = fma(wr[u], q[u][e], acc[e]);
+    for (int u = 0; u < RU; ++u) {
+      wr[u] = coef(r + u);
+      V16<TQ>::load(a.C + (r + u) * a.ldc + col, qv[u]);
     }
-    for (; r < r1; r += 4) {
-      TQ q[W];
-      const TQ wr = a.w[r];
-      V16<TQ>::load(a.C + r * a.ldc + col, q);
 #pragma unroll
-      for (int e = 0; e < W; ++e) acc[e] = fma(wr, q[e], acc[e]);
-    }
+    for (int u = 0; u < RU; ++u)
+#pragma unroll
+      for (int e = 0; e < W; ++e) acc[e] = fma(wr[u], qv[u][e], acc[e]);
+  }
+  for (; r < r1; ++r) {
+    TQ qv[W];
+    const TQ wr = coef(r);
+    V16<TQ>::load(a.C + r * a.ldc + col, qv);
+#pragma unroll
+    for (int e = 0; e < W; ++e) acc[e] = fma(wr, qv[e], acc[e]);
   }
 
-  __shared__ TQ red[kThreads / 64][SW];
-  __shared__ unsigned ticket;
+  double* xi = a.x + static_cast<int64_t>(i) * a.ldx;
 #pragma unroll
-  for (int e = 0; e < W; ++e) red[wv][lane * W + e] = acc[e];
-  __syncthreads();
-
-  const int t = threadIdx.x;
-  const int64_t j = static_cast<int64_t>(s) * SW + t;
-  const bool mine = (t < SW) && (j < a.ldc);
-  if (mine) {
-    const TQ pr = (red[0][t] + red[1][t]) + (red[2][t] + red[3][t]);
-    double* xi = a.x + static_cast<int64_t>(i) * a.ldx;
-    const double xo = xi[j];
-    const double d = a.xbar[j] - xo;
-    xi[j] = xo + a.gamma * (d - static_cast<double>(pr));
+  for (int e = 0; e < W; ++e) {
+    const double xo = xi[col + e];
+    const double d = a.xbar[col + e] - xo;
+    xi[col + e] = xo + a.gamma * (d - static_cast<double>(acc[e]));
   }
+}
 
-  // Fused eq. (2b): publish this block's slab, take a ticket; the last of the
-  // m workgroups of the slab forms the average in block order.
-  __threadfence();
+// ------------------------------------------------------------------ average
+
+// Eq. (2b) over a 64-column stripe: wave w sums blocks w, w+4, ... in order,
+// the four partial sums are added as (s0 + s1) + (s2 + s3), then
+// x_bar <- alpha * sum + beta * x_bar (beta == 0 does not read x_bar).  When
+// d is given, the next pass A's differences d_i = x_bar - x_i are written,
+// rounded to the projection precision.
+template <typename TD>
+__global__ __launch_bounds__(256) void k_combine(const double* x, int64_t ldx, int32_t m,
+                                                 int64_t n, double alpha, double beta,
+                                                 double* xbar, TD* d, int64_t ldd) {
+  __shared__ double part[4][64];
+  __shared__ double xb[64];
+  const int lane = threadIdx.x & 63;
+  const int wv = threadIdx.x >> 6;
+  const int64_t j = static_cast<int64_t>(blockIdx.x) * 64 + lane;
+  double s = 0.0;
+  if (j < n)
+    for (int i = wv; i < m; i += 4) s += x[static_cast<int64_t>(i) * ldx + j];
+  part[wv][lane] = s;
   __syncthreads();
-  if (t == 0) ticket = atomicAdd(&a.counters[s], 1u);
-  __syncthreads();
-  if (ticket == static_cast<unsigned>(a.m - 1)) {
-    __threadfence();
-    if (mine) {
-      double sum = 0.0;
-      for (int ii = 0; ii < a.m; ++ii) sum += a.x[static_cast<int64_t>(ii) * a.ldx + j];
-      a.xbar[j] = (a.eta / a.m) * sum + (1.0 - a.eta) * a.xbar[j];
-    }
-    if (t == 0) atomicExch(&a.counters[s], 0u);
+  if (wv == 0 && j < n) {
+    const double tot = (part[0][lane] + part[1][lane]) + (part[2][lane] + part[3][lane]);
+    const double v = beta == 0.0 ? alpha * tot : alpha * tot + beta * xbar[j];
+    xbar[j] = v;
+    xb[lane] = v;
   }
+  if (!d) return;
+  __syncthreads();
+  if (j < n)
+    for (int i = wv; i < m; i += 4)
+      d[static_cast<int64_t>(i) * ldd + j] =
+          static_cast<TD>(xb[lane] - x[static_cast<int64_t>(i) * ldx + j]);
 }
 
 // ------------------------------------------------------------------ expand (FP64)
 
-template <int RU>
-__global__ __launch_bounds__(kThreads) void k_expand(ExpandArgs a) {
-  constexpr int W = 2;
+// y_i = beta * y_i + alpha * sum_{r in block i} w_r C[r][:], FP64 accumulation.
+// A workgroup owns a 64-lane column slab of one block; its 4 waves take
+// interleaved rows and combine in LDS.  w_r sums nsplit partials in order.
+template <typename TQ>
+__global__ __launch_bounds__(kThreads) void k_expand(ExpandArgs<TQ> a) {
+  constexpr int W = V16<TQ>::W;
   constexpr int SW = 64 * W;
   const int s = blockIdx.x % a.nslab;
-  const int i = blockIdx.x / a.nslab;
+  const int i = a.blk_begin + static_cast<int>(blockIdx.x / a.nslab);
   const int lane = threadIdx.x & 63;
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int64_t r0 = a.off ? a.off[i] : 0;
   const int64_t r1 = a.off ? a.off[i + 1] : a.rows_total;
   const int64_t col = static_cast<int64_t>(s) * SW + lane * W;
-  double acc[W] = {0.0, 0.0};
+  double acc[W];
+#pragma unroll
+  for (int e = 0; e < W; ++e) acc[e] = 0.0;
   if (col < a.ldc) {
     for (int64_t r = r0 + wv; r < r1; r += 4) {
-      double q[W];
-      const double wr = a.w[r];
-      V16<double>::load(a.C + r * a.ldc + col, q);
-      acc[0] = fma(wr, q[0], acc[0]);
-      acc[1] = fma(wr, q[1], acc[1]);
+      double wr = a.w[r];
+      for (int sp = 1; sp < a.nsplit; ++sp) wr += a.w[sp * a.w_stride + r];
+      TQ q[W];
+      V16<TQ>::load(a.C + r * a.ldc + col, q);
+#pragma unroll
+      for (int e = 0; e < W; ++e) acc[e] = fma(wr, static_cast<double>(q[e]), acc[e]);
     }
   }
   __shared__ double red[kThreads / 64][SW];
-  red[wv][lane * W + 0] = acc[0];
-  red[wv][lane * W + 1] = acc[1];
+#pragma unroll
+  for (int e = 0; e < W; ++e) red[wv][lane * W + e] = acc[e];
   __syncthreads();
-  const int t = threadIdx.x;
-  const int64_t j = static_cast<int64_t>(s) * SW + t;
-  if (t < SW && j < a.ldc) {
+  for (int t = threadIdx.x; t < SW; t += kThreads) {
+    const int64_t j = static_cast<int64_t>(s) * SW + t;
+    if (j >= a.ldc) break;
     const double v = (red[0][t] + red[1][t]) + (red[2][t] + red[3][t]);
     double* yi = a.y + static_cast<int64_t>(i) * a.ldy;
     yi[j] = (a.beta == 0.0 ? 0.0 : a.beta * yi[j]) + a.alpha * v;
   }
-}
-
-__global__ void k_block_sum(const double* y, int64_t ldy, int32_t m, int64_t n, double scale,
-                            double* out) {
-  const int64_t j = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (j >= n) return;
-  double s = 0.0;
-  for (int i = 0; i < m; ++i) s += y[static_cast<int64_t>(i) * ldy + j];
-  out[j] = scale * s;
 }
 
 // ------------------------------------------------------------------ setup
@@ -479,6 +505,7 @@ __global__ void k_copy_strided(const double* src, int64_t lds, double* dst, int6
 
 __global__ __launch_bounds__(1024) void k_lanczos_normalize(const double* y, int64_t n,
                                                             const double* h, const double* h2,
+                                                            int32_t nsplit, int64_t hstride,
                                                             int32_t j, double* alpha,
                                                             double* beta, double* vnext) {
   __shared__ double part[1024 / 64];
@@ -494,7 +521,12 @@ __global__ __launch_bounds__(1024) void k_lanczos_normalize(const double* y, int
     const double b = sqrt(t);
     bsh = b;
     beta[j] = b;
-    alpha[j] = h[j] + h2[j];
+    double a1 = 0.0, a2 = 0.0;
+    for (int sp = 0; sp < nsplit; ++sp) {
+      a1 += h[sp * hstride + j];
+      a2 += h2[sp * hstride + j];
+    }
+    alpha[j] = a1 + a2;
   }
   __syncthreads();
   const double b = bsh;
@@ -557,18 +589,32 @@ __global__ __launch_bounds__(256) void k_sum_partials(const double* partial, int
 
 // ------------------------------------------------------------------ launchers
 
-template <typename TQ>
-static hipError_t rowdot_impl(const RowdotArgs<TQ>& a, hipStream_t s) {
+template <typename TQ, typename TA>
+static hipError_t rowdot_impl(const RowdotArgs<TQ, TA>& a, hipStream_t s) {
   if (a.ntiles <= 0) return hipSuccess;
-  unsigned grid = static_cast<unsigned>(a.ntiles);
-  if (a.xcd_remap) grid = static_cast<unsigned>(((a.ntiles + kXcds - 1) / kXcds) * kXcds);
-  constexpr int U = sizeof(TQ) == 4 ? 4 : 2;
-  hipLaunchKernelGGL((k_rowdot<TQ, kRowTile, U>), dim3(grid), dim3(kThreads), 0, s, a);
+  const int total = a.ntiles * a.nsplit;
+  unsigned grid = static_cast<unsigned>(total);
+  if (a.xcd_remap) grid = static_cast<unsigned>(((total + kXcds - 1) / kXcds) * kXcds);
+  constexpr int U = rowdot_unroll<TQ>();
+  switch (a.rows_per_tile) {
+    case 8:
+      hipLaunchKernelGGL((k_rowdot<TQ, TA, 8, U>), dim3(grid), dim3(kThreads), 0, s, a);
+      break;
+    case 16:
+      hipLaunchKernelGGL((k_rowdot<TQ, TA, 16, U>), dim3(grid), dim3(kThreads), 0, s, a);
+      break;
+    case 32:
+      hipLaunchKernelGGL((k_rowdot<TQ, TA, 32, U>), dim3(grid), dim3(kThreads), 0, s, a);
+      break;
+    default:
+      return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 
-hipError_t launch_rowdot_f64(const RowdotArgs<double>& a, hipStream_t s) { return rowdot_impl(a, s); }
-hipError_t launch_rowdot_f32(const RowdotArgs<float>& a, hipStream_t s) { return rowdot_impl(a, s); }
+hipError_t launch_rowdot_f64(const RowdotArgs<double, double>& a, hipStream_t s) { return rowdot_impl(a, s); }
+hipError_t launch_rowdot_f32(const RowdotArgs<float, float>& a, hipStream_t s) { return rowdot_impl(a, s); }
+hipError_t launch_rowdot_f32x64(const RowdotArgs<float, double>& a, hipStream_t s) { return rowdot_impl(a, s); }
 
 template <typename TQ>
 static hipError_t pass_b_impl(const PassBArgs<TQ>& a, hipStream_t s) {
@@ -581,18 +627,34 @@ static hipError_t pass_b_impl(const PassBArgs<TQ>& a, hipStream_t s) {
 hipError_t launch_pass_b_f64(const PassBArgs<double>& a, hipStream_t s) { return pass_b_impl(a, s); }
 hipError_t launch_pass_b_f32(const PassBArgs<float>& a, hipStream_t s) { return pass_b_impl(a, s); }
 
-hipError_t launch_expand(const ExpandArgs& a, hipStream_t s) {
-  const unsigned grid = static_cast<unsigned>(a.nslab) * static_cast<unsigned>(a.m);
-  if (grid == 0) return hipSuccess;
-  hipLaunchKernelGGL((k_expand<4>), dim3(grid), dim3(kThreads), 0, s, a);
+template <typename TD>
+static hipError_t combine_impl(const double* x, int64_t ldx, int32_t m, int64_t n, double alpha,
+                               double beta, double* xbar, TD* d, int64_t ldd, hipStream_t s) {
+  hipLaunchKernelGGL((k_combine<TD>), dim3(grid_for(n, 64)), dim3(256), 0, s, x, ldx, m, n, alpha,
+                     beta, xbar, d, ldd);
   return hipGetLastError();
 }
 
-hipError_t launch_block_sum(const double* y, int64_t ldy, int32_t m, int64_t n, double scale,
-                            double* out, hipStream_t s) {
-  hipLaunchKernelGGL(k_block_sum, dim3(grid_for(n, 256)), dim3(256), 0, s, y, ldy, m, n, scale, out);
+hipError_t launch_combine_f64(const double* x, int64_t ldx, int32_t m, int64_t n, double alpha,
+                              double beta, double* xbar, double* d, int64_t ldd, hipStream_t s) {
+  return combine_impl(x, ldx, m, n, alpha, beta, xbar, d, ldd, s);
+}
+
+hipError_t launch_combine_f32(const double* x, int64_t ldx, int32_t m, int64_t n, double alpha,
+                              double beta, double* xbar, float* d, int64_t ldd, hipStream_t s) {
+  return combine_impl(x, ldx, m, n, alpha, beta, xbar, d, ldd, s);
+}
+
+template <typename TQ>
+static hipError_t expand_impl(const ExpandArgs<TQ>& a, hipStream_t s) {
+  const unsigned grid = static_cast<unsigned>(a.nslab) * static_cast<unsigned>(a.m);
+  if (grid == 0) return hipSuccess;
+  hipLaunchKernelGGL((k_expand<TQ>), dim3(grid), dim3(kThreads), 0, s, a);
   return hipGetLastError();
 }
+
+hipError_t launch_expand_f64(const ExpandArgs<double>& a, hipStream_t s) { return expand_impl(a, s); }
+hipError_t launch_expand_f32(const ExpandArgs<float>& a, hipStream_t s) { return expand_impl(a, s); }
 
 hipError_t launch_copy_pad(const double* A, int64_t lda, const double* B, int64_t ldb, int64_t N,
                            int64_t n, double* C, int64_t ldc, double* c, hipStream_t s) {
@@ -646,10 +708,10 @@ hipError_t launch_copy_strided(const double* src, int64_t lds, double* dst, int6
 }
 
 hipError_t launch_lanczos_normalize(const double* y, int64_t n, const double* h, const double* h2,
-                                    int32_t j, double* alpha, double* beta, double* vnext,
-                                    hipStream_t s) {
-  hipLaunchKernelGGL(k_lanczos_normalize, dim3(1), dim3(1024), 0, s, y, n, h, h2, j, alpha, beta,
-                     vnext);
+                                    int32_t nsplit, int64_t hstride, int32_t j, double* alpha,
+                                    double* beta, double* vnext, hipStream_t s) {
+  hipLaunchKernelGGL(k_lanczos_normalize, dim3(1), dim3(1024), 0, s, y, n, h, h2, nsplit, hstride,
+                     j, alpha, beta, vnext);
   return hipGetLastError();
 }
 

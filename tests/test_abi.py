@@ -164,3 +164,10 @@ def test_tridiag_bounds_enclose_true_extremes():
     lo, hi, blo, bhi = apc.apc_tridiag_extremes(al, be, with_bounds=True)
     assert lo - blo <= mu[0] + 1e-12 and hi + bhi >= mu[-1] - 1e-12
     assert lo >= mu[0] - 1e-12 and hi <= mu[-1] + 1e-12
+
+
+def test_one_hip_runtime_in_process():
+    """torch bundles a HIP runtime with the system runtime's soname; the binding loads
+    torch first so libapc binds to the same one."""
+    runtimes = apc._hip_runtimes()
+    assert len(runtimes) == 1, runtimes
