@@ -419,11 +419,11 @@ apc_status x_matvec(apc_plan_s* P, const double* v, double* out) {
 // Lanczos with full (twice classical Gram-Schmidt) reorthogonalisation on
 // X v = (1/m) sum_i Q_i (Q_i^T v), on the GPU in FP64 arithmetic.  Returns an
 // interval [lo, hi] for Theorem 1's closed form.  Ritz values lie inside the
-// spectrum: hi gets a margin above the converged largest Ritz value
-// (underestimating mu_max can make the iteration diverge); lo is the smallest
-// Ritz value, an estimate from above (overestimating mu_min only slows
-// convergence: for any mu in (0, lo) the roots of p_i stay inside the unit
-// disc).
+// spectrum, and a spectrum that pokes out of [lo, hi] costs far more than a
+// slightly wide interval: an eigenvalue delta outside turns the roots of p_i
+// real and raises the rate by ~sqrt(delta), while widening the interval by
+// delta raises it by O(delta).  So both ends are pushed outwards by a margin
+// that covers the Ritz values' remaining movement.
 apc_status lanczos(apc_plan_s* P, double* lo_out, double* hi_out, int* steps_out) {
   const int64_t ldc = P->L.ldc, n = P->n;
   const int kmax = static_cast<int>(P->L.kmax);
@@ -457,7 +457,7 @@ apc_status lanczos(apc_plan_s* P, double* lo_out, double* hi_out, int* steps_out
 
   std::vector<double> a, b;
   double th_lo = 0, th_hi = 0, bd_lo = INFINITY, bd_hi = INFINITY;
-  double prev_lo = NAN, prev_hi = NAN;
+  double prev_lo = NAN, prev_hi = NAN, d_lo = INFINITY, d_hi = INFINITY;
   bool done = false;
   int steps = 0;
   for (int j = 0; j < kmax && !done; ++j) {
@@ -502,12 +502,14 @@ apc_status lanczos(apc_plan_s* P, double* lo_out, double* hi_out, int* steps_out
       bd_hi = std::min(bd_hi, 1e-13 * th_hi);
     }
     // Converged ends: a small residual bound, or a Ritz value that has
-    // stopped moving since the previous check (with a loose bound as a guard
-    // against an early plateau).
-    const bool hi_ok = bd_hi <= 1e-10 * th_hi ||
-                       (std::fabs(th_hi - prev_hi) <= 1e-9 * th_hi && bd_hi <= 1e-3 * th_hi);
-    const bool lo_ok = bd_lo <= 1e-6 * th_lo ||
-                       (std::fabs(th_lo - prev_lo) <= 1e-4 * th_lo && bd_lo <= 0.1 * th_lo);
+    // (nearly) stopped moving since the previous check, with a loose bound as
+    // a guard against an early plateau.  The margins below cover the
+    // remaining movement (about 5x the last change for the convergence rates
+    // seen at the spectral edges here) with a factor of 4 to spare.
+    d_lo = std::isnan(prev_lo) ? INFINITY : std::fabs(th_lo - prev_lo);
+    d_hi = std::isnan(prev_hi) ? INFINITY : std::fabs(th_hi - prev_hi);
+    const bool hi_ok = bd_hi <= 1e-10 * th_hi || (d_hi <= 1e-6 * th_hi && bd_hi <= 1e-2 * th_hi);
+    const bool lo_ok = bd_lo <= 1e-6 * th_lo || (d_lo <= 1e-3 * th_lo && bd_lo <= 0.5 * th_lo);
     prev_lo = th_lo;
     prev_hi = th_hi;
     done = exhausted || (hi_ok && lo_ok);
@@ -520,8 +522,10 @@ apc_status lanczos(apc_plan_s* P, double* lo_out, double* hi_out, int* steps_out
   if (!(th_lo > n * std::numeric_limits<double>::epsilon() * th_hi))
     return fail(APC_ESINGULAR, "mu_min(X) ~ 0 (Ritz value %g, mu_max %g): no unique solution",
                 th_lo, th_hi);
-  *lo_out = bd_lo <= 1e-6 * th_lo ? th_lo - bd_lo : th_lo;
-  *hi_out = std::min(th_hi + std::max(std::min(bd_hi, 1e-8 * th_hi), 1e-13 * th_hi), 1.0);
+  const double m_lo = std::max(std::min(bd_lo, 20.0 * d_lo), 1e-13 * th_hi);
+  const double m_hi = std::max(std::min(bd_hi, 20.0 * d_hi), 1e-13 * th_hi);
+  *lo_out = std::max(th_lo - m_lo, 0.5 * th_lo);
+  *hi_out = std::min(th_hi + m_hi, 1.0);
   return APC_OK;
 }
 
