@@ -24,8 +24,10 @@
  *   - No C++ exception crosses this boundary.  A non-OK status leaves a
  *     message for apc_last_error() (thread-local).  Argument errors are
  *     detected on the host before any GPU work is enqueued.
- *   - k (number of right-hand sides) must be 1 in this version; B is then a
- *     length-N vector with stride ldb between consecutive entries.
+ *   - k right-hand sides (1 <= k <= 1024) are solved together: B is N x k
+ *     row-major, entry (r, c) at B[r*ldb + c] (ldb >= k; for k = 1, ldb is the
+ *     stride between consecutive entries), and x_bar is returned as n x k
+ *     row-major with row stride ldx (>= k; for k = 1, the entry stride).
  */
 #ifndef APC_H
 #define APC_H
@@ -68,7 +70,7 @@ size_t apc_workspace_bytes(int64_t N, int64_t n, const int64_t* off, int32_t m, 
  *   A      device, N x n FP64, row stride lda >= n.  Read during setup, and
  *          again by apc_residual / apc_solve: keep it alive and unchanged
  *          until apc_destroy.
- *   B      device, FP64 right-hand side b (k = 1), entry r at B[r * ldb].
+ *   B      device, FP64 right-hand sides, N x k, entry (r, c) at B[r*ldb + c].
  *          Read during setup and by apc_residual / apc_solve (keep alive).
  *   off    host, m+1 block offsets as in apc_workspace_bytes (copied).
  *   gamma, eta  the parameters of eq. (2).  If either is NaN, both are set to
@@ -104,30 +106,33 @@ apc_status apc_iterate(apc_plan p, int32_t T);
 apc_status apc_iterate_timed(apc_plan p, int32_t T, float* ms_total, float* ms_pass_a,
                              float* ms_pass_b, float* ms_average);
 
-/* Relative residual ||b - A x_bar||_2 / ||b||_2 in FP64 on the GPU (the
+/* Relative residual ||B - A X_bar||_F / ||B||_F in FP64 on the GPU (the
  * solver's convergence monitor).  *relres is host.  Synchronises. */
 apc_status apc_residual(apc_plan p, double* relres);
 
 /* Iterate until apc_residual <= rtol, checking every 8 updates, for at most
- * max_iters updates; then copy x_bar (n doubles, device, stride ldx >= 1
- * between entries) to Xbar.  *iters_out, *relres_out are host (may be NULL).
+ * max_iters updates; then copy x_bar (device, n x k, as apc_get_xbar) to
+ * Xbar.  *iters_out, *relres_out are host (may be NULL).
  * Returns APC_ENOCONV if rtol was not reached (Xbar is still written),
  * APC_EDIVERGED if the residual became non-finite.  Synchronises. */
 apc_status apc_solve(apc_plan p, double rtol, int32_t max_iters, double* Xbar, int64_t ldx,
                      int32_t* iters_out, double* relres_out);
 
-/* Copy the master estimate x_bar (n doubles) to device memory Xbar with stride
- * ldx.  Asynchronous (stream-ordered). */
+/* Copy the master estimate x_bar (n x k) to device memory: entry (j, c) at
+ * Xbar[j*ldx + c] (ldx >= k; for k = 1 the stride between entries, >= 1).
+ * Asynchronous (stream-ordered). */
 apc_status apc_get_xbar(apc_plan p, double* Xbar, int64_t ldx);
 
-/* Copy every local solution x_i (m rows of n doubles, row i at X + i*ldx,
- * ldx >= n) to device memory.  Asynchronous. */
+/* Copy every local solution x_i to device memory.  k = 1: m rows of n
+ * doubles, row i at X + i*ldx (ldx >= n).  k > 1: m blocks of n x k, entry
+ * (i, j, c) at X[(i*n + j)*ldx + c] (ldx >= k).  Asynchronous. */
 apc_status apc_get_local(apc_plan p, double* X, int64_t ldx);
 
 /* Apply every block's FP64 projector to its own row: out_i = P_i v_i =
  * v_i - Q_i (Q_i^T v_i) (Sec. 3.1), for m device rows of n doubles (stride
  * ldv >= n for both V and Out; V and Out must not overlap).  Uses the FP64
- * factor in every precision mode.  Asynchronous. */
+ * factor in every precision mode.  Needs a plan with k = 1 (else
+ * APC_EUNSUPPORTED).  Asynchronous. */
 apc_status apc_project(apc_plan p, const double* V, double* Out, int64_t ldv);
 
 /* Host copies of the parameters in use and of the eigenvalue estimate

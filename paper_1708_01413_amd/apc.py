@@ -216,9 +216,10 @@ def apc_last_error() -> str:
 class Plan:
     """An APC solver instance on one GPU.
 
-    A: (N, n) float64 CUDA tensor (row stride may exceed n); b: (N,) float64
-    CUDA tensor; off: m+1 block offsets.  gamma/eta None selects Theorem 1's
-    optimum.  The plan keeps references to A, b and its workspace.
+    A: (N, n) float64 CUDA tensor (row stride may exceed n); b: (N,) or (N, k)
+    float64 CUDA tensor (row-major); off: m+1 block offsets.  gamma/eta None
+    selects Theorem 1's optimum.  The plan keeps references to A, b and its
+    workspace.
     """
 
     def __init__(self, A, b, off, precision: str = "f64", gamma=None, eta=None, stream=None,
@@ -231,16 +232,17 @@ class Plan:
             raise TypeError("A and b must be device tensors")
         if A.dim() != 2 or A.stride(1) != 1:
             raise ValueError("A must be a row-major matrix")
-        if b.dim() != 1:
-            raise ValueError("b must be a vector (k = 1)")
+        if b.dim() not in (1, 2) or (b.dim() == 2 and b.stride(1) != 1):
+            raise ValueError("b must be a vector or a row-major (N, k) matrix")
         self._torch = torch
         self.device = A.device
         self.N, self.n = A.shape
         self.off = np.asarray(off, dtype=np.int64)
         self.m = len(self.off) - 1
+        self.k = 1 if b.dim() == 1 else b.shape[1]
         self.precision = PRECISIONS[precision]
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
-        ws = apc_workspace_bytes(self.N, self.n, self.off, self.m, 1, self.precision)
+        ws = apc_workspace_bytes(self.N, self.n, self.off, self.m, self.k, self.precision)
         if ws == 0:
             raise ApcError(APC_EINVAL, apc_last_error())
         self.ws_bytes = ws
@@ -255,8 +257,8 @@ class Plan:
         g = math.nan if gamma is None else float(gamma)
         e = math.nan if eta is None else float(eta)
         self.handle = apc_setup(A.data_ptr(), A.stride(0), b.data_ptr(), b.stride(0), self.N,
-                                self.n, self.off, self.m, 1, self.precision, g, e, self._ws_ptr,
-                                ws, self.stream.cuda_stream)
+                                self.n, self.off, self.m, self.k, self.precision, g, e,
+                                self._ws_ptr, ws, self.stream.cuda_stream)
 
     # -- iteration
     def iterate(self, T: int):
@@ -267,30 +269,34 @@ class Plan:
         return apc_iterate_timed(self.handle, T)
 
     @staticmethod
-    def workspace_bytes(N, n, off, precision="f64") -> int:
+    def workspace_bytes(N, n, off, precision="f64", k=1) -> int:
         """Bytes to pass as a preallocated ``workspace`` (uint8) tensor."""
         off = np.asarray(off, dtype=np.int64)
-        return apc_workspace_bytes(N, n, off, len(off) - 1, 1, PRECISIONS[precision]) + 256
+        return apc_workspace_bytes(N, n, off, len(off) - 1, k, PRECISIONS[precision]) + 256
 
     def residual(self) -> float:
         return apc_residual(self.handle)
 
+    def _xshape(self):
+        return (self.n,) if self.k == 1 else (self.n, self.k)
+
     def solve(self, rtol: float, max_iters: int):
-        x = self._torch.empty(self.n, dtype=self._torch.float64, device=self.device)
-        st, it, rr = apc_solve(self.handle, rtol, max_iters, x.data_ptr(), 1)
+        x = self._torch.empty(self._xshape(), dtype=self._torch.float64, device=self.device)
+        st, it, rr = apc_solve(self.handle, rtol, max_iters, x.data_ptr(), 1 if self.k == 1 else self.k)
         if st not in (APC_OK, APC_ENOCONV):
             _check(st)
         return x, it, rr, st
 
     # -- state access
     def xbar(self):
-        x = self._torch.empty(self.n, dtype=self._torch.float64, device=self.device)
-        apc_get_xbar(self.handle, x.data_ptr(), 1)
+        x = self._torch.empty(self._xshape(), dtype=self._torch.float64, device=self.device)
+        apc_get_xbar(self.handle, x.data_ptr(), 1 if self.k == 1 else self.k)
         return x
 
     def local(self):
-        X = self._torch.empty((self.m, self.n), dtype=self._torch.float64, device=self.device)
-        apc_get_local(self.handle, X.data_ptr(), self.n)
+        shape = (self.m, self.n) if self.k == 1 else (self.m, self.n, self.k)
+        X = self._torch.empty(shape, dtype=self._torch.float64, device=self.device)
+        apc_get_local(self.handle, X.data_ptr(), self.n if self.k == 1 else self.k)
         return X
 
     def project(self, V):

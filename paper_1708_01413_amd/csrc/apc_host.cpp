@@ -60,11 +60,14 @@ int64_t round_up(int64_t v, int64_t a) { return (v + a - 1) / a * a; }
 struct Layout {
   int64_t ldc = 0, kmax = 0, S = 0;
   int32_t ntiles_a = 0, ntiles_g = 0, ntiles_t = 0, nparts = 0;
+  int32_t ntiles_k = 0;
+  size_t wpart, wsum, tiles_k;
   size_t C64a, C64b, C32, x, xbar, dv, w, ca, cb, Y, vtmp, V, h, h2, alpha, beta, G, Linv, flags, scal, partial, tiles_a, tiles_g, tiles_t, doff, goff, total;
 };
 
 struct Tiles {
   std::vector<int32_t> a_row0, a_nrows, a_blk;  // pass-A row tiles, aligned to block starts
+  std::vector<int32_t> k_row0, k_nrows, k_blk;  // 128-row tiles of the k-RHS pass A
   std::vector<int32_t> g;                        // Gram tiles (blk, ta, tb), ta >= tb
   std::vector<int32_t> t;                        // TRMM tiles (blk, ta, tc)
   std::vector<int64_t> goff;                     // offset of G_i in the packed Gram storage
@@ -73,6 +76,7 @@ struct Tiles {
 constexpr int kMinRowTile = 8;  // the workspace holds pass-A tile lists of this height or more
 constexpr int kPassARows = 8;   // default rows per pass-A workgroup
 constexpr int kMaxSplit = 8;    // pass-A column splits the workspace holds partials for
+constexpr int kMaxSplitK = 16;  // split-K factor cap of the k-RHS pass A
 
 void build_tiles(const int64_t* off, int32_t m, int64_t ldc, int rows_per_tile, Tiles* T) {
   int64_t g = 0;
@@ -83,6 +87,11 @@ void build_tiles(const int64_t* off, int32_t m, int64_t ldc, int rows_per_tile, 
       T->a_row0.push_back(static_cast<int32_t>(off[i] + r));
       T->a_nrows.push_back(static_cast<int32_t>(std::min<int64_t>(rows_per_tile, p - r)));
       T->a_blk.push_back(i);
+    }
+    for (int64_t r = 0; r < p; r += kMfmaTileRows) {
+      T->k_row0.push_back(static_cast<int32_t>(off[i] + r));
+      T->k_nrows.push_back(static_cast<int32_t>(std::min<int64_t>(kMfmaTileRows, p - r)));
+      T->k_blk.push_back(i);
     }
     const int64_t pt = (p + kGramTile - 1) / kGramTile;
     for (int64_t a = 0; a < pt; ++a) {
@@ -102,9 +111,14 @@ void build_tiles(const int64_t* off, int32_t m, int64_t ldc, int rows_per_tile, 
   }
 }
 
-Layout make_layout(int64_t N, int64_t n, const int64_t* off, int32_t m, int32_t prec,
+// Columns the state keeps per right-hand side set: k itself for k = 1, else k
+// rounded up to the 16-wide matrix-core tile (the extra columns stay zero).
+int32_t padded_rhs(int32_t k) { return k == 1 ? 1 : static_cast<int32_t>(round_up(k, 16)); }
+
+Layout make_layout(int64_t N, int64_t n, const int64_t* off, int32_t m, int32_t k, int32_t prec,
                    const Tiles& T) {
   Layout L;
+  const int64_t kp = padded_rhs(k);
   L.ldc = round_up(n, kLdAlign);
   L.kmax = std::min<int64_t>(n, kLanczosMax);
   for (int i = 0; i < m; ++i) L.S += (off[i + 1] - off[i]) * (off[i + 1] - off[i]);
@@ -124,12 +138,12 @@ Layout make_layout(int64_t N, int64_t n, const int64_t* off, int32_t m, int32_t 
   L.C64a = take(N * L.ldc * d);
   L.C64b = take(N * L.ldc * d);
   L.C32 = take(prec == APC_F32 ? N * L.ldc * 4 : 0);
-  L.x = take(m * L.ldc * d);
-  L.xbar = take(L.ldc * d);
-  L.dv = take(m * L.ldc * d);
-  L.w = take(kMaxSplit * N * d);
-  L.ca = take(N * d);
-  L.cb = take(N * d);
+  L.x = take(m * kp * L.ldc * d);
+  L.xbar = take(kp * L.ldc * d);
+  L.dv = take(m * kp * L.ldc * d);
+  L.w = take(kMaxSplit * N * kp * d);
+  L.ca = take(N * kp * d);
+  L.cb = take(N * kp * d);
   L.Y = take(m * L.ldc * d);
   L.vtmp = take(L.ldc * d);
   L.V = take((L.kmax + 1) * L.ldc * d);
@@ -141,7 +155,14 @@ Layout make_layout(int64_t N, int64_t n, const int64_t* off, int32_t m, int32_t 
   L.Linv = take(L.S * d);
   L.flags = take(4 * 4);
   L.scal = take(8 * d);
-  L.partial = take(L.nparts * d);
+  L.partial = take(L.nparts * kp * d);
+  // k-RHS matrix-core path (FP32 mode, k > 1): split-K partials of W, their sum
+  // (16 spare columns per row), and the 128-row tile lists.
+  const bool mfma = prec == APC_F32 && k > 1;
+  L.ntiles_k = static_cast<int32_t>(T.k_row0.size());
+  L.wpart = take(mfma ? kMaxSplitK * kp * N * 4 : 0);
+  L.wsum = take(mfma ? kp * (N + 16) * 4 : 0);
+  L.tiles_k = take(mfma ? 3 * static_cast<int64_t>(L.ntiles_k) * 4 : 0);
   L.tiles_a = take(3 * max_tiles_a * 4);
   L.tiles_g = take(3 * static_cast<int64_t>(L.ntiles_g) * 4);
   L.tiles_t = take(3 * static_cast<int64_t>(L.ntiles_t) * 4);
@@ -156,7 +177,7 @@ apc_status validate(int64_t N, int64_t n, const int64_t* off, int32_t m, int32_t
   if (n < 1 || N < n) return fail(APC_EINVAL, "need N >= n >= 1 (got N=%lld n=%lld)", (long long)N, (long long)n);
   if (m < 1 || m > N) return fail(APC_EINVAL, "need 1 <= m <= N (got m=%d)", m);
   if (!off) return fail(APC_EINVAL, "off is NULL");
-  if (k != 1) return fail(APC_EUNSUPPORTED, "only k = 1 right-hand side is supported (got %d)", k);
+  if (k < 1 || k > 1024) return fail(APC_EINVAL, "need 1 <= k <= 1024 (got %d)", k);
   if (prec != APC_F64 && prec != APC_F32) return fail(APC_EINVAL, "unknown precision %d", prec);
   if (off[0] != 0 || off[m] != N) return fail(APC_EINVAL, "off[0] must be 0 and off[m] must be N");
   const int64_t pmax = std::min<int64_t>(n, kMaxBlockRows);
@@ -261,7 +282,7 @@ struct apc_plan_s {
   int device = 0;
   hipStream_t stream = nullptr;
   int64_t N = 0, n = 0;
-  int32_t m = 0, k = 1, prec = APC_F64;
+  int32_t m = 0, k = 1, kp = 1, prec = APC_F64;
   std::vector<int64_t> off;
   Layout L;
   char* ws = nullptr;
@@ -277,6 +298,9 @@ struct apc_plan_s {
   int32_t xcd_remap = 1, passa_rows = kRowTile, nsplit = 1;
   int64_t split_cols = 0;
   int32_t group_blocks = 0;            // blocks per pass-A/pass-B group (MALL reuse)
+  bool mfma = false;                   // k-RHS FP32 path on matrix cores
+  int32_t ksplit = 1;                  // its split-K factor
+  int64_t ksplit_cols = 0;
   std::vector<int32_t> tile_start;     // first pass-A tile of every block (m+1)
   std::vector<hipEvent_t> events;
 
@@ -287,25 +311,30 @@ struct apc_plan_s {
   double* xbar() const { return at<double>(L.xbar); }
   int64_t* doff() const { return at<int64_t>(L.doff); }
   int32_t* ta(int which) const { return at<int32_t>(L.tiles_a) + which * L.ntiles_a; }
+  int32_t* tk(int which) const { return at<int32_t>(L.tiles_k) + which * L.ntiles_k; }
   int32_t slab_cols() const { return pass_b_slab(prec == APC_F32 ? 4 : 8); }
+  int64_t state_ld() const { return static_cast<int64_t>(kp) * L.ldc; }  // block stride of x, d
 };
 
 namespace {
 
-// Pass A over blocks [i0, i1): w = C d with d_i = x_bar - x_i precomputed by
-// the previous average (or by setup).
-apc_status pass_a(apc_plan_s* P, int i0, int i1) {
+// Pass A over blocks [i0, i1) for right-hand side col: w = C d with
+// d_i = x_bar - x_i precomputed by the previous average (or by setup).
+apc_status pass_a(apc_plan_s* P, int i0, int i1, int col) {
   const int32_t t0 = P->tile_start[i0], nt = P->tile_start[i1] - t0;
+  const int64_t coff = static_cast<int64_t>(col) * P->L.ldc;
+  const int64_t woff = static_cast<int64_t>(col) * P->nsplit * P->N;
   if (P->prec == APC_F32) {
     RowdotArgs<float> a{P->at<float>(P->L.C32), P->L.ldc, P->ta(0), P->ta(1), P->ta(2), nt, 0,
-                        nullptr, nullptr, 0, P->at<float>(P->L.dv), P->L.ldc,
-                        P->at<float>(P->L.w), P->N, P->nsplit, P->split_cols, P->xcd_remap,
-                        P->passa_rows, t0};
+                        nullptr, nullptr, 0, P->at<float>(P->L.dv) + coff, P->state_ld(),
+                        P->at<float>(P->L.w) + woff, P->N, P->nsplit, P->split_cols,
+                        P->xcd_remap, P->passa_rows, t0};
     HIP_TRY(launch_rowdot_f32(a, P->stream));
   } else {
     RowdotArgs<double> a{P->C64(), P->L.ldc, P->ta(0), P->ta(1), P->ta(2), nt, 0, nullptr,
-                         nullptr, 0, P->at<double>(P->L.dv), P->L.ldc, P->at<double>(P->L.w),
-                         P->N, P->nsplit, P->split_cols, P->xcd_remap, P->passa_rows, t0};
+                         nullptr, 0, P->at<double>(P->L.dv) + coff, P->state_ld(),
+                         P->at<double>(P->L.w) + woff, P->N, P->nsplit, P->split_cols,
+                         P->xcd_remap, P->passa_rows, t0};
     HIP_TRY(launch_rowdot_f64(a, P->stream));
   }
   return APC_OK;
@@ -313,26 +342,31 @@ apc_status pass_a(apc_plan_s* P, int i0, int i1) {
 
 // x_bar <- alpha sum_i x_i + beta x_bar, and the differences d_i for pass A.
 apc_status average(apc_plan_s* P, double alpha, double beta) {
+  const int64_t ld = P->state_ld();  // the average is elementwise over each block's state
   if (P->prec == APC_F32)
-    HIP_TRY(launch_combine_f32(P->x(), P->L.ldc, P->m, P->L.ldc, alpha, beta, P->xbar(),
-                               P->at<float>(P->L.dv), P->L.ldc, P->stream));
+    HIP_TRY(launch_combine_f32(P->x(), ld, P->m, ld, alpha, beta, P->xbar(),
+                               P->at<float>(P->L.dv), ld, P->stream));
   else
-    HIP_TRY(launch_combine_f64(P->x(), P->L.ldc, P->m, P->L.ldc, alpha, beta, P->xbar(),
-                               P->at<double>(P->L.dv), P->L.ldc, P->stream));
+    HIP_TRY(launch_combine_f64(P->x(), ld, P->m, ld, alpha, beta, P->xbar(),
+                               P->at<double>(P->L.dv), ld, P->stream));
   return APC_OK;
 }
 
-// Pass B over blocks [i0, i1): x_i += gamma (x_bar - x_i - Q_i w_i).
-apc_status pass_b(apc_plan_s* P, int i0, int i1) {
+// Pass B over blocks [i0, i1) for right-hand side col:
+// x_i += gamma (x_bar - x_i - Q_i w_i).
+apc_status pass_b(apc_plan_s* P, int i0, int i1, int col) {
   const int32_t nslab = static_cast<int32_t>((P->L.ldc + P->slab_cols() - 1) / P->slab_cols());
+  const int64_t coff = static_cast<int64_t>(col) * P->L.ldc;
+  const int64_t woff = static_cast<int64_t>(col) * P->nsplit * P->N;
   if (P->prec == APC_F32) {
     PassBArgs<float> a{P->at<float>(P->L.C32), P->L.ldc, P->doff(), i1 - i0, nslab,
-                       P->at<float>(P->L.w), P->nsplit, P->N, P->x(), P->L.ldc, P->xbar(),
-                       P->gamma, i0};
+                       P->at<float>(P->L.w) + woff, P->nsplit, P->N, P->x() + coff,
+                       P->state_ld(), P->xbar() + coff, P->gamma, i0};
     HIP_TRY(launch_pass_b_f32(a, P->stream));
   } else {
-    PassBArgs<double> a{P->C64(), P->L.ldc, P->doff(), i1 - i0, nslab, P->at<double>(P->L.w),
-                        P->nsplit, P->N, P->x(), P->L.ldc, P->xbar(), P->gamma, i0};
+    PassBArgs<double> a{P->C64(), P->L.ldc, P->doff(), i1 - i0, nslab,
+                        P->at<double>(P->L.w) + woff, P->nsplit, P->N, P->x() + coff,
+                        P->state_ld(), P->xbar() + coff, P->gamma, i0};
     HIP_TRY(launch_pass_b_f64(a, P->stream));
   }
   return APC_OK;
@@ -343,14 +377,38 @@ apc_status pass_b(apc_plan_s* P, int i0, int i1) {
 // re-read while they are still in the Infinity Cache), then the average.
 // With ev non-null, an event is recorded after every launch and the launch
 // kinds (0 pass A, 1 pass B, 2 average) are appended to kinds.
+apc_status update_mfma(apc_plan_s* P, hipEvent_t* ev, int* kinds) {
+  const Layout& L = P->L;
+  int e = 0;
+  MfmaAArgs a{P->at<float>(L.C32), L.ldc, P->tk(0), P->tk(1), P->tk(2), L.ntiles_k,
+              P->at<float>(L.dv), P->state_ld(), L.ldc, P->kp, P->ksplit, P->ksplit_cols,
+              P->at<float>(L.wpart), P->N};
+  HIP_TRY(launch_passa_mfma(a, P->stream));
+  HIP_TRY(launch_wsum(P->at<float>(L.wpart), P->ksplit, P->kp, P->N, P->at<float>(L.wsum),
+                      P->N + 16, P->stream));
+  if (ev) { HIP_TRY(hipEventRecord(ev[e], P->stream)); kinds[e++] = 0; }
+  // Difference form: the state is x_bar (FP64) and d_i = x_bar - x_i (FP32);
+  // pass B writes e_i = x_i(t+1) - x_bar(t) into the x region.
+  float* ebuf = reinterpret_cast<float*>(P->x());
+  MfmaBArgs b{P->at<float>(L.C32), L.ldc, P->doff(), P->m, P->at<float>(L.wsum), P->N + 16,
+              P->kp, P->at<float>(L.dv), ebuf, P->state_ld(), L.ldc, P->gamma};
+  HIP_TRY(launch_passb_mfma(b, P->stream));
+  if (ev) { HIP_TRY(hipEventRecord(ev[e], P->stream)); kinds[e++] = 1; }
+  HIP_TRY(launch_combine_diff(ebuf, P->state_ld(), P->m, P->state_ld(), P->eta / P->m, P->xbar(),
+                              P->at<float>(L.dv), P->stream));
+  if (ev) { HIP_TRY(hipEventRecord(ev[e], P->stream)); kinds[e++] = 2; }
+  return APC_OK;
+}
+
 apc_status update(apc_plan_s* P, hipEvent_t* ev, int* kinds) {
+  if (P->mfma) return update_mfma(P, ev, kinds);
   const int g = P->group_blocks > 0 ? P->group_blocks : P->m;
   int e = 0;
   for (int i0 = 0; i0 < P->m; i0 += g) {
     const int i1 = std::min(P->m, i0 + g);
-    ST_TRY(pass_a(P, i0, i1));
+    for (int col = 0; col < P->k; ++col) ST_TRY(pass_a(P, i0, i1, col));
     if (ev) { HIP_TRY(hipEventRecord(ev[e], P->stream)); kinds[e++] = 0; }
-    ST_TRY(pass_b(P, i0, i1));
+    for (int col = 0; col < P->k; ++col) ST_TRY(pass_b(P, i0, i1, col));
     if (ev) { HIP_TRY(hipEventRecord(ev[e], P->stream)); kinds[e++] = 1; }
   }
   ST_TRY(average(P, P->eta / P->m, 1.0 - P->eta));
@@ -359,6 +417,7 @@ apc_status update(apc_plan_s* P, hipEvent_t* ev, int* kinds) {
 }
 
 int launches_per_update(const apc_plan_s* P) {
+  if (P->mfma) return 3;
   const int g = P->group_blocks > 0 ? P->group_blocks : P->m;
   return 2 * ((P->m + g - 1) / g) + 1;
 }
@@ -529,11 +588,16 @@ apc_status lanczos(apc_plan_s* P, double* lo_out, double* hi_out, int* steps_out
   return APC_OK;
 }
 
+// ||B - A X||_F^2 into out_dev (X in RHS-major state layout, or null for ||B||^2).
 apc_status residual_norm2(apc_plan_s* P, const double* x, double* out_dev) {
   int32_t parts = 0;
-  HIP_TRY(launch_residual_partial(P->A, P->lda, P->B, P->ldb, P->N, P->n, x,
-                                  P->at<double>(P->L.partial), &parts, P->stream));
-  HIP_TRY(launch_sum_partials(P->at<double>(P->L.partial), parts, out_dev, P->stream));
+  double* partial = P->at<double>(P->L.partial);
+  for (int col = 0; col < P->k; ++col)
+    HIP_TRY(launch_residual_partial(P->A, P->lda, P->B + col, P->ldb, P->N, P->n,
+                                    x ? x + static_cast<int64_t>(col) * P->L.ldc : nullptr,
+                                    partial + static_cast<int64_t>(col) * P->L.nparts, &parts,
+                                    P->stream));
+  HIP_TRY(launch_sum_partials(partial, parts * P->k, out_dev, P->stream));
   return APC_OK;
 }
 
@@ -564,6 +628,14 @@ apc_status setup_impl(apc_plan_s* P, const Tiles& T) {
   HIP_TRY(hipMemcpyAsync(P->at<int32_t>(L.tiles_g), T.g.data(), T.g.size() * 4, hipMemcpyHostToDevice, st));
   HIP_TRY(hipMemcpyAsync(P->at<int32_t>(L.tiles_t), T.t.data(), T.t.size() * 4, hipMemcpyHostToDevice, st));
   HIP_TRY(hipMemcpyAsync(P->doff(), P->off.data(), (m + 1) * 8, hipMemcpyHostToDevice, st));
+  if (P->mfma) {
+    std::vector<int32_t> tk;
+    tk.insert(tk.end(), T.k_row0.begin(), T.k_row0.end());
+    tk.insert(tk.end(), T.k_nrows.begin(), T.k_nrows.end());
+    tk.insert(tk.end(), T.k_blk.begin(), T.k_blk.end());
+    HIP_TRY(hipMemcpyAsync(P->at<int32_t>(L.tiles_k), tk.data(), tk.size() * 4,
+                           hipMemcpyHostToDevice, st));
+  }
   HIP_TRY(hipMemcpyAsync(P->at<int64_t>(L.goff), T.goff.data(), m * 8, hipMemcpyHostToDevice, st));
   HIP_TRY(launch_fill_u32(P->at<unsigned>(L.flags), 4, 0u, st));
 
@@ -575,7 +647,7 @@ apc_status setup_impl(apc_plan_s* P, const Tiles& T) {
   double* Cb = P->at<double>(L.C64b);
   double* ca = P->at<double>(L.ca);
   double* cb = P->at<double>(L.cb);
-  HIP_TRY(launch_copy_pad(P->A, P->lda, P->B, P->ldb, N, n, Ca, ldc, ca, st));
+  HIP_TRY(launch_copy_pad(P->A, P->lda, P->B, P->ldb, N, n, Ca, ldc, ca, P->k, P->kp, st));
   int64_t pmax = 1;
   for (int i = 0; i < m; ++i) pmax = std::max(pmax, P->off[i + 1] - P->off[i]);
   const double rank_tol = 32.0 * std::numeric_limits<double>::epsilon() *
@@ -588,7 +660,8 @@ apc_status setup_impl(apc_plan_s* P, const Tiles& T) {
     HIP_TRY(launch_gram(src, ldc, P->doff(), P->at<int32_t>(L.tiles_g), L.ntiles_g,
                         P->at<int64_t>(L.goff), P->at<double>(L.G), st));
     HIP_TRY(launch_chol_inv(P->doff(), P->at<int64_t>(L.goff), m, P->at<double>(L.G),
-                            P->at<double>(L.Linv), cs, cd, P->at<int>(L.flags), rank_tol, st));
+                            P->at<double>(L.Linv), cs, cd, P->kp, N, P->at<int>(L.flags), rank_tol,
+                            st));
     HIP_TRY(launch_trmm(src, dst, ldc, P->doff(), P->at<int32_t>(L.tiles_t), L.ntiles_t,
                         P->at<int64_t>(L.goff), P->at<double>(L.Linv), st));
   }
@@ -604,7 +677,15 @@ apc_status setup_impl(apc_plan_s* P, const Tiles& T) {
 
   // Alg. 1 initialisation: x_i(0) = Q_i c_i (minimum-norm local solutions),
   // x_bar(0) = (1/m) sum_i x_i(0).
-  ST_TRY(expand_blocks(P, ca, P->x(), 1.0, 0.0));
+  if (P->kp > P->k)
+    HIP_TRY(launch_fill_u32(reinterpret_cast<unsigned*>(P->x()), 2 * m * P->state_ld(), 0u, st));
+  for (int col = 0; col < P->k; ++col) {
+    ExpandArgs<double> e{Ca, ldc, P->doff(), m,
+                         static_cast<int32_t>((ldc + expand_slab(8) - 1) / expand_slab(8)), N,
+                         ca + static_cast<int64_t>(col) * N, 1, 0,
+                         P->x() + static_cast<int64_t>(col) * ldc, P->state_ld(), 1.0, 0.0, 0};
+    HIP_TRY(launch_expand_f64(e, st));
+  }
   ST_TRY(average(P, 1.0 / m, 0.0));
   if (P->prec == APC_F32) HIP_TRY(launch_cast_f32(Ca, P->at<float>(L.C32), N * ldc, st));
 
@@ -631,7 +712,7 @@ size_t apc_workspace_bytes(int64_t N, int64_t n, const int64_t* off, int32_t m, 
   if (validate(N, n, off, m, k, precision) != APC_OK) return 0;
   Tiles T;
   build_tiles(off, m, round_up(n, kLdAlign), kPassARows, &T);
-  return make_layout(N, n, off, m, precision, T).total;
+  return make_layout(N, n, off, m, k, precision, T).total;
 }
 
 apc_status apc_setup(apc_plan* out, const double* A, int64_t lda, const double* B, int64_t ldb,
@@ -662,7 +743,7 @@ apc_status apc_setup(apc_plan* out, const double* A, int64_t lda, const double* 
   }
   Tiles T;
   build_tiles(off, m, round_up(n, kLdAlign), passa_rows, &T);
-  const Layout L = make_layout(N, n, off, m, precision, T);
+  const Layout L = make_layout(N, n, off, m, k, precision, T);
   if (ws_bytes < L.total)
     return fail(APC_EINVAL, "workspace has %zu bytes, needs %zu", ws_bytes, L.total);
 
@@ -678,6 +759,7 @@ apc_status apc_setup(apc_plan* out, const double* A, int64_t lda, const double* 
   P->n = n;
   P->m = m;
   P->k = k;
+  P->kp = padded_rhs(k);
   P->prec = precision;
   P->off.assign(off, off + m + 1);
   P->L = L;
@@ -695,6 +777,17 @@ apc_status apc_setup(apc_plan* out, const double* A, int64_t lda, const double* 
     P->tile_start.push_back(P->tile_start.back() +
                             static_cast<int32_t>((off[i + 1] - off[i] + passa_rows - 1) / passa_rows));
   P->group_blocks = group_blocks >= 0 ? group_blocks : 0;
+  P->mfma = precision == APC_F32 && k > 1;
+  if (const char* e = std::getenv("APC_KRHS_MFMA")) P->mfma = P->mfma && std::atoi(e) != 0;
+  if (P->mfma) {
+    // Split K (the n columns) so that pass A runs ~2048 workgroups.
+    const int64_t ncb = (P->kp + 63) / 64;
+    const int64_t base = std::max<int64_t>(1, static_cast<int64_t>(L.ntiles_k) * ncb);
+    int64_t want = std::min<int64_t>({(2048 + base - 1) / base, kMaxSplitK, L.ldc / 64});
+    want = std::max<int64_t>(want, 1);
+    P->ksplit_cols = round_up((L.ldc + want - 1) / want, 64);
+    P->ksplit = static_cast<int32_t>((L.ldc + P->ksplit_cols - 1) / P->ksplit_cols);
+  }
   {
     // Column splits of pass A: about 4096 workgroups (16 per CU, measured best
     // for streaming at the 16384 x 8192 shape), each split at least one
@@ -799,19 +892,35 @@ apc_status apc_solve(apc_plan p, double rtol, int32_t max_iters, double* Xbar, i
 }
 
 apc_status apc_get_xbar(apc_plan p, double* Xbar, int64_t ldx) {
-  if (!p || !Xbar || ldx < 1) return fail(APC_EINVAL, "bad argument");
-  HIP_TRY(launch_copy_strided(p->xbar(), 1, Xbar, ldx, p->n, 1, p->stream));
+  if (!p || !Xbar || ldx < (p->k == 1 ? 1 : p->k)) return fail(APC_EINVAL, "bad argument");
+  if (p->k == 1)
+    HIP_TRY(launch_copy_strided(p->xbar(), 1, Xbar, ldx, p->n, 1, p->stream));
+  else
+    HIP_TRY(launch_copy_t(p->xbar(), p->L.ldc, Xbar, ldx, p->n, p->k, p->stream));
   return APC_OK;
 }
 
 apc_status apc_get_local(apc_plan p, double* X, int64_t ldx) {
-  if (!p || !X || ldx < p->n) return fail(APC_EINVAL, "bad argument");
-  HIP_TRY(launch_copy_strided(p->x(), p->L.ldc, X, ldx, p->m, p->n, p->stream));
+  if (!p || !X) return fail(APC_EINVAL, "bad argument");
+  if (p->k == 1) {
+    if (ldx < p->n) return fail(APC_EINVAL, "ldx < n");
+    HIP_TRY(launch_copy_strided(p->x(), p->L.ldc, X, ldx, p->m, p->n, p->stream));
+  } else if (p->mfma) {
+    if (ldx < p->k) return fail(APC_EINVAL, "ldx < k");
+    HIP_TRY(launch_local_from_diff(p->xbar(), p->at<float>(p->L.dv), p->L.ldc, p->state_ld(), p->m,
+                                   p->n, p->k, X, ldx, p->stream));
+  } else {
+    if (ldx < p->k) return fail(APC_EINVAL, "ldx < k");
+    for (int i = 0; i < p->m; ++i)
+      HIP_TRY(launch_copy_t(p->x() + i * p->state_ld(), p->L.ldc, X + i * p->n * ldx, ldx, p->n,
+                            p->k, p->stream));
+  }
   return APC_OK;
 }
 
 apc_status apc_project(apc_plan p, const double* V, double* Out, int64_t ldv) {
   if (!p || !V || !Out || ldv < p->n) return fail(APC_EINVAL, "bad argument");
+  if (p->k != 1) return fail(APC_EUNSUPPORTED, "apc_project needs a plan with k = 1");
   const Layout& L = p->L;
   double* Y = p->at<double>(L.Y);
   // Y_i <- V_i zero-padded to ldc; w = Q_i^T (0 - Y_i) = -Q_i^T V_i; Y_i += Q_i w.

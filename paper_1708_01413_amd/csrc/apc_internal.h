@@ -105,6 +105,57 @@ hipError_t launch_pass_b_f32(const PassBArgs<float>& a, hipStream_t s);
 hipError_t launch_expand_f64(const ExpandArgs<double>& a, hipStream_t s);
 hipError_t launch_expand_f32(const ExpandArgs<float>& a, hipStream_t s);
 
+// k right-hand sides, FP32 projections on matrix cores.
+// Pass A: wpart[(split*kp + c)*N + r] = sum_{j in split} C[r][j] d_blk[c][j] over
+// 128-row tiles (tile lists aligned to block starts), kp a multiple of 16,
+// split_cols a multiple of 64.
+struct MfmaAArgs {
+  const float* C;
+  int64_t ldc;
+  const int32_t* tile_row0;
+  const int32_t* tile_nrows;
+  const int32_t* tile_blk;
+  int32_t ntiles;
+  const float* d;             // d[blk*ldd_blk + c*ldd_col + j]
+  int64_t ldd_blk;
+  int64_t ldd_col;
+  int32_t kp;
+  int32_t nsplit;
+  int64_t split_cols;
+  float* wpart;
+  int64_t N;
+};
+// Pass B in difference form: e_i[c][j] = -(1 - gamma) d_i[c][j] - gamma sum_{r in
+// block i} C[r][j] W[c][r] (e_i = x_i(t+1) - x_bar(t)), with W[c*ldw + r]
+// (ldw >= N + 16).
+struct MfmaBArgs {
+  const float* C;
+  int64_t ldc;
+  const int64_t* off;
+  int32_t m;
+  const float* W;
+  int64_t ldw;
+  int32_t kp;
+  const float* d;             // d[blk*ld_blk + c*ld_col + j]
+  float* e;                   // same layout
+  int64_t ld_blk;
+  int64_t ld_col;
+  double gamma;
+};
+constexpr int kMfmaTileRows = 128;
+hipError_t launch_passa_mfma(const MfmaAArgs& a, hipStream_t s);
+hipError_t launch_wsum(const float* wpart, int32_t nsplit, int32_t kp, int64_t N, float* W,
+                       int64_t ldw, hipStream_t s);
+hipError_t launch_passb_mfma(const MfmaBArgs& a, hipStream_t s);
+// delta = scale * sum_i e_i (fixed order), xbar += delta, d_i = delta - e_i, over
+// n entries of each block's state (block stride ld).
+hipError_t launch_combine_diff(const float* e, int64_t ld, int32_t m, int64_t n, double scale,
+                               double* xbar, float* d, hipStream_t s);
+// X[(i*n + j)*ldx + c] = xbar[c*ld_col + j] - d[i*ld_blk + c*ld_col + j].
+hipError_t launch_local_from_diff(const double* xbar, const float* d, int64_t ld_col,
+                                  int64_t ld_blk, int32_t m, int64_t n, int32_t k, double* X,
+                                  int64_t ldx, hipStream_t s);
+
 // Eq. (2b) and the next differences: xbar[j] = alpha * sum_{i<m} x[i*ldx + j]
 // + beta * xbar[j] for j < n in a fixed order (wave w sums i = w, w+4, ...;
 // then (s0 + s1) + (s2 + s3)); beta == 0 does not read xbar.  If d is not
@@ -118,21 +169,27 @@ hipError_t launch_combine_f32(const double* x, int64_t ldx, int32_t m, int64_t n
 // Setup kernels (FP64)
 // ---------------------------------------------------------------------------
 
-// C[r][j] = A[r*lda + j] (j < n), 0 for n <= j < ldc; c[r] = B[r*ldb].
+// C[r][j] = A[r*lda + j] (j < n), 0 for n <= j < ldc; the right-hand sides in
+// RHS-major order: c[col*N + r] = B[r*ldb + col] for col < k, 0 up to kp.
 hipError_t launch_copy_pad(const double* A, int64_t lda, const double* B, int64_t ldb, int64_t N,
-                           int64_t n, double* C, int64_t ldc, double* c, hipStream_t s);
+                           int64_t n, double* C, int64_t ldc, double* c, int32_t k, int32_t kp,
+                           hipStream_t s);
 // G_i = C_i C_i^T for every block (tiles: (blk, ta, tb) with ta >= tb).
 hipError_t launch_gram(const double* C, int64_t ldc, const int64_t* off, const int32_t* tiles,
                        int32_t ntiles, const int64_t* goff, double* G, hipStream_t s);
-// Per block: Cholesky G_i = L L^T in place, Linv_i = L^{-1}, c_out = Linv c_in;
+// Per block: Cholesky G_i = L L^T in place, Linv_i = L^{-1}, and for each of
+// the kp right-hand-side columns (stride ldcv) c_out = Linv c_in;
 // flags[0] <- 1 + (first block whose pivot fails the rank test).
 hipError_t launch_chol_inv(const int64_t* off, const int64_t* goff, int32_t m, double* G,
-                           double* Linv, const double* c_in, double* c_out, int* flags,
-                           double rank_tol, hipStream_t s);
+                           double* Linv, const double* c_in, double* c_out, int32_t kp,
+                           int64_t ldcv, int* flags, double rank_tol, hipStream_t s);
 // Out_i = Linv_i In_i for every block (tiles: (blk, ta, tc)).
 hipError_t launch_trmm(const double* In, double* Out, int64_t ldc, const int64_t* off,
                        const int32_t* tiles, int32_t ntiles, const int64_t* goff,
                        const double* Linv, hipStream_t s);
+// dst[j*ldd + c] = src[c*lds + j] for j < n, c < k.
+hipError_t launch_copy_t(const double* src, int64_t lds, double* dst, int64_t ldd, int64_t n,
+                         int32_t k, hipStream_t s);
 hipError_t launch_cast_f32(const double* src, float* dst, int64_t count, hipStream_t s);
 hipError_t launch_fill_u32(unsigned* p, int64_t count, unsigned v, hipStream_t s);
 hipError_t launch_copy_strided(const double* src, int64_t lds, double* dst, int64_t ldd,

@@ -213,6 +213,265 @@ __global__ __launch_bounds__(kThreads) void k_pass_b(PassBArgs<TQ> a) {
   }
 }
 
+// ------------------------------------------------------------------ k right-hand sides (FP32, matrix cores)
+
+// With k right-hand sides both passes are GEMMs (W_i = Q_i^T D_i and
+// Y_i = Q_i W_i) and run on v_mfma_f32_16x16x4f32.  Lane layout of that
+// instruction (wave64): A operand lane l holds A[l % 16][l / 16], B operand
+// B[l / 16][l % 16]; the 4 results of lane l are D[4 (l / 16) + q][l % 16].
+// The K index of one instruction can be any permutation shared by A and B:
+// pass A lets lane group s = l / 16 cover 16 consecutive columns, so its A
+// fragments are 16-byte loads straight from rows of C.
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+__device__ inline f32x4 mfma16x16x4(float a, float b, f32x4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+constexpr int KA_ROWS = 128;  // rows of C per pass-A workgroup (4 waves x 2 x 16)
+constexpr int KA_J = 64;      // columns of C per chunk
+constexpr int KB_J = 128;     // columns of C per pass-B workgroup (4 waves x 2 x 16)
+constexpr int KB_R = 16;      // rows of C per pass-B chunk
+constexpr int K_COLS = 64;    // right-hand sides per workgroup (4 x 16)
+
+// wpart[(split * kp + c) * N + r] = sum_{j in split} C[r][j] d_blk[c][j].
+__global__ __launch_bounds__(256) void k_passa_mfma(MfmaAArgs a) {
+  const int ncb = (a.kp + K_COLS - 1) / K_COLS;
+  int q = blockIdx.x;
+  const int split = q % a.nsplit;
+  q /= a.nsplit;
+  const int cb = q % ncb;
+  const int tile = q / ncb;
+  const int row0 = a.tile_row0[tile];
+  const int nrows = a.tile_nrows[tile];
+  const int blk = a.tile_blk[tile];
+  const int nct = min(K_COLS, a.kp - cb * K_COLS) / 16;
+  const int64_t c0 = static_cast<int64_t>(split) * a.split_cols;
+  const int64_t c1 = min(a.ldc, c0 + a.split_cols);
+  const int lane = threadIdx.x & 63;
+  const int wv = threadIdx.x >> 6;
+  const int li = lane & 15, lg = lane >> 4;
+  const float* dblk = a.d + static_cast<int64_t>(blk) * a.ldd_blk;
+
+  __shared__ float dl[K_COLS][KA_J + 1];
+  f32x4 acc[2][4];
+#pragma unroll
+  for (int st = 0; st < 2; ++st)
+#pragma unroll
+    for (int ct = 0; ct < 4; ++ct) acc[st][ct] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+  for (int64_t jb = c0; jb < c1; jb += KA_J) {
+    // d chunk (64 right-hand sides x 64 columns) into LDS, shared by the 4 waves.
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int idx = threadIdx.x + 256 * e;
+      const int cc = idx >> 4;
+      const int jj = (idx & 15) * 4;
+      const int c = cb * K_COLS + cc;
+      float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (c < a.kp) v = *reinterpret_cast<const float4*>(dblk + c * a.ldd_col + jb + jj);
+      dl[cc][jj + 0] = v.x;
+      dl[cc][jj + 1] = v.y;
+      dl[cc][jj + 2] = v.z;
+      dl[cc][jj + 3] = v.w;
+    }
+    // A fragments: lane (li, lg) of sub-tile st holds C[row][jb + 16 lg + t], t < 16.
+    float af[2][16];
+#pragma unroll
+    for (int st = 0; st < 2; ++st) {
+      const int rr = wv * 32 + st * 16 + li;
+      if (rr < nrows) {
+        const float* src = a.C + static_cast<int64_t>(row0 + rr) * a.ldc + jb + 16 * lg;
+#pragma unroll
+        for (int v4 = 0; v4 < 4; ++v4) {
+          const float4 v = *reinterpret_cast<const float4*>(src + 4 * v4);
+          af[st][4 * v4 + 0] = v.x;
+          af[st][4 * v4 + 1] = v.y;
+          af[st][4 * v4 + 2] = v.z;
+          af[st][4 * v4 + 3] = v.w;
+        }
+      } else {
+#pragma unroll
+        for (int t = 0; t < 16; ++t) af[st][t] = 0.f;
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int t = 0; t < 16; ++t) {
+#pragma unroll
+      for (int ct = 0; ct < 4; ++ct) {
+        if (ct < nct) {
+          const float bv = dl[ct * 16 + li][16 * lg + t];
+#pragma unroll
+          for (int st = 0; st < 2; ++st) acc[st][ct] = mfma16x16x4(af[st][t], bv, acc[st][ct]);
+        }
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int st = 0; st < 2; ++st)
+#pragma unroll
+    for (int ct = 0; ct < 4; ++ct) {
+      if (ct >= nct) continue;
+      const int c = cb * K_COLS + ct * 16 + li;
+#pragma unroll
+      for (int qq = 0; qq < 4; ++qq) {
+        const int rr = wv * 32 + st * 16 + 4 * lg + qq;
+        if (rr < nrows)
+          a.wpart[(static_cast<int64_t>(split) * a.kp + c) * a.N + row0 + rr] = acc[st][ct][qq];
+      }
+    }
+}
+
+// W[c * ldw + r] = sum over the nsplit partials, in split order.
+__global__ void k_wsum(const float* wpart, int32_t nsplit, int32_t kp, int64_t N, float* W,
+                       int64_t ldw) {
+  const int64_t total = static_cast<int64_t>(kp) * N;
+  for (int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; e < total;
+       e += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    const int64_t c = e / N;
+    const int64_t r = e - c * N;
+    float s = 0.f;
+    for (int sp = 0; sp < nsplit; ++sp) s += wpart[(sp * kp + c) * N + r];
+    W[c * ldw + r] = s;
+  }
+}
+
+// Y_i = Q_i W_i on a 128-column x 64-RHS tile of block i (K = the block's rows),
+// then x_i[c][j] += gamma (x_bar[c][j] - x_i[c][j] - Y[j][c]) in FP64.
+__global__ __launch_bounds__(256) void k_passb_mfma(MfmaBArgs a) {
+  const int ncb = (a.kp + K_COLS - 1) / K_COLS;
+  const int njt = static_cast<int>((a.ldc + KB_J - 1) / KB_J);
+  int q = blockIdx.x;
+  const int cb = q % ncb;
+  q /= ncb;
+  const int jt = q % njt;
+  const int blk = q / njt;
+  const int64_t r0 = a.off[blk];
+  const int64_t r1 = a.off[blk + 1];
+  const int nct = min(K_COLS, a.kp - cb * K_COLS) / 16;
+  const int lane = threadIdx.x & 63;
+  const int wv = threadIdx.x >> 6;
+  const int li = lane & 15, lg = lane >> 4;
+  const int64_t j0 = static_cast<int64_t>(jt) * KB_J;
+
+  __shared__ float cl[KB_R][KB_J + 4];
+  f32x4 acc[2][4];
+#pragma unroll
+  for (int st = 0; st < 2; ++st)
+#pragma unroll
+    for (int ct = 0; ct < 4; ++ct) acc[st][ct] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+  for (int64_t rb = r0; rb < r1; rb += KB_R) {
+    // C chunk (16 rows x 128 columns) into LDS with coalesced 16-byte loads.
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+      const int idx = threadIdx.x + 256 * e;
+      const int rr = idx >> 5;
+      const int jj = (idx & 31) * 4;
+      float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (rb + rr < r1 && j0 + jj < a.ldc)
+        v = *reinterpret_cast<const float4*>(a.C + (rb + rr) * a.ldc + j0 + jj);
+      cl[rr][jj + 0] = v.x;
+      cl[rr][jj + 1] = v.y;
+      cl[rr][jj + 2] = v.z;
+      cl[rr][jj + 3] = v.w;
+    }
+    // B fragments: lane (li, lg) holds W[rb + 4 lg + t][c], t < 4 (rows past the
+    // block read as 0; W has 16 spare columns per row, so the loads stay inside).
+    float bw[4][4];
+#pragma unroll
+    for (int ct = 0; ct < 4; ++ct) {
+      if (ct < nct) {
+        const int c = cb * K_COLS + ct * 16 + li;
+        const int64_t r = rb + 4 * lg;
+        const float4 v = *reinterpret_cast<const float4*>(a.W + c * a.ldw + r);
+        bw[ct][0] = r + 0 < r1 ? v.x : 0.f;
+        bw[ct][1] = r + 1 < r1 ? v.y : 0.f;
+        bw[ct][2] = r + 2 < r1 ? v.z : 0.f;
+        bw[ct][3] = r + 3 < r1 ? v.w : 0.f;
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+#pragma unroll
+      for (int st = 0; st < 2; ++st) {
+        const float av = cl[4 * lg + t][wv * 32 + st * 16 + li];
+#pragma unroll
+        for (int ct = 0; ct < 4; ++ct)
+          if (ct < nct) acc[st][ct] = mfma16x16x4(av, bw[ct][t], acc[st][ct]);
+      }
+    }
+    __syncthreads();
+  }
+  // e_i = x_i(t+1) - x_bar(t) = -(1 - gamma) d_i - gamma Q_i W_i  (d_i = x_bar - x_i).
+  const float* db = a.d + static_cast<int64_t>(blk) * a.ld_blk;
+  float* eb = a.e + static_cast<int64_t>(blk) * a.ld_blk;
+  const float omg = static_cast<float>(1.0 - a.gamma), g = static_cast<float>(a.gamma);
+#pragma unroll
+  for (int st = 0; st < 2; ++st)
+#pragma unroll
+    for (int ct = 0; ct < 4; ++ct) {
+      if (ct >= nct) continue;
+      const int c = cb * K_COLS + ct * 16 + li;
+      const int64_t j = j0 + wv * 32 + st * 16 + 4 * lg;
+      if (j >= a.ldc) continue;  // ldc is a multiple of 4: the 4 rows below are all in range
+      const float4 dv = *reinterpret_cast<const float4*>(db + c * a.ld_col + j);
+      float4 ev;
+      ev.x = -omg * dv.x - g * acc[st][ct][0];
+      ev.y = -omg * dv.y - g * acc[st][ct][1];
+      ev.z = -omg * dv.z - g * acc[st][ct][2];
+      ev.w = -omg * dv.w - g * acc[st][ct][3];
+      *reinterpret_cast<float4*>(eb + c * a.ld_col + j) = ev;
+    }
+}
+
+// Difference-form average over a 64-column stripe of every block's state:
+// delta = (eta/m) sum_i e_i (fixed order as k_combine), x_bar += delta in
+// FP64, d_i = delta - e_i (the next differences x_bar - x_i, rounded to FP32).
+__global__ __launch_bounds__(256) void k_combine_diff(const float* e, int64_t ld, int32_t m,
+                                                      int64_t n, double scale, double* xbar,
+                                                      float* d) {
+  __shared__ double part[4][64];
+  __shared__ double dl[64];
+  const int lane = threadIdx.x & 63;
+  const int wv = threadIdx.x >> 6;
+  const int64_t j = static_cast<int64_t>(blockIdx.x) * 64 + lane;
+  double s = 0.0;
+  if (j < n)
+    for (int i = wv; i < m; i += 4) s += static_cast<double>(e[static_cast<int64_t>(i) * ld + j]);
+  part[wv][lane] = s;
+  __syncthreads();
+  if (wv == 0 && j < n) {
+    const double delta = scale * ((part[0][lane] + part[1][lane]) + (part[2][lane] + part[3][lane]));
+    xbar[j] += delta;
+    dl[lane] = delta;
+  }
+  __syncthreads();
+  if (j < n)
+    for (int i = wv; i < m; i += 4)
+      d[static_cast<int64_t>(i) * ld + j] =
+          static_cast<float>(dl[lane] - static_cast<double>(e[static_cast<int64_t>(i) * ld + j]));
+}
+
+// X[(i*n + j)*ldx + c] = x_bar[c][j] - d_i[c][j]: local solutions from the
+// difference-form state.
+__global__ void k_local_from_diff(const double* xbar, const float* d, int64_t ld_col,
+                                  int64_t ld_blk, int32_t m, int64_t n, int32_t k, double* X,
+                                  int64_t ldx) {
+  const int64_t total = static_cast<int64_t>(m) * n * k;
+  for (int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; e < total;
+       e += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    const int c = static_cast<int>(e % k);
+    const int64_t ij = e / k;
+    const int64_t j = ij % n;
+    const int64_t i = ij / n;
+    X[ij * ldx + c] = xbar[c * ld_col + j] - static_cast<double>(d[i * ld_blk + c * ld_col + j]);
+  }
+}
+
 // ------------------------------------------------------------------ average
 
 // Eq. (2b) over a 64-column stripe: wave w sums blocks w, w+4, ... in order,
@@ -292,11 +551,14 @@ __global__ __launch_bounds__(kThreads) void k_expand(ExpandArgs<TQ> a) {
 
 // ------------------------------------------------------------------ setup
 
+// C <- A zero-padded to ldc columns; c <- B in RHS-major order
+// (c[col * N + r] = B[r * ldb + col]), zero for k <= col < kp.
 __global__ void k_copy_pad(const double* A, int64_t lda, const double* B, int64_t ldb, int64_t N,
-                           int64_t n, double* C, int64_t ldc, double* c) {
+                           int64_t n, double* C, int64_t ldc, double* c, int32_t k, int32_t kp) {
   for (int64_t r = blockIdx.x; r < N; r += gridDim.x) {
     for (int64_t j = threadIdx.x; j < ldc; j += blockDim.x) C[r * ldc + j] = j < n ? A[r * lda + j] : 0.0;
-    if (threadIdx.x == 0) c[r] = B[r * ldb];
+    for (int col = threadIdx.x; col < kp; col += blockDim.x)
+      c[static_cast<int64_t>(col) * N + r] = col < k ? B[r * ldb + col] : 0.0;
   }
 }
 
@@ -362,7 +624,8 @@ __global__ __launch_bounds__(256) void k_gram(const double* C, int64_t ldc, cons
 // row (zeros above the diagonal), then c_out = Linv c_in.
 __global__ __launch_bounds__(1024) void k_chol_inv(const int64_t* off, const int64_t* goff,
                                                    double* G, double* Linv, const double* c_in,
-                                                   double* c_out, int* flags, double rank_tol) {
+                                                   double* c_out, int32_t kp, int64_t ldcv,
+                                                   int* flags, double rank_tol) {
   const int blk = blockIdx.x;
   const int64_t r0 = off[blk];
   const int p = static_cast<int>(off[blk + 1] - r0);
@@ -413,10 +676,12 @@ __global__ __launch_bounds__(1024) void k_chol_inv(const int64_t* off, const int
     }
     __syncthreads();
   }
-  for (int r = tid; r < p; r += nt) {
+  for (int e = tid; e < p * kp; e += nt) {
+    const int r = e % p;
+    const int64_t col = static_cast<int64_t>(e / p) * ldcv;
     double s = 0.0;
-    for (int k = 0; k <= r; ++k) s += Lb[static_cast<int64_t>(r) * p + k] * c_in[r0 + k];
-    c_out[r0 + r] = s;
+    for (int k = 0; k <= r; ++k) s += Lb[static_cast<int64_t>(r) * p + k] * c_in[col + r0 + k];
+    c_out[col + r0 + r] = s;
   }
   if (tid == 0 && bad) atomicCAS(flags, 0, blk + 1);
 }
@@ -501,6 +766,18 @@ __global__ void k_copy_strided(const double* src, int64_t lds, double* dst, int6
   }
   for (int64_t r = blockIdx.x; r < rows; r += gridDim.x)
     for (int64_t j = threadIdx.x; j < cols; j += blockDim.x) dst[r * ldd + j] = src[r * lds + j];
+}
+
+// dst[j * ldd + c] = src[c * lds + j] for j < n, c < k (RHS-major -> row-major).
+__global__ void k_copy_t(const double* src, int64_t lds, double* dst, int64_t ldd, int64_t n,
+                         int32_t k) {
+  const int64_t total = n * k;
+  for (int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; e < total;
+       e += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    const int64_t j = e / k;
+    const int c = static_cast<int>(e - j * k);
+    dst[j * ldd + c] = src[c * lds + j];
+  }
 }
 
 __global__ __launch_bounds__(1024) void k_lanczos_normalize(const double* y, int64_t n,
@@ -656,10 +933,53 @@ static hipError_t expand_impl(const ExpandArgs<TQ>& a, hipStream_t s) {
 hipError_t launch_expand_f64(const ExpandArgs<double>& a, hipStream_t s) { return expand_impl(a, s); }
 hipError_t launch_expand_f32(const ExpandArgs<float>& a, hipStream_t s) { return expand_impl(a, s); }
 
+hipError_t launch_passa_mfma(const MfmaAArgs& a, hipStream_t s) {
+  const int ncb = (a.kp + K_COLS - 1) / K_COLS;
+  const unsigned grid = static_cast<unsigned>(a.ntiles) * ncb * a.nsplit;
+  if (grid == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_passa_mfma, dim3(grid), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_wsum(const float* wpart, int32_t nsplit, int32_t kp, int64_t N, float* W,
+                       int64_t ldw, hipStream_t s) {
+  unsigned g = grid_for(static_cast<int64_t>(kp) * N, 256);
+  if (g > 8192) g = 8192;
+  hipLaunchKernelGGL(k_wsum, dim3(g), dim3(256), 0, s, wpart, nsplit, kp, N, W, ldw);
+  return hipGetLastError();
+}
+
+hipError_t launch_passb_mfma(const MfmaBArgs& a, hipStream_t s) {
+  const int ncb = (a.kp + K_COLS - 1) / K_COLS;
+  const int njt = static_cast<int>((a.ldc + KB_J - 1) / KB_J);
+  const unsigned grid = static_cast<unsigned>(a.m) * njt * ncb;
+  if (grid == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_passb_mfma, dim3(grid), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_combine_diff(const float* e, int64_t ld, int32_t m, int64_t n, double scale,
+                               double* xbar, float* d, hipStream_t s) {
+  hipLaunchKernelGGL(k_combine_diff, dim3(grid_for(n, 64)), dim3(256), 0, s, e, ld, m, n, scale,
+                     xbar, d);
+  return hipGetLastError();
+}
+
+hipError_t launch_local_from_diff(const double* xbar, const float* d, int64_t ld_col,
+                                  int64_t ld_blk, int32_t m, int64_t n, int32_t k, double* X,
+                                  int64_t ldx, hipStream_t s) {
+  unsigned g = grid_for(static_cast<int64_t>(m) * n * k, 256);
+  if (g > 8192) g = 8192;
+  hipLaunchKernelGGL(k_local_from_diff, dim3(g), dim3(256), 0, s, xbar, d, ld_col, ld_blk, m, n,
+                     k, X, ldx);
+  return hipGetLastError();
+}
+
 hipError_t launch_copy_pad(const double* A, int64_t lda, const double* B, int64_t ldb, int64_t N,
-                           int64_t n, double* C, int64_t ldc, double* c, hipStream_t s) {
+                           int64_t n, double* C, int64_t ldc, double* c, int32_t k, int32_t kp,
+                           hipStream_t s) {
   const unsigned g = N > 8192 ? 8192u : static_cast<unsigned>(N);
-  hipLaunchKernelGGL(k_copy_pad, dim3(g), dim3(256), 0, s, A, lda, B, ldb, N, n, C, ldc, c);
+  hipLaunchKernelGGL(k_copy_pad, dim3(g), dim3(256), 0, s, A, lda, B, ldb, N, n, C, ldc, c, k, kp);
   return hipGetLastError();
 }
 
@@ -671,10 +991,10 @@ hipError_t launch_gram(const double* C, int64_t ldc, const int64_t* off, const i
 }
 
 hipError_t launch_chol_inv(const int64_t* off, const int64_t* goff, int32_t m, double* G,
-                           double* Linv, const double* c_in, double* c_out, int* flags,
-                           double rank_tol, hipStream_t s) {
-  hipLaunchKernelGGL(k_chol_inv, dim3(m), dim3(1024), 0, s, off, goff, G, Linv, c_in, c_out, flags,
-                     rank_tol);
+                           double* Linv, const double* c_in, double* c_out, int32_t kp,
+                           int64_t ldcv, int* flags, double rank_tol, hipStream_t s) {
+  hipLaunchKernelGGL(k_chol_inv, dim3(m), dim3(1024), 0, s, off, goff, G, Linv, c_in, c_out, kp,
+                     ldcv, flags, rank_tol);
   return hipGetLastError();
 }
 
@@ -704,6 +1024,14 @@ hipError_t launch_copy_strided(const double* src, int64_t lds, double* dst, int6
   unsigned g = cols == 1 ? grid_for(rows, 256) : static_cast<unsigned>(rows);
   if (g > 8192) g = 8192;
   hipLaunchKernelGGL(k_copy_strided, dim3(g), dim3(256), 0, s, src, lds, dst, ldd, rows, cols);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy_t(const double* src, int64_t lds, double* dst, int64_t ldd, int64_t n,
+                         int32_t kcols, hipStream_t s) {
+  unsigned g = grid_for(n * kcols, 256);
+  if (g > 8192) g = 8192;
+  hipLaunchKernelGGL(k_copy_t, dim3(g), dim3(256), 0, s, src, lds, dst, ldd, n, kcols);
   return hipGetLastError();
 }
 

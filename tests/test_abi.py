@@ -66,7 +66,8 @@ def _setup_status(N=64, n=64, off=None, m=4, k=1, prec=0, lda=None, ldb=1, A=0x1
     (dict(off=[1, 16, 32, 48, 64]), apc.APC_EINVAL),                     # off[0] != 0
     (dict(N=128, n=32, m=2, off=[0, 40, 128]), apc.APC_EINVAL),         # p_i > n
     (dict(m=0, off=[0]), apc.APC_EINVAL),
-    (dict(k=2), apc.APC_EUNSUPPORTED),
+    (dict(k=0), apc.APC_EINVAL),
+    (dict(k=2000), apc.APC_EINVAL),
     (dict(prec=7), apc.APC_EINVAL),
     (dict(lda=10), apc.APC_EINVAL),
     (dict(ldb=0), apc.APC_EINVAL),

@@ -414,3 +414,66 @@ def test_fp64_eigen_estimate_uneven_blocks():
     say(p, plan.info(), mn, mx)
     assert mx * (1 - 1e-12) <= p["mu_max"] <= mx * (1 + 1e-4)
     assert mn * (1 - 5e-2) <= p["mu_min"] <= mn * (1 + 1e-9)
+
+
+# ---------------------------------------------------------------- k right-hand sides
+
+
+MULTI = [
+    # (N, n, m, size range, k, seed)
+    (300, 200, 7, (20, 60), 3, 31),        # k padded to 16; n not a multiple of 64
+    (1000, 800, 9, (40, 160), 20, 32),      # k padded to 32; 128-row tiles + tails
+    (2048, 2048, 16, (64, 192), 64, 33),    # full 64-wide tile, square, shifted
+]
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("N,n,m,rng_sizes,k,seed", MULTI)
+def test_multi_rhs_trajectory(prec, N, n, m, rng_sizes, k, seed):
+    """k right-hand sides (batched updates: matrix cores in FP32 mode, one pass per column
+    in FP64 mode) against the oracle run on the same k columns.  Bar: max over t of
+    ||X_gpu(t) - X_oracle(t)||_F / ||X*||_F."""
+    apc = _apc()
+    torch = _torch()
+    sizes = synth.renormalised_sizes(np.random.default_rng(seed), m, N, *rng_sizes)
+    S = synth.gaussian_system(N, n, m, k=k, seed=seed, sizes=sizes, scale=1 / math.sqrt(n),
+                              shift=2.0 if N == n else 0.0)
+    say(f"case: multi-rhs {prec} N={N} n={n} m={m} k={k} sizes={np.diff(S.off).tolist()}")
+    g, e, _ = O.optimal_params(*O.spectrum(S.A, S.off))
+    T = 40
+    Qt, R = O.factor(S.A, S.off)
+    x = O.init_local(Qt, R, S.B, S.off)
+    xbar = O.initial_average(x)
+    ref = [xbar.copy()]
+    for _ in range(T):
+        x, xbar = O.apc_step(Qt, x, xbar, g, e)
+        ref.append(xbar.copy())
+    A, b = upload(S)
+    plan = apc.Plan(A, b, S.off, prec, gamma=g, eta=e)
+    snaps = [plan.xbar()]
+    for _ in range(T):
+        plan.iterate(1)
+        snaps.append(plan.xbar())
+    torch.cuda.synchronize()
+    got = torch.stack(snaps).cpu().numpy()
+    dev = max(np.linalg.norm(got[t] - ref[t]) for t in range(T + 1)) / np.linalg.norm(S.xstar)
+    err = np.linalg.norm(got[-1] - S.xstar) / np.linalg.norm(S.xstar)
+    say(f"max dev {dev:.3e} (tol {TOL[prec]}), err(T) {err:.2e}")
+    assert dev <= TOL[prec]
+    # the local solutions keep A_i x_i = b_i for every column
+    X = plan.local().cpu().numpy()
+    for i, (Ai, bi) in enumerate(zip(O.blocks(S.A, S.off), O.blocks(S.B, S.off))):
+        r = np.linalg.norm(Ai @ X[i] - bi) / np.linalg.norm(bi)
+        assert r < (1e-10 if prec == "f64" else 1e-4), (i, r)
+
+
+def test_multi_rhs_solve_and_residual():
+    apc = _apc()
+    S = synth.shifted_square(1024, 8, k=5, seed=34)
+    say("case: multi-rhs solve")
+    A, b = upload(S)
+    plan = apc.Plan(A, b, S.off, "f32")
+    x, it, rr, st = plan.solve(1e-6, 400)
+    assert st == apc.APC_OK and rr <= 1e-6
+    ref = np.linalg.solve(S.A, S.B)
+    assert np.linalg.norm(x.cpu().numpy() - ref) / np.linalg.norm(ref) < 1e-5
