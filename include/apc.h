@@ -42,9 +42,14 @@ extern "C" {
 typedef struct apc_plan_s* apc_plan; /* opaque, host-side, owned by the library */
 
 typedef enum {
-  APC_F64 = 0, /* Q_i and all arithmetic in FP64                                  */
-  APC_F32 = 1  /* Q_i stored in FP32, projections (both mat-vecs) in FP32 with     */
-               /* FP32 accumulation; x_i, x_bar and the update/average in FP64     */
+  APC_F64 = 0,    /* Q_i and all arithmetic in FP64                                 */
+  APC_F32 = 1,    /* Q_i stored in FP32, projections in FP32 with FP32             */
+                  /* accumulation; k = 1: x_i, x_bar and the update/average in     */
+                  /* FP64; k > 1: matrix-core GEMMs, x_bar in FP64 and the         */
+                  /* differences x_bar - x_i in FP32                               */
+  APC_BF16_IR = 2 /* iterative refinement: inner APC on a bf16 Q_i (matrix cores,  */
+                  /* FP32 accumulation and state), FP64 residual B - A X on matrix */
+                  /* cores; setup QR and eigenvalue estimate in FP64               */
 } apc_precision;
 
 typedef enum {
@@ -112,7 +117,10 @@ apc_status apc_residual(apc_plan p, double* relres);
 
 /* Iterate until apc_residual <= rtol, checking every 8 updates, for at most
  * max_iters updates; then copy x_bar (device, n x k, as apc_get_xbar) to
- * Xbar.  *iters_out, *relres_out are host (may be NULL).
+ * Xbar.  In APC_BF16_IR mode each check is one refinement step: the inner
+ * solve runs ~log(1e-3)/log(rho) updates, its result is added to the FP64
+ * solution X, R = B - A X is formed in FP64 and the next inner solve starts on
+ * R.  *iters_out (updates) and *relres_out are host (may be NULL).
  * Returns APC_ENOCONV if rtol was not reached (Xbar is still written),
  * APC_EDIVERGED if the residual became non-finite.  Synchronises. */
 apc_status apc_solve(apc_plan p, double rtol, int32_t max_iters, double* Xbar, int64_t ldx,
@@ -125,7 +133,8 @@ apc_status apc_get_xbar(apc_plan p, double* Xbar, int64_t ldx);
 
 /* Copy every local solution x_i to device memory.  k = 1: m rows of n
  * doubles, row i at X + i*ldx (ldx >= n).  k > 1: m blocks of n x k, entry
- * (i, j, c) at X[(i*n + j)*ldx + c] (ldx >= k).  Asynchronous. */
+ * (i, j, c) at X[(i*n + j)*ldx + c] (ldx >= k).  Not available in APC_BF16_IR
+ * mode (APC_EUNSUPPORTED).  Asynchronous. */
 apc_status apc_get_local(apc_plan p, double* X, int64_t ldx);
 
 /* Apply every block's FP64 projector to its own row: out_i = P_i v_i =
@@ -160,13 +169,13 @@ apc_status apc_tridiag_extremes(const double* alpha, const double* beta, int32_t
                                 int32_t with_bounds, double* lo, double* hi, double* bound_lo,
                                 double* bound_hi);
 
-/* Host copies of setup diagnostics: the number of Lanczos steps the
- * eigenvalue estimate took (0 when gamma and eta were given), and the launch
- * shape chosen for this problem: pass-A rows per workgroup and column splits,
- * and the number of block groups each update runs pass A and pass B over.
- * Any pointer may be NULL. */
+/* Host copies of diagnostics: the number of Lanczos steps the eigenvalue
+ * estimate took (0 when gamma and eta were given); the launch shape chosen for
+ * this problem (pass-A rows per workgroup and column splits, block groups per
+ * update); and the refinement steps apc_solve has taken (APC_BF16_IR).  Any
+ * pointer may be NULL. */
 apc_status apc_get_info(apc_plan p, int32_t* lanczos_steps, int32_t* rows_per_tile,
-                        int32_t* column_splits, int32_t* block_groups);
+                        int32_t* column_splits, int32_t* block_groups, int32_t* refinements);
 
 /* Number of updates applied since setup (host). */
 int64_t apc_iterations(apc_plan p);

@@ -21,8 +21,8 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libapc.so")
 
-APC_F64, APC_F32 = 0, 1
-PRECISIONS = {"f64": APC_F64, "f32": APC_F32}
+APC_F64, APC_F32, APC_BF16_IR = 0, 1, 2
+PRECISIONS = {"f64": APC_F64, "f32": APC_F32, "bf16_ir": APC_BF16_IR}
 
 STATUS_NAMES = {
     0: "APC_OK", 1: "APC_EINVAL", 2: "APC_ERANK", 3: "APC_ESINGULAR", 4: "APC_EDIVERGED",
@@ -87,7 +87,7 @@ def _load() -> ctypes.CDLL:
         "apc_project": (i32, [vp, vp, vp, i64]),
         "apc_get_params": (i32, [vp, Pd, Pd, Pd, Pd, Pd]),
         "apc_iterations": (i64, [vp]),
-        "apc_get_info": (i32, [vp, Pi, Pi, Pi, Pi]),
+        "apc_get_info": (i32, [vp, Pi, Pi, Pi, Pi, Pi]),
         "apc_optimal_params": (i32, [f64, f64, Pd, Pd, Pd]),
         "apc_tridiag_extremes": (i32, [Pd, Pd, i32, i32, Pd, Pd, Pd, Pd]),
         "apc_destroy": (None, [vp]),
@@ -171,10 +171,10 @@ def apc_get_params(plan) -> dict:
 
 
 def apc_get_info(plan) -> dict:
-    vals = [ctypes.c_int32() for _ in range(4)]
+    vals = [ctypes.c_int32() for _ in range(5)]
     _check(lib.apc_get_info(plan, *[ctypes.byref(v) for v in vals]))
-    return dict(zip(("lanczos_steps", "rows_per_tile", "column_splits", "block_groups"),
-                    (v.value for v in vals)))
+    return dict(zip(("lanczos_steps", "rows_per_tile", "column_splits", "block_groups",
+                     "refinements"), (v.value for v in vals)))
 
 
 def apc_iterations(plan) -> int:

@@ -61,7 +61,8 @@ struct Layout {
   int64_t ldc = 0, kmax = 0, S = 0;
   int32_t ntiles_a = 0, ntiles_g = 0, ntiles_t = 0, nparts = 0;
   int32_t ntiles_k = 0;
-  size_t wpart, wsum, tiles_k;
+  int64_t ldw16 = 0;
+  size_t wpart, wsum, tiles_k, C16, W16, Xs, Rb, cw, Linv2, ssq;
   size_t C64a, C64b, C32, x, xbar, dv, w, ca, cb, Y, vtmp, V, h, h2, alpha, beta, G, Linv, flags, scal, partial, tiles_a, tiles_g, tiles_t, doff, goff, total;
 };
 
@@ -113,12 +114,14 @@ void build_tiles(const int64_t* off, int32_t m, int64_t ldc, int rows_per_tile, 
 
 // Columns the state keeps per right-hand side set: k itself for k = 1, else k
 // rounded up to the 16-wide matrix-core tile (the extra columns stay zero).
-int32_t padded_rhs(int32_t k) { return k == 1 ? 1 : static_cast<int32_t>(round_up(k, 16)); }
+int32_t padded_rhs(int32_t k, int32_t prec) {
+  return (k == 1 && prec != APC_BF16_IR) ? 1 : static_cast<int32_t>(round_up(k, 16));
+}
 
 Layout make_layout(int64_t N, int64_t n, const int64_t* off, int32_t m, int32_t k, int32_t prec,
                    const Tiles& T) {
   Layout L;
-  const int64_t kp = padded_rhs(k);
+  const int64_t kp = padded_rhs(k, prec);
   L.ldc = round_up(n, kLdAlign);
   L.kmax = std::min<int64_t>(n, kLanczosMax);
   for (int i = 0; i < m; ++i) L.S += (off[i + 1] - off[i]) * (off[i + 1] - off[i]);
@@ -153,16 +156,28 @@ Layout make_layout(int64_t N, int64_t n, const int64_t* off, int32_t m, int32_t 
   L.beta = take((L.kmax + 1) * d);
   L.G = take(L.S * d);
   L.Linv = take(L.S * d);
+  L.Linv2 = take(prec == APC_BF16_IR ? L.S * d : 0);
   L.flags = take(4 * 4);
   L.scal = take(8 * d);
   L.partial = take(L.nparts * kp * d);
   // k-RHS matrix-core path (FP32 mode, k > 1): split-K partials of W, their sum
   // (16 spare columns per row), and the 128-row tile lists.
-  const bool mfma = prec == APC_F32 && k > 1;
+  const bool bf = prec == APC_BF16_IR;
+  const bool mfma = (prec == APC_F32 && k > 1) || bf;
   L.ntiles_k = static_cast<int32_t>(T.k_row0.size());
   L.wpart = take(mfma ? kMaxSplitK * kp * N * 4 : 0);
-  L.wsum = take(mfma ? kp * (N + 16) * 4 : 0);
+  L.wsum = take(mfma && !bf ? kp * (N + 16) * 4 : 0);
   L.tiles_k = take(mfma ? 3 * static_cast<int64_t>(L.ntiles_k) * 4 : 0);
+  // Mixed precision: bf16 factor and W, FP64 committed solution X, residual R,
+  // right-hand-side work vector, the first CholeskyQR pass's inverse factor.
+  L.ldw16 = round_up(N, 8);
+  const int64_t big = std::max<int64_t>(N, L.ldc);
+  L.C16 = take(bf ? N * L.ldc * 2 : 0);
+  L.W16 = take(bf ? kp * L.ldw16 * 2 : 0);
+  L.Xs = take(bf ? kp * L.ldc * d : 0);
+  L.Rb = take(k > 1 || bf ? kp * big * d : 0);
+  L.cw = take(bf ? kp * big * d : 0);
+  L.ssq = take(sumsq_parts() * d);
   L.tiles_a = take(3 * max_tiles_a * 4);
   L.tiles_g = take(3 * static_cast<int64_t>(L.ntiles_g) * 4);
   L.tiles_t = take(3 * static_cast<int64_t>(L.ntiles_t) * 4);
@@ -178,7 +193,8 @@ apc_status validate(int64_t N, int64_t n, const int64_t* off, int32_t m, int32_t
   if (m < 1 || m > N) return fail(APC_EINVAL, "need 1 <= m <= N (got m=%d)", m);
   if (!off) return fail(APC_EINVAL, "off is NULL");
   if (k < 1 || k > 1024) return fail(APC_EINVAL, "need 1 <= k <= 1024 (got %d)", k);
-  if (prec != APC_F64 && prec != APC_F32) return fail(APC_EINVAL, "unknown precision %d", prec);
+  if (prec != APC_F64 && prec != APC_F32 && prec != APC_BF16_IR)
+    return fail(APC_EINVAL, "unknown precision %d", prec);
   if (off[0] != 0 || off[m] != N) return fail(APC_EINVAL, "off[0] must be 0 and off[m] must be N");
   const int64_t pmax = std::min<int64_t>(n, kMaxBlockRows);
   for (int i = 0; i < m; ++i) {
@@ -299,6 +315,8 @@ struct apc_plan_s {
   int64_t split_cols = 0;
   int32_t group_blocks = 0;            // blocks per pass-A/pass-B group (MALL reuse)
   bool mfma = false;                   // k-RHS FP32 path on matrix cores
+  bool bf16 = false;                   // mixed precision: bf16 inner solver + FP64 refinement
+  int refinements = 0;
   int32_t ksplit = 1;                  // its split-K factor
   int64_t ksplit_cols = 0;
   std::vector<int32_t> tile_start;     // first pass-A tile of every block (m+1)
@@ -400,7 +418,46 @@ apc_status update_mfma(apc_plan_s* P, hipEvent_t* ev, int* kinds) {
   return APC_OK;
 }
 
+// One inner update of the mixed-precision mode (difference form, bf16 factor).
+apc_status update_bf16(apc_plan_s* P, hipEvent_t* ev, int* kinds) {
+  const Layout& L = P->L;
+  int e = 0;
+  MfmaAArgs16 a{P->at<__bf16>(L.C16), L.ldc, P->tk(0), P->tk(1), P->tk(2), L.ntiles_k,
+                P->at<float>(L.dv), P->state_ld(), L.ldc, P->kp, P->ksplit, P->ksplit_cols,
+                P->at<float>(L.wpart), P->N};
+  HIP_TRY(launch_passa_bf16(a, P->stream));
+  HIP_TRY(launch_wsum_bf16(P->at<float>(L.wpart), P->ksplit, P->kp, P->N, P->at<__bf16>(L.W16),
+                           L.ldw16, P->stream));
+  if (ev) { HIP_TRY(hipEventRecord(ev[e], P->stream)); kinds[e++] = 0; }
+  float* ebuf = reinterpret_cast<float*>(P->x());
+  MfmaBArgs16 b{P->at<__bf16>(L.C16), L.ldc, P->doff(), P->m, P->at<__bf16>(L.W16), L.ldw16,
+                P->kp, P->at<float>(L.dv), ebuf, P->state_ld(), L.ldc, P->gamma, 0};
+  HIP_TRY(launch_passb_bf16(b, P->stream));
+  if (ev) { HIP_TRY(hipEventRecord(ev[e], P->stream)); kinds[e++] = 1; }
+  HIP_TRY(launch_combine_diff(ebuf, P->state_ld(), P->m, P->state_ld(), P->eta / P->m, P->xbar(),
+                              P->at<float>(L.dv), P->stream));
+  if (ev) { HIP_TRY(hipEventRecord(ev[e], P->stream)); kinds[e++] = 2; }
+  return APC_OK;
+}
+
+// Starts the inner (bf16) solve of A x = R for the right-hand sides held, after
+// the inverse Cholesky factors were applied, in cw (RHS-major, stride N):
+// W = c, e_i = Q_i c_i (minimum-norm local solutions), x_bar = mean, d_i = x_bar - x_i.
+apc_status start_inner(apc_plan_s* P, const double* c_rhs) {
+  const Layout& L = P->L;
+  HIP_TRY(launch_to_bf16(c_rhs, P->N, P->kp, P->N, P->at<__bf16>(L.W16), L.ldw16, P->stream));
+  float* ebuf = reinterpret_cast<float*>(P->x());
+  MfmaBArgs16 b{P->at<__bf16>(L.C16), L.ldc, P->doff(), P->m, P->at<__bf16>(L.W16), L.ldw16,
+                P->kp, P->at<float>(L.dv), ebuf, P->state_ld(), L.ldc, 0.0, 1};
+  HIP_TRY(launch_passb_bf16(b, P->stream));
+  HIP_TRY(launch_fill_u32(reinterpret_cast<unsigned*>(P->xbar()), 2 * P->state_ld(), 0u, P->stream));
+  HIP_TRY(launch_combine_diff(ebuf, P->state_ld(), P->m, P->state_ld(), 1.0 / P->m, P->xbar(),
+                              P->at<float>(L.dv), P->stream));
+  return APC_OK;
+}
+
 apc_status update(apc_plan_s* P, hipEvent_t* ev, int* kinds) {
+  if (P->bf16) return update_bf16(P, ev, kinds);
   if (P->mfma) return update_mfma(P, ev, kinds);
   const int g = P->group_blocks > 0 ? P->group_blocks : P->m;
   int e = 0;
@@ -417,7 +474,7 @@ apc_status update(apc_plan_s* P, hipEvent_t* ev, int* kinds) {
 }
 
 int launches_per_update(const apc_plan_s* P) {
-  if (P->mfma) return 3;
+  if (P->mfma || P->bf16) return 3;
   const int g = P->group_blocks > 0 ? P->group_blocks : P->m;
   return 2 * ((P->m + g - 1) / g) + 1;
 }
@@ -451,7 +508,7 @@ apc_status x_matvec(apc_plan_s* P, const double* v, double* out) {
   for (int i0 = 0; i0 < P->m; i0 += g) {
     const int i1 = std::min(P->m, i0 + g);
     const int32_t t0 = P->tile_start[i0], nt = P->tile_start[i1] - t0;
-    if (P->prec == APC_F32) {
+    if (P->prec == APC_F32) {  // FP32 factor (the BF16 mode estimates on the FP64 factor)
       RowdotArgs<float, double> a{P->at<float>(L.C32), L.ldc, P->ta(0), P->ta(1), P->ta(2), nt, 0,
                                   v, nullptr, 0, nullptr, 0, u, 0, 1, L.ldc, P->xcd_remap,
                                   P->passa_rows, t0};
@@ -589,15 +646,41 @@ apc_status lanczos(apc_plan_s* P, double* lo_out, double* hi_out, int* steps_out
 }
 
 // ||B - A X||_F^2 into out_dev (X in RHS-major state layout, or null for ||B||^2).
+// k = 1: row-dot kernel; k > 1: the FP64 matrix-core residual into R, then a
+// fixed-order sum of squares.
 apc_status residual_norm2(apc_plan_s* P, const double* x, double* out_dev) {
   int32_t parts = 0;
   double* partial = P->at<double>(P->L.partial);
+  if (x && P->k > 1) {
+    ResidArgs r{P->A, P->lda, P->B, P->ldb, x, P->L.ldc, P->N, P->n, P->k,
+                P->at<double>(P->L.Rb), P->N};
+    HIP_TRY(launch_resid_f64(r, P->stream));
+    HIP_TRY(launch_sumsq(P->at<double>(P->L.Rb), static_cast<int64_t>(P->k) * P->N,
+                         P->at<double>(P->L.ssq), P->stream));
+    HIP_TRY(launch_sum_partials(P->at<double>(P->L.ssq), sumsq_parts(), out_dev, P->stream));
+    return APC_OK;
+  }
   for (int col = 0; col < P->k; ++col)
     HIP_TRY(launch_residual_partial(P->A, P->lda, P->B + col, P->ldb, P->N, P->n,
                                     x ? x + static_cast<int64_t>(col) * P->L.ldc : nullptr,
                                     partial + static_cast<int64_t>(col) * P->L.nparts, &parts,
                                     P->stream));
   HIP_TRY(launch_sum_partials(partial, parts * P->k, out_dev, P->stream));
+  return APC_OK;
+}
+
+// The current estimate in RHS-major layout: x_bar, or in the mixed-precision
+// mode the committed solution plus the inner solve's x_bar (formed in cw).
+apc_status current_solution(apc_plan_s* P, const double** out) {
+  if (!P->bf16) {
+    *out = P->xbar();
+    return APC_OK;
+  }
+  double* cw = P->at<double>(P->L.cw);
+  const int64_t cnt = P->state_ld();
+  HIP_TRY(launch_copy_strided(P->xbar(), 1, cw, 1, cnt, 1, P->stream));
+  HIP_TRY(launch_axpy(cnt, 1.0, P->at<double>(P->L.Xs), cw, P->stream));
+  *out = cw;
   return APC_OK;
 }
 
@@ -628,7 +711,7 @@ apc_status setup_impl(apc_plan_s* P, const Tiles& T) {
   HIP_TRY(hipMemcpyAsync(P->at<int32_t>(L.tiles_g), T.g.data(), T.g.size() * 4, hipMemcpyHostToDevice, st));
   HIP_TRY(hipMemcpyAsync(P->at<int32_t>(L.tiles_t), T.t.data(), T.t.size() * 4, hipMemcpyHostToDevice, st));
   HIP_TRY(hipMemcpyAsync(P->doff(), P->off.data(), (m + 1) * 8, hipMemcpyHostToDevice, st));
-  if (P->mfma) {
+  if (P->mfma || P->bf16) {
     std::vector<int32_t> tk;
     tk.insert(tk.end(), T.k_row0.begin(), T.k_row0.end());
     tk.insert(tk.end(), T.k_nrows.begin(), T.k_nrows.end());
@@ -659,11 +742,13 @@ apc_status setup_impl(apc_plan_s* P, const Tiles& T) {
     double* cd = pass == 0 ? cb : ca;
     HIP_TRY(launch_gram(src, ldc, P->doff(), P->at<int32_t>(L.tiles_g), L.ntiles_g,
                         P->at<int64_t>(L.goff), P->at<double>(L.G), st));
-    HIP_TRY(launch_chol_inv(P->doff(), P->at<int64_t>(L.goff), m, P->at<double>(L.G),
-                            P->at<double>(L.Linv), cs, cd, P->kp, N, P->at<int>(L.flags), rank_tol,
-                            st));
+    // The mixed-precision mode keeps both inverse factors: each refinement
+    // step forms the inner right-hand sides c = L2^{-1} L1^{-1} r.
+    double* Li = (pass == 1 && P->bf16) ? P->at<double>(L.Linv2) : P->at<double>(L.Linv);
+    HIP_TRY(launch_chol_inv(P->doff(), P->at<int64_t>(L.goff), m, P->at<double>(L.G), Li, cs, cd,
+                            P->kp, N, P->at<int>(L.flags), rank_tol, st));
     HIP_TRY(launch_trmm(src, dst, ldc, P->doff(), P->at<int32_t>(L.tiles_t), L.ntiles_t,
-                        P->at<int64_t>(L.goff), P->at<double>(L.Linv), st));
+                        P->at<int64_t>(L.goff), Li, st));
   }
   int flags[4] = {0, 0, 0, 0};
   HIP_TRY(hipMemcpyAsync(flags, P->at<int>(L.flags), sizeof flags, hipMemcpyDeviceToHost, st));
@@ -676,7 +761,13 @@ apc_status setup_impl(apc_plan_s* P, const Tiles& T) {
   P->bnorm = std::sqrt(scal[1]);
 
   // Alg. 1 initialisation: x_i(0) = Q_i c_i (minimum-norm local solutions),
-  // x_bar(0) = (1/m) sum_i x_i(0).
+  // x_bar(0) = (1/m) sum_i x_i(0).  The mixed-precision mode starts its first
+  // inner solve (right-hand sides B, committed solution X = 0) on the bf16 factor.
+  if (P->bf16) {
+    HIP_TRY(launch_cast_bf16(Ca, P->at<__bf16>(L.C16), N * ldc, st));
+    HIP_TRY(launch_fill_u32(P->at<unsigned>(L.Xs), 2 * P->state_ld(), 0u, st));
+    ST_TRY(start_inner(P, ca));
+  } else {
   if (P->kp > P->k)
     HIP_TRY(launch_fill_u32(reinterpret_cast<unsigned*>(P->x()), 2 * m * P->state_ld(), 0u, st));
   for (int col = 0; col < P->k; ++col) {
@@ -687,6 +778,7 @@ apc_status setup_impl(apc_plan_s* P, const Tiles& T) {
     HIP_TRY(launch_expand_f64(e, st));
   }
   ST_TRY(average(P, 1.0 / m, 0.0));
+  }
   if (P->prec == APC_F32) HIP_TRY(launch_cast_f32(Ca, P->at<float>(L.C32), N * ldc, st));
 
   // Parameters: caller's, or Theorem 1's optimum from the estimated spectrum.
@@ -759,7 +851,7 @@ apc_status apc_setup(apc_plan* out, const double* A, int64_t lda, const double* 
   P->n = n;
   P->m = m;
   P->k = k;
-  P->kp = padded_rhs(k);
+  P->kp = padded_rhs(k, precision);
   P->prec = precision;
   P->off.assign(off, off + m + 1);
   P->L = L;
@@ -779,13 +871,15 @@ apc_status apc_setup(apc_plan* out, const double* A, int64_t lda, const double* 
   P->group_blocks = group_blocks >= 0 ? group_blocks : 0;
   P->mfma = precision == APC_F32 && k > 1;
   if (const char* e = std::getenv("APC_KRHS_MFMA")) P->mfma = P->mfma && std::atoi(e) != 0;
-  if (P->mfma) {
+  P->bf16 = precision == APC_BF16_IR;
+  if (P->mfma || P->bf16) {
     // Split K (the n columns) so that pass A runs ~2048 workgroups.
     const int64_t ncb = (P->kp + 63) / 64;
     const int64_t base = std::max<int64_t>(1, static_cast<int64_t>(L.ntiles_k) * ncb);
-    int64_t want = std::min<int64_t>({(2048 + base - 1) / base, kMaxSplitK, L.ldc / 64});
+    const int64_t unit = P->bf16 ? 128 : 64;   // column chunk of the pass-A kernel
+    int64_t want = std::min<int64_t>({(2048 + base - 1) / base, kMaxSplitK, (L.ldc + unit - 1) / unit});
     want = std::max<int64_t>(want, 1);
-    P->ksplit_cols = round_up((L.ldc + want - 1) / want, 64);
+    P->ksplit_cols = round_up((L.ldc + want - 1) / want, unit);
     P->ksplit = static_cast<int32_t>((L.ldc + P->ksplit_cols - 1) / P->ksplit_cols);
   }
   {
@@ -855,7 +949,9 @@ apc_status apc_iterate_timed(apc_plan p, int32_t T, float* ms_total, float* ms_p
 apc_status apc_residual(apc_plan p, double* relres) {
   if (!p || !relres) return fail(APC_EINVAL, "NULL argument");
   double* dst = p->at<double>(p->L.scal);
-  ST_TRY(residual_norm2(p, p->xbar(), dst));
+  const double* x = nullptr;
+  ST_TRY(current_solution(p, &x));
+  ST_TRY(residual_norm2(p, x, dst));
   double r2 = 0;
   HIP_TRY(hipMemcpyAsync(&r2, dst, sizeof r2, hipMemcpyDeviceToHost, p->stream));
   HIP_TRY(hipStreamSynchronize(p->stream));
@@ -863,22 +959,86 @@ apc_status apc_residual(apc_plan p, double* relres) {
   return APC_OK;
 }
 
+namespace {
+
+// Mixed precision: iterative refinement around the bf16 inner solver.  Each
+// step runs `inner` updates of the current inner solve, commits X += x_bar,
+// forms R = B - A X in FP64 on matrix cores, and (unless done) restarts the
+// inner solve on R.
+apc_status solve_refined(apc_plan_s* p, double rtol, int32_t max_iters, int32_t* done_out,
+                         double* rr_out) {
+  const Layout& L = p->L;
+  int inner = 25;
+  if (std::isfinite(p->rho) && p->rho > 0.0 && p->rho < 1.0)
+    inner = static_cast<int>(std::ceil(std::log(1e-3) / std::log(p->rho)));
+  inner = std::max(8, std::min(inner, 200));
+  int32_t done = 0;
+  double rr = 0.0;
+  double* Rb = p->at<double>(L.Rb);
+  double* cw = p->at<double>(L.cw);
+  double* dst = p->at<double>(L.scal);
+  for (;;) {
+    const int32_t T = std::min(inner, max_iters - done);
+    if (T > 0) ST_TRY(apc_iterate(p, T));
+    done += T;
+    // Commit the correction and restart the inner state from zero.
+    HIP_TRY(launch_axpy(p->state_ld(), 1.0, p->xbar(), p->at<double>(L.Xs), p->stream));
+    HIP_TRY(launch_fill_u32(reinterpret_cast<unsigned*>(p->xbar()), 2 * p->state_ld(), 0u, p->stream));
+    ResidArgs r{p->A, p->lda, p->B, p->ldb, p->at<double>(L.Xs), L.ldc, p->N, p->n, p->k, Rb, p->N};
+    HIP_TRY(launch_resid_f64(r, p->stream));
+    HIP_TRY(launch_sumsq(Rb, static_cast<int64_t>(p->k) * p->N, p->at<double>(L.ssq), p->stream));
+    HIP_TRY(launch_sum_partials(p->at<double>(L.ssq), sumsq_parts(), dst, p->stream));
+    double r2 = 0.0;
+    HIP_TRY(hipMemcpyAsync(&r2, dst, sizeof r2, hipMemcpyDeviceToHost, p->stream));
+    HIP_TRY(hipStreamSynchronize(p->stream));
+    rr = p->bnorm > 0 ? std::sqrt(r2) / p->bnorm : std::sqrt(r2);
+    ++p->refinements;
+    if (!std::isfinite(rr)) {
+      *done_out = done;
+      *rr_out = rr;
+      return fail(APC_EDIVERGED, "residual became non-finite after %d refinement steps",
+                  p->refinements);
+    }
+    if (rr <= rtol || done >= max_iters) break;
+    // Inner right-hand sides for R: c = L2^{-1} L1^{-1} r per block (padded
+    // columns of R are zero), then restart the inner solve.
+    if (p->kp > p->k)
+      HIP_TRY(launch_fill_u32(reinterpret_cast<unsigned*>(Rb + static_cast<int64_t>(p->k) * p->N),
+                              2 * (p->kp - p->k) * p->N, 0u, p->stream));
+    HIP_TRY(launch_linv_apply(p->doff(), p->at<int64_t>(L.goff), p->m, p->at<double>(L.Linv), Rb,
+                              p->N, cw, p->N, p->kp, p->stream));
+    HIP_TRY(launch_linv_apply(p->doff(), p->at<int64_t>(L.goff), p->m, p->at<double>(L.Linv2), cw,
+                              p->N, Rb, p->N, p->kp, p->stream));
+    ST_TRY(start_inner(p, Rb));
+  }
+  *done_out = done;
+  *rr_out = rr;
+  return APC_OK;
+}
+
+}  // namespace
+
 apc_status apc_solve(apc_plan p, double rtol, int32_t max_iters, double* Xbar, int64_t ldx,
                      int32_t* iters_out, double* relres_out) {
   if (!p || !Xbar) return fail(APC_EINVAL, "NULL argument");
   if (ldx < 1 || max_iters < 0 || !(rtol >= 0)) return fail(APC_EINVAL, "bad ldx/max_iters/rtol");
   double rr = 0;
-  ST_TRY(apc_residual(p, &rr));
   int32_t done = 0;
   apc_status st = APC_OK;
-  while (rr > rtol && done < max_iters) {
-    const int32_t T = std::min(8, max_iters - done);
-    ST_TRY(apc_iterate(p, T));
-    done += T;
+  if (p->bf16) {
+    st = solve_refined(p, rtol, max_iters, &done, &rr);
+    if (st != APC_OK && st != APC_EDIVERGED) return st;
+  } else {
     ST_TRY(apc_residual(p, &rr));
-    if (!std::isfinite(rr)) {
-      st = fail(APC_EDIVERGED, "residual became non-finite after %d updates", done);
-      break;
+    while (rr > rtol && done < max_iters) {
+      const int32_t T = std::min(8, max_iters - done);
+      ST_TRY(apc_iterate(p, T));
+      done += T;
+      ST_TRY(apc_residual(p, &rr));
+      if (!std::isfinite(rr)) {
+        st = fail(APC_EDIVERGED, "residual became non-finite after %d updates", done);
+        break;
+      }
     }
   }
   if (st == APC_OK && rr > rtol)
@@ -893,15 +1053,18 @@ apc_status apc_solve(apc_plan p, double rtol, int32_t max_iters, double* Xbar, i
 
 apc_status apc_get_xbar(apc_plan p, double* Xbar, int64_t ldx) {
   if (!p || !Xbar || ldx < (p->k == 1 ? 1 : p->k)) return fail(APC_EINVAL, "bad argument");
+  const double* x = nullptr;
+  ST_TRY(current_solution(p, &x));
   if (p->k == 1)
-    HIP_TRY(launch_copy_strided(p->xbar(), 1, Xbar, ldx, p->n, 1, p->stream));
+    HIP_TRY(launch_copy_strided(x, 1, Xbar, ldx, p->n, 1, p->stream));
   else
-    HIP_TRY(launch_copy_t(p->xbar(), p->L.ldc, Xbar, ldx, p->n, p->k, p->stream));
+    HIP_TRY(launch_copy_t(x, p->L.ldc, Xbar, ldx, p->n, p->k, p->stream));
   return APC_OK;
 }
 
 apc_status apc_get_local(apc_plan p, double* X, int64_t ldx) {
   if (!p || !X) return fail(APC_EINVAL, "bad argument");
+  if (p->bf16) return fail(APC_EUNSUPPORTED, "local solutions are not kept in the mixed-precision mode");
   if (p->k == 1) {
     if (ldx < p->n) return fail(APC_EINVAL, "ldx < n");
     HIP_TRY(launch_copy_strided(p->x(), p->L.ldc, X, ldx, p->m, p->n, p->stream));
@@ -973,8 +1136,9 @@ apc_status apc_tridiag_extremes(const double* alpha, const double* beta, int32_t
 }
 
 apc_status apc_get_info(apc_plan p, int32_t* lanczos_steps, int32_t* rows_per_tile,
-                        int32_t* column_splits, int32_t* block_groups) {
+                        int32_t* column_splits, int32_t* block_groups, int32_t* refinements) {
   if (!p) return fail(APC_EINVAL, "plan is NULL");
+  if (refinements) *refinements = p->refinements;
   if (lanczos_steps) *lanczos_steps = p->lanczos_steps;
   if (rows_per_tile) *rows_per_tile = p->passa_rows;
   if (column_splits) *column_splits = p->nsplit;

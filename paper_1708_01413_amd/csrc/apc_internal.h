@@ -142,7 +142,72 @@ struct MfmaBArgs {
   int64_t ld_col;
   double gamma;
 };
+// BF16 factor variants (inner solver of the mixed-precision mode): C16 is the
+// bf16 factor, d and e stay FP32, W16 is bf16 with ldw >= N; split_cols is a
+// multiple of 128.
+struct MfmaAArgs16 {
+  const __bf16* C;
+  int64_t ldc;
+  const int32_t* tile_row0;
+  const int32_t* tile_nrows;
+  const int32_t* tile_blk;
+  int32_t ntiles;
+  const float* d;
+  int64_t ldd_blk;
+  int64_t ldd_col;
+  int32_t kp;
+  int32_t nsplit;
+  int64_t split_cols;
+  float* wpart;
+  int64_t N;
+};
+struct MfmaBArgs16 {
+  const __bf16* C;
+  int64_t ldc;
+  const int64_t* off;
+  int32_t m;
+  const __bf16* W;
+  int64_t ldw;
+  int32_t kp;
+  const float* d;
+  float* e;
+  int64_t ld_blk;
+  int64_t ld_col;
+  double gamma;
+  int32_t expand_only;        // 1: e_i = Q_i W_i
+};
+hipError_t launch_passa_bf16(const MfmaAArgs16& a, hipStream_t s);
+hipError_t launch_wsum_bf16(const float* wpart, int32_t nsplit, int32_t kp, int64_t N, __bf16* W,
+                            int64_t ldw, hipStream_t s);
+hipError_t launch_passb_bf16(const MfmaBArgs16& a, hipStream_t s);
 constexpr int kMfmaTileRows = 128;
+
+// FP64 residual of the refinement: R[c*ldr + r] = B[r*ldb + c] - (A X)[r][c],
+// X[c*ldx + j] (right-hand-side major), r < N, c < k.
+struct ResidArgs {
+  const double* A;
+  int64_t lda;
+  const double* B;
+  int64_t ldb;
+  const double* X;
+  int64_t ldx;
+  int64_t N;
+  int64_t n;
+  int32_t k;
+  double* R;
+  int64_t ldr;
+};
+hipError_t launch_resid_f64(const ResidArgs& a, hipStream_t s);
+// Per block: out[col*ldo + r0 + r] = sum_{q<=r} Linv_i[r][q] in[col*ldi + r0 + q], col < kc.
+hipError_t launch_linv_apply(const int64_t* off, const int64_t* goff, int32_t m, const double* Linv,
+                             const double* in, int64_t ldi, double* out, int64_t ldo, int32_t kc,
+                             hipStream_t s);
+hipError_t launch_to_bf16(const double* src, int64_t lds, int32_t kc, int64_t N, __bf16* W,
+                          int64_t ldw, hipStream_t s);
+hipError_t launch_axpy(int64_t count, double alpha, const double* x, double* y, hipStream_t s);
+hipError_t launch_sumsq(const double* src, int64_t count, double* partial, hipStream_t s);
+int sumsq_parts();
+hipError_t launch_cast_bf16(const double* src, __bf16* dst, int64_t count, hipStream_t s);
 hipError_t launch_passa_mfma(const MfmaAArgs& a, hipStream_t s);
 hipError_t launch_wsum(const float* wpart, int32_t nsplit, int32_t kp, int64_t N, float* W,
                        int64_t ldw, hipStream_t s);

@@ -477,3 +477,42 @@ def test_multi_rhs_solve_and_residual():
     assert st == apc.APC_OK and rr <= 1e-6
     ref = np.linalg.solve(S.A, S.B)
     assert np.linalg.norm(x.cpu().numpy() - ref) / np.linalg.norm(ref) < 1e-5
+
+
+# ---------------------------------------------------------------- mixed precision
+
+
+@pytest.mark.parametrize("alpha,k", [(3.0, 32), (1.5, 32), (3.0, 1)])
+def test_bf16_refinement_reaches_fp64_accuracy(alpha, k):
+    """BF16 projections on matrix cores inside FP64 iterative refinement: the solution
+    matches x* (b = A x* in FP64; kappa(A) < 10 here) to 1e-10 relative error, the
+    bar for the mixed-precision mode against the FP64 oracle's direct solve."""
+    apc = _apc()
+    S = synth.shifted_square(2048, 8, k=k, shift=alpha, seed=40)
+    say(f"case: bf16 refinement alpha={alpha} k={k}")
+    A, b = upload(S)
+    plan = apc.Plan(A, b, S.off, "bf16_ir")
+    x, it, rr, st = plan.solve(1e-13, 2000)
+    info = plan.info()
+    xs = S.xstar
+    err = np.linalg.norm(x.cpu().numpy() - xs) / np.linalg.norm(xs)
+    ref = np.linalg.solve(S.A, S.B)
+    dev = np.linalg.norm(x.cpu().numpy() - ref) / np.linalg.norm(ref)
+    say(f"status {st} updates {it} refinements {info['refinements']} relres {rr:.2e} "
+        f"err vs x* {err:.2e} vs LAPACK solve {dev:.2e}")
+    assert st == apc.APC_OK
+    assert err <= 1e-10 and dev <= 1e-10
+    assert info["refinements"] >= 2      # the inner bf16 solve alone cannot reach 1e-10
+
+
+def test_bf16_inner_solve_contracts():
+    """One inner solve on the bf16 factor (no refinement) cuts the residual by > 100x."""
+    apc = _apc()
+    S = synth.shifted_square(2048, 8, k=16, shift=3.0, seed=41)
+    A, b = upload(S)
+    plan = apc.Plan(A, b, S.off, "bf16_ir")
+    r0 = plan.residual()
+    plan.iterate(20)
+    r1 = plan.residual()
+    say(f"case: bf16 inner solve relres {r0:.2e} -> {r1:.2e}")
+    assert r1 < 1e-2 * r0
