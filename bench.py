@@ -29,6 +29,42 @@ sys.path.insert(0, ROOT)
 
 METRIC = "time-to-1e-6 rel. error & HBM GB/s per APC iteration; batched/BF16 vs plain"
 HBM_PEAK_GBS = 8000.0
+COPY_BYTES = 1 << 30
+KERNELS = os.path.join(ROOT, "paper_1708_01413_amd", "csrc", "apc_kernels.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_tall16k_fp32.md")
+
+
+def kernel_source_hash(names):
+    """sha256 over the source text of the named __global__ functions (brace-matched)."""
+    import hashlib
+    src = open(KERNELS).read()
+    h = hashlib.sha256()
+    for name in names:
+        i = src.index(f"void {name}(")
+        j = src.index("{", i)
+        depth = 0
+        for e in range(j, len(src)):
+            depth += {"{": 1, "}": -1}.get(src[e], 0)
+            if depth == 0:
+                break
+        h.update(src[i:e + 1].encode())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel_label, fn_name):
+    """HBM bytes per launch of a kernel from the committed rocprofv3 counter summary, or
+    None when the summary is missing or the kernel's source changed since it was taken."""
+    try:
+        lines = open(TRAFFIC_FILE).read().splitlines()
+    except OSError:
+        return None
+    want_hash = kernel_source_hash([fn_name])
+    for ln in lines:
+        if ln.startswith("traffic|"):
+            _, label, src_hash, nbytes = ln.split("|")[:4]
+            if label.strip() == kernel_label and src_hash.strip() == want_hash:
+                return float(nbytes)
+    return None
 
 
 def algorithmic_bytes(N, n, m, sq=4, sx=8):
@@ -78,6 +114,106 @@ def cpu_baseline(S, per_iter_bytes, budget_iters=8):
     }
 
 
+def _err(plan, xs, xs_norm):
+    import torch
+    return float(torch.linalg.norm(plan.xbar() - xs)) / xs_norm
+
+
+def time_plain(apc, A, b, off, xs, prec, target, ws, max_updates=400):
+    """Setup + the number of updates that reaches `target` relative error (counted
+    in an untimed run), timed end to end with the stream synchronised."""
+    import torch
+    xs_norm = float(torch.linalg.norm(xs))
+    plan = apc.Plan(A, b, off, prec, workspace=ws)
+    T, err = 0, _err(plan, xs, xs_norm)
+    while err > target and T < max_updates:
+        plan.iterate(1)
+        T += 1
+        err = _err(plan, xs, xs_norm)
+    plan.close()
+    if err > target:
+        # FP32 stalls at its rounding floor: report that, and the time to 10x the target.
+        res = {"reached": False, "updates_tried": T, "floor_err": err}
+        if target < 1e-5:
+            res["time_to_%.0e" % (10 * target)] = time_plain(apc, A, b, off, xs, prec,
+                                                              10 * target, ws, max_updates)
+        return res
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plan = apc.Plan(A, b, off, prec, workspace=ws)
+    t1 = time.perf_counter()
+    tot, pa, pb, pv = plan.iterate_timed(T)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    err = _err(plan, xs, xs_norm)
+    plan.close()
+    return {"reached": True, "updates": T, "err": err, "setup_ms": round((t1 - t0) * 1e3, 2),
+            "iterate_ms": round((t2 - t1) * 1e3, 2), "total_ms": round((t2 - t0) * 1e3, 2),
+            "us_per_update": round(tot * 1e3 / max(T, 1), 1),
+            "pass_a_us": round(pa * 1e3 / max(T, 1), 1), "pass_b_us": round(pb * 1e3 / max(T, 1), 1),
+            "average_us": round(pv * 1e3 / max(T, 1), 1)}
+
+
+def time_refined(apc, A, b, off, xs, rtol, ws):
+    """Mixed precision: setup + apc_solve to relative residual rtol."""
+    import torch
+    xs_norm = float(torch.linalg.norm(xs))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plan = apc.Plan(A, b, off, "bf16_ir", workspace=ws)
+    t1 = time.perf_counter()
+    x, it, rr, st = plan.solve(rtol, 5000)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    err = float(torch.linalg.norm(x - xs)) / xs_norm
+    info = plan.info()
+    plan.close()
+    return {"rtol": rtol, "status": apc.STATUS_NAMES.get(st, st), "err": err, "updates": it,
+            "refinements": info["refinements"], "setup_ms": round((t1 - t0) * 1e3, 2),
+            "solve_ms": round((t2 - t1) * 1e3, 2), "total_ms": round((t2 - t0) * 1e3, 2)}
+
+
+def secondary(apc, synth, dev):
+    """Batched and mixed-precision workloads, each against plain FP32 on the same inputs."""
+    import torch
+    out = {}
+    # Batched: N = n = 8192, A = G/sqrt(n) + 2I, k = 64, 64 blocks of uneven size.
+    S = synth.shifted_uneven_8k(k=64)
+    A = torch.from_numpy(S.A).to(dev)
+    b = torch.from_numpy(np.ascontiguousarray(S.B)).to(dev)
+    xs = torch.from_numpy(S.xstar).to(dev)
+    ws = torch.empty(apc.Plan.workspace_bytes(S.N, S.n, S.off, "f32", k=64), dtype=torch.uint8,
+                     device=dev)
+    out["batched_fp32"] = {"workload": "N=n=8192, A=G/sqrt(n)+2I, k=64, m=64 uneven p_i in "
+                                       "[28, 228]", "time_to_1e-6": time_plain(
+                               apc, A, b, S.off, xs, "f32", 1e-6, ws)}
+    del A, b, xs, ws, S
+    torch.cuda.empty_cache()
+    # Mixed precision vs plain FP32: N = n = 16384, A = G/sqrt(n) + alpha I, k = 128, m = 64.
+    n, k, m = 16384, 128, 64
+    rng = np.random.default_rng(0)
+    G = torch.from_numpy(rng.standard_normal((n, n)) / np.sqrt(n)).to(dev)
+    Xs = torch.from_numpy(rng.standard_normal((n, k))).to(dev)
+    off = synth.offsets_from_sizes(synth.even_sizes(n, m))
+    ws32 = torch.empty(apc.Plan.workspace_bytes(n, n, off, "f32", k=k), dtype=torch.uint8, device=dev)
+    ws16 = torch.empty(apc.Plan.workspace_bytes(n, n, off, "bf16_ir", k=k), dtype=torch.uint8,
+                       device=dev)
+    mixed = {"workload": "N=n=16384, A=G/sqrt(n)+alpha I, k=128, m=64 blocks of 256"}
+    for alpha in (3.0, 1.5):
+        A = G.clone()
+        A.diagonal().add_(alpha)
+        B = (A @ Xs).contiguous()
+        entry = {"plain_fp32_time_to_1e-6": time_plain(apc, A, B, off, Xs, "f32", 1e-6, ws32),
+                 "bf16_ir_time_to_1e-6": time_refined(apc, A, B, off, Xs, 1e-7, ws16),
+                 "bf16_ir_time_to_1e-10": time_refined(apc, A, B, off, Xs, 1e-11, ws16)}
+        mixed[f"alpha={alpha}"] = entry
+        del A, B
+    out["mixed_precision"] = mixed
+    del G, Xs, ws32, ws16
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -86,10 +222,14 @@ def main():
     ap.add_argument("--precision", default="f32", choices=["f32", "f64"])
     ap.add_argument("--target", type=float, default=1e-6)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--main-only", action="store_true",
+                    help="skip the batched and mixed-precision comparisons")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="first run a plain 1 GiB device copy (reference for HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on one GPU only: the multi-GPU block sharding of APC is a design "
-              "(one all-reduce of sum_i x_i per update), not part of this build", file=sys.stderr)
+        print("bench.py measures one GPU only: sharding the blocks over several GPUs (one "
+              "all-reduce of sum_i x_i per update) is not implemented", file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -97,6 +237,13 @@ def main():
     from paper_1708_01413_amd import apc, synth
 
     dev = torch.device("cuda:0")
+    if args.copy_calibration:
+        src = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     S = synth.tall_gaussian_16k()
     N, n, m = S.N, S.n, S.m
     A = torch.from_numpy(S.A).to(dev)
@@ -165,6 +312,8 @@ def main():
     dom, dom_bytes, dom_ms = (("pass_b", bytes_b_l, avg_b) if avg_b >= avg_a
                               else ("pass_a", bytes_a_l, avg_a))
     achieved = dom_bytes / (dom_ms * 1e-3) / 1e9
+    dom_label, dom_fn = {"pass_a": ("k_rowdot<float, float, 8, 2>", "k_rowdot"),
+                         "pass_b": ("k_pass_b<float, 8>", "k_pass_b")}[dom]
 
     out = {
         "metric": METRIC,
@@ -186,13 +335,12 @@ def main():
         },
         "roofline": {
             "bound": "hbm",
-            "kernel": {"pass_a": "k_rowdot<float, float, 8, 2>",
-                       "pass_b": "k_pass_b<float, 8>"}[dom] if args.precision == "f32" else dom,
+            "kernel": dom_label if args.precision == "f32" else dom,
             "achieved": round(achieved, 1),
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": None,
+            "traffic": (measured_traffic(dom_label, dom_fn) if args.precision == "f32" else None),
             "algorithmic_bytes_per_launch": dom_bytes,
             "avg_launch_us": round(dom_ms * 1e3, 2),
         },
@@ -220,6 +368,10 @@ def main():
         "params": prm,
         "relres_at_end": relres,
     }
+    if not args.main_only:
+        del A, b, xs, ws
+        torch.cuda.empty_cache()
+        out.update(secondary(apc, synth, dev))
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(S, per_iter)
     print(json.dumps(out), flush=True)
