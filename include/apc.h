@@ -44,13 +44,23 @@ typedef struct apc_plan_s* apc_plan; /* opaque, host-side, owned by the library 
 typedef enum {
   APC_F64 = 0,    /* Q_i and all arithmetic in FP64                                 */
   APC_F32 = 1,    /* Q_i stored in FP32, projections in FP32 with FP32             */
-                  /* accumulation; k = 1: x_i, x_bar and the update/average in     */
-                  /* FP64; k > 1: matrix-core GEMMs, x_bar in FP64 and the         */
-                  /* differences x_bar - x_i in FP32                               */
+                  /* accumulation, iterates and update arithmetic in FP64          */
   APC_BF16_IR = 2 /* iterative refinement: inner APC on a bf16 Q_i (matrix cores,  */
-                  /* FP32 accumulation and state), FP64 residual B - A X on matrix */
-                  /* cores; setup QR and eigenvalue estimate in FP64               */
+                  /* FP32 accumulation, FP64 state), FP64 residual B - A X and     */
+                  /* FP64 start x_bar(0) on matrix cores; setup QR and eigenvalue  */
+                  /* estimate in FP64                                              */
 } apc_precision;
+
+/* Two forms of the same iteration:
+ *  - k = 1 with APC_F64 / APC_F32 keeps every local iterate x_i, as eq. (2a)
+ *    states it (the m n-vectors are <1% of the bytes an update moves);
+ *  - k > 1, and APC_BF16_IR for any k, keeps the exact reduced state
+ *    (y, x_bar): with x_i(0) = Q_i c_i every iterate of eq. (2a) is
+ *    x_i(t) = x_i(0) + P_i y(t), y(0) = 0, y(t+1) = (1-gamma) y(t) +
+ *    gamma x_bar(t), hence (1/m) sum_i x_i(t+1) = x_bar(0) + y(t+1) -
+ *    X y(t+1) with X = (1/m) sum_i Q_i Q_i^T (eq. (3)).  Per update it forms
+ *    W = C y and Z = C^T W, C = [Q_1^T; ...; Q_m^T], as two matrix-core
+ *    products; the x_i are reconstructed on request (apc_get_local). */
 
 typedef enum {
   APC_OK = 0,
@@ -98,9 +108,12 @@ apc_status apc_setup(apc_plan* out, const double* A, int64_t lda, const double* 
                      size_t ws_bytes, void* stream);
 
 /* Apply T updates of eq. (2a)-(2b) (T >= 0).  Asynchronous: per update it
- * enqueues, for each group of blocks, projection pass A (w_i = Q_i^T (x_bar -
- * x_i)) and pass B (x_i += gamma (x_bar - x_i - Q_i w_i)), then the momentum
- * average x_bar <- (eta/m) sum_i x_i + (1 - eta) x_bar, and returns. */
+ * enqueues, k = 1: for each group of blocks, projection pass A (w_i =
+ * Q_i^T (x_bar - x_i)) and pass B (x_i += gamma (x_bar - x_i - Q_i w_i)), then
+ * the momentum average x_bar <- (eta/m) sum_i x_i + (1 - eta) x_bar;
+ * k-RHS form: pass A (W = C y), its split sum, pass B (Z = C^T W) and the
+ * elementwise step y <- (1-gamma) y + gamma x_bar,
+ * x_bar <- eta (x_bar(0) + y - Z/m) + (1 - eta) x_bar.  Returns at once. */
 apc_status apc_iterate(apc_plan p, int32_t T);
 
 /* As apc_iterate, and also times the launches with HIP events recorded on the
@@ -176,6 +189,31 @@ apc_status apc_tridiag_extremes(const double* alpha, const double* beta, int32_t
  * pointer may be NULL. */
 apc_status apc_get_info(apc_plan p, int32_t* lanczos_steps, int32_t* rows_per_tile,
                         int32_t* column_splits, int32_t* block_groups, int32_t* refinements);
+
+/* Launch shape the k-RHS path chose for one of its contractions (which: 0 =
+ * pass A, 1 = pass B, 2 = the FP64 start x_bar(0) = (1/m) C^T c, 3 = the FP64
+ * residual): rows of the streamed operand per workgroup, split-K factor, and
+ * the measured time per launch when it was chosen by timing (0 when fixed by
+ * APC_TN_TUNE=0 / APC_TN_RT / APC_TN_SPLIT).  Shapes are timed once per
+ * problem shape and process.  Host pointers, any may be NULL.
+ * APC_EUNSUPPORTED for a k = 1 FP64/FP32 plan. */
+apc_status apc_get_launch(apc_plan p, int32_t which, int32_t* rows_per_wg, int32_t* splits,
+                          float* tuned_us);
+
+/* Anchor spacing of the FP32 / bf16 k-RHS iteration (plans whose updates use
+ * the (y, x_bar) form with APC_F32 or APC_BF16_IR).  With every > 0, the first
+ * update after setup (and after each refinement restart) and then every
+ * every-th update form X y in FP64 on the FP64 factor and keep it as the anchor
+ * (y_ref, u_ref = X y_ref); the updates in between multiply only y - y_ref
+ * in low precision and add u_ref, so the error of the stored factor and of the
+ * low-precision products acts on a vector that shrinks as the iteration
+ * converges instead of on y itself.  every = 0 runs every update in the plan's
+ * precision (the plain FP32 / bf16 iteration, whose accuracy levels off near
+ * eps_FP32 / mu_min).  Default: 16 for APC_F32, 0 for APC_BF16_IR (there the
+ * outer refinement corrects the inner solver).  Call after apc_setup and before
+ * the first update.  Host-only.  APC_EUNSUPPORTED for other plans, APC_EINVAL
+ * for every < 0 or after an update. */
+apc_status apc_set_anchor(apc_plan p, int32_t every);
 
 /* Number of updates applied since setup (host). */
 int64_t apc_iterations(apc_plan p);

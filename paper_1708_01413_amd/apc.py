@@ -35,7 +35,7 @@ EXPORTED = (
     "apc_workspace_bytes", "apc_setup", "apc_iterate", "apc_iterate_timed", "apc_residual",
     "apc_solve", "apc_get_xbar", "apc_get_local", "apc_project", "apc_get_params",
     "apc_iterations", "apc_destroy", "apc_last_error", "apc_optimal_params",
-    "apc_tridiag_extremes", "apc_get_info",
+    "apc_tridiag_extremes", "apc_get_info", "apc_get_launch", "apc_set_anchor",
 )
 
 
@@ -88,6 +88,8 @@ def _load() -> ctypes.CDLL:
         "apc_get_params": (i32, [vp, Pd, Pd, Pd, Pd, Pd]),
         "apc_iterations": (i64, [vp]),
         "apc_get_info": (i32, [vp, Pi, Pi, Pi, Pi, Pi]),
+        "apc_get_launch": (i32, [vp, i32, Pi, Pi, Pf]),
+        "apc_set_anchor": (i32, [vp, i32]),
         "apc_optimal_params": (i32, [f64, f64, Pd, Pd, Pd]),
         "apc_tridiag_extremes": (i32, [Pd, Pd, i32, i32, Pd, Pd, Pd, Pd]),
         "apc_destroy": (None, [vp]),
@@ -177,6 +179,17 @@ def apc_get_info(plan) -> dict:
                      "refinements"), (v.value for v in vals)))
 
 
+def apc_get_launch(plan, which: int) -> dict:
+    rows, splits, us = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_float()
+    _check(lib.apc_get_launch(plan, which, ctypes.byref(rows), ctypes.byref(splits),
+                              ctypes.byref(us)))
+    return {"rows_per_wg": rows.value, "splits": splits.value, "tuned_us": us.value}
+
+
+def apc_set_anchor(plan, every: int):
+    _check(lib.apc_set_anchor(plan, every))
+
+
 def apc_iterations(plan) -> int:
     return int(lib.apc_iterations(plan))
 
@@ -219,11 +232,12 @@ class Plan:
     A: (N, n) float64 CUDA tensor (row stride may exceed n); b: (N,) or (N, k)
     float64 CUDA tensor (row-major); off: m+1 block offsets.  gamma/eta None
     selects Theorem 1's optimum.  The plan keeps references to A, b and its
-    workspace.
+    workspace.  anchor_every (FP32 / bf16 plans with k > 1 or bf16): FP64
+    anchor spacing, see apc_set_anchor (None keeps the library default).
     """
 
     def __init__(self, A, b, off, precision: str = "f64", gamma=None, eta=None, stream=None,
-                 workspace=None):
+                 workspace=None, anchor_every=None):
         import torch
 
         if A.dtype != torch.float64 or b.dtype != torch.float64:
@@ -259,6 +273,8 @@ class Plan:
         self.handle = apc_setup(A.data_ptr(), A.stride(0), b.data_ptr(), b.stride(0), self.N,
                                 self.n, self.off, self.m, self.k, self.precision, g, e,
                                 self._ws_ptr, ws, self.stream.cuda_stream)
+        if anchor_every is not None:
+            apc_set_anchor(self.handle, int(anchor_every))
 
     # -- iteration
     def iterate(self, T: int):
@@ -311,6 +327,11 @@ class Plan:
 
     def info(self) -> dict:
         return apc_get_info(self.handle)
+
+    def launch_shapes(self) -> dict:
+        """Launch shapes of the k-RHS contractions (pass A, pass B, start, residual)."""
+        return {name: apc_get_launch(self.handle, w)
+                for w, name in enumerate(("pass_a", "pass_b", "start", "residual"))}
 
     @property
     def iterations(self) -> int:

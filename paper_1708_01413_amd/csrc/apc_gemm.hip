@@ -1,0 +1,444 @@
+// Streaming contractions on the gfx950 matrix cores for k right-hand sides.
+//
+// With k > 1 every projection pass is a tall-skinny matrix product.  One
+// kernel serves all of them:
+//
+//   part[s][c][r] = sum_{j in split s} M[r][j] * V[c][j]
+//
+// M (rows x K, row-major) is the large operand and is read exactly once: each
+// lane loads 64 contiguous bytes of a row per step straight into MFMA operand
+// registers (no LDS round trip).  V (one row per right-hand side, K
+// contiguous) is small and re-read by every workgroup: one 256-byte-per-row
+// step of it is staged in LDS and shared by the four waves.  Both operands
+// are laid out K-contiguous, so the per-update passes of the (y, x_bar) form
+// of APC are
+//
+//   pass A:  W  = C  y     M = C   (N x n),  V = y^T (k x n)
+//   pass B:  Z  = C^T W    M = C^T (n x N),  V = W^T (k x N)
+//
+// with C = [Q_1^T; ...; Q_m^T] kept in both orientations.  The same kernel in
+// FP64 forms the minimum-norm start x_bar(0) = (1/m) C^T c and the
+// refinement residual B - A X.
+//
+// K permutation: the MFMA instructions reduce over a K index that is only a
+// label, so a lane's 64-byte run of a row is split into four 16-byte pieces,
+// piece p feeding the p-th MFMA of the step (bf16: one 16x16x32, f32: four
+// 16x16x4, f64: two 16x16x4).  V is read from LDS with exactly the same
+// (lane group, piece, element) -> K mapping, so the sum is over all of K.
+//
+// Split-K partials are written per split and summed in a fixed order by the
+// epilogue kernels, so results do not depend on timing.
+
+#include <hip/hip_runtime.h>
+
+#include "apc_internal.h"
+
+namespace apc {
+
+namespace {
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+typedef double f64x2 __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+
+template <typename T>
+struct TnTraits;
+template <>
+struct TnTraits<__bf16> {
+  using Acc = f32x4;
+  using Part = float;
+};
+template <>
+struct TnTraits<float> {
+  using Acc = f32x4;
+  using Part = float;
+};
+template <>
+struct TnTraits<double> {
+  using Acc = f64x4;
+  using Part = double;
+};
+
+// MFMA over one 16-byte piece of A (lane's row) and B (lane's right-hand side).
+__device__ inline void mma_piece(const u32x4& a, const u32x4& b, f32x4& c, __bf16*) {
+  c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a),
+                                              __builtin_bit_cast(bf16x8, b), c, 0, 0, 0);
+}
+__device__ inline void mma_piece(const u32x4& a, const u32x4& b, f32x4& c, float*) {
+  const f32x4 av = __builtin_bit_cast(f32x4, a);
+  const f32x4 bv = __builtin_bit_cast(f32x4, b);
+#pragma unroll
+  for (int e = 0; e < 4; ++e) c = __builtin_amdgcn_mfma_f32_16x16x4f32(av[e], bv[e], c, 0, 0, 0);
+}
+__device__ inline void mma_piece(const u32x4& a, const u32x4& b, f64x4& c, double*) {
+  const f64x2 av = __builtin_bit_cast(f64x2, a);
+  const f64x2 bv = __builtin_bit_cast(f64x2, b);
+#pragma unroll
+  for (int e = 0; e < 2; ++e) c = __builtin_amdgcn_mfma_f64_16x16x4f64(av[e], bv[e], c, 0, 0, 0);
+}
+
+// Workgroup: 4 waves, wave w owns RT consecutive 16-row tiles, all 16*NCT
+// right-hand sides of its column group.  Grid: (rows / (64 RT)) x ncg x nsplit,
+// with the split index fastest so that, dealt round-robin over the 8 XCDs, one
+// XCD works on one split (nsplit | 8) and keeps that split's V in its L2.
+template <typename T, int RT, int NCT>
+__global__ __launch_bounds__(256) void k_tn(TnArgs a) {
+  using Acc = typename TnTraits<T>::Acc;
+  using Part = typename TnTraits<T>::Part;
+  constexpr int kE = 16 / sizeof(T);  // elements per 16-byte piece
+  constexpr int kStep = 16 * kE;      // elements per row per step (256 bytes)
+  const int ncg = a.kp / (16 * NCT);
+  int q = blockIdx.x;
+  const int split = q % a.nsplit;
+  q /= a.nsplit;
+  const int cg = q % ncg;
+  const int64_t rtile = q / ncg;
+  const int lane = threadIdx.x & 63;
+  const int wv = threadIdx.x >> 6;
+  const int li = lane & 15, g = lane >> 4;
+  const int64_t kb0 = static_cast<int64_t>(split) * a.klen;
+  const int64_t kend = min(a.K, kb0 + a.klen);
+  const int nsteps = kend > kb0 ? static_cast<int>((kend - kb0) / kStep) : 0;
+  const T* M = static_cast<const T*>(a.M);
+  const T* V = static_cast<const T*>(a.V) + static_cast<int64_t>(cg) * NCT * 16 * a.ldv + kb0;
+  const int64_t rb = rtile * 64 * RT + static_cast<int64_t>(wv) * 16 * RT;
+
+  const T* mrow[RT];
+#pragma unroll
+  for (int t = 0; t < RT; ++t) mrow[t] = M + (rb + 16 * t + li) * a.ldm + kb0 + g * 4 * kE;
+  const int vr = threadIdx.x >> 4, vp = threadIdx.x & 15;
+  const T* vsrc = V + static_cast<int64_t>(vr) * a.ldv + vp * kE;
+
+  __shared__ u32x4 vs[2][NCT * 16][17];  // 16 pieces per row + 1 pad: conflict-free reads
+  Acc acc[RT][NCT];
+#pragma unroll
+  for (int t = 0; t < RT; ++t)
+#pragma unroll
+    for (int ct = 0; ct < NCT; ++ct) acc[t][ct] = Acc{};
+  u32x4 mc[RT][4], mn[RT][4], vst[NCT];
+
+  if (nsteps > 0) {
+#pragma unroll
+    for (int t = 0; t < RT; ++t)
+#pragma unroll
+      for (int p = 0; p < 4; ++p) mc[t][p] = *reinterpret_cast<const u32x4*>(mrow[t] + p * kE);
+#pragma unroll
+    for (int u = 0; u < NCT; ++u)
+      vst[u] = *reinterpret_cast<const u32x4*>(vsrc + static_cast<int64_t>(16 * u) * a.ldv);
+#pragma unroll
+    for (int u = 0; u < NCT; ++u) vs[0][vr + 16 * u][vp] = vst[u];
+  }
+  __syncthreads();
+  for (int step = 0; step < nsteps; ++step) {
+    const int buf = step & 1;
+    const bool more = step + 1 < nsteps;
+    if (more) {
+      const int64_t o = static_cast<int64_t>(step + 1) * kStep;
+#pragma unroll
+      for (int t = 0; t < RT; ++t)
+#pragma unroll
+        for (int p = 0; p < 4; ++p) mn[t][p] = *reinterpret_cast<const u32x4*>(mrow[t] + o + p * kE);
+#pragma unroll
+      for (int u = 0; u < NCT; ++u)
+        vst[u] = *reinterpret_cast<const u32x4*>(vsrc + static_cast<int64_t>(16 * u) * a.ldv + o);
+    }
+#pragma unroll
+    for (int p = 0; p < 4; ++p) {
+      u32x4 bf[NCT];
+#pragma unroll
+      for (int ct = 0; ct < NCT; ++ct) bf[ct] = vs[buf][ct * 16 + li][4 * g + p];
+#pragma unroll
+      for (int t = 0; t < RT; ++t)
+#pragma unroll
+        for (int ct = 0; ct < NCT; ++ct) mma_piece(mc[t][p], bf[ct], acc[t][ct], static_cast<T*>(nullptr));
+    }
+    if (more) {
+#pragma unroll
+      for (int u = 0; u < NCT; ++u) vs[buf ^ 1][vr + 16 * u][vp] = vst[u];
+    }
+    __syncthreads();
+    if (more) {
+#pragma unroll
+      for (int t = 0; t < RT; ++t)
+#pragma unroll
+        for (int p = 0; p < 4; ++p) mc[t][p] = mn[t][p];
+    }
+  }
+
+  // Result layout: f32 accumulators hold D[4 g + q][li]; f64 ones D[g + 4 q][li].
+  Part* part = static_cast<Part*>(a.part);
+#pragma unroll
+  for (int t = 0; t < RT; ++t)
+#pragma unroll
+    for (int ct = 0; ct < NCT; ++ct) {
+      const int c = cg * NCT * 16 + ct * 16 + li;
+      Part* dst = part + (static_cast<int64_t>(split) * a.kp + c) * a.ldp + rb + 16 * t;
+      if constexpr (sizeof(Part) == 8) {
+#pragma unroll
+        for (int qq = 0; qq < 4; ++qq) dst[g + 4 * qq] = acc[t][ct][qq];
+      } else {
+        *reinterpret_cast<f32x4*>(dst + 4 * g) = acc[t][ct];
+      }
+    }
+}
+
+template <typename T, int RT>
+hipError_t tn_nct(const TnArgs& a, hipStream_t s) {
+  const int nct = a.kp >= 128 ? 8 : a.kp / 16;
+  const int64_t ncg = a.kp / (16 * nct);
+  const int64_t blocks = (a.rows / (64 * RT)) * ncg * a.nsplit;
+  const dim3 grid(static_cast<unsigned>(blocks)), block(256);
+  switch (nct) {
+    case 1: k_tn<T, RT, 1><<<grid, block, 0, s>>>(a); break;
+    case 2: k_tn<T, RT, 2><<<grid, block, 0, s>>>(a); break;
+    case 4: k_tn<T, RT, 4><<<grid, block, 0, s>>>(a); break;
+    case 8: k_tn<T, RT, 8><<<grid, block, 0, s>>>(a); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t tn_rt(int rt, const TnArgs& a, hipStream_t s) {
+  switch (rt) {
+    case 1: return tn_nct<T, 1>(a, s);
+    case 2: return tn_nct<T, 2>(a, s);
+    case 4:
+      if constexpr (sizeof(T) == 8) return hipErrorInvalidValue;
+      else return tn_nct<T, 4>(a, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+// ------------------------------------------------------------------ epilogues
+
+template <typename T>
+__device__ inline T cvt(double v);
+template <>
+__device__ inline double cvt<double>(double v) { return v; }
+template <>
+__device__ inline float cvt<float>(double v) { return static_cast<float>(v); }
+template <>
+__device__ inline __bf16 cvt<__bf16>(double v) { return static_cast<__bf16>(static_cast<float>(v)); }
+
+template <typename P>
+__device__ inline double split_sum(const P* part, int32_t nsplit, int64_t split_stride, int64_t idx) {
+  P s = part[idx];
+  for (int sp = 1; sp < nsplit; ++sp) s += part[sp * split_stride + idx];
+  return static_cast<double>(s);
+}
+
+// out[c*ldo + r] = TQ(sum of the split partials), r < rows, c < kp.
+template <typename P, typename TQ>
+__global__ __launch_bounds__(256) void k_tn_sum_cast(const P* part, int32_t nsplit, int32_t kp,
+                                                     int64_t ldp, int64_t rows, TQ* out, int64_t ldo) {
+  const int64_t total = static_cast<int64_t>(kp) * rows;
+  const int64_t stride = static_cast<int64_t>(kp) * ldp;
+  for (int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; e < total;
+       e += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    const int64_t c = e / rows, r = e - c * rows;
+    P s = part[c * ldp + r];
+    for (int sp = 1; sp < nsplit; ++sp) s += part[sp * stride + c * ldp + r];
+    out[c * ldo + r] = static_cast<TQ>(s);
+  }
+}
+
+// The (y, x_bar) update, its start, or an anchor update; see TnUpdateArgs.
+template <typename P, typename TQ>
+__global__ __launch_bounds__(256) void k_tn_update(TnUpdateArgs a) {
+  const int64_t total = static_cast<int64_t>(a.kp) * a.n;
+  const int64_t stride = static_cast<int64_t>(a.kp) * a.ldp;
+  const P* part = static_cast<const P*>(a.part);
+  TQ* yq = static_cast<TQ*>(a.yq);
+  const double g = a.gamma, omg = 1.0 - a.gamma, eta = a.eta, ome = 1.0 - a.eta;
+  for (int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; e < total;
+       e += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    const int64_t c = e / a.n, j = e - c * a.n;
+    const double z = split_sum(part, a.nsplit, stride, c * a.ldp + j);
+    const int64_t i = c * a.ldx + j;
+    if (a.mode == 1) {
+      const double x0 = z * a.inv_m;
+      a.x0[i] = x0;
+      a.xb[i] = x0;
+      a.y[i] = 0.0;
+      if (a.yref) {
+        a.yref[i] = 0.0;
+        a.uref[i] = 0.0;
+      }
+      yq[c * a.ldq + j] = cvt<TQ>(g * x0);
+      continue;
+    }
+    const double xb = a.xb[i];
+    // y1 = (1 - gamma) y + gamma x_bar; an anchor update reads the copy its
+    // FP64 product was formed from.
+    const double y1 = a.mode == 2 ? a.yref[i] : omg * a.y[i] + g * xb;
+    double u = z * a.inv_m;
+    double ref = 0.0;
+    if (a.mode == 2) {  // z = m X y1 in FP64: new anchor
+      a.uref[i] = u;
+      ref = y1;
+    } else if (a.yref) {  // z = m X~ (y1 - y_ref)
+      u += a.uref[i];
+      ref = a.yref[i];
+    }
+    const double xn = eta * (a.x0[i] + y1 - u) + ome * xb;
+    a.y[i] = y1;
+    a.xb[i] = xn;
+    yq[c * a.ldq + j] = cvt<TQ>(omg * y1 + g * xn - ref);
+  }
+}
+
+// y_ref = (1 - gamma) y + gamma x_bar (the vector the next update multiplies), FP64.
+__global__ __launch_bounds__(256) void k_tn_anchor_vec(const double* y, const double* xb, int64_t count,
+                                                       double gamma, double* yref) {
+  for (int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; e < count;
+       e += static_cast<int64_t>(gridDim.x) * blockDim.x)
+    yref[e] = (1.0 - gamma) * y[e] + gamma * xb[e];
+}
+
+// R[c*ldr + r] = B[r*ldb + c] - sum of the FP64 split partials, r < N, c < k.
+__global__ __launch_bounds__(256) void k_tn_resid(const double* part, int32_t nsplit, int32_t kp,
+                                                  int64_t ldp, int64_t N, int32_t k, const double* B,
+                                                  int64_t ldb, double* R, int64_t ldr) {
+  const int64_t total = static_cast<int64_t>(k) * N;
+  const int64_t stride = static_cast<int64_t>(kp) * ldp;
+  for (int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; e < total;
+       e += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    const int64_t r = e / k, c = e - r * k;  // B read row by row
+    R[c * ldr + r] = B[r * ldb + c] - split_sum(part, nsplit, stride, c * ldp + r);
+  }
+}
+
+// dst (drows x ldd, type TQ) = src or src^T (FP64, srows x scols, stride lds),
+// zero outside the source.  64 x 64 tiles through LDS for the transpose.
+template <typename TQ>
+__global__ __launch_bounds__(256) void k_tn_pack(const double* src, int64_t lds, int64_t srows,
+                                                 int64_t scols, int32_t transpose, TQ* dst,
+                                                 int64_t ldd, int64_t drows) {
+  __shared__ double tile[64][65];
+  const int64_t tiles_c = (ldd + 63) / 64;
+  const int64_t tr = blockIdx.x / tiles_c, tc = blockIdx.x % tiles_c;
+  const int64_t r0 = tr * 64, c0 = tc * 64;  // destination tile origin
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  if (!transpose) {
+    for (int rr = ty; rr < 64; rr += 4) {
+      const int64_t r = r0 + rr, c = c0 + tx;
+      if (r >= drows || c >= ldd) continue;
+      const double v = (r < srows && c < scols) ? src[r * lds + c] : 0.0;
+      dst[r * ldd + c] = cvt<TQ>(v);
+    }
+    return;
+  }
+  // dst[r][c] = src[c][r]: read src rows c0.. (coalesced along r), write dst rows r0..
+  for (int cc = ty; cc < 64; cc += 4) {
+    const int64_t sr = c0 + cc, sc = r0 + tx;
+    tile[cc][tx] = (sr < srows && sc < scols) ? src[sr * lds + sc] : 0.0;
+  }
+  __syncthreads();
+  for (int rr = ty; rr < 64; rr += 4) {
+    const int64_t r = r0 + rr, c = c0 + tx;
+    if (r < drows && c < ldd) dst[r * ldd + c] = cvt<TQ>(tile[tx][rr]);
+  }
+}
+
+unsigned grid_stride_blocks(int64_t total) {
+  int64_t b = (total + 255) / 256;
+  return static_cast<unsigned>(std::max<int64_t>(1, std::min<int64_t>(b, 8192)));
+}
+
+}  // namespace
+
+hipError_t launch_tn(int type, int rt, const TnArgs& a, hipStream_t s) {
+  if (a.kp < 16 || (a.kp > 128 && a.kp % 128) || (a.kp <= 128 && (a.kp & (a.kp - 1))) ||
+      a.rows % (64 * rt) || a.nsplit < 1 || a.nsplit > kTnMaxSplit)
+    return hipErrorInvalidValue;
+  switch (type) {
+    case kTnF64: return tn_rt<double>(rt, a, s);
+    case kTnF32: return tn_rt<float>(rt, a, s);
+    case kTnBF16: return tn_rt<__bf16>(rt, a, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+int tn_step_elems(int type) { return type == kTnF64 ? 32 : type == kTnF32 ? 64 : 128; }
+
+hipError_t launch_tn_sum_cast(int type, const void* part, int32_t nsplit, int32_t kp, int64_t ldp,
+                              int64_t rows, void* out, int64_t ldo, hipStream_t s) {
+  const unsigned g = grid_stride_blocks(static_cast<int64_t>(kp) * rows);
+  switch (type) {
+    case kTnF64:
+      k_tn_sum_cast<double, double><<<g, 256, 0, s>>>(static_cast<const double*>(part), nsplit, kp,
+                                                      ldp, rows, static_cast<double*>(out), ldo);
+      break;
+    case kTnF32:
+      k_tn_sum_cast<float, float><<<g, 256, 0, s>>>(static_cast<const float*>(part), nsplit, kp,
+                                                    ldp, rows, static_cast<float*>(out), ldo);
+      break;
+    case kTnBF16:
+      k_tn_sum_cast<float, __bf16><<<g, 256, 0, s>>>(static_cast<const float*>(part), nsplit, kp,
+                                                     ldp, rows, static_cast<__bf16*>(out), ldo);
+      break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_tn_update(int type, int part_f64, const TnUpdateArgs& a, hipStream_t s) {
+  const unsigned g = grid_stride_blocks(static_cast<int64_t>(a.kp) * a.n);
+  if (part_f64) {
+    switch (type) {
+      case kTnF64: k_tn_update<double, double><<<g, 256, 0, s>>>(a); break;
+      case kTnF32: k_tn_update<double, float><<<g, 256, 0, s>>>(a); break;
+      case kTnBF16: k_tn_update<double, __bf16><<<g, 256, 0, s>>>(a); break;
+      default: return hipErrorInvalidValue;
+    }
+  } else {
+    switch (type) {
+      case kTnF32: k_tn_update<float, float><<<g, 256, 0, s>>>(a); break;
+      case kTnBF16: k_tn_update<float, __bf16><<<g, 256, 0, s>>>(a); break;
+      default: return hipErrorInvalidValue;
+    }
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_tn_anchor_vec(const double* y, const double* xb, int64_t count, double gamma,
+                               double* yref, hipStream_t s) {
+  k_tn_anchor_vec<<<grid_stride_blocks(count), 256, 0, s>>>(y, xb, count, gamma, yref);
+  return hipGetLastError();
+}
+
+hipError_t launch_tn_resid(const double* part, int32_t nsplit, int32_t kp, int64_t ldp, int64_t N,
+                           int32_t k, const double* B, int64_t ldb, double* R, int64_t ldr,
+                           hipStream_t s) {
+  k_tn_resid<<<grid_stride_blocks(static_cast<int64_t>(k) * N), 256, 0, s>>>(part, nsplit, kp, ldp,
+                                                                           N, k, B, ldb, R, ldr);
+  return hipGetLastError();
+}
+
+hipError_t launch_tn_pack(int type, const double* src, int64_t lds, int64_t srows, int64_t scols,
+                          int32_t transpose, void* dst, int64_t ldd, int64_t drows, hipStream_t s) {
+  const int64_t blocks = ((drows + 63) / 64) * ((ldd + 63) / 64);
+  if (blocks < 1) return hipSuccess;
+  const dim3 grid(static_cast<unsigned>(blocks));
+  switch (type) {
+    case kTnF64:
+      k_tn_pack<double><<<grid, 256, 0, s>>>(src, lds, srows, scols, transpose,
+                                             static_cast<double*>(dst), ldd, drows);
+      break;
+    case kTnF32:
+      k_tn_pack<float><<<grid, 256, 0, s>>>(src, lds, srows, scols, transpose,
+                                            static_cast<float*>(dst), ldd, drows);
+      break;
+    case kTnBF16:
+      k_tn_pack<__bf16><<<grid, 256, 0, s>>>(src, lds, srows, scols, transpose,
+                                             static_cast<__bf16*>(dst), ldd, drows);
+      break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace apc

@@ -13,7 +13,10 @@
 #include <cstdlib>
 #include <cstring>
 #include <limits>
+#include <map>
+#include <mutex>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "apc.h"
@@ -52,6 +55,7 @@ apc_status fail(apc_status st, const char* fmt, ...) {
 constexpr int64_t kAlign = 256;
 constexpr int kLanczosMax = 1024;   // Lanczos steps cap (full reorthogonalisation)
 constexpr int kLanczosCheck = 4;    // steps between convergence checks (host syncs)
+constexpr int kAnchorEvery = 16;    // default anchor spacing of the FP32 k-RHS iteration
 
 int64_t round_up(int64_t v, int64_t a) { return (v + a - 1) / a * a; }
 
@@ -60,15 +64,15 @@ int64_t round_up(int64_t v, int64_t a) { return (v + a - 1) / a * a; }
 struct Layout {
   int64_t ldc = 0, kmax = 0, S = 0;
   int32_t ntiles_a = 0, ntiles_g = 0, ntiles_t = 0, nparts = 0;
-  int32_t ntiles_k = 0;
-  int64_t ldw16 = 0;
-  size_t wpart, wsum, tiles_k, C16, W16, Xs, Rb, cw, Linv2, ssq;
+  // k-RHS path: rows/K padding of its operands (N and n rounded up to kTnPad)
+  int64_t Np = 0, np = 0;
+  size_t Cq, CqT, C64T, Apad, yq, Wq, tnpart, x0, ys, c64p, Xs, Rb, cw, Linv2, ssq;
+  size_t C64p, yref, uref, W64;  // FP64 anchor of the FP32 / bf16 k-RHS iteration
   size_t C64a, C64b, C32, x, xbar, dv, w, ca, cb, Y, vtmp, V, h, h2, alpha, beta, G, Linv, flags, scal, partial, tiles_a, tiles_g, tiles_t, doff, goff, total;
 };
 
 struct Tiles {
   std::vector<int32_t> a_row0, a_nrows, a_blk;  // pass-A row tiles, aligned to block starts
-  std::vector<int32_t> k_row0, k_nrows, k_blk;  // 128-row tiles of the k-RHS pass A
   std::vector<int32_t> g;                        // Gram tiles (blk, ta, tb), ta >= tb
   std::vector<int32_t> t;                        // TRMM tiles (blk, ta, tc)
   std::vector<int64_t> goff;                     // offset of G_i in the packed Gram storage
@@ -77,7 +81,6 @@ struct Tiles {
 constexpr int kMinRowTile = 8;  // the workspace holds pass-A tile lists of this height or more
 constexpr int kPassARows = 8;   // default rows per pass-A workgroup
 constexpr int kMaxSplit = 8;    // pass-A column splits the workspace holds partials for
-constexpr int kMaxSplitK = 16;  // split-K factor cap of the k-RHS pass A
 
 void build_tiles(const int64_t* off, int32_t m, int64_t ldc, int rows_per_tile, Tiles* T) {
   int64_t g = 0;
@@ -88,11 +91,6 @@ void build_tiles(const int64_t* off, int32_t m, int64_t ldc, int rows_per_tile, 
       T->a_row0.push_back(static_cast<int32_t>(off[i] + r));
       T->a_nrows.push_back(static_cast<int32_t>(std::min<int64_t>(rows_per_tile, p - r)));
       T->a_blk.push_back(i);
-    }
-    for (int64_t r = 0; r < p; r += kMfmaTileRows) {
-      T->k_row0.push_back(static_cast<int32_t>(off[i] + r));
-      T->k_nrows.push_back(static_cast<int32_t>(std::min<int64_t>(kMfmaTileRows, p - r)));
-      T->k_blk.push_back(i);
     }
     const int64_t pt = (p + kGramTile - 1) / kGramTile;
     for (int64_t a = 0; a < pt; ++a) {
@@ -112,10 +110,18 @@ void build_tiles(const int64_t* off, int32_t m, int64_t ldc, int rows_per_tile, 
   }
 }
 
-// Columns the state keeps per right-hand side set: k itself for k = 1, else k
-// rounded up to the 16-wide matrix-core tile (the extra columns stay zero).
+// k > 1 (and the mixed-precision mode) run the (y, x_bar) form on the matrix
+// cores; k = 1 in FP64/FP32 keeps every block's x_i.
+bool uses_gemm(int32_t k, int32_t prec) { return k > 1 || prec == APC_BF16_IR; }
+
+// Right-hand sides the k-RHS state holds: 16, 32, 64, then multiples of 128
+// (one matrix-core column group); the extra columns stay zero.
 int32_t padded_rhs(int32_t k, int32_t prec) {
-  return (k == 1 && prec != APC_BF16_IR) ? 1 : static_cast<int32_t>(round_up(k, 16));
+  if (!uses_gemm(k, prec)) return 1;
+  if (k <= 16) return 16;
+  if (k <= 32) return 32;
+  if (k <= 64) return 64;
+  return static_cast<int32_t>(round_up(k, 128));
 }
 
 Layout make_layout(int64_t N, int64_t n, const int64_t* off, int32_t m, int32_t k, int32_t prec,
@@ -138,13 +144,15 @@ Layout make_layout(int64_t N, int64_t n, const int64_t* off, int32_t m, int32_t 
     return at;
   };
   const int64_t d = sizeof(double);
+  const bool gemm = uses_gemm(k, prec);
+  const bool bf = prec == APC_BF16_IR;
+  const int64_t kq = k == 1 ? 1 : kp;        // k = 1 state columns
   L.C64a = take(N * L.ldc * d);
   L.C64b = take(N * L.ldc * d);
-  L.C32 = take(prec == APC_F32 ? N * L.ldc * 4 : 0);
-  L.x = take(m * kp * L.ldc * d);
-  L.xbar = take(kp * L.ldc * d);
-  L.dv = take(m * kp * L.ldc * d);
-  L.w = take(kMaxSplit * N * kp * d);
+  L.C32 = take(prec == APC_F32 && !gemm ? N * L.ldc * 4 : 0);
+  L.x = take(gemm ? 0 : m * kq * L.ldc * d);
+  L.dv = take(gemm ? 0 : m * kq * L.ldc * d);
+  L.w = take(kMaxSplit * N * d);
   L.ca = take(N * kp * d);
   L.cb = take(N * kp * d);
   L.Y = take(m * L.ldc * d);
@@ -156,27 +164,38 @@ Layout make_layout(int64_t N, int64_t n, const int64_t* off, int32_t m, int32_t 
   L.beta = take((L.kmax + 1) * d);
   L.G = take(L.S * d);
   L.Linv = take(L.S * d);
-  L.Linv2 = take(prec == APC_BF16_IR ? L.S * d : 0);
+  L.Linv2 = take(bf ? L.S * d : 0);
   L.flags = take(4 * 4);
   L.scal = take(8 * d);
-  L.partial = take(L.nparts * kp * d);
-  // k-RHS matrix-core path (FP32 mode, k > 1): split-K partials of W, their sum
-  // (16 spare columns per row), and the 128-row tile lists.
-  const bool bf = prec == APC_BF16_IR;
-  const bool mfma = (prec == APC_F32 && k > 1) || bf;
-  L.ntiles_k = static_cast<int32_t>(T.k_row0.size());
-  L.wpart = take(mfma ? kMaxSplitK * kp * N * 4 : 0);
-  L.wsum = take(mfma && !bf ? kp * (N + 16) * 4 : 0);
-  L.tiles_k = take(mfma ? 3 * static_cast<int64_t>(L.ntiles_k) * 4 : 0);
-  // Mixed precision: bf16 factor and W, FP64 committed solution X, residual R,
-  // right-hand-side work vector, the first CholeskyQR pass's inverse factor.
-  L.ldw16 = round_up(N, 8);
-  const int64_t big = std::max<int64_t>(N, L.ldc);
-  L.C16 = take(bf ? N * L.ldc * 2 : 0);
-  L.W16 = take(bf ? kp * L.ldw16 * 2 : 0);
-  L.Xs = take(bf ? kp * L.ldc * d : 0);
-  L.Rb = take(k > 1 || bf ? kp * big * d : 0);
-  L.cw = take(bf ? kp * big * d : 0);
+  L.partial = take(L.nparts * kq * d);
+  // k-RHS path: the factor in the iteration's precision in both orientations
+  // (C: Np x np, C^T: np x Np), its FP64 transpose for x_bar(0) = (1/m) C^T c
+  // (the FP64 mode iterates on it), a padded FP64 copy of A for the residual,
+  // the operands y and W, split-K partials, the FP64 state x0, y, x_bar.
+  L.Np = gemm ? round_up(N, kTnPad) : 0;
+  L.np = gemm ? round_up(n, kTnPad) : 0;
+  const int64_t sq = prec == APC_F64 ? 8 : prec == APC_F32 ? 4 : 2;
+  L.Cq = take(gemm ? L.Np * L.np * sq : 0);
+  L.CqT = take(gemm ? L.np * L.Np * sq : 0);
+  L.C64T = take(gemm && prec != APC_F64 ? L.np * L.Np * d : 0);
+  L.Apad = take(gemm ? L.Np * L.np * d : 0);
+  L.yq = take(gemm ? kp * L.np * sq : 0);
+  L.Wq = take(gemm ? kp * L.Np * sq : 0);
+  L.tnpart = take(gemm ? static_cast<int64_t>(kTnMaxSplit) * kp * std::max(L.Np, L.np) * d : 0);
+  L.xbar = take((gemm ? kp * L.np : kq * L.ldc) * d);
+  L.x0 = take(gemm ? kp * L.np * d : 0);
+  L.ys = take(gemm ? kp * L.np * d : 0);
+  L.c64p = take(gemm ? kp * L.Np * d : 0);
+  L.Xs = take(bf ? kp * L.np * d : 0);
+  // Anchor updates (FP32 and bf16 iterations): the FP64 factor as pass-A
+  // operand, the anchor y_ref, u_ref = X y_ref, and the FP64 W.
+  const bool anc = gemm && prec != APC_F64;
+  L.C64p = take(anc ? L.Np * L.np * d : 0);
+  L.yref = take(anc ? kp * L.np * d : 0);
+  L.uref = take(anc ? kp * L.np * d : 0);
+  L.W64 = take(anc ? kp * L.Np * d : 0);
+  L.Rb = take(gemm ? kp * N * d : 0);
+  L.cw = take(bf ? kp * N * d : 0);
   L.ssq = take(sumsq_parts() * d);
   L.tiles_a = take(3 * max_tiles_a * 4);
   L.tiles_g = take(3 * static_cast<int64_t>(L.ntiles_g) * 4);
@@ -294,6 +313,13 @@ uint64_t splitmix64(uint64_t x) {
 
 // ------------------------------------------------------------------ the plan
 
+// Launch shape of one streaming contraction (rows per workgroup = 64 rt).
+struct TnChoice {
+  int rt = 2;
+  int nsplit = 1;
+  float us = 0.f;  // measured time per launch when tuned
+};
+
 struct apc_plan_s {
   int device = 0;
   hipStream_t stream = nullptr;
@@ -314,11 +340,13 @@ struct apc_plan_s {
   int32_t xcd_remap = 1, passa_rows = kRowTile, nsplit = 1;
   int64_t split_cols = 0;
   int32_t group_blocks = 0;            // blocks per pass-A/pass-B group (MALL reuse)
-  bool mfma = false;                   // k-RHS FP32 path on matrix cores
+  bool gemm = false;                   // k-RHS path: (y, x_bar) form on the matrix cores
   bool bf16 = false;                   // mixed precision: bf16 inner solver + FP64 refinement
+  int tq = kTnF64;                     // element type of the k-RHS factor copies
+  TnChoice tnA, tnB, tnX0, tnR;        // launch shapes: pass A, pass B, x_bar(0), residual
+  int anchor_every = 0;                // k-RHS FP32/bf16: every this many updates one in FP64
+  int64_t since_start = 0;             // k-RHS updates since the last start
   int refinements = 0;
-  int32_t ksplit = 1;                  // its split-K factor
-  int64_t ksplit_cols = 0;
   std::vector<int32_t> tile_start;     // first pass-A tile of every block (m+1)
   std::vector<hipEvent_t> events;
 
@@ -329,7 +357,6 @@ struct apc_plan_s {
   double* xbar() const { return at<double>(L.xbar); }
   int64_t* doff() const { return at<int64_t>(L.doff); }
   int32_t* ta(int which) const { return at<int32_t>(L.tiles_a) + which * L.ntiles_a; }
-  int32_t* tk(int which) const { return at<int32_t>(L.tiles_k) + which * L.ntiles_k; }
   int32_t slab_cols() const { return pass_b_slab(prec == APC_F32 ? 4 : 8); }
   int64_t state_ld() const { return static_cast<int64_t>(kp) * L.ldc; }  // block stride of x, d
 };
@@ -390,91 +417,249 @@ apc_status pass_b(apc_plan_s* P, int i0, int i1, int col) {
   return APC_OK;
 }
 
-// One update of eq. (2a)-(2b): for each group of blocks, pass A then pass B
-// (pass B of a block needs only that block's w, so a group's rows of C are
-// re-read while they are still in the Infinity Cache), then the average.
+// ------------------------------------------------------------------ k right-hand sides
+//
+// For k > 1 the plan keeps APC in its (y, x_bar) form.  With the minimum-norm
+// start x_i(0) = Q_i c_i (so P_i x_i(0) = 0), eq. (2a) keeps every local
+// iterate at x_i(t) = x_i(0) + P_i y(t) with y(0) = 0 and
+// y(t+1) = (1 - gamma) y(t) + gamma x_bar(t), so the average in eq. (2b) is
+// (1/m) sum_i x_i(t+1) = x_bar(0) + y(t+1) - X y(t+1),  X = (1/m) C^T C.
+// An update is then pass A (W = C y), pass B (Z = C^T W) and an elementwise
+// step; no per-block state is streamed.
+
+TnArgs tn_args(const void* M, int64_t ldm, int64_t rows, const void* V, int64_t ldv, int32_t kp,
+               int64_t K, const TnChoice& ch, int type, void* part, int64_t ldp) {
+  TnArgs a{M, ldm, rows, V, ldv, kp, K, ch.nsplit, 0, part, ldp};
+  a.klen = round_up((K + ch.nsplit - 1) / ch.nsplit, tn_step_elems(type));
+  return a;
+}
+
+TnArgs pass_a_args(const apc_plan_s* P) {
+  const Layout& L = P->L;
+  return tn_args(P->ws + L.Cq, L.np, L.Np, P->ws + L.yq, L.np, P->kp, L.np, P->tnA, P->tq,
+                 P->ws + L.tnpart, L.Np);
+}
+TnArgs pass_b_args(const apc_plan_s* P) {
+  const Layout& L = P->L;
+  return tn_args(P->ws + L.CqT, L.Np, L.np, P->ws + L.Wq, L.Np, P->kp, L.Np, P->tnB, P->tq,
+                 P->ws + L.tnpart, L.np);
+}
+TnArgs x0_args(const apc_plan_s* P) {
+  const Layout& L = P->L;
+  const void* Mt = P->tq == kTnF64 ? P->ws + L.CqT : P->ws + L.C64T;
+  return tn_args(Mt, L.Np, L.np, P->ws + L.c64p, L.Np, P->kp, L.Np, P->tnX0, kTnF64,
+                 P->ws + L.tnpart, L.np);
+}
+TnArgs resid_args(const apc_plan_s* P, const double* X) {
+  const Layout& L = P->L;
+  return tn_args(P->ws + L.Apad, L.np, L.Np, X, L.np, P->kp, L.np, P->tnR, kTnF64,
+                 P->ws + L.tnpart, L.Np);
+}
+
+TnUpdateArgs update_args(const apc_plan_s* P, const TnChoice& ch, int mode) {
+  const Layout& L = P->L;
+  // The start zeroes y_ref and u_ref whenever they exist (with both zero an
+  // update is the same as an unanchored one).
+  const bool anc = P->prec != APC_F64 && (P->anchor_every > 0 || mode == 1);
+  return TnUpdateArgs{P->ws + L.tnpart, ch.nsplit, P->kp, L.np, L.np, P->at<double>(L.x0),
+                      P->at<double>(L.ys), P->xbar(), L.np, P->ws + L.yq, L.np, P->gamma, P->eta,
+                      1.0 / P->m, mode, anc ? P->at<double>(L.yref) : nullptr,
+                      anc ? P->at<double>(L.uref) : nullptr};
+}
+
+// One update of the (y, x_bar) form.  In the FP32 and bf16 iterations every
+// anchor_every-th update (the first after a start included) forms X y in FP64
+// and keeps it as the anchor: u_ref = X y_ref.  The low-precision updates in
+// between multiply only y - y_ref, which shrinks as the iteration converges,
+// so their rounding (and the rounding of the stored factor) stops limiting
+// the attainable accuracy.  *nev receives the number of events recorded.
+apc_status update_gemm(apc_plan_s* P, hipEvent_t* ev, int* kinds, int* nev) {
+  const Layout& L = P->L;
+  int e = 0;
+  void* part = P->ws + L.tnpart;
+  const bool anchor = P->anchor_every > 0 && P->since_start % P->anchor_every == 0;
+  if (anchor) {
+    const int64_t cnt = static_cast<int64_t>(P->kp) * L.np;
+    HIP_TRY(launch_tn_anchor_vec(P->at<double>(L.ys), P->xbar(), cnt, P->gamma,
+                                 P->at<double>(L.yref), P->stream));
+    TnArgs a = tn_args(P->ws + L.C64p, L.np, L.Np, P->ws + L.yref, L.np, P->kp, L.np, P->tnR,
+                       kTnF64, part, L.Np);
+    HIP_TRY(launch_tn(kTnF64, P->tnR.rt, a, P->stream));
+    if (ev) { HIP_TRY(hipEventRecord(ev[e], P->stream)); kinds[e++] = 0; }
+    HIP_TRY(launch_tn_sum_cast(kTnF64, part, P->tnR.nsplit, P->kp, L.Np, L.Np, P->ws + L.W64,
+                               L.Np, P->stream));
+    if (ev) { HIP_TRY(hipEventRecord(ev[e], P->stream)); kinds[e++] = 2; }
+    TnArgs b = tn_args(P->ws + L.C64T, L.Np, L.np, P->ws + L.W64, L.Np, P->kp, L.Np, P->tnX0,
+                       kTnF64, part, L.np);
+    HIP_TRY(launch_tn(kTnF64, P->tnX0.rt, b, P->stream));
+    if (ev) { HIP_TRY(hipEventRecord(ev[e], P->stream)); kinds[e++] = 1; }
+    HIP_TRY(launch_tn_update(P->tq, 1, update_args(P, P->tnX0, 2), P->stream));
+    if (ev) { HIP_TRY(hipEventRecord(ev[e], P->stream)); kinds[e++] = 2; }
+  } else {
+    HIP_TRY(launch_tn(P->tq, P->tnA.rt, pass_a_args(P), P->stream));
+    if (ev) { HIP_TRY(hipEventRecord(ev[e], P->stream)); kinds[e++] = 0; }
+    HIP_TRY(launch_tn_sum_cast(P->tq, part, P->tnA.nsplit, P->kp, L.Np, L.Np, P->ws + L.Wq, L.Np,
+                               P->stream));
+    if (ev) { HIP_TRY(hipEventRecord(ev[e], P->stream)); kinds[e++] = 2; }
+    HIP_TRY(launch_tn(P->tq, P->tnB.rt, pass_b_args(P), P->stream));
+    if (ev) { HIP_TRY(hipEventRecord(ev[e], P->stream)); kinds[e++] = 1; }
+    HIP_TRY(launch_tn_update(P->tq, P->tq == kTnF64, update_args(P, P->tnB, 0), P->stream));
+    if (ev) { HIP_TRY(hipEventRecord(ev[e], P->stream)); kinds[e++] = 2; }
+  }
+  ++P->since_start;
+  if (nev) *nev = e;
+  return APC_OK;
+}
+
+// Starts the (y, x_bar) iteration for the right-hand sides whose transformed
+// values c = R^{-T} b (RHS-major, stride N, zero past k) are given:
+// x_bar(0) = (1/m) C^T c in FP64, y(0) = 0.
+apc_status start_gemm(apc_plan_s* P, const double* c_rhs) {
+  const Layout& L = P->L;
+  HIP_TRY(launch_tn_pack(kTnF64, c_rhs, P->N, P->kp, P->N, 0, P->ws + L.c64p, L.Np, P->kp,
+                         P->stream));
+  HIP_TRY(launch_tn(kTnF64, P->tnX0.rt, x0_args(P), P->stream));
+  HIP_TRY(launch_tn_update(P->tq, 1, update_args(P, P->tnX0, 1), P->stream));
+  P->since_start = 0;
+  return APC_OK;
+}
+
+// R = B - A X (X: kp x np FP64, RHS-major) into R (RHS-major, stride N), k columns.
+apc_status gemm_residual(apc_plan_s* P, const double* X, double* R) {
+  const Layout& L = P->L;
+  HIP_TRY(launch_tn(kTnF64, P->tnR.rt, resid_args(P, X), P->stream));
+  HIP_TRY(launch_tn_resid(P->at<double>(L.tnpart), P->tnR.nsplit, P->kp, L.Np, P->N, P->k, P->B,
+                          P->ldb, R, P->N, P->stream));
+  return APC_OK;
+}
+
+// Chooses the launch shape of one contraction by timing the candidates on the
+// plan's operands (the partial buffer is scratch here).  Shapes are cached per
+// (type, rows, K, kp) for the life of the process, so repeated plans of one
+// shape launch identically and give identical results.
+apc_status tn_tune(apc_plan_s* P, int type, TnArgs base, TnChoice* out) {
+  struct Key {
+    int type;
+    int64_t rows, K;
+    int32_t kp;
+    bool operator<(const Key& o) const {
+      return std::tie(type, rows, K, kp) < std::tie(o.type, o.rows, o.K, o.kp);
+    }
+  };
+  const int64_t ncg = base.kp >= 128 ? base.kp / 128 : 1;
+  auto blocks = [&](int rt, int ns) { return (base.rows / (64 * rt)) * ncg * ns; };
+  const int splits[4] = {1, 2, 4, 8};
+  const char* fix_rt = std::getenv("APC_TN_RT");
+  const char* fix_ns = std::getenv("APC_TN_SPLIT");
+  const char* tune = std::getenv("APC_TN_TUNE");
+  if (fix_rt || fix_ns || (tune && std::atoi(tune) == 0)) {
+    // Fixed shape (not cached): 128 rows per workgroup, the smallest split
+    // with >= 512 workgroups, unless the environment names them.
+    TnChoice c;
+    c.rt = fix_rt ? std::atoi(fix_rt) : 2;
+    if (c.rt != 1 && c.rt != 2 && c.rt != 4) c.rt = 2;
+    if (type == kTnF64 && c.rt == 4) c.rt = 2;
+    if (base.rows % (64 * c.rt)) c.rt = 1;
+    c.nsplit = 8;
+    for (int ns : splits)
+      if (blocks(c.rt, ns) >= 512) { c.nsplit = ns; break; }
+    if (fix_ns) c.nsplit = std::max(1, std::min(kTnMaxSplit, std::atoi(fix_ns)));
+    *out = c;
+    return APC_OK;
+  }
+  static std::mutex mu;
+  static std::map<Key, TnChoice> cache;
+  const Key key{type, base.rows, base.K, base.kp};
+  {
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = cache.find(key);
+    if (it != cache.end()) {
+      *out = it->second;
+      return APC_OK;
+    }
+  }
+  std::vector<TnChoice> cand;
+  const int rts[3] = {1, 2, 4};
+  for (int rt : rts) {
+    if (type == kTnF64 && rt == 4) continue;
+    if (base.rows % (64 * rt)) continue;
+    for (int ns : splits) {
+      if (blocks(rt, ns) < 64 && !(rt == 1 && ns == 8)) continue;
+      if (static_cast<int64_t>(ns) * tn_step_elems(type) > base.K && ns > 1) continue;
+      TnChoice c;
+      c.rt = rt;
+      c.nsplit = ns;
+      cand.push_back(c);
+    }
+  }
+  if (cand.empty()) cand.push_back(TnChoice{1, 1, 0.f});
+  TnChoice best;
+  {
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    float best_ms = 0.f;
+    bool have = false;
+    for (const TnChoice& c : cand) {
+      TnArgs a = base;
+      a.nsplit = c.nsplit;
+      a.klen = round_up((a.K + c.nsplit - 1) / c.nsplit, tn_step_elems(type));
+      hipError_t err = launch_tn(type, c.rt, a, P->stream);  // warm-up
+      for (int r = 0; err == hipSuccess && r < 1; ++r) {
+        err = hipEventRecord(e0, P->stream);
+        for (int q = 0; err == hipSuccess && q < 3; ++q) err = launch_tn(type, c.rt, a, P->stream);
+        if (err == hipSuccess) err = hipEventRecord(e1, P->stream);
+      }
+      float ms = 0.f;
+      if (err == hipSuccess) err = hipEventSynchronize(e1);
+      if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
+      if (err != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        return fail(APC_EHIP, "tuning launch failed: %s", hipGetErrorString(err));
+      }
+      ms /= 3.f;
+      if (!have || ms < best_ms) {
+        best = c;
+        best_ms = ms;
+        have = true;
+      }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    best.us = best_ms * 1e3f;
+  }
+  std::lock_guard<std::mutex> lk(mu);
+  cache[key] = best;
+  *out = best;
+  return APC_OK;
+}
+
+// One update of eq. (2a)-(2b).  k = 1: for each group of blocks, pass A then
+// pass B (pass B of a block needs only that block's w, so a group's rows of C
+// are re-read while they are still in the Infinity Cache), then the average.
 // With ev non-null, an event is recorded after every launch and the launch
-// kinds (0 pass A, 1 pass B, 2 average) are appended to kinds.
-apc_status update_mfma(apc_plan_s* P, hipEvent_t* ev, int* kinds) {
-  const Layout& L = P->L;
-  int e = 0;
-  MfmaAArgs a{P->at<float>(L.C32), L.ldc, P->tk(0), P->tk(1), P->tk(2), L.ntiles_k,
-              P->at<float>(L.dv), P->state_ld(), L.ldc, P->kp, P->ksplit, P->ksplit_cols,
-              P->at<float>(L.wpart), P->N};
-  HIP_TRY(launch_passa_mfma(a, P->stream));
-  HIP_TRY(launch_wsum(P->at<float>(L.wpart), P->ksplit, P->kp, P->N, P->at<float>(L.wsum),
-                      P->N + 16, P->stream));
-  if (ev) { HIP_TRY(hipEventRecord(ev[e], P->stream)); kinds[e++] = 0; }
-  // Difference form: the state is x_bar (FP64) and d_i = x_bar - x_i (FP32);
-  // pass B writes e_i = x_i(t+1) - x_bar(t) into the x region.
-  float* ebuf = reinterpret_cast<float*>(P->x());
-  MfmaBArgs b{P->at<float>(L.C32), L.ldc, P->doff(), P->m, P->at<float>(L.wsum), P->N + 16,
-              P->kp, P->at<float>(L.dv), ebuf, P->state_ld(), L.ldc, P->gamma};
-  HIP_TRY(launch_passb_mfma(b, P->stream));
-  if (ev) { HIP_TRY(hipEventRecord(ev[e], P->stream)); kinds[e++] = 1; }
-  HIP_TRY(launch_combine_diff(ebuf, P->state_ld(), P->m, P->state_ld(), P->eta / P->m, P->xbar(),
-                              P->at<float>(L.dv), P->stream));
-  if (ev) { HIP_TRY(hipEventRecord(ev[e], P->stream)); kinds[e++] = 2; }
-  return APC_OK;
-}
-
-// One inner update of the mixed-precision mode (difference form, bf16 factor).
-apc_status update_bf16(apc_plan_s* P, hipEvent_t* ev, int* kinds) {
-  const Layout& L = P->L;
-  int e = 0;
-  MfmaAArgs16 a{P->at<__bf16>(L.C16), L.ldc, P->tk(0), P->tk(1), P->tk(2), L.ntiles_k,
-                P->at<float>(L.dv), P->state_ld(), L.ldc, P->kp, P->ksplit, P->ksplit_cols,
-                P->at<float>(L.wpart), P->N};
-  HIP_TRY(launch_passa_bf16(a, P->stream));
-  HIP_TRY(launch_wsum_bf16(P->at<float>(L.wpart), P->ksplit, P->kp, P->N, P->at<__bf16>(L.W16),
-                           L.ldw16, P->stream));
-  if (ev) { HIP_TRY(hipEventRecord(ev[e], P->stream)); kinds[e++] = 0; }
-  float* ebuf = reinterpret_cast<float*>(P->x());
-  MfmaBArgs16 b{P->at<__bf16>(L.C16), L.ldc, P->doff(), P->m, P->at<__bf16>(L.W16), L.ldw16,
-                P->kp, P->at<float>(L.dv), ebuf, P->state_ld(), L.ldc, P->gamma, 0};
-  HIP_TRY(launch_passb_bf16(b, P->stream));
-  if (ev) { HIP_TRY(hipEventRecord(ev[e], P->stream)); kinds[e++] = 1; }
-  HIP_TRY(launch_combine_diff(ebuf, P->state_ld(), P->m, P->state_ld(), P->eta / P->m, P->xbar(),
-                              P->at<float>(L.dv), P->stream));
-  if (ev) { HIP_TRY(hipEventRecord(ev[e], P->stream)); kinds[e++] = 2; }
-  return APC_OK;
-}
-
-// Starts the inner (bf16) solve of A x = R for the right-hand sides held, after
-// the inverse Cholesky factors were applied, in cw (RHS-major, stride N):
-// W = c, e_i = Q_i c_i (minimum-norm local solutions), x_bar = mean, d_i = x_bar - x_i.
-apc_status start_inner(apc_plan_s* P, const double* c_rhs) {
-  const Layout& L = P->L;
-  HIP_TRY(launch_to_bf16(c_rhs, P->N, P->kp, P->N, P->at<__bf16>(L.W16), L.ldw16, P->stream));
-  float* ebuf = reinterpret_cast<float*>(P->x());
-  MfmaBArgs16 b{P->at<__bf16>(L.C16), L.ldc, P->doff(), P->m, P->at<__bf16>(L.W16), L.ldw16,
-                P->kp, P->at<float>(L.dv), ebuf, P->state_ld(), L.ldc, 0.0, 1};
-  HIP_TRY(launch_passb_bf16(b, P->stream));
-  HIP_TRY(launch_fill_u32(reinterpret_cast<unsigned*>(P->xbar()), 2 * P->state_ld(), 0u, P->stream));
-  HIP_TRY(launch_combine_diff(ebuf, P->state_ld(), P->m, P->state_ld(), 1.0 / P->m, P->xbar(),
-                              P->at<float>(L.dv), P->stream));
-  return APC_OK;
-}
-
-apc_status update(apc_plan_s* P, hipEvent_t* ev, int* kinds) {
-  if (P->bf16) return update_bf16(P, ev, kinds);
-  if (P->mfma) return update_mfma(P, ev, kinds);
+// kinds (0 pass A, 1 pass B, 2 average/epilogue) are appended to kinds; *nev
+// receives the number recorded (at most launches_per_update).
+apc_status update(apc_plan_s* P, hipEvent_t* ev, int* kinds, int* nev) {
+  if (P->gemm) return update_gemm(P, ev, kinds, nev);
   const int g = P->group_blocks > 0 ? P->group_blocks : P->m;
   int e = 0;
   for (int i0 = 0; i0 < P->m; i0 += g) {
     const int i1 = std::min(P->m, i0 + g);
-    for (int col = 0; col < P->k; ++col) ST_TRY(pass_a(P, i0, i1, col));
+    ST_TRY(pass_a(P, i0, i1, 0));
     if (ev) { HIP_TRY(hipEventRecord(ev[e], P->stream)); kinds[e++] = 0; }
-    for (int col = 0; col < P->k; ++col) ST_TRY(pass_b(P, i0, i1, col));
+    ST_TRY(pass_b(P, i0, i1, 0));
     if (ev) { HIP_TRY(hipEventRecord(ev[e], P->stream)); kinds[e++] = 1; }
   }
   ST_TRY(average(P, P->eta / P->m, 1.0 - P->eta));
   if (ev) { HIP_TRY(hipEventRecord(ev[e], P->stream)); kinds[e++] = 2; }
+  if (nev) *nev = e;
   return APC_OK;
 }
 
 int launches_per_update(const apc_plan_s* P) {
-  if (P->mfma || P->bf16) return 3;
+  if (P->gemm) return 4;
   const int g = P->group_blocks > 0 ? P->group_blocks : P->m;
   return 2 * ((P->m + g - 1) / g) + 1;
 }
@@ -508,7 +693,7 @@ apc_status x_matvec(apc_plan_s* P, const double* v, double* out) {
   for (int i0 = 0; i0 < P->m; i0 += g) {
     const int i1 = std::min(P->m, i0 + g);
     const int32_t t0 = P->tile_start[i0], nt = P->tile_start[i1] - t0;
-    if (P->prec == APC_F32) {  // FP32 factor (the BF16 mode estimates on the FP64 factor)
+    if (P->prec == APC_F32 && !P->gemm) {  // the k = 1 FP32 factor; else the FP64 one
       RowdotArgs<float, double> a{P->at<float>(L.C32), L.ldc, P->ta(0), P->ta(1), P->ta(2), nt, 0,
                                   v, nullptr, 0, nullptr, 0, u, 0, 1, L.ldc, P->xcd_remap,
                                   P->passa_rows, t0};
@@ -646,15 +831,13 @@ apc_status lanczos(apc_plan_s* P, double* lo_out, double* hi_out, int* steps_out
 }
 
 // ||B - A X||_F^2 into out_dev (X in RHS-major state layout, or null for ||B||^2).
-// k = 1: row-dot kernel; k > 1: the FP64 matrix-core residual into R, then a
-// fixed-order sum of squares.
+// k = 1: row-dot kernel; k-RHS path: the FP64 matrix-core residual into R,
+// then a fixed-order sum of squares.
 apc_status residual_norm2(apc_plan_s* P, const double* x, double* out_dev) {
   int32_t parts = 0;
   double* partial = P->at<double>(P->L.partial);
-  if (x && P->k > 1) {
-    ResidArgs r{P->A, P->lda, P->B, P->ldb, x, P->L.ldc, P->N, P->n, P->k,
-                P->at<double>(P->L.Rb), P->N};
-    HIP_TRY(launch_resid_f64(r, P->stream));
+  if (x && P->gemm) {
+    ST_TRY(gemm_residual(P, x, P->at<double>(P->L.Rb)));
     HIP_TRY(launch_sumsq(P->at<double>(P->L.Rb), static_cast<int64_t>(P->k) * P->N,
                          P->at<double>(P->L.ssq), P->stream));
     HIP_TRY(launch_sum_partials(P->at<double>(P->L.ssq), sumsq_parts(), out_dev, P->stream));
@@ -676,8 +859,9 @@ apc_status current_solution(apc_plan_s* P, const double** out) {
     *out = P->xbar();
     return APC_OK;
   }
-  double* cw = P->at<double>(P->L.cw);
-  const int64_t cnt = P->state_ld();
+  // c64p (kp x Np >= kp x np) is free outside the start of an inner solve.
+  double* cw = P->at<double>(P->L.c64p);
+  const int64_t cnt = static_cast<int64_t>(P->kp) * P->L.np;
   HIP_TRY(launch_copy_strided(P->xbar(), 1, cw, 1, cnt, 1, P->stream));
   HIP_TRY(launch_axpy(cnt, 1.0, P->at<double>(P->L.Xs), cw, P->stream));
   *out = cw;
@@ -711,14 +895,6 @@ apc_status setup_impl(apc_plan_s* P, const Tiles& T) {
   HIP_TRY(hipMemcpyAsync(P->at<int32_t>(L.tiles_g), T.g.data(), T.g.size() * 4, hipMemcpyHostToDevice, st));
   HIP_TRY(hipMemcpyAsync(P->at<int32_t>(L.tiles_t), T.t.data(), T.t.size() * 4, hipMemcpyHostToDevice, st));
   HIP_TRY(hipMemcpyAsync(P->doff(), P->off.data(), (m + 1) * 8, hipMemcpyHostToDevice, st));
-  if (P->mfma || P->bf16) {
-    std::vector<int32_t> tk;
-    tk.insert(tk.end(), T.k_row0.begin(), T.k_row0.end());
-    tk.insert(tk.end(), T.k_nrows.begin(), T.k_nrows.end());
-    tk.insert(tk.end(), T.k_blk.begin(), T.k_blk.end());
-    HIP_TRY(hipMemcpyAsync(P->at<int32_t>(L.tiles_k), tk.data(), tk.size() * 4,
-                           hipMemcpyHostToDevice, st));
-  }
   HIP_TRY(hipMemcpyAsync(P->at<int64_t>(L.goff), T.goff.data(), m * 8, hipMemcpyHostToDevice, st));
   HIP_TRY(launch_fill_u32(P->at<unsigned>(L.flags), 4, 0u, st));
 
@@ -760,26 +936,44 @@ apc_status setup_impl(apc_plan_s* P, const Tiles& T) {
                 flags[0] - 1, rank_tol);
   P->bnorm = std::sqrt(scal[1]);
 
-  // Alg. 1 initialisation: x_i(0) = Q_i c_i (minimum-norm local solutions),
-  // x_bar(0) = (1/m) sum_i x_i(0).  The mixed-precision mode starts its first
-  // inner solve (right-hand sides B, committed solution X = 0) on the bf16 factor.
-  if (P->bf16) {
-    HIP_TRY(launch_cast_bf16(Ca, P->at<__bf16>(L.C16), N * ldc, st));
-    HIP_TRY(launch_fill_u32(P->at<unsigned>(L.Xs), 2 * P->state_ld(), 0u, st));
-    ST_TRY(start_inner(P, ca));
+  if (P->gemm) {
+    // Factor copies for the matrix cores (C and C^T in the iteration's
+    // precision, C^T in FP64), the padded FP64 copy of A, zeroed operands.
+    const int64_t Np = L.Np, np = L.np;
+    HIP_TRY(launch_tn_pack(P->tq, Ca, ldc, N, n, 0, P->ws + L.Cq, np, Np, st));
+    HIP_TRY(launch_tn_pack(P->tq, Ca, ldc, N, n, 1, P->ws + L.CqT, Np, np, st));
+    if (P->tq != kTnF64) {
+      HIP_TRY(launch_tn_pack(kTnF64, Ca, ldc, N, n, 1, P->ws + L.C64T, Np, np, st));
+      HIP_TRY(launch_tn_pack(kTnF64, Ca, ldc, N, n, 0, P->ws + L.C64p, np, Np, st));
+    }
+    HIP_TRY(launch_tn_pack(kTnF64, P->A, P->lda, N, n, 0, P->ws + L.Apad, np, Np, st));
+    const int64_t sq = P->tq == kTnF64 ? 8 : P->tq == kTnF32 ? 4 : 2;
+    HIP_TRY(launch_fill_u32(P->at<unsigned>(L.yq), P->kp * np * sq / 4, 0u, st));
+    HIP_TRY(launch_fill_u32(P->at<unsigned>(L.Wq), P->kp * Np * sq / 4, 0u, st));
+    HIP_TRY(launch_fill_u32(P->at<unsigned>(L.c64p), 2 * P->kp * Np, 0u, st));
+    HIP_TRY(launch_fill_u32(P->at<unsigned>(L.xbar), 2 * P->kp * np, 0u, st));
+    HIP_TRY(launch_fill_u32(P->at<unsigned>(L.Rb), 2 * P->kp * N, 0u, st));
+    if (P->bf16) {
+      HIP_TRY(launch_fill_u32(P->at<unsigned>(L.cw), 2 * P->kp * N, 0u, st));
+      HIP_TRY(launch_fill_u32(P->at<unsigned>(L.Xs), 2 * P->kp * np, 0u, st));
+    }
+    ST_TRY(tn_tune(P, P->tq, pass_a_args(P), &P->tnA));
+    ST_TRY(tn_tune(P, P->tq, pass_b_args(P), &P->tnB));
+    ST_TRY(tn_tune(P, kTnF64, x0_args(P), &P->tnX0));
+    ST_TRY(tn_tune(P, kTnF64, resid_args(P, P->xbar()), &P->tnR));
   } else {
-  if (P->kp > P->k)
-    HIP_TRY(launch_fill_u32(reinterpret_cast<unsigned*>(P->x()), 2 * m * P->state_ld(), 0u, st));
-  for (int col = 0; col < P->k; ++col) {
-    ExpandArgs<double> e{Ca, ldc, P->doff(), m,
-                         static_cast<int32_t>((ldc + expand_slab(8) - 1) / expand_slab(8)), N,
-                         ca + static_cast<int64_t>(col) * N, 1, 0,
-                         P->x() + static_cast<int64_t>(col) * ldc, P->state_ld(), 1.0, 0.0, 0};
-    HIP_TRY(launch_expand_f64(e, st));
+    // Alg. 1 initialisation: x_i(0) = Q_i c_i (minimum-norm local solutions),
+    // x_bar(0) = (1/m) sum_i x_i(0).
+    for (int col = 0; col < P->k; ++col) {
+      ExpandArgs<double> e{Ca, ldc, P->doff(), m,
+                           static_cast<int32_t>((ldc + expand_slab(8) - 1) / expand_slab(8)), N,
+                           ca + static_cast<int64_t>(col) * N, 1, 0,
+                           P->x() + static_cast<int64_t>(col) * ldc, P->state_ld(), 1.0, 0.0, 0};
+      HIP_TRY(launch_expand_f64(e, st));
+    }
+    ST_TRY(average(P, 1.0 / m, 0.0));
+    if (P->prec == APC_F32) HIP_TRY(launch_cast_f32(Ca, P->at<float>(L.C32), N * ldc, st));
   }
-  ST_TRY(average(P, 1.0 / m, 0.0));
-  }
-  if (P->prec == APC_F32) HIP_TRY(launch_cast_f32(Ca, P->at<float>(L.C32), N * ldc, st));
 
   // Parameters: caller's, or Theorem 1's optimum from the estimated spectrum.
   if (std::isnan(P->gamma) || std::isnan(P->eta)) {
@@ -789,6 +983,10 @@ apc_status setup_impl(apc_plan_s* P, const Tiles& T) {
     P->mu_max = hi;
     optimum(lo, hi, &P->gamma, &P->eta, &P->rho);
   }
+  // The k-RHS start needs gamma (its first operand is y(1) = gamma x_bar(0)).
+  // The mixed-precision mode's first inner solve has right-hand sides B and
+  // committed solution X = 0.
+  if (P->gemm) ST_TRY(start_gemm(P, ca));
   HIP_TRY(hipStreamSynchronize(st));
   return APC_OK;
 }
@@ -869,19 +1067,14 @@ apc_status apc_setup(apc_plan* out, const double* A, int64_t lda, const double* 
     P->tile_start.push_back(P->tile_start.back() +
                             static_cast<int32_t>((off[i + 1] - off[i] + passa_rows - 1) / passa_rows));
   P->group_blocks = group_blocks >= 0 ? group_blocks : 0;
-  P->mfma = precision == APC_F32 && k > 1;
-  if (const char* e = std::getenv("APC_KRHS_MFMA")) P->mfma = P->mfma && std::atoi(e) != 0;
+  P->gemm = uses_gemm(k, precision);
   P->bf16 = precision == APC_BF16_IR;
-  if (P->mfma || P->bf16) {
-    // Split K (the n columns) so that pass A runs ~2048 workgroups.
-    const int64_t ncb = (P->kp + 63) / 64;
-    const int64_t base = std::max<int64_t>(1, static_cast<int64_t>(L.ntiles_k) * ncb);
-    const int64_t unit = P->bf16 ? 128 : 64;   // column chunk of the pass-A kernel
-    int64_t want = std::min<int64_t>({(2048 + base - 1) / base, kMaxSplitK, (L.ldc + unit - 1) / unit});
-    want = std::max<int64_t>(want, 1);
-    P->ksplit_cols = round_up((L.ldc + want - 1) / want, unit);
-    P->ksplit = static_cast<int32_t>((L.ldc + P->ksplit_cols - 1) / P->ksplit_cols);
-  }
+  P->tq = precision == APC_F64 ? kTnF64 : precision == APC_F32 ? kTnF32 : kTnBF16;
+  // FP32 k-RHS: an FP64 anchor update every kAnchorEvery updates; the bf16 inner solver
+  // is corrected by the outer refinement instead (0 = never).
+  P->anchor_every = (P->gemm && precision == APC_F32) ? kAnchorEvery : 0;
+  if (const char* e = std::getenv("APC_ANCHOR_EVERY"))
+    if (P->gemm && precision != APC_F64) P->anchor_every = std::max(0, std::atoi(e));
   {
     // Column splits of pass A: about 4096 workgroups (16 per CU, measured best
     // for streaming at the 16384 x 8192 shape), each split at least one
@@ -907,7 +1100,7 @@ apc_status apc_setup(apc_plan* out, const double* A, int64_t lda, const double* 
 apc_status apc_iterate(apc_plan p, int32_t T) {
   if (!p) return fail(APC_EINVAL, "plan is NULL");
   if (T < 0) return fail(APC_EINVAL, "T must be >= 0");
-  for (int32_t t = 0; t < T; ++t) ST_TRY(update(p, nullptr, nullptr));
+  for (int32_t t = 0; t < T; ++t) ST_TRY(update(p, nullptr, nullptr, nullptr));
   p->iters += T;
   return APC_OK;
 }
@@ -924,20 +1117,23 @@ apc_status apc_iterate_timed(apc_plan p, int32_t T, float* ms_total, float* ms_p
     p->events.push_back(e);
   }
   std::vector<int> kinds(need, -1);
+  size_t used = 1;
   if (T > 0) HIP_TRY(hipEventRecord(p->events[0], p->stream));
-  for (int32_t t = 0; t < T; ++t)
-    ST_TRY(update(p, p->events.data() + 1 + static_cast<size_t>(t) * per,
-                  kinds.data() + 1 + static_cast<size_t>(t) * per));
+  for (int32_t t = 0; t < T; ++t) {
+    int nev = 0;
+    ST_TRY(update(p, p->events.data() + used, kinds.data() + used, &nev));
+    used += static_cast<size_t>(nev);
+  }
   p->iters += T;
   float sums[3] = {0.f, 0.f, 0.f}, tot = 0.f;
   if (T > 0) {
-    HIP_TRY(hipEventSynchronize(p->events[need - 1]));
-    for (size_t e = 1; e < need; ++e) {
+    HIP_TRY(hipEventSynchronize(p->events[used - 1]));
+    for (size_t e = 1; e < used; ++e) {
       float ms = 0.f;
       HIP_TRY(hipEventElapsedTime(&ms, p->events[e - 1], p->events[e]));
       sums[kinds[e]] += ms;
     }
-    HIP_TRY(hipEventElapsedTime(&tot, p->events[0], p->events[need - 1]));
+    HIP_TRY(hipEventElapsedTime(&tot, p->events[0], p->events[used - 1]));
   }
   if (ms_total) *ms_total = tot;
   if (ms_pass_a) *ms_pass_a = sums[0];
@@ -981,11 +1177,11 @@ apc_status solve_refined(apc_plan_s* p, double rtol, int32_t max_iters, int32_t*
     const int32_t T = std::min(inner, max_iters - done);
     if (T > 0) ST_TRY(apc_iterate(p, T));
     done += T;
-    // Commit the correction and restart the inner state from zero.
-    HIP_TRY(launch_axpy(p->state_ld(), 1.0, p->xbar(), p->at<double>(L.Xs), p->stream));
-    HIP_TRY(launch_fill_u32(reinterpret_cast<unsigned*>(p->xbar()), 2 * p->state_ld(), 0u, p->stream));
-    ResidArgs r{p->A, p->lda, p->B, p->ldb, p->at<double>(L.Xs), L.ldc, p->N, p->n, p->k, Rb, p->N};
-    HIP_TRY(launch_resid_f64(r, p->stream));
+    // Commit the correction and form R = B - A X in FP64.
+    const int64_t cnt = static_cast<int64_t>(p->kp) * L.np;
+    HIP_TRY(launch_axpy(cnt, 1.0, p->xbar(), p->at<double>(L.Xs), p->stream));
+    HIP_TRY(launch_fill_u32(reinterpret_cast<unsigned*>(p->xbar()), 2 * cnt, 0u, p->stream));
+    ST_TRY(gemm_residual(p, p->at<double>(L.Xs), Rb));
     HIP_TRY(launch_sumsq(Rb, static_cast<int64_t>(p->k) * p->N, p->at<double>(L.ssq), p->stream));
     HIP_TRY(launch_sum_partials(p->at<double>(L.ssq), sumsq_parts(), dst, p->stream));
     double r2 = 0.0;
@@ -1009,7 +1205,7 @@ apc_status solve_refined(apc_plan_s* p, double rtol, int32_t max_iters, int32_t*
                               p->N, cw, p->N, p->kp, p->stream));
     HIP_TRY(launch_linv_apply(p->doff(), p->at<int64_t>(L.goff), p->m, p->at<double>(L.Linv2), cw,
                               p->N, Rb, p->N, p->kp, p->stream));
-    ST_TRY(start_inner(p, Rb));
+    ST_TRY(start_gemm(p, Rb));
   }
   *done_out = done;
   *rr_out = rr;
@@ -1055,28 +1251,39 @@ apc_status apc_get_xbar(apc_plan p, double* Xbar, int64_t ldx) {
   if (!p || !Xbar || ldx < (p->k == 1 ? 1 : p->k)) return fail(APC_EINVAL, "bad argument");
   const double* x = nullptr;
   ST_TRY(current_solution(p, &x));
-  if (p->k == 1)
+  if (!p->gemm)
     HIP_TRY(launch_copy_strided(x, 1, Xbar, ldx, p->n, 1, p->stream));
   else
-    HIP_TRY(launch_copy_t(x, p->L.ldc, Xbar, ldx, p->n, p->k, p->stream));
+    HIP_TRY(launch_copy_t(x, p->L.np, Xbar, ldx, p->n, p->k, p->stream));
   return APC_OK;
 }
 
 apc_status apc_get_local(apc_plan p, double* X, int64_t ldx) {
   if (!p || !X) return fail(APC_EINVAL, "bad argument");
   if (p->bf16) return fail(APC_EUNSUPPORTED, "local solutions are not kept in the mixed-precision mode");
-  if (p->k == 1) {
+  if (!p->gemm) {
     if (ldx < p->n) return fail(APC_EINVAL, "ldx < n");
     HIP_TRY(launch_copy_strided(p->x(), p->L.ldc, X, ldx, p->m, p->n, p->stream));
-  } else if (p->mfma) {
-    if (ldx < p->k) return fail(APC_EINVAL, "ldx < k");
-    HIP_TRY(launch_local_from_diff(p->xbar(), p->at<float>(p->L.dv), p->L.ldc, p->state_ld(), p->m,
-                                   p->n, p->k, X, ldx, p->stream));
-  } else {
-    if (ldx < p->k) return fail(APC_EINVAL, "ldx < k");
+    return APC_OK;
+  }
+  if (ldx < p->k) return fail(APC_EINVAL, "ldx < k");
+  // x_i(t) = x_i(0) + P_i y(t) = y + Q_i (c_i - Q_i^T y), per right-hand side,
+  // in FP64 on the FP64 factor.
+  const Layout& L = p->L;
+  double* w = p->at<double>(L.w);
+  double* r = p->at<double>(L.cb);
+  double* Y = p->at<double>(L.Y);
+  for (int col = 0; col < p->k; ++col) {
+    const double* y = p->at<double>(L.ys) + static_cast<int64_t>(col) * L.np;
+    ST_TRY(rowdot64(p, y, nullptr, 0, w));
+    HIP_TRY(launch_copy_strided(p->at<double>(L.ca) + static_cast<int64_t>(col) * p->N, 1, r, 1,
+                                p->N, 1, p->stream));
+    HIP_TRY(launch_axpy(p->N, -1.0, w, r, p->stream));
+    HIP_TRY(launch_copy_strided(y, 0, Y, L.ldc, p->m, L.ldc, p->stream));
+    ST_TRY(expand_blocks(p, r, Y, 1.0, 1.0));
     for (int i = 0; i < p->m; ++i)
-      HIP_TRY(launch_copy_t(p->x() + i * p->state_ld(), p->L.ldc, X + i * p->n * ldx, ldx, p->n,
-                            p->k, p->stream));
+      HIP_TRY(launch_copy_t(Y + static_cast<int64_t>(i) * L.ldc, 0, X + i * p->n * ldx + col, ldx,
+                            p->n, 1, p->stream));
   }
   return APC_OK;
 }
@@ -1143,6 +1350,29 @@ apc_status apc_get_info(apc_plan p, int32_t* lanczos_steps, int32_t* rows_per_ti
   if (rows_per_tile) *rows_per_tile = p->passa_rows;
   if (column_splits) *column_splits = p->nsplit;
   if (block_groups) *block_groups = (launches_per_update(p) - 1) / 2;
+  return APC_OK;
+}
+
+apc_status apc_get_launch(apc_plan p, int32_t which, int32_t* rows_per_wg, int32_t* splits,
+                          float* tuned_us) {
+  if (!p) return fail(APC_EINVAL, "plan is NULL");
+  if (!p->gemm) return fail(APC_EUNSUPPORTED, "launch shapes are reported for the k-RHS path only");
+  if (which < 0 || which > 3) return fail(APC_EINVAL, "which must be 0..3");
+  const TnChoice& c = which == 0 ? p->tnA : which == 1 ? p->tnB : which == 2 ? p->tnX0 : p->tnR;
+  if (rows_per_wg) *rows_per_wg = 64 * c.rt;
+  if (splits) *splits = c.nsplit;
+  if (tuned_us) *tuned_us = c.us;
+  return APC_OK;
+}
+
+apc_status apc_set_anchor(apc_plan p, int32_t every) {
+  if (!p) return fail(APC_EINVAL, "plan is NULL");
+  if (every < 0) return fail(APC_EINVAL, "every must be >= 0");
+  if (!p->gemm || p->prec == APC_F64)
+    return fail(APC_EUNSUPPORTED, "anchor updates exist for FP32 / bf16 plans with the k-RHS form");
+  if (p->since_start != 0)
+    return fail(APC_EINVAL, "set the anchor spacing before the first update after setup");
+  p->anchor_every = every;
   return APC_OK;
 }
 

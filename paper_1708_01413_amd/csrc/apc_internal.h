@@ -105,121 +105,86 @@ hipError_t launch_pass_b_f32(const PassBArgs<float>& a, hipStream_t s);
 hipError_t launch_expand_f64(const ExpandArgs<double>& a, hipStream_t s);
 hipError_t launch_expand_f32(const ExpandArgs<float>& a, hipStream_t s);
 
-// k right-hand sides, FP32 projections on matrix cores.
-// Pass A: wpart[(split*kp + c)*N + r] = sum_{j in split} C[r][j] d_blk[c][j] over
-// 128-row tiles (tile lists aligned to block starts), kp a multiple of 16,
-// split_cols a multiple of 64.
-struct MfmaAArgs {
-  const float* C;
-  int64_t ldc;
-  const int32_t* tile_row0;
-  const int32_t* tile_nrows;
-  const int32_t* tile_blk;
-  int32_t ntiles;
-  const float* d;             // d[blk*ldd_blk + c*ldd_col + j]
-  int64_t ldd_blk;
-  int64_t ldd_col;
-  int32_t kp;
-  int32_t nsplit;
-  int64_t split_cols;
-  float* wpart;
-  int64_t N;
-};
-// Pass B in difference form: e_i[c][j] = -(1 - gamma) d_i[c][j] - gamma sum_{r in
-// block i} C[r][j] W[c][r] (e_i = x_i(t+1) - x_bar(t)), with W[c*ldw + r]
-// (ldw >= N + 16).
-struct MfmaBArgs {
-  const float* C;
-  int64_t ldc;
-  const int64_t* off;
-  int32_t m;
-  const float* W;
-  int64_t ldw;
-  int32_t kp;
-  const float* d;             // d[blk*ld_blk + c*ld_col + j]
-  float* e;                   // same layout
-  int64_t ld_blk;
-  int64_t ld_col;
-  double gamma;
-};
-// BF16 factor variants (inner solver of the mixed-precision mode): C16 is the
-// bf16 factor, d and e stay FP32, W16 is bf16 with ldw >= N; split_cols is a
-// multiple of 128.
-struct MfmaAArgs16 {
-  const __bf16* C;
-  int64_t ldc;
-  const int32_t* tile_row0;
-  const int32_t* tile_nrows;
-  const int32_t* tile_blk;
-  int32_t ntiles;
-  const float* d;
-  int64_t ldd_blk;
-  int64_t ldd_col;
-  int32_t kp;
-  int32_t nsplit;
-  int64_t split_cols;
-  float* wpart;
-  int64_t N;
-};
-struct MfmaBArgs16 {
-  const __bf16* C;
-  int64_t ldc;
-  const int64_t* off;
-  int32_t m;
-  const __bf16* W;
-  int64_t ldw;
-  int32_t kp;
-  const float* d;
-  float* e;
-  int64_t ld_blk;
-  int64_t ld_col;
-  double gamma;
-  int32_t expand_only;        // 1: e_i = Q_i W_i
-};
-hipError_t launch_passa_bf16(const MfmaAArgs16& a, hipStream_t s);
-hipError_t launch_wsum_bf16(const float* wpart, int32_t nsplit, int32_t kp, int64_t N, __bf16* W,
-                            int64_t ldw, hipStream_t s);
-hipError_t launch_passb_bf16(const MfmaBArgs16& a, hipStream_t s);
-constexpr int kMfmaTileRows = 128;
+// ---------------------------------------------------------------------------
+// k right-hand sides: streaming contractions on the matrix cores (apc_gemm.hip)
+// ---------------------------------------------------------------------------
 
-// FP64 residual of the refinement: R[c*ldr + r] = B[r*ldb + c] - (A X)[r][c],
-// X[c*ldx + j] (right-hand-side major), r < N, c < k.
-struct ResidArgs {
-  const double* A;
-  int64_t lda;
-  const double* B;
-  int64_t ldb;
-  const double* X;
-  int64_t ldx;
-  int64_t N;
-  int64_t n;
-  int32_t k;
-  double* R;
-  int64_t ldr;
+enum { kTnF64 = 0, kTnF32 = 1, kTnBF16 = 2 };
+constexpr int kTnPad = 256;       // rows and K of every operand, zero-padded to a multiple of this
+constexpr int kTnMaxSplit = 8;    // split-K factors the partial buffer holds
+
+// part[(s*kp + c)*ldp + r] = sum_{j in [s*klen, min((s+1)*klen, K))} M[r*ldm + j] V[c*ldv + j]
+// for r < rows and c < kp, accumulated in FP32 (f32, bf16 operands) or FP64.
+// rows is a multiple of 64*rt, K and klen multiples of the step (256 bytes of
+// a row), kp is 16, 32, 64 or a multiple of 128, M and V rows are 16-byte
+// aligned and zero wherever they extend past the data.
+struct TnArgs {
+  const void* M;
+  int64_t ldm;
+  int64_t rows;
+  const void* V;
+  int64_t ldv;
+  int32_t kp;
+  int64_t K;
+  int32_t nsplit;
+  int64_t klen;
+  void* part;
+  int64_t ldp;
 };
-hipError_t launch_resid_f64(const ResidArgs& a, hipStream_t s);
+hipError_t launch_tn(int type, int rt, const TnArgs& a, hipStream_t s);
+int tn_step_elems(int type);
+// out[c*ldo + r] = TQ(sum over the nsplit partials in split order), r < rows, c < kp.
+hipError_t launch_tn_sum_cast(int type, const void* part, int32_t nsplit, int32_t kp, int64_t ldp,
+                              int64_t rows, void* out, int64_t ldo, hipStream_t s);
+// One update of APC in the (y, x_bar) form, over c < kp, j < n (state FP64 with
+// stride ldx, z = the summed partials of C^T W):
+//   y1 = (1 - gamma) y + gamma x_bar
+//   u  = z / m (+ u_ref when anchored)                       (= X y1)
+//   x_bar <- eta (x0 + y1 - u) + (1 - eta) x_bar,  y <- y1
+//   yq = TQ((1 - gamma) y1 + gamma x_bar - y_ref)   (the next pass-A operand)
+// mode 0: an update (y_ref, u_ref may be null: 0); mode 2: an anchor update,
+// whose z was formed in FP64 from y1 itself: u_ref <- z / m, y_ref = y1;
+// mode 1: the start, x0 = x_bar = z / m, y = 0 (y_ref = u_ref = 0),
+// yq = TQ(gamma x0).
+struct TnUpdateArgs {
+  const void* part;
+  int32_t nsplit;
+  int32_t kp;
+  int64_t ldp;
+  int64_t n;
+  double* x0;
+  double* y;
+  double* xb;
+  int64_t ldx;
+  void* yq;
+  int64_t ldq;
+  double gamma;
+  double eta;
+  double inv_m;
+  int32_t mode;
+  double* yref;
+  double* uref;
+};
+// y_ref[e] = (1 - gamma) y[e] + gamma x_bar[e], e < count.
+hipError_t launch_tn_anchor_vec(const double* y, const double* xb, int64_t count, double gamma,
+                                double* yref, hipStream_t s);
+hipError_t launch_tn_update(int type, int part_f64, const TnUpdateArgs& a, hipStream_t s);
+// R[c*ldr + r] = B[r*ldb + c] - sum of the FP64 partials, r < N, c < k.
+hipError_t launch_tn_resid(const double* part, int32_t nsplit, int32_t kp, int64_t ldp, int64_t N,
+                           int32_t k, const double* B, int64_t ldb, double* R, int64_t ldr,
+                           hipStream_t s);
+// dst (drows x ldd, element type of `type`) = src, or src^T when transpose,
+// zero outside the FP64 source (srows x scols, stride lds).
+hipError_t launch_tn_pack(int type, const double* src, int64_t lds, int64_t srows, int64_t scols,
+                          int32_t transpose, void* dst, int64_t ldd, int64_t drows, hipStream_t s);
+
 // Per block: out[col*ldo + r0 + r] = sum_{q<=r} Linv_i[r][q] in[col*ldi + r0 + q], col < kc.
 hipError_t launch_linv_apply(const int64_t* off, const int64_t* goff, int32_t m, const double* Linv,
                              const double* in, int64_t ldi, double* out, int64_t ldo, int32_t kc,
                              hipStream_t s);
-hipError_t launch_to_bf16(const double* src, int64_t lds, int32_t kc, int64_t N, __bf16* W,
-                          int64_t ldw, hipStream_t s);
 hipError_t launch_axpy(int64_t count, double alpha, const double* x, double* y, hipStream_t s);
 hipError_t launch_sumsq(const double* src, int64_t count, double* partial, hipStream_t s);
 int sumsq_parts();
-hipError_t launch_cast_bf16(const double* src, __bf16* dst, int64_t count, hipStream_t s);
-hipError_t launch_passa_mfma(const MfmaAArgs& a, hipStream_t s);
-hipError_t launch_wsum(const float* wpart, int32_t nsplit, int32_t kp, int64_t N, float* W,
-                       int64_t ldw, hipStream_t s);
-hipError_t launch_passb_mfma(const MfmaBArgs& a, hipStream_t s);
-// delta = scale * sum_i e_i (fixed order), xbar += delta, d_i = delta - e_i, over
-// n entries of each block's state (block stride ld).
-hipError_t launch_combine_diff(const float* e, int64_t ld, int32_t m, int64_t n, double scale,
-                               double* xbar, float* d, hipStream_t s);
-// X[(i*n + j)*ldx + c] = xbar[c*ld_col + j] - d[i*ld_blk + c*ld_col + j].
-hipError_t launch_local_from_diff(const double* xbar, const float* d, int64_t ld_col,
-                                  int64_t ld_blk, int32_t m, int64_t n, int32_t k, double* X,
-                                  int64_t ldx, hipStream_t s);
 
 // Eq. (2b) and the next differences: xbar[j] = alpha * sum_{i<m} x[i*ldx + j]
 // + beta * xbar[j] for j < n in a fixed order (wave w sums i = w, w+4, ...;

@@ -213,521 +213,7 @@ __global__ __launch_bounds__(kThreads) void k_pass_b(PassBArgs<TQ> a) {
   }
 }
 
-// ------------------------------------------------------------------ k right-hand sides (FP32, matrix cores)
-
-// With k right-hand sides both passes are GEMMs (W_i = Q_i^T D_i and
-// Y_i = Q_i W_i) and run on v_mfma_f32_16x16x4f32.  Lane layout of that
-// instruction (wave64): A operand lane l holds A[l % 16][l / 16], B operand
-// B[l / 16][l % 16]; the 4 results of lane l are D[4 (l / 16) + q][l % 16].
-// The K index of one instruction can be any permutation shared by A and B:
-// pass A lets lane group s = l / 16 cover 16 consecutive columns, so its A
-// fragments are 16-byte loads straight from rows of C.
-typedef float f32x4 __attribute__((ext_vector_type(4)));
-
-__device__ inline f32x4 mfma16x16x4(float a, float b, f32x4 c) {
-  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
-}
-
-constexpr int KA_ROWS = 128;  // rows of C per pass-A workgroup (4 waves x 2 x 16)
-constexpr int KA_J = 64;      // columns of C per chunk
-constexpr int KB_J = 128;     // columns of C per pass-B workgroup (4 waves x 2 x 16)
-constexpr int KB_R = 16;      // rows of C per pass-B chunk
-constexpr int K_COLS = 64;    // right-hand sides per workgroup (4 x 16)
-
-// wpart[(split * kp + c) * N + r] = sum_{j in split} C[r][j] d_blk[c][j].
-__global__ __launch_bounds__(256) void k_passa_mfma(MfmaAArgs a) {
-  const int ncb = (a.kp + K_COLS - 1) / K_COLS;
-  int q = blockIdx.x;
-  const int split = q % a.nsplit;
-  q /= a.nsplit;
-  const int cb = q % ncb;
-  const int tile = q / ncb;
-  const int row0 = a.tile_row0[tile];
-  const int nrows = a.tile_nrows[tile];
-  const int blk = a.tile_blk[tile];
-  const int nct = min(K_COLS, a.kp - cb * K_COLS) / 16;
-  const int64_t c0 = static_cast<int64_t>(split) * a.split_cols;
-  const int64_t c1 = min(a.ldc, c0 + a.split_cols);
-  const int lane = threadIdx.x & 63;
-  const int wv = threadIdx.x >> 6;
-  const int li = lane & 15, lg = lane >> 4;
-  const float* dblk = a.d + static_cast<int64_t>(blk) * a.ldd_blk;
-
-  __shared__ float dl[K_COLS][KA_J + 1];
-  f32x4 acc[2][4];
-#pragma unroll
-  for (int st = 0; st < 2; ++st)
-#pragma unroll
-    for (int ct = 0; ct < 4; ++ct) acc[st][ct] = f32x4{0.f, 0.f, 0.f, 0.f};
-
-  for (int64_t jb = c0; jb < c1; jb += KA_J) {
-    // d chunk (64 right-hand sides x 64 columns) into LDS, shared by the 4 waves.
-#pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      const int idx = threadIdx.x + 256 * e;
-      const int cc = idx >> 4;
-      const int jj = (idx & 15) * 4;
-      const int c = cb * K_COLS + cc;
-      float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-      if (c < a.kp) v = *reinterpret_cast<const float4*>(dblk + c * a.ldd_col + jb + jj);
-      dl[cc][jj + 0] = v.x;
-      dl[cc][jj + 1] = v.y;
-      dl[cc][jj + 2] = v.z;
-      dl[cc][jj + 3] = v.w;
-    }
-    // A fragments: lane (li, lg) of sub-tile st holds C[row][jb + 16 lg + t], t < 16.
-    float af[2][16];
-#pragma unroll
-    for (int st = 0; st < 2; ++st) {
-      const int rr = wv * 32 + st * 16 + li;
-      if (rr < nrows) {
-        const float* src = a.C + static_cast<int64_t>(row0 + rr) * a.ldc + jb + 16 * lg;
-#pragma unroll
-        for (int v4 = 0; v4 < 4; ++v4) {
-          const float4 v = *reinterpret_cast<const float4*>(src + 4 * v4);
-          af[st][4 * v4 + 0] = v.x;
-          af[st][4 * v4 + 1] = v.y;
-          af[st][4 * v4 + 2] = v.z;
-          af[st][4 * v4 + 3] = v.w;
-        }
-      } else {
-#pragma unroll
-        for (int t = 0; t < 16; ++t) af[st][t] = 0.f;
-      }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int t = 0; t < 16; ++t) {
-#pragma unroll
-      for (int ct = 0; ct < 4; ++ct) {
-        if (ct < nct) {
-          const float bv = dl[ct * 16 + li][16 * lg + t];
-#pragma unroll
-          for (int st = 0; st < 2; ++st) acc[st][ct] = mfma16x16x4(af[st][t], bv, acc[st][ct]);
-        }
-      }
-    }
-    __syncthreads();
-  }
-#pragma unroll
-  for (int st = 0; st < 2; ++st)
-#pragma unroll
-    for (int ct = 0; ct < 4; ++ct) {
-      if (ct >= nct) continue;
-      const int c = cb * K_COLS + ct * 16 + li;
-#pragma unroll
-      for (int qq = 0; qq < 4; ++qq) {
-        const int rr = wv * 32 + st * 16 + 4 * lg + qq;
-        if (rr < nrows)
-          a.wpart[(static_cast<int64_t>(split) * a.kp + c) * a.N + row0 + rr] = acc[st][ct][qq];
-      }
-    }
-}
-
-// W[c * ldw + r] = sum over the nsplit partials, in split order.
-__global__ void k_wsum(const float* wpart, int32_t nsplit, int32_t kp, int64_t N, float* W,
-                       int64_t ldw) {
-  const int64_t total = static_cast<int64_t>(kp) * N;
-  for (int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; e < total;
-       e += static_cast<int64_t>(gridDim.x) * blockDim.x) {
-    const int64_t c = e / N;
-    const int64_t r = e - c * N;
-    float s = 0.f;
-    for (int sp = 0; sp < nsplit; ++sp) s += wpart[(sp * kp + c) * N + r];
-    W[c * ldw + r] = s;
-  }
-}
-
-// Y_i = Q_i W_i on a 128-column x 64-RHS tile of block i (K = the block's rows),
-// then x_i[c][j] += gamma (x_bar[c][j] - x_i[c][j] - Y[j][c]) in FP64.
-__global__ __launch_bounds__(256) void k_passb_mfma(MfmaBArgs a) {
-  const int ncb = (a.kp + K_COLS - 1) / K_COLS;
-  const int njt = static_cast<int>((a.ldc + KB_J - 1) / KB_J);
-  int q = blockIdx.x;
-  const int cb = q % ncb;
-  q /= ncb;
-  const int jt = q % njt;
-  const int blk = q / njt;
-  const int64_t r0 = a.off[blk];
-  const int64_t r1 = a.off[blk + 1];
-  const int nct = min(K_COLS, a.kp - cb * K_COLS) / 16;
-  const int lane = threadIdx.x & 63;
-  const int wv = threadIdx.x >> 6;
-  const int li = lane & 15, lg = lane >> 4;
-  const int64_t j0 = static_cast<int64_t>(jt) * KB_J;
-
-  __shared__ float cl[KB_R][KB_J + 4];
-  f32x4 acc[2][4];
-#pragma unroll
-  for (int st = 0; st < 2; ++st)
-#pragma unroll
-    for (int ct = 0; ct < 4; ++ct) acc[st][ct] = f32x4{0.f, 0.f, 0.f, 0.f};
-
-  for (int64_t rb = r0; rb < r1; rb += KB_R) {
-    // C chunk (16 rows x 128 columns) into LDS with coalesced 16-byte loads.
-#pragma unroll
-    for (int e = 0; e < 2; ++e) {
-      const int idx = threadIdx.x + 256 * e;
-      const int rr = idx >> 5;
-      const int jj = (idx & 31) * 4;
-      float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-      if (rb + rr < r1 && j0 + jj < a.ldc)
-        v = *reinterpret_cast<const float4*>(a.C + (rb + rr) * a.ldc + j0 + jj);
-      cl[rr][jj + 0] = v.x;
-      cl[rr][jj + 1] = v.y;
-      cl[rr][jj + 2] = v.z;
-      cl[rr][jj + 3] = v.w;
-    }
-    // B fragments: lane (li, lg) holds W[rb + 4 lg + t][c], t < 4 (rows past the
-    // block read as 0; W has 16 spare columns per row, so the loads stay inside).
-    float bw[4][4];
-#pragma unroll
-    for (int ct = 0; ct < 4; ++ct) {
-      if (ct < nct) {
-        const int c = cb * K_COLS + ct * 16 + li;
-        const int64_t r = rb + 4 * lg;
-        const float4 v = *reinterpret_cast<const float4*>(a.W + c * a.ldw + r);
-        bw[ct][0] = r + 0 < r1 ? v.x : 0.f;
-        bw[ct][1] = r + 1 < r1 ? v.y : 0.f;
-        bw[ct][2] = r + 2 < r1 ? v.z : 0.f;
-        bw[ct][3] = r + 3 < r1 ? v.w : 0.f;
-      }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int t = 0; t < 4; ++t) {
-#pragma unroll
-      for (int st = 0; st < 2; ++st) {
-        const float av = cl[4 * lg + t][wv * 32 + st * 16 + li];
-#pragma unroll
-        for (int ct = 0; ct < 4; ++ct)
-          if (ct < nct) acc[st][ct] = mfma16x16x4(av, bw[ct][t], acc[st][ct]);
-      }
-    }
-    __syncthreads();
-  }
-  // e_i = x_i(t+1) - x_bar(t) = -(1 - gamma) d_i - gamma Q_i W_i  (d_i = x_bar - x_i).
-  const float* db = a.d + static_cast<int64_t>(blk) * a.ld_blk;
-  float* eb = a.e + static_cast<int64_t>(blk) * a.ld_blk;
-  const float omg = static_cast<float>(1.0 - a.gamma), g = static_cast<float>(a.gamma);
-#pragma unroll
-  for (int st = 0; st < 2; ++st)
-#pragma unroll
-    for (int ct = 0; ct < 4; ++ct) {
-      if (ct >= nct) continue;
-      const int c = cb * K_COLS + ct * 16 + li;
-      const int64_t j = j0 + wv * 32 + st * 16 + 4 * lg;
-      if (j >= a.ldc) continue;  // ldc is a multiple of 4: the 4 rows below are all in range
-      const float4 dv = *reinterpret_cast<const float4*>(db + c * a.ld_col + j);
-      float4 ev;
-      ev.x = -omg * dv.x - g * acc[st][ct][0];
-      ev.y = -omg * dv.y - g * acc[st][ct][1];
-      ev.z = -omg * dv.z - g * acc[st][ct][2];
-      ev.w = -omg * dv.w - g * acc[st][ct][3];
-      *reinterpret_cast<float4*>(eb + c * a.ld_col + j) = ev;
-    }
-}
-
-// Difference-form average over a 64-column stripe of every block's state:
-// delta = (eta/m) sum_i e_i (fixed order as k_combine), x_bar += delta in
-// FP64, d_i = delta - e_i (the next differences x_bar - x_i, rounded to FP32).
-__global__ __launch_bounds__(256) void k_combine_diff(const float* e, int64_t ld, int32_t m,
-                                                      int64_t n, double scale, double* xbar,
-                                                      float* d) {
-  __shared__ double part[4][64];
-  __shared__ double dl[64];
-  const int lane = threadIdx.x & 63;
-  const int wv = threadIdx.x >> 6;
-  const int64_t j = static_cast<int64_t>(blockIdx.x) * 64 + lane;
-  double s = 0.0;
-  if (j < n)
-    for (int i = wv; i < m; i += 4) s += static_cast<double>(e[static_cast<int64_t>(i) * ld + j]);
-  part[wv][lane] = s;
-  __syncthreads();
-  if (wv == 0 && j < n) {
-    const double delta = scale * ((part[0][lane] + part[1][lane]) + (part[2][lane] + part[3][lane]));
-    xbar[j] += delta;
-    dl[lane] = delta;
-  }
-  __syncthreads();
-  if (j < n)
-    for (int i = wv; i < m; i += 4)
-      d[static_cast<int64_t>(i) * ld + j] =
-          static_cast<float>(dl[lane] - static_cast<double>(e[static_cast<int64_t>(i) * ld + j]));
-}
-
-// X[(i*n + j)*ldx + c] = x_bar[c][j] - d_i[c][j]: local solutions from the
-// difference-form state.
-__global__ void k_local_from_diff(const double* xbar, const float* d, int64_t ld_col,
-                                  int64_t ld_blk, int32_t m, int64_t n, int32_t k, double* X,
-                                  int64_t ldx) {
-  const int64_t total = static_cast<int64_t>(m) * n * k;
-  for (int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; e < total;
-       e += static_cast<int64_t>(gridDim.x) * blockDim.x) {
-    const int c = static_cast<int>(e % k);
-    const int64_t ij = e / k;
-    const int64_t j = ij % n;
-    const int64_t i = ij / n;
-    X[ij * ldx + c] = xbar[c * ld_col + j] - static_cast<double>(d[i * ld_blk + c * ld_col + j]);
-  }
-}
-
-// ------------------------------------------------------------------ BF16 projections (inner solver)
-
-// v_mfma_f32_16x16x32_bf16: lane l of A holds 8 bf16 of row l % 16, lane l of
-// B 8 bf16 of column l % 16; lane group l / 16 and element e name the same K
-// index in both, and the results follow the 16x16 layout above.  Lane group
-// s is given 8 consecutive columns (pass A: a 16-byte load from a row of C)
-// or 8 consecutive rows (pass B: a 16-byte read of a transposed LDS tile).
-typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
-
-__device__ inline f32x4 mfma16x16x32bf16(bf16x8 a, bf16x8 b, f32x4 c) {
-  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
-}
-
-constexpr int KA16_J = 128;  // columns of C per pass-A chunk
-constexpr int KB16_R = 32;   // rows of C per pass-B chunk
-
-// wpart[(split * kp + c) * N + r] = sum_{j in split} C16[r][j] bf16(d_blk[c][j]).
-__global__ __launch_bounds__(256) void k_passa_bf16(MfmaAArgs16 a) {
-  const int ncb = (a.kp + K_COLS - 1) / K_COLS;
-  int q = blockIdx.x;
-  const int split = q % a.nsplit;
-  q /= a.nsplit;
-  const int cb = q % ncb;
-  const int tile = q / ncb;
-  const int row0 = a.tile_row0[tile];
-  const int nrows = a.tile_nrows[tile];
-  const int blk = a.tile_blk[tile];
-  const int nct = min(K_COLS, a.kp - cb * K_COLS) / 16;
-  const int64_t c0 = static_cast<int64_t>(split) * a.split_cols;
-  const int64_t c1 = min(a.ldc, c0 + a.split_cols);
-  const int lane = threadIdx.x & 63;
-  const int wv = threadIdx.x >> 6;
-  const int li = lane & 15, lg = lane >> 4;
-  const float* dblk = a.d + static_cast<int64_t>(blk) * a.ldd_blk;
-
-  __shared__ __attribute__((aligned(16))) __bf16 dl[K_COLS][KA16_J + 8];
-  f32x4 acc[2][4];
-#pragma unroll
-  for (int st = 0; st < 2; ++st)
-#pragma unroll
-    for (int ct = 0; ct < 4; ++ct) acc[st][ct] = f32x4{0.f, 0.f, 0.f, 0.f};
-
-  for (int64_t jb = c0; jb < c1; jb += KA16_J) {
-    // d chunk (64 right-hand sides x 128 columns, FP32 -> bf16) into LDS.
-#pragma unroll
-    for (int e = 0; e < 8; ++e) {
-      const int idx = threadIdx.x + 256 * e;
-      const int cc = idx >> 5;
-      const int jj = (idx & 31) * 4;
-      const int c = cb * K_COLS + cc;
-      float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-      if (c < a.kp && jb + jj < c1) v = *reinterpret_cast<const float4*>(dblk + c * a.ldd_col + jb + jj);
-      dl[cc][jj + 0] = static_cast<__bf16>(v.x);
-      dl[cc][jj + 1] = static_cast<__bf16>(v.y);
-      dl[cc][jj + 2] = static_cast<__bf16>(v.z);
-      dl[cc][jj + 3] = static_cast<__bf16>(v.w);
-    }
-    // A fragments: sub-tile st, step t: 8 bf16 at C16[row][jb + 32 t + 8 lg].
-    bf16x8 af[2][4];
-#pragma unroll
-    for (int st = 0; st < 2; ++st) {
-      const int rr = wv * 32 + st * 16 + li;
-#pragma unroll
-      for (int t = 0; t < 4; ++t) {
-        const int64_t jj = jb + 32 * t + 8 * lg;
-        if (rr < nrows && jj < c1)
-          af[st][t] = *reinterpret_cast<const bf16x8*>(a.C + static_cast<int64_t>(row0 + rr) * a.ldc + jj);
-        else
-          af[st][t] = bf16x8{};
-      }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int t = 0; t < 4; ++t) {
-#pragma unroll
-      for (int ct = 0; ct < 4; ++ct) {
-        if (ct < nct) {
-          const bf16x8 bv = *reinterpret_cast<const bf16x8*>(&dl[ct * 16 + li][32 * t + 8 * lg]);
-#pragma unroll
-          for (int st = 0; st < 2; ++st) acc[st][ct] = mfma16x16x32bf16(af[st][t], bv, acc[st][ct]);
-        }
-      }
-    }
-    __syncthreads();
-  }
-#pragma unroll
-  for (int st = 0; st < 2; ++st)
-#pragma unroll
-    for (int ct = 0; ct < 4; ++ct) {
-      if (ct >= nct) continue;
-      const int c = cb * K_COLS + ct * 16 + li;
-#pragma unroll
-      for (int qq = 0; qq < 4; ++qq) {
-        const int rr = wv * 32 + st * 16 + 4 * lg + qq;
-        if (rr < nrows)
-          a.wpart[(static_cast<int64_t>(split) * a.kp + c) * a.N + row0 + rr] = acc[st][ct][qq];
-      }
-    }
-}
-
-// W16[c * ldw + r] = bf16(sum of the nsplit partials, in split order).
-__global__ void k_wsum_bf16(const float* wpart, int32_t nsplit, int32_t kp, int64_t N, __bf16* W,
-                            int64_t ldw) {
-  const int64_t total = static_cast<int64_t>(kp) * N;
-  for (int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; e < total;
-       e += static_cast<int64_t>(gridDim.x) * blockDim.x) {
-    const int64_t c = e / N;
-    const int64_t r = e - c * N;
-    float s = 0.f;
-    for (int sp = 0; sp < nsplit; ++sp) s += wpart[(sp * kp + c) * N + r];
-    W[c * ldw + r] = static_cast<__bf16>(s);
-  }
-}
-
-// Y = Q_i W_i on a 128-column x 64-RHS tile of block i, K = the block's rows in
-// chunks of 32; the chunk of C is staged transposed (cl[j][r]) so a lane's
-// 8 consecutive rows are one 16-byte read.  Epilogue: e_i = -(1 - gamma) d_i
-// - gamma Y, or e_i = Y when expand_only (the inner solver's initial x_i).
-__global__ __launch_bounds__(256) void k_passb_bf16(MfmaBArgs16 a) {
-  const int ncb = (a.kp + K_COLS - 1) / K_COLS;
-  const int njt = static_cast<int>((a.ldc + KB_J - 1) / KB_J);
-  int q = blockIdx.x;
-  const int cb = q % ncb;
-  q /= ncb;
-  const int jt = q % njt;
-  const int blk = q / njt;
-  const int64_t r0 = a.off[blk];
-  const int64_t r1 = a.off[blk + 1];
-  const int nct = min(K_COLS, a.kp - cb * K_COLS) / 16;
-  const int lane = threadIdx.x & 63;
-  const int wv = threadIdx.x >> 6;
-  const int li = lane & 15, lg = lane >> 4;
-  const int64_t j0 = static_cast<int64_t>(jt) * KB_J;
-
-  __shared__ __attribute__((aligned(16))) __bf16 cl[KB_J][KB16_R + 8];
-  f32x4 acc[2][4];
-#pragma unroll
-  for (int st = 0; st < 2; ++st)
-#pragma unroll
-    for (int ct = 0; ct < 4; ++ct) acc[st][ct] = f32x4{0.f, 0.f, 0.f, 0.f};
-
-  for (int64_t rb = r0; rb < r1; rb += KB16_R) {
-    // C chunk (32 rows x 128 columns): 16-byte loads, stored transposed.
-#pragma unroll
-    for (int e = 0; e < 2; ++e) {
-      const int idx = threadIdx.x + 256 * e;
-      const int rr = idx >> 4;
-      const int jj = (idx & 15) * 8;
-      bf16x8 v{};
-      if (rb + rr < r1 && j0 + jj < a.ldc)
-        v = *reinterpret_cast<const bf16x8*>(a.C + (rb + rr) * a.ldc + j0 + jj);
-#pragma unroll
-      for (int u = 0; u < 8; ++u) cl[jj + u][rr] = v[u];
-    }
-    // B fragments: W16[c][rb + 8 lg + u]; rows past the block are not read.
-    bf16x8 bw[4];
-#pragma unroll
-    for (int ct = 0; ct < 4; ++ct) {
-      bw[ct] = bf16x8{};
-      if (ct < nct) {
-        const int c = cb * K_COLS + ct * 16 + li;
-        const int64_t r = rb + 8 * lg;   // block starts need not be 8-aligned: 2-byte loads
-        const __bf16* src = a.W + c * a.ldw + r;
-#pragma unroll
-        for (int u = 0; u < 8; ++u) bw[ct][u] = (r + u < r1) ? src[u] : static_cast<__bf16>(0.f);
-      }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int st = 0; st < 2; ++st) {
-      const bf16x8 av = *reinterpret_cast<const bf16x8*>(&cl[wv * 32 + st * 16 + li][8 * lg]);
-#pragma unroll
-      for (int ct = 0; ct < 4; ++ct)
-        if (ct < nct) acc[st][ct] = mfma16x16x32bf16(av, bw[ct], acc[st][ct]);
-    }
-    __syncthreads();
-  }
-  const float* db = a.d + static_cast<int64_t>(blk) * a.ld_blk;
-  float* eb = a.e + static_cast<int64_t>(blk) * a.ld_blk;
-  const float omg = static_cast<float>(1.0 - a.gamma), g = static_cast<float>(a.gamma);
-#pragma unroll
-  for (int st = 0; st < 2; ++st)
-#pragma unroll
-    for (int ct = 0; ct < 4; ++ct) {
-      if (ct >= nct) continue;
-      const int c = cb * K_COLS + ct * 16 + li;
-      const int64_t j = j0 + wv * 32 + st * 16 + 4 * lg;
-      if (j >= a.ldc) continue;
-      float4 ev;
-      if (a.expand_only) {
-        ev = make_float4(acc[st][ct][0], acc[st][ct][1], acc[st][ct][2], acc[st][ct][3]);
-      } else {
-        const float4 dv = *reinterpret_cast<const float4*>(db + c * a.ld_col + j);
-        ev.x = -omg * dv.x - g * acc[st][ct][0];
-        ev.y = -omg * dv.y - g * acc[st][ct][1];
-        ev.z = -omg * dv.z - g * acc[st][ct][2];
-        ev.w = -omg * dv.w - g * acc[st][ct][3];
-      }
-      *reinterpret_cast<float4*>(eb + c * a.ld_col + j) = ev;
-    }
-}
-
 // ------------------------------------------------------------------ FP64 refinement
-
-typedef double f64x4 __attribute__((ext_vector_type(4)));
-
-// R[c * ldr + r] = B[r * ldb + c] - sum_j A[r * lda + j] X[c * ldx + j] for r < N,
-// c < k, on v_mfma_f64_16x16x4f64: operands as the 16x16 FP32 form (one double
-// per lane, A[l % 16][l / 16], B[l / 16][l % 16]), but result q of lane l is
-// D[l / 16 + 4 q][l % 16].  A workgroup owns 64 rows x 64 right-hand sides;
-// lane group s covers 4 consecutive columns per 4 instructions.
-__global__ __launch_bounds__(256) void k_resid_f64(ResidArgs a) {
-  const int ncb = (a.k + 63) / 64;
-  const int cb = blockIdx.x % ncb;
-  const int64_t rt = blockIdx.x / ncb;
-  const int lane = threadIdx.x & 63;
-  const int wv = threadIdx.x >> 6;
-  const int li = lane & 15, lg = lane >> 4;
-  const int64_t row = rt * 64 + wv * 16 + li;
-  f64x4 acc[4];
-#pragma unroll
-  for (int ct = 0; ct < 4; ++ct) acc[ct] = f64x4{0.0, 0.0, 0.0, 0.0};
-  const double* arow = a.A + row * a.lda;
-  for (int64_t j0 = 0; j0 < a.n; j0 += 16) {
-    double av[4], bv[4][4];
-#pragma unroll
-    for (int t = 0; t < 4; ++t) {
-      const int64_t jj = j0 + 4 * lg + t;
-      av[t] = (row < a.N && jj < a.n) ? arow[jj] : 0.0;
-    }
-#pragma unroll
-    for (int ct = 0; ct < 4; ++ct) {
-      const int c = cb * 64 + ct * 16 + li;
-#pragma unroll
-      for (int t = 0; t < 4; ++t) {
-        const int64_t jj = j0 + 4 * lg + t;
-        bv[ct][t] = (c < a.k && jj < a.n) ? a.X[c * a.ldx + jj] : 0.0;
-      }
-    }
-#pragma unroll
-    for (int t = 0; t < 4; ++t)
-#pragma unroll
-      for (int ct = 0; ct < 4; ++ct)
-        acc[ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[t], bv[ct][t], acc[ct], 0, 0, 0);
-  }
-#pragma unroll
-  for (int ct = 0; ct < 4; ++ct) {
-    const int c = cb * 64 + ct * 16 + li;
-    if (c >= a.k) continue;
-#pragma unroll
-    for (int qq = 0; qq < 4; ++qq) {
-      const int64_t r = rt * 64 + wv * 16 + lg + 4 * qq;
-      if (r < a.N) a.R[c * a.ldr + r] = a.B[r * a.ldb + c] - acc[ct][qq];
-    }
-  }
-}
 
 // Per block: out[col * ldo + r0 + r] = sum_{q <= r} Linv_i[r][q] in[col * ldi + r0 + q].
 __global__ __launch_bounds__(256) void k_linv_apply(const int64_t* off, const int64_t* goff,
@@ -747,17 +233,6 @@ __global__ __launch_bounds__(256) void k_linv_apply(const int64_t* off, const in
   }
 }
 
-// W16[c * ldw + r] = bf16(src[c * lds + r]) for c < kc, r < N.
-__global__ void k_to_bf16(const double* src, int64_t lds, int32_t kc, int64_t N, __bf16* W,
-                          int64_t ldw) {
-  const int64_t total = static_cast<int64_t>(kc) * N;
-  for (int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; e < total;
-       e += static_cast<int64_t>(gridDim.x) * blockDim.x) {
-    const int64_t c = e / N;
-    const int64_t r = e - c * N;
-    W[c * ldw + r] = static_cast<__bf16>(static_cast<float>(src[c * lds + r]));
-  }
-}
 
 // y[e] = alpha * x[e] + y[e].
 __global__ void k_axpy(int64_t count, double alpha, const double* x, double* y) {
@@ -1051,11 +526,6 @@ __global__ __launch_bounds__(256) void k_trmm(const double* In, double* Out, int
   }
 }
 
-__global__ void k_cast_bf16(const double* src, __bf16* dst, int64_t count) {
-  for (int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; e < count;
-       e += static_cast<int64_t>(gridDim.x) * blockDim.x)
-    dst[e] = static_cast<__bf16>(static_cast<float>(src[e]));
-}
 
 __global__ void k_cast_f32(const double* src, float* dst, int64_t count) {
   for (int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; e < count;
@@ -1246,93 +716,10 @@ static hipError_t expand_impl(const ExpandArgs<TQ>& a, hipStream_t s) {
 hipError_t launch_expand_f64(const ExpandArgs<double>& a, hipStream_t s) { return expand_impl(a, s); }
 hipError_t launch_expand_f32(const ExpandArgs<float>& a, hipStream_t s) { return expand_impl(a, s); }
 
-hipError_t launch_passa_mfma(const MfmaAArgs& a, hipStream_t s) {
-  const int ncb = (a.kp + K_COLS - 1) / K_COLS;
-  const unsigned grid = static_cast<unsigned>(a.ntiles) * ncb * a.nsplit;
-  if (grid == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_passa_mfma, dim3(grid), dim3(256), 0, s, a);
-  return hipGetLastError();
-}
-
-hipError_t launch_wsum(const float* wpart, int32_t nsplit, int32_t kp, int64_t N, float* W,
-                       int64_t ldw, hipStream_t s) {
-  unsigned g = grid_for(static_cast<int64_t>(kp) * N, 256);
-  if (g > 8192) g = 8192;
-  hipLaunchKernelGGL(k_wsum, dim3(g), dim3(256), 0, s, wpart, nsplit, kp, N, W, ldw);
-  return hipGetLastError();
-}
-
-hipError_t launch_passb_mfma(const MfmaBArgs& a, hipStream_t s) {
-  const int ncb = (a.kp + K_COLS - 1) / K_COLS;
-  const int njt = static_cast<int>((a.ldc + KB_J - 1) / KB_J);
-  const unsigned grid = static_cast<unsigned>(a.m) * njt * ncb;
-  if (grid == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_passb_mfma, dim3(grid), dim3(256), 0, s, a);
-  return hipGetLastError();
-}
-
-hipError_t launch_combine_diff(const float* e, int64_t ld, int32_t m, int64_t n, double scale,
-                               double* xbar, float* d, hipStream_t s) {
-  hipLaunchKernelGGL(k_combine_diff, dim3(grid_for(n, 64)), dim3(256), 0, s, e, ld, m, n, scale,
-                     xbar, d);
-  return hipGetLastError();
-}
-
-hipError_t launch_local_from_diff(const double* xbar, const float* d, int64_t ld_col,
-                                  int64_t ld_blk, int32_t m, int64_t n, int32_t k, double* X,
-                                  int64_t ldx, hipStream_t s) {
-  unsigned g = grid_for(static_cast<int64_t>(m) * n * k, 256);
-  if (g > 8192) g = 8192;
-  hipLaunchKernelGGL(k_local_from_diff, dim3(g), dim3(256), 0, s, xbar, d, ld_col, ld_blk, m, n,
-                     k, X, ldx);
-  return hipGetLastError();
-}
-
-hipError_t launch_passa_bf16(const MfmaAArgs16& a, hipStream_t s) {
-  const int ncb = (a.kp + K_COLS - 1) / K_COLS;
-  const unsigned grid = static_cast<unsigned>(a.ntiles) * ncb * a.nsplit;
-  if (grid == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_passa_bf16, dim3(grid), dim3(256), 0, s, a);
-  return hipGetLastError();
-}
-
-hipError_t launch_wsum_bf16(const float* wpart, int32_t nsplit, int32_t kp, int64_t N, __bf16* W,
-                            int64_t ldw, hipStream_t s) {
-  unsigned g = grid_for(static_cast<int64_t>(kp) * N, 256);
-  if (g > 8192) g = 8192;
-  hipLaunchKernelGGL(k_wsum_bf16, dim3(g), dim3(256), 0, s, wpart, nsplit, kp, N, W, ldw);
-  return hipGetLastError();
-}
-
-hipError_t launch_passb_bf16(const MfmaBArgs16& a, hipStream_t s) {
-  const int ncb = (a.kp + K_COLS - 1) / K_COLS;
-  const int njt = static_cast<int>((a.ldc + KB_J - 1) / KB_J);
-  const unsigned grid = static_cast<unsigned>(a.m) * njt * ncb;
-  if (grid == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_passb_bf16, dim3(grid), dim3(256), 0, s, a);
-  return hipGetLastError();
-}
-
-hipError_t launch_resid_f64(const ResidArgs& a, hipStream_t s) {
-  const int64_t ncb = (a.k + 63) / 64;
-  const unsigned grid = static_cast<unsigned>(((a.N + 63) / 64) * ncb);
-  if (grid == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_resid_f64, dim3(grid), dim3(256), 0, s, a);
-  return hipGetLastError();
-}
-
 hipError_t launch_linv_apply(const int64_t* off, const int64_t* goff, int32_t m, const double* Linv,
                              const double* in, int64_t ldi, double* out, int64_t ldo, int32_t kc,
                              hipStream_t s) {
   hipLaunchKernelGGL(k_linv_apply, dim3(m), dim3(256), 0, s, off, goff, Linv, in, ldi, out, ldo, kc);
-  return hipGetLastError();
-}
-
-hipError_t launch_to_bf16(const double* src, int64_t lds, int32_t kc, int64_t N, __bf16* W,
-                          int64_t ldw, hipStream_t s) {
-  unsigned g = grid_for(static_cast<int64_t>(kc) * N, 256);
-  if (g > 8192) g = 8192;
-  hipLaunchKernelGGL(k_to_bf16, dim3(g), dim3(256), 0, s, src, lds, kc, N, W, ldw);
   return hipGetLastError();
 }
 
@@ -1379,12 +766,6 @@ hipError_t launch_trmm(const double* In, double* Out, int64_t ldc, const int64_t
                        const double* Linv, hipStream_t s) {
   if (ntiles <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_trmm, dim3(ntiles), dim3(256), 0, s, In, Out, ldc, off, tiles, goff, Linv);
-  return hipGetLastError();
-}
-
-hipError_t launch_cast_bf16(const double* src, __bf16* dst, int64_t count, hipStream_t s) {
-  const unsigned g = grid_for(count, 256) > 4096 ? 4096 : grid_for(count, 256);
-  hipLaunchKernelGGL(k_cast_bf16, dim3(g), dim3(256), 0, s, src, dst, count);
   return hipGetLastError();
 }
 

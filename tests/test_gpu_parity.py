@@ -424,15 +424,16 @@ MULTI = [
     (300, 200, 7, (20, 60), 3, 31),        # k padded to 16; n not a multiple of 64
     (1000, 800, 9, (40, 160), 20, 32),      # k padded to 32; 128-row tiles + tails
     (2048, 2048, 16, (64, 192), 64, 33),    # full 64-wide tile, square, shifted
+    (512, 512, 4, (96, 160), 130, 35),      # k > 128: two 128-wide column groups
 ]
 
 
-@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("prec", ["f64", "f32", "f32-plain"])
 @pytest.mark.parametrize("N,n,m,rng_sizes,k,seed", MULTI)
 def test_multi_rhs_trajectory(prec, N, n, m, rng_sizes, k, seed):
-    """k right-hand sides (batched updates: matrix cores in FP32 mode, one pass per column
-    in FP64 mode) against the oracle run on the same k columns.  Bar: max over t of
-    ||X_gpu(t) - X_oracle(t)||_F / ||X*||_F."""
+    """k right-hand sides, the (y, x_bar) form on the matrix cores (FP64; FP32 with the
+    default FP64 anchors; "f32-plain": every update in FP32), against the literal oracle
+    run on the same k columns.  Bar: max over t of ||X_gpu(t) - X_oracle(t)||_F / ||X*||_F."""
     apc = _apc()
     torch = _torch()
     sizes = synth.renormalised_sizes(np.random.default_rng(seed), m, N, *rng_sizes)
@@ -449,7 +450,9 @@ def test_multi_rhs_trajectory(prec, N, n, m, rng_sizes, k, seed):
         x, xbar = O.apc_step(Qt, x, xbar, g, e)
         ref.append(xbar.copy())
     A, b = upload(S)
-    plan = apc.Plan(A, b, S.off, prec, gamma=g, eta=e)
+    base = prec.split("-")[0]
+    plan = apc.Plan(A, b, S.off, base, gamma=g, eta=e,
+                    anchor_every=0 if prec.endswith("plain") else None)
     snaps = [plan.xbar()]
     for _ in range(T):
         plan.iterate(1)
@@ -458,13 +461,76 @@ def test_multi_rhs_trajectory(prec, N, n, m, rng_sizes, k, seed):
     got = torch.stack(snaps).cpu().numpy()
     dev = max(np.linalg.norm(got[t] - ref[t]) for t in range(T + 1)) / np.linalg.norm(S.xstar)
     err = np.linalg.norm(got[-1] - S.xstar) / np.linalg.norm(S.xstar)
-    say(f"max dev {dev:.3e} (tol {TOL[prec]}), err(T) {err:.2e}")
-    assert dev <= TOL[prec]
+    say(f"max dev {dev:.3e} (tol {TOL[base]}), err(T) {err:.2e}, shapes {plan.launch_shapes()}")
+    assert dev <= TOL[base]
     # the local solutions keep A_i x_i = b_i for every column
     X = plan.local().cpu().numpy()
     for i, (Ai, bi) in enumerate(zip(O.blocks(S.A, S.off), O.blocks(S.B, S.off))):
         r = np.linalg.norm(Ai @ X[i] - bi) / np.linalg.norm(bi)
-        assert r < (1e-10 if prec == "f64" else 1e-4), (i, r)
+        assert r < (1e-10 if base == "f64" else 1e-4), (i, r)
+
+
+def test_fp32_anchor_updates_remove_the_fp32_floor():
+    """Plain FP32 products on y level off near eps_32 / mu_min; with FP64 anchor updates
+    the FP32 products act on y - y_ref only and the error keeps falling at the FP64 rate."""
+    apc = _apc()
+    torch = _torch()
+    S = synth.shifted_square(2048, 16, k=16, shift=1.5, seed=36)
+    A, b = upload(S)
+    xs = torch.from_numpy(S.xstar).to(A.device)
+    errs = {}
+    for every in (0, 16):
+        plan = apc.Plan(A, b, S.off, "f32", anchor_every=every)
+        plan.iterate(150)
+        errs[every] = float(torch.linalg.norm(plan.xbar() - xs) / torch.linalg.norm(xs))
+        plan.close()
+    ref = apc.Plan(A, b, S.off, "f64")
+    ref.iterate(150)
+    e64 = float(torch.linalg.norm(ref.xbar() - xs) / torch.linalg.norm(xs))
+    say(f"case: anchors; err(150) plain FP32 {errs[0]:.2e}, anchored {errs[16]:.2e}, FP64 {e64:.2e}")
+    assert errs[16] <= max(10 * e64, 1e-11)
+    assert errs[16] < 1e-2 * errs[0]
+
+
+def test_anchor_argument_errors():
+    apc = _apc()
+    S = synth.shifted_square(256, 4, k=2, seed=37)
+    A, b = upload(S)
+    p64 = apc.Plan(A, b, S.off, "f64")
+    with pytest.raises(apc.ApcError) as ex:
+        apc.apc_set_anchor(p64.handle, 4)
+    assert ex.value.status == apc.APC_EUNSUPPORTED
+    p32 = apc.Plan(A, b, S.off, "f32")
+    with pytest.raises(apc.ApcError) as ex:
+        apc.apc_set_anchor(p32.handle, -1)
+    assert ex.value.status == apc.APC_EINVAL
+    p32.iterate(1)
+    with pytest.raises(apc.ApcError) as ex:
+        apc.apc_set_anchor(p32.handle, 4)
+    assert ex.value.status == apc.APC_EINVAL
+
+
+@pytest.mark.parametrize("rt,split", [("1", "8"), ("4", "1"), ("2", "3")])
+def test_launch_shapes_change_rounding_only(rt, split, monkeypatch):
+    """Every (rows per workgroup, split-K) shape computes the same products: FP64
+    trajectories from forced shapes agree with the tuned one to rounding."""
+    apc = _apc()
+    torch = _torch()
+    S = synth.gaussian_system(1500, 1000, 10, k=24, seed=38, scale=1 / math.sqrt(1000))
+    A, b = upload(S)
+    g, e, _ = O.optimal_params(*O.spectrum(S.A, S.off))
+    tuned = apc.Plan(A, b, S.off, "f64", gamma=g, eta=e)
+    tuned.iterate(25)
+    x_tuned = tuned.xbar()
+    monkeypatch.setenv("APC_TN_RT", rt)
+    monkeypatch.setenv("APC_TN_SPLIT", split)
+    forced = apc.Plan(A, b, S.off, "f64", gamma=g, eta=e)
+    shapes = forced.launch_shapes()
+    forced.iterate(25)
+    dev = float(torch.linalg.norm(forced.xbar() - x_tuned) / torch.linalg.norm(x_tuned))
+    say(f"case: forced shapes {shapes['pass_a']} {shapes['pass_b']}: dev {dev:.2e}")
+    assert shapes["pass_b"]["splits"] == int(split)
+    assert dev <= 1e-12
 
 
 def test_multi_rhs_solve_and_residual():
@@ -482,16 +548,16 @@ def test_multi_rhs_solve_and_residual():
 # ---------------------------------------------------------------- mixed precision
 
 
-@pytest.mark.parametrize("alpha,k", [(3.0, 32), (1.5, 32), (3.0, 1)])
-def test_bf16_refinement_reaches_fp64_accuracy(alpha, k):
+@pytest.mark.parametrize("alpha,k,anchor", [(3.0, 32, 0), (1.5, 32, 0), (3.0, 1, 0), (1.5, 32, 8)])
+def test_bf16_refinement_reaches_fp64_accuracy(alpha, k, anchor):
     """BF16 projections on matrix cores inside FP64 iterative refinement: the solution
     matches x* (b = A x* in FP64; kappa(A) < 10 here) to 1e-10 relative error, the
     bar for the mixed-precision mode against the FP64 oracle's direct solve."""
     apc = _apc()
     S = synth.shifted_square(2048, 8, k=k, shift=alpha, seed=40)
-    say(f"case: bf16 refinement alpha={alpha} k={k}")
+    say(f"case: bf16 refinement alpha={alpha} k={k} anchor={anchor}")
     A, b = upload(S)
-    plan = apc.Plan(A, b, S.off, "bf16_ir")
+    plan = apc.Plan(A, b, S.off, "bf16_ir", anchor_every=anchor)
     x, it, rr, st = plan.solve(1e-13, 2000)
     info = plan.info()
     xs = S.xstar
