@@ -119,12 +119,15 @@ def _err(plan, xs, xs_norm):
     return float(torch.linalg.norm(plan.xbar() - xs)) / xs_norm
 
 
-def time_plain(apc, A, b, off, xs, prec, target, ws, max_updates=400):
+MFMA_PEAK_TFLOPS = {"f32": 157.3, "bf16": 2500.0, "f64": 78.6}
+
+
+def time_plain(apc, A, b, off, xs, prec, target, ws, max_updates=400, anchor=None):
     """Setup + the number of updates that reaches `target` relative error (counted
     in an untimed run), timed end to end with the stream synchronised."""
     import torch
     xs_norm = float(torch.linalg.norm(xs))
-    plan = apc.Plan(A, b, off, prec, workspace=ws)
+    plan = apc.Plan(A, b, off, prec, workspace=ws, anchor_every=anchor)
     T, err = 0, _err(plan, xs, xs_norm)
     while err > target and T < max_updates:
         plan.iterate(1)
@@ -132,15 +135,15 @@ def time_plain(apc, A, b, off, xs, prec, target, ws, max_updates=400):
         err = _err(plan, xs, xs_norm)
     plan.close()
     if err > target:
-        # FP32 stalls at its rounding floor: report that, and the time to 10x the target.
+        # Plain FP32 levels off at its rounding floor: report that, and the time to 10x.
         res = {"reached": False, "updates_tried": T, "floor_err": err}
         if target < 1e-5:
             res["time_to_%.0e" % (10 * target)] = time_plain(apc, A, b, off, xs, prec,
-                                                              10 * target, ws, max_updates)
+                                                              10 * target, ws, max_updates, anchor)
         return res
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    plan = apc.Plan(A, b, off, prec, workspace=ws)
+    plan = apc.Plan(A, b, off, prec, workspace=ws, anchor_every=anchor)
     t1 = time.perf_counter()
     tot, pa, pb, pv = plan.iterate_timed(T)
     torch.cuda.synchronize()
@@ -151,16 +154,16 @@ def time_plain(apc, A, b, off, xs, prec, target, ws, max_updates=400):
             "iterate_ms": round((t2 - t1) * 1e3, 2), "total_ms": round((t2 - t0) * 1e3, 2),
             "us_per_update": round(tot * 1e3 / max(T, 1), 1),
             "pass_a_us": round(pa * 1e3 / max(T, 1), 1), "pass_b_us": round(pb * 1e3 / max(T, 1), 1),
-            "average_us": round(pv * 1e3 / max(T, 1), 1)}
+            "epilogue_us": round(pv * 1e3 / max(T, 1), 1)}
 
 
-def time_refined(apc, A, b, off, xs, rtol, ws):
+def time_refined(apc, A, b, off, xs, rtol, ws, anchor=None):
     """Mixed precision: setup + apc_solve to relative residual rtol."""
     import torch
     xs_norm = float(torch.linalg.norm(xs))
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    plan = apc.Plan(A, b, off, "bf16_ir", workspace=ws)
+    plan = apc.Plan(A, b, off, "bf16_ir", workspace=ws, anchor_every=anchor)
     t1 = time.perf_counter()
     x, it, rr, st = plan.solve(rtol, 5000)
     torch.cuda.synchronize()
@@ -173,10 +176,51 @@ def time_refined(apc, A, b, off, xs, rtol, ws):
             "solve_ms": round((t2 - t1) * 1e3, 2), "total_ms": round((t2 - t0) * 1e3, 2)}
 
 
+def krhs_rates(apc, A, b, off, prec, ws, T=16):
+    """Per-kernel rates of the k-RHS passes (low-precision updates only, anchor off):
+    algorithmic flops 2 N n k per pass, bytes = the streamed factor + V + W/Z."""
+    N, n = A.shape
+    k = b.shape[1]
+    sq = {"f32": 4, "bf16_ir": 2, "f64": 8}[prec]
+    plan = apc.Plan(A, b, off, prec, workspace=ws, anchor_every=0 if prec != "f64" else None)
+    shapes = plan.launch_shapes()
+    tot, pa, pb, pv = plan.iterate_timed(T)
+    plan.close()
+    name = {"f32": "f32", "bf16_ir": "bf16", "f64": "f64"}[prec]
+    flops = 2.0 * N * n * k
+    out = {"kernel": f"k_tn<{name}>", "launch_shapes": shapes, "us_per_update": round(tot * 1e3 / T, 1)}
+    for tag, ms, rows, K in (("pass_a", pa, N, n), ("pass_b", pb, n, N)):
+        t = ms * 1e-3 / T
+        byts = rows * K * sq + (K + rows) * k * sq
+        out[tag] = {"us": round(t * 1e6, 1), "tflops": round(flops / t / 1e12, 1),
+                    "mfma_frac": round(flops / t / 1e12 / MFMA_PEAK_TFLOPS[name], 3),
+                    "hbm_GBs": round(byts / t / 1e9, 1),
+                    "hbm_frac": round(byts / t / 1e9 / HBM_PEAK_GBS, 3)}
+    out["epilogue_us"] = round(pv * 1e3 / T, 1)
+    return out
+
+
 def secondary(apc, synth, dev):
     """Batched and mixed-precision workloads, each against plain FP32 on the same inputs."""
     import torch
     out = {}
+    # Square Gaussian N = n = 512, m = 8, FP64, 2000 updates (latency-bound: C is 2 MiB).
+    S = synth.square_gaussian_512()
+    A = torch.from_numpy(S.A).to(dev)
+    b = torch.from_numpy(S.B).to(dev)
+    plan = apc.Plan(A, b, S.off, "f64")
+    plan.iterate(50)
+    tot, pa, pb, pv = plan.iterate_timed(2000)
+    err = float(torch.linalg.norm(plan.xbar() - torch.from_numpy(S.xstar).to(dev))) / float(
+        np.linalg.norm(S.xstar))
+    out["square512_fp64"] = {"workload": "N=n=512, A, x* iid N(0,1), m=8 blocks of 64, FP64",
+                             "updates": 2000, "us_per_update": round(tot * 1e3 / 2000, 2),
+                             "pass_a_us": round(pa * 1e3 / 2000, 2),
+                             "pass_b_us": round(pb * 1e3 / 2000, 2),
+                             "average_us": round(pv * 1e3 / 2000, 2),
+                             "err_after_2050": err, "params": plan.params()}
+    plan.close()
+    del A, b, S
     # Batched: N = n = 8192, A = G/sqrt(n) + 2I, k = 64, 64 blocks of uneven size.
     S = synth.shifted_uneven_8k(k=64)
     A = torch.from_numpy(S.A).to(dev)
@@ -184,9 +228,15 @@ def secondary(apc, synth, dev):
     xs = torch.from_numpy(S.xstar).to(dev)
     ws = torch.empty(apc.Plan.workspace_bytes(S.N, S.n, S.off, "f32", k=64), dtype=torch.uint8,
                      device=dev)
-    out["batched_fp32"] = {"workload": "N=n=8192, A=G/sqrt(n)+2I, k=64, m=64 uneven p_i in "
-                                       "[28, 228]", "time_to_1e-6": time_plain(
-                               apc, A, b, S.off, xs, "f32", 1e-6, ws)}
+    out["batched_fp32"] = {
+        "workload": "N=n=8192, A=G/sqrt(n)+2I, k=64, m=64 uneven p_i in [28, 228]",
+        "time_to_1e-6": time_plain(apc, A, b, S.off, xs, "f32", 1e-6, ws),
+        "time_to_1e-10": time_plain(apc, A, b, S.off, xs, "f32", 1e-10, ws),
+        "plain_fp32_time_to_1e-6": time_plain(apc, A, b, S.off, xs, "f32", 1e-6, ws, anchor=0),
+        "kernels": krhs_rates(apc, A, b, S.off, "f32", ws),
+        "note": "FP32 projections on matrix cores with an FP64 anchor update every 16 updates "
+                "(default); plain_fp32 = every update in FP32",
+    }
     del A, b, xs, ws, S
     torch.cuda.empty_cache()
     # Mixed precision vs plain FP32: N = n = 16384, A = G/sqrt(n) + alpha I, k = 128, m = 64.
@@ -203,9 +253,14 @@ def secondary(apc, synth, dev):
         A = G.clone()
         A.diagonal().add_(alpha)
         B = (A @ Xs).contiguous()
-        entry = {"plain_fp32_time_to_1e-6": time_plain(apc, A, B, off, Xs, "f32", 1e-6, ws32),
+        entry = {"plain_fp32_time_to_1e-6": time_plain(apc, A, B, off, Xs, "f32", 1e-6, ws32,
+                                                       anchor=0),
+                 "fp32_anchored_time_to_1e-6": time_plain(apc, A, B, off, Xs, "f32", 1e-6, ws32),
                  "bf16_ir_time_to_1e-6": time_refined(apc, A, B, off, Xs, 1e-7, ws16),
                  "bf16_ir_time_to_1e-10": time_refined(apc, A, B, off, Xs, 1e-11, ws16)}
+        if alpha == 3.0:
+            entry["kernels_bf16"] = krhs_rates(apc, A, B, off, "bf16_ir", ws16)
+            entry["kernels_fp32"] = krhs_rates(apc, A, B, off, "f32", ws32)
         mixed[f"alpha={alpha}"] = entry
         del A, B
     out["mixed_precision"] = mixed
