@@ -287,6 +287,65 @@ def apc_run(A, B, off, T: int, gamma: float | None = None, eta: float | None = N
 
 
 # ----------------------------------------------------------------------------
+# Differentiation of the unrolled iteration (adjoint of Alg. 1)
+# ----------------------------------------------------------------------------
+
+def apc_adjoint(A, B, off, T: int, gamma: float, eta: float, dxbar: np.ndarray):
+    """Reverse-mode derivative of x_bar(T) from Alg. 1 (R2, R3) with respect to
+    b, gamma and eta, for the scalar L with dL/dx_bar(T) = dxbar.
+
+    The forward trajectory (every x_i(t), x_bar(t)) is stored; the reverse pass
+    applies the transpose of each step of eqs. (2a)-(2b) in the opposite order.
+    With l_i = lambda_i(t+1) + (eta/m) mu(t+1) (the adjoint of x_i(t+1), its
+    direct path plus the path through x_bar(t+1)) and P_i symmetric:
+        lambda_i(t) = l_i - gamma P_i l_i                  (transpose of eq. (2a) in x_i)
+        mu(t)       = (1 - eta) mu(t+1) + gamma sum_i P_i l_i
+        dL/dgamma  += sum_i <l_i, P_i (x_bar(t) - x_i(t))>
+        dL/deta    += <mu(t+1), (1/m) sum_i x_i(t+1) - x_bar(t)>
+    and for the start x_i(0) = Q_i R_i^{-T} b_i, x_bar(0) = mean:
+        dL/db_i = R_i^{-1} Q_i^T (lambda_i(0) + mu(0) / m).
+    Returns (dB (N, k), dgamma, deta).
+    """
+    A = np.asarray(A, dtype=np.float64)
+    B = _as_cols(B)
+    dxbar = _as_cols(dxbar)
+    Qt, R = factor(A, off)
+    x = init_local(Qt, R, B, off)
+    xbar = initial_average(x)
+    m = x.shape[0]
+    xs, xbars = [x], [xbar]
+    for _ in range(T):
+        x, xbar = apc_step(Qt, x, xbar, gamma, eta)
+        xs.append(x)
+        xbars.append(xbar)
+    lam = np.zeros_like(xs[0])
+    mu = dxbar.copy()
+    dgamma = 0.0
+    deta = 0.0
+    for t in range(T - 1, -1, -1):
+        x_t, xb_t, x_next = xs[t], xbars[t], xs[t + 1]
+        acc = np.zeros_like(xb_t)
+        for i in range(m):
+            acc = acc + x_next[i]
+        deta += float(np.sum(mu * (acc / m - xb_t)))
+        lam_new = np.empty_like(lam)
+        push = np.zeros_like(mu)
+        for i in range(m):
+            li = lam[i] + (eta / m) * mu
+            pli = project(Qt[i], li)
+            dgamma += float(np.sum(pli * (xb_t - x_t[i])))   # <l_i, P_i d> = <P_i l_i, d>
+            lam_new[i] = li - gamma * pli
+            push = push + pli
+        mu = (1.0 - eta) * mu + gamma * push
+        lam = lam_new
+    dB = np.zeros_like(B)
+    for i, (Qti, Ri) in enumerate(zip(Qt, R)):
+        gi = Qti @ (lam[i] + mu / m)
+        dB[off[i]:off[i + 1]] = solve_triangular(Ri, gi, lower=False)
+    return dB, dgamma, deta
+
+
+# ----------------------------------------------------------------------------
 # Sec. 4.5: block Cimmino (used only to check Proposition 2)
 # ----------------------------------------------------------------------------
 

@@ -316,6 +316,62 @@ def test_state_reduction_identity():
             np.testing.assert_allclose(x[i], x0[i] + Ps[i] @ y, atol=1e-11)
 
 
+# ---------------------------------------------------------------- adjoint
+
+
+def _loss_fn(S, T, dx):
+    """L(b, gamma, eta) = <dx, x_bar(T)>, through the forward oracle only."""
+    return lambda Bv, g, e: float(np.sum(dx * O.apc_run(S.A, Bv, S.off, T, g, e)["xbar"]))
+
+
+@pytest.mark.parametrize("N,n,m,k,T,seed", [(24, 12, 3, 2, 15, 5), (30, 30, 5, 1, 25, 6)])
+def test_adjoint_matches_central_differences(N, n, m, k, T, seed):
+    """x_bar(T) is linear in b, so a central difference along any direction is exact
+    up to rounding; in gamma and eta it is smooth, so central differences with h = 1e-5
+    agree to O(h^2)."""
+    S = small_system(N=N, n=n, m=m, k=k, seed=seed)
+    g, e, _ = O.optimal_params(*O.spectrum(S.A, S.off))
+    rng = np.random.default_rng(seed + 100)
+    dx = rng.standard_normal((n, k))
+    dB, dg, de = O.apc_adjoint(S.A, S.B, S.off, T, g, e, dx)
+    L = _loss_fn(S, T, dx)
+    d = rng.standard_normal(S.B.reshape(N, k).shape)
+    base = S.B.reshape(N, k)
+    fd_b = (L(base + d, g, e) - L(base - d, g, e)) / 2.0
+    assert abs(np.sum(dB * d) - fd_b) <= 1e-9 * max(1.0, abs(fd_b))
+    h = 1e-5
+    fd_g = (L(base, g + h, e) - L(base, g - h, e)) / (2 * h)
+    fd_e = (L(base, g, e + h) - L(base, g, e - h)) / (2 * h)
+    assert abs(dg - fd_g) <= 1e-6 * max(1.0, abs(fd_g))
+    assert abs(de - fd_e) <= 1e-6 * max(1.0, abs(fd_e))
+
+
+def test_adjoint_of_the_start():
+    """T = 0: x_bar(0) = (1/m) sum_i A_i^T (A_i A_i^T)^{-1} b_i, so
+    dL/db_i = (1/m) (A_i A_i^T)^{-1} A_i dx (written from the definition, no QR)."""
+    S = small_system(N=20, n=16, m=4, k=3, seed=7)
+    dx = np.random.default_rng(8).standard_normal((16, 3))
+    dB, dg, de = O.apc_adjoint(S.A, S.B, S.off, 0, 1.2, 3.0, dx)
+    for i, Ai in enumerate(O.blocks(S.A, S.off)):
+        ref = np.linalg.solve(Ai @ Ai.T, Ai @ dx) / 4
+        np.testing.assert_allclose(dB[S.off[i]:S.off[i + 1]], ref, atol=1e-12)
+    assert dg == 0.0 and de == 0.0
+
+
+def test_adjoint_converged_gradient():
+    """Square A: x_bar(T) -> A^{-1} b, hence dL/db -> A^{-T} dx, while the limit does not
+    depend on gamma or eta (their derivatives vanish)."""
+    S = synth.shifted_square(32, 4, k=2, shift=2.0, seed=9)
+    g, e, rho = O.optimal_params(*O.spectrum(S.A, S.off))
+    dx = np.random.default_rng(10).standard_normal((32, 2))
+    T = int(np.ceil(np.log(1e-15) / np.log(rho))) + 40
+    dB, dg, de = O.apc_adjoint(S.A, S.B, S.off, T, g, e, dx)
+    ref = np.linalg.solve(S.A.T, dx)
+    assert np.linalg.norm(dB - ref) <= 1e-10 * np.linalg.norm(ref)
+    scale = np.linalg.norm(dx) * np.linalg.norm(S.xstar)
+    assert abs(dg) <= 1e-9 * scale and abs(de) <= 1e-9 * scale
+
+
 def test_block_order_changes_result_only_by_rounding():
     S = small_system(N=32, n=32, m=4, seed=20, shift=1.0)
     out = O.apc_run(S.A, S.B, S.off, T=40)

@@ -73,6 +73,49 @@ def _X_missing_inverse(A, off):
 
 
 _orig_params = O.optimal_params
+_orig_adjoint = O.apc_adjoint
+
+
+def _adjoint_variant(direct_average_path=True, start_transposed=False):
+    """The oracle's adjoint with one planted mistake (same steps otherwise)."""
+    from scipy.linalg import solve_triangular
+
+    def adj(A, B, off, T, gamma, eta, dxbar):
+        B = B[:, None] if B.ndim == 1 else B
+        dxbar = dxbar[:, None] if dxbar.ndim == 1 else dxbar
+        Qt, R = O.factor(A, off)
+        x = O.init_local(Qt, R, B, off)
+        xbar = O.initial_average(x)
+        m = x.shape[0]
+        xs, xbars = [x], [xbar]
+        for _ in range(T):
+            x, xbar = O.apc_step(Qt, x, xbar, gamma, eta)
+            xs.append(x)
+            xbars.append(xbar)
+        lam, mu, dg, de = np.zeros_like(xs[0]), dxbar.copy(), 0.0, 0.0
+        for t in range(T - 1, -1, -1):
+            de += float(np.sum(mu * (xs[t + 1].mean(0) - xbars[t])))
+            lam_new, push = np.empty_like(lam), np.zeros_like(mu)
+            for i in range(m):
+                li = lam[i] + ((eta / m) * mu if direct_average_path else 0.0)
+                pli = O.project(Qt[i], li)
+                dg += float(np.sum(pli * (xbars[t] - xs[t][i])))
+                lam_new[i] = li - gamma * pli
+                push = push + pli
+            mu, lam = (1.0 - eta) * mu + gamma * push, lam_new
+        dB = np.zeros_like(B)
+        for i, (Qti, Ri) in enumerate(zip(Qt, R)):
+            gi = Qti @ (lam[i] + mu / m)
+            dB[off[i]:off[i + 1]] = solve_triangular(Ri, gi, trans="T" if start_transposed else "N",
+                                                     lower=False)
+        return dB, dg, de
+    return adj
+
+
+_adjoint_no_average_path = _adjoint_variant(direct_average_path=False)
+_adjoint_no_average_path.__name__ = "_adjoint_no_average_path"
+_adjoint_start_transposed = _adjoint_variant(start_transposed=True)
+_adjoint_start_transposed.__name__ = "_adjoint_start_transposed"
 
 MUTANTS = [
     ("apc_step", _step_wrong_sign, ["test_single_update_solves_the_constrained_problem",
@@ -87,6 +130,11 @@ MUTANTS = [
     ("optimal_params", _params_plain_kappa, ["test_optimal_params_satisfy_theorem1"]),
     ("init_local", _init_transposed, ["test_init_is_min_norm_solution"]),
     ("X_matrix", _X_missing_inverse, ["test_X_matrix_properties"]),
+    ("apc_adjoint", _adjoint_no_average_path, ["test_adjoint_matches_central_differences",
+                                               "test_adjoint_converged_gradient"]),
+    ("apc_adjoint", _adjoint_start_transposed, ["test_adjoint_matches_central_differences",
+                                                "test_adjoint_of_the_start",
+                                                "test_adjoint_converged_gradient"]),
 ]
 
 
@@ -95,6 +143,8 @@ def _run_pin(name):
     if name == "test_optimal_params_satisfy_theorem1":
         for seed in range(5):
             fn(seed)
+    elif name == "test_adjoint_matches_central_differences":
+        fn(24, 12, 3, 2, 15, 5)
     else:
         fn()
 
