@@ -45,10 +45,12 @@ typedef enum {
   APC_F64 = 0,    /* Q_i and all arithmetic in FP64                                 */
   APC_F32 = 1,    /* Q_i stored in FP32, projections in FP32 with FP32             */
                   /* accumulation, iterates and update arithmetic in FP64          */
-  APC_BF16_IR = 2 /* iterative refinement: inner APC on a bf16 Q_i (matrix cores,  */
-                  /* FP32 accumulation, FP64 state), FP64 residual B - A X and     */
-                  /* FP64 start x_bar(0) on matrix cores; setup QR and eigenvalue  */
-                  /* estimate in FP64                                              */
+  APC_BF16_IR = 2, /* iterative refinement: inner APC on a bf16 Q_i (matrix cores, */
+                   /* FP32 accumulation, FP64 state), FP64 residual B - A X and    */
+                   /* FP64 start x_bar(0) on matrix cores; setup QR and eigenvalue */
+                   /* estimate in FP64                                             */
+  APC_REDUCED_FORM = 16 /* flag, OR'ed into APC_F64 / APC_F32: use the (y, x_bar)    */
+                        /* form below also for k = 1 (needed by apc_backward)      */
 } apc_precision;
 
 /* Two forms of the same iteration:
@@ -214,6 +216,48 @@ apc_status apc_get_launch(apc_plan p, int32_t which, int32_t* rows_per_wg, int32
  * the first update.  Host-only.  APC_EUNSUPPORTED for other plans, APC_EINVAL
  * for every < 0 or after an update. */
 apc_status apc_set_anchor(apc_plan p, int32_t every);
+
+/* Replace the iteration parameters of eq. (2) (e.g. to probe the derivative in
+ * gamma or eta).  Takes effect at the next update; host-only; mu_min, mu_max
+ * and rho keep describing the setup's estimate.  APC_EINVAL for non-finite. */
+apc_status apc_set_params(apc_plan p, double gamma, double eta);
+
+/* Start Alg. 1 again without refactoring A: with B != NULL, new right-hand
+ * sides (device, N x k FP64, entry (r, c) at B[r*ldb + c]; kept by pointer
+ * like apc_setup's B); c_i = R_i^{-T} b_i, x_i(0) = Q_i c_i, x_bar(0) = mean
+ * (Alg. 1 initialisation, via the stored inverse CholeskyQR factors).  With
+ * B == NULL, restarts from the current right-hand sides.  The update count and
+ * refinement count return to 0.  Synchronises when B is given (||B||). */
+apc_status apc_restart(apc_plan p, const double* B, int64_t ldb);
+
+/* Bytes of device workspace apc_backward needs for T updates with a checkpoint
+ * every ckpt_every updates: ceil(T/ckpt_every)+1 saved (y, x_bar) pairs, one
+ * recomputed segment of ckpt_every+1 pairs, the adjoint vectors.  0 for a plan
+ * without the (y, x_bar) form or invalid arguments. */
+size_t apc_backward_workspace_bytes(apc_plan p, int32_t T, int32_t ckpt_every);
+
+/* Reverse-mode derivative of the unrolled iteration (Alg. 1 from its start,
+ * T updates of eq. (2a)-(2b), with the plan's gamma and eta) for a scalar L
+ * given dL/dx_bar(T) = dXbar (device, n x k FP64, entry (j, c) at
+ * dXbar[j*ldd + c]).  Writes dL/dB to dB (device, N x k, entry (r, c) at
+ * dB[r*lddb + c]) and dL/dgamma, dL/deta to *dgamma, *deta (host).
+ *
+ * The forward is run again from the start, keeping (y, x_bar) every
+ * ckpt_every updates (~sqrt(T) balances memory and recomputation); the
+ * reverse pass recomputes one segment at a time and applies the transpose of
+ * each update.  X is symmetric, so the transposed update is the same two
+ * contractions as a forward update (W = C v, Z = C^T W) plus an elementwise
+ * step; the start x_bar(0) = (1/m) C^T c, c_i = R_i^{-T} b_i, is transposed
+ * by one FP64 product and the two inverse CholeskyQR factors.  With L linear
+ * in x_bar(T), dL/dB is exact in exact arithmetic; in FP32 plans the
+ * products run in FP32 as in the forward.  Needs an APC_F64 / APC_F32 plan in
+ * the (y, x_bar) form (k > 1 or APC_REDUCED_FORM; else APC_EUNSUPPORTED).
+ * bwd_ws: device, 256-byte aligned, >= apc_backward_workspace_bytes.  The plan
+ * is left at x_bar(T) of the forward run (apc_iterations = T).
+ * Synchronises. */
+apc_status apc_backward(apc_plan p, const double* dXbar, int64_t ldd, int32_t T,
+                        int32_t ckpt_every, double* dB, int64_t lddb, double* dgamma,
+                        double* deta, void* bwd_ws, size_t bwd_bytes);
 
 /* Number of updates applied since setup (host). */
 int64_t apc_iterations(apc_plan p);

@@ -22,6 +22,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libapc.so")
 
 APC_F64, APC_F32, APC_BF16_IR = 0, 1, 2
+APC_REDUCED_FORM = 16
 PRECISIONS = {"f64": APC_F64, "f32": APC_F32, "bf16_ir": APC_BF16_IR}
 
 STATUS_NAMES = {
@@ -35,7 +36,8 @@ EXPORTED = (
     "apc_workspace_bytes", "apc_setup", "apc_iterate", "apc_iterate_timed", "apc_residual",
     "apc_solve", "apc_get_xbar", "apc_get_local", "apc_project", "apc_get_params",
     "apc_iterations", "apc_destroy", "apc_last_error", "apc_optimal_params",
-    "apc_tridiag_extremes", "apc_get_info", "apc_get_launch", "apc_set_anchor",
+    "apc_tridiag_extremes", "apc_get_info", "apc_get_launch", "apc_set_anchor", "apc_set_params",
+    "apc_restart", "apc_backward_workspace_bytes", "apc_backward",
 )
 
 
@@ -90,6 +92,10 @@ def _load() -> ctypes.CDLL:
         "apc_get_info": (i32, [vp, Pi, Pi, Pi, Pi, Pi]),
         "apc_get_launch": (i32, [vp, i32, Pi, Pi, Pf]),
         "apc_set_anchor": (i32, [vp, i32]),
+        "apc_set_params": (i32, [vp, f64, f64]),
+        "apc_restart": (i32, [vp, vp, i64]),
+        "apc_backward_workspace_bytes": (ctypes.c_size_t, [vp, i32, i32]),
+        "apc_backward": (i32, [vp, vp, i64, i32, i32, vp, i64, Pd, Pd, vp, ctypes.c_size_t]),
         "apc_optimal_params": (i32, [f64, f64, Pd, Pd, Pd]),
         "apc_tridiag_extremes": (i32, [Pd, Pd, i32, i32, Pd, Pd, Pd, Pd]),
         "apc_destroy": (None, [vp]),
@@ -190,6 +196,26 @@ def apc_set_anchor(plan, every: int):
     _check(lib.apc_set_anchor(plan, every))
 
 
+def apc_set_params(plan, gamma: float, eta: float):
+    _check(lib.apc_set_params(plan, gamma, eta))
+
+
+def apc_restart(plan, B: int, ldb: int):
+    _check(lib.apc_restart(plan, B, ldb))
+
+
+def apc_backward_workspace_bytes(plan, T: int, ckpt_every: int) -> int:
+    return int(lib.apc_backward_workspace_bytes(plan, T, ckpt_every))
+
+
+def apc_backward(plan, dXbar: int, ldd: int, T: int, ckpt_every: int, dB: int, lddb: int,
+                 ws: int, ws_bytes: int):
+    dg, de = ctypes.c_double(), ctypes.c_double()
+    _check(lib.apc_backward(plan, dXbar, ldd, T, ckpt_every, dB, lddb, ctypes.byref(dg),
+                            ctypes.byref(de), ws, ws_bytes))
+    return dg.value, de.value
+
+
 def apc_iterations(plan) -> int:
     return int(lib.apc_iterations(plan))
 
@@ -234,10 +260,11 @@ class Plan:
     selects Theorem 1's optimum.  The plan keeps references to A, b and its
     workspace.  anchor_every (FP32 / bf16 plans with k > 1 or bf16): FP64
     anchor spacing, see apc_set_anchor (None keeps the library default).
+    reduced_form: run k = 1 in the (y, x_bar) form too (needed for backward()).
     """
 
     def __init__(self, A, b, off, precision: str = "f64", gamma=None, eta=None, stream=None,
-                 workspace=None, anchor_every=None):
+                 workspace=None, anchor_every=None, reduced_form=False):
         import torch
 
         if A.dtype != torch.float64 or b.dtype != torch.float64:
@@ -254,7 +281,7 @@ class Plan:
         self.off = np.asarray(off, dtype=np.int64)
         self.m = len(self.off) - 1
         self.k = 1 if b.dim() == 1 else b.shape[1]
-        self.precision = PRECISIONS[precision]
+        self.precision = PRECISIONS[precision] | (APC_REDUCED_FORM if reduced_form else 0)
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         ws = apc_workspace_bytes(self.N, self.n, self.off, self.m, self.k, self.precision)
         if ws == 0:
@@ -303,6 +330,40 @@ class Plan:
             _check(st)
         return x, it, rr, st
 
+    def set_params(self, gamma: float, eta: float):
+        apc_set_params(self.handle, float(gamma), float(eta))
+
+    def restart(self, b=None):
+        """Start Alg. 1 again, optionally from new right-hand sides b (same shape)."""
+        if b is None:
+            apc_restart(self.handle, None, 1)
+            return
+        if b.dtype != self._torch.float64 or not b.is_cuda or b.shape != self.b.shape:
+            raise ValueError("b must be a float64 CUDA tensor shaped like the plan's b")
+        b = b.contiguous()
+        self.b = b
+        apc_restart(self.handle, b.data_ptr(), 1 if self.k == 1 else self.k)
+
+    def backward(self, dxbar, T: int, ckpt_every: int | None = None):
+        """(dL/db, dL/dgamma, dL/deta) for dL/dx_bar(T) = dxbar over T updates from the start."""
+        torch = self._torch
+        if ckpt_every is None:
+            ckpt_every = max(1, int(math.isqrt(max(T, 1))))
+        dxbar = dxbar.to(device=self.device, dtype=torch.float64).contiguous()
+        if dxbar.shape != tuple(self._xshape()):
+            raise ValueError(f"dxbar must have shape {tuple(self._xshape())}")
+        nb = apc_backward_workspace_bytes(self.handle, T, ckpt_every)
+        if nb == 0:
+            raise ApcError(APC_EUNSUPPORTED, "backward needs the (y, x_bar) form: k > 1 or "
+                           "reduced_form=True, precision f64 or f32")
+        ws = torch.empty(nb + 256, dtype=torch.uint8, device=self.device)
+        wp = (ws.data_ptr() + 255) // 256 * 256
+        dB = torch.empty(self.b.shape, dtype=torch.float64, device=self.device)
+        ld = 1 if self.k == 1 else self.k
+        dg, de = apc_backward(self.handle, dxbar.data_ptr(), ld, T, ckpt_every, dB.data_ptr(), ld,
+                              wp, nb)
+        return dB, dg, de
+
     # -- state access
     def xbar(self):
         x = self._torch.empty(self._xshape(), dtype=self._torch.float64, device=self.device)
@@ -348,3 +409,46 @@ class Plan:
             self.close()
         except Exception:
             pass
+
+
+class UnrolledAPC:
+    """torch.autograd.Function wrapper: x_bar(T) = APC_T(b; gamma, eta) on a plan's
+    factorisation, differentiable in b, gamma and eta (adjoint with checkpoints)."""
+
+    _fn = None
+
+    @classmethod
+    def function(cls):
+        if cls._fn is None:
+            import torch
+
+            class _F(torch.autograd.Function):
+                @staticmethod
+                def forward(ctx, b, gamma, eta, plan, T, ckpt_every):
+                    plan.set_params(float(gamma), float(eta))
+                    plan.restart(b.detach())
+                    plan.iterate(T)
+                    ctx.plan, ctx.T, ctx.ckpt = plan, T, ckpt_every
+                    ctx.params = (float(gamma), float(eta))
+                    return plan.xbar()
+
+                @staticmethod
+                def backward(ctx, gx):
+                    plan = ctx.plan
+                    plan.set_params(*ctx.params)
+                    dB, dg, de = plan.backward(gx, ctx.T, ctx.ckpt)
+                    return (dB, torch.tensor(dg, dtype=torch.float64),
+                            torch.tensor(de, dtype=torch.float64), None, None, None)
+
+            cls._fn = _F
+        return cls._fn
+
+
+def unrolled_apc(plan, b, gamma, eta, T: int, ckpt_every: int | None = None):
+    """x_bar(T) of Alg. 1 with right-hand sides b and parameters (gamma, eta) as tensors;
+    gradients flow to every argument that requires them."""
+    import torch
+    g = gamma if torch.is_tensor(gamma) else torch.tensor(float(gamma), dtype=torch.float64)
+    e = eta if torch.is_tensor(eta) else torch.tensor(float(eta), dtype=torch.float64)
+    ck = ckpt_every if ckpt_every is not None else max(1, int(math.isqrt(max(T, 1))))
+    return UnrolledAPC.function().apply(b, g, e, plan, T, ck)

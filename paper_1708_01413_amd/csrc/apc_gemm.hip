@@ -298,6 +298,58 @@ __global__ __launch_bounds__(256) void k_tn_anchor_vec(const double* y, const do
     yref[e] = (1.0 - gamma) * y[e] + gamma * xb[e];
 }
 
+// Operand yq = TQ((1 - gamma) y + gamma x_bar) after the state was restored.
+template <typename TQ>
+__global__ __launch_bounds__(256) void k_tn_prep(const double* y, const double* xb, int64_t count,
+                                                 double gamma, TQ* yq) {
+  for (int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; e < count;
+       e += static_cast<int64_t>(gridDim.x) * blockDim.x)
+    yq[e] = cvt<TQ>((1.0 - gamma) * y[e] + gamma * xb[e]);
+}
+
+// One reverse step of the (y, x_bar) iteration; see TnAdjointArgs.  Each
+// workgroup adds its own share of the dL/dgamma and dL/deta sums to red[2 b],
+// red[2 b + 1] (grid fixed by the launcher, so the sums are deterministic).
+template <typename P, typename TQ>
+__global__ __launch_bounds__(256) void k_tn_adjoint(TnAdjointArgs a) {
+  const int64_t total = static_cast<int64_t>(a.kp) * a.n;
+  const int64_t stride = static_cast<int64_t>(a.kp) * a.ldp;
+  const P* part = static_cast<const P*>(a.part);
+  TQ* bq = static_cast<TQ*>(a.bq);
+  const double g = a.gamma, eta = a.eta;
+  double sg = 0.0, se = 0.0;
+  for (int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; e < total;
+       e += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    const int64_t c = e / a.n, j = e - c * a.n;
+    const int64_t i = c * a.ldx + j;
+    const double xbh = split_sum(part, a.nsplit, stride, c * a.ldp + j) * a.inv_m;  // X b
+    const double bh = a.bh[i];
+    const double at = a.a[i] + eta * (bh - xbh);
+    sg += at * (a.xb_t[i] - a.y_t[i]);
+    se += bh * (a.xb_next[i] - a.xb_t[i]);
+    a.g0[i] += eta * bh;
+    a.a[i] = (1.0 - g) * at;
+    const double bn = (1.0 - eta) * bh + g * at;
+    a.bh[i] = bn;
+    bq[c * a.ldq + j] = cvt<TQ>(bn);
+  }
+  __shared__ double rs[2][256];
+  rs[0][threadIdx.x] = sg;
+  rs[1][threadIdx.x] = se;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) {
+      rs[0][threadIdx.x] += rs[0][threadIdx.x + o];
+      rs[1][threadIdx.x] += rs[1][threadIdx.x + o];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    a.red[2 * blockIdx.x] += rs[0][0];
+    a.red[2 * blockIdx.x + 1] += rs[1][0] / eta;
+  }
+}
+
 // R[c*ldr + r] = B[r*ldb + c] - sum of the FP64 split partials, r < N, c < k.
 __global__ __launch_bounds__(256) void k_tn_resid(const double* part, int32_t nsplit, int32_t kp,
                                                   int64_t ldp, int64_t N, int32_t k, const double* B,
@@ -407,6 +459,29 @@ hipError_t launch_tn_update(int type, int part_f64, const TnUpdateArgs& a, hipSt
 hipError_t launch_tn_anchor_vec(const double* y, const double* xb, int64_t count, double gamma,
                                double* yref, hipStream_t s) {
   k_tn_anchor_vec<<<grid_stride_blocks(count), 256, 0, s>>>(y, xb, count, gamma, yref);
+  return hipGetLastError();
+}
+
+hipError_t launch_tn_prep(int type, const double* y, const double* xb, int64_t count, double gamma,
+                          void* yq, hipStream_t s) {
+  const unsigned g = grid_stride_blocks(count);
+  switch (type) {
+    case kTnF64: k_tn_prep<double><<<g, 256, 0, s>>>(y, xb, count, gamma, static_cast<double*>(yq)); break;
+    case kTnF32: k_tn_prep<float><<<g, 256, 0, s>>>(y, xb, count, gamma, static_cast<float*>(yq)); break;
+    case kTnBF16: k_tn_prep<__bf16><<<g, 256, 0, s>>>(y, xb, count, gamma, static_cast<__bf16*>(yq)); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+int tn_adjoint_blocks() { return kTnAdjointBlocks; }
+
+hipError_t launch_tn_adjoint(int type, const TnAdjointArgs& a, hipStream_t s) {
+  switch (type) {
+    case kTnF64: k_tn_adjoint<double, double><<<kTnAdjointBlocks, 256, 0, s>>>(a); break;
+    case kTnF32: k_tn_adjoint<float, float><<<kTnAdjointBlocks, 256, 0, s>>>(a); break;
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 

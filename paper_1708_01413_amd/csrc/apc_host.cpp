@@ -112,7 +112,10 @@ void build_tiles(const int64_t* off, int32_t m, int64_t ldc, int rows_per_tile, 
 
 // k > 1 (and the mixed-precision mode) run the (y, x_bar) form on the matrix
 // cores; k = 1 in FP64/FP32 keeps every block's x_i.
-bool uses_gemm(int32_t k, int32_t prec) { return k > 1 || prec == APC_BF16_IR; }
+int32_t base_precision(int32_t prec) { return prec & ~static_cast<int32_t>(APC_REDUCED_FORM); }
+bool uses_gemm(int32_t k, int32_t prec) {
+  return k > 1 || base_precision(prec) == APC_BF16_IR || (prec & APC_REDUCED_FORM) != 0;
+}
 
 // Right-hand sides the k-RHS state holds: 16, 32, 64, then multiples of 128
 // (one matrix-core column group); the extra columns stay zero.
@@ -124,10 +127,11 @@ int32_t padded_rhs(int32_t k, int32_t prec) {
   return static_cast<int32_t>(round_up(k, 128));
 }
 
-Layout make_layout(int64_t N, int64_t n, const int64_t* off, int32_t m, int32_t k, int32_t prec,
+Layout make_layout(int64_t N, int64_t n, const int64_t* off, int32_t m, int32_t k, int32_t flags,
                    const Tiles& T) {
   Layout L;
-  const int64_t kp = padded_rhs(k, prec);
+  const int64_t kp = padded_rhs(k, flags);
+  const int32_t prec = base_precision(flags);
   L.ldc = round_up(n, kLdAlign);
   L.kmax = std::min<int64_t>(n, kLanczosMax);
   for (int i = 0; i < m; ++i) L.S += (off[i + 1] - off[i]) * (off[i + 1] - off[i]);
@@ -144,7 +148,7 @@ Layout make_layout(int64_t N, int64_t n, const int64_t* off, int32_t m, int32_t 
     return at;
   };
   const int64_t d = sizeof(double);
-  const bool gemm = uses_gemm(k, prec);
+  const bool gemm = uses_gemm(k, flags);
   const bool bf = prec == APC_BF16_IR;
   const int64_t kq = k == 1 ? 1 : kp;        // k = 1 state columns
   L.C64a = take(N * L.ldc * d);
@@ -164,7 +168,7 @@ Layout make_layout(int64_t N, int64_t n, const int64_t* off, int32_t m, int32_t 
   L.beta = take((L.kmax + 1) * d);
   L.G = take(L.S * d);
   L.Linv = take(L.S * d);
-  L.Linv2 = take(bf ? L.S * d : 0);
+  L.Linv2 = take(L.S * d);  // both inverse CholeskyQR factors: c = L2^-1 L1^-1 b and back
   L.flags = take(4 * 4);
   L.scal = take(8 * d);
   L.partial = take(L.nparts * kq * d);
@@ -212,7 +216,8 @@ apc_status validate(int64_t N, int64_t n, const int64_t* off, int32_t m, int32_t
   if (m < 1 || m > N) return fail(APC_EINVAL, "need 1 <= m <= N (got m=%d)", m);
   if (!off) return fail(APC_EINVAL, "off is NULL");
   if (k < 1 || k > 1024) return fail(APC_EINVAL, "need 1 <= k <= 1024 (got %d)", k);
-  if (prec != APC_F64 && prec != APC_F32 && prec != APC_BF16_IR)
+  const int32_t base = base_precision(prec);
+  if (base != APC_F64 && base != APC_F32 && base != APC_BF16_IR)
     return fail(APC_EINVAL, "unknown precision %d", prec);
   if (off[0] != 0 || off[m] != N) return fail(APC_EINVAL, "off[0] must be 0 and off[m] must be N");
   const int64_t pmax = std::min<int64_t>(n, kMaxBlockRows);
@@ -345,6 +350,7 @@ struct apc_plan_s {
   int tq = kTnF64;                     // element type of the k-RHS factor copies
   TnChoice tnA, tnB, tnX0, tnR;        // launch shapes: pass A, pass B, x_bar(0), residual
   int anchor_every = 0;                // k-RHS FP32/bf16: every this many updates one in FP64
+  int64_t pmax = 1;                    // largest block
   int64_t since_start = 0;             // k-RHS updates since the last start
   int refinements = 0;
   std::vector<int32_t> tile_start;     // first pass-A tile of every block (m+1)
@@ -918,9 +924,9 @@ apc_status setup_impl(apc_plan_s* P, const Tiles& T) {
     double* cd = pass == 0 ? cb : ca;
     HIP_TRY(launch_gram(src, ldc, P->doff(), P->at<int32_t>(L.tiles_g), L.ntiles_g,
                         P->at<int64_t>(L.goff), P->at<double>(L.G), st));
-    // The mixed-precision mode keeps both inverse factors: each refinement
-    // step forms the inner right-hand sides c = L2^{-1} L1^{-1} r.
-    double* Li = (pass == 1 && P->bf16) ? P->at<double>(L.Linv2) : P->at<double>(L.Linv);
+    // Both inverse factors are kept: refinement and apc_restart form
+    // c = L2^{-1} L1^{-1} r, the adjoint applies L1^{-T} L2^{-T}.
+    double* Li = pass == 1 ? P->at<double>(L.Linv2) : P->at<double>(L.Linv);
     HIP_TRY(launch_chol_inv(P->doff(), P->at<int64_t>(L.goff), m, P->at<double>(L.G), Li, cs, cd,
                             P->kp, N, P->at<int>(L.flags), rank_tol, st));
     HIP_TRY(launch_trmm(src, dst, ldc, P->doff(), P->at<int32_t>(L.tiles_t), L.ntiles_t,
@@ -1050,8 +1056,9 @@ apc_status apc_setup(apc_plan* out, const double* A, int64_t lda, const double* 
   P->m = m;
   P->k = k;
   P->kp = padded_rhs(k, precision);
-  P->prec = precision;
+  P->prec = base_precision(precision);
   P->off.assign(off, off + m + 1);
+  for (int i = 0; i < m; ++i) P->pmax = std::max(P->pmax, off[i + 1] - off[i]);
   P->L = L;
   P->ws = static_cast<char*>(workspace);
   P->A = A;
@@ -1068,18 +1075,18 @@ apc_status apc_setup(apc_plan* out, const double* A, int64_t lda, const double* 
                             static_cast<int32_t>((off[i + 1] - off[i] + passa_rows - 1) / passa_rows));
   P->group_blocks = group_blocks >= 0 ? group_blocks : 0;
   P->gemm = uses_gemm(k, precision);
-  P->bf16 = precision == APC_BF16_IR;
-  P->tq = precision == APC_F64 ? kTnF64 : precision == APC_F32 ? kTnF32 : kTnBF16;
+  P->bf16 = P->prec == APC_BF16_IR;
+  P->tq = P->prec == APC_F64 ? kTnF64 : P->prec == APC_F32 ? kTnF32 : kTnBF16;
   // FP32 k-RHS: an FP64 anchor update every kAnchorEvery updates; the bf16 inner solver
   // is corrected by the outer refinement instead (0 = never).
-  P->anchor_every = (P->gemm && precision == APC_F32) ? kAnchorEvery : 0;
+  P->anchor_every = (P->gemm && P->prec == APC_F32) ? kAnchorEvery : 0;
   if (const char* e = std::getenv("APC_ANCHOR_EVERY"))
-    if (P->gemm && precision != APC_F64) P->anchor_every = std::max(0, std::atoi(e));
+    if (P->gemm && P->prec != APC_F64) P->anchor_every = std::max(0, std::atoi(e));
   {
     // Column splits of pass A: about 4096 workgroups (16 per CU, measured best
     // for streaming at the 16384 x 8192 shape), each split at least one
     // register chunk wide.
-    const int64_t chunk = precision == APC_F32 ? rowdot_chunk<float>() : rowdot_chunk<double>();
+    const int64_t chunk = P->prec == APC_F32 ? rowdot_chunk<float>() : rowdot_chunk<double>();
     const int64_t max_split = std::max<int64_t>(1, (L.ldc + chunk - 1) / chunk);
     int64_t want = nsplit_req > 0 ? nsplit_req
                                   : (4096 + L.ntiles_a - 1) / std::max<int32_t>(L.ntiles_a, 1);
@@ -1201,10 +1208,10 @@ apc_status solve_refined(apc_plan_s* p, double rtol, int32_t max_iters, int32_t*
     if (p->kp > p->k)
       HIP_TRY(launch_fill_u32(reinterpret_cast<unsigned*>(Rb + static_cast<int64_t>(p->k) * p->N),
                               2 * (p->kp - p->k) * p->N, 0u, p->stream));
-    HIP_TRY(launch_linv_apply(p->doff(), p->at<int64_t>(L.goff), p->m, p->at<double>(L.Linv), Rb,
-                              p->N, cw, p->N, p->kp, p->stream));
-    HIP_TRY(launch_linv_apply(p->doff(), p->at<int64_t>(L.goff), p->m, p->at<double>(L.Linv2), cw,
-                              p->N, Rb, p->N, p->kp, p->stream));
+    HIP_TRY(launch_linv_apply(p->doff(), p->at<int64_t>(L.goff), p->m, p->pmax,
+                              p->at<double>(L.Linv), Rb, p->N, cw, p->N, p->kp, 0, 1.0, p->stream));
+    HIP_TRY(launch_linv_apply(p->doff(), p->at<int64_t>(L.goff), p->m, p->pmax,
+                              p->at<double>(L.Linv2), cw, p->N, Rb, p->N, p->kp, 0, 1.0, p->stream));
     ST_TRY(start_gemm(p, Rb));
   }
   *done_out = done;
@@ -1266,7 +1273,7 @@ apc_status apc_get_local(apc_plan p, double* X, int64_t ldx) {
     HIP_TRY(launch_copy_strided(p->x(), p->L.ldc, X, ldx, p->m, p->n, p->stream));
     return APC_OK;
   }
-  if (ldx < p->k) return fail(APC_EINVAL, "ldx < k");
+  if (ldx < (p->k == 1 ? p->n : p->k)) return fail(APC_EINVAL, "ldx < k (k = 1: ldx < n)");
   // x_i(t) = x_i(0) + P_i y(t) = y + Q_i (c_i - Q_i^T y), per right-hand side,
   // in FP64 on the FP64 factor.
   const Layout& L = p->L;
@@ -1281,9 +1288,12 @@ apc_status apc_get_local(apc_plan p, double* X, int64_t ldx) {
     HIP_TRY(launch_axpy(p->N, -1.0, w, r, p->stream));
     HIP_TRY(launch_copy_strided(y, 0, Y, L.ldc, p->m, L.ldc, p->stream));
     ST_TRY(expand_blocks(p, r, Y, 1.0, 1.0));
-    for (int i = 0; i < p->m; ++i)
-      HIP_TRY(launch_copy_t(Y + static_cast<int64_t>(i) * L.ldc, 0, X + i * p->n * ldx + col, ldx,
+    for (int i = 0; i < p->m; ++i) {
+      // k = 1: row i at X + i*ldx; k > 1: entry (i, j, c) at X[(i*n + j)*ldx + c].
+      double* dst = p->k == 1 ? X + i * ldx : X + i * p->n * ldx + col;
+      HIP_TRY(launch_copy_t(Y + static_cast<int64_t>(i) * L.ldc, 0, dst, p->k == 1 ? 1 : ldx,
                             p->n, 1, p->stream));
+    }
   }
   return APC_OK;
 }
@@ -1373,6 +1383,219 @@ apc_status apc_set_anchor(apc_plan p, int32_t every) {
   if (p->since_start != 0)
     return fail(APC_EINVAL, "set the anchor spacing before the first update after setup");
   p->anchor_every = every;
+  return APC_OK;
+}
+
+apc_status apc_set_params(apc_plan p, double gamma, double eta) {
+  if (!p) return fail(APC_EINVAL, "plan is NULL");
+  if (!std::isfinite(gamma) || !std::isfinite(eta))
+    return fail(APC_EINVAL, "gamma and eta must be finite");
+  p->gamma = gamma;
+  p->eta = eta;
+  return APC_OK;
+}
+
+namespace {
+
+// New right-hand sides (or the stored ones): c = L2^{-1} L1^{-1} b per block,
+// then the start of Alg. 1 again.
+apc_status restart_impl(apc_plan_s* P, const double* B, int64_t ldb) {
+  const Layout& L = P->L;
+  hipStream_t st = P->stream;
+  if (B) {
+    P->B = B;
+    P->ldb = ldb;
+    double* cb = P->at<double>(L.cb);
+    double* ca = P->at<double>(L.ca);
+    // RHS-major copy of B (columns k..kp zero), then the two inverse factors.
+    HIP_TRY(launch_tn_pack(kTnF64, B, ldb, P->N, P->k, 1, cb, P->N, P->kp, st));
+    HIP_TRY(launch_linv_apply(P->doff(), P->at<int64_t>(L.goff), P->m, P->pmax,
+                              P->at<double>(L.Linv), cb, P->N, ca, P->N, P->kp, 0, 1.0, st));
+    HIP_TRY(launch_linv_apply(P->doff(), P->at<int64_t>(L.goff), P->m, P->pmax,
+                              P->at<double>(L.Linv2), ca, P->N, cb, P->N, P->kp, 0, 1.0, st));
+    HIP_TRY(launch_copy_strided(cb, 1, ca, 1, static_cast<int64_t>(P->kp) * P->N, 1, st));
+    ST_TRY(residual_norm2(P, nullptr, P->at<double>(L.scal) + 1));
+    double b2 = 0;
+    HIP_TRY(hipMemcpyAsync(&b2, P->at<double>(L.scal) + 1, sizeof b2, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    P->bnorm = std::sqrt(b2);
+  }
+  const double* ca = P->at<double>(L.ca);
+  if (P->gemm) {
+    if (P->bf16)
+      HIP_TRY(launch_fill_u32(P->at<unsigned>(L.Xs), 2 * static_cast<int64_t>(P->kp) * L.np, 0u, st));
+    ST_TRY(start_gemm(P, ca));
+  } else {
+    ExpandArgs<double> e{P->C64(), L.ldc, P->doff(), P->m,
+                         static_cast<int32_t>((L.ldc + expand_slab(8) - 1) / expand_slab(8)), P->N,
+                         ca, 1, 0, P->x(), P->state_ld(), 1.0, 0.0, 0};
+    HIP_TRY(launch_expand_f64(e, st));
+    ST_TRY(average(P, 1.0 / P->m, 0.0));
+  }
+  P->iters = 0;
+  P->refinements = 0;
+  return APC_OK;
+}
+
+// Slices of the caller's backward workspace.
+struct BwdLayout {
+  size_t ck, seg, a, bh, g0, bq, red, total;
+};
+
+BwdLayout bwd_layout(const apc_plan_s* P, int32_t T, int32_t ckpt) {
+  BwdLayout B{};
+  const int64_t st = static_cast<int64_t>(P->kp) * P->L.np * 8;  // one FP64 state vector set
+  const int64_t nck = T > 0 ? (T + ckpt - 1) / ckpt : 0;
+  const int64_t sq = P->tq == kTnF64 ? 8 : 4;
+  size_t cur = 0;
+  auto take = [&](int64_t bytes) {
+    const size_t at = cur;
+    cur += static_cast<size_t>(round_up(std::max<int64_t>(bytes, 1), kAlign));
+    return at;
+  };
+  B.ck = take((nck + 1) * 2 * st);             // (y, x_bar) at t = 0, ckpt, 2 ckpt, ... and T
+  B.seg = take((std::min<int64_t>(ckpt, std::max(T, 1)) + 1) * 2 * st);  // one segment
+  B.a = take(st);
+  B.bh = take(st);
+  B.g0 = take(st);
+  B.bq = take(static_cast<int64_t>(P->kp) * P->L.np * sq);
+  B.red = take(2 * static_cast<int64_t>(tn_adjoint_blocks()) * 8);
+  B.total = cur;
+  return B;
+}
+
+apc_status copy_state(apc_plan_s* P, double* y_dst, double* xb_dst, const double* y_src,
+                      const double* xb_src) {
+  const int64_t cnt = static_cast<int64_t>(P->kp) * P->L.np;
+  HIP_TRY(launch_copy_strided(y_src, 1, y_dst, 1, cnt, 1, P->stream));
+  HIP_TRY(launch_copy_strided(xb_src, 1, xb_dst, 1, cnt, 1, P->stream));
+  return APC_OK;
+}
+
+// Put a saved (y, x_bar) back as the plan's state; the next update is an
+// anchor update when anchoring is on, else its operand is formed here.
+apc_status restore_state(apc_plan_s* P, const double* y, const double* xb) {
+  const Layout& L = P->L;
+  ST_TRY(copy_state(P, P->at<double>(L.ys), P->xbar(), y, xb));
+  HIP_TRY(launch_tn_prep(P->tq, P->at<double>(L.ys), P->xbar(),
+                         static_cast<int64_t>(P->kp) * L.np, P->gamma, P->ws + L.yq, P->stream));
+  P->since_start = 0;
+  return APC_OK;
+}
+
+}  // namespace
+
+apc_status apc_restart(apc_plan p, const double* B, int64_t ldb) {
+  if (!p) return fail(APC_EINVAL, "plan is NULL");
+  if (B && ldb < (p->k == 1 ? 1 : p->k)) return fail(APC_EINVAL, "ldb < k");
+  return restart_impl(p, B, ldb);
+}
+
+size_t apc_backward_workspace_bytes(apc_plan p, int32_t T, int32_t ckpt_every) {
+  if (!p || !p->gemm || T < 0 || ckpt_every < 1) return 0;
+  return bwd_layout(p, T, ckpt_every).total;
+}
+
+apc_status apc_backward(apc_plan p, const double* dXbar, int64_t ldd, int32_t T,
+                        int32_t ckpt_every, double* dB, int64_t lddb, double* dgamma, double* deta,
+                        void* bwd_ws, size_t bwd_bytes) {
+  if (!p || !dXbar || !dB) return fail(APC_EINVAL, "NULL argument");
+  if (!p->gemm || p->bf16)
+    return fail(APC_EUNSUPPORTED, "the adjoint needs an FP64/FP32 plan in the (y, x_bar) form "
+                "(k > 1 or APC_REDUCED_FORM)");
+  if (T < 0 || ckpt_every < 1) return fail(APC_EINVAL, "need T >= 0 and ckpt_every >= 1");
+  const int64_t kmin = p->k == 1 ? 1 : p->k;
+  if (ldd < kmin || lddb < kmin) return fail(APC_EINVAL, "ldd and lddb must be >= k");
+  const BwdLayout BL = bwd_layout(p, T, ckpt_every);
+  if (!bwd_ws || bwd_bytes < BL.total)
+    return fail(APC_EINVAL, "backward workspace has %zu bytes, needs %zu", bwd_bytes, BL.total);
+  if (reinterpret_cast<uintptr_t>(bwd_ws) % kAlign != 0)
+    return fail(APC_EINVAL, "backward workspace must be 256-byte aligned");
+  apc_plan_s* P = p;
+  const Layout& L = P->L;
+  hipStream_t st = P->stream;
+  char* bw = static_cast<char*>(bwd_ws);
+  const int64_t cnt = static_cast<int64_t>(P->kp) * L.np;
+  auto ck = [&](int64_t s) { return reinterpret_cast<double*>(bw + BL.ck) + 2 * s * cnt; };
+  auto seg = [&](int64_t s) { return reinterpret_cast<double*>(bw + BL.seg) + 2 * s * cnt; };
+  double* a = reinterpret_cast<double*>(bw + BL.a);
+  double* bh = reinterpret_cast<double*>(bw + BL.bh);
+  double* g0 = reinterpret_cast<double*>(bw + BL.g0);
+  void* bq = bw + BL.bq;
+  double* red = reinterpret_cast<double*>(bw + BL.red);
+  double* ys = P->at<double>(L.ys);
+  double* xb = P->xbar();
+  const int64_t nck = T > 0 ? (T + ckpt_every - 1) / ckpt_every : 0;
+
+  // Forward from the start, keeping (y, x_bar) every ckpt_every updates and at T.
+  ST_TRY(restart_impl(P, nullptr, 0));
+  for (int32_t t = 0; t < T; ++t) {
+    if (t % ckpt_every == 0) ST_TRY(copy_state(P, ck(t / ckpt_every), ck(t / ckpt_every) + cnt, ys, xb));
+    ST_TRY(update(P, nullptr, nullptr, nullptr));
+  }
+  ST_TRY(copy_state(P, ck(nck), ck(nck) + cnt, ys, xb));
+
+  // Adjoint start: dL/dx_bar(T) = dXbar, dL/dy(T) = 0.
+  HIP_TRY(launch_fill_u32(reinterpret_cast<unsigned*>(a), 2 * cnt, 0u, st));
+  HIP_TRY(launch_fill_u32(reinterpret_cast<unsigned*>(g0), 2 * cnt, 0u, st));
+  HIP_TRY(launch_fill_u32(reinterpret_cast<unsigned*>(red), 4 * tn_adjoint_blocks(), 0u, st));
+  HIP_TRY(launch_tn_pack(kTnF64, dXbar, ldd, P->n, P->k, 1, bh, L.np, P->kp, st));
+  HIP_TRY(launch_tn_prep(P->tq, a, bh, cnt, 1.0, bq, st));  // bq = TQ(bh)
+
+  void* part = P->ws + L.tnpart;
+  for (int64_t sgi = nck - 1; sgi >= 0; --sgi) {
+    const int32_t t0 = static_cast<int32_t>(sgi * ckpt_every);
+    const int32_t t1 = std::min(T, t0 + ckpt_every);
+    // Recompute the segment's states.
+    ST_TRY(restore_state(P, ck(sgi), ck(sgi) + cnt));
+    ST_TRY(copy_state(P, seg(0), seg(0) + cnt, ys, xb));
+    for (int32_t t = t0; t < t1; ++t) {
+      ST_TRY(update(P, nullptr, nullptr, nullptr));
+      ST_TRY(copy_state(P, seg(t - t0 + 1), seg(t - t0 + 1) + cnt, ys, xb));
+    }
+    // Reverse through it: X bh by the same two contractions as an update.
+    for (int32_t t = t1 - 1; t >= t0; --t) {
+      TnArgs pa = tn_args(P->ws + L.Cq, L.np, L.Np, bq, L.np, P->kp, L.np, P->tnA, P->tq, part, L.Np);
+      HIP_TRY(launch_tn(P->tq, P->tnA.rt, pa, st));
+      HIP_TRY(launch_tn_sum_cast(P->tq, part, P->tnA.nsplit, P->kp, L.Np, L.Np, P->ws + L.Wq, L.Np, st));
+      HIP_TRY(launch_tn(P->tq, P->tnB.rt, pass_b_args(P), st));
+      const double* s_t = seg(t - t0);
+      const double* s_n = seg(t - t0 + 1);
+      TnAdjointArgs ad{part, P->tnB.nsplit, P->kp, L.np, L.np, a, bh, g0, s_t, s_t + cnt,
+                       s_n + cnt, L.np, bq, L.np, P->gamma, P->eta, 1.0 / P->m, red};
+      HIP_TRY(launch_tn_adjoint(P->tq, ad, st));
+    }
+  }
+  // x_bar(0) = x0 itself: its adjoint gets dL/dx_bar(0) too.
+  HIP_TRY(launch_axpy(cnt, 1.0, bh, g0, st));
+  // dL/dc = (1/m) C g0 in FP64, then dL/db_i = L1^{-T} L2^{-T} dL/dc_i.
+  const void* C64 = P->tq == kTnF64 ? static_cast<const void*>(P->ws + L.Cq)
+                                    : static_cast<const void*>(P->ws + L.C64p);
+  double* W64 = P->tq == kTnF64 ? P->at<double>(L.Wq) : P->at<double>(L.W64);
+  TnArgs pc = tn_args(C64, L.np, L.Np, g0, L.np, P->kp, L.np, P->tnR, kTnF64, part, L.Np);
+  HIP_TRY(launch_tn(kTnF64, P->tnR.rt, pc, st));
+  HIP_TRY(launch_tn_sum_cast(kTnF64, part, P->tnR.nsplit, P->kp, L.Np, L.Np, W64, L.Np, st));
+  double* t1b = P->at<double>(L.Rb);
+  double* t2b = P->at<double>(L.cb);
+  HIP_TRY(launch_linv_apply(P->doff(), P->at<int64_t>(L.goff), P->m, P->pmax,
+                            P->at<double>(L.Linv2), W64, L.Np, t1b, P->N, P->kp, 1, 1.0 / P->m, st));
+  HIP_TRY(launch_linv_apply(P->doff(), P->at<int64_t>(L.goff), P->m, P->pmax,
+                            P->at<double>(L.Linv), t1b, P->N, t2b, P->N, P->kp, 1, 1.0, st));
+  HIP_TRY(launch_copy_t(t2b, P->N, dB, lddb, P->N, P->k, st));
+  // The plan is left at x_bar(T) of the forward run.
+  ST_TRY(restore_state(P, ck(nck), ck(nck) + cnt));
+  P->since_start = 0;
+  P->iters = T;
+  std::vector<double> hr(2 * static_cast<size_t>(tn_adjoint_blocks()));
+  HIP_TRY(hipMemcpyAsync(hr.data(), red, hr.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  double sg = 0.0, se = 0.0;
+  for (int b = 0; b < tn_adjoint_blocks(); ++b) {
+    sg += hr[2 * b];
+    se += hr[2 * b + 1];
+  }
+  if (dgamma) *dgamma = sg;
+  if (deta) *deta = se;
   return APC_OK;
 }
 

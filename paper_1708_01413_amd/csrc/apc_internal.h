@@ -169,6 +169,42 @@ struct TnUpdateArgs {
 hipError_t launch_tn_anchor_vec(const double* y, const double* xb, int64_t count, double gamma,
                                 double* yref, hipStream_t s);
 hipError_t launch_tn_update(int type, int part_f64, const TnUpdateArgs& a, hipStream_t s);
+// yq = TQ((1 - gamma) y + gamma x_bar), count entries (the pass-A operand for a
+// restored state).
+hipError_t launch_tn_prep(int type, const double* y, const double* xb, int64_t count, double gamma,
+                          void* yq, hipStream_t s);
+
+// One reverse step of the (y, x_bar) iteration (FP64 adjoints a = dL/dy(t+1),
+// bh = dL/dx_bar(t+1); z = the summed partials of C^T C b_q, so X bh = z / m):
+//   at = a + eta (bh - X bh)            (the adjoint of y(t+1), both paths)
+//   dL/dgamma += <at, x_bar(t) - y(t)>,  dL/deta += <bh, x_bar(t+1) - x_bar(t)> / eta
+//   g0 += eta bh                        (the adjoint of x_bar(0) through eq. (2b))
+//   a <- (1 - gamma) at,  bh <- (1 - eta) bh + gamma at,  bq = TQ(bh)
+// over c < kp, j < n (stride ldx); red holds 2 running sums per workgroup.
+struct TnAdjointArgs {
+  const void* part;
+  int32_t nsplit;
+  int32_t kp;
+  int64_t ldp;
+  int64_t n;
+  double* a;
+  double* bh;
+  double* g0;
+  const double* y_t;
+  const double* xb_t;
+  const double* xb_next;
+  int64_t ldx;
+  void* bq;
+  int64_t ldq;
+  double gamma;
+  double eta;
+  double inv_m;
+  double* red;
+};
+constexpr int kTnAdjointBlocks = 512;
+int tn_adjoint_blocks();
+hipError_t launch_tn_adjoint(int type, const TnAdjointArgs& a, hipStream_t s);
+
 // R[c*ldr + r] = B[r*ldb + c] - sum of the FP64 partials, r < N, c < k.
 hipError_t launch_tn_resid(const double* part, int32_t nsplit, int32_t kp, int64_t ldp, int64_t N,
                            int32_t k, const double* B, int64_t ldb, double* R, int64_t ldr,
@@ -178,10 +214,11 @@ hipError_t launch_tn_resid(const double* part, int32_t nsplit, int32_t kp, int64
 hipError_t launch_tn_pack(int type, const double* src, int64_t lds, int64_t srows, int64_t scols,
                           int32_t transpose, void* dst, int64_t ldd, int64_t drows, hipStream_t s);
 
-// Per block: out[col*ldo + r0 + r] = sum_{q<=r} Linv_i[r][q] in[col*ldi + r0 + q], col < kc.
-hipError_t launch_linv_apply(const int64_t* off, const int64_t* goff, int32_t m, const double* Linv,
-                             const double* in, int64_t ldi, double* out, int64_t ldo, int32_t kc,
-                             hipStream_t s);
+// Per block: out[col*ldo + r0 + r] = scale * sum_q Lop[r][q] in[col*ldi + r0 + q], col < kc,
+// with Lop = Linv_i (q <= r) or, when trans, Linv_i^T (q >= r); pmax = max p_i.
+hipError_t launch_linv_apply(const int64_t* off, const int64_t* goff, int32_t m, int64_t pmax,
+                             const double* Linv, const double* in, int64_t ldi, double* out,
+                             int64_t ldo, int32_t kc, int32_t trans, double scale, hipStream_t s);
 hipError_t launch_axpy(int64_t count, double alpha, const double* x, double* y, hipStream_t s);
 hipError_t launch_sumsq(const double* src, int64_t count, double* partial, hipStream_t s);
 int sumsq_parts();

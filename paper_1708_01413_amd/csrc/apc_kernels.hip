@@ -215,24 +215,73 @@ __global__ __launch_bounds__(kThreads) void k_pass_b(PassBArgs<TQ> a) {
 
 // ------------------------------------------------------------------ FP64 refinement
 
-// Per block: out[col * ldo + r0 + r] = sum_{q <= r} Linv_i[r][q] in[col * ldi + r0 + q].
-__global__ __launch_bounds__(256) void k_linv_apply(const int64_t* off, const int64_t* goff,
-                                                    const double* Linv, const double* in,
-                                                    int64_t ldi, double* out, int64_t ldo,
-                                                    int32_t kc) {
-  const int blk = blockIdx.x;
+// Per block i: out[c*ldo + r0 + r] = scale * sum_q Lop[r][q] in[c*ldi + r0 + q] for
+// r < p_i, c < kc, with Lop = Linv_i (lower triangular, q <= r) or, for TRANS,
+// Linv_i^T (q >= r).  Grid: (row tiles of 64) x (column tiles of 64) x blocks;
+// 16 x 16 threads, 4 x 4 outputs each, 32-wide K chunks staged in LDS.
+template <bool TRANS>
+__global__ __launch_bounds__(256) void k_tri_apply(const int64_t* off, const int64_t* goff,
+                                                   const double* Linv, const double* in,
+                                                   int64_t ldi, double* out, int64_t ldo,
+                                                   int32_t kc, double scale) {
+  const int blk = blockIdx.z;
   const int64_t r0 = off[blk];
   const int p = static_cast<int>(off[blk + 1] - r0);
+  const int rt0 = blockIdx.x * 64, ct0 = blockIdx.y * 64;
+  if (rt0 >= p || ct0 >= kc) return;
   const double* Lb = Linv + goff[blk];
-  for (int e = threadIdx.x; e < p * kc; e += blockDim.x) {
-    const int r = e % p;
-    const int64_t col = e / p;
-    double s = 0.0;
-    for (int q = 0; q <= r; ++q) s += Lb[static_cast<int64_t>(r) * p + q] * in[col * ldi + r0 + q];
-    out[col * ldo + r0 + r] = s;
+  __shared__ double Ls[64][33];
+  __shared__ double Is[32][65];
+  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+  double acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
+  const int qbeg = TRANS ? rt0 : 0;
+  const int qend = TRANS ? p : min(p, rt0 + 64);
+  for (int q0 = qbeg; q0 < qend; q0 += 32) {
+    for (int e = threadIdx.x; e < 64 * 32; e += 256) {
+      int rr, qq;
+      if (TRANS) { rr = e & 63; qq = e >> 6; }  // Linv[q][r]: consecutive r
+      else { qq = e & 31; rr = e >> 5; }        // Linv[r][q]: consecutive q
+      const int r = rt0 + rr, q = q0 + qq;
+      double v = 0.0;
+      if (r < p && q < qend && (TRANS ? q >= r : q <= r))
+        v = TRANS ? Lb[static_cast<int64_t>(q) * p + r] : Lb[static_cast<int64_t>(r) * p + q];
+      Ls[rr][qq] = v;
+    }
+    for (int e = threadIdx.x; e < 32 * 64; e += 256) {
+      const int qq = e & 31, cc = e >> 5;
+      const int q = q0 + qq, c = ct0 + cc;
+      Is[qq][cc] = (q < qend && c < kc) ? in[static_cast<int64_t>(c) * ldi + r0 + q] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll 4
+    for (int qq = 0; qq < 32; ++qq) {
+      double av[4], bv[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) av[i] = Ls[tx * 4 + i][qq];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) bv[j] = Is[qq][ty * 4 + j];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] += av[i] * bv[j];
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int c = ct0 + ty * 4 + j;
+    if (c >= kc) continue;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int r = rt0 + tx * 4 + i;
+      if (r < p) out[static_cast<int64_t>(c) * ldo + r0 + r] = scale * acc[i][j];
+    }
   }
 }
-
 
 // y[e] = alpha * x[e] + y[e].
 __global__ void k_axpy(int64_t count, double alpha, const double* x, double* y) {
@@ -716,10 +765,15 @@ static hipError_t expand_impl(const ExpandArgs<TQ>& a, hipStream_t s) {
 hipError_t launch_expand_f64(const ExpandArgs<double>& a, hipStream_t s) { return expand_impl(a, s); }
 hipError_t launch_expand_f32(const ExpandArgs<float>& a, hipStream_t s) { return expand_impl(a, s); }
 
-hipError_t launch_linv_apply(const int64_t* off, const int64_t* goff, int32_t m, const double* Linv,
-                             const double* in, int64_t ldi, double* out, int64_t ldo, int32_t kc,
-                             hipStream_t s) {
-  hipLaunchKernelGGL(k_linv_apply, dim3(m), dim3(256), 0, s, off, goff, Linv, in, ldi, out, ldo, kc);
+hipError_t launch_linv_apply(const int64_t* off, const int64_t* goff, int32_t m, int64_t pmax,
+                             const double* Linv, const double* in, int64_t ldi, double* out,
+                             int64_t ldo, int32_t kc, int32_t trans, double scale, hipStream_t s) {
+  const dim3 grid(static_cast<unsigned>((pmax + 63) / 64), static_cast<unsigned>((kc + 63) / 64),
+                  static_cast<unsigned>(m));
+  if (trans)
+    k_tri_apply<true><<<grid, 256, 0, s>>>(off, goff, Linv, in, ldi, out, ldo, kc, scale);
+  else
+    k_tri_apply<false><<<grid, 256, 0, s>>>(off, goff, Linv, in, ldi, out, ldo, kc, scale);
   return hipGetLastError();
 }
 

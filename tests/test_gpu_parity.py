@@ -582,3 +582,161 @@ def test_bf16_inner_solve_contracts():
     r1 = plan.residual()
     say(f"case: bf16 inner solve relres {r0:.2e} -> {r1:.2e}")
     assert r1 < 1e-2 * r0
+
+
+# ---------------------------------------------------------------- differentiation
+
+
+def test_restart_and_set_params_reproduce_fresh_plans():
+    """apc_restart(B2) + apc_set_params(g, e) give the trajectory of a plan set up on B2
+    with (g, e): same factor, so FP64 results agree to rounding."""
+    apc = _apc()
+    torch = _torch()
+    S = synth.gaussian_system(600, 400, 6, k=5, seed=50, scale=1 / math.sqrt(400))
+    A, b = upload(S)
+    b2 = torch.from_numpy(np.random.default_rng(51).standard_normal(S.B.shape)).to(A.device)
+    plan = apc.Plan(A, b, S.off, "f64")
+    g, e = plan.params()["gamma"] * 0.97, plan.params()["eta"] * 0.9
+    plan.iterate(7)
+    plan.set_params(g, e)
+    plan.restart(b2)
+    assert plan.iterations == 0
+    plan.iterate(30)
+    fresh = apc.Plan(A, b2, S.off, "f64", gamma=g, eta=e)
+    fresh.iterate(30)
+    dev = float(torch.linalg.norm(plan.xbar() - fresh.xbar()) / torch.linalg.norm(fresh.xbar()))
+    say(f"case: restart/set_params dev {dev:.2e}")
+    assert dev <= 1e-13
+
+
+@pytest.mark.parametrize("N,n,m,k,T,ckpt,reduced", [(300, 200, 7, 3, 25, 4, False),
+                                                    (256, 256, 4, 1, 20, 5, True),
+                                                    (512, 384, 8, 20, 16, 16, False)])
+def test_backward_matches_oracle_adjoint(N, n, m, k, T, ckpt, reduced):
+    """FP64 plan: dL/dB, dL/dgamma, dL/deta from apc_backward against the oracle's
+    literal-form adjoint on the same inputs and (gamma, eta)."""
+    apc = _apc()
+    torch = _torch()
+    S = synth.gaussian_system(N, n, m, k=k, seed=52 + k, scale=1 / math.sqrt(n),
+                              shift=1.5 if N == n else 0.0)
+    g, e, _ = O.optimal_params(*O.spectrum(S.A, S.off))
+    dx = np.random.default_rng(60 + k).standard_normal((n, k) if k > 1 else (n,))
+    dB_ref, dg_ref, de_ref = O.apc_adjoint(S.A, S.B, S.off, T, g, e, dx)
+    A, b = upload(S)
+    plan = apc.Plan(A, b, S.off, "f64", gamma=g, eta=e, reduced_form=reduced)
+    dB, dg, de = plan.backward(torch.from_numpy(dx).to(A.device), T, ckpt)
+    dB = dB.cpu().numpy().reshape(dB_ref.shape)
+    rel_b = np.linalg.norm(dB - dB_ref) / np.linalg.norm(dB_ref)
+    say(f"case: backward f64 N={N} n={n} k={k} T={T}: dB rel {rel_b:.2e}, dgamma {dg:.6e} vs "
+        f"{dg_ref:.6e}, deta {de:.6e} vs {de_ref:.6e}")
+    assert rel_b <= 1e-10
+    scale = np.linalg.norm(dx) * np.linalg.norm(S.xstar)
+    assert abs(dg - dg_ref) <= 1e-9 * max(abs(dg_ref), scale)
+    assert abs(de - de_ref) <= 1e-9 * max(abs(de_ref), scale)
+    assert plan.iterations == T
+
+
+def test_backward_fp32_converged_gradient_and_differences():
+    """N = n = 4096, A = G/sqrt(n) + 2I, k = 16, m = 32 blocks of 128, FP32, T = 200 with a
+    checkpoint every 14 updates, L = 1/2 ||x_bar(T) - x_target||^2.  At T = 200 the
+    iteration has converged: dL/dB = A^{-T} (x_bar(T) - x_target) and dL/dgamma, dL/deta
+    ~ 0.  At T = 10 (before convergence): the FP64 adjoint against central differences
+    of the FP64 forward (h = 1e-5, and h = 1e-3 within that difference's own Richardson
+    truncation estimate), the FP32 adjoint against the FP64 one, and dL/dB along a
+    direction (exact: L is quadratic in B)."""
+    apc = _apc()
+    torch = _torch()
+    S = synth.shifted_square(4096, 32, k=16, shift=2.0, seed=70, with_target=True)
+    A, b = upload(S)
+    dev = A.device
+    xt = torch.from_numpy(S.extra["x_target"]).to(dev)
+    p32 = apc.Plan(A, b, S.off, "f32")
+    g, e = p32.params()["gamma"], p32.params()["eta"]
+    p32.iterate(200)
+    r = p32.xbar() - xt
+    dB, dg, de = p32.backward(r, 200, 14)
+    ref = torch.linalg.solve(A.T.contiguous(), r)
+    rel = float(torch.linalg.norm(dB - ref) / torch.linalg.norm(ref))
+    scale = float(torch.linalg.norm(r) * torch.linalg.norm(p32.xbar()))
+    say(f"case: adjoint T=200: dB vs A^-T r rel {rel:.2e}; dgamma {dg:.2e}, deta {de:.2e} "
+        f"(scale {scale:.2e})")
+    assert rel <= 1e-5
+    assert abs(dg) <= 1e-6 * scale and abs(de) <= 1e-6 * scale
+    # Before convergence: FP64 forward differences.
+    T = 10
+    p64 = apc.Plan(A, b, S.off, "f64", gamma=g, eta=e)
+
+    def loss(gg, ee, bb=None):
+        p64.set_params(gg, ee)
+        p64.restart(bb if bb is not None else b)
+        p64.iterate(T)
+        return 0.5 * float(torch.linalg.norm(p64.xbar() - xt) ** 2)
+
+    p32.set_params(g, e)
+    p32.restart(b)
+    p32.iterate(T)
+    r10 = p32.xbar() - xt
+    dB10, dg10, de10 = p32.backward(r10, T, 3)
+    p64.set_params(g, e)
+    p64.restart(b)
+    p64.iterate(T)
+    _, dg64, de64 = p64.backward(p64.xbar() - xt, T, 3)
+    fd = {}
+    for h in (1e-3, 5e-4, 1e-5):
+        fd[h] = ((loss(g + h, e) - loss(g - h, e)) / (2 * h),
+                 (loss(g, e + h) - loss(g, e - h)) / (2 * h))
+    h = 1e-3
+    d = torch.from_numpy(np.random.default_rng(71).standard_normal(S.B.shape)).to(dev)
+    fd_b = (loss(g, e, b + h * d) - loss(g, e, b - h * d)) / (2 * h)
+    dir_b = float(torch.sum(dB10 * d))
+    say(f"case: adjoint T=10: dgamma f32 {dg10:.6e} f64 {dg64:.6e} fd(1e-3) {fd[1e-3][0]:.6e} "
+        f"fd(1e-5) {fd[1e-5][0]:.6e}; deta f32 {de10:.6e} f64 {de64:.6e} fd(1e-3) "
+        f"{fd[1e-3][1]:.6e}; dB.d {dir_b:.6e} fd {fd_b:.6e}")
+    for q, (adj64, adj32) in enumerate(((dg64, dg10), (de64, de10))):
+        # Central differences are L' + c h^2 + ...; c estimated from h = 1e-3 and h/2
+        # bounds the truncation at h = 1e-3 and, scaled by h^2, at h = 1e-5.
+        c = (fd[1e-3][q] - fd[5e-4][q]) / (1e-6 - 0.25e-6)
+        for h in (1e-3, 1e-5):
+            assert abs(adj64 - fd[h][q]) <= 2.0 * abs(c) * h * h + 1e-6 * abs(fd[h][q])
+        # FP32 products in the FP32 plan's adjoint.
+        assert abs(adj32 - adj64) <= 1e-4 * abs(adj64)
+    assert abs(dir_b - fd_b) <= 1e-4 * abs(fd_b)
+
+
+def test_autograd_function_matches_oracle():
+    """torch.autograd through unrolled_apc (FP64 plan) gives the oracle adjoint of
+    L = 1/2 ||x_bar(T) - x_target||^2 for b, gamma and eta."""
+    apc = _apc()
+    torch = _torch()
+    S = synth.shifted_square(384, 6, k=4, shift=1.5, seed=72, with_target=True)
+    A, b = upload(S)
+    T = 12
+    g0, e0, _ = O.optimal_params(*O.spectrum(S.A, S.off))
+    plan = apc.Plan(A, b, S.off, "f64")
+    bb = b.clone().requires_grad_(True)
+    gg = torch.tensor(g0, dtype=torch.float64, requires_grad=True)
+    ee = torch.tensor(e0, dtype=torch.float64, requires_grad=True)
+    x = apc.unrolled_apc(plan, bb, gg, ee, T, ckpt_every=5)
+    xt = torch.from_numpy(S.extra["x_target"]).to(A.device)
+    loss = 0.5 * torch.sum((x - xt) ** 2)
+    loss.backward()
+    xr = O.apc_run(S.A, S.B, S.off, T, g0, e0)["xbar"]
+    dB_ref, dg_ref, de_ref = O.apc_adjoint(S.A, S.B, S.off, T, g0, e0, xr - S.extra["x_target"])
+    rel = np.linalg.norm(bb.grad.cpu().numpy() - dB_ref) / np.linalg.norm(dB_ref)
+    say(f"case: autograd: dB rel {rel:.2e}, dgamma {float(gg.grad):.6e} vs {dg_ref:.6e}, "
+        f"deta {float(ee.grad):.6e} vs {de_ref:.6e}")
+    assert rel <= 1e-10
+    assert abs(float(gg.grad) - dg_ref) <= 1e-9 * abs(dg_ref)
+    assert abs(float(ee.grad) - de_ref) <= 1e-9 * abs(de_ref)
+
+
+def test_backward_unsupported_plans():
+    apc = _apc()
+    torch = _torch()
+    S = synth.shifted_square(256, 4, k=1, seed=73)
+    A, b = upload(S)
+    for prec, kw in (("f64", {}), ("bf16_ir", {})):
+        plan = apc.Plan(A, b, S.off, prec, **kw)
+        with pytest.raises(apc.ApcError) as ex:
+            plan.backward(torch.zeros(256, dtype=torch.float64, device=A.device), 5, 2)
+        assert ex.value.status in (apc.APC_EUNSUPPORTED,)
