@@ -200,6 +200,73 @@ def krhs_rates(apc, A, b, off, prec, ws, T=16):
     return out
 
 
+def many_systems(apc, synth, dev, count=256):
+    """256 independent square systems (n uniform in [64, 1024], m in {4, 8, 16},
+    A = G/sqrt(n) + 2I, one RHS each): one persistent launch per pass for all of them,
+    against the same plans iterated one after another."""
+    import torch
+    systems = synth.many_small_systems(count=count, seed=0)
+    stream = torch.cuda.Stream(device=dev)
+    t0 = time.perf_counter()
+    plans, keep = [], []
+    for S in systems:
+        A = torch.from_numpy(S.A).to(dev)
+        b = torch.from_numpy(S.B).to(dev)
+        keep.append((A, b))
+        plans.append(apc.Plan(A, b, S.off, "f32", stream=stream))
+    setup_s = time.perf_counter() - t0
+    batch = apc.Batch(plans)
+    # Bytes an update must move, summed over systems (as the k = 1 FP32 path).
+    per_update = sum(2 * S.N * S.n * 4 + 3 * S.m * S.n * 8 for S in systems)
+    T = 20
+
+    def timed(fn):
+        stream.synchronize()
+        t = time.perf_counter()
+        fn()
+        stream.synchronize()
+        return (time.perf_counter() - t) / T
+
+    batch.iterate(T, graph=True)                      # capture + warm
+    t_graph = timed(lambda: batch.iterate(T, graph=True))
+    t_eager = timed(lambda: batch.iterate(T, graph=False))
+
+    def one_by_one():
+        for p in plans:
+            p.iterate(T)
+    t_seq = timed(one_by_one)
+    # Fresh start, then per-system stopping at relative residual 1e-7.
+    for p in plans:
+        p.restart()
+    batch.activate()
+    stream.synchronize()
+    t = time.perf_counter()
+    iters, rr, st = batch.solve(1e-7, 400, check_every=8, graph=True)
+    stream.synchronize()
+    solve_ms = (time.perf_counter() - t) * 1e3
+    errs = [float(torch.linalg.norm(p.xbar() - torch.from_numpy(S.xstar).to(dev))
+                  / np.linalg.norm(S.xstar)) for p, S in zip(plans, systems)]
+    res = {
+        "workload": f"{count} systems, n in [64, 1024], m in {{4, 8, 16}}, A = G/sqrt(n)+2I, "
+                    "k = 1 each, FP32 projections",
+        "sum_n2": int(sum(S.n * S.n for S in systems)),
+        "launch": batch.launch(),
+        "setup_s_all_plans": round(setup_s, 2),
+        "us_per_update_graph": round(t_graph * 1e6, 1),
+        "us_per_update_eager": round(t_eager * 1e6, 1),
+        "us_per_update_one_plan_at_a_time": round(t_seq * 1e6, 1),
+        "algorithmic_bytes_per_update": per_update,
+        "GBs_graph": round(per_update / t_graph / 1e9, 1),
+        "solve_to_relres_1e-7": {"status": apc.STATUS_NAMES.get(st, st), "ms": round(solve_ms, 2),
+                                 "updates_min": int(iters.min()), "updates_max": int(iters.max()),
+                                 "max_rel_err": max(errs)},
+    }
+    batch.close()
+    for p in plans:
+        p.close()
+    return res
+
+
 def secondary(apc, synth, dev):
     """Batched and mixed-precision workloads, each against plain FP32 on the same inputs."""
     import torch
@@ -238,6 +305,8 @@ def secondary(apc, synth, dev):
                 "(default); plain_fp32 = every update in FP32",
     }
     del A, b, xs, ws, S
+    torch.cuda.empty_cache()
+    out["many_systems_fp32"] = many_systems(apc, synth, dev)
     torch.cuda.empty_cache()
     # Mixed precision vs plain FP32: N = n = 16384, A = G/sqrt(n) + alpha I, k = 128, m = 64.
     n, k, m = 16384, 128, 64

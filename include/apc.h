@@ -259,6 +259,63 @@ apc_status apc_backward(apc_plan p, const double* dXbar, int64_t ldd, int32_t T,
                         int32_t ckpt_every, double* dB, int64_t lddb, double* dgamma,
                         double* deta, void* bwd_ws, size_t bwd_bytes);
 
+/* ---- Many independent systems (one persistent launch per pass) ----------
+ *
+ * A batch runs eq. (2a)-(2b) for many independent systems at once: every
+ * system is a plan from apc_setup (k = 1, APC_F32, per-block form; all plans
+ * on one stream), keeping its own factor and state in its own workspace.  Per
+ * update a batch enqueues three launches for all systems together -- pass A
+ * over a work list of (system, 8-row tile) items, pass B over (system, block,
+ * column slab) items, the average over (system, column chunk) items -- each a
+ * persistent grid of a fixed number of workgroups looping over the list.  The
+ * grid is chosen at creation by timing pass A (APC_BATCH_GRID fixes it).  Each
+ * system's gamma, eta and ||b|| are captured at creation.  The plans must
+ * outlive the batch; apc_get_xbar etc. on a plan see the batch's updates. */
+typedef struct apc_batch_s* apc_batch;
+
+/* Bytes of device workspace (descriptors and work lists) for a batch of these
+ * plans; 0 when they cannot form a batch. */
+size_t apc_batch_workspace_bytes(const apc_plan* plans, int32_t count);
+
+/* Build the batch (host array of count plans; workspace device, 256-byte
+ * aligned, caller-owned).  Synchronises.  APC_EUNSUPPORTED for plans other than
+ * k = 1 FP32 per-block form, APC_EINVAL for mixed streams or a small workspace. */
+apc_status apc_batch_create(apc_batch* out, const apc_plan* plans, int32_t count, void* workspace,
+                            size_t ws_bytes);
+
+/* T updates of every active system (asynchronous). */
+apc_status apc_batch_iterate(apc_batch b, int32_t T);
+
+/* The same T updates through a hipGraph: captured on the batch's stream at the
+ * first call for this T (the stream must not be the default stream), replayed
+ * after.  Results are identical to apc_batch_iterate. */
+apc_status apc_batch_iterate_graph(apc_batch b, int32_t T);
+
+/* FP64 relative residual ||b_s - A_s x_bar_s|| / ||b_s|| of every active system
+ * into relres (host, count; inactive systems keep their last value), and
+ * deactivate each system whose residual is <= rtol or not finite (rtol < 0:
+ * none).  active (host, count, may be NULL) receives the flags.  Synchronises. */
+apc_status apc_batch_residuals(apc_batch b, double rtol, double* relres, int32_t* active);
+
+/* Mark every system active again. */
+apc_status apc_batch_activate(apc_batch b);
+
+/* Per-system stopping: check residuals every check_every updates, stop each
+ * system once its residual is <= rtol, until none is left or max_iters updates
+ * were applied.  use_graph != 0 runs the updates through apc_batch_iterate_graph.
+ * iters_out, relres_out: host arrays of count (may be NULL).  APC_ENOCONV if
+ * some system did not reach rtol.  Synchronises. */
+apc_status apc_batch_solve(apc_batch b, double rtol, int32_t max_iters, int32_t check_every,
+                           int32_t use_graph, int32_t* iters_out, double* relres_out);
+
+/* Launch shape: workgroups per persistent launch, work items per pass, and the
+ * measured pass-A time when the grid was chosen by timing.  Host pointers. */
+apc_status apc_batch_get_launch(apc_batch b, int32_t* grid, int32_t* items_a, int32_t* items_b,
+                                int32_t* items_avg, float* tuned_us);
+
+/* Release the batch (and its captured graphs). */
+void apc_batch_destroy(apc_batch b);
+
 /* Number of updates applied since setup (host). */
 int64_t apc_iterations(apc_plan p);
 

@@ -38,6 +38,9 @@ EXPORTED = (
     "apc_iterations", "apc_destroy", "apc_last_error", "apc_optimal_params",
     "apc_tridiag_extremes", "apc_get_info", "apc_get_launch", "apc_set_anchor", "apc_set_params",
     "apc_restart", "apc_backward_workspace_bytes", "apc_backward",
+    "apc_batch_workspace_bytes", "apc_batch_create", "apc_batch_iterate",
+    "apc_batch_iterate_graph", "apc_batch_residuals", "apc_batch_activate", "apc_batch_solve",
+    "apc_batch_get_launch", "apc_batch_destroy",
 )
 
 
@@ -96,6 +99,15 @@ def _load() -> ctypes.CDLL:
         "apc_restart": (i32, [vp, vp, i64]),
         "apc_backward_workspace_bytes": (ctypes.c_size_t, [vp, i32, i32]),
         "apc_backward": (i32, [vp, vp, i64, i32, i32, vp, i64, Pd, Pd, vp, ctypes.c_size_t]),
+        "apc_batch_workspace_bytes": (ctypes.c_size_t, [ctypes.POINTER(vp), i32]),
+        "apc_batch_create": (i32, [ctypes.POINTER(vp), ctypes.POINTER(vp), i32, vp, ctypes.c_size_t]),
+        "apc_batch_iterate": (i32, [vp, i32]),
+        "apc_batch_iterate_graph": (i32, [vp, i32]),
+        "apc_batch_residuals": (i32, [vp, f64, Pd, Pi]),
+        "apc_batch_activate": (i32, [vp]),
+        "apc_batch_solve": (i32, [vp, f64, i32, i32, i32, Pi, Pd]),
+        "apc_batch_get_launch": (i32, [vp, Pi, Pi, Pi, Pi, Pf]),
+        "apc_batch_destroy": (None, [vp]),
         "apc_optimal_params": (i32, [f64, f64, Pd, Pd, Pd]),
         "apc_tridiag_extremes": (i32, [Pd, Pd, i32, i32, Pd, Pd, Pd, Pd]),
         "apc_destroy": (None, [vp]),
@@ -452,3 +464,65 @@ def unrolled_apc(plan, b, gamma, eta, T: int, ckpt_every: int | None = None):
     e = eta if torch.is_tensor(eta) else torch.tensor(float(eta), dtype=torch.float64)
     ck = ckpt_every if ckpt_every is not None else max(1, int(math.isqrt(max(T, 1))))
     return UnrolledAPC.function().apply(b, g, e, plan, T, ck)
+
+
+class Batch:
+    """Many independent k = 1 FP32 plans iterated together: one persistent launch per
+    pass over a work list covering every system (apc_batch_*).  The plans must share
+    one stream and outlive the batch."""
+
+    def __init__(self, plans):
+        import torch
+        self._torch = torch
+        self.plans = list(plans)
+        self.count = len(self.plans)
+        arr = (ctypes.c_void_p * self.count)(*[p.handle for p in self.plans])
+        self._arr = arr
+        nb = int(lib.apc_batch_workspace_bytes(arr, self.count))
+        if nb == 0:
+            raise ApcError(APC_EUNSUPPORTED, lib.apc_last_error().decode(errors="replace"))
+        dev = self.plans[0].device
+        self.workspace = torch.empty(nb + 256, dtype=torch.uint8, device=dev)
+        wp = (self.workspace.data_ptr() + 255) // 256 * 256
+        h = ctypes.c_void_p()
+        _check(lib.apc_batch_create(ctypes.byref(h), arr, self.count, wp, nb))
+        self.handle = h.value
+
+    def iterate(self, T: int, graph: bool = False):
+        _check((lib.apc_batch_iterate_graph if graph else lib.apc_batch_iterate)(self.handle, T))
+
+    def residuals(self, rtol: float = -1.0):
+        rr = (ctypes.c_double * self.count)()
+        act = (ctypes.c_int32 * self.count)()
+        _check(lib.apc_batch_residuals(self.handle, rtol, rr, act))
+        return np.array(rr[:]), np.array(act[:])
+
+    def activate(self):
+        _check(lib.apc_batch_activate(self.handle))
+
+    def solve(self, rtol: float, max_iters: int, check_every: int = 8, graph: bool = True):
+        it = (ctypes.c_int32 * self.count)()
+        rr = (ctypes.c_double * self.count)()
+        st = lib.apc_batch_solve(self.handle, rtol, max_iters, check_every, 1 if graph else 0, it, rr)
+        if st not in (APC_OK, APC_ENOCONV):
+            _check(st)
+        return np.array(it[:]), np.array(rr[:]), st
+
+    def launch(self) -> dict:
+        g, a, b, v, us = (ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32(),
+                          ctypes.c_float())
+        _check(lib.apc_batch_get_launch(self.handle, ctypes.byref(g), ctypes.byref(a),
+                                        ctypes.byref(b), ctypes.byref(v), ctypes.byref(us)))
+        return {"grid": g.value, "items_a": a.value, "items_b": b.value, "items_avg": v.value,
+                "tuned_us": us.value}
+
+    def close(self):
+        if getattr(self, "handle", None) is not None:
+            lib.apc_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

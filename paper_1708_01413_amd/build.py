@@ -11,7 +11,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libapc.so")
 SOURCES = [os.path.join(CSRC, "apc_kernels.hip"), os.path.join(CSRC, "apc_gemm.hip"),
-           os.path.join(CSRC, "apc_host.cpp")]
+           os.path.join(CSRC, "apc_batch.hip"), os.path.join(CSRC, "apc_host.cpp")]
 
 HIPCC_FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "-shared",

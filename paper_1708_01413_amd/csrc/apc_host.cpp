@@ -14,6 +14,7 @@
 #include <cstring>
 #include <limits>
 #include <map>
+#include <memory>
 #include <mutex>
 #include <string>
 #include <tuple>
@@ -1608,5 +1609,315 @@ void apc_destroy(apc_plan p) {
 }
 
 const char* apc_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ batches of systems
+
+struct apc_batch_s {
+  std::vector<apc_plan_s*> plans;
+  int32_t count = 0;
+  hipStream_t stream = nullptr;
+  char* ws = nullptr;
+  BatchSys* sys = nullptr;
+  int4* itemsA = nullptr;
+  int4* itemsB = nullptr;
+  int2* itemsV = nullptr;
+  int32_t nA = 0, nB = 0, nV = 0;
+  int32_t* active = nullptr;
+  int32_t* item_start = nullptr;
+  double* partial = nullptr;
+  double* relres = nullptr;
+  int32_t gridA = 1024, gridB = 1024, gridV = 1024;
+  float tuned_us = 0.f;
+  std::vector<int32_t> h_active;
+  std::map<int32_t, std::pair<hipGraph_t, hipGraphExec_t>> graphs;
+};
+
+namespace {
+
+struct BatchPlanItems {
+  std::vector<int4> A, B;
+  std::vector<int2> V;
+  std::vector<int32_t> start;
+};
+
+apc_status batch_items(const apc_plan* plans, int32_t count, BatchPlanItems* it) {
+  it->start.push_back(0);
+  for (int32_t s = 0; s < count; ++s) {
+    const apc_plan_s* P = plans[s];
+    for (int i = 0; i < P->m; ++i) {
+      const int64_t r0 = P->off[i], p = P->off[i + 1] - r0;
+      for (int64_t r = 0; r < p; r += 8)
+        it->A.push_back(make_int4(s, static_cast<int>(r0 + r), static_cast<int>(std::min<int64_t>(8, p - r)), i));
+      for (int64_t j = 0; j < P->n; j += 256) it->B.push_back(make_int4(s, i, static_cast<int>(j), 0));
+    }
+    for (int64_t j = 0; j < P->n; j += 256) it->V.push_back(make_int2(s, static_cast<int>(j)));
+    it->start.push_back(static_cast<int32_t>(it->A.size()));
+  }
+  return APC_OK;
+}
+
+struct BatchLayout {
+  size_t sys, A, B, V, active, start, partial, relres, total;
+};
+
+BatchLayout batch_layout(int32_t count, const BatchPlanItems& it) {
+  BatchLayout L{};
+  size_t cur = 0;
+  auto take = [&](int64_t bytes) {
+    const size_t at = cur;
+    cur += static_cast<size_t>(round_up(std::max<int64_t>(bytes, 1), kAlign));
+    return at;
+  };
+  L.sys = take(static_cast<int64_t>(count) * sizeof(BatchSys));
+  L.A = take(static_cast<int64_t>(it.A.size()) * sizeof(int4));
+  L.B = take(static_cast<int64_t>(it.B.size()) * sizeof(int4));
+  L.V = take(static_cast<int64_t>(it.V.size()) * sizeof(int2));
+  L.active = take(static_cast<int64_t>(count) * 4);
+  L.start = take(static_cast<int64_t>(count + 1) * 4);
+  L.partial = take(static_cast<int64_t>(it.A.size()) * 8);
+  L.relres = take(static_cast<int64_t>(count) * 8);
+  L.total = cur;
+  return L;
+}
+
+apc_status batch_check_plans(const apc_plan* plans, int32_t count) {
+  if (!plans || count < 1) return fail(APC_EINVAL, "need at least one plan");
+  for (int32_t s = 0; s < count; ++s) {
+    const apc_plan_s* P = plans[s];
+    if (!P) return fail(APC_EINVAL, "plan %d is NULL", s);
+    if (P->gemm || P->k != 1 || P->prec != APC_F32)
+      return fail(APC_EUNSUPPORTED, "plan %d: batches take k = 1 FP32 plans in the per-block form", s);
+    if (P->stream != plans[0]->stream) return fail(APC_EINVAL, "plans must share one stream");
+    if (P->n > (1 << 30) || P->N > (1 << 30)) return fail(APC_EINVAL, "plan %d too large", s);
+  }
+  return APC_OK;
+}
+
+apc_status batch_update(apc_batch_s* B) {
+  HIP_TRY(launch_batch_pass_a(0, B->gridA, B->sys, B->itemsA, B->nA, B->active, B->stream));
+  HIP_TRY(launch_batch_pass_b(0, B->gridB, B->sys, B->itemsB, B->nB, B->active, B->stream));
+  HIP_TRY(launch_batch_average(0, B->gridV, B->sys, B->itemsV, B->nV, B->active, B->stream));
+  return APC_OK;
+}
+
+void batch_count(apc_batch_s* B, int32_t T) {
+  for (int32_t s = 0; s < B->count; ++s)
+    if (B->h_active[s]) B->plans[s]->iters += T;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t apc_batch_workspace_bytes(const apc_plan* plans, int32_t count) {
+  if (batch_check_plans(plans, count) != APC_OK) return 0;
+  BatchPlanItems it;
+  batch_items(plans, count, &it);
+  return batch_layout(count, it).total;
+}
+
+apc_status apc_batch_create(apc_batch* out, const apc_plan* plans, int32_t count, void* workspace,
+                            size_t ws_bytes) {
+  if (!out) return fail(APC_EINVAL, "out is NULL");
+  *out = nullptr;
+  ST_TRY(batch_check_plans(plans, count));
+  if (!workspace || reinterpret_cast<uintptr_t>(workspace) % kAlign != 0)
+    return fail(APC_EINVAL, "workspace must be a 256-byte aligned device pointer");
+  BatchPlanItems it;
+  batch_items(plans, count, &it);
+  const BatchLayout L = batch_layout(count, it);
+  if (ws_bytes < L.total) return fail(APC_EINVAL, "workspace has %zu bytes, needs %zu", ws_bytes, L.total);
+  if (it.A.size() > static_cast<size_t>(std::numeric_limits<int32_t>::max()))
+    return fail(APC_EINVAL, "too many work items");
+  apc_batch_s* B = new (std::nothrow) apc_batch_s();
+  if (!B) return fail(APC_EINVAL, "out of host memory");
+  std::unique_ptr<apc_batch_s> guard(B);
+  B->plans.assign(plans, plans + count);
+  B->count = count;
+  B->stream = plans[0]->stream;
+  B->ws = static_cast<char*>(workspace);
+  B->sys = reinterpret_cast<BatchSys*>(B->ws + L.sys);
+  B->itemsA = reinterpret_cast<int4*>(B->ws + L.A);
+  B->itemsB = reinterpret_cast<int4*>(B->ws + L.B);
+  B->itemsV = reinterpret_cast<int2*>(B->ws + L.V);
+  B->active = reinterpret_cast<int32_t*>(B->ws + L.active);
+  B->item_start = reinterpret_cast<int32_t*>(B->ws + L.start);
+  B->partial = reinterpret_cast<double*>(B->ws + L.partial);
+  B->relres = reinterpret_cast<double*>(B->ws + L.relres);
+  B->nA = static_cast<int32_t>(it.A.size());
+  B->nB = static_cast<int32_t>(it.B.size());
+  B->nV = static_cast<int32_t>(it.V.size());
+  std::vector<BatchSys> hs(count);
+  for (int32_t s = 0; s < count; ++s) {
+    apc_plan_s* P = plans[s];
+    BatchSys& d = hs[s];
+    d.C = P->at<float>(P->L.C32);
+    d.d = P->at<float>(P->L.dv);
+    d.w = P->at<float>(P->L.w);
+    d.x = P->x();
+    d.xbar = P->xbar();
+    d.off = P->doff();
+    d.A = P->A;
+    d.lda = P->lda;
+    d.b = P->B;
+    d.ldb = P->ldb;
+    d.ldc = P->L.ldc;
+    d.n = P->n;
+    d.N = P->N;
+    d.m = P->m;
+    d.gamma = P->gamma;
+    d.eta = P->eta;
+    d.bnorm = P->bnorm;
+  }
+  B->h_active.assign(count, 1);
+  hipStream_t st = B->stream;
+  HIP_TRY(hipMemcpyAsync(B->sys, hs.data(), hs.size() * sizeof(BatchSys), hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(B->itemsA, it.A.data(), it.A.size() * sizeof(int4), hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(B->itemsB, it.B.data(), it.B.size() * sizeof(int4), hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(B->itemsV, it.V.data(), it.V.size() * sizeof(int2), hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(B->active, B->h_active.data(), count * 4, hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(B->item_start, it.start.data(), it.start.size() * 4, hipMemcpyHostToDevice, st));
+  // Persistent grid: time pass A (it only writes the scratch w) for a few
+  // workgroup counts and use the fastest for all three passes, unless the
+  // environment fixes it.
+  if (const char* e = std::getenv("APC_BATCH_GRID")) {
+    const int g = std::max(1, std::atoi(e));
+    B->gridA = B->gridB = B->gridV = g;
+  } else {
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    const int cands[5] = {256, 512, 1024, 2048, 4096};
+    float best = 0.f;
+    for (int c : cands) {
+      hipError_t err = launch_batch_pass_a(0, c, B->sys, B->itemsA, B->nA, B->active, st);
+      if (err == hipSuccess) err = hipEventRecord(e0, st);
+      for (int r = 0; err == hipSuccess && r < 3; ++r)
+        err = launch_batch_pass_a(0, c, B->sys, B->itemsA, B->nA, B->active, st);
+      if (err == hipSuccess) err = hipEventRecord(e1, st);
+      if (err == hipSuccess) err = hipEventSynchronize(e1);
+      float ms = 0.f;
+      if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
+      if (err != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        return fail(APC_EHIP, "batch tuning failed: %s", hipGetErrorString(err));
+      }
+      if (c == cands[0] || ms < best) {
+        best = ms;
+        B->gridA = B->gridB = B->gridV = c;
+      }
+    }
+    B->tuned_us = best * 1e3f / 3.f;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+  }
+  HIP_TRY(hipStreamSynchronize(st));
+  *out = guard.release();
+  return APC_OK;
+}
+
+apc_status apc_batch_iterate(apc_batch b, int32_t T) {
+  if (!b || T < 0) return fail(APC_EINVAL, "bad argument");
+  for (int32_t t = 0; t < T; ++t) ST_TRY(batch_update(b));
+  batch_count(b, T);
+  return APC_OK;
+}
+
+apc_status apc_batch_iterate_graph(apc_batch b, int32_t T) {
+  if (!b || T < 0) return fail(APC_EINVAL, "bad argument");
+  if (T == 0) return APC_OK;
+  if (b->stream == nullptr) return fail(APC_EINVAL, "graph capture needs a non-default stream");
+  auto itg = b->graphs.find(T);
+  if (itg == b->graphs.end()) {
+    hipGraph_t g = nullptr;
+    HIP_TRY(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+    apc_status st = APC_OK;
+    for (int32_t t = 0; t < T && st == APC_OK; ++t) st = batch_update(b);
+    hipError_t e = hipStreamEndCapture(b->stream, &g);
+    if (st != APC_OK) return st;
+    HIP_TRY(e);
+    hipGraphExec_t ex = nullptr;
+    e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+      (void)hipGraphDestroy(g);
+      HIP_TRY(e);
+    }
+    itg = b->graphs.emplace(T, std::make_pair(g, ex)).first;
+  }
+  HIP_TRY(hipGraphLaunch(itg->second.second, b->stream));
+  batch_count(b, T);
+  return APC_OK;
+}
+
+apc_status apc_batch_residuals(apc_batch b, double rtol, double* relres, int32_t* active) {
+  if (!b) return fail(APC_EINVAL, "batch is NULL");
+  HIP_TRY(launch_batch_resid(b->gridA, b->sys, b->itemsA, b->nA, b->active, b->partial, b->stream));
+  HIP_TRY(launch_batch_check(b->sys, b->count, b->item_start, b->partial, rtol, b->active,
+                             b->relres, b->stream));
+  std::vector<double> rr(b->count);
+  HIP_TRY(hipMemcpyAsync(rr.data(), b->relres, b->count * 8, hipMemcpyDeviceToHost, b->stream));
+  HIP_TRY(hipMemcpyAsync(b->h_active.data(), b->active, b->count * 4, hipMemcpyDeviceToHost, b->stream));
+  HIP_TRY(hipStreamSynchronize(b->stream));
+  if (relres) std::copy(rr.begin(), rr.end(), relres);
+  if (active) std::copy(b->h_active.begin(), b->h_active.end(), active);
+  return APC_OK;
+}
+
+apc_status apc_batch_activate(apc_batch b) {
+  if (!b) return fail(APC_EINVAL, "batch is NULL");
+  b->h_active.assign(b->count, 1);
+  HIP_TRY(hipMemcpyAsync(b->active, b->h_active.data(), b->count * 4, hipMemcpyHostToDevice, b->stream));
+  HIP_TRY(hipStreamSynchronize(b->stream));
+  return APC_OK;
+}
+
+apc_status apc_batch_solve(apc_batch b, double rtol, int32_t max_iters, int32_t check_every,
+                           int32_t use_graph, int32_t* iters_out, double* relres_out) {
+  if (!b || max_iters < 0 || check_every < 1 || !(rtol >= 0)) return fail(APC_EINVAL, "bad argument");
+  std::vector<int64_t> start(b->count);
+  for (int32_t s = 0; s < b->count; ++s) start[s] = b->plans[s]->iters;
+  std::vector<double> rr(b->count, 0.0);
+  int32_t done = 0;
+  for (;;) {
+    ST_TRY(apc_batch_residuals(b, rtol, rr.data(), nullptr));
+    int32_t left = 0;
+    for (int32_t s = 0; s < b->count; ++s) left += b->h_active[s];
+    if (left == 0 || done >= max_iters) break;
+    const int32_t T = std::min(check_every, max_iters - done);
+    if (use_graph) ST_TRY(apc_batch_iterate_graph(b, T));
+    else ST_TRY(apc_batch_iterate(b, T));
+    done += T;
+  }
+  for (int32_t s = 0; s < b->count; ++s) {
+    if (iters_out) iters_out[s] = static_cast<int32_t>(b->plans[s]->iters - start[s]);
+    if (relres_out) relres_out[s] = rr[s];
+  }
+  for (int32_t s = 0; s < b->count; ++s)
+    if (b->h_active[s]) return fail(APC_ENOCONV, "system %d did not reach %g in %d updates", s, rtol, max_iters);
+  return APC_OK;
+}
+
+apc_status apc_batch_get_launch(apc_batch b, int32_t* grid, int32_t* items_a, int32_t* items_b,
+                                int32_t* items_avg, float* tuned_us) {
+  if (!b) return fail(APC_EINVAL, "batch is NULL");
+  if (grid) *grid = b->gridA;
+  if (items_a) *items_a = b->nA;
+  if (items_b) *items_b = b->nB;
+  if (items_avg) *items_avg = b->nV;
+  if (tuned_us) *tuned_us = b->tuned_us;
+  return APC_OK;
+}
+
+void apc_batch_destroy(apc_batch b) {
+  if (!b) return;
+  for (auto& kv : b->graphs) {
+    (void)hipGraphExecDestroy(kv.second.second);
+    (void)hipGraphDestroy(kv.second.first);
+  }
+  delete b;
+}
 
 }  // extern "C"

@@ -205,6 +205,46 @@ constexpr int kTnAdjointBlocks = 512;
 int tn_adjoint_blocks();
 hipError_t launch_tn_adjoint(int type, const TnAdjointArgs& a, hipStream_t s);
 
+// ---------------------------------------------------------------------------
+// Many independent k = 1 systems (apc_batch.hip)
+// ---------------------------------------------------------------------------
+
+// One system of a batch: pointers into its own plan's workspace.
+struct BatchSys {
+  const void* C;        // factor in the projection precision, N x ldc
+  void* d;              // differences x_bar - x_i, m x ldc (projection precision)
+  void* w;              // pass-A output, N (projection precision)
+  double* x;            // local solutions, m x ldc
+  double* xbar;         // average, ldc
+  const int64_t* off;   // device block offsets, m + 1
+  const double* A;      // FP64 system matrix (residual), row stride lda
+  int64_t lda;
+  const double* b;      // right-hand side, entry stride ldb
+  int64_t ldb;
+  int64_t ldc;
+  int64_t n;
+  int64_t N;
+  int32_t m;
+  double gamma;
+  double eta;
+  double bnorm;
+};
+// Items: pass A (sys, first row, rows <= 8, block); pass B (sys, block, first
+// column of a 256-column slab, 0); average (sys, first column of 256).
+hipError_t launch_batch_pass_a(int f64, int32_t grid, const BatchSys* sys, const int4* items,
+                               int32_t nitems, const int32_t* active, hipStream_t s);
+hipError_t launch_batch_pass_b(int f64, int32_t grid, const BatchSys* sys, const int4* items,
+                               int32_t nitems, const int32_t* active, hipStream_t s);
+hipError_t launch_batch_average(int f64, int32_t grid, const BatchSys* sys, const int2* items,
+                                int32_t nitems, const int32_t* active, hipStream_t s);
+// partial[item] = sum over the item's rows of (b_r - a_r . x_bar)^2 (pass-A items).
+hipError_t launch_batch_resid(int32_t grid, const BatchSys* sys, const int4* items, int32_t nitems,
+                              const int32_t* active, double* partial, hipStream_t s);
+// relres[s] = sqrt(sum of system s's partials) / ||b_s||; active[s] = 0 once <= rtol.
+hipError_t launch_batch_check(const BatchSys* sys, int32_t count, const int32_t* item_start,
+                              const double* partial, double rtol, int32_t* active, double* relres,
+                              hipStream_t s);
+
 // R[c*ldr + r] = B[r*ldb + c] - sum of the FP64 partials, r < N, c < k.
 hipError_t launch_tn_resid(const double* part, int32_t nsplit, int32_t kp, int64_t ldp, int64_t N,
                            int32_t k, const double* B, int64_t ldb, double* R, int64_t ldr,

@@ -740,3 +740,96 @@ def test_backward_unsupported_plans():
         with pytest.raises(apc.ApcError) as ex:
             plan.backward(torch.zeros(256, dtype=torch.float64, device=A.device), 5, 2)
         assert ex.value.status in (apc.APC_EUNSUPPORTED,)
+
+
+# ---------------------------------------------------------------- many independent systems
+
+
+def _batch_plans(systems, stream, params=True):
+    apc = _apc()
+    torch = _torch()
+    plans, tensors = [], []
+    for S in systems:
+        A = torch.from_numpy(S.A).to("cuda")
+        b = torch.from_numpy(S.B).to("cuda")
+        if params:
+            g, e, _ = O.optimal_params(*O.spectrum(S.A, S.off))
+            plans.append(apc.Plan(A, b, S.off, "f32", gamma=g, eta=e, stream=stream))
+        else:
+            plans.append(apc.Plan(A, b, S.off, "f32", stream=stream))
+        tensors.append((A, b))
+    return plans, tensors
+
+
+def test_batch_matches_oracle_and_single_plans():
+    """Ten independent systems (n in [64, 700], m in {4, 8, 16}, uneven n) through one
+    persistent launch per pass: every x_bar(T) within the FP32 bar of the oracle's, and
+    equal to the same plan iterated alone up to FP32 rounding."""
+    apc = _apc()
+    torch = _torch()
+    systems = synth.many_small_systems(count=10, seed=80, lo=64, hi=700)
+    stream = torch.cuda.Stream()
+    plans, keep = _batch_plans(systems, stream)
+    single, keep2 = _batch_plans(systems, stream)
+    batch = apc.Batch(plans)
+    say(f"case: batch of {len(systems)}: n = {[S.n for S in systems]}, launch {batch.launch()}")
+    T = 30
+    batch.iterate(T)
+    for p in single:
+        p.iterate(T)
+    stream.synchronize()
+    worst_o, worst_s = 0.0, 0.0
+    for S, p, q in zip(systems, plans, single):
+        g, e = p.params()["gamma"], p.params()["eta"]
+        ref = O.apc_run(S.A, S.B, S.off, T, g, e)["xbar"][:, 0]
+        x = p.xbar().cpu().numpy()
+        worst_o = max(worst_o, np.linalg.norm(x - ref) / np.linalg.norm(S.xstar))
+        worst_s = max(worst_s, np.linalg.norm(x - q.xbar().cpu().numpy()) / np.linalg.norm(S.xstar))
+        assert p.iterations == T
+    say(f"max dev vs oracle {worst_o:.2e}, vs single plans {worst_s:.2e}")
+    assert worst_o <= TOL["f32"]
+    assert worst_s <= 1e-6
+    batch.close()
+
+
+def test_batch_graph_replays_match_eager_launches():
+    """The captured graph of 5 updates, replayed three times with eager work and syncs in
+    between, gives bitwise the same states as eager launches, at every replay."""
+    apc = _apc()
+    torch = _torch()
+    systems = synth.many_small_systems(count=6, seed=81, lo=64, hi=400)
+    stream = torch.cuda.Stream()
+    pa, k1 = _batch_plans(systems, stream)
+    pb, k2 = _batch_plans(systems, stream)
+    ba, bb = apc.Batch(pa), apc.Batch(pb)
+    for rep in range(3):
+        ba.iterate(5, graph=True)
+        bb.iterate(5, graph=False)
+        stream.synchronize()
+        junk = torch.randn(1000, device="cuda").sum().item()  # eager work between replays
+        ra, _ = ba.residuals()
+        for p, q in zip(pa, pb):
+            assert torch.equal(p.xbar(), q.xbar()), (rep, junk)
+        say(f"case: graph replay {rep}: residuals {ra.max():.2e}")
+    ba.close()
+    bb.close()
+
+
+def test_batch_solve_stops_each_system():
+    """Per-system stopping: every system reaches rtol, systems converge after different
+    numbers of updates, and each x_bar is near its x*."""
+    apc = _apc()
+    torch = _torch()
+    systems = synth.many_small_systems(count=16, seed=82, lo=64, hi=1024)
+    stream = torch.cuda.Stream()
+    plans, keep = _batch_plans(systems, stream, params=False)
+    batch = apc.Batch(plans)
+    iters, rr, st = batch.solve(1e-5, 400, check_every=4, graph=True)
+    say(f"case: batch solve: status {st}, iterations {iters.tolist()}, max relres {rr.max():.2e}")
+    assert st == apc.APC_OK
+    assert np.all(rr <= 1e-5)
+    assert len(set(iters.tolist())) > 1
+    for S, p in zip(systems, plans):
+        err = np.linalg.norm(p.xbar().cpu().numpy() - S.xstar) / np.linalg.norm(S.xstar)
+        assert err <= 1e-4
+    batch.close()
