@@ -928,8 +928,10 @@ apc_status setup_impl(apc_plan_s* P, const Tiles& T) {
     // Both inverse factors are kept: refinement and apc_restart form
     // c = L2^{-1} L1^{-1} r, the adjoint applies L1^{-T} L2^{-T}.
     double* Li = pass == 1 ? P->at<double>(L.Linv2) : P->at<double>(L.Linv);
-    HIP_TRY(launch_chol_inv(P->doff(), P->at<int64_t>(L.goff), m, P->at<double>(L.G), Li, cs, cd,
-                            P->kp, N, P->at<int>(L.flags), rank_tol, st));
+    HIP_TRY(launch_chol_inv(P->doff(), P->at<int64_t>(L.goff), m, P->at<double>(L.G), Li,
+                            P->at<int>(L.flags), rank_tol, st));
+    HIP_TRY(launch_linv_apply(P->doff(), P->at<int64_t>(L.goff), m, P->pmax, Li, cs, N, cd, N,
+                              P->kp, 0, 1.0, st));
     HIP_TRY(launch_trmm(src, dst, ldc, P->doff(), P->at<int32_t>(L.tiles_t), L.ntiles_t,
                         P->at<int64_t>(L.goff), Li, st));
   }

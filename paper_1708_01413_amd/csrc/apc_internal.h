@@ -284,12 +284,11 @@ hipError_t launch_copy_pad(const double* A, int64_t lda, const double* B, int64_
 // G_i = C_i C_i^T for every block (tiles: (blk, ta, tb) with ta >= tb).
 hipError_t launch_gram(const double* C, int64_t ldc, const int64_t* off, const int32_t* tiles,
                        int32_t ntiles, const int64_t* goff, double* G, hipStream_t s);
-// Per block: Cholesky G_i = L L^T in place, Linv_i = L^{-1}, and for each of
-// the kp right-hand-side columns (stride ldcv) c_out = Linv c_in;
-// flags[0] <- 1 + (first block whose pivot fails the rank test).
+// Per block: Cholesky G_i = L L^T in place (lower triangle), Linv_i = L^{-1}
+// (zeros above the diagonal); flags[0] <- 1 + (first block whose pivot fails
+// the rank test).
 hipError_t launch_chol_inv(const int64_t* off, const int64_t* goff, int32_t m, double* G,
-                           double* Linv, const double* c_in, double* c_out, int32_t kp,
-                           int64_t ldcv, int* flags, double rank_tol, hipStream_t s);
+                           double* Linv, int* flags, double rank_tol, hipStream_t s);
 // Out_i = Linv_i In_i for every block (tiles: (blk, ta, tc)).
 hipError_t launch_trmm(const double* In, double* Out, int64_t ldc, const int64_t* off,
                        const int32_t* tiles, int32_t ntiles, const int64_t* goff,

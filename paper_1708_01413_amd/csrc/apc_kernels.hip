@@ -450,69 +450,177 @@ __global__ __launch_bounds__(256) void k_gram(const double* C, int64_t ldc, cons
   }
 }
 
-// One workgroup per block.  G_i (p x p, row-major, full symmetric) is
-// factored in place (lower triangle = L), then Linv = L^{-1} is formed row by
-// row (zeros above the diagonal), then c_out = Linv c_in.
-__global__ __launch_bounds__(1024) void k_chol_inv(const int64_t* off, const int64_t* goff,
-                                                   double* G, double* Linv, const double* c_in,
-                                                   double* c_out, int32_t kp, int64_t ldcv,
-                                                   int* flags, double rank_tol) {
+// Blocked Cholesky G_i = L L^T and Linv_i = L^{-1}, one workgroup per block.
+// Panels of 32 columns: wave 0 factors and inverts the 32 x 32 diagonal block
+// in registers (lane i holds row i; broadcasts by shuffles), all threads then
+// solve the panel below it (rows times L_kk^{-T}) and update the trailing
+// lower triangle from an LDS copy of the panel.  Then Linv's block rows below
+// the diagonal: Linv[I, J] = -L_II^{-1} sum_{K=J}^{I-1} L[I, K] Linv[K, J].
+// Linv's strict upper triangle is written as zeros (the tiled products read
+// whole tiles).  flags[0] <- 1 + (first block whose pivot fails the rank test).
+constexpr int kNB = 32;
+constexpr int kPanelRows = 384;  // panels of up to this many rows are kept in LDS
+
+__global__ __launch_bounds__(512) void k_chol_inv(const int64_t* off, const int64_t* goff,
+                                                   double* G, double* Linv, int* flags,
+                                                   double rank_tol) {
   const int blk = blockIdx.x;
-  const int64_t r0 = off[blk];
-  const int p = static_cast<int>(off[blk + 1] - r0);
+  const int p = static_cast<int>(off[blk + 1] - off[blk]);
   double* Gb = G + goff[blk];
   double* Lb = Linv + goff[blk];
-  const int tid = threadIdx.x;
-  const int nt = blockDim.x;
-  __shared__ double maxdiag;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const int lane = tid & 63, wv = tid >> 6;
+  __shared__ double dl[kNB][kNB + 1];   // L_kk, then (column-solve input)
+  __shared__ double di[kNB][kNB + 1];   // L_kk^{-1}
+  __shared__ double pan[kPanelRows][kNB + 1];
+  __shared__ double red[1024 / 64];  // per-wave maxima (up to 16 waves)
   __shared__ int bad;
-  if (tid == 0) {
-    double mx = 0.0;
-    for (int k = 0; k < p; ++k) mx = fmax(mx, Gb[static_cast<int64_t>(k) * p + k]);
-    maxdiag = mx;
-    bad = 0;
+
+  // Largest diagonal entry (rank test scale) and the zero upper triangle of Linv.
+  double mx = 0.0;
+  for (int k = tid; k < p; k += nt) mx = fmax(mx, Gb[static_cast<int64_t>(k) * p + k]);
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o, 64));
+  if (lane == 0) red[wv] = mx;
+  if (tid == 0) bad = 0;
+  for (int64_t e = tid; e < static_cast<int64_t>(p) * p; e += nt) {
+    const int r = static_cast<int>(e / p), c = static_cast<int>(e % p);
+    if (c > r) Lb[e] = 0.0;
   }
   __syncthreads();
-  for (int k = 0; k < p; ++k) {
-    double piv = Gb[static_cast<int64_t>(k) * p + k];
-    if (!(piv > rank_tol * maxdiag)) {  // also catches NaN
-      if (tid == 0) bad = 1;
-      piv = maxdiag > 0.0 ? maxdiag : 1.0;  // keep going without NaNs; result is flagged
-    }
-    const double lkk = sqrt(piv);
-    __syncthreads();
-    for (int i = k + 1 + tid; i < p; i += nt) Gb[static_cast<int64_t>(i) * p + k] /= lkk;
-    if (tid == 0) Gb[static_cast<int64_t>(k) * p + k] = lkk;
-    __syncthreads();
-    const int q = p - k - 1;
-    for (int64_t e = tid; e < static_cast<int64_t>(q) * q; e += nt) {
-      const int ii = k + 1 + static_cast<int>(e / q);
-      const int jj = k + 1 + static_cast<int>(e % q);
-      if (jj <= ii)
-        Gb[static_cast<int64_t>(ii) * p + jj] -=
-            Gb[static_cast<int64_t>(ii) * p + k] * Gb[static_cast<int64_t>(jj) * p + k];
-    }
-    __syncthreads();
-  }
-  for (int r = 0; r < p; ++r) {
-    const double* Lr = Gb + static_cast<int64_t>(r) * p;
-    for (int c = tid; c < p; c += nt) {
-      double v = 0.0;
-      if (c <= r) {
-        double s = (r == c) ? 1.0 : 0.0;
-        for (int k = c; k < r; ++k) s -= Lr[k] * Lb[static_cast<int64_t>(k) * p + c];
-        v = s / Lr[r];
+  double maxdiag = 0.0;
+  for (int w = 0; w < nt / 64; ++w) maxdiag = fmax(maxdiag, red[w]);
+
+  for (int kb = 0; kb < p; kb += kNB) {
+    const int nb = min(kNB, p - kb);
+    // (1) diagonal block: Cholesky and inverse in wave 0's registers.
+    if (wv == 0) {
+      double a[kNB];
+#pragma unroll
+      for (int j = 0; j < kNB; ++j) {
+        double v = (lane == j) ? 1.0 : 0.0;  // identity past nb
+        if (lane < nb && j < nb && j <= lane) v = Gb[static_cast<int64_t>(kb + lane) * p + kb + j];
+        a[j] = v;
       }
-      Lb[static_cast<int64_t>(r) * p + c] = v;
+#pragma unroll
+      for (int j = 0; j < kNB; ++j) {
+        double piv = __shfl(a[j], j, 64);
+        if (j < nb && !(piv > rank_tol * maxdiag)) {  // also catches NaN
+          if (lane == 0) bad = 1;
+          piv = maxdiag > 0.0 ? maxdiag : 1.0;
+        }
+        const double d = sqrt(piv);
+        if (lane > j) a[j] /= d;
+        if (lane == j) a[j] = d;
+#pragma unroll
+        for (int jj = j + 1; jj < kNB; ++jj) {
+          const double ljj = __shfl(a[j], jj, 64);
+          if (lane >= jj) a[jj] -= a[j] * ljj;
+        }
+      }
+      if (lane < kNB) {
+#pragma unroll
+        for (int j = 0; j < kNB; ++j) dl[lane][j] = (j <= lane) ? a[j] : 0.0;
+      }
+    }
+    __syncthreads();
+    // Inverse of L_kk, lane c of wave 0 builds column c by forward substitution.
+    if (wv == 0 && lane < kNB) {
+      const int c = lane;
+      double x[kNB];
+#pragma unroll
+      for (int i = 0; i < kNB; ++i) {
+        double sacc = (i == c) ? 1.0 : 0.0;
+#pragma unroll
+        for (int q = 0; q < i; ++q) sacc -= dl[i][q] * x[q];
+        x[i] = (i < c) ? 0.0 : sacc / dl[i][i];
+      }
+#pragma unroll
+      for (int i = 0; i < kNB; ++i) di[i][c] = x[i];
+    }
+    __syncthreads();
+    // Write L_kk and L_kk^{-1} back.
+    for (int e = tid; e < nb * nb; e += nt) {
+      const int i = e / nb, j = e % nb;
+      if (j <= i) {
+        Gb[static_cast<int64_t>(kb + i) * p + kb + j] = dl[i][j];
+        Lb[static_cast<int64_t>(kb + i) * p + kb + j] = di[i][j];
+      }
+    }
+    // (2) panel below: rows times L_kk^{-T}.
+    const int T = p - kb - nb;
+    const bool in_lds = T <= kPanelRows;
+    for (int t = tid; t < T; t += nt) {
+      const int r = kb + nb + t;
+      double* row = Gb + static_cast<int64_t>(r) * p + kb;
+      double o[kNB];
+#pragma unroll
+      for (int j = 0; j < kNB; ++j) o[j] = 0.0;
+#pragma unroll 1
+      for (int q = 0; q < nb; ++q) {  // o[j] = sum_{q <= j} row[q] Linv_kk[j][q]
+        const double sq = row[q];
+#pragma unroll
+        for (int j = 0; j < kNB; ++j) o[j] += (j >= q) ? sq * di[j][q] : 0.0;
+      }
+#pragma unroll
+      for (int j = 0; j < kNB; ++j) {
+        if (j < nb) {
+          row[j] = o[j];
+          if (in_lds) pan[t][j] = o[j];
+        }
+      }
+    }
+    __syncthreads();
+    // (3) trailing update of the lower triangle.
+    for (int64_t e = tid; e < static_cast<int64_t>(T) * T; e += nt) {
+      const int rr = static_cast<int>(e / T), cc = static_cast<int>(e % T);
+      if (cc > rr) continue;
+      double sacc = 0.0;
+      if (in_lds) {
+        for (int q = 0; q < nb; ++q) sacc += pan[rr][q] * pan[cc][q];
+      } else {
+        const double* pr = Gb + static_cast<int64_t>(kb + nb + rr) * p + kb;
+        const double* pc = Gb + static_cast<int64_t>(kb + nb + cc) * p + kb;
+        for (int q = 0; q < nb; ++q) sacc += pr[q] * pc[q];
+      }
+      Gb[static_cast<int64_t>(kb + nb + rr) * p + kb + nb + cc] -= sacc;
     }
     __syncthreads();
   }
-  for (int e = tid; e < p * kp; e += nt) {
-    const int r = e % p;
-    const int64_t col = static_cast<int64_t>(e / p) * ldcv;
-    double s = 0.0;
-    for (int k = 0; k <= r; ++k) s += Lb[static_cast<int64_t>(r) * p + k] * c_in[col + r0 + k];
-    c_out[col + r0 + r] = s;
+
+  // Off-diagonal block rows of Linv, top to bottom.
+  for (int I0 = kNB; I0 < p; I0 += kNB) {
+    const int nbI = min(kNB, p - I0);
+    // t[i][c] = sum_{k=c}^{I0-1} L[I0+i][k] Linv[k][c], stored in Linv's block row.
+    for (int64_t e = tid; e < static_cast<int64_t>(nbI) * I0; e += nt) {
+      const int i = static_cast<int>(e / I0), c = static_cast<int>(e % I0);
+      const double* Lr = Gb + static_cast<int64_t>(I0 + i) * p;
+      double sacc = 0.0;
+      for (int k = c; k < I0; ++k) sacc += Lr[k] * Lb[static_cast<int64_t>(k) * p + c];
+      Lb[static_cast<int64_t>(I0 + i) * p + c] = sacc;
+    }
+    // L_II^{-1} into LDS (zero-padded to 32 x 32).
+    for (int e = tid; e < kNB * kNB; e += nt) {
+      const int i = e / kNB, q = e % kNB;
+      di[i][q] = (i < nbI && q <= i) ? Lb[static_cast<int64_t>(I0 + i) * p + I0 + q] : 0.0;
+    }
+    __syncthreads();
+    // Linv[I0+i][c] = -sum_{q<=i} Linv_II[i][q] t[q][c]: one thread per column.
+    for (int c = tid; c < I0; c += nt) {
+      double o[kNB];
+#pragma unroll
+      for (int i = 0; i < kNB; ++i) o[i] = 0.0;
+#pragma unroll 1
+      for (int q = 0; q < nbI; ++q) {  // o[i] = sum_{q <= i} Linv_II[i][q] t[q][c]
+        const double tq = Lb[static_cast<int64_t>(I0 + q) * p + c];
+#pragma unroll
+        for (int i = 0; i < kNB; ++i) o[i] += (i >= q) ? di[i][q] * tq : 0.0;
+      }
+#pragma unroll
+      for (int i = 0; i < kNB; ++i)
+        if (i < nbI) Lb[static_cast<int64_t>(I0 + i) * p + c] = -o[i];
+    }
+    __syncthreads();
   }
   if (tid == 0 && bad) atomicCAS(flags, 0, blk + 1);
 }
@@ -808,10 +916,8 @@ hipError_t launch_gram(const double* C, int64_t ldc, const int64_t* off, const i
 }
 
 hipError_t launch_chol_inv(const int64_t* off, const int64_t* goff, int32_t m, double* G,
-                           double* Linv, const double* c_in, double* c_out, int32_t kp,
-                           int64_t ldcv, int* flags, double rank_tol, hipStream_t s) {
-  hipLaunchKernelGGL(k_chol_inv, dim3(m), dim3(1024), 0, s, off, goff, G, Linv, c_in, c_out, kp,
-                     ldcv, flags, rank_tol);
+                           double* Linv, int* flags, double rank_tol, hipStream_t s) {
+  hipLaunchKernelGGL(k_chol_inv, dim3(m), dim3(512), 0, s, off, goff, G, Linv, flags, rank_tol);
   return hipGetLastError();
 }
 
