@@ -27,6 +27,13 @@ __device__ inline float4 ld4(const TQ* p);
 template <>
 __device__ inline float4 ld4<float>(const float* p) { return *reinterpret_cast<const float4*>(p); }
 
+// The factor is read once per pass: non-temporal loads.
+typedef float bf32x4 __attribute__((ext_vector_type(4)));
+__device__ inline float4 ld4_nt(const float* p) {
+  const bf32x4 v = __builtin_nontemporal_load(reinterpret_cast<const bf32x4*>(p));
+  return make_float4(v[0], v[1], v[2], v[3]);
+}
+
 template <typename T>
 __device__ inline T wsum64(T v) {
 #pragma unroll
@@ -52,7 +59,7 @@ __global__ __launch_bounds__(256) void k_batch_pass_a(const BatchSys* sys, const
       TQ acc = 0;
       for (int64_t j = static_cast<int64_t>(lane) * 4; j < S.n; j += 256) {
         if (j + 4 <= S.n) {
-          const float4 c = ld4(row + j), v = ld4(d + j);
+          const float4 c = ld4_nt(row + j), v = ld4(d + j);
           acc += c.x * v.x + c.y * v.y + c.z * v.z + c.w * v.w;
         } else {
           for (int64_t q = j; q < S.n; ++q) acc += row[q] * d[q];
@@ -85,7 +92,7 @@ __global__ __launch_bounds__(256) void k_batch_pass_b(const BatchSys* sys, const
     if (j + 4 <= S.ldc) {  // rows are padded to ldc (zeros past n)
       int64_t r = r0 + wv;
       for (; r + 4 < r1; r += 8) {
-        const float4 c0 = ld4(C + r * S.ldc + j), c1 = ld4(C + (r + 4) * S.ldc + j);
+        const float4 c0 = ld4_nt(C + r * S.ldc + j), c1 = ld4_nt(C + (r + 4) * S.ldc + j);
         const float s0 = wvec[r], s1 = wvec[r + 4];
         acc[0] += c0.x * s0 + c1.x * s1;
         acc[1] += c0.y * s0 + c1.y * s1;
@@ -93,7 +100,7 @@ __global__ __launch_bounds__(256) void k_batch_pass_b(const BatchSys* sys, const
         acc[3] += c0.w * s0 + c1.w * s1;
       }
       if (r < r1) {
-        const float4 c0 = ld4(C + r * S.ldc + j);
+        const float4 c0 = ld4_nt(C + r * S.ldc + j);
         const float s0 = wvec[r];
         acc[0] += c0.x * s0;
         acc[1] += c0.y * s0;

@@ -7,7 +7,8 @@
 //
 // M (rows x K, row-major) is the large operand and is read exactly once: each
 // lane loads 64 contiguous bytes of a row per step straight into MFMA operand
-// registers (no LDS round trip).  V (one row per right-hand side, K
+// registers (no LDS round trip).  (Plain loads: a lane's four 16-byte loads of
+// one 64-byte run share cache lines, which non-temporal loads measured slower.)  V (one row per right-hand side, K
 // contiguous) is small and re-read by every workgroup: one 256-byte-per-row
 // step of it is staged in LDS and shared by the four waves.  Both operands
 // are laid out K-contiguous, so the per-update passes of the (y, x_bar) form

@@ -352,6 +352,8 @@ struct apc_plan_s {
   TnChoice tnA, tnB, tnX0, tnR;        // launch shapes: pass A, pass B, x_bar(0), residual
   int anchor_every = 0;                // k-RHS FP32/bf16: every this many updates one in FP64
   int64_t pmax = 1;                    // largest block
+  int32_t passb_nt = 1;                // k = 1 pass B: non-temporal loads of C
+  int32_t passa_nt = 1;                // k = 1 pass A: non-temporal loads of C
   int64_t since_start = 0;             // k-RHS updates since the last start
   int refinements = 0;
   std::vector<int32_t> tile_start;     // first pass-A tile of every block (m+1)
@@ -380,13 +382,13 @@ apc_status pass_a(apc_plan_s* P, int i0, int i1, int col) {
     RowdotArgs<float> a{P->at<float>(P->L.C32), P->L.ldc, P->ta(0), P->ta(1), P->ta(2), nt, 0,
                         nullptr, nullptr, 0, P->at<float>(P->L.dv) + coff, P->state_ld(),
                         P->at<float>(P->L.w) + woff, P->N, P->nsplit, P->split_cols,
-                        P->xcd_remap, P->passa_rows, t0};
+                        P->xcd_remap, P->passa_rows, t0, P->passa_nt};
     HIP_TRY(launch_rowdot_f32(a, P->stream));
   } else {
     RowdotArgs<double> a{P->C64(), P->L.ldc, P->ta(0), P->ta(1), P->ta(2), nt, 0, nullptr,
                          nullptr, 0, P->at<double>(P->L.dv) + coff, P->state_ld(),
                          P->at<double>(P->L.w) + woff, P->N, P->nsplit, P->split_cols,
-                         P->xcd_remap, P->passa_rows, t0};
+                         P->xcd_remap, P->passa_rows, t0, P->passa_nt};
     HIP_TRY(launch_rowdot_f64(a, P->stream));
   }
   return APC_OK;
@@ -413,12 +415,12 @@ apc_status pass_b(apc_plan_s* P, int i0, int i1, int col) {
   if (P->prec == APC_F32) {
     PassBArgs<float> a{P->at<float>(P->L.C32), P->L.ldc, P->doff(), i1 - i0, nslab,
                        P->at<float>(P->L.w) + woff, P->nsplit, P->N, P->x() + coff,
-                       P->state_ld(), P->xbar() + coff, P->gamma, i0};
+                       P->state_ld(), P->xbar() + coff, P->gamma, i0, P->passb_nt};
     HIP_TRY(launch_pass_b_f32(a, P->stream));
   } else {
     PassBArgs<double> a{P->C64(), P->L.ldc, P->doff(), i1 - i0, nslab,
                         P->at<double>(P->L.w) + woff, P->nsplit, P->N, P->x() + coff,
-                        P->state_ld(), P->xbar() + coff, P->gamma, i0};
+                        P->state_ld(), P->xbar() + coff, P->gamma, i0, P->passb_nt};
     HIP_TRY(launch_pass_b_f64(a, P->stream));
   }
   return APC_OK;
@@ -1033,9 +1035,13 @@ apc_status apc_setup(apc_plan* out, const double* A, int64_t lda, const double* 
     return fail(APC_EINVAL, "gamma and eta must be finite (or NaN for the optimum)");
   // Launch-shape knobs (defaults are the tuned ones; the environment may override).
   int32_t xcd_remap = 1, passa_rows = kPassARows, nsplit_req = 0, group_blocks = -1;
-  if (const char* e = std::getenv("APC_XCD_REMAP")) xcd_remap = std::atoi(e) != 0;
+  if (const char* e = std::getenv("APC_XCD_REMAP")) xcd_remap = std::max(0, std::min(2, std::atoi(e)));
+  int32_t passa_nt = 1;
+  if (const char* e = std::getenv("APC_PASSA_NT")) passa_nt = std::atoi(e) != 0;
   if (const char* e = std::getenv("APC_PASSA_SPLIT")) nsplit_req = std::atoi(e);
   if (const char* e = std::getenv("APC_GROUP_BLOCKS")) group_blocks = std::atoi(e);
+  int32_t passb_nt = 1;
+  if (const char* e = std::getenv("APC_PASSB_NT")) passb_nt = std::atoi(e) != 0;
   if (const char* e = std::getenv("APC_PASSA_ROWS")) {
     const int r = std::atoi(e);
     if (r == 8 || r == 16 || r == 32) passa_rows = r;
@@ -1071,6 +1077,8 @@ apc_status apc_setup(apc_plan* out, const double* A, int64_t lda, const double* 
   P->gamma = given ? gamma : NAN;
   P->eta = given ? eta : NAN;
   P->xcd_remap = xcd_remap;
+  P->passb_nt = passb_nt;
+  P->passa_nt = passa_nt;
   P->passa_rows = passa_rows;
   P->tile_start.assign(1, 0);
   for (int i = 0; i < m; ++i)

@@ -41,9 +41,11 @@ struct RowdotArgs {
   int64_t out_stride;
   int32_t nsplit;
   int64_t split_cols;
-  int32_t xcd_remap;          // 1: give each XCD a contiguous range of tiles
+  int32_t xcd_remap;          // 1: give each XCD a contiguous range of tiles;
+                              // 2: walk the tiles from last to first
   int32_t rows_per_tile;      // 8, 16 or 32 (must match the tile lists)
   int32_t tile_begin;         // first tile of this launch (block-tile lists only)
+  int32_t nt_loads = 1;       // 1: non-temporal loads of C
 };
 
 template <typename TQ>
@@ -69,6 +71,7 @@ struct PassBArgs {
   double* xbar;
   double gamma;
   int32_t blk_begin;
+  int32_t nt_loads;           // 1: non-temporal loads of C
 };
 
 // Columns per pass-B slab for an element size.

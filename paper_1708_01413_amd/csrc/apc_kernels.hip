@@ -30,22 +30,32 @@ namespace {
 
 // ------------------------------------------------------------------ helpers
 
+// 16-byte loads of the streamed factor.  Every element of C is read once per
+// pass, so the loads are non-temporal: they do not displace the vectors that
+// are reused (d_i, w, x_bar) from the caches, and streaming reads measured
+// ~7.0 TB/s this way against ~6.3 TB/s with ordinary loads.
+typedef float f32x4_t __attribute__((ext_vector_type(4)));
+typedef double f64x2_t __attribute__((ext_vector_type(2)));
 template <typename T>
 struct V16;
 template <>
 struct V16<float> {
   static constexpr int W = 4;
+  template <bool NT = true>
   __device__ static inline void load(const float* p, float (&o)[4]) {
-    const float4 v = *reinterpret_cast<const float4*>(p);
-    o[0] = v.x; o[1] = v.y; o[2] = v.z; o[3] = v.w;
+    const f32x4_t* q = reinterpret_cast<const f32x4_t*>(p);
+    const f32x4_t v = NT ? __builtin_nontemporal_load(q) : *q;
+    o[0] = v[0]; o[1] = v[1]; o[2] = v[2]; o[3] = v[3];
   }
 };
 template <>
 struct V16<double> {
   static constexpr int W = 2;
+  template <bool NT = true>
   __device__ static inline void load(const double* p, double (&o)[2]) {
-    const double2 v = *reinterpret_cast<const double2*>(p);
-    o[0] = v.x; o[1] = v.y;
+    const f64x2_t* q = reinterpret_cast<const f64x2_t*>(p);
+    const f64x2_t v = NT ? __builtin_nontemporal_load(q) : *q;
+    o[0] = v[0]; o[1] = v[1];
   }
 };
 
@@ -67,7 +77,7 @@ inline unsigned grid_for(int64_t work, int per) {
 // One workgroup per (row tile, column split).  The difference vector d of the
 // tile's block is held in registers one chunk (U sweeps of 256 x 16 B) at a
 // time; every row of the tile is streamed with 16-byte loads against it.
-template <typename TQ, typename TA, int ROWS, int U>
+template <typename TQ, typename TA, int ROWS, int U, bool NT>
 __global__ __launch_bounds__(kThreads) void k_rowdot(RowdotArgs<TQ, TA> a) {
   constexpr int W = V16<TQ>::W;
   constexpr int SWEEP = kThreads * W;
@@ -75,11 +85,13 @@ __global__ __launch_bounds__(kThreads) void k_rowdot(RowdotArgs<TQ, TA> a) {
 
   const int total = a.ntiles * a.nsplit;
   int q = blockIdx.x;
-  if (a.xcd_remap) {
+  if (a.xcd_remap == 1) {
     const int per = (total + kXcds - 1) / kXcds;
     q = (blockIdx.x % kXcds) * per + blockIdx.x / kXcds;
+  } else if (a.xcd_remap == 2) {
+    q = total - 1 - static_cast<int>(blockIdx.x);
   }
-  if (q >= total) return;
+  if (q < 0 || q >= total) return;
   const int Lrel = q / a.nsplit;
   const int split = q - Lrel * a.nsplit;
   const int L = a.tile_begin + Lrel;
@@ -132,7 +144,7 @@ __global__ __launch_bounds__(kThreads) void k_rowdot(RowdotArgs<TQ, TA> a) {
           const int64_t j = base + u * SWEEP + tcol;
           if (j < c1) {
             TQ qv[W];
-            V16<TQ>::load(crow + j, qv);
+            V16<TQ>::template load<NT>(crow + j, qv);
 #pragma unroll
             for (int e = 0; e < W; ++e) acc[r] = fma(static_cast<TA>(qv[e]), d[u][e], acc[r]);
           }
@@ -163,7 +175,8 @@ __global__ __launch_bounds__(kThreads) void k_rowdot(RowdotArgs<TQ, TA> a) {
 // all rows of the block over its own 64 x 16 B of the slab, so each row read
 // by the workgroup is 4 KB contiguous and no cross-wave combine is needed.
 // w_r is the sum of pass A's column-split partials, added in split order.
-template <typename TQ, int RU>
+// NT selects non-temporal loads of C.
+template <typename TQ, int RU, bool NT>
 __global__ __launch_bounds__(kThreads) void k_pass_b(PassBArgs<TQ> a) {
   constexpr int W = V16<TQ>::W;
   constexpr int SW = kThreads * W;  // columns per slab
@@ -189,7 +202,7 @@ __global__ __launch_bounds__(kThreads) void k_pass_b(PassBArgs<TQ> a) {
 #pragma unroll
     for (int u = 0; u < RU; ++u) {
       wr[u] = coef(r + u);
-      V16<TQ>::load(a.C + (r + u) * a.ldc + col, qv[u]);
+      V16<TQ>::template load<NT>(a.C + (r + u) * a.ldc + col, qv[u]);
     }
 #pragma unroll
     for (int u = 0; u < RU; ++u)
@@ -199,7 +212,7 @@ __global__ __launch_bounds__(kThreads) void k_pass_b(PassBArgs<TQ> a) {
   for (; r < r1; ++r) {
     TQ qv[W];
     const TQ wr = coef(r);
-    V16<TQ>::load(a.C + r * a.ldc + col, qv);
+    V16<TQ>::template load<NT>(a.C + r * a.ldc + col, qv);
 #pragma unroll
     for (int e = 0; e < W; ++e) acc[e] = fma(wr, qv[e], acc[e]);
   }
@@ -811,21 +824,23 @@ static hipError_t rowdot_impl(const RowdotArgs<TQ, TA>& a, hipStream_t s) {
   if (a.ntiles <= 0) return hipSuccess;
   const int total = a.ntiles * a.nsplit;
   unsigned grid = static_cast<unsigned>(total);
-  if (a.xcd_remap) grid = static_cast<unsigned>(((total + kXcds - 1) / kXcds) * kXcds);
+  if (a.xcd_remap == 1) grid = static_cast<unsigned>(((total + kXcds - 1) / kXcds) * kXcds);
   constexpr int U = rowdot_unroll<TQ>();
+#define APC_ROWDOT_CASE(R)                                                                  \
+  case R:                                                                                   \
+    if (a.nt_loads)                                                                         \
+      hipLaunchKernelGGL((k_rowdot<TQ, TA, R, U, true>), dim3(grid), dim3(kThreads), 0, s, a); \
+    else                                                                                    \
+      hipLaunchKernelGGL((k_rowdot<TQ, TA, R, U, false>), dim3(grid), dim3(kThreads), 0, s, a); \
+    break;
   switch (a.rows_per_tile) {
-    case 8:
-      hipLaunchKernelGGL((k_rowdot<TQ, TA, 8, U>), dim3(grid), dim3(kThreads), 0, s, a);
-      break;
-    case 16:
-      hipLaunchKernelGGL((k_rowdot<TQ, TA, 16, U>), dim3(grid), dim3(kThreads), 0, s, a);
-      break;
-    case 32:
-      hipLaunchKernelGGL((k_rowdot<TQ, TA, 32, U>), dim3(grid), dim3(kThreads), 0, s, a);
-      break;
+    APC_ROWDOT_CASE(8)
+    APC_ROWDOT_CASE(16)
+    APC_ROWDOT_CASE(32)
     default:
       return hipErrorInvalidValue;
   }
+#undef APC_ROWDOT_CASE
   return hipGetLastError();
 }
 
@@ -837,7 +852,10 @@ template <typename TQ>
 static hipError_t pass_b_impl(const PassBArgs<TQ>& a, hipStream_t s) {
   const unsigned grid = static_cast<unsigned>(a.nslab) * static_cast<unsigned>(a.m);
   if (grid == 0) return hipSuccess;
-  hipLaunchKernelGGL((k_pass_b<TQ, 8>), dim3(grid), dim3(kThreads), 0, s, a);
+  if (a.nt_loads)
+    hipLaunchKernelGGL((k_pass_b<TQ, 8, true>), dim3(grid), dim3(kThreads), 0, s, a);
+  else
+    hipLaunchKernelGGL((k_pass_b<TQ, 8, false>), dim3(grid), dim3(kThreads), 0, s, a);
   return hipGetLastError();
 }
 
