@@ -436,8 +436,8 @@ def main():
     dom, dom_bytes, dom_ms = (("pass_b", bytes_b_l, avg_b) if avg_b >= avg_a
                               else ("pass_a", bytes_a_l, avg_a))
     achieved = dom_bytes / (dom_ms * 1e-3) / 1e9
-    dom_label, dom_fn = {"pass_a": ("k_rowdot<float, float, 8, 2>", "k_rowdot"),
-                         "pass_b": ("k_pass_b<float, 8>", "k_pass_b")}[dom]
+    dom_label, dom_fn = {"pass_a": ("k_rowdot<float, float, 8, 2, true>", "k_rowdot"),
+                         "pass_b": ("k_pass_b<float, 8, true>", "k_pass_b")}[dom]
 
     out = {
         "metric": METRIC,
