@@ -122,12 +122,13 @@ def _err(plan, xs, xs_norm):
 MFMA_PEAK_TFLOPS = {"f32": 157.3, "bf16": 2500.0, "f64": 78.6}
 
 
-def time_plain(apc, A, b, off, xs, prec, target, ws, max_updates=400, anchor=None):
+def time_plain(apc, A, b, off, xs, prec, target, ws, max_updates=400, anchor=None, gamma=None,
+               eta=None):
     """Setup + the number of updates that reaches `target` relative error (counted
     in an untimed run), timed end to end with the stream synchronised."""
     import torch
     xs_norm = float(torch.linalg.norm(xs))
-    plan = apc.Plan(A, b, off, prec, workspace=ws, anchor_every=anchor)
+    plan = apc.Plan(A, b, off, prec, workspace=ws, anchor_every=anchor, gamma=gamma, eta=eta)
     T, err = 0, _err(plan, xs, xs_norm)
     while err > target and T < max_updates:
         plan.iterate(1)
@@ -139,11 +140,12 @@ def time_plain(apc, A, b, off, xs, prec, target, ws, max_updates=400, anchor=Non
         res = {"reached": False, "updates_tried": T, "floor_err": err}
         if target < 1e-5:
             res["time_to_%.0e" % (10 * target)] = time_plain(apc, A, b, off, xs, prec,
-                                                              10 * target, ws, max_updates, anchor)
+                                                              10 * target, ws, max_updates, anchor,
+                                                              gamma, eta)
         return res
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    plan = apc.Plan(A, b, off, prec, workspace=ws, anchor_every=anchor)
+    plan = apc.Plan(A, b, off, prec, workspace=ws, anchor_every=anchor, gamma=gamma, eta=eta)
     t1 = time.perf_counter()
     tot, pa, pb, pv = plan.iterate_timed(T)
     torch.cuda.synchronize()
@@ -267,6 +269,57 @@ def many_systems(apc, synth, dev, count=256):
     return res
 
 
+def adjoint_workload(apc, synth, dev):
+    """N = n = 4096, A = G/sqrt(n) + 2I, k = 16, m = 32 blocks of 128, FP32, T = 200,
+    checkpoint every 14, L = 1/2 ||x_bar(T) - x_target||^2."""
+    import torch
+    S = synth.shifted_square(4096, 32, k=16, shift=2.0, seed=70, with_target=True)
+    A = torch.from_numpy(S.A).to(dev)
+    b = torch.from_numpy(S.B).to(dev)
+    xt = torch.from_numpy(S.extra["x_target"]).to(dev)
+    plan = apc.Plan(A, b, S.off, "f32")
+    plan.iterate(200)
+    r = plan.xbar() - xt
+    plan.backward(r, 200, 14)                       # warm
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plan.restart()
+    plan.iterate(200)
+    r = plan.xbar() - xt
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    dB, dg, de = plan.backward(r, 200, 14)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    ref = torch.linalg.solve(A.T.contiguous(), r)
+    res = {"workload": "N=n=4096, A=G/sqrt(n)+2I, k=16, m=32, FP32, T=200, checkpoint every 14",
+           "forward_ms": round((t1 - t0) * 1e3, 2), "backward_ms": round((t2 - t1) * 1e3, 2),
+           "dB_vs_A^-T_r_rel": float(torch.linalg.norm(dB - ref) / torch.linalg.norm(ref)),
+           "dL_dgamma": dg, "dL_deta": de}
+    plan.close()
+    return res
+
+
+def cimmino_baseline(apc, synth, dev):
+    """Block Cimmino (Sec. 4.5) on the benchmark system, run as APC with gamma = 1 and
+    eta = 2 / (mu_min + mu_max) (Prop. 2: nu = eta / m, the optimal Cimmino step)."""
+    import torch
+    S = synth.tall_gaussian_16k()
+    A = torch.from_numpy(S.A).to(dev)
+    b = torch.from_numpy(S.B).to(dev)
+    xs = torch.from_numpy(S.xstar).to(dev)
+    ws = torch.empty(apc.Plan.workspace_bytes(S.N, S.n, S.off, "f32"), dtype=torch.uint8, device=dev)
+    p = apc.Plan(A, b, S.off, "f32", workspace=ws)
+    prm = p.params()
+    p.close()
+    eta = 2.0 / (prm["mu_min"] + prm["mu_max"])
+    out = {"workload": "tall Gaussian N=16384 n=8192 m=64, FP32, gamma=1, eta=2/(mu_min+mu_max)",
+           "time_to_1e-6": time_plain(apc, A, b, S.off, xs, "f32", 1e-6, ws, max_updates=1000,
+                                      gamma=1.0, eta=eta)}
+    del A, b, xs, ws
+    return out
+
+
 def secondary(apc, synth, dev):
     """Batched and mixed-precision workloads, each against plain FP32 on the same inputs."""
     import torch
@@ -307,6 +360,9 @@ def secondary(apc, synth, dev):
     del A, b, xs, ws, S
     torch.cuda.empty_cache()
     out["many_systems_fp32"] = many_systems(apc, synth, dev)
+    torch.cuda.empty_cache()
+    out["adjoint_fp32"] = adjoint_workload(apc, synth, dev)
+    out["block_cimmino_baseline"] = cimmino_baseline(apc, synth, dev)
     torch.cuda.empty_cache()
     # Mixed precision vs plain FP32: N = n = 16384, A = G/sqrt(n) + alpha I, k = 128, m = 64.
     n, k, m = 16384, 128, 64
