@@ -84,7 +84,7 @@ __device__ inline void mma_piece(const u32x4& a, const u32x4& b, f64x4& c, doubl
 // right-hand sides of its column group.  Grid: (rows / (64 RT)) x ncg x nsplit,
 // with the split index fastest so that, dealt round-robin over the 8 XCDs, one
 // XCD works on one split (nsplit | 8) and keeps that split's V in its L2.
-template <typename T, int RT, int NCT>
+template <typename T, int RT, int NCT, int PF>
 __global__ __launch_bounds__(256) void k_tn(TnArgs a) {
   using Acc = typename TnTraits<T>::Acc;
   using Part = typename TnTraits<T>::Part;
@@ -118,53 +118,59 @@ __global__ __launch_bounds__(256) void k_tn(TnArgs a) {
   for (int t = 0; t < RT; ++t)
 #pragma unroll
     for (int ct = 0; ct < NCT; ++ct) acc[t][ct] = Acc{};
-  u32x4 mc[RT][4], mn[RT][4], vst[NCT];
-
-  if (nsteps > 0) {
+  // Ring of PF + 1 register sets for M: the loads for step s + PF are issued
+  // while step s computes.  The step loop is unrolled by the ring size so that
+  // every slot index is a compile-time constant.
+  constexpr int D = PF + 1;
+  u32x4 mr[D][RT][4], vst[NCT];
+  auto load_m = [&](u32x4 (&dst)[RT][4], int step) {
+    const int64_t o = static_cast<int64_t>(step) * kStep;
 #pragma unroll
     for (int t = 0; t < RT; ++t)
 #pragma unroll
-      for (int p = 0; p < 4; ++p) mc[t][p] = *reinterpret_cast<const u32x4*>(mrow[t] + p * kE);
+      for (int p = 0; p < 4; ++p) dst[t][p] = *reinterpret_cast<const u32x4*>(mrow[t] + o + p * kE);
+  };
+  auto load_v = [&](int step) {
+    const int64_t o = static_cast<int64_t>(step) * kStep;
 #pragma unroll
     for (int u = 0; u < NCT; ++u)
-      vst[u] = *reinterpret_cast<const u32x4*>(vsrc + static_cast<int64_t>(16 * u) * a.ldv);
+      vst[u] = *reinterpret_cast<const u32x4*>(vsrc + static_cast<int64_t>(16 * u) * a.ldv + o);
+  };
+#pragma unroll
+  for (int s0 = 0; s0 < PF; ++s0)
+    if (s0 < nsteps) load_m(mr[s0], s0);
+  if (nsteps > 0) {
+    load_v(0);
 #pragma unroll
     for (int u = 0; u < NCT; ++u) vs[0][vr + 16 * u][vp] = vst[u];
   }
   __syncthreads();
-  for (int step = 0; step < nsteps; ++step) {
-    const int buf = step & 1;
-    const bool more = step + 1 < nsteps;
-    if (more) {
-      const int64_t o = static_cast<int64_t>(step + 1) * kStep;
+  for (int step0 = 0; step0 < nsteps; step0 += D) {
 #pragma unroll
-      for (int t = 0; t < RT; ++t)
+    for (int i = 0; i < D; ++i) {
+      const int step = step0 + i;
+      if (step < nsteps) {  // uniform across the workgroup
+        const int buf = step & 1;
+        const bool more = step + 1 < nsteps;
+        if (step + PF < nsteps) load_m(mr[(i + PF) % D], step + PF);
+        if (more) load_v(step + 1);
 #pragma unroll
-        for (int p = 0; p < 4; ++p) mn[t][p] = *reinterpret_cast<const u32x4*>(mrow[t] + o + p * kE);
+        for (int p = 0; p < 4; ++p) {
+          u32x4 bf[NCT];
 #pragma unroll
-      for (int u = 0; u < NCT; ++u)
-        vst[u] = *reinterpret_cast<const u32x4*>(vsrc + static_cast<int64_t>(16 * u) * a.ldv + o);
-    }
+          for (int ct = 0; ct < NCT; ++ct) bf[ct] = vs[buf][ct * 16 + li][4 * g + p];
 #pragma unroll
-    for (int p = 0; p < 4; ++p) {
-      u32x4 bf[NCT];
+          for (int t = 0; t < RT; ++t)
 #pragma unroll
-      for (int ct = 0; ct < NCT; ++ct) bf[ct] = vs[buf][ct * 16 + li][4 * g + p];
+            for (int ct = 0; ct < NCT; ++ct)
+              mma_piece(mr[i][t][p], bf[ct], acc[t][ct], static_cast<T*>(nullptr));
+        }
+        if (more) {
 #pragma unroll
-      for (int t = 0; t < RT; ++t)
-#pragma unroll
-        for (int ct = 0; ct < NCT; ++ct) mma_piece(mc[t][p], bf[ct], acc[t][ct], static_cast<T*>(nullptr));
-    }
-    if (more) {
-#pragma unroll
-      for (int u = 0; u < NCT; ++u) vs[buf ^ 1][vr + 16 * u][vp] = vst[u];
-    }
-    __syncthreads();
-    if (more) {
-#pragma unroll
-      for (int t = 0; t < RT; ++t)
-#pragma unroll
-        for (int p = 0; p < 4; ++p) mc[t][p] = mn[t][p];
+          for (int u = 0; u < NCT; ++u) vs[buf ^ 1][vr + 16 * u][vp] = vst[u];
+        }
+        __syncthreads();
+      }
     }
   }
 
@@ -185,30 +191,39 @@ __global__ __launch_bounds__(256) void k_tn(TnArgs a) {
     }
 }
 
-template <typename T, int RT>
+template <typename T, int RT, int PF>
 hipError_t tn_nct(const TnArgs& a, hipStream_t s) {
   const int nct = a.kp >= 128 ? 8 : a.kp / 16;
   const int64_t ncg = a.kp / (16 * nct);
   const int64_t blocks = (a.rows / (64 * RT)) * ncg * a.nsplit;
   const dim3 grid(static_cast<unsigned>(blocks)), block(256);
   switch (nct) {
-    case 1: k_tn<T, RT, 1><<<grid, block, 0, s>>>(a); break;
-    case 2: k_tn<T, RT, 2><<<grid, block, 0, s>>>(a); break;
-    case 4: k_tn<T, RT, 4><<<grid, block, 0, s>>>(a); break;
-    case 8: k_tn<T, RT, 8><<<grid, block, 0, s>>>(a); break;
+    case 1: k_tn<T, RT, 1, PF><<<grid, block, 0, s>>>(a); break;
+    case 2: k_tn<T, RT, 2, PF><<<grid, block, 0, s>>>(a); break;
+    case 4: k_tn<T, RT, 4, PF><<<grid, block, 0, s>>>(a); break;
+    case 8: k_tn<T, RT, 8, PF><<<grid, block, 0, s>>>(a); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
 
-template <typename T>
+template <typename T, int PF>
 hipError_t tn_rt(int rt, const TnArgs& a, hipStream_t s) {
   switch (rt) {
-    case 1: return tn_nct<T, 1>(a, s);
-    case 2: return tn_nct<T, 2>(a, s);
+    case 1: return tn_nct<T, 1, PF>(a, s);
+    case 2: return tn_nct<T, 2, PF>(a, s);
     case 4:
       if constexpr (sizeof(T) == 8) return hipErrorInvalidValue;
-      else return tn_nct<T, 4>(a, s);
+      else return tn_nct<T, 4, PF>(a, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <typename T>
+hipError_t tn_pf(int rt, int pf, const TnArgs& a, hipStream_t s) {
+  switch (pf) {
+    case 1: return tn_rt<T, 1>(rt, a, s);
+    case 2: return tn_rt<T, 2>(rt, a, s);
     default: return hipErrorInvalidValue;
   }
 }
@@ -403,14 +418,14 @@ unsigned grid_stride_blocks(int64_t total) {
 
 }  // namespace
 
-hipError_t launch_tn(int type, int rt, const TnArgs& a, hipStream_t s) {
+hipError_t launch_tn(int type, int rt, int pf, const TnArgs& a, hipStream_t s) {
   if (a.kp < 16 || (a.kp > 128 && a.kp % 128) || (a.kp <= 128 && (a.kp & (a.kp - 1))) ||
       a.rows % (64 * rt) || a.nsplit < 1 || a.nsplit > kTnMaxSplit)
     return hipErrorInvalidValue;
   switch (type) {
-    case kTnF64: return tn_rt<double>(rt, a, s);
-    case kTnF32: return tn_rt<float>(rt, a, s);
-    case kTnBF16: return tn_rt<__bf16>(rt, a, s);
+    case kTnF64: return tn_pf<double>(rt, pf, a, s);
+    case kTnF32: return tn_pf<float>(rt, pf, a, s);
+    case kTnBF16: return tn_pf<__bf16>(rt, pf, a, s);
     default: return hipErrorInvalidValue;
   }
 }

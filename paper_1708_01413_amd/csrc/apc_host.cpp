@@ -324,6 +324,7 @@ struct TnChoice {
   int rt = 2;
   int nsplit = 1;
   float us = 0.f;  // measured time per launch when tuned
+  int pf = 1;      // steps of the streamed operand loaded ahead
 };
 
 struct apc_plan_s {
@@ -493,24 +494,24 @@ apc_status update_gemm(apc_plan_s* P, hipEvent_t* ev, int* kinds, int* nev) {
                                  P->at<double>(L.yref), P->stream));
     TnArgs a = tn_args(P->ws + L.C64p, L.np, L.Np, P->ws + L.yref, L.np, P->kp, L.np, P->tnR,
                        kTnF64, part, L.Np);
-    HIP_TRY(launch_tn(kTnF64, P->tnR.rt, a, P->stream));
+    HIP_TRY(launch_tn(kTnF64, P->tnR.rt, P->tnR.pf, a, P->stream));
     if (ev) { HIP_TRY(hipEventRecord(ev[e], P->stream)); kinds[e++] = 0; }
     HIP_TRY(launch_tn_sum_cast(kTnF64, part, P->tnR.nsplit, P->kp, L.Np, L.Np, P->ws + L.W64,
                                L.Np, P->stream));
     if (ev) { HIP_TRY(hipEventRecord(ev[e], P->stream)); kinds[e++] = 2; }
     TnArgs b = tn_args(P->ws + L.C64T, L.Np, L.np, P->ws + L.W64, L.Np, P->kp, L.Np, P->tnX0,
                        kTnF64, part, L.np);
-    HIP_TRY(launch_tn(kTnF64, P->tnX0.rt, b, P->stream));
+    HIP_TRY(launch_tn(kTnF64, P->tnX0.rt, P->tnX0.pf, b, P->stream));
     if (ev) { HIP_TRY(hipEventRecord(ev[e], P->stream)); kinds[e++] = 1; }
     HIP_TRY(launch_tn_update(P->tq, 1, update_args(P, P->tnX0, 2), P->stream));
     if (ev) { HIP_TRY(hipEventRecord(ev[e], P->stream)); kinds[e++] = 2; }
   } else {
-    HIP_TRY(launch_tn(P->tq, P->tnA.rt, pass_a_args(P), P->stream));
+    HIP_TRY(launch_tn(P->tq, P->tnA.rt, P->tnA.pf, pass_a_args(P), P->stream));
     if (ev) { HIP_TRY(hipEventRecord(ev[e], P->stream)); kinds[e++] = 0; }
     HIP_TRY(launch_tn_sum_cast(P->tq, part, P->tnA.nsplit, P->kp, L.Np, L.Np, P->ws + L.Wq, L.Np,
                                P->stream));
     if (ev) { HIP_TRY(hipEventRecord(ev[e], P->stream)); kinds[e++] = 2; }
-    HIP_TRY(launch_tn(P->tq, P->tnB.rt, pass_b_args(P), P->stream));
+    HIP_TRY(launch_tn(P->tq, P->tnB.rt, P->tnB.pf, pass_b_args(P), P->stream));
     if (ev) { HIP_TRY(hipEventRecord(ev[e], P->stream)); kinds[e++] = 1; }
     HIP_TRY(launch_tn_update(P->tq, P->tq == kTnF64, update_args(P, P->tnB, 0), P->stream));
     if (ev) { HIP_TRY(hipEventRecord(ev[e], P->stream)); kinds[e++] = 2; }
@@ -527,7 +528,7 @@ apc_status start_gemm(apc_plan_s* P, const double* c_rhs) {
   const Layout& L = P->L;
   HIP_TRY(launch_tn_pack(kTnF64, c_rhs, P->N, P->kp, P->N, 0, P->ws + L.c64p, L.Np, P->kp,
                          P->stream));
-  HIP_TRY(launch_tn(kTnF64, P->tnX0.rt, x0_args(P), P->stream));
+  HIP_TRY(launch_tn(kTnF64, P->tnX0.rt, P->tnX0.pf, x0_args(P), P->stream));
   HIP_TRY(launch_tn_update(P->tq, 1, update_args(P, P->tnX0, 1), P->stream));
   P->since_start = 0;
   return APC_OK;
@@ -536,7 +537,7 @@ apc_status start_gemm(apc_plan_s* P, const double* c_rhs) {
 // R = B - A X (X: kp x np FP64, RHS-major) into R (RHS-major, stride N), k columns.
 apc_status gemm_residual(apc_plan_s* P, const double* X, double* R) {
   const Layout& L = P->L;
-  HIP_TRY(launch_tn(kTnF64, P->tnR.rt, resid_args(P, X), P->stream));
+  HIP_TRY(launch_tn(kTnF64, P->tnR.rt, P->tnR.pf, resid_args(P, X), P->stream));
   HIP_TRY(launch_tn_resid(P->at<double>(L.tnpart), P->tnR.nsplit, P->kp, L.Np, P->N, P->k, P->B,
                           P->ldb, R, P->N, P->stream));
   return APC_OK;
@@ -561,7 +562,7 @@ apc_status tn_tune(apc_plan_s* P, int type, TnArgs base, TnChoice* out) {
   const char* fix_rt = std::getenv("APC_TN_RT");
   const char* fix_ns = std::getenv("APC_TN_SPLIT");
   const char* tune = std::getenv("APC_TN_TUNE");
-  if (fix_rt || fix_ns || (tune && std::atoi(tune) == 0)) {
+  if (fix_rt || fix_ns || std::getenv("APC_TN_PF") || (tune && std::atoi(tune) == 0)) {
     // Fixed shape (not cached): 128 rows per workgroup, the smallest split
     // with >= 512 workgroups, unless the environment names them.
     TnChoice c;
@@ -573,6 +574,7 @@ apc_status tn_tune(apc_plan_s* P, int type, TnArgs base, TnChoice* out) {
     for (int ns : splits)
       if (blocks(c.rt, ns) >= 512) { c.nsplit = ns; break; }
     if (fix_ns) c.nsplit = std::max(1, std::min(kTnMaxSplit, std::atoi(fix_ns)));
+    if (const char* e = std::getenv("APC_TN_PF")) c.pf = std::atoi(e) == 2 ? 2 : 1;
     *out = c;
     return APC_OK;
   }
@@ -595,13 +597,16 @@ apc_status tn_tune(apc_plan_s* P, int type, TnArgs base, TnChoice* out) {
     for (int ns : splits) {
       if (blocks(rt, ns) < 64 && !(rt == 1 && ns == 8)) continue;
       if (static_cast<int64_t>(ns) * tn_step_elems(type) > base.K && ns > 1) continue;
-      TnChoice c;
-      c.rt = rt;
-      c.nsplit = ns;
-      cand.push_back(c);
+      for (int pf = 1; pf <= 2; ++pf) {
+        TnChoice c;
+        c.rt = rt;
+        c.nsplit = ns;
+        c.pf = pf;
+        cand.push_back(c);
+      }
     }
   }
-  if (cand.empty()) cand.push_back(TnChoice{1, 1, 0.f});
+  if (cand.empty()) cand.push_back(TnChoice{1, 1, 0.f, 1});
   TnChoice best;
   {
     hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -613,10 +618,10 @@ apc_status tn_tune(apc_plan_s* P, int type, TnArgs base, TnChoice* out) {
       TnArgs a = base;
       a.nsplit = c.nsplit;
       a.klen = round_up((a.K + c.nsplit - 1) / c.nsplit, tn_step_elems(type));
-      hipError_t err = launch_tn(type, c.rt, a, P->stream);  // warm-up
+      hipError_t err = launch_tn(type, c.rt, c.pf, a, P->stream);  // warm-up
       for (int r = 0; err == hipSuccess && r < 1; ++r) {
         err = hipEventRecord(e0, P->stream);
-        for (int q = 0; err == hipSuccess && q < 3; ++q) err = launch_tn(type, c.rt, a, P->stream);
+        for (int q = 0; err == hipSuccess && q < 3; ++q) err = launch_tn(type, c.rt, c.pf, a, P->stream);
         if (err == hipSuccess) err = hipEventRecord(e1, P->stream);
       }
       float ms = 0.f;
@@ -1567,9 +1572,9 @@ apc_status apc_backward(apc_plan p, const double* dXbar, int64_t ldd, int32_t T,
     // Reverse through it: X bh by the same two contractions as an update.
     for (int32_t t = t1 - 1; t >= t0; --t) {
       TnArgs pa = tn_args(P->ws + L.Cq, L.np, L.Np, bq, L.np, P->kp, L.np, P->tnA, P->tq, part, L.Np);
-      HIP_TRY(launch_tn(P->tq, P->tnA.rt, pa, st));
+      HIP_TRY(launch_tn(P->tq, P->tnA.rt, P->tnA.pf, pa, st));
       HIP_TRY(launch_tn_sum_cast(P->tq, part, P->tnA.nsplit, P->kp, L.Np, L.Np, P->ws + L.Wq, L.Np, st));
-      HIP_TRY(launch_tn(P->tq, P->tnB.rt, pass_b_args(P), st));
+      HIP_TRY(launch_tn(P->tq, P->tnB.rt, P->tnB.pf, pass_b_args(P), st));
       const double* s_t = seg(t - t0);
       const double* s_n = seg(t - t0 + 1);
       TnAdjointArgs ad{part, P->tnB.nsplit, P->kp, L.np, L.np, a, bh, g0, s_t, s_t + cnt,
@@ -1584,7 +1589,7 @@ apc_status apc_backward(apc_plan p, const double* dXbar, int64_t ldd, int32_t T,
                                     : static_cast<const void*>(P->ws + L.C64p);
   double* W64 = P->tq == kTnF64 ? P->at<double>(L.Wq) : P->at<double>(L.W64);
   TnArgs pc = tn_args(C64, L.np, L.Np, g0, L.np, P->kp, L.np, P->tnR, kTnF64, part, L.Np);
-  HIP_TRY(launch_tn(kTnF64, P->tnR.rt, pc, st));
+  HIP_TRY(launch_tn(kTnF64, P->tnR.rt, P->tnR.pf, pc, st));
   HIP_TRY(launch_tn_sum_cast(kTnF64, part, P->tnR.nsplit, P->kp, L.Np, L.Np, W64, L.Np, st));
   double* t1b = P->at<double>(L.Rb);
   double* t2b = P->at<double>(L.cb);

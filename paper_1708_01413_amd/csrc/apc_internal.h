@@ -134,7 +134,8 @@ struct TnArgs {
   void* part;
   int64_t ldp;
 };
-hipError_t launch_tn(int type, int rt, const TnArgs& a, hipStream_t s);
+// rt: 16-row tiles per wave (1, 2, 4; FP64 1, 2); pf: steps of M loaded ahead (1, 2).
+hipError_t launch_tn(int type, int rt, int pf, const TnArgs& a, hipStream_t s);
 int tn_step_elems(int type);
 // out[c*ldo + r] = TQ(sum over the nsplit partials in split order), r < rows, c < kp.
 hipError_t launch_tn_sum_cast(int type, const void* part, int32_t nsplit, int32_t kp, int64_t ldp,
