@@ -36,6 +36,9 @@ design notes):
                     n * eps * max|diag R_i| (thin QR of A_i^T).
   R7 singular    -- no unique solution when mu_min <= n * eps (App. A, steady
                     state: the error vanishes iff mu_min != 0).
+  R13 D-HBM start -- Sec. 4.3 gives no start for the comparison methods; D-HBM
+                    and its preconditioned form start from APC's x_bar(0) with
+                    zero momentum, so every method starts from the same point.
 
 Parity note: every function here is pinned by tests that do not reuse its
 arithmetic (definitions written differently, brute force, closed forms, the
@@ -356,3 +359,111 @@ def cimmino_step(A, B, off, xbar: np.ndarray, nu: float) -> np.ndarray:
     for Ai, bi in zip(blocks(np.asarray(A, dtype=np.float64), off), blocks(B, off)):
         upd = upd + Ai.T @ np.linalg.solve(Ai @ Ai.T, bi - Ai @ xbar)
     return xbar + nu * upd
+
+
+# ----------------------------------------------------------------------------
+# Sec. 4.3 (distributed heavy-ball method, D-HBM) and Sec. 6 (distributed
+# preconditioning): the comparison methods, run on the same row blocks
+# ----------------------------------------------------------------------------
+
+def hbm_optimal_params(lam_min: float, lam_max: float):
+    """Optimal heavy-ball step alpha, momentum beta and rate for a quadratic
+    whose Hessian spectrum lies in [lam_min, lam_max] (the rate Sec. 4.3
+    quotes for D-HBM).
+
+    For one eigenvalue lam the iteration's characteristic polynomial is
+    z^2 - (1 + beta - alpha lam) z + beta; its roots are complex with
+    |z| = sqrt(beta) exactly when (1 - sqrt(beta))^2 <= alpha lam <=
+    (1 + sqrt(beta))^2.  Putting lam_min and lam_max on the two ends gives
+    sqrt(alpha) (sqrt(lam_max) + sqrt(lam_min)) = 2 and
+    sqrt(alpha) (sqrt(lam_max) - sqrt(lam_min)) = 2 sqrt(beta), so
+    alpha = 4 / (sqrt(lam_max) + sqrt(lam_min))^2, sqrt(beta) = rho =
+    (sqrt(kappa) - 1) / (sqrt(kappa) + 1).
+    """
+    if not (0.0 < lam_min <= lam_max):
+        raise OracleError("need 0 < lam_min <= lam_max")
+    a, c = np.sqrt(lam_max), np.sqrt(lam_min)
+    alpha = 4.0 / (a + c) ** 2
+    rho = (a - c) / (a + c)
+    return float(alpha), float(rho * rho), float(rho)
+
+
+def normal_spectrum(Cb: list[np.ndarray]):
+    """(lam_min, lam_max) of sum_i C_i^T C_i, the Hessian of the D-HBM
+    objective (1/2) sum_i ||C_i x - d_i||^2 (Sec. 4.3)."""
+    n = Cb[0].shape[1]
+    H = np.zeros((n, n))
+    for Ci in Cb:
+        H = H + Ci.T @ Ci
+    lam = np.linalg.eigvalsh(H)
+    if lam[0] <= n * EPS * lam[-1]:
+        raise OracleError("singular normal matrix: no unique solution")
+    return float(lam[0]), float(lam[-1])
+
+
+def precondition(A: np.ndarray, B: np.ndarray, off: np.ndarray):
+    """Sec. 6: every machine premultiplies its equations by (A_i A_i^T)^{-1/2};
+    returns the blocks C_i = (A_i A_i^T)^{-1/2} A_i and
+    d_i = (A_i A_i^T)^{-1/2} b_i.  The inverse square root is taken from the
+    symmetric eigendecomposition of A_i A_i^T."""
+    A = np.asarray(A, dtype=np.float64)
+    B = _as_cols(B)
+    Cb, db = [], []
+    for Ai, bi in zip(blocks(A, off), blocks(B, off)):
+        lam, U = np.linalg.eigh(Ai @ Ai.T)
+        if lam[0] <= Ai.shape[1] * EPS * lam[-1]:
+            raise OracleError("rank-deficient block")
+        S = U @ np.diag(1.0 / np.sqrt(lam)) @ U.T
+        Cb.append(S @ Ai)
+        db.append(S @ bi)
+    return Cb, db
+
+
+def dhbm_step(Cb, db, x: np.ndarray, z: np.ndarray, alpha: float, beta: float):
+    """One D-HBM update (Sec. 4.3): every machine forms its gradient
+    C_i^T (C_i x - d_i); the master sums them in block order, then
+    z <- beta z + sum, x <- x - alpha z."""
+    g = np.zeros_like(x)
+    for Ci, di in zip(Cb, db):
+        g = g + Ci.T @ (Ci @ x - di)
+    zn = beta * z + g
+    return x - alpha * zn, zn
+
+
+def dhbm_run(A, B, off, T: int, preconditioned: bool = False, alpha: float | None = None,
+             beta: float | None = None, x0=None, xstar=None, keep_traj: bool = False):
+    """T updates of D-HBM (Sec. 4.3) on the blocks [A_i, b_i], or on the
+    preconditioned blocks of Sec. 6.  alpha/beta default to the optimum for the
+    spectrum of sum_i C_i^T C_i.  The start is x(0) = APC's initial average
+    (Alg. 1 with reading R2), z(0) = 0 (reading R13), unless x0 is given."""
+    A = np.asarray(A, dtype=np.float64)
+    B = _as_cols(B)
+    if preconditioned:
+        Cb, db = precondition(A, B, off)
+    else:
+        Cb, db = blocks(A, off), blocks(B, off)
+    lam_min, lam_max = normal_spectrum(Cb)
+    a_opt, b_opt, rho = hbm_optimal_params(lam_min, lam_max)
+    alpha = a_opt if alpha is None else alpha
+    beta = b_opt if beta is None else beta
+    if x0 is None:
+        Qt, R = factor(A, off)
+        x = initial_average(init_local(Qt, R, B, off))
+    else:
+        x = _as_cols(np.array(x0, dtype=np.float64))
+    z = np.zeros_like(x)
+    out = {"alpha": alpha, "beta": beta, "rho": rho, "lam_min": lam_min, "lam_max": lam_max}
+    errs, traj = [], []
+    for t in range(T + 1):
+        if xstar is not None:
+            errs.append(rel_error(x, xstar))
+        if keep_traj:
+            traj.append(x.copy())
+        if t < T:
+            x, z = dhbm_step(Cb, db, x, z, alpha, beta)
+    out["x"] = x
+    if xstar is not None:
+        out["err"] = np.array(errs)
+    if keep_traj:
+        out["traj"] = np.stack(traj)
+    return out

@@ -428,3 +428,123 @@ def test_table2_tall_gaussian_context():
     assert T_apc == pytest.approx(ref["T"]["APC"], rel=0.25)
     assert T_hbm == pytest.approx(ref["T"]["D-HBM"], rel=0.25)
     assert T_apc < T_hbm
+
+
+# ------------------------------------------------------- Sec. 4.3 and Sec. 6: D-HBM
+
+
+def _hbm_radius(lams, alpha, beta):
+    """Largest root magnitude of z^2 - (1 + beta - alpha lam) z + beta over lams."""
+    return max(float(np.max(np.abs(np.roots([1.0, -(1.0 + beta - alpha * lam), beta]))))
+               for lam in lams)
+
+
+def test_hbm_params_minimise_radius():
+    """The heavy-ball optimum: its radius over the whole interval equals the
+    rate Sec. 4.3 prints, (sqrt(kappa)-1)/(sqrt(kappa)+1), and no (alpha, beta)
+    on a grid around it does better."""
+    lo, hi = 0.3, 7.5
+    lams = np.linspace(lo, hi, 41)
+    alpha, beta, rho = O.hbm_optimal_params(lo, hi)
+    kappa = hi / lo
+    assert abs(rho - (np.sqrt(kappa) - 1) / (np.sqrt(kappa) + 1)) < 1e-14
+    assert abs(_hbm_radius(lams, alpha, beta) - rho) < 1e-6
+    best = min(_hbm_radius(lams, a, b) for a in np.linspace(0.5 * alpha, 1.5 * alpha, 41)
+               for b in np.linspace(0.0, 0.99, 100))
+    assert best >= rho - 1e-6
+
+
+def test_dhbm_step_is_the_heavy_ball_recursion():
+    """Sec. 4.3's (z, x) form equals the three-term recursion
+    x(t+1) = x(t) - alpha (H x(t) - A^T b) + beta (x(t) - x(t-1)), H = A^T A
+    formed densely, with x(-1) = x(0)."""
+    S = small_system(N=30, n=12, m=5, seed=21)
+    alpha, beta = 0.01, 0.6
+    out = O.dhbm_run(S.A, S.B, S.off, T=12, alpha=alpha, beta=beta, keep_traj=True)
+    H = S.A.T @ S.A
+    g0 = S.A.T @ S.B
+    prev = cur = out["traj"][0][:, 0]
+    for t in range(12):
+        nxt = cur - alpha * (H @ cur - g0) + beta * (cur - prev)
+        prev, cur = cur, nxt
+        np.testing.assert_allclose(out["traj"][t + 1][:, 0], cur, rtol=0, atol=1e-12 * np.abs(cur).max())
+
+
+def test_dhbm_radius_at_optimum_is_the_paper_rate():
+    """The 2n x 2n iteration matrix on (x(t), x(t-1)) at the optimal parameters
+    has spectral radius (sqrt(kappa(A^T A)) - 1)/(sqrt(kappa(A^T A)) + 1)."""
+    S = small_system(N=24, n=10, m=4, seed=22)
+    lo, hi = O.normal_spectrum(O.blocks(S.A, S.off))
+    ev = np.linalg.eigvalsh(S.A.T @ S.A)
+    assert abs(lo - ev[0]) < 1e-12 * ev[-1] and abs(hi - ev[-1]) < 1e-12 * ev[-1]
+    alpha, beta, rho = O.hbm_optimal_params(lo, hi)
+    n = S.A.shape[1]
+    M = np.zeros((2 * n, 2 * n))
+    M[:n, :n] = (1 + beta) * np.eye(n) - alpha * (S.A.T @ S.A)
+    M[:n, n:] = -beta * np.eye(n)
+    M[n:, :n] = np.eye(n)
+    radius = np.max(np.abs(np.linalg.eigvals(M)))
+    kappa = ev[-1] / ev[0]
+    assert abs(radius - (np.sqrt(kappa) - 1) / (np.sqrt(kappa) + 1)) < 1e-6
+    assert abs(rho - (np.sqrt(kappa) - 1) / (np.sqrt(kappa) + 1)) < 1e-12
+
+
+def test_dhbm_converges_to_direct_solve():
+    S = synth.shifted_square(40, 4, k=2, shift=2.0, seed=23)
+    ref = np.linalg.solve(S.A, S.B)
+    for pre in (False, True):
+        out = O.dhbm_run(S.A, S.B, S.off, T=120, preconditioned=pre)
+        assert np.abs(out["x"] - ref).max() / np.abs(ref).max() < 1e-11
+
+
+def test_preconditioner_identities():
+    """Sec. 6: C_i = (A_i A_i^T)^{-1/2} A_i has orthonormal rows, C_i^T C_i is
+    the projector onto the row space of A_i (I - P_i), so sum_i C_i^T C_i = m X;
+    the preconditioned system keeps the solution (C_i x* = d_i)."""
+    S = small_system(N=30, n=14, m=4, seed=24, sizes=[9, 6, 8, 7])
+    Cb, db = O.precondition(S.A, S.B, S.off)
+    m = len(Cb)
+    for Ci, di, Ai in zip(Cb, db, O.blocks(S.A, S.off)):
+        np.testing.assert_allclose(Ci @ Ci.T, np.eye(Ci.shape[0]), atol=1e-13)
+        np.testing.assert_allclose(Ci.T @ Ci, np.eye(S.A.shape[1]) - O.projector(Ai), atol=1e-13)
+    np.testing.assert_allclose(sum(Ci.T @ Ci for Ci in Cb), m * O.X_matrix(S.A, S.off), atol=1e-12)
+    for Ci, di in zip(Cb, db):
+        np.testing.assert_allclose(Ci @ S.xstar, di[:, 0], atol=1e-12 * np.abs(S.xstar).max())
+
+
+def test_preconditioned_dhbm_rate_equals_apc_rate():
+    """Sec. 6's claim: D-HBM on the preconditioned system has APC's optimal
+    rate, since kappa(C^T C) = kappa(X); and the observed decay follows it."""
+    S = small_system(N=48, n=24, m=4, seed=25)
+    lo, hi = O.normal_spectrum(O.precondition(S.A, S.B, S.off)[0])
+    mu_min, mu_max = O.spectrum(S.A, S.off)
+    assert abs(lo / hi - mu_min / mu_max) < 1e-10 * (mu_min / mu_max)
+    _, _, rho_hbm = O.hbm_optimal_params(lo, hi)
+    _, _, rho_apc = O.optimal_params(mu_min, mu_max)
+    assert abs(rho_hbm - rho_apc) < 1e-12
+    out = O.dhbm_run(S.A, S.B, S.off, T=45, preconditioned=True, xstar=S.xstar)
+    err = out["err"]
+    rate = (err[45] / err[20]) ** (1 / 25)
+    assert rho_hbm * 0.6 <= rate <= rho_hbm * 1.1
+
+
+@pytest.mark.parametrize("gamma,eta", [(None, None), (1.2, 3.0), (0.7, 1.5)])
+def test_apc_average_is_preconditioned_heavy_ball(gamma, eta):
+    """Eliminating y from the (y, x_bar) form of eq. (2a)-(2b) gives
+    x_bar(t+1) = x_bar(t) - gamma eta (X x_bar(t) - x_bar(0))
+                 + (gamma - 1)(eta - 1)(x_bar(t) - x_bar(t-1)),
+    which is D-HBM on Sec. 6's preconditioned blocks (gradient
+    m (X x - x_bar(0))) with alpha = gamma eta / m, beta = (gamma-1)(eta-1),
+    from the same start.  Theorem 1's optimum maps onto the heavy-ball optimum,
+    so with default parameters both runs are the same sequence."""
+    S = small_system(N=36, n=18, m=4, seed=26)
+    a = O.apc_run(S.A, S.B, S.off, T=25, gamma=gamma, eta=eta, keep_traj=True)
+    m = len(S.off) - 1
+    g, e = a["gamma"], a["eta"]
+    kw = {} if gamma is None else {"alpha": g * e / m, "beta": (g - 1) * (e - 1)}
+    h = O.dhbm_run(S.A, S.B, S.off, T=25, preconditioned=True, keep_traj=True, **kw)
+    if gamma is None:
+        assert abs(h["alpha"] - g * e / m) < 1e-12 * h["alpha"]
+        assert abs(h["beta"] - (g - 1) * (e - 1)) < 1e-12
+    scale = np.abs(a["traj"]).max()
+    np.testing.assert_allclose(h["traj"], a["traj"], rtol=0, atol=1e-12 * scale)

@@ -112,6 +112,34 @@ def _adjoint_variant(direct_average_path=True, start_transposed=False):
     return adj
 
 
+def _hbm_params_unsquared(lam_min, lam_max):
+    alpha, beta, rho = _orig_hbm_params(lam_min, lam_max)
+    return alpha, rho, rho                                       # momentum rho instead of rho^2
+
+
+def _precondition_full_inverse(A, B, off):
+    B = B[:, None] if B.ndim == 1 else B
+    Cb, db = [], []
+    for Ai, bi in zip(O.blocks(A, off), O.blocks(B, off)):
+        S = np.linalg.inv(Ai @ Ai.T)                             # (A_i A_i^T)^{-1}, not ^{-1/2}
+        Cb.append(S @ Ai)
+        db.append(S @ bi)
+    return Cb, db
+
+
+def _dhbm_step_gradient_first(Cb, db, x, z, alpha, beta):
+    g = sum(Ci.T @ (Ci @ x - di) for Ci, di in zip(Cb, db))
+    return x - alpha * g, beta * z + g                           # x moves along g, not along new z
+
+
+def _dhbm_step_wrong_sign(Cb, db, x, z, alpha, beta):
+    g = sum(Ci.T @ (di - Ci @ x) for Ci, di in zip(Cb, db))      # gradient sign flipped
+    zn = beta * z + g
+    return x - alpha * zn, zn
+
+
+_orig_hbm_params = O.hbm_optimal_params
+
 _adjoint_no_average_path = _adjoint_variant(direct_average_path=False)
 _adjoint_no_average_path.__name__ = "_adjoint_no_average_path"
 _adjoint_start_transposed = _adjoint_variant(start_transposed=True)
@@ -135,6 +163,15 @@ MUTANTS = [
     ("apc_adjoint", _adjoint_start_transposed, ["test_adjoint_matches_central_differences",
                                                 "test_adjoint_of_the_start",
                                                 "test_adjoint_converged_gradient"]),
+    ("hbm_optimal_params", _hbm_params_unsquared, ["test_hbm_params_minimise_radius",
+                                                   "test_dhbm_radius_at_optimum_is_the_paper_rate",
+                                                   "test_apc_average_is_preconditioned_heavy_ball"]),
+    ("precondition", _precondition_full_inverse, ["test_preconditioner_identities",
+                                                  "test_preconditioned_dhbm_rate_equals_apc_rate"]),
+    ("dhbm_step", _dhbm_step_gradient_first, ["test_dhbm_step_is_the_heavy_ball_recursion",
+                                              "test_apc_average_is_preconditioned_heavy_ball"]),
+    ("dhbm_step", _dhbm_step_wrong_sign, ["test_dhbm_step_is_the_heavy_ball_recursion",
+                                          "test_dhbm_converges_to_direct_solve"]),
 ]
 
 
@@ -145,6 +182,8 @@ def _run_pin(name):
             fn(seed)
     elif name == "test_adjoint_matches_central_differences":
         fn(24, 12, 3, 2, 15, 5)
+    elif name == "test_apc_average_is_preconditioned_heavy_ball":
+        fn(None, None)
     else:
         fn()
 
