@@ -316,6 +316,74 @@ apc_status apc_batch_get_launch(apc_batch b, int32_t* grid, int32_t* items_a, in
 /* Release the batch (and its captured graphs). */
 void apc_batch_destroy(apc_batch b);
 
+/* ---- Comparison methods on the same passes (Sec. 4.3, Sec. 6) -----------
+ *
+ * The distributed heavy-ball method (D-HBM, Sec. 4.3) on plan p's row blocks:
+ *     z <- beta z + sum_i C_i^T (C_i x - d_i),     x <- x - alpha z,
+ * with [C_i, d_i] = [A_i, b_i] (APC_HBM_PLAIN), or Sec. 6's preconditioned
+ * blocks [(A_i A_i^T)^{-1/2} A_i, (A_i A_i^T)^{-1/2} b_i]
+ * (APC_HBM_PRECONDITIONED).  The preconditioned blocks are realised as
+ * [Q_i^T, c_i] with the plan's factor and c_i = R_i^{-T} b_i: they differ from
+ * Sec. 6's by an orthogonal p_i x p_i factor per block, so the gradient
+ * C_i^T (C_i x - d_i) = Q_i (Q_i^T x - c_i) is the same.  One update is a row
+ * pass (w_r = C_r . x - d_r, FP64 accumulation), a block pass
+ * (sum over the block's rows of w_r C_r, per block) and an elementwise step that
+ * adds the blocks in a fixed order; the factor or the copy of A is streamed in
+ * the plan's precision (APC_F32: FP32), vectors and arithmetic are FP64.
+ * Start (not fixed by the paper): x(0) = the plan's x_bar(0) (Alg. 1
+ * initialisation), z(0) = 0, so both methods start where APC starts.  Needs a
+ * k = 1 APC_F64 / APC_F32 plan in the per-block form (else APC_EUNSUPPORTED).
+ * The plan must outlive the object; its own state is not changed. */
+typedef struct apc_hbm_s* apc_hbm;
+
+typedef enum {
+  APC_HBM_PLAIN = 0,          /* blocks [A_i, b_i] (Sec. 4.3)                  */
+  APC_HBM_PRECONDITIONED = 1  /* blocks (A_i A_i^T)^{-1/2} [A_i, b_i] (Sec. 6) */
+} apc_hbm_kind;
+
+/* Bytes of device workspace for a heavy-ball run of this kind on plan p:
+ * x, z, per-block partial sums, row-pass partials, and for APC_HBM_PLAIN a
+ * copy of A in the plan's precision padded like the factor plus a copy of b.
+ * 0 for an unsupported plan or kind. */
+size_t apc_hbm_workspace_bytes(apc_plan p, int32_t kind);
+
+/* Create the run.  alpha, beta: the step and momentum; if either is NaN both
+ * are set to the heavy-ball optimum alpha = 4/(sqrt(L)+sqrt(l))^2,
+ * beta = ((sqrt(L)-sqrt(l))/(sqrt(L)+sqrt(l)))^2 for the spectrum [l, L] of
+ * sum_i C_i^T C_i: m times the plan's enclosure of X's spectrum for the
+ * preconditioned kind (sum_i Q_i Q_i^T = m X), and for the plain kind the
+ * enclosure of A^T A's spectrum from the same GPU Lanczos procedure as the
+ * plan's (run on the streamed copy of A).  workspace: device, 256-byte
+ * aligned, >= apc_hbm_workspace_bytes, caller-owned.  Synchronises.
+ * APC_EINVAL for a bad kind or small workspace, APC_ESINGULAR when A^T A is
+ * numerically singular. */
+apc_status apc_hbm_create(apc_hbm* out, apc_plan p, int32_t kind, double alpha, double beta,
+                          void* workspace, size_t ws_bytes);
+
+/* T updates (asynchronous, on the plan's stream). */
+apc_status apc_hbm_iterate(apc_hbm h, int32_t T);
+
+/* Back to x(0), z = 0 (asynchronous). */
+apc_status apc_hbm_restart(apc_hbm h);
+
+/* Copy x (n doubles) to device memory with entry stride ldx >= 1.
+ * Asynchronous. */
+apc_status apc_hbm_get_x(apc_hbm h, double* x, int64_t ldx);
+
+/* ||b - A x|| / ||b|| in FP64 (host result).  Synchronises. */
+apc_status apc_hbm_residual(apc_hbm h, double* relres);
+
+/* The run's parameters (host pointers, each may be NULL): alpha, beta, the
+ * spectrum enclosure [lam_min, lam_max] they came from (NaN when the caller
+ * gave alpha and beta), the predicted rate sqrt(beta) at the optimum, the
+ * Lanczos steps spent (0 when none ran), and the updates applied. */
+apc_status apc_hbm_get_params(apc_hbm h, double* alpha, double* beta, double* lam_min,
+                              double* lam_max, double* rho, int32_t* lanczos_steps,
+                              int64_t* iters);
+
+/* Release the host-side object. */
+void apc_hbm_destroy(apc_hbm h);
+
 /* Number of updates applied since setup (host). */
 int64_t apc_iterations(apc_plan p);
 

@@ -41,7 +41,10 @@ EXPORTED = (
     "apc_batch_workspace_bytes", "apc_batch_create", "apc_batch_iterate",
     "apc_batch_iterate_graph", "apc_batch_residuals", "apc_batch_activate", "apc_batch_solve",
     "apc_batch_get_launch", "apc_batch_destroy",
+    "apc_hbm_workspace_bytes", "apc_hbm_create", "apc_hbm_iterate", "apc_hbm_restart",
+    "apc_hbm_get_x", "apc_hbm_residual", "apc_hbm_get_params", "apc_hbm_destroy",
 )
+APC_HBM_PLAIN, APC_HBM_PRECONDITIONED = 0, 1
 
 
 class ApcError(RuntimeError):
@@ -108,6 +111,14 @@ def _load() -> ctypes.CDLL:
         "apc_batch_solve": (i32, [vp, f64, i32, i32, i32, Pi, Pd]),
         "apc_batch_get_launch": (i32, [vp, Pi, Pi, Pi, Pi, Pf]),
         "apc_batch_destroy": (None, [vp]),
+        "apc_hbm_workspace_bytes": (ctypes.c_size_t, [vp, i32]),
+        "apc_hbm_create": (i32, [ctypes.POINTER(vp), vp, i32, f64, f64, vp, ctypes.c_size_t]),
+        "apc_hbm_iterate": (i32, [vp, i32]),
+        "apc_hbm_restart": (i32, [vp]),
+        "apc_hbm_get_x": (i32, [vp, vp, i64]),
+        "apc_hbm_residual": (i32, [vp, Pd]),
+        "apc_hbm_get_params": (i32, [vp, Pd, Pd, Pd, Pd, Pd, Pi, P64]),
+        "apc_hbm_destroy": (None, [vp]),
         "apc_optimal_params": (i32, [f64, f64, Pd, Pd, Pd]),
         "apc_tridiag_extremes": (i32, [Pd, Pd, i32, i32, Pd, Pd, Pd, Pd]),
         "apc_destroy": (None, [vp]),
@@ -519,6 +530,66 @@ class Batch:
     def close(self):
         if getattr(self, "handle", None) is not None:
             lib.apc_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class HeavyBall:
+    """The distributed heavy-ball method (Sec. 4.3) on a plan's row blocks, plain
+    (kind APC_HBM_PLAIN) or on Sec. 6's preconditioned blocks
+    (APC_HBM_PRECONDITIONED), through apc_hbm_*.  alpha/beta None: the
+    heavy-ball optimum from the estimated spectrum.  The plan must outlive it."""
+
+    def __init__(self, plan, kind: int = APC_HBM_PRECONDITIONED, alpha=None, beta=None):
+        import torch
+        self._torch = torch
+        self.plan = plan
+        nb = int(lib.apc_hbm_workspace_bytes(plan.handle, kind))
+        if nb == 0:
+            raise ApcError(APC_EUNSUPPORTED, lib.apc_last_error().decode(errors="replace"))
+        self.workspace = torch.empty(nb + 256, dtype=torch.uint8, device=plan.device)
+        wp = (self.workspace.data_ptr() + 255) // 256 * 256
+        nan = float("nan")
+        h = ctypes.c_void_p()
+        _check(lib.apc_hbm_create(ctypes.byref(h), plan.handle, kind,
+                                  nan if alpha is None else float(alpha),
+                                  nan if beta is None else float(beta), wp, nb))
+        self.handle = h.value
+
+    def iterate(self, T: int):
+        _check(lib.apc_hbm_iterate(self.handle, T))
+
+    def restart(self):
+        _check(lib.apc_hbm_restart(self.handle))
+
+    def x(self):
+        out = self._torch.empty(self.plan.n, dtype=self._torch.float64, device=self.plan.device)
+        _check(lib.apc_hbm_get_x(self.handle, out.data_ptr(), 1))
+        return out
+
+    def residual(self) -> float:
+        r = ctypes.c_double()
+        _check(lib.apc_hbm_residual(self.handle, ctypes.byref(r)))
+        return r.value
+
+    def params(self) -> dict:
+        v = [ctypes.c_double() for _ in range(5)]
+        steps, iters = ctypes.c_int32(), ctypes.c_int64()
+        _check(lib.apc_hbm_get_params(self.handle, *[ctypes.byref(q) for q in v],
+                                      ctypes.byref(steps), ctypes.byref(iters)))
+        return {"alpha": v[0].value, "beta": v[1].value, "lam_min": v[2].value,
+                "lam_max": v[3].value, "rho": v[4].value, "lanczos_steps": steps.value,
+                "iters": iters.value}
+
+    def close(self):
+        if getattr(self, "handle", None) is not None:
+            self.plan.stream.synchronize()
+            lib.apc_hbm_destroy(self.handle)
             self.handle = None
 
     def __del__(self):

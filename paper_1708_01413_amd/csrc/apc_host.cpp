@@ -699,7 +699,24 @@ apc_status rowdot64(apc_plan_s* P, const double* va, const double* vb, int64_t l
 // X v for the eigenvalue estimate, through the factor the iteration uses
 // (FP64, or FP32 storage with FP64 accumulation): u = C v, Y_i = Q_i u_i,
 // out = (1/m) sum_i Y_i.
-apc_status x_matvec(apc_plan_s* P, const double* v, double* out) {
+// A symmetric operator v -> scale * sum_i C_i^T (C_i v) over the plan's row
+// blocks, for a row-major N x ldc matrix C streamed in FP32 or FP64: the
+// plan's X (C = the factor, scale 1/m), or A^T A (C = a padded copy of A).
+struct NormalOp {
+  const void* C;
+  bool f32;
+  double scale;
+};
+
+NormalOp x_operator(const apc_plan_s* P) {
+  const bool f32 = P->prec == APC_F32 && !P->gemm;  // the k = 1 FP32 factor; else the FP64 one
+  return NormalOp{f32 ? static_cast<const void*>(P->at<float>(P->L.C32))
+                      : static_cast<const void*>(P->C64()),
+                  f32, 1.0 / P->m};
+}
+
+// out = op(v), FP64 vectors and accumulation.
+apc_status normal_matvec(apc_plan_s* P, const NormalOp& op, const double* v, double* out) {
   const Layout& L = P->L;
   double* u = P->at<double>(L.w);
   double* Y = P->at<double>(L.Y);
@@ -707,39 +724,44 @@ apc_status x_matvec(apc_plan_s* P, const double* v, double* out) {
   for (int i0 = 0; i0 < P->m; i0 += g) {
     const int i1 = std::min(P->m, i0 + g);
     const int32_t t0 = P->tile_start[i0], nt = P->tile_start[i1] - t0;
-    if (P->prec == APC_F32 && !P->gemm) {  // the k = 1 FP32 factor; else the FP64 one
-      RowdotArgs<float, double> a{P->at<float>(L.C32), L.ldc, P->ta(0), P->ta(1), P->ta(2), nt, 0,
+    if (op.f32) {
+      const float* C = static_cast<const float*>(op.C);
+      RowdotArgs<float, double> a{C, L.ldc, P->ta(0), P->ta(1), P->ta(2), nt, 0,
                                   v, nullptr, 0, nullptr, 0, u, 0, 1, L.ldc, P->xcd_remap,
                                   P->passa_rows, t0};
       HIP_TRY(launch_rowdot_f32x64(a, P->stream));
-      ExpandArgs<float> e{P->at<float>(L.C32), L.ldc, P->doff(), i1 - i0,
+      ExpandArgs<float> e{C, L.ldc, P->doff(), i1 - i0,
                           static_cast<int32_t>((L.ldc + expand_slab(4) - 1) / expand_slab(4)),
                           P->N, u, 1, 0, Y, L.ldc, 1.0, 0.0, i0};
       HIP_TRY(launch_expand_f32(e, P->stream));
     } else {
-      RowdotArgs<double, double> a{P->C64(), L.ldc, P->ta(0), P->ta(1), P->ta(2), nt, 0, v,
+      const double* C = static_cast<const double*>(op.C);
+      RowdotArgs<double, double> a{C, L.ldc, P->ta(0), P->ta(1), P->ta(2), nt, 0, v,
                                    nullptr, 0, nullptr, 0, u, 0, 1, L.ldc, P->xcd_remap,
                                    P->passa_rows, t0};
       HIP_TRY(launch_rowdot_f64(a, P->stream));
-      ExpandArgs<double> e{P->C64(), L.ldc, P->doff(), i1 - i0,
+      ExpandArgs<double> e{C, L.ldc, P->doff(), i1 - i0,
                            static_cast<int32_t>((L.ldc + expand_slab(8) - 1) / expand_slab(8)),
                            P->N, u, 1, 0, Y, L.ldc, 1.0, 0.0, i0};
       HIP_TRY(launch_expand_f64(e, P->stream));
     }
   }
-  HIP_TRY(launch_combine_f64(Y, L.ldc, P->m, L.ldc, 1.0 / P->m, 0.0, out, nullptr, 0, P->stream));
+  HIP_TRY(launch_combine_f64(Y, L.ldc, P->m, L.ldc, op.scale, 0.0, out, nullptr, 0, P->stream));
   return APC_OK;
 }
 
-// Lanczos with full (twice classical Gram-Schmidt) reorthogonalisation on
-// X v = (1/m) sum_i Q_i (Q_i^T v), on the GPU in FP64 arithmetic.  Returns an
-// interval [lo, hi] for Theorem 1's closed form.  Ritz values lie inside the
+// Lanczos with full (twice classical Gram-Schmidt) reorthogonalisation on a
+// NormalOp (the plan's X v = (1/m) sum_i Q_i (Q_i^T v), or A^T A v for the
+// heavy-ball comparison), on the GPU in FP64 arithmetic.  Returns an interval
+// [lo, hi] (hi capped at `cap`: X's spectrum lies in [0, 1]) for the closed
+// forms of the optimal parameters.  Ritz values lie inside the
 // spectrum, and a spectrum that pokes out of [lo, hi] costs far more than a
 // slightly wide interval: an eigenvalue delta outside turns the roots of p_i
 // real and raises the rate by ~sqrt(delta), while widening the interval by
 // delta raises it by O(delta).  So both ends are pushed outwards by a margin
 // that covers the Ritz values' remaining movement.
-apc_status lanczos(apc_plan_s* P, double* lo_out, double* hi_out, int* steps_out) {
+apc_status lanczos(apc_plan_s* P, const NormalOp& op, double cap, double* lo_out, double* hi_out,
+                   int* steps_out) {
   const int64_t ldc = P->L.ldc, n = P->n;
   const int kmax = static_cast<int>(P->L.kmax);
   const int64_t hstride = P->L.kmax + 1;
@@ -776,7 +798,7 @@ apc_status lanczos(apc_plan_s* P, double* lo_out, double* hi_out, int* steps_out
   bool done = false;
   int steps = 0;
   for (int j = 0; j < kmax && !done; ++j) {
-    ST_TRY(x_matvec(P, V + static_cast<int64_t>(j) * ldc, vt));
+    ST_TRY(normal_matvec(P, op, V + static_cast<int64_t>(j) * ldc, vt));
     for (int pass = 0; pass < 2; ++pass) {
       double* hh = pass == 0 ? h : h2;
       RowdotArgs<double> r{V, ldc, nullptr, nullptr, nullptr, (j + 1 + 7) / 8, j + 1, vt, nullptr,
@@ -835,12 +857,12 @@ apc_status lanczos(apc_plan_s* P, double* lo_out, double* hi_out, int* steps_out
                 "(theta in [%g, %g], bounds %g, %g); pass gamma and eta explicitly", kmax,
                 th_lo, th_hi, bd_lo, bd_hi);
   if (!(th_lo > n * std::numeric_limits<double>::epsilon() * th_hi))
-    return fail(APC_ESINGULAR, "mu_min(X) ~ 0 (Ritz value %g, mu_max %g): no unique solution",
-                th_lo, th_hi);
+    return fail(APC_ESINGULAR, "smallest eigenvalue ~ 0 (Ritz value %g, largest %g): no unique "
+                "solution", th_lo, th_hi);
   const double m_lo = std::max(std::min(bd_lo, 20.0 * d_lo), 1e-13 * th_hi);
   const double m_hi = std::max(std::min(bd_hi, 20.0 * d_hi), 1e-13 * th_hi);
   *lo_out = std::max(th_lo - m_lo, 0.5 * th_lo);
-  *hi_out = std::min(th_hi + m_hi, 1.0);
+  *hi_out = std::min(th_hi + m_hi, cap);
   return APC_OK;
 }
 
@@ -994,7 +1016,7 @@ apc_status setup_impl(apc_plan_s* P, const Tiles& T) {
   // Parameters: caller's, or Theorem 1's optimum from the estimated spectrum.
   if (std::isnan(P->gamma) || std::isnan(P->eta)) {
     double lo = 0, hi = 0;
-    ST_TRY(lanczos(P, &lo, &hi, &P->lanczos_steps));
+    ST_TRY(lanczos(P, x_operator(P), 1.0, &lo, &hi, &P->lanczos_steps));
     P->mu_min = lo;
     P->mu_max = hi;
     optimum(lo, hi, &P->gamma, &P->eta, &P->rho);
@@ -1934,5 +1956,233 @@ void apc_batch_destroy(apc_batch b) {
   }
   delete b;
 }
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ heavy-ball comparison
+
+// D-HBM (Sec. 4.3) on the plan's row blocks, plain or on Sec. 6's
+// preconditioned blocks (realised as [Q_i^T, c_i], which has the same
+// gradient).  The object keeps its own x, z and scratch; the plan's iterates
+// are not touched (its Lanczos scratch is reused at creation only).
+struct apc_hbm_s {
+  apc_plan_s* P = nullptr;
+  int32_t kind = 0;
+  char* ws = nullptr;
+  double* x = nullptr;      // ldc
+  double* z = nullptr;      // ldc
+  double* Y = nullptr;      // m x ldc per-block sums
+  double* w = nullptr;      // kMaxSplit x N row-pass partials
+  void* C = nullptr;        // the streamed matrix (plan's factor, or the copy of A)
+  const double* d = nullptr;  // per-row right-hand side (c or b)
+  double alpha = 0, beta = 0, lam_min = NAN, lam_max = NAN, rho = NAN;
+  int lanczos_steps = 0;
+  int64_t iters = 0;
+};
+
+namespace {
+
+struct HbmLayout {
+  size_t x, z, Y, w, A, b, total;
+};
+
+HbmLayout hbm_layout(const apc_plan_s* P, int32_t kind) {
+  HbmLayout H{};
+  size_t cur = 0;
+  auto take = [&](int64_t bytes) {
+    const size_t at = cur;
+    cur += static_cast<size_t>(round_up(std::max<int64_t>(bytes, 1), kAlign));
+    return at;
+  };
+  const int64_t ldc = P->L.ldc, d = sizeof(double);
+  H.x = take(ldc * d);
+  H.z = take(ldc * d);
+  H.Y = take(static_cast<int64_t>(P->m) * ldc * d);
+  H.w = take(static_cast<int64_t>(kMaxSplit) * P->N * d);
+  const int64_t sq = P->prec == APC_F32 ? 4 : 8;
+  H.A = take(kind == APC_HBM_PLAIN ? P->N * ldc * sq : 0);
+  H.b = take(kind == APC_HBM_PLAIN ? P->N * d : 0);
+  H.total = cur;
+  return H;
+}
+
+apc_status hbm_check(const apc_plan_s* P, int32_t kind) {
+  if (!P) return fail(APC_EINVAL, "plan is NULL");
+  if (kind != APC_HBM_PLAIN && kind != APC_HBM_PRECONDITIONED)
+    return fail(APC_EINVAL, "unknown heavy-ball kind %d", kind);
+  if (P->gemm || P->k != 1 || (P->prec != APC_F32 && P->prec != APC_F64))
+    return fail(APC_EUNSUPPORTED, "the heavy-ball comparison takes k = 1 APC_F64 / APC_F32 plans "
+                "in the per-block form");
+  return APC_OK;
+}
+
+// x(0) = the plan's x_bar(0) = (1/m) sum_i Q_i c_i (Alg. 1 initialisation,
+// recomputed from the stored c so the plan's state is not needed), z(0) = 0.
+apc_status hbm_start(apc_hbm_s* H) {
+  apc_plan_s* P = H->P;
+  const Layout& L = P->L;
+  ExpandArgs<double> e{P->C64(), L.ldc, P->doff(), P->m,
+                       static_cast<int32_t>((L.ldc + expand_slab(8) - 1) / expand_slab(8)), P->N,
+                       P->at<double>(L.ca), 1, 0, H->Y, L.ldc, 1.0, 0.0, 0};
+  HIP_TRY(launch_expand_f64(e, P->stream));
+  HIP_TRY(launch_combine_f64(H->Y, L.ldc, P->m, L.ldc, 1.0 / P->m, 0.0, H->x, nullptr, 0,
+                             P->stream));
+  HIP_TRY(launch_fill_u32(reinterpret_cast<unsigned*>(H->z), 2 * L.ldc, 0u, P->stream));
+  H->iters = 0;
+  return APC_OK;
+}
+
+// One update: w_r = C_r . x (row pass, FP64 accumulation, the plan's pass-A
+// tiling and column splits), Y_i = sum_{r in block i} (w_r - d_r) C_r (block
+// pass), then the heavy-ball step over the blocks' sums.
+apc_status hbm_update(apc_hbm_s* H) {
+  apc_plan_s* P = H->P;
+  const Layout& L = P->L;
+  const int32_t nt = P->tile_start[P->m];
+  const bool f32 = P->prec == APC_F32;
+  if (f32) {
+    const float* C = static_cast<const float*>(H->C);
+    RowdotArgs<float, double> a{C, L.ldc, P->ta(0), P->ta(1), P->ta(2), nt, 0, H->x, nullptr, 0,
+                                nullptr, 0, H->w, P->N, P->nsplit, P->split_cols, P->xcd_remap,
+                                P->passa_rows, 0, P->passa_nt};
+    HIP_TRY(launch_rowdot_f32x64(a, P->stream));
+    ExpandArgs<float> e{C, L.ldc, P->doff(), P->m,
+                        static_cast<int32_t>((L.ldc + expand_slab(4) - 1) / expand_slab(4)), P->N,
+                        H->w, P->nsplit, P->N, H->Y, L.ldc, 1.0, 0.0, 0, H->d};
+    HIP_TRY(launch_expand_f32(e, P->stream));
+  } else {
+    const double* C = static_cast<const double*>(H->C);
+    RowdotArgs<double, double> a{C, L.ldc, P->ta(0), P->ta(1), P->ta(2), nt, 0, H->x, nullptr, 0,
+                                 nullptr, 0, H->w, P->N, P->nsplit, P->split_cols, P->xcd_remap,
+                                 P->passa_rows, 0, P->passa_nt};
+    HIP_TRY(launch_rowdot_f64(a, P->stream));
+    ExpandArgs<double> e{C, L.ldc, P->doff(), P->m,
+                         static_cast<int32_t>((L.ldc + expand_slab(8) - 1) / expand_slab(8)), P->N,
+                         H->w, P->nsplit, P->N, H->Y, L.ldc, 1.0, 0.0, 0, H->d};
+    HIP_TRY(launch_expand_f64(e, P->stream));
+  }
+  HIP_TRY(launch_hbm_step(H->Y, L.ldc, P->m, P->n, H->alpha, H->beta, H->x, H->z, P->stream));
+  return APC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t apc_hbm_workspace_bytes(apc_plan p, int32_t kind) {
+  if (hbm_check(p, kind) != APC_OK) return 0;
+  return hbm_layout(p, kind).total;
+}
+
+apc_status apc_hbm_create(apc_hbm* out, apc_plan p, int32_t kind, double alpha, double beta,
+                          void* workspace, size_t ws_bytes) {
+  if (!out) return fail(APC_EINVAL, "out is NULL");
+  *out = nullptr;
+  ST_TRY(hbm_check(p, kind));
+  if (!workspace || reinterpret_cast<uintptr_t>(workspace) % kAlign != 0)
+    return fail(APC_EINVAL, "workspace must be a 256-byte aligned device pointer");
+  const HbmLayout L = hbm_layout(p, kind);
+  if (ws_bytes < L.total) return fail(APC_EINVAL, "workspace has %zu bytes, needs %zu", ws_bytes, L.total);
+  const bool given = !std::isnan(alpha) && !std::isnan(beta);
+  if (given && !(alpha > 0.0 && beta >= 0.0 && beta < 1.0 && std::isfinite(alpha)))
+    return fail(APC_EINVAL, "need alpha > 0 and 0 <= beta < 1 (got %g, %g)", alpha, beta);
+  std::unique_ptr<apc_hbm_s> H(new apc_hbm_s);
+  H->P = p;
+  H->kind = kind;
+  H->ws = static_cast<char*>(workspace);
+  H->x = reinterpret_cast<double*>(H->ws + L.x);
+  H->z = reinterpret_cast<double*>(H->ws + L.z);
+  H->Y = reinterpret_cast<double*>(H->ws + L.Y);
+  H->w = reinterpret_cast<double*>(H->ws + L.w);
+  const bool f32 = p->prec == APC_F32;
+  if (kind == APC_HBM_PLAIN) {
+    H->C = H->ws + L.A;
+    double* b = reinterpret_cast<double*>(H->ws + L.b);
+    HIP_TRY(launch_pad_cast(f32 ? 1 : 0, p->A, p->lda, p->N, p->n, H->C, p->L.ldc, p->stream));
+    HIP_TRY(launch_copy_strided(p->B, p->ldb, b, 1, p->N, 1, p->stream));
+    H->d = b;
+  } else {
+    H->C = f32 ? static_cast<void*>(p->at<float>(p->L.C32)) : static_cast<void*>(p->C64());
+    H->d = p->at<double>(p->L.ca);
+  }
+  if (given) {
+    H->alpha = alpha;
+    H->beta = beta;
+  } else {
+    double lo = 0, hi = 0;
+    if (kind == APC_HBM_PRECONDITIONED) {
+      // sum_i Q_i Q_i^T = m X: the plan's enclosure of X's spectrum, or a new
+      // one when the plan was given its parameters.
+      if (std::isnan(p->mu_min) || std::isnan(p->mu_max)) {
+        ST_TRY(lanczos(p, x_operator(p), 1.0, &lo, &hi, &H->lanczos_steps));
+      } else {
+        lo = p->mu_min;
+        hi = p->mu_max;
+      }
+      lo *= p->m;
+      hi *= p->m;
+    } else {
+      ST_TRY(lanczos(p, NormalOp{H->C, f32, 1.0}, std::numeric_limits<double>::infinity(), &lo,
+                     &hi, &H->lanczos_steps));
+    }
+    const double a = std::sqrt(hi), c = std::sqrt(lo);
+    H->alpha = 4.0 / ((a + c) * (a + c));
+    H->rho = (a - c) / (a + c);
+    H->beta = H->rho * H->rho;
+    H->lam_min = lo;
+    H->lam_max = hi;
+  }
+  ST_TRY(hbm_start(H.get()));
+  HIP_TRY(hipStreamSynchronize(p->stream));
+  *out = H.release();
+  return APC_OK;
+}
+
+apc_status apc_hbm_iterate(apc_hbm h, int32_t T) {
+  if (!h) return fail(APC_EINVAL, "heavy-ball run is NULL");
+  if (T < 0) return fail(APC_EINVAL, "T must be >= 0");
+  for (int32_t t = 0; t < T; ++t) ST_TRY(hbm_update(h));
+  h->iters += T;
+  return APC_OK;
+}
+
+apc_status apc_hbm_restart(apc_hbm h) {
+  if (!h) return fail(APC_EINVAL, "heavy-ball run is NULL");
+  return hbm_start(h);
+}
+
+apc_status apc_hbm_get_x(apc_hbm h, double* x, int64_t ldx) {
+  if (!h || !x || ldx < 1) return fail(APC_EINVAL, "bad argument");
+  HIP_TRY(launch_copy_strided(h->x, 1, x, ldx, h->P->n, 1, h->P->stream));
+  return APC_OK;
+}
+
+apc_status apc_hbm_residual(apc_hbm h, double* relres) {
+  if (!h || !relres) return fail(APC_EINVAL, "NULL argument");
+  apc_plan_s* P = h->P;
+  double* dst = P->at<double>(P->L.scal);
+  ST_TRY(residual_norm2(P, h->x, dst));
+  double r2 = 0;
+  HIP_TRY(hipMemcpyAsync(&r2, dst, sizeof r2, hipMemcpyDeviceToHost, P->stream));
+  HIP_TRY(hipStreamSynchronize(P->stream));
+  *relres = P->bnorm > 0 ? std::sqrt(r2) / P->bnorm : std::sqrt(r2);
+  return APC_OK;
+}
+
+apc_status apc_hbm_get_params(apc_hbm h, double* alpha, double* beta, double* lam_min,
+                              double* lam_max, double* rho, int32_t* lanczos_steps,
+                              int64_t* iters) {
+  if (!h) return fail(APC_EINVAL, "heavy-ball run is NULL");
+  if (alpha) *alpha = h->alpha;
+  if (beta) *beta = h->beta;
+  if (lam_min) *lam_min = h->lam_min;
+  if (lam_max) *lam_max = h->lam_max;
+  if (rho) *rho = h->rho;
+  if (lanczos_steps) *lanczos_steps = h->lanczos_steps;
+  if (iters) *iters = h->iters;
+  return APC_OK;
+}
+
+void apc_hbm_destroy(apc_hbm h) { delete h; }
 
 }  // extern "C"

@@ -96,6 +96,7 @@ struct ExpandArgs {
   double alpha;
   double beta;
   int32_t blk_begin;          // first block of this launch (off != null)
+  const double* wsub = nullptr;  // optional per-row value subtracted from w_r
 };
 
 inline int expand_slab(int elem_bytes) { return 64 * (16 / elem_bytes); }
@@ -301,6 +302,12 @@ hipError_t launch_trmm(const double* In, double* Out, int64_t ldc, const int64_t
 hipError_t launch_copy_t(const double* src, int64_t lds, double* dst, int64_t ldd, int64_t n,
                          int32_t k, hipStream_t s);
 hipError_t launch_cast_f32(const double* src, float* dst, int64_t count, hipStream_t s);
+// C <- A (N x n, row stride lda) in FP32 (f32 != 0) or FP64, zero-padded to ldc.
+hipError_t launch_pad_cast(int f32, const double* A, int64_t lda, int64_t N, int64_t n, void* C,
+                           int64_t ldc, hipStream_t s);
+// Heavy-ball step: g = sum_i Y_i (block order), z <- beta z + g, x <- x - alpha z.
+hipError_t launch_hbm_step(const double* Y, int64_t ldy, int32_t m, int64_t n, double alpha,
+                           double beta, double* x, double* z, hipStream_t s);
 hipError_t launch_fill_u32(unsigned* p, int64_t count, unsigned v, hipStream_t s);
 hipError_t launch_copy_strided(const double* src, int64_t lds, double* dst, int64_t ldd,
                                int64_t rows, int64_t cols, hipStream_t s);

@@ -374,6 +374,7 @@ __global__ __launch_bounds__(kThreads) void k_expand(ExpandArgs<TQ> a) {
     for (int64_t r = r0 + wv; r < r1; r += 4) {
       double wr = a.w[r];
       for (int sp = 1; sp < a.nsplit; ++sp) wr += a.w[sp * a.w_stride + r];
+      if (a.wsub) wr -= a.wsub[r];
       TQ q[W];
       V16<TQ>::load(a.C + r * a.ldc + col, q);
 #pragma unroll
@@ -709,6 +710,37 @@ __global__ void k_fill_u32(unsigned* p, int64_t count, unsigned v) {
     p[e] = v;
 }
 
+// C <- A zero-padded to ldc columns, converted to T.
+template <typename T>
+__global__ void k_pad_cast(const double* A, int64_t lda, int64_t N, int64_t n, T* C, int64_t ldc) {
+  for (int64_t r = blockIdx.x; r < N; r += gridDim.x)
+    for (int64_t j = threadIdx.x; j < ldc; j += blockDim.x)
+      C[r * ldc + j] = j < n ? static_cast<T>(A[r * lda + j]) : T(0);
+}
+
+// Heavy-ball step (Sec. 4.3) after the block pass: g = sum_i Y_i with the
+// blocks added in the same fixed order as the APC average, then
+// z <- beta z + g, x <- x - alpha z.  One column per lane of wave 0.
+__global__ __launch_bounds__(256) void k_hbm_step(const double* Y, int64_t ldy, int32_t m,
+                                                  int64_t n, double alpha, double beta, double* x,
+                                                  double* z) {
+  __shared__ double part[4][64];
+  const int lane = threadIdx.x & 63;
+  const int wv = threadIdx.x >> 6;
+  const int64_t j = static_cast<int64_t>(blockIdx.x) * 64 + lane;
+  double s = 0.0;
+  if (j < n)
+    for (int i = wv; i < m; i += 4) s += Y[static_cast<int64_t>(i) * ldy + j];
+  part[wv][lane] = s;
+  __syncthreads();
+  if (wv == 0 && j < n) {
+    const double g = (part[0][lane] + part[1][lane]) + (part[2][lane] + part[3][lane]);
+    const double zn = beta * z[j] + g;
+    z[j] = zn;
+    x[j] -= alpha * zn;
+  }
+}
+
 __global__ void k_copy_strided(const double* src, int64_t lds, double* dst, int64_t ldd,
                                int64_t rows, int64_t cols) {
   if (cols == 1) {
@@ -944,6 +976,28 @@ hipError_t launch_trmm(const double* In, double* Out, int64_t ldc, const int64_t
                        const double* Linv, hipStream_t s) {
   if (ntiles <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_trmm, dim3(ntiles), dim3(256), 0, s, In, Out, ldc, off, tiles, goff, Linv);
+  return hipGetLastError();
+}
+
+hipError_t launch_pad_cast(int f32, const double* A, int64_t lda, int64_t N, int64_t n, void* C,
+                           int64_t ldc, hipStream_t s) {
+  const int grid = static_cast<int>(N > 65535 ? 65535 : N);
+  if (grid <= 0) return hipSuccess;
+  if (f32)
+    hipLaunchKernelGGL(k_pad_cast<float>, dim3(grid), dim3(256), 0, s, A, lda, N, n,
+                       static_cast<float*>(C), ldc);
+  else
+    hipLaunchKernelGGL(k_pad_cast<double>, dim3(grid), dim3(256), 0, s, A, lda, N, n,
+                       static_cast<double*>(C), ldc);
+  return hipGetLastError();
+}
+
+hipError_t launch_hbm_step(const double* Y, int64_t ldy, int32_t m, int64_t n, double alpha,
+                           double beta, double* x, double* z, hipStream_t s) {
+  const int64_t grid = (n + 63) / 64;
+  if (grid <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_hbm_step, dim3(static_cast<unsigned>(grid)), dim3(256), 0, s, Y, ldy, m, n,
+                     alpha, beta, x, z);
   return hipGetLastError();
 }
 

@@ -172,3 +172,16 @@ def test_one_hip_runtime_in_process():
     torch first so libapc binds to the same one."""
     runtimes = apc._hip_runtimes()
     assert len(runtimes) == 1, runtimes
+
+
+def test_hbm_null_arguments_are_rejected():
+    assert apc.lib.apc_hbm_workspace_bytes(None, 0) == 0
+    assert apc.lib.apc_hbm_iterate(None, 1) == apc.APC_EINVAL
+    assert apc.lib.apc_hbm_restart(None) == apc.APC_EINVAL
+    assert apc.lib.apc_hbm_residual(None, None) == apc.APC_EINVAL
+    assert apc.lib.apc_hbm_get_params(None, None, None, None, None, None, None, None) == apc.APC_EINVAL
+    import ctypes
+    h = ctypes.c_void_p()
+    assert apc.lib.apc_hbm_create(ctypes.byref(h), None, 0, 0.1, 0.5, None, 0) == apc.APC_EINVAL
+    assert h.value is None
+    apc.lib.apc_hbm_destroy(None)
