@@ -114,6 +114,19 @@ def cpu_baseline(S, per_iter_bytes, budget_iters=8):
     }
 
 
+def plain_updates_ms(plan, T):
+    """T updates timed by two HIP events on the plan's stream and nothing between the
+    kernels (whole-update time as a caller sees it)."""
+    import torch
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(plan.stream)
+    plan.iterate(T)
+    e1.record(plan.stream)
+    e1.synchronize()
+    return e0.elapsed_time(e1)
+
+
 def _err(plan, xs, xs_norm):
     import torch
     return float(torch.linalg.norm(plan.xbar() - xs)) / xs_norm
@@ -147,10 +160,14 @@ def time_plain(apc, A, b, off, xs, prec, target, ws, max_updates=400, anchor=Non
     t0 = time.perf_counter()
     plan = apc.Plan(A, b, off, prec, workspace=ws, anchor_every=anchor, gamma=gamma, eta=eta)
     t1 = time.perf_counter()
-    tot, pa, pb, pv = plan.iterate_timed(T)
+    tot = plain_updates_ms(plan, T)
     torch.cuda.synchronize()
     t2 = time.perf_counter()
     err = _err(plan, xs, xs_norm)
+    # Per-kernel times: the same number of updates again, each kernel timed by events
+    # attached to its own launch (not part of the time to target).
+    plan.restart()
+    _, pa, pb, pv = plan.iterate_timed(T)
     plan.close()
     return {"reached": True, "updates": T, "err": err, "setup_ms": round((t1 - t0) * 1e3, 2),
             "iterate_ms": round((t2 - t1) * 1e3, 2), "total_ms": round((t2 - t0) * 1e3, 2),
@@ -186,7 +203,8 @@ def krhs_rates(apc, A, b, off, prec, ws, T=16):
     sq = {"f32": 4, "bf16_ir": 2, "f64": 8}[prec]
     plan = apc.Plan(A, b, off, prec, workspace=ws, anchor_every=0 if prec != "f64" else None)
     shapes = plan.launch_shapes()
-    tot, pa, pb, pv = plan.iterate_timed(T)
+    tot = plain_updates_ms(plan, T)
+    _, pa, pb, pv = plan.iterate_timed(T)
     plan.close()
     name = {"f32": "f32", "bf16_ir": "bf16", "f64": "f64"}[prec]
     flops = 2.0 * N * n * k
@@ -300,23 +318,75 @@ def adjoint_workload(apc, synth, dev):
     return res
 
 
-def cimmino_baseline(apc, synth, dev):
-    """Block Cimmino (Sec. 4.5) on the benchmark system, run as APC with gamma = 1 and
-    eta = 2 / (mu_min + mu_max) (Prop. 2: nu = eta / m, the optimal Cimmino step)."""
+def time_hbm(apc, plan, kind, xs, target, max_updates, check_every=8):
+    """A heavy-ball comparison run (apc_hbm_*) on a plan: creation (the spectrum
+    estimate of the plain kind included), updates to `target` relative error counted
+    in an untimed run, then those updates timed by two HIP events."""
     import torch
-    S = synth.tall_gaussian_16k()
-    A = torch.from_numpy(S.A).to(dev)
-    b = torch.from_numpy(S.B).to(dev)
-    xs = torch.from_numpy(S.xstar).to(dev)
-    ws = torch.empty(apc.Plan.workspace_bytes(S.N, S.n, S.off, "f32"), dtype=torch.uint8, device=dev)
-    p = apc.Plan(A, b, S.off, "f32", workspace=ws)
-    prm = p.params()
-    p.close()
-    eta = 2.0 / (prm["mu_min"] + prm["mu_max"])
-    out = {"workload": "tall Gaussian N=16384 n=8192 m=64, FP32, gamma=1, eta=2/(mu_min+mu_max)",
-           "time_to_1e-6": time_plain(apc, A, b, S.off, xs, "f32", 1e-6, ws, max_updates=1000,
-                                      gamma=1.0, eta=eta)}
-    del A, b, xs, ws
+    xs_norm = float(torch.linalg.norm(xs))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    h = apc.HeavyBall(plan, kind)
+    t1 = time.perf_counter()
+    q = h.params()
+    T, err = 0, float(torch.linalg.norm(h.x() - xs)) / xs_norm
+    while err > target and T < max_updates:
+        h.iterate(check_every)
+        T += check_every
+        err = float(torch.linalg.norm(h.x() - xs)) / xs_norm
+    res = {"kind": ["plain (Sec. 4.3)", "preconditioned (Sec. 6)"][kind],
+           "create_ms": round((t1 - t0) * 1e3, 2), "lanczos_steps": q["lanczos_steps"],
+           "lam_min": q["lam_min"], "lam_max": q["lam_max"], "rho_predicted": q["rho"],
+           "reached": err <= target, "updates": T, "err": err}
+    if err <= target:
+        h.restart()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(plan.stream)
+        h.iterate(T)
+        e1.record(plan.stream)
+        e1.synchronize()
+        ms = e0.elapsed_time(e1)
+        res.update({"iterate_ms": round(ms, 2), "us_per_update": round(ms * 1e3 / max(T, 1), 1),
+                    "create_plus_iterate_ms": round((t1 - t0) * 1e3 + ms, 2)})
+    h.close()
+    return res
+
+
+def comparison_methods(apc, synth, dev):
+    """The paper's comparison methods on the same GPU passes, each from APC's start
+    to 1e-6 relative error: block Cimmino (Sec. 4.5, run as APC with gamma = 1 and
+    eta = 2 / (mu_min + mu_max): Prop. 2 with the optimal Cimmino step), D-HBM on the
+    blocks [A_i, b_i] (Sec. 4.3) and on Sec. 6's preconditioned blocks; on the benchmark
+    system (FP32) and on the same shape with entries of mean 1 (FP64: the plain
+    heavy ball's FP32 rounding floor is above 1e-6 there).  Update counts are checked
+    every 8 updates for the heavy-ball runs."""
+    import torch
+    out = {}
+    for name, gen, prec in (("tall16k_fp32", synth.tall_gaussian_16k, "f32"),
+                            ("tall16k_mean1_fp64", synth.tall_gaussian_16k_mean1, "f64")):
+        S = gen()
+        A = torch.from_numpy(S.A).to(dev)
+        b = torch.from_numpy(S.B).to(dev)
+        xs = torch.from_numpy(S.xstar).to(dev)
+        ws = torch.empty(apc.Plan.workspace_bytes(S.N, S.n, S.off, prec), dtype=torch.uint8,
+                         device=dev)
+        p = apc.Plan(A, b, S.off, prec, workspace=ws)
+        prm = p.params()
+        p.close()
+        eta = 2.0 / (prm["mu_min"] + prm["mu_max"])
+        entry = {"workload": f"{S.name}: N={S.N} n={S.n} m={S.m}, {prec.upper()}",
+                 "apc_params": prm}
+        if name != "tall16k_fp32":       # the main line already times APC on the first system
+            entry["apc"] = time_plain(apc, A, b, S.off, xs, prec, 1e-6, ws, max_updates=1000)
+        entry["block_cimmino"] = time_plain(apc, A, b, S.off, xs, prec, 1e-6, ws, max_updates=1000,
+                                            gamma=1.0, eta=eta)
+        p = apc.Plan(A, b, S.off, prec, workspace=ws)
+        entry["dhbm_preconditioned"] = time_hbm(apc, p, 1, xs, 1e-6, 4000)
+        entry["dhbm_plain"] = time_hbm(apc, p, 0, xs, 1e-6, 4000)
+        p.close()
+        out[name] = entry
+        del A, b, xs, ws, S
+        torch.cuda.empty_cache()
     return out
 
 
@@ -330,9 +400,10 @@ def secondary(apc, synth, dev):
     b = torch.from_numpy(S.B).to(dev)
     plan = apc.Plan(A, b, S.off, "f64")
     plan.iterate(50)
-    tot, pa, pb, pv = plan.iterate_timed(2000)
+    tot = plain_updates_ms(plan, 2000)
     err = float(torch.linalg.norm(plan.xbar() - torch.from_numpy(S.xstar).to(dev))) / float(
         np.linalg.norm(S.xstar))
+    _, pa, pb, pv = plan.iterate_timed(2000)
     out["square512_fp64"] = {"workload": "N=n=512, A, x* iid N(0,1), m=8 blocks of 64, FP64",
                              "updates": 2000, "us_per_update": round(tot * 1e3 / 2000, 2),
                              "pass_a_us": round(pa * 1e3 / 2000, 2),
@@ -362,7 +433,7 @@ def secondary(apc, synth, dev):
     out["many_systems_fp32"] = many_systems(apc, synth, dev)
     torch.cuda.empty_cache()
     out["adjoint_fp32"] = adjoint_workload(apc, synth, dev)
-    out["block_cimmino_baseline"] = cimmino_baseline(apc, synth, dev)
+    out["comparison_methods"] = comparison_methods(apc, synth, dev)
     torch.cuda.empty_cache()
     # Mixed precision vs plain FP32: N = n = 16384, A = G/sqrt(n) + alpha I, k = 128, m = 64.
     n, k, m = 16384, 128, 64
@@ -465,12 +536,14 @@ def main():
         ts = time.perf_counter()
         plan = apc.Plan(A, b, S.off, args.precision, workspace=ws, stream=stream)
         setup_ms.append((time.perf_counter() - ts) * 1e3)    # setup synchronises at its end
-        tot, a_ms, b_ms, v_ms = plan.iterate_timed(T)
-        iter_ms.append(tot)
+        iter_ms.append(plain_updates_ms(plan, T))
+        relres = plan.residual()
+        # Per-kernel launch times (roofline): T more updates with events attached to
+        # each kernel's own launch; not part of the time to target.
+        _, a_ms, b_ms, v_ms = plan.iterate_timed(T)
         pa_ms.append(a_ms)
         pb_ms.append(b_ms)
         av_ms.append(v_ms)
-        relres = plan.residual()
         prm = plan.params()
         plan_info = plan.info()
         plan.close()
@@ -493,7 +566,7 @@ def main():
                               else ("pass_a", bytes_a_l, avg_a))
     achieved = dom_bytes / (dom_ms * 1e-3) / 1e9
     dom_label, dom_fn = {"pass_a": ("k_rowdot<float, float, 8, 2, true>", "k_rowdot"),
-                         "pass_b": ("k_pass_b<float, 8, true>", "k_pass_b")}[dom]
+                         "pass_b": ("k_pass_b_rows<float, true>", "k_pass_b_rows")}[dom]
 
     out = {
         "metric": METRIC,

@@ -198,10 +198,10 @@ hipError_t tn_nct(const TnArgs& a, hipStream_t s) {
   const int64_t blocks = (a.rows / (64 * RT)) * ncg * a.nsplit;
   const dim3 grid(static_cast<unsigned>(blocks)), block(256);
   switch (nct) {
-    case 1: k_tn<T, RT, 1, PF><<<grid, block, 0, s>>>(a); break;
-    case 2: k_tn<T, RT, 2, PF><<<grid, block, 0, s>>>(a); break;
-    case 4: k_tn<T, RT, 4, PF><<<grid, block, 0, s>>>(a); break;
-    case 8: k_tn<T, RT, 8, PF><<<grid, block, 0, s>>>(a); break;
+    case 1: APC_LAUNCH((k_tn<T, RT, 1, PF>), grid, block, 0, s, a); break;
+    case 2: APC_LAUNCH((k_tn<T, RT, 2, PF>), grid, block, 0, s, a); break;
+    case 4: APC_LAUNCH((k_tn<T, RT, 4, PF>), grid, block, 0, s, a); break;
+    case 8: APC_LAUNCH((k_tn<T, RT, 8, PF>), grid, block, 0, s, a); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -437,16 +437,19 @@ hipError_t launch_tn_sum_cast(int type, const void* part, int32_t nsplit, int32_
   const unsigned g = grid_stride_blocks(static_cast<int64_t>(kp) * rows);
   switch (type) {
     case kTnF64:
-      k_tn_sum_cast<double, double><<<g, 256, 0, s>>>(static_cast<const double*>(part), nsplit, kp,
-                                                      ldp, rows, static_cast<double*>(out), ldo);
+      APC_LAUNCH((k_tn_sum_cast<double, double>), dim3(g), dim3(256), 0, s,
+                 static_cast<const double*>(part), nsplit, kp, ldp, rows, static_cast<double*>(out),
+                 ldo);
       break;
     case kTnF32:
-      k_tn_sum_cast<float, float><<<g, 256, 0, s>>>(static_cast<const float*>(part), nsplit, kp,
-                                                    ldp, rows, static_cast<float*>(out), ldo);
+      APC_LAUNCH((k_tn_sum_cast<float, float>), dim3(g), dim3(256), 0, s,
+                 static_cast<const float*>(part), nsplit, kp, ldp, rows, static_cast<float*>(out),
+                 ldo);
       break;
     case kTnBF16:
-      k_tn_sum_cast<float, __bf16><<<g, 256, 0, s>>>(static_cast<const float*>(part), nsplit, kp,
-                                                     ldp, rows, static_cast<__bf16*>(out), ldo);
+      APC_LAUNCH((k_tn_sum_cast<float, __bf16>), dim3(g), dim3(256), 0, s,
+                 static_cast<const float*>(part), nsplit, kp, ldp, rows, static_cast<__bf16*>(out),
+                 ldo);
       break;
     default: return hipErrorInvalidValue;
   }
@@ -457,15 +460,15 @@ hipError_t launch_tn_update(int type, int part_f64, const TnUpdateArgs& a, hipSt
   const unsigned g = grid_stride_blocks(static_cast<int64_t>(a.kp) * a.n);
   if (part_f64) {
     switch (type) {
-      case kTnF64: k_tn_update<double, double><<<g, 256, 0, s>>>(a); break;
-      case kTnF32: k_tn_update<double, float><<<g, 256, 0, s>>>(a); break;
-      case kTnBF16: k_tn_update<double, __bf16><<<g, 256, 0, s>>>(a); break;
+      case kTnF64: APC_LAUNCH((k_tn_update<double, double>), dim3(g), dim3(256), 0, s, a); break;
+      case kTnF32: APC_LAUNCH((k_tn_update<double, float>), dim3(g), dim3(256), 0, s, a); break;
+      case kTnBF16: APC_LAUNCH((k_tn_update<double, __bf16>), dim3(g), dim3(256), 0, s, a); break;
       default: return hipErrorInvalidValue;
     }
   } else {
     switch (type) {
-      case kTnF32: k_tn_update<float, float><<<g, 256, 0, s>>>(a); break;
-      case kTnBF16: k_tn_update<float, __bf16><<<g, 256, 0, s>>>(a); break;
+      case kTnF32: APC_LAUNCH((k_tn_update<float, float>), dim3(g), dim3(256), 0, s, a); break;
+      case kTnBF16: APC_LAUNCH((k_tn_update<float, __bf16>), dim3(g), dim3(256), 0, s, a); break;
       default: return hipErrorInvalidValue;
     }
   }

@@ -354,6 +354,7 @@ struct apc_plan_s {
   int anchor_every = 0;                // k-RHS FP32/bf16: every this many updates one in FP64
   int64_t pmax = 1;                    // largest block
   int32_t passb_nt = 1;                // k = 1 pass B: non-temporal loads of C
+  int32_t passb_rows = 1;              // k = 1 pass B: waves split the block's rows
   int32_t passa_nt = 1;                // k = 1 pass A: non-temporal loads of C
   int64_t since_start = 0;             // k-RHS updates since the last start
   int refinements = 0;
@@ -367,7 +368,7 @@ struct apc_plan_s {
   double* xbar() const { return at<double>(L.xbar); }
   int64_t* doff() const { return at<int64_t>(L.doff); }
   int32_t* ta(int which) const { return at<int32_t>(L.tiles_a) + which * L.ntiles_a; }
-  int32_t slab_cols() const { return pass_b_slab(prec == APC_F32 ? 4 : 8); }
+  int32_t slab_cols() const { return pass_b_slab(prec == APC_F32 ? 4 : 8, passb_rows); }
   int64_t state_ld() const { return static_cast<int64_t>(kp) * L.ldc; }  // block stride of x, d
 };
 
@@ -416,12 +417,14 @@ apc_status pass_b(apc_plan_s* P, int i0, int i1, int col) {
   if (P->prec == APC_F32) {
     PassBArgs<float> a{P->at<float>(P->L.C32), P->L.ldc, P->doff(), i1 - i0, nslab,
                        P->at<float>(P->L.w) + woff, P->nsplit, P->N, P->x() + coff,
-                       P->state_ld(), P->xbar() + coff, P->gamma, i0, P->passb_nt};
+                       P->state_ld(), P->xbar() + coff, P->gamma, i0, P->passb_nt,
+                       P->passb_rows};
     HIP_TRY(launch_pass_b_f32(a, P->stream));
   } else {
     PassBArgs<double> a{P->C64(), P->L.ldc, P->doff(), i1 - i0, nslab,
                         P->at<double>(P->L.w) + woff, P->nsplit, P->N, P->x() + coff,
-                        P->state_ld(), P->xbar() + coff, P->gamma, i0, P->passb_nt};
+                        P->state_ld(), P->xbar() + coff, P->gamma, i0, P->passb_nt,
+                       P->passb_rows};
     HIP_TRY(launch_pass_b_f64(a, P->stream));
   }
   return APC_OK;
@@ -483,6 +486,28 @@ TnUpdateArgs update_args(const apc_plan_s* P, const TnChoice& ch, int mode) {
 // between multiply only y - y_ref, which shrinks as the iteration converges,
 // so their rounding (and the rounding of the stored factor) stops limiting
 // the attainable accuracy.  *nev receives the number of events recorded.
+// Timed updates: ev holds two events per timed kernel (start, end), kinds its
+// pass (0 = A, 1 = B, 2 = average / epilogue).  time_next hands the next pair to
+// the launcher (pending_timing); timed_done checks that the launch took it, and
+// records the pair back to back when the launcher enqueued nothing.
+void time_next(apc_plan_s*, hipEvent_t* ev, int* kinds, int* e, int kind) {
+  if (!ev) return;
+  pending_timing() = TimedLaunch{ev[2 * *e], ev[2 * *e + 1]};
+  kinds[*e] = kind;
+  ++*e;
+}
+
+apc_status timed_done(apc_plan_s* P, hipEvent_t* ev, int e) {
+  if (!ev) return APC_OK;
+  TimedLaunch& t = pending_timing();
+  if (t.start) {
+    t = TimedLaunch{};
+    HIP_TRY(hipEventRecord(ev[2 * (e - 1)], P->stream));
+    HIP_TRY(hipEventRecord(ev[2 * (e - 1) + 1], P->stream));
+  }
+  return APC_OK;
+}
+
 apc_status update_gemm(apc_plan_s* P, hipEvent_t* ev, int* kinds, int* nev) {
   const Layout& L = P->L;
   int e = 0;
@@ -494,27 +519,35 @@ apc_status update_gemm(apc_plan_s* P, hipEvent_t* ev, int* kinds, int* nev) {
                                  P->at<double>(L.yref), P->stream));
     TnArgs a = tn_args(P->ws + L.C64p, L.np, L.Np, P->ws + L.yref, L.np, P->kp, L.np, P->tnR,
                        kTnF64, part, L.Np);
+    time_next(P, ev, kinds, &e, 0);
     HIP_TRY(launch_tn(kTnF64, P->tnR.rt, P->tnR.pf, a, P->stream));
-    if (ev) { HIP_TRY(hipEventRecord(ev[e], P->stream)); kinds[e++] = 0; }
+    ST_TRY(timed_done(P, ev, e));
+    time_next(P, ev, kinds, &e, 2);
     HIP_TRY(launch_tn_sum_cast(kTnF64, part, P->tnR.nsplit, P->kp, L.Np, L.Np, P->ws + L.W64,
                                L.Np, P->stream));
-    if (ev) { HIP_TRY(hipEventRecord(ev[e], P->stream)); kinds[e++] = 2; }
+    ST_TRY(timed_done(P, ev, e));
     TnArgs b = tn_args(P->ws + L.C64T, L.Np, L.np, P->ws + L.W64, L.Np, P->kp, L.Np, P->tnX0,
                        kTnF64, part, L.np);
+    time_next(P, ev, kinds, &e, 1);
     HIP_TRY(launch_tn(kTnF64, P->tnX0.rt, P->tnX0.pf, b, P->stream));
-    if (ev) { HIP_TRY(hipEventRecord(ev[e], P->stream)); kinds[e++] = 1; }
+    ST_TRY(timed_done(P, ev, e));
+    time_next(P, ev, kinds, &e, 2);
     HIP_TRY(launch_tn_update(P->tq, 1, update_args(P, P->tnX0, 2), P->stream));
-    if (ev) { HIP_TRY(hipEventRecord(ev[e], P->stream)); kinds[e++] = 2; }
+    ST_TRY(timed_done(P, ev, e));
   } else {
+    time_next(P, ev, kinds, &e, 0);
     HIP_TRY(launch_tn(P->tq, P->tnA.rt, P->tnA.pf, pass_a_args(P), P->stream));
-    if (ev) { HIP_TRY(hipEventRecord(ev[e], P->stream)); kinds[e++] = 0; }
+    ST_TRY(timed_done(P, ev, e));
+    time_next(P, ev, kinds, &e, 2);
     HIP_TRY(launch_tn_sum_cast(P->tq, part, P->tnA.nsplit, P->kp, L.Np, L.Np, P->ws + L.Wq, L.Np,
                                P->stream));
-    if (ev) { HIP_TRY(hipEventRecord(ev[e], P->stream)); kinds[e++] = 2; }
+    ST_TRY(timed_done(P, ev, e));
+    time_next(P, ev, kinds, &e, 1);
     HIP_TRY(launch_tn(P->tq, P->tnB.rt, P->tnB.pf, pass_b_args(P), P->stream));
-    if (ev) { HIP_TRY(hipEventRecord(ev[e], P->stream)); kinds[e++] = 1; }
+    ST_TRY(timed_done(P, ev, e));
+    time_next(P, ev, kinds, &e, 2);
     HIP_TRY(launch_tn_update(P->tq, P->tq == kTnF64, update_args(P, P->tnB, 0), P->stream));
-    if (ev) { HIP_TRY(hipEventRecord(ev[e], P->stream)); kinds[e++] = 2; }
+    ST_TRY(timed_done(P, ev, e));
   }
   ++P->since_start;
   if (nev) *nev = e;
@@ -661,13 +694,16 @@ apc_status update(apc_plan_s* P, hipEvent_t* ev, int* kinds, int* nev) {
   int e = 0;
   for (int i0 = 0; i0 < P->m; i0 += g) {
     const int i1 = std::min(P->m, i0 + g);
+    time_next(P, ev, kinds, &e, 0);
     ST_TRY(pass_a(P, i0, i1, 0));
-    if (ev) { HIP_TRY(hipEventRecord(ev[e], P->stream)); kinds[e++] = 0; }
+    ST_TRY(timed_done(P, ev, e));
+    time_next(P, ev, kinds, &e, 1);
     ST_TRY(pass_b(P, i0, i1, 0));
-    if (ev) { HIP_TRY(hipEventRecord(ev[e], P->stream)); kinds[e++] = 1; }
+    ST_TRY(timed_done(P, ev, e));
   }
+  time_next(P, ev, kinds, &e, 2);
   ST_TRY(average(P, P->eta / P->m, 1.0 - P->eta));
-  if (ev) { HIP_TRY(hipEventRecord(ev[e], P->stream)); kinds[e++] = 2; }
+  ST_TRY(timed_done(P, ev, e));
   if (nev) *nev = e;
   return APC_OK;
 }
@@ -1069,6 +1105,8 @@ apc_status apc_setup(apc_plan* out, const double* A, int64_t lda, const double* 
   if (const char* e = std::getenv("APC_GROUP_BLOCKS")) group_blocks = std::atoi(e);
   int32_t passb_nt = 1;
   if (const char* e = std::getenv("APC_PASSB_NT")) passb_nt = std::atoi(e) != 0;
+  int32_t passb_rows = 1;
+  if (const char* e = std::getenv("APC_PASSB_ROWS")) passb_rows = std::atoi(e) != 0;
   if (const char* e = std::getenv("APC_PASSA_ROWS")) {
     const int r = std::atoi(e);
     if (r == 8 || r == 16 || r == 32) passa_rows = r;
@@ -1105,6 +1143,7 @@ apc_status apc_setup(apc_plan* out, const double* A, int64_t lda, const double* 
   P->eta = given ? eta : NAN;
   P->xcd_remap = xcd_remap;
   P->passb_nt = passb_nt;
+  P->passb_rows = passb_rows;
   P->passa_nt = passa_nt;
   P->passa_rows = passa_rows;
   P->tile_start.assign(1, 0);
@@ -1155,30 +1194,34 @@ apc_status apc_iterate_timed(apc_plan p, int32_t T, float* ms_total, float* ms_p
   if (!p) return fail(APC_EINVAL, "plan is NULL");
   if (T < 0) return fail(APC_EINVAL, "T must be >= 0");
   const int per = launches_per_update(p);
-  const size_t need = static_cast<size_t>(T) * per + 1;
+  // Two bracketing events for the whole run, two per timed kernel.
+  const size_t kern = static_cast<size_t>(T) * per;
+  const size_t need = 2 * kern + 2;
   while (p->events.size() < need) {
     hipEvent_t e = nullptr;
     HIP_TRY(hipEventCreate(&e));
     p->events.push_back(e);
   }
-  std::vector<int> kinds(need, -1);
-  size_t used = 1;
+  std::vector<int> kinds(kern + 1, -1);
+  hipEvent_t* kev = p->events.data() + 2;
+  size_t used = 0;
   if (T > 0) HIP_TRY(hipEventRecord(p->events[0], p->stream));
   for (int32_t t = 0; t < T; ++t) {
     int nev = 0;
-    ST_TRY(update(p, p->events.data() + used, kinds.data() + used, &nev));
+    ST_TRY(update(p, kev + 2 * used, kinds.data() + used, &nev));
     used += static_cast<size_t>(nev);
   }
   p->iters += T;
   float sums[3] = {0.f, 0.f, 0.f}, tot = 0.f;
   if (T > 0) {
-    HIP_TRY(hipEventSynchronize(p->events[used - 1]));
-    for (size_t e = 1; e < used; ++e) {
+    HIP_TRY(hipEventRecord(p->events[1], p->stream));
+    HIP_TRY(hipEventSynchronize(p->events[1]));
+    for (size_t e = 0; e < used; ++e) {
       float ms = 0.f;
-      HIP_TRY(hipEventElapsedTime(&ms, p->events[e - 1], p->events[e]));
+      HIP_TRY(hipEventElapsedTime(&ms, kev[2 * e], kev[2 * e + 1]));
       sums[kinds[e]] += ms;
     }
-    HIP_TRY(hipEventElapsedTime(&tot, p->events[0], p->events[used - 1]));
+    HIP_TRY(hipEventElapsedTime(&tot, p->events[0], p->events[1]));
   }
   if (ms_total) *ms_total = tot;
   if (ms_pass_a) *ms_pass_a = sums[0];

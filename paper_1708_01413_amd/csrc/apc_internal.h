@@ -1,11 +1,35 @@
 // Internal declarations shared by the HIP kernels and the host side of libapc.
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
 
 namespace apc {
+
+// Per-kernel timing without extra packets on the stream: when a pair of events
+// is pending, the next timed launch takes it and records the two events from
+// its own dispatch (the kernel's start and end), so timing adds no idle gap
+// between kernels.  A launcher that enqueues nothing leaves the pair pending.
+struct TimedLaunch {
+  hipEvent_t start = nullptr;
+  hipEvent_t stop = nullptr;
+};
+TimedLaunch& pending_timing();
+
+#define APC_LAUNCH(kernel, grid, block, shmem, stream, ...)                                  \
+  do {                                                                                      \
+    ::apc::TimedLaunch& tl_ = ::apc::pending_timing();                                      \
+    if (tl_.start) {                                                                        \
+      hipExtLaunchKernelGGL(kernel, grid, block, shmem, stream, tl_.start, tl_.stop, 0,      \
+                            __VA_ARGS__);                                                   \
+      tl_ = ::apc::TimedLaunch{};                                                           \
+    } else {                                                                                \
+      hipLaunchKernelGGL(kernel, grid, block, shmem, stream, __VA_ARGS__);                  \
+    }                                                                                       \
+  } while (0)
+
 
 constexpr int kThreads = 256;       // threads per workgroup for streaming kernels
 constexpr int kRowTile = 16;        // rows per pass-A workgroup
@@ -72,10 +96,15 @@ struct PassBArgs {
   double gamma;
   int32_t blk_begin;
   int32_t nt_loads;           // 1: non-temporal loads of C
+  int32_t row_split = 1;      // 1: waves split the block's rows over a 64-lane slab;
+                              // 0: every wave streams all rows over its own part of a
+                              //    kThreads-lane slab
 };
 
-// Columns per pass-B slab for an element size.
-inline int pass_b_slab(int elem_bytes) { return kThreads * (16 / elem_bytes); }
+// Columns per pass-B slab for an element size and slab layout.
+inline int pass_b_slab(int elem_bytes, int row_split) {
+  return (row_split ? 64 : kThreads) * (16 / elem_bytes);
+}
 
 // y_i = beta * y_i + alpha * sum_{r in block i} w_r C[r][:], FP64 accumulation,
 // w_r = sum over nsplit partials (w + s * w_stride).  off == null: a single

@@ -226,6 +226,49 @@ __global__ __launch_bounds__(kThreads) void k_pass_b(PassBArgs<TQ> a) {
   }
 }
 
+// The same update with the block's rows split over the waves: one workgroup
+// per (block i, 64 x 16-byte column slab); wave v streams rows r0+v, r0+v+4,
+// ... (1 KB contiguous per row), the four partial sums are added in LDS in a
+// fixed order, then one thread per column applies the FP64 update.  Four times
+// as many workgroups as the layout above at the same shape.
+template <typename TQ, bool NT>
+__global__ __launch_bounds__(kThreads) void k_pass_b_rows(PassBArgs<TQ> a) {
+  constexpr int W = V16<TQ>::W;
+  constexpr int SW = 64 * W;  // columns per slab
+  const int s = blockIdx.x % a.nslab;
+  const int i = a.blk_begin + static_cast<int>(blockIdx.x / a.nslab);
+  const int lane = threadIdx.x & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int64_t r0 = a.off[i];
+  const int64_t r1 = a.off[i + 1];
+  const int64_t col = static_cast<int64_t>(s) * SW + lane * W;
+  TQ acc[W];
+#pragma unroll
+  for (int e = 0; e < W; ++e) acc[e] = TQ(0);
+  if (col < a.ldc) {
+    for (int64_t r = r0 + wv; r < r1; r += 4) {
+      TQ wr = a.w[r];
+      for (int sp = 1; sp < a.nsplit; ++sp) wr += a.w[sp * a.w_stride + r];
+      TQ q[W];
+      V16<TQ>::template load<NT>(a.C + r * a.ldc + col, q);
+#pragma unroll
+      for (int e = 0; e < W; ++e) acc[e] = fma(wr, q[e], acc[e]);
+    }
+  }
+  __shared__ TQ red[kThreads / 64][SW];
+#pragma unroll
+  for (int e = 0; e < W; ++e) red[wv][lane * W + e] = acc[e];
+  __syncthreads();
+  double* xi = a.x + static_cast<int64_t>(i) * a.ldx;
+  for (int t = threadIdx.x; t < SW; t += kThreads) {
+    const int64_t j = static_cast<int64_t>(s) * SW + t;
+    if (j >= a.ldc) break;
+    const TQ v = (red[0][t] + red[1][t]) + (red[2][t] + red[3][t]);
+    const double xo = xi[j];
+    xi[j] = xo + a.gamma * ((a.xbar[j] - xo) - static_cast<double>(v));
+  }
+}
+
 // ------------------------------------------------------------------ FP64 refinement
 
 // Per block i: out[c*ldo + r0 + r] = scale * sum_q Lop[r][q] in[c*ldi + r0 + q] for
@@ -861,9 +904,9 @@ static hipError_t rowdot_impl(const RowdotArgs<TQ, TA>& a, hipStream_t s) {
 #define APC_ROWDOT_CASE(R)                                                                  \
   case R:                                                                                   \
     if (a.nt_loads)                                                                         \
-      hipLaunchKernelGGL((k_rowdot<TQ, TA, R, U, true>), dim3(grid), dim3(kThreads), 0, s, a); \
+      APC_LAUNCH((k_rowdot<TQ, TA, R, U, true>), dim3(grid), dim3(kThreads), 0, s, a);  \
     else                                                                                    \
-      hipLaunchKernelGGL((k_rowdot<TQ, TA, R, U, false>), dim3(grid), dim3(kThreads), 0, s, a); \
+      APC_LAUNCH((k_rowdot<TQ, TA, R, U, false>), dim3(grid), dim3(kThreads), 0, s, a); \
     break;
   switch (a.rows_per_tile) {
     APC_ROWDOT_CASE(8)
@@ -884,10 +927,16 @@ template <typename TQ>
 static hipError_t pass_b_impl(const PassBArgs<TQ>& a, hipStream_t s) {
   const unsigned grid = static_cast<unsigned>(a.nslab) * static_cast<unsigned>(a.m);
   if (grid == 0) return hipSuccess;
-  if (a.nt_loads)
-    hipLaunchKernelGGL((k_pass_b<TQ, 8, true>), dim3(grid), dim3(kThreads), 0, s, a);
-  else
-    hipLaunchKernelGGL((k_pass_b<TQ, 8, false>), dim3(grid), dim3(kThreads), 0, s, a);
+  if (a.row_split) {
+    if (a.nt_loads)
+      APC_LAUNCH((k_pass_b_rows<TQ, true>), dim3(grid), dim3(kThreads), 0, s, a);
+    else
+      APC_LAUNCH((k_pass_b_rows<TQ, false>), dim3(grid), dim3(kThreads), 0, s, a);
+  } else if (a.nt_loads) {
+    APC_LAUNCH((k_pass_b<TQ, 8, true>), dim3(grid), dim3(kThreads), 0, s, a);
+  } else {
+    APC_LAUNCH((k_pass_b<TQ, 8, false>), dim3(grid), dim3(kThreads), 0, s, a);
+  }
   return hipGetLastError();
 }
 
@@ -897,7 +946,7 @@ hipError_t launch_pass_b_f32(const PassBArgs<float>& a, hipStream_t s) { return 
 template <typename TD>
 static hipError_t combine_impl(const double* x, int64_t ldx, int32_t m, int64_t n, double alpha,
                                double beta, double* xbar, TD* d, int64_t ldd, hipStream_t s) {
-  hipLaunchKernelGGL((k_combine<TD>), dim3(grid_for(n, 64)), dim3(256), 0, s, x, ldx, m, n, alpha,
+  APC_LAUNCH((k_combine<TD>), dim3(grid_for(n, 64)), dim3(256), 0, s, x, ldx, m, n, alpha,
                      beta, xbar, d, ldd);
   return hipGetLastError();
 }
@@ -977,6 +1026,11 @@ hipError_t launch_trmm(const double* In, double* Out, int64_t ldc, const int64_t
   if (ntiles <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_trmm, dim3(ntiles), dim3(256), 0, s, In, Out, ldc, off, tiles, goff, Linv);
   return hipGetLastError();
+}
+
+TimedLaunch& pending_timing() {
+  static thread_local TimedLaunch t;
+  return t;
 }
 
 hipError_t launch_pad_cast(int f32, const double* A, int64_t lda, int64_t N, int64_t n, void* C,

@@ -75,12 +75,15 @@ def renormalised_sizes(rng, m: int, total: int, lo: int, hi: int) -> np.ndarray:
 
 
 def gaussian_system(N: int, n: int, m: int | None = None, *, k: int = 1, seed: int = 0,
-                    scale: float = 1.0, shift: float = 0.0, sizes=None,
+                    scale: float = 1.0, shift: float = 0.0, sizes=None, mean: float = 0.0,
                     name: str = "") -> System:
-    """A = scale * G (+ shift * I on the leading n x n block), G iid N(0, 1);
+    """A = scale * (G + mean) (+ shift * I on the leading n x n block), G iid N(0, 1);
     X* iid N(0, 1) with k columns (a vector when k == 1); B = A X*."""
     rng = np.random.default_rng(seed)
-    A = rng.standard_normal((N, n)) * scale
+    A = rng.standard_normal((N, n))
+    if mean:
+        A += mean
+    A *= scale
     if shift:
         A[np.arange(min(N, n)), np.arange(min(N, n))] += shift
     xs = rng.standard_normal((n, k))
@@ -95,6 +98,15 @@ def gaussian_system(N: int, n: int, m: int | None = None, *, k: int = 1, seed: i
 # ---------------------------------------------------------------------------
 # Named workloads (sizes follow the benchmark configurations)
 # ---------------------------------------------------------------------------
+
+def tall_gaussian_16k_mean1(seed: int = 0) -> System:
+    """The benchmark shape with entries of mean 1: A = (G + 1)/sqrt(n), x* iid N(0, 1),
+    m = 64 blocks of 256 rows (the nonzero-mean random systems of the paper's comparison,
+    where A^T A has one large outlying eigenvalue)."""
+    n = 8192
+    return gaussian_system(16384, n, 64, seed=seed, scale=1.0 / np.sqrt(n), mean=1.0,
+                           name="tall-gauss-mean1-16384x8192-m64")
+
 
 def square_gaussian_512(seed: int = 0) -> System:
     """N = n = 512, A and x* iid N(0, 1), m = 8 blocks of 64 rows (FP64 case)."""
