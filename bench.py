@@ -378,7 +378,7 @@ def comparison_methods(apc, synth, dev):
                  "apc_params": prm}
         if name != "tall16k_fp32":       # the main line already times APC on the first system
             entry["apc"] = time_plain(apc, A, b, S.off, xs, prec, 1e-6, ws, max_updates=1000)
-        entry["block_cimmino"] = time_plain(apc, A, b, S.off, xs, prec, 1e-6, ws, max_updates=1000,
+        entry["block_cimmino"] = time_plain(apc, A, b, S.off, xs, prec, 1e-6, ws, max_updates=4000,
                                             gamma=1.0, eta=eta)
         p = apc.Plan(A, b, S.off, prec, workspace=ws)
         entry["dhbm_preconditioned"] = time_hbm(apc, p, 1, xs, 1e-6, 4000)
