@@ -536,3 +536,185 @@ hipError_t launch_tn_pack(int type, const double* src, int64_t lds, int64_t srow
 }
 
 }  // namespace apc
+
+namespace apc {
+
+// ------------------------------------------------------------------ FP64 setup products
+//
+// The two products of CholeskyQR2 on the matrix cores: the Gram matrix
+// G_i = C_i C_i^T and the triangular product Out_i = L_i^{-1} In_i, one 64 x 64
+// output tile per workgroup over the same tile lists as the vector kernels.
+// Wave w owns the 32 x 32 quadrant (w / 2, w % 2) as 2 x 2 MFMA 16x16x4 f64
+// tiles.  A K step is 32 elements: lane (li, g) contributes the elements
+// k = k0 + 8 g + 2 p + e (piece p < 4, element e < 2) of its operand rows, the
+// p-th piece feeding two MFMAs, so each MFMA reduces over a K subset that both
+// operands label alike (as in k_tn).
+
+namespace {
+
+__global__ __launch_bounds__(256) void k_gram_mfma(const double* C, int64_t ldc,
+                                                   const int64_t* off, const int32_t* tiles,
+                                                   const int64_t* goff, double* G) {
+  const int blk = tiles[3 * blockIdx.x + 0];
+  const int ta = tiles[3 * blockIdx.x + 1];
+  const int tb = tiles[3 * blockIdx.x + 2];
+  const int64_t r0 = off[blk];
+  const int p = static_cast<int>(off[blk + 1] - r0);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int li = lane & 15, g = lane >> 4;
+  const int qa = wv >> 1, qb = wv & 1;
+  // Operand rows of this lane: two 16-row tiles of the A quadrant, two of the B
+  // quadrant.  Rows past the block read its first row and are zeroed.
+  const double* pa[2];
+  const double* pb[2];
+  bool va[2], vb[2];
+#pragma unroll
+  for (int t = 0; t < 2; ++t) {
+    const int ra = ta * 64 + qa * 32 + 16 * t + li;
+    const int rb = tb * 64 + qb * 32 + 16 * t + li;
+    va[t] = ra < p;
+    vb[t] = rb < p;
+    pa[t] = C + (r0 + (va[t] ? ra : 0)) * ldc + 8 * g;
+    pb[t] = C + (r0 + (vb[t] ? rb : 0)) * ldc + 8 * g;
+  }
+  f64x2 ar[2][2][4], br[2][2][4];
+  f64x4 acc[2][2];
+#pragma unroll
+  for (int t = 0; t < 2; ++t)
+#pragma unroll
+    for (int u = 0; u < 2; ++u) acc[t][u] = f64x4{};
+  auto load = [&](f64x2 (&a)[2][4], f64x2 (&b)[2][4], int step) {
+    const int64_t o = static_cast<int64_t>(step) * 32;
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+#pragma unroll
+      for (int pc = 0; pc < 4; ++pc) {
+        const f64x2 x = *reinterpret_cast<const f64x2*>(pa[t] + o + 2 * pc);
+        const f64x2 y = *reinterpret_cast<const f64x2*>(pb[t] + o + 2 * pc);
+        a[t][pc] = va[t] ? x : f64x2{};
+        b[t][pc] = vb[t] ? y : f64x2{};
+      }
+  };
+  auto compute = [&](const f64x2 (&a)[2][4], const f64x2 (&b)[2][4]) {
+#pragma unroll
+    for (int pc = 0; pc < 4; ++pc)
+#pragma unroll
+      for (int e = 0; e < 2; ++e)
+#pragma unroll
+        for (int t = 0; t < 2; ++t)
+#pragma unroll
+          for (int u = 0; u < 2; ++u)
+            acc[t][u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[t][pc][e], b[u][pc][e], acc[t][u],
+                                                             0, 0, 0);
+  };
+  const int nsteps = static_cast<int>(ldc / 32);
+  if (nsteps > 0) load(ar[0], br[0], 0);
+  for (int s0 = 0; s0 < nsteps; s0 += 2) {
+    if (s0 + 1 < nsteps) load(ar[1], br[1], s0 + 1);
+    compute(ar[0], br[0]);
+    if (s0 + 1 < nsteps) {
+      if (s0 + 2 < nsteps) load(ar[0], br[0], s0 + 2);
+      compute(ar[1], br[1]);
+    }
+  }
+  // acc[t][u][q] = G[row base + g + 4 q][column base + li].
+  double* Gb = G + goff[blk];
+#pragma unroll
+  for (int t = 0; t < 2; ++t)
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int ra = ta * 64 + qa * 32 + 16 * t + g + 4 * q;
+        const int rb = tb * 64 + qb * 32 + 16 * u + li;
+        if (ra < p && rb < p) {
+          Gb[static_cast<int64_t>(ra) * p + rb] = acc[t][u][q];
+          if (ta != tb) Gb[static_cast<int64_t>(rb) * p + ra] = acc[t][u][q];
+        }
+      }
+}
+
+// Out_i[r][c] = sum_{k <= r} Linv_i[r][k] In_i[k][c] for the tile's 64 rows of
+// the block and 64 columns.  Linv_i (p x p, zero above the diagonal) is read
+// element-wise with k < min(p, 64 (ta + 1)); In's K index runs along its rows,
+// so each lane gathers its 8 elements per step from 8 rows of one column.
+__global__ __launch_bounds__(256) void k_trmm_mfma(const double* In, double* Out, int64_t ldc,
+                                                   const int64_t* off, const int32_t* tiles,
+                                                   const int64_t* goff, const double* Linv) {
+  const int blk = tiles[3 * blockIdx.x + 0];
+  const int ta = tiles[3 * blockIdx.x + 1];
+  const int tc = tiles[3 * blockIdx.x + 2];
+  const int64_t r0 = off[blk];
+  const int p = static_cast<int>(off[blk + 1] - r0);
+  const double* Lb = Linv + goff[blk];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int li = lane & 15, g = lane >> 4;
+  const int qa = wv >> 1, qb = wv & 1;
+  const int kend = min(p, (ta + 1) * 64);
+  int ra[2];
+  bool va[2];
+  int64_t cb[2];
+#pragma unroll
+  for (int t = 0; t < 2; ++t) {
+    ra[t] = ta * 64 + qa * 32 + 16 * t + li;
+    va[t] = ra[t] < p;
+    cb[t] = static_cast<int64_t>(tc) * 64 + qb * 32 + 16 * t + li;
+  }
+  const double* inb = In + r0 * ldc;
+  f64x4 acc[2][2];
+#pragma unroll
+  for (int t = 0; t < 2; ++t)
+#pragma unroll
+    for (int u = 0; u < 2; ++u) acc[t][u] = f64x4{};
+  for (int k0 = 0; k0 < kend; k0 += 32) {
+    double a[2][8], b[2][8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int k = k0 + 8 * g + j;
+      const bool kin = k < kend;
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        a[t][j] = (kin && va[t]) ? Lb[static_cast<int64_t>(ra[t]) * p + k] : 0.0;
+        b[t][j] = (kin && cb[t] < ldc) ? inb[static_cast<int64_t>(k) * ldc + cb[t]] : 0.0;
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < 8; ++j)
+#pragma unroll
+      for (int t = 0; t < 2; ++t)
+#pragma unroll
+        for (int u = 0; u < 2; ++u)
+          acc[t][u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[t][j], b[u][j], acc[t][u], 0, 0, 0);
+  }
+#pragma unroll
+  for (int t = 0; t < 2; ++t)
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int r = ta * 64 + qa * 32 + 16 * t + g + 4 * q;
+        const int64_t c = static_cast<int64_t>(tc) * 64 + qb * 32 + 16 * u + li;
+        if (r < p && c < ldc) Out[(r0 + r) * ldc + c] = acc[t][u][q];
+      }
+}
+
+}  // namespace
+
+hipError_t launch_gram_mfma(const double* C, int64_t ldc, const int64_t* off,
+                            const int32_t* tiles, int32_t ntiles, const int64_t* goff, double* G,
+                            hipStream_t s) {
+  if (ntiles <= 0) return hipSuccess;
+  if (ldc % 32 != 0) return hipErrorInvalidValue;
+  k_gram_mfma<<<ntiles, 256, 0, s>>>(C, ldc, off, tiles, goff, G);
+  return hipGetLastError();
+}
+
+hipError_t launch_trmm_mfma(const double* In, double* Out, int64_t ldc, const int64_t* off,
+                            const int32_t* tiles, int32_t ntiles, const int64_t* goff,
+                            const double* Linv, hipStream_t s) {
+  if (ntiles <= 0) return hipSuccess;
+  k_trmm_mfma<<<ntiles, 256, 0, s>>>(In, Out, ldc, off, tiles, goff, Linv);
+  return hipGetLastError();
+}
+
+}  // namespace apc

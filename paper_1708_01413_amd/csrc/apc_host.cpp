@@ -983,13 +983,21 @@ apc_status setup_impl(apc_plan_s* P, const Tiles& T) {
   for (int i = 0; i < m; ++i) pmax = std::max(pmax, P->off[i + 1] - P->off[i]);
   const double rank_tol = 32.0 * std::numeric_limits<double>::epsilon() *
                           static_cast<double>(std::max<int64_t>(pmax, 32));
+  // The Gram and triangular products run on the FP64 matrix cores
+  // (APC_SETUP_MFMA=0 selects the vector kernels).
+  bool mfma = true;
+  if (const char* e = std::getenv("APC_SETUP_MFMA")) mfma = std::atoi(e) != 0;
   for (int pass = 0; pass < 2; ++pass) {
     double* src = pass == 0 ? Ca : Cb;
     double* dst = pass == 0 ? Cb : Ca;
     const double* cs = pass == 0 ? ca : cb;
     double* cd = pass == 0 ? cb : ca;
-    HIP_TRY(launch_gram(src, ldc, P->doff(), P->at<int32_t>(L.tiles_g), L.ntiles_g,
-                        P->at<int64_t>(L.goff), P->at<double>(L.G), st));
+    if (mfma)
+      HIP_TRY(launch_gram_mfma(src, ldc, P->doff(), P->at<int32_t>(L.tiles_g), L.ntiles_g,
+                               P->at<int64_t>(L.goff), P->at<double>(L.G), st));
+    else
+      HIP_TRY(launch_gram(src, ldc, P->doff(), P->at<int32_t>(L.tiles_g), L.ntiles_g,
+                          P->at<int64_t>(L.goff), P->at<double>(L.G), st));
     // Both inverse factors are kept: refinement and apc_restart form
     // c = L2^{-1} L1^{-1} r, the adjoint applies L1^{-T} L2^{-T}.
     double* Li = pass == 1 ? P->at<double>(L.Linv2) : P->at<double>(L.Linv);
@@ -997,8 +1005,12 @@ apc_status setup_impl(apc_plan_s* P, const Tiles& T) {
                             P->at<int>(L.flags), rank_tol, st));
     HIP_TRY(launch_linv_apply(P->doff(), P->at<int64_t>(L.goff), m, P->pmax, Li, cs, N, cd, N,
                               P->kp, 0, 1.0, st));
-    HIP_TRY(launch_trmm(src, dst, ldc, P->doff(), P->at<int32_t>(L.tiles_t), L.ntiles_t,
-                        P->at<int64_t>(L.goff), Li, st));
+    if (mfma)
+      HIP_TRY(launch_trmm_mfma(src, dst, ldc, P->doff(), P->at<int32_t>(L.tiles_t), L.ntiles_t,
+                               P->at<int64_t>(L.goff), Li, st));
+    else
+      HIP_TRY(launch_trmm(src, dst, ldc, P->doff(), P->at<int32_t>(L.tiles_t), L.ntiles_t,
+                          P->at<int64_t>(L.goff), Li, st));
   }
   int flags[4] = {0, 0, 0, 0};
   HIP_TRY(hipMemcpyAsync(flags, P->at<int>(L.flags), sizeof flags, hipMemcpyDeviceToHost, st));

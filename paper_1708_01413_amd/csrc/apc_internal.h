@@ -324,6 +324,13 @@ hipError_t launch_gram(const double* C, int64_t ldc, const int64_t* off, const i
 hipError_t launch_chol_inv(const int64_t* off, const int64_t* goff, int32_t m, double* G,
                            double* Linv, int* flags, double rank_tol, hipStream_t s);
 // Out_i = Linv_i In_i for every block (tiles: (blk, ta, tc)).
+// The same two products on the FP64 matrix cores (ldc a multiple of 32).
+hipError_t launch_gram_mfma(const double* C, int64_t ldc, const int64_t* off,
+                            const int32_t* tiles, int32_t ntiles, const int64_t* goff, double* G,
+                            hipStream_t s);
+hipError_t launch_trmm_mfma(const double* In, double* Out, int64_t ldc, const int64_t* off,
+                            const int32_t* tiles, int32_t ntiles, const int64_t* goff,
+                            const double* Linv, hipStream_t s);
 hipError_t launch_trmm(const double* In, double* Out, int64_t ldc, const int64_t* off,
                        const int32_t* tiles, int32_t ntiles, const int64_t* goff,
                        const double* Linv, hipStream_t s);
