@@ -634,68 +634,74 @@ __global__ __launch_bounds__(256) void k_gram_mfma(const double* C, int64_t ldc,
       }
 }
 
-// Out_i[r][c] = sum_{k <= r} Linv_i[r][k] In_i[k][c] for the tile's 64 rows of
-// the block and 64 columns.  Linv_i (p x p, zero above the diagonal) is read
-// element-wise with k < min(p, 64 (ta + 1)); In's K index runs along its rows,
-// so each lane gathers its 8 elements per step from 8 rows of one column.
+// Out_i[r][c] = sum_{k <= r} Linv_i[r][k] In_i[k][c].  One workgroup per
+// (block i, 64-column slab) covers all p_i rows, in groups of 256: wave w owns
+// the 16-row tiles 4 j + w (j < 4) of the group, so the triangular work is
+// spread evenly.  In's K index runs along its rows: each 32-row chunk of the
+// slab is staged in LDS once and read by every row tile (its B fragments),
+// while Linv_i (zero above the diagonal) is read from L2 element-wise; chunks
+// entirely above a row tile's diagonal are skipped.
+constexpr int kTrmmRowsPerGroup = 256;
 __global__ __launch_bounds__(256) void k_trmm_mfma(const double* In, double* Out, int64_t ldc,
-                                                   const int64_t* off, const int32_t* tiles,
+                                                   const int64_t* off, int32_t nslab,
                                                    const int64_t* goff, const double* Linv) {
-  const int blk = tiles[3 * blockIdx.x + 0];
-  const int ta = tiles[3 * blockIdx.x + 1];
-  const int tc = tiles[3 * blockIdx.x + 2];
+  const int blk = blockIdx.x / nslab;
+  const int slab = blockIdx.x % nslab;
   const int64_t r0 = off[blk];
   const int p = static_cast<int>(off[blk + 1] - r0);
   const double* Lb = Linv + goff[blk];
+  const int64_t c0 = static_cast<int64_t>(slab) * 64;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int li = lane & 15, g = lane >> 4;
-  const int qa = wv >> 1, qb = wv & 1;
-  const int kend = min(p, (ta + 1) * 64);
-  int ra[2];
-  bool va[2];
-  int64_t cb[2];
+  const double* inb = In + r0 * ldc + c0;
+  __shared__ double sB[32][65];
+  for (int grp = 0; grp * kTrmmRowsPerGroup < p; ++grp) {
+    f64x4 acc[4][4];
 #pragma unroll
-  for (int t = 0; t < 2; ++t) {
-    ra[t] = ta * 64 + qa * 32 + 16 * t + li;
-    va[t] = ra[t] < p;
-    cb[t] = static_cast<int64_t>(tc) * 64 + qb * 32 + 16 * t + li;
-  }
-  const double* inb = In + r0 * ldc;
-  f64x4 acc[2][2];
+    for (int jt = 0; jt < 4; ++jt)
 #pragma unroll
-  for (int t = 0; t < 2; ++t)
+      for (int u = 0; u < 4; ++u) acc[jt][u] = f64x4{};
+    const int kend = min(p, (grp + 1) * kTrmmRowsPerGroup);
+    for (int kc = 0; kc < kend; kc += 32) {
+      __syncthreads();
+      for (int e = threadIdx.x; e < 32 * 64; e += 256) {
+        const int r = e >> 6, c = e & 63;
+        sB[r][c] = kc + r < kend ? inb[static_cast<int64_t>(kc + r) * ldc + c] : 0.0;
+      }
+      __syncthreads();
+      double bf[4][8];
 #pragma unroll
-    for (int u = 0; u < 2; ++u) acc[t][u] = f64x4{};
-  for (int k0 = 0; k0 < kend; k0 += 32) {
-    double a[2][8], b[2][8];
+      for (int u = 0; u < 4; ++u)
 #pragma unroll
-    for (int j = 0; j < 8; ++j) {
-      const int k = k0 + 8 * g + j;
-      const bool kin = k < kend;
+        for (int j = 0; j < 8; ++j) bf[u][j] = sB[8 * g + j][16 * u + li];
 #pragma unroll
-      for (int t = 0; t < 2; ++t) {
-        a[t][j] = (kin && va[t]) ? Lb[static_cast<int64_t>(ra[t]) * p + k] : 0.0;
-        b[t][j] = (kin && cb[t] < ldc) ? inb[static_cast<int64_t>(k) * ldc + cb[t]] : 0.0;
+      for (int jt = 0; jt < 4; ++jt) {
+        const int rt = grp * (kTrmmRowsPerGroup / 16) + 4 * jt + wv;
+        if (16 * rt >= p || kc >= 16 * (rt + 1)) continue;  // uniform per wave
+        const int row = 16 * rt + li;
+        double a[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+          const int k = kc + 8 * g + j;
+          a[j] = (row < p && k < p) ? Lb[static_cast<int64_t>(row) * p + k] : 0.0;
+        }
+#pragma unroll
+        for (int j = 0; j < 8; ++j)
+#pragma unroll
+          for (int u = 0; u < 4; ++u)
+            acc[jt][u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[j], bf[u][j], acc[jt][u], 0, 0, 0);
       }
     }
 #pragma unroll
-    for (int j = 0; j < 8; ++j)
+    for (int jt = 0; jt < 4; ++jt)
 #pragma unroll
-      for (int t = 0; t < 2; ++t)
+      for (int u = 0; u < 4; ++u)
 #pragma unroll
-        for (int u = 0; u < 2; ++u)
-          acc[t][u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[t][j], b[u][j], acc[t][u], 0, 0, 0);
+        for (int q = 0; q < 4; ++q) {
+          const int row = 16 * (grp * (kTrmmRowsPerGroup / 16) + 4 * jt + wv) + g + 4 * q;
+          if (row < p) Out[(r0 + row) * ldc + c0 + 16 * u + li] = acc[jt][u][q];
+        }
   }
-#pragma unroll
-  for (int t = 0; t < 2; ++t)
-#pragma unroll
-    for (int u = 0; u < 2; ++u)
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int r = ta * 64 + qa * 32 + 16 * t + g + 4 * q;
-        const int64_t c = static_cast<int64_t>(tc) * 64 + qb * 32 + 16 * u + li;
-        if (r < p && c < ldc) Out[(r0 + r) * ldc + c] = acc[t][u][q];
-      }
 }
 
 }  // namespace
@@ -710,10 +716,12 @@ hipError_t launch_gram_mfma(const double* C, int64_t ldc, const int64_t* off,
 }
 
 hipError_t launch_trmm_mfma(const double* In, double* Out, int64_t ldc, const int64_t* off,
-                            const int32_t* tiles, int32_t ntiles, const int64_t* goff,
-                            const double* Linv, hipStream_t s) {
-  if (ntiles <= 0) return hipSuccess;
-  k_trmm_mfma<<<ntiles, 256, 0, s>>>(In, Out, ldc, off, tiles, goff, Linv);
+                            int32_t m, const int64_t* goff, const double* Linv, hipStream_t s) {
+  if (m <= 0) return hipSuccess;
+  if (ldc % 64 != 0) return hipErrorInvalidValue;
+  const int32_t nslab = static_cast<int32_t>(ldc / 64);
+  k_trmm_mfma<<<static_cast<unsigned>(m) * nslab, 256, 0, s>>>(In, Out, ldc, off, nslab, goff,
+                                                                Linv);
   return hipGetLastError();
 }
 

@@ -329,8 +329,7 @@ hipError_t launch_gram_mfma(const double* C, int64_t ldc, const int64_t* off,
                             const int32_t* tiles, int32_t ntiles, const int64_t* goff, double* G,
                             hipStream_t s);
 hipError_t launch_trmm_mfma(const double* In, double* Out, int64_t ldc, const int64_t* off,
-                            const int32_t* tiles, int32_t ntiles, const int64_t* goff,
-                            const double* Linv, hipStream_t s);
+                            int32_t m, const int64_t* goff, const double* Linv, hipStream_t s);
 hipError_t launch_trmm(const double* In, double* Out, int64_t ldc, const int64_t* off,
                        const int32_t* tiles, int32_t ntiles, const int64_t* goff,
                        const double* Linv, hipStream_t s);

@@ -645,37 +645,54 @@ __global__ __launch_bounds__(512) void k_chol_inv(const int64_t* off, const int6
     __syncthreads();
   }
 
-  // Off-diagonal block rows of Linv, top to bottom.
+  // Off-diagonal block rows of Linv, top to bottom, in 32 x 32 blocks through
+  // LDS: for block row I and block column J < I,
+  //   Linv[I][J] = -Linv_II sum_{K=J}^{I-1} L[I][K] Linv[K][J].
+  // Thread (i, c-pair): i = tid / 16, columns 2 (tid % 16) and 2 (tid % 16) + 1.
+  const int ti = tid >> 4, tc2 = (tid & 15) * 2;
   for (int I0 = kNB; I0 < p; I0 += kNB) {
     const int nbI = min(kNB, p - I0);
-    // t[i][c] = sum_{k=c}^{I0-1} L[I0+i][k] Linv[k][c], stored in Linv's block row.
-    for (int64_t e = tid; e < static_cast<int64_t>(nbI) * I0; e += nt) {
-      const int i = static_cast<int>(e / I0), c = static_cast<int>(e % I0);
-      const double* Lr = Gb + static_cast<int64_t>(I0 + i) * p;
-      double sacc = 0.0;
-      for (int k = c; k < I0; ++k) sacc += Lr[k] * Lb[static_cast<int64_t>(k) * p + c];
-      Lb[static_cast<int64_t>(I0 + i) * p + c] = sacc;
-    }
     // L_II^{-1} into LDS (zero-padded to 32 x 32).
     for (int e = tid; e < kNB * kNB; e += nt) {
       const int i = e / kNB, q = e % kNB;
       di[i][q] = (i < nbI && q <= i) ? Lb[static_cast<int64_t>(I0 + i) * p + I0 + q] : 0.0;
     }
-    __syncthreads();
-    // Linv[I0+i][c] = -sum_{q<=i} Linv_II[i][q] t[q][c]: one thread per column.
-    for (int c = tid; c < I0; c += nt) {
-      double o[kNB];
-#pragma unroll
-      for (int i = 0; i < kNB; ++i) o[i] = 0.0;
-#pragma unroll 1
-      for (int q = 0; q < nbI; ++q) {  // o[i] = sum_{q <= i} Linv_II[i][q] t[q][c]
-        const double tq = Lb[static_cast<int64_t>(I0 + q) * p + c];
-#pragma unroll
-        for (int i = 0; i < kNB; ++i) o[i] += (i >= q) ? di[i][q] * tq : 0.0;
+    for (int J0 = 0; J0 < I0; J0 += kNB) {
+      double t0 = 0.0, t1 = 0.0;
+      for (int K0 = J0; K0 < I0; K0 += kNB) {
+        __syncthreads();
+        // dl <- L[I0 + i][K0 + k], pan[0..31] <- Linv[K0 + k][J0 + c] (all in range:
+        // K0 + k < I0 <= p - 1 and J0 + c < I0).
+        for (int e = tid; e < kNB * kNB; e += nt) {
+          const int r = e / kNB, q = e % kNB;
+          dl[r][q] = r < nbI ? Gb[static_cast<int64_t>(I0 + r) * p + K0 + q] : 0.0;
+          pan[r][q] = Lb[static_cast<int64_t>(K0 + r) * p + J0 + q];
+        }
+        __syncthreads();
+        if (tid < 512) {
+#pragma unroll 8
+          for (int k = 0; k < kNB; ++k) {
+            const double l = dl[ti][k];
+            t0 = fma(l, pan[k][tc2], t0);
+            t1 = fma(l, pan[k][tc2 + 1], t1);
+          }
+        }
       }
-#pragma unroll
-      for (int i = 0; i < kNB; ++i)
-        if (i < nbI) Lb[static_cast<int64_t>(I0 + i) * p + c] = -o[i];
+      __syncthreads();
+      dl[ti][tc2] = t0;
+      dl[ti][tc2 + 1] = t1;
+      __syncthreads();
+      double o0 = 0.0, o1 = 0.0;
+#pragma unroll 8
+      for (int q = 0; q < kNB; ++q) {
+        const double d = di[ti][q];  // zero above the diagonal
+        o0 = fma(d, dl[q][tc2], o0);
+        o1 = fma(d, dl[q][tc2 + 1], o1);
+      }
+      if (ti < nbI) {
+        Lb[static_cast<int64_t>(I0 + ti) * p + J0 + tc2] = -o0;
+        Lb[static_cast<int64_t>(I0 + ti) * p + J0 + tc2 + 1] = -o1;
+      }
     }
     __syncthreads();
   }
