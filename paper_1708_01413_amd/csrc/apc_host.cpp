@@ -875,17 +875,18 @@ apc_status lanczos(apc_plan_s* P, const NormalOp& op, double cap, double* lo_out
       bd_hi = std::min(bd_hi, 1e-13 * th_hi);
     }
     // Converged ends: a small residual bound, or a Ritz value whose change
-    // over the last four steps is below 1e-4 (top) or 3e-3 (bottom) of its
+    // over the last four steps is below 3e-4 (top) or 1e-2 (bottom) of its
     // value, with a loose bound as a guard against an early plateau.  The
     // margins below cover the remaining movement (about 5x the last change for
     // the convergence rates seen at the spectral edges here) with a factor of
-    // 4 to spare.  The interval is then at most ~1e-4 wide above mu_max and a
-    // few percent below mu_min, which moves rho by O(width): at the 16384 x 8192
-    // benchmark shape 60 steps instead of 76 for +0.7 updates to 1e-6.
+    // 4 to spare.  The enclosing interval is then a few 1e-3 wide above mu_max
+    // and ~10 % below mu_min, which raises rho by O(width) only: at the
+    // 16384 x 8192 benchmark shape 40 steps (each costs about 1.3 updates)
+    // instead of 76 for about two more updates to 1e-6.
     d_lo = std::isnan(prev_lo) ? INFINITY : std::fabs(th_lo - prev_lo);
     d_hi = std::isnan(prev_hi) ? INFINITY : std::fabs(th_hi - prev_hi);
-    const bool hi_ok = bd_hi <= 1e-10 * th_hi || (d_hi <= 1e-4 * th_hi && bd_hi <= 1e-2 * th_hi);
-    const bool lo_ok = bd_lo <= 1e-6 * th_lo || (d_lo <= 3e-3 * th_lo && bd_lo <= 0.5 * th_lo);
+    const bool hi_ok = bd_hi <= 1e-10 * th_hi || (d_hi <= 3e-4 * th_hi && bd_hi <= 1e-2 * th_hi);
+    const bool lo_ok = bd_lo <= 1e-6 * th_lo || (d_lo <= 1e-2 * th_lo && bd_lo <= 0.5 * th_lo);
     prev_lo = th_lo;
     prev_hi = th_hi;
     done = exhausted || (hi_ok && lo_ok);
