@@ -265,7 +265,7 @@ apc_status apc_backward(apc_plan p, const double* dXbar, int64_t ldd, int32_t T,
  * system is a plan from apc_setup (k = 1, APC_F32, per-block form; all plans
  * on one stream), keeping its own factor and state in its own workspace.  Per
  * update a batch enqueues three launches for all systems together -- pass A
- * over a work list of (system, 8-row tile) items, pass B over (system, block,
+ * over a work list of (system, 16-row tile) items, pass B over (system, block,
  * column slab) items, the average over (system, column chunk) items -- each a
  * persistent grid of a fixed number of workgroups looping over the list.  The
  * grid is chosen at creation by timing pass A (APC_BATCH_GRID fixes it).  Each

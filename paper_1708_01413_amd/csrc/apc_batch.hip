@@ -8,7 +8,7 @@
 // skipped, so converged systems stop costing bandwidth.
 //
 // Per update (eq. (2a)-(2b) for every system):
-//   pass A   items (system, 8-row tile of one block):  w_r = C_r . d_i
+//   pass A   items (system, 16-row tile of one block): w_r = C_r . d_i
 //   pass B   items (system, block, 256-column slab):   x_i += gamma (x_bar - x_i - Q_i w_i)
 //   average  items (system, 256-column chunk):          x_bar <- (eta/m) sum_i x_i + (1-eta) x_bar,
 //                                                       d_i = x_bar - x_i
@@ -41,7 +41,9 @@ __device__ inline T wsum64(T v) {
   return v;
 }
 
-// Pass A: one wave per row of the item's tile.
+// Pass A: wave v takes rows v, v + 4, v + 8, v + 12 of the item's tile (up to
+// 16 rows), with all its rows' loads in flight together.  Rows past the tile
+// repeat the wave's first row and are not stored.
 template <typename TQ>
 __global__ __launch_bounds__(256) void k_batch_pass_a(const BatchSys* sys, const int4* items,
                                                       int32_t nitems, const int32_t* active) {
@@ -49,30 +51,42 @@ __global__ __launch_bounds__(256) void k_batch_pass_a(const BatchSys* sys, const
   for (int32_t it = blockIdx.x; it < nitems; it += gridDim.x) {
     const int4 w = items[it];
     if (!active[w.x]) continue;
+    if (wv >= w.z) continue;  // uniform per wave
     const BatchSys& S = sys[w.x];
     const TQ* C = static_cast<const TQ*>(S.C);
     const TQ* d = static_cast<const TQ*>(S.d) + static_cast<int64_t>(w.w) * S.ldc;
     TQ* out = static_cast<TQ*>(S.w);
-    for (int rr = wv; rr < w.z; rr += 4) {
-      const int64_t r = w.y + rr;
-      const TQ* row = C + r * S.ldc;
-      TQ acc = 0;
-      for (int64_t j = static_cast<int64_t>(lane) * 4; j < S.n; j += 256) {
-        if (j + 4 <= S.n) {
-          const float4 c = ld4_nt(row + j), v = ld4(d + j);
-          acc += c.x * v.x + c.y * v.y + c.z * v.z + c.w * v.w;
-        } else {
-          for (int64_t q = j; q < S.n; ++q) acc += row[q] * d[q];
-        }
+    const int64_t r0 = w.y + wv;
+    const TQ* row[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) row[q] = C + (wv + 4 * q < w.z ? r0 + 4 * q : r0) * S.ldc;
+    TQ acc[4] = {0, 0, 0, 0};
+    for (int64_t j = static_cast<int64_t>(lane) * 4; j < S.n; j += 256) {
+      if (j + 4 <= S.n) {
+        const float4 v = ld4(d + j);
+        float4 c[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) c[q] = ld4_nt(row[q] + j);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) acc[q] += c[q].x * v.x + c[q].y * v.y + c[q].z * v.z + c[q].w * v.w;
+      } else {
+        for (int64_t e = j; e < S.n; ++e)
+#pragma unroll
+          for (int q = 0; q < 4; ++q) acc[q] += row[q][e] * d[e];
       }
-      acc = wsum64(acc);
-      if (lane == 0) out[r] = acc;
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) acc[q] = wsum64(acc[q]);
+    if (lane == 0) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        if (wv + 4 * q < w.z) out[r0 + 4 * q] = acc[q];
     }
   }
 }
 
 // Pass B: lane l owns 4 columns of the item's 256-column slab; the 4 waves
-// take interleaved rows of the block (2 rows in flight per wave) and combine
+// take interleaved rows of the block (4 rows in flight per wave) and combine
 // in LDS; then one thread per column applies the FP64 update.
 template <typename TQ>
 __global__ __launch_bounds__(256) void k_batch_pass_b(const BatchSys* sys, const int4* items,
@@ -91,15 +105,16 @@ __global__ __launch_bounds__(256) void k_batch_pass_b(const BatchSys* sys, const
     float acc[4] = {0.f, 0.f, 0.f, 0.f};
     if (j + 4 <= S.ldc) {  // rows are padded to ldc (zeros past n)
       int64_t r = r0 + wv;
-      for (; r + 4 < r1; r += 8) {
+      for (; r + 12 < r1; r += 16) {
         const float4 c0 = ld4_nt(C + r * S.ldc + j), c1 = ld4_nt(C + (r + 4) * S.ldc + j);
-        const float s0 = wvec[r], s1 = wvec[r + 4];
-        acc[0] += c0.x * s0 + c1.x * s1;
-        acc[1] += c0.y * s0 + c1.y * s1;
-        acc[2] += c0.z * s0 + c1.z * s1;
-        acc[3] += c0.w * s0 + c1.w * s1;
+        const float4 c2 = ld4_nt(C + (r + 8) * S.ldc + j), c3 = ld4_nt(C + (r + 12) * S.ldc + j);
+        const float s0 = wvec[r], s1 = wvec[r + 4], s2 = wvec[r + 8], s3 = wvec[r + 12];
+        acc[0] += (c0.x * s0 + c1.x * s1) + (c2.x * s2 + c3.x * s3);
+        acc[1] += (c0.y * s0 + c1.y * s1) + (c2.y * s2 + c3.y * s3);
+        acc[2] += (c0.z * s0 + c1.z * s1) + (c2.z * s2 + c3.z * s3);
+        acc[3] += (c0.w * s0 + c1.w * s1) + (c2.w * s2 + c3.w * s3);
       }
-      if (r < r1) {
+      for (; r < r1; r += 4) {
         const float4 c0 = ld4_nt(C + r * S.ldc + j);
         const float s0 = wvec[r];
         acc[0] += c0.x * s0;

@@ -1743,8 +1743,8 @@ apc_status batch_items(const apc_plan* plans, int32_t count, BatchPlanItems* it)
     const apc_plan_s* P = plans[s];
     for (int i = 0; i < P->m; ++i) {
       const int64_t r0 = P->off[i], p = P->off[i + 1] - r0;
-      for (int64_t r = 0; r < p; r += 8)
-        it->A.push_back(make_int4(s, static_cast<int>(r0 + r), static_cast<int>(std::min<int64_t>(8, p - r)), i));
+      for (int64_t r = 0; r < p; r += 16)
+        it->A.push_back(make_int4(s, static_cast<int>(r0 + r), static_cast<int>(std::min<int64_t>(16, p - r)), i));
       for (int64_t j = 0; j < P->n; j += 256) it->B.push_back(make_int4(s, i, static_cast<int>(j), 0));
     }
     for (int64_t j = 0; j < P->n; j += 256) it->V.push_back(make_int2(s, static_cast<int>(j)));
