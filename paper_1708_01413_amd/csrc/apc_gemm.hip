@@ -577,7 +577,7 @@ __global__ __launch_bounds__(256) void k_gram_mfma(const double* C, int64_t ldc,
     pa[t] = C + (r0 + (va[t] ? ra : 0)) * ldc + 8 * g;
     pb[t] = C + (r0 + (vb[t] ? rb : 0)) * ldc + 8 * g;
   }
-  f64x2 ar[2][2][4], br[2][2][4];
+  f64x2 ar[3][2][4], br[3][2][4];  // ring of three K steps: two loaded ahead
   f64x4 acc[2][2];
 #pragma unroll
   for (int t = 0; t < 2; ++t)
@@ -609,12 +609,17 @@ __global__ __launch_bounds__(256) void k_gram_mfma(const double* C, int64_t ldc,
   };
   const int nsteps = static_cast<int>(ldc / 32);
   if (nsteps > 0) load(ar[0], br[0], 0);
-  for (int s0 = 0; s0 < nsteps; s0 += 2) {
-    if (s0 + 1 < nsteps) load(ar[1], br[1], s0 + 1);
+  if (nsteps > 1) load(ar[1], br[1], 1);
+  for (int s0 = 0; s0 < nsteps; s0 += 3) {
+    if (s0 + 2 < nsteps) load(ar[2], br[2], s0 + 2);
     compute(ar[0], br[0]);
     if (s0 + 1 < nsteps) {
-      if (s0 + 2 < nsteps) load(ar[0], br[0], s0 + 2);
+      if (s0 + 3 < nsteps) load(ar[0], br[0], s0 + 3);
       compute(ar[1], br[1]);
+    }
+    if (s0 + 2 < nsteps) {
+      if (s0 + 4 < nsteps) load(ar[1], br[1], s0 + 4);
+      compute(ar[2], br[2]);
     }
   }
   // acc[t][u][q] = G[row base + g + 4 q][column base + li].
