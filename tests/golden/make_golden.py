@@ -1,11 +1,16 @@
 """Write the oracle's expected values for the full-size parity tests.
 
-Calls only the FP64 oracle and the seeded input generator.  Output:
-tests/golden/tall_gauss_16384x8192_m64.npz with the oracle's spectrum
-estimate inputs (mu_min, mu_max), Theorem 1's parameters, the relative error
-curve err(t) for t = 0..T and x_bar(t) at every 8th coordinate for a few t.
+Calls only the FP64 oracle and the seeded input generators.  Outputs:
 
-Run:  python tests/golden/make_golden.py      (about a minute, ~3 GB of RAM)
+* tall_gauss_16384x8192_m64.npz: the oracle's spectrum (mu_min, mu_max),
+  Theorem 1's parameters, the relative error curve err(t) for t = 0..T and
+  x_bar(t) at every 8th coordinate for a few t;
+* shifted_uneven_8192_k64.npz: the same for N = n = 8192, A = G/sqrt(n) + 2I,
+  64 uneven blocks, 64 right-hand sides (every 64th coordinate of 8 columns);
+* many_small_systems_256.npz: for each of the 256 independent systems, its
+  parameters and x_bar(T) at every 16th coordinate after T updates.
+
+Run:  python tests/golden/make_golden.py [tall|batched|many]   (a few minutes)
 """
 
 import os
@@ -52,5 +57,73 @@ def main():
     print("wrote", out)
 
 
+BATCHED_T = 56
+BATCHED_CHECK = [0, 1, 2, 5, 10, 20, 34, 45, 56]
+BATCHED_COLS = [0, 1, 7, 13, 21, 34, 55, 63]
+BATCHED_STRIDE = 64
+
+
+def batched():
+    t0 = time.time()
+    S = synth.shifted_uneven_8k(k=64)
+    Qt, R = O.factor(S.A, S.off)
+    x = O.init_local(Qt, R, S.B, S.off)
+    xbar = O.initial_average(x)
+    mu_min, mu_max = O.spectrum(S.A, S.off)
+    g, e, rho = O.optimal_params(mu_min, mu_max)
+    print(f"batched: setup {time.time() - t0:.1f}s mu=[{mu_min:.6g}, {mu_max:.6g}] rho={rho:.6g}",
+          flush=True)
+    idx = np.arange(0, S.n, BATCHED_STRIDE)
+    cols = np.array(BATCHED_COLS)
+    xs = S.xstar
+    def err_of(xb):   # Frobenius norm over all columns, relative to ||X*||_F
+        return float(np.linalg.norm(xb - xs) / np.linalg.norm(xs))
+    err = [err_of(xbar)]
+    samples = {0: xbar[np.ix_(idx, cols)].copy()}
+    for t in range(1, BATCHED_T + 1):
+        x, xbar = O.apc_step(Qt, x, xbar, g, e)
+        err.append(err_of(xbar))
+        if t in BATCHED_CHECK:
+            samples[t] = xbar[np.ix_(idx, cols)].copy()
+    print(f"batched: iterate {time.time() - t0:.1f}s err(T)={err[-1]:.3e}", flush=True)
+    out = os.path.join(os.path.dirname(os.path.abspath(__file__)), "shifted_uneven_8192_k64.npz")
+    np.savez(out, mu_min=mu_min, mu_max=mu_max, gamma=g, eta=e, rho=rho, err=np.array(err),
+             check_t=np.array(BATCHED_CHECK), idx=idx, cols=cols,
+             samples=np.stack([samples[t] for t in BATCHED_CHECK]),
+             xstar_norm=np.linalg.norm(xs))
+    print("wrote", out)
+
+
+MANY_T = 20
+MANY_STRIDE = 16
+
+
+def many():
+    t0 = time.time()
+    systems = synth.many_small_systems(count=256, seed=0)
+    gam, eta, starts, vals, errs = [], [], [0], [], []
+    for S in systems:
+        mu_min, mu_max = O.spectrum(S.A, S.off)
+        g, e, _ = O.optimal_params(mu_min, mu_max)
+        out = O.apc_run(S.A, S.B, S.off, T=MANY_T, gamma=g, eta=e)
+        xb = out["xbar"][:, 0]
+        gam.append(g)
+        eta.append(e)
+        vals.append(xb[::MANY_STRIDE])
+        starts.append(starts[-1] + len(vals[-1]))
+        errs.append(np.linalg.norm(xb - S.xstar) / np.linalg.norm(S.xstar))
+    print(f"many: {time.time() - t0:.1f}s, err(T) in [{min(errs):.2e}, {max(errs):.2e}]", flush=True)
+    out = os.path.join(os.path.dirname(os.path.abspath(__file__)), "many_small_systems_256.npz")
+    np.savez(out, gamma=np.array(gam), eta=np.array(eta), T=MANY_T, stride=MANY_STRIDE,
+             starts=np.array(starts), samples=np.concatenate(vals), err=np.array(errs))
+    print("wrote", out)
+
+
 if __name__ == "__main__":
-    main()
+    which = sys.argv[1] if len(sys.argv) > 1 else "all"
+    if which in ("tall", "all"):
+        main()
+    if which in ("batched", "all"):
+        batched()
+    if which in ("many", "all"):
+        many()
