@@ -685,9 +685,9 @@ apc_status tn_tune(apc_plan_s* P, int type, TnArgs base, TnChoice* out) {
 // One update of eq. (2a)-(2b).  k = 1: for each group of blocks, pass A then
 // pass B (pass B of a block needs only that block's w, so a group's rows of C
 // are re-read while they are still in the Infinity Cache), then the average.
-// With ev non-null, an event is recorded after every launch and the launch
-// kinds (0 pass A, 1 pass B, 2 average/epilogue) are appended to kinds; *nev
-// receives the number recorded (at most launches_per_update).
+// With ev non-null, every kernel takes a pair of events (time_next) and its
+// kind (0 pass A, 1 pass B, 2 average/epilogue) is appended to kinds; *nev
+// receives the number of timed kernels (at most launches_per_update).
 apc_status update(apc_plan_s* P, hipEvent_t* ev, int* kinds, int* nev) {
   if (P->gemm) return update_gemm(P, ev, kinds, nev);
   const int g = P->group_blocks > 0 ? P->group_blocks : P->m;
