@@ -478,6 +478,9 @@ def main():
                     help="skip the batched and mixed-precision comparisons")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a plain 1 GiB device copy (reference for HBM counters)")
+    ap.add_argument("--bf16-contraction-only", action="store_true",
+                    help="only the mixed-precision system (16384^2, k = 128, alpha = 3): setup and "
+                         "8 bf16 updates, for counter runs of the matrix-core contraction")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: sharding the blocks over several GPUs (one "
@@ -496,6 +499,20 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    if args.bf16_contraction_only:
+        nn, kk, mm = 16384, 128, 64
+        rng = np.random.default_rng(0)
+        G = torch.from_numpy(rng.standard_normal((nn, nn)) / np.sqrt(nn)).to(dev)
+        G.diagonal().add_(3.0)
+        Xs = torch.from_numpy(rng.standard_normal((nn, kk))).to(dev)
+        Bm = (G @ Xs).contiguous()
+        offm = synth.offsets_from_sizes(synth.even_sizes(nn, mm))
+        plan = apc.Plan(G, Bm, offm, "bf16_ir", gamma=1.0, eta=1.0, anchor_every=0)
+        plan.iterate(8)
+        torch.cuda.synchronize()
+        print(json.dumps({"workload": "N=n=16384, A=G/sqrt(n)+3I, k=128, m=64, bf16 contraction",
+                          "updates": 8, "launch_shapes": plan.launch_shapes()}), flush=True)
+        return
     S = synth.tall_gaussian_16k()
     N, n, m = S.N, S.n, S.m
     A = torch.from_numpy(S.A).to(dev)
