@@ -83,6 +83,28 @@ def algorithmic_bytes(N, n, m, sq=4, sx=8):
     return pass_a, pass_b, average, per_update
 
 
+def algorithmic_bytes_single(N, n, m, ntiles, sq=4, sx=8):
+    """Bytes of the single-pass update (each launch's inputs read once, outputs written once).
+
+    single pass: C once, the differences d_i, one partial row (n entries) per row tile.
+    combine: the partial rows, x_i read and written, x_bar read and written, d_i written.
+    Per update: N n s_Q + 2 m n s_Q + 2 ntiles n s_Q + 2 m n s_x + 2 n s_x.
+    """
+    single = N * n * sq + m * n * sq + ntiles * n * sq
+    combine = ntiles * n * sq + 2 * m * n * sx + 2 * n * sx + m * n * sq
+    return single, combine, single + combine
+
+
+def chunks_per_thread(n, elem):
+    """Register chunks (16 bytes) of a row per thread of the single-pass kernel."""
+    ldc = -(-n // 64) * 64
+    chunks = ldc * elem // 16
+    c = 1
+    while chunks > 256 * c:
+        c *= 2
+    return c
+
+
 def cpu_baseline(S, per_iter_bytes, budget_iters=8):
     """The FP64 oracle, as it stands, on the same system: factor + init once, then a few
     updates; reported in the benchmark's unit (the GPU path's bytes per update)."""
@@ -405,12 +427,14 @@ def secondary(apc, synth, dev):
     err = float(torch.linalg.norm(plan.xbar() - torch.from_numpy(S.xstar).to(dev))) / float(
         np.linalg.norm(S.xstar))
     _, pa, pb, pv = plan.iterate_timed(2000)
-    out["square512_fp64"] = {"workload": "N=n=512, A, x* iid N(0,1), m=8 blocks of 64, FP64",
-                             "updates": 2000, "us_per_update": round(tot * 1e3 / 2000, 2),
-                             "pass_a_us": round(pa * 1e3 / 2000, 2),
-                             "pass_b_us": round(pb * 1e3 / 2000, 2),
-                             "average_us": round(pv * 1e3 / 2000, 2),
-                             "err_after_2050": err, "params": plan.params()}
+    single = plan.single_pass_shape()
+    kern = ({"single_pass_us": round(pa * 1e3 / 2000, 2), "combine_us": round(pv * 1e3 / 2000, 2),
+             "single_pass_shape": single} if single is not None else
+            {"pass_a_us": round(pa * 1e3 / 2000, 2), "pass_b_us": round(pb * 1e3 / 2000, 2),
+             "average_us": round(pv * 1e3 / 2000, 2)})
+    out["square512_fp64"] = dict({"workload": "N=n=512, A, x* iid N(0,1), m=8 blocks of 64, FP64",
+                                  "updates": 2000, "us_per_update": round(tot * 1e3 / 2000, 2),
+                                  "err_after_2050": err, "params": plan.params()}, **kern)
     plan.close()
     del A, b, S
     # Batched: N = n = 8192, A = G/sqrt(n) + 2I, k = 64, 64 blocks of uneven size.
@@ -564,27 +588,77 @@ def main():
         av_ms.append(v_ms)
         prm = plan.params()
         plan_info = plan.info()
+        single = plan.single_pass_shape()
         plan.close()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ms_per_step = wall * 1e3 / args.steps
 
     sq = 4 if args.precision == "f32" else 8
-    plan_groups = plan_info["block_groups"]
-    bytes_a, bytes_b, bytes_v, per_iter = algorithmic_bytes(N, n, m, sq=sq)
     it_ms = float(np.mean(iter_ms))
+    ptype = "float" if args.precision == "f32" else "double"
+    if single is not None:
+        rows, grp = single["rows_per_wg"], single["rows_per_group"]
+        ntiles = int(sum(-(-int(p) // rows) for p in np.diff(S.off)))
+        bytes_f, bytes_c, per_iter = algorithmic_bytes_single(N, n, m, ntiles, sq=sq)
+        launches = T * args.steps
+        avg_f = float(np.sum(pa_ms)) / launches
+        avg_c = float(np.sum(av_ms)) / launches
+        dom_bytes, dom_ms = bytes_f, avg_f
+        dom_label = f"k_fused<{ptype}, {ptype}, {chunks_per_thread(n, sq)}, {grp}>"
+        dom_fn = "k_fused"
+        iteration = {
+            "form": "single pass over C per update, then the x_i update + average launch",
+            "single_pass_us_per_launch": round(avg_f * 1e3, 2),
+            "combine_us_per_launch": round(avg_c * 1e3, 2),
+            "single_pass_GBs": round(bytes_f / (avg_f * 1e-3) / 1e9, 1),
+            "combine_GBs": round(bytes_c / (avg_c * 1e-3) / 1e9, 1),
+            "rows_per_workgroup": rows, "rows_per_register_group": grp, "tiles": ntiles,
+        }
+    else:
+        plan_groups = plan_info["block_groups"]
+        bytes_a, bytes_b, bytes_v, per_iter = algorithmic_bytes(N, n, m, sq=sq)
+        # Per-launch averages (a group of blocks is one launch of each pass).
+        launches = plan_groups * T * args.steps
+        avg_a = float(np.sum(pa_ms)) / launches
+        avg_b = float(np.sum(pb_ms)) / launches
+        avg_v = float(np.sum(av_ms)) / (T * args.steps)
+        bytes_a_l, bytes_b_l = bytes_a / plan_groups, bytes_b / plan_groups
+        dom, dom_bytes, dom_ms = (("pass_b", bytes_b_l, avg_b) if avg_b >= avg_a
+                                  else ("pass_a", bytes_a_l, avg_a))
+        dom_label, dom_fn = {"pass_a": (f"k_rowdot<{ptype}, {ptype}, 8, 2, true>", "k_rowdot"),
+                             "pass_b": (f"k_pass_b_rows<{ptype}, true>", "k_pass_b_rows")}[dom]
+        iteration = {
+            "form": "two passes over C per update, then the average",
+            "block_groups": plan_groups,
+            "pass_a_us_per_launch": round(avg_a * 1e3, 2),
+            "pass_b_us_per_launch": round(avg_b * 1e3, 2),
+            "average_us": round(avg_v * 1e3, 2),
+            "pass_a_GBs": round(bytes_a_l / (avg_a * 1e-3) / 1e9, 1),
+            "pass_b_GBs": round(bytes_b_l / (avg_b * 1e-3) / 1e9, 1),
+            "average_GBs": round(bytes_v / (avg_v * 1e-3) / 1e9, 1),
+        }
     value = per_iter * T / (it_ms * 1e-3) / 1e9
-    # Per-launch averages (a group of blocks is one launch of each pass).
-    launches = plan_groups * T * args.steps
-    avg_a = float(np.sum(pa_ms)) / launches
-    avg_b = float(np.sum(pb_ms)) / launches
-    avg_v = float(np.sum(av_ms)) / (T * args.steps)
-    bytes_a_l, bytes_b_l = bytes_a / plan_groups, bytes_b / plan_groups
-    dom, dom_bytes, dom_ms = (("pass_b", bytes_b_l, avg_b) if avg_b >= avg_a
-                              else ("pass_a", bytes_a_l, avg_a))
     achieved = dom_bytes / (dom_ms * 1e-3) / 1e9
-    dom_label, dom_fn = {"pass_a": ("k_rowdot<float, float, 8, 2, true>", "k_rowdot"),
-                         "pass_b": ("k_pass_b_rows<float, true>", "k_pass_b_rows")}[dom]
+    # The same system with two passes over C per update (the form the single pass
+    # replaces), for comparison: whole-update time only.
+    two_pass = None
+    if single is not None:
+        os.environ["APC_FUSED"] = "0"
+        try:
+            p2 = apc.Plan(A, b, S.off, args.precision, workspace=ws, stream=stream)
+        finally:
+            del os.environ["APC_FUSED"]
+        p2.iterate(T)
+        t2 = plain_updates_ms(p2, T)
+        _, a2, b2, v2 = p2.iterate_timed(T)
+        ba, bb, _, per2 = algorithmic_bytes(N, n, m, sq=sq)
+        two_pass = {"us_per_update": round(t2 * 1e3 / T, 2),
+                    "pass_a_us": round(a2 * 1e3 / T, 2), "pass_b_us": round(b2 * 1e3 / T, 2),
+                    "average_us": round(v2 * 1e3 / T, 2),
+                    "algorithmic_bytes_per_update": per2,
+                    "GBs": round(per2 * T / (t2 * 1e-3) / 1e9, 1)}
+        p2.close()
 
     out = {
         "metric": METRIC,
@@ -606,30 +680,25 @@ def main():
         },
         "roofline": {
             "bound": "hbm",
-            "kernel": dom_label if args.precision == "f32" else dom,
+            "kernel": dom_label,
             "achieved": round(achieved, 1),
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": (measured_traffic(dom_label, dom_fn) if args.precision == "f32" else None),
+            "traffic": measured_traffic(dom_label, dom_fn),
             "algorithmic_bytes_per_launch": dom_bytes,
             "avg_launch_us": round(dom_ms * 1e3, 2),
         },
-        "iteration": {
+        "iteration": dict({
             "updates_to_1e-5": iters_needed.get(1e-5),
             f"updates_to_{args.target:g}": T,
             "err_at_end_of_warmup": final_err,
             "us_per_update": round(it_ms * 1e3 / T, 2),
-            "block_groups": plan_groups,
-            "pass_a_us_per_launch": round(avg_a * 1e3, 2),
-            "pass_b_us_per_launch": round(avg_b * 1e3, 2),
-            "average_us": round(avg_v * 1e3, 2),
-            "pass_a_GBs": round(bytes_a_l / (avg_a * 1e-3) / 1e9, 1),
-            "pass_b_GBs": round(bytes_b_l / (avg_b * 1e-3) / 1e9, 1),
-            "average_GBs": round(bytes_v / (avg_v * 1e-3) / 1e9, 1),
+            "updates_per_s": round(T / (it_ms * 1e-3), 1),
             "algorithmic_bytes_per_update": per_iter,
             "launch_shape": plan_info,
-        },
+        }, **iteration),
+        "two_pass_same_system": two_pass,
         "time_to_target_ms": {
             "target_rel_err": args.target,
             "setup_ms": round(float(np.mean(setup_ms)), 3),

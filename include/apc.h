@@ -110,19 +110,26 @@ apc_status apc_setup(apc_plan* out, const double* A, int64_t lda, const double* 
                      size_t ws_bytes, void* stream);
 
 /* Apply T updates of eq. (2a)-(2b) (T >= 0).  Asynchronous: per update it
- * enqueues, k = 1: for each group of blocks, projection pass A (w_i =
- * Q_i^T (x_bar - x_i)) and pass B (x_i += gamma (x_bar - x_i - Q_i w_i)), then
- * the momentum average x_bar <- (eta/m) sum_i x_i + (1 - eta) x_bar;
+ * enqueues, k = 1 with n <= 16384 (FP32) or 8192 (FP64): one pass over the
+ * factor that forms w_i = Q_i^T (x_bar - x_i) row by row and adds each row's
+ * share of Q_i w_i while the row is in registers, then one launch for
+ * x_i += gamma (x_bar - x_i - Q_i w_i), the momentum average
+ * x_bar <- (eta/m) sum_i x_i + (1 - eta) x_bar and the next differences;
+ * other k = 1 plans (or APC_FUSED=0 in the environment at setup): for each
+ * group of blocks, projection pass A (w_i = Q_i^T (x_bar - x_i)) and pass B
+ * (x_i += gamma (x_bar - x_i - Q_i w_i)), then the average;
  * k-RHS form: pass A (W = C y), its split sum, pass B (Z = C^T W) and the
  * elementwise step y <- (1-gamma) y + gamma x_bar,
  * x_bar <- eta (x_bar(0) + y - Z/m) + (1 - eta) x_bar.  Returns at once. */
 apc_status apc_iterate(apc_plan p, int32_t T);
 
-/* As apc_iterate, and also times the launches with HIP events recorded on the
- * plan's stream after every launch: *ms_total receives the span of the T
- * updates (launch gaps included); *ms_pass_a, *ms_pass_b and *ms_average the
- * summed durations of the pass-A, pass-B and averaging launches (host
- * pointers, any may be NULL).  Synchronises the stream once, at the end. */
+/* As apc_iterate, and also times every launch with a pair of HIP events that
+ * the launch itself records at its start and end: *ms_total receives the span
+ * of the T updates; *ms_pass_a, *ms_pass_b and *ms_average the summed
+ * durations of the pass-A, pass-B and averaging launches (the single-pass
+ * update counts its pass over C as pass A and its second launch as the
+ * average).  Host pointers, any may be NULL.  Synchronises the stream once,
+ * at the end. */
 apc_status apc_iterate_timed(apc_plan p, int32_t T, float* ms_total, float* ms_pass_a,
                              float* ms_pass_b, float* ms_average);
 
@@ -197,8 +204,10 @@ apc_status apc_get_info(apc_plan p, int32_t* lanczos_steps, int32_t* rows_per_ti
  * residual): rows of the streamed operand per workgroup, split-K factor, and
  * the measured time per launch when it was chosen by timing (0 when fixed by
  * APC_TN_TUNE=0 / APC_TN_RT / APC_TN_SPLIT).  Shapes are timed once per
- * problem shape and process.  Host pointers, any may be NULL.
- * APC_EUNSUPPORTED for a k = 1 FP64/FP32 plan. */
+ * problem shape and process.  which = 4: the single-pass k = 1 update, rows
+ * per workgroup and rows per register group (in *splits), *tuned_us = 0.
+ * Host pointers, any may be NULL.  APC_EUNSUPPORTED for which 0..3 on a k = 1
+ * FP64/FP32 plan and for which = 4 on a plan that updates in two passes. */
 apc_status apc_get_launch(apc_plan p, int32_t which, int32_t* rows_per_wg, int32_t* splits,
                           float* tuned_us);
 

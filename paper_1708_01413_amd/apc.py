@@ -417,6 +417,17 @@ class Plan:
         return {name: apc_get_launch(self.handle, w)
                 for w, name in enumerate(("pass_a", "pass_b", "start", "residual"))}
 
+    def single_pass_shape(self):
+        """Rows per workgroup and rows per register group of the single-pass k = 1
+        update, or None when the plan updates in two passes over C."""
+        rows, g, us = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_float()
+        st = lib.apc_get_launch(self.handle, 4, ctypes.byref(rows), ctypes.byref(g),
+                                ctypes.byref(us))
+        if st == APC_EUNSUPPORTED:
+            return None
+        _check(st)
+        return {"rows_per_wg": rows.value, "rows_per_group": g.value}
+
     @property
     def iterations(self) -> int:
         return apc_iterations(self.handle)

@@ -65,6 +65,8 @@ int64_t round_up(int64_t v, int64_t a) { return (v + a - 1) / a * a; }
 struct Layout {
   int64_t ldc = 0, kmax = 0, S = 0;
   int32_t ntiles_a = 0, ntiles_g = 0, ntiles_t = 0, nparts = 0;
+  int32_t ntiles_fmax = 0;  // single-pass row tiles the workspace holds (k = 1)
+  size_t tiles_f = 0, fpart = 0;
   // k-RHS path: rows/K padding of its operands (N and n rounded up to kTnPad)
   int64_t Np = 0, np = 0;
   size_t Cq, CqT, C64T, Apad, yq, Wq, tnpart, x0, ys, c64p, Xs, Rb, cw, Linv2, ssq;
@@ -77,7 +79,36 @@ struct Tiles {
   std::vector<int32_t> g;                        // Gram tiles (blk, ta, tb), ta >= tb
   std::vector<int32_t> t;                        // TRMM tiles (blk, ta, tc)
   std::vector<int64_t> goff;                     // offset of G_i in the packed Gram storage
+  std::vector<int32_t> f_row0, f_nrows, f_blk;  // single-pass row tiles (k = 1)
+  std::vector<int32_t> f_first;                 // first single-pass tile of every block (m+1)
 };
+
+constexpr int kFusedMinRows = 16;  // the workspace holds single-pass tiles of this height or more
+
+void build_fused_tiles(const int64_t* off, int32_t m, int rows_per_tile, Tiles* T) {
+  T->f_first.assign(1, 0);
+  for (int i = 0; i < m; ++i) {
+    const int64_t p = off[i + 1] - off[i];
+    for (int64_t r = 0; r < p; r += rows_per_tile) {
+      T->f_row0.push_back(static_cast<int32_t>(off[i] + r));
+      T->f_nrows.push_back(static_cast<int32_t>(std::min<int64_t>(rows_per_tile, p - r)));
+      T->f_blk.push_back(i);
+    }
+    T->f_first.push_back(static_cast<int32_t>(T->f_row0.size()));
+  }
+}
+
+// Default single-pass shape: two rows per register group (one at the widest
+// rows, where two spill), and tiles of 64 rows, fewer when that leaves under
+// about one workgroup per CU.  At 16384 x 8192 in FP32, 64 rows and groups of
+// two measured best (85.5 us per launch against 88-145 us for 16-128 rows and
+// groups of one to four).
+void fused_shape(int64_t N, int elem, int cpt, int32_t* rows, int32_t* g) {
+  *g = fused_shape_ok(elem, elem, cpt, 2) ? 2 : 1;
+  int32_t r = 64;
+  while (r > kFusedMinRows && N / r < 256) r /= 2;
+  *rows = r;
+}
 
 constexpr int kMinRowTile = 8;  // the workspace holds pass-A tile lists of this height or more
 constexpr int kPassARows = 8;   // default rows per pass-A workgroup
@@ -203,6 +234,15 @@ Layout make_layout(int64_t N, int64_t n, const int64_t* off, int32_t m, int32_t 
   L.cw = take(bf ? kp * N * d : 0);
   L.ssq = take(sumsq_parts() * d);
   L.tiles_a = take(3 * max_tiles_a * 4);
+  // Single-pass k = 1 iteration: its tile lists and one partial row per tile.
+  if (!gemm && k == 1) {
+    int64_t nf = 0;
+    for (int i = 0; i < m; ++i) nf += (off[i + 1] - off[i] + kFusedMinRows - 1) / kFusedMinRows;
+    L.ntiles_fmax = static_cast<int32_t>(nf);
+  }
+  L.tiles_f = take((3 * static_cast<int64_t>(L.ntiles_fmax) + m + 1) * 4);
+  // FP64 entries: the normal operator of the eigenvalue estimate sums in FP64.
+  L.fpart = take(static_cast<int64_t>(L.ntiles_fmax) * L.ldc * 8);
   L.tiles_g = take(3 * static_cast<int64_t>(L.ntiles_g) * 4);
   L.tiles_t = take(3 * static_cast<int64_t>(L.ntiles_t) * 4);
   L.doff = take((m + 1) * 8);
@@ -356,6 +396,9 @@ struct apc_plan_s {
   int32_t passb_nt = 1;                // k = 1 pass B: non-temporal loads of C
   int32_t passb_rows = 1;              // k = 1 pass B: waves split the block's rows
   int32_t passa_nt = 1;                // k = 1 pass A: non-temporal loads of C
+  bool fused = false;                  // k = 1: both halves of eq. (2a) in one pass over C
+  int32_t fused_rows = 0, fused_g = 0, ntiles_f = 0;
+  int32_t fused_tpb = 0;               // > 0: every block has this many single-pass tiles
   int64_t since_start = 0;             // k-RHS updates since the last start
   int refinements = 0;
   std::vector<int32_t> tile_start;     // first pass-A tile of every block (m+1)
@@ -368,6 +411,7 @@ struct apc_plan_s {
   double* xbar() const { return at<double>(L.xbar); }
   int64_t* doff() const { return at<int64_t>(L.doff); }
   int32_t* ta(int which) const { return at<int32_t>(L.tiles_a) + which * L.ntiles_a; }
+  int32_t* tf(int which) const { return at<int32_t>(L.tiles_f) + which * ntiles_f; }
   int32_t slab_cols() const { return pass_b_slab(prec == APC_F32 ? 4 : 8, passb_rows); }
   int64_t state_ld() const { return static_cast<int64_t>(kp) * L.ldc; }  // block stride of x, d
 };
@@ -426,6 +470,44 @@ apc_status pass_b(apc_plan_s* P, int i0, int i1, int col) {
                         P->state_ld(), P->xbar() + coff, P->gamma, i0, P->passb_nt,
                        P->passb_rows};
     HIP_TRY(launch_pass_b_f64(a, P->stream));
+  }
+  return APC_OK;
+}
+
+// Both halves of eq. (2a) in one pass over C (k = 1): every single-pass tile
+// writes its part of Q_i w_i, w = C_i d_i formed row by row on the way.
+apc_status fused_pass(apc_plan_s* P) {
+  const Layout& L = P->L;
+  const int32_t remap = P->xcd_remap == 1 ? 1 : 0;
+  if (P->prec == APC_F32) {
+    FusedArgs<float, float> a{P->at<float>(L.C32), L.ldc, P->n, P->tf(0), P->tf(1), P->tf(2),
+                              P->ntiles_f, P->at<float>(L.dv), P->state_ld(),
+                              P->at<float>(L.fpart), L.ldc, remap};
+    HIP_TRY(launch_fused_f32(a, P->fused_g, P->stream));
+  } else {
+    FusedArgs<double, double> a{P->C64(), L.ldc, P->n, P->tf(0), P->tf(1), P->tf(2),
+                                P->ntiles_f, P->at<double>(L.dv), P->state_ld(),
+                                P->at<double>(L.fpart), L.ldc, remap};
+    HIP_TRY(launch_fused_f64(a, P->fused_g, P->stream));
+  }
+  return APC_OK;
+}
+
+// After fused_pass: x_i += gamma (x_bar - x_i - Q_i w_i), the average of
+// eq. (2b) with weights (alpha, beta), and the next d_i.
+apc_status fused_combine(apc_plan_s* P, double alpha, double beta) {
+  const Layout& L = P->L;
+  const int64_t ld = P->state_ld();
+  if (P->prec == APC_F32) {
+    FusedCombineArgs<float> a{P->at<float>(L.fpart), L.ldc, P->tf(3), P->x(), ld, P->m, P->n,
+                              P->gamma, alpha, beta, P->xbar(), P->at<float>(L.dv), ld,
+                              P->fused_tpb};
+    HIP_TRY(launch_fused_combine_f32(a, P->stream));
+  } else {
+    FusedCombineArgs<double> a{P->at<double>(L.fpart), L.ldc, P->tf(3), P->x(), ld, P->m, P->n,
+                               P->gamma, alpha, beta, P->xbar(), P->at<double>(L.dv), ld,
+                               P->fused_tpb};
+    HIP_TRY(launch_fused_combine_f64(a, P->stream));
   }
   return APC_OK;
 }
@@ -682,7 +764,8 @@ apc_status tn_tune(apc_plan_s* P, int type, TnArgs base, TnChoice* out) {
   return APC_OK;
 }
 
-// One update of eq. (2a)-(2b).  k = 1: for each group of blocks, pass A then
+// One update of eq. (2a)-(2b).  k = 1, single pass: fused_pass, then
+// fused_combine.  k = 1, two passes: for each group of blocks, pass A then
 // pass B (pass B of a block needs only that block's w, so a group's rows of C
 // are re-read while they are still in the Infinity Cache), then the average.
 // With ev non-null, every kernel takes a pair of events (time_next) and its
@@ -690,6 +773,17 @@ apc_status tn_tune(apc_plan_s* P, int type, TnArgs base, TnChoice* out) {
 // receives the number of timed kernels (at most launches_per_update).
 apc_status update(apc_plan_s* P, hipEvent_t* ev, int* kinds, int* nev) {
   if (P->gemm) return update_gemm(P, ev, kinds, nev);
+  if (P->fused) {
+    int e = 0;
+    time_next(P, ev, kinds, &e, 0);
+    ST_TRY(fused_pass(P));
+    ST_TRY(timed_done(P, ev, e));
+    time_next(P, ev, kinds, &e, 2);
+    ST_TRY(fused_combine(P, P->eta / P->m, 1.0 - P->eta));
+    ST_TRY(timed_done(P, ev, e));
+    if (nev) *nev = e;
+    return APC_OK;
+  }
   const int g = P->group_blocks > 0 ? P->group_blocks : P->m;
   int e = 0;
   for (int i0 = 0; i0 < P->m; i0 += g) {
@@ -710,6 +804,7 @@ apc_status update(apc_plan_s* P, hipEvent_t* ev, int* kinds, int* nev) {
 
 int launches_per_update(const apc_plan_s* P) {
   if (P->gemm) return 4;
+  if (P->fused) return 2;
   const int g = P->group_blocks > 0 ? P->group_blocks : P->m;
   return 2 * ((P->m + g - 1) / g) + 1;
 }
@@ -754,6 +849,24 @@ NormalOp x_operator(const apc_plan_s* P) {
 // out = op(v), FP64 vectors and accumulation.
 apc_status normal_matvec(apc_plan_s* P, const NormalOp& op, const double* v, double* out) {
   const Layout& L = P->L;
+  // One pass over C (the plan's single-pass tiles, v shared by every tile),
+  // then the FP64 sum of the tiles' partial rows.
+  const int cpt32 = fused_cpt(L.ldc, 4), cpt64 = fused_cpt(L.ldc, 8);
+  if (P->fused && (op.f32 ? fused_shape_ok(4, 8, cpt32, 1) : cpt64 > 0)) {
+    double* part = P->at<double>(L.fpart);
+    const int32_t remap = P->xcd_remap == 1 ? 1 : 0;
+    if (op.f32) {
+      FusedArgs<float, double> a{static_cast<const float*>(op.C), L.ldc, P->n, P->tf(0),
+                                 P->tf(1), P->tf(2), P->ntiles_f, v, 0, part, L.ldc, remap};
+      HIP_TRY(launch_fused_f32x64(a, 1, P->stream));
+    } else {
+      FusedArgs<double, double> a{static_cast<const double*>(op.C), L.ldc, P->n, P->tf(0),
+                                  P->tf(1), P->tf(2), P->ntiles_f, v, 0, part, L.ldc, remap};
+      HIP_TRY(launch_fused_f64(a, cpt64 >= 16 ? 1 : 2, P->stream));
+    }
+    HIP_TRY(launch_fused_sum(part, L.ldc, P->ntiles_f, L.ldc, op.scale, out, P->stream));
+    return APC_OK;
+  }
   double* u = P->at<double>(L.w);
   double* Y = P->at<double>(L.Y);
   const int g = P->group_blocks > 0 ? P->group_blocks : P->m;
@@ -969,6 +1082,14 @@ apc_status setup_impl(apc_plan_s* P, const Tiles& T) {
   ta.insert(ta.end(), T.a_blk.begin(), T.a_blk.end());
   HIP_TRY(hipMemcpyAsync(P->at<int32_t>(L.tiles_a), ta.data(), ta.size() * 4, hipMemcpyHostToDevice, st));
   HIP_TRY(hipMemcpyAsync(P->at<int32_t>(L.tiles_g), T.g.data(), T.g.size() * 4, hipMemcpyHostToDevice, st));
+  std::vector<int32_t> tf;
+  if (P->fused) {
+    tf.insert(tf.end(), T.f_row0.begin(), T.f_row0.end());
+    tf.insert(tf.end(), T.f_nrows.begin(), T.f_nrows.end());
+    tf.insert(tf.end(), T.f_blk.begin(), T.f_blk.end());
+    tf.insert(tf.end(), T.f_first.begin(), T.f_first.end());
+    HIP_TRY(hipMemcpyAsync(P->at<int32_t>(L.tiles_f), tf.data(), tf.size() * 4, hipMemcpyHostToDevice, st));
+  }
   HIP_TRY(hipMemcpyAsync(P->at<int32_t>(L.tiles_t), T.t.data(), T.t.size() * 4, hipMemcpyHostToDevice, st));
   HIP_TRY(hipMemcpyAsync(P->doff(), P->off.data(), (m + 1) * 8, hipMemcpyHostToDevice, st));
   HIP_TRY(hipMemcpyAsync(P->at<int64_t>(L.goff), T.goff.data(), m * 8, hipMemcpyHostToDevice, st));
@@ -1128,6 +1249,26 @@ apc_status apc_setup(apc_plan* out, const double* A, int64_t lda, const double* 
   }
   Tiles T;
   build_tiles(off, m, round_up(n, kLdAlign), passa_rows, &T);
+  // k = 1 FP64/FP32: one pass over C per update when a row fits the
+  // single-pass kernel (n up to 16384 in FP32, 8192 in FP64).
+  const int32_t base_prec = base_precision(precision);
+  const int elem = base_prec == APC_F32 ? 4 : 8;
+  const int cpt = fused_cpt(round_up(n, kLdAlign), elem);
+  bool fused = !uses_gemm(k, precision) && k == 1 && cpt > 0;
+  if (const char* e = std::getenv("APC_FUSED")) fused = fused && std::atoi(e) != 0;
+  int32_t fused_rows = 0, fused_g = 0;
+  if (fused) {
+    fused_shape(N, elem, cpt, &fused_rows, &fused_g);
+    if (const char* e = std::getenv("APC_FUSED_ROWS")) {
+      const int r = std::atoi(e);
+      if (r == 16 || r == 32 || r == 64 || r == 128) fused_rows = r;
+    }
+    if (const char* e = std::getenv("APC_FUSED_G")) {
+      const int g = std::atoi(e);
+      if (fused_shape_ok(elem, elem, cpt, g)) fused_g = g;
+    }
+    build_fused_tiles(off, m, fused_rows, &T);
+  }
   const Layout L = make_layout(N, n, off, m, k, precision, T);
   if (ws_bytes < L.total)
     return fail(APC_EINVAL, "workspace has %zu bytes, needs %zu", ws_bytes, L.total);
@@ -1161,6 +1302,16 @@ apc_status apc_setup(apc_plan* out, const double* A, int64_t lda, const double* 
   P->passb_rows = passb_rows;
   P->passa_nt = passa_nt;
   P->passa_rows = passa_rows;
+  P->fused = fused;
+  P->fused_rows = fused_rows;
+  P->fused_g = fused_g;
+  P->ntiles_f = static_cast<int32_t>(T.f_row0.size());
+  if (fused) {
+    const int32_t t0 = T.f_first[1];
+    bool same = true;
+    for (int i = 0; i < m; ++i) same = same && T.f_first[i + 1] - T.f_first[i] == t0;
+    if (same && (t0 == 1 || t0 == 2 || t0 == 4 || t0 == 8)) P->fused_tpb = t0;
+  }
   P->tile_start.assign(1, 0);
   for (int i = 0; i < m; ++i)
     P->tile_start.push_back(P->tile_start.back() +
@@ -1462,8 +1613,15 @@ apc_status apc_get_info(apc_plan p, int32_t* lanczos_steps, int32_t* rows_per_ti
 apc_status apc_get_launch(apc_plan p, int32_t which, int32_t* rows_per_wg, int32_t* splits,
                           float* tuned_us) {
   if (!p) return fail(APC_EINVAL, "plan is NULL");
+  if (which == 4) {
+    if (!p->fused) return fail(APC_EUNSUPPORTED, "the plan does not use the single-pass k = 1 update");
+    if (rows_per_wg) *rows_per_wg = p->fused_rows;
+    if (splits) *splits = p->fused_g;
+    if (tuned_us) *tuned_us = 0.f;
+    return APC_OK;
+  }
   if (!p->gemm) return fail(APC_EUNSUPPORTED, "launch shapes are reported for the k-RHS path only");
-  if (which < 0 || which > 3) return fail(APC_EINVAL, "which must be 0..3");
+  if (which < 0 || which > 3) return fail(APC_EINVAL, "which must be 0..4");
   const TnChoice& c = which == 0 ? p->tnA : which == 1 ? p->tnB : which == 2 ? p->tnX0 : p->tnR;
   if (rows_per_wg) *rows_per_wg = 64 * c.rt;
   if (splits) *splits = c.nsplit;
@@ -2098,6 +2256,27 @@ apc_status hbm_update(apc_hbm_s* H) {
   const Layout& L = P->L;
   const int32_t nt = P->tile_start[P->m];
   const bool f32 = P->prec == APC_F32;
+  // Single pass (the plan's tiles): every tile's partial of sum_r (C_r x - d_r) C_r,
+  // their sum (the gradient), then the heavy-ball step.
+  const int cpt32 = fused_cpt(L.ldc, 4), cpt64 = fused_cpt(L.ldc, 8);
+  if (P->fused && (f32 ? fused_shape_ok(4, 8, cpt32, 1) : cpt64 > 0)) {
+    double* part = P->at<double>(L.fpart);
+    const int32_t remap = P->xcd_remap == 1 ? 1 : 0;
+    if (f32) {
+      FusedArgs<float, double> a{static_cast<const float*>(H->C), L.ldc, P->n, P->tf(0),
+                                 P->tf(1), P->tf(2), P->ntiles_f, H->x, 0, part, L.ldc, remap,
+                                 H->d};
+      HIP_TRY(launch_fused_f32x64(a, 1, P->stream));
+    } else {
+      FusedArgs<double, double> a{static_cast<const double*>(H->C), L.ldc, P->n, P->tf(0),
+                                  P->tf(1), P->tf(2), P->ntiles_f, H->x, 0, part, L.ldc, remap,
+                                  H->d};
+      HIP_TRY(launch_fused_f64(a, cpt64 >= 16 ? 1 : 2, P->stream));
+    }
+    HIP_TRY(launch_fused_sum(part, L.ldc, P->ntiles_f, L.ldc, 1.0, H->Y, P->stream));
+    HIP_TRY(launch_hbm_step(H->Y, L.ldc, 1, P->n, H->alpha, H->beta, H->x, H->z, P->stream));
+    return APC_OK;
+  }
   if (f32) {
     const float* C = static_cast<const float*>(H->C);
     RowdotArgs<float, double> a{C, L.ldc, P->ta(0), P->ta(1), P->ta(2), nt, 0, H->x, nullptr, 0,

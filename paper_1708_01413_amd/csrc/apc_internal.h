@@ -138,6 +138,73 @@ hipError_t launch_pass_b_f32(const PassBArgs<float>& a, hipStream_t s);
 hipError_t launch_expand_f64(const ExpandArgs<double>& a, hipStream_t s);
 hipError_t launch_expand_f32(const ExpandArgs<float>& a, hipStream_t s);
 
+// One pass over C for both halves of eq. (2a): every workgroup owns a tile of
+// rows of one block and the whole row width.  For each row r it forms
+// w_r = C[r][:] . d_blk (accumulated in TA) and adds w_r C[r][:] to its own
+// partial sum, so each row is read once and used twice:
+//   part[t * ldp + j] = sum_{r in tile t} (C[r][:] . d_blk) C[r][j],  j < ldc
+// (zero for j >= n).
+// d_blk = d + blk * ldd (ldd = 0: one vector for every tile); entries of d at
+// j >= n are not read (taken as 0).  C is N x ldc, zero past column n, ldc a
+// multiple of kLdAlign.  cpt: 16-byte chunks of a row per thread (ldc * sizeof(TQ)
+// <= kThreads * 16 * cpt); g: rows per register group (two groups in flight).
+template <typename TQ, typename TA = TQ>
+struct FusedArgs {
+  const TQ* C;
+  int64_t ldc;
+  int64_t n;
+  const int32_t* tile_row0;
+  const int32_t* tile_nrows;
+  const int32_t* tile_blk;
+  int32_t ntiles;
+  const TA* d;
+  int64_t ldd;
+  TA* part;
+  int64_t ldp;
+  int32_t xcd_remap;          // 1: give each XCD a contiguous range of tiles
+  const TA* wsub = nullptr;   // optional: w_r = C[r][:] . d_blk - wsub[r] (global row r)
+};
+// cpt for a row width: the smallest of 1, 2, 4, 8, 16 that covers it (0 when
+// none does).  A launcher accepts g in 1, 2, 4 when fused_shape_ok: the two
+// register groups, d_blk and the partial sum fit 256 registers per thread
+// (q_bytes = sizeof(TQ), a_bytes = sizeof(TA)).
+int fused_cpt(int64_t ldc, int elem_bytes);
+bool fused_shape_ok(int q_bytes, int a_bytes, int cpt, int g);
+hipError_t launch_fused_f32(const FusedArgs<float, float>& a, int g, hipStream_t s);
+hipError_t launch_fused_f64(const FusedArgs<double, double>& a, int g, hipStream_t s);
+// FP32 factor, FP64 vector and sums (the normal operator of the eigenvalue
+// estimate).
+hipError_t launch_fused_f32x64(const FusedArgs<float, double>& a, int g, hipStream_t s);
+// out[j] = alpha * sum over all ntiles partial rows part[t][j] (FP64), j < n.
+hipError_t launch_fused_sum(const double* part, int64_t ldp, int32_t ntiles, int64_t n,
+                            double alpha, double* out, hipStream_t s);
+
+// The rest of one update after the single-pass kernel, per column j < n:
+//   x_i[j] += gamma (x_bar[j] - x_i[j] - sum_{t in block i} part[t][j])   (eq. 2a)
+//   x_bar[j] <- alpha sum_i x_i[j] + beta x_bar[j]                         (eq. 2b)
+//   d_i[j] = TD(x_bar[j] - x_i[j])                                         (next pass)
+// The partials of block i are tiles tile_first[i] .. tile_first[i+1]-1, summed
+// in FP64 in tile order; the block sum runs in a fixed order.
+template <typename TD>
+struct FusedCombineArgs {
+  const TD* part;
+  int64_t ldp;
+  const int32_t* tile_first;
+  double* x;
+  int64_t ldx;
+  int32_t m;
+  int64_t n;
+  double gamma;
+  double alpha;
+  double beta;
+  double* xbar;
+  TD* d;
+  int64_t ldd;
+  int32_t tpb = 0;            // > 0: every block has exactly tpb tiles (1, 2, 4 or 8)
+};
+hipError_t launch_fused_combine_f32(const FusedCombineArgs<float>& a, hipStream_t s);
+hipError_t launch_fused_combine_f64(const FusedCombineArgs<double>& a, hipStream_t s);
+
 // ---------------------------------------------------------------------------
 // k right-hand sides: streaming contractions on the matrix cores (apc_gemm.hip)
 // ---------------------------------------------------------------------------

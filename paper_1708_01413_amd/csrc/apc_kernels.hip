@@ -394,6 +394,231 @@ __global__ __launch_bounds__(256) void k_combine(const double* x, int64_t ldx, i
           static_cast<TD>(xb[lane] - x[static_cast<int64_t>(i) * ldx + j]);
 }
 
+// ------------------------------------------------------------------ single pass
+
+// Stores of one thread's 16-byte runs (W elements of TA per chunk of C).
+template <typename T, int W>
+__device__ inline void store_run(T* p, const T (&v)[W]) {
+  if constexpr (sizeof(T) == 4 && W == 4) {
+    *reinterpret_cast<f32x4_t*>(p) = f32x4_t{v[0], v[1], v[2], v[3]};
+  } else if constexpr (sizeof(T) == 8 && W % 2 == 0) {
+#pragma unroll
+    for (int h = 0; h < W; h += 2) *reinterpret_cast<f64x2_t*>(p + h) = f64x2_t{v[h], v[h + 1]};
+  } else {
+#pragma unroll
+    for (int e = 0; e < W; ++e) p[e] = v[e];
+  }
+}
+
+// Both halves of eq. (2a) in one pass over C.  One workgroup per row tile of
+// one block, all of the row's width: thread t owns the 16-byte chunks t,
+// t + 256, ... of every row, so the tile's d_blk and the running sum of
+// w_r C[r][:] stay in its registers.  Rows go in groups of G.  While one
+// group's dot products are reduced across the workgroup (a wave sum each, then
+// the four wave values through LDS), the next group's loads are in flight; the
+// LDS slot alternates between groups, so one barrier per group is enough.
+template <typename TQ, typename TA, int CPT, int G>
+__global__ __launch_bounds__(kThreads) void k_fused(FusedArgs<TQ, TA> a) {
+  constexpr int W = V16<TQ>::W;
+  int q = blockIdx.x;
+  if (a.xcd_remap == 1) {
+    const int per = (a.ntiles + kXcds - 1) / kXcds;
+    q = (blockIdx.x % kXcds) * per + blockIdx.x / kXcds;
+  }
+  if (q >= a.ntiles) return;
+  const int row0 = a.tile_row0[q];
+  const int nrows = a.tile_nrows[q];
+  const TA* dblk = a.d + static_cast<int64_t>(a.tile_blk[q]) * a.ldd;
+
+  // A chunk takes part when it starts before column n; C is zero from n to
+  // ldc (a multiple of W), so the chunk's loads stay inside the row.
+  bool ok[CPT];
+  TA dv[CPT][W], acc[CPT][W];
+#pragma unroll
+  for (int c = 0; c < CPT; ++c) {
+    const int64_t j = static_cast<int64_t>(threadIdx.x + c * kThreads) * W;
+    ok[c] = j < a.n;
+#pragma unroll
+    for (int e = 0; e < W; ++e) {
+      dv[c][e] = j + e < a.n ? dblk[j + e] : TA(0);
+      acc[c][e] = TA(0);
+    }
+  }
+
+  const TQ* base = a.C + static_cast<int64_t>(row0) * a.ldc + threadIdx.x * W;
+  auto load = [&](TQ (&b)[G][CPT][W], int r0) {
+#pragma unroll
+    for (int r = 0; r < G; ++r) {
+      const bool row_ok = r0 + r < nrows;
+#pragma unroll
+      for (int c = 0; c < CPT; ++c) {
+        if (row_ok && ok[c]) {
+          V16<TQ>::template load<true>(base + static_cast<int64_t>(r0 + r) * a.ldc + c * kThreads * W,
+                                       b[r][c]);
+        } else {
+#pragma unroll
+          for (int e = 0; e < W; ++e) b[r][c][e] = TQ(0);
+        }
+      }
+    }
+  };
+
+  __shared__ TA red[2][kThreads / 64][G];
+  const int lane = threadIdx.x & 63;
+  const int wv = threadIdx.x >> 6;
+  // Rows past the tile were loaded as zeros, so their w is 0 and they add nothing.
+  auto step = [&](const TQ (&b)[G][CPT][W], int r0, int slot) {
+    TA sum[G];
+#pragma unroll
+    for (int r = 0; r < G; ++r) {
+      sum[r] = TA(0);
+#pragma unroll
+      for (int c = 0; c < CPT; ++c)
+#pragma unroll
+        for (int e = 0; e < W; ++e) sum[r] = fma(static_cast<TA>(b[r][c][e]), dv[c][e], sum[r]);
+    }
+#pragma unroll
+    for (int r = 0; r < G; ++r) {
+      const TA v = wave_sum(sum[r]);
+      if (lane == 0) red[slot][wv][r] = v;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < G; ++r) {
+      TA w = (red[slot][0][r] + red[slot][1][r]) + (red[slot][2][r] + red[slot][3][r]);
+      if (a.wsub && r0 + r < nrows) w -= a.wsub[row0 + r0 + r];
+#pragma unroll
+      for (int c = 0; c < CPT; ++c)
+#pragma unroll
+        for (int e = 0; e < W; ++e) acc[c][e] = fma(w, static_cast<TA>(b[r][c][e]), acc[c][e]);
+    }
+  };
+
+  TQ b0[G][CPT][W], b1[G][CPT][W];
+  load(b0, 0);
+  for (int r0 = 0; r0 < nrows; r0 += 2 * G) {
+    load(b1, r0 + G);
+    step(b0, r0, 0);
+    load(b0, r0 + 2 * G);
+    step(b1, r0 + G, 1);
+  }
+
+  // Every chunk inside the padded row is written (zeros past n), so a partial
+  // row is defined on all of [0, ldc).
+  TA* out = a.part + static_cast<int64_t>(q) * a.ldp + threadIdx.x * W;
+#pragma unroll
+  for (int c = 0; c < CPT; ++c)
+    if (static_cast<int64_t>(threadIdx.x + c * kThreads) * W < a.ldc)
+      store_run<TA, W>(out + c * kThreads * W, acc[c]);
+}
+
+// The x_i update, the average and the next differences after k_fused.  A
+// workgroup owns 32 columns; its 8 lanes per column take every eighth block,
+// U blocks at a time with all their loads issued before any store.  TPB > 0:
+// every block has exactly TPB tiles (tile t of block i is i TPB + t), so a
+// block's partials are loaded together; TPB = 0 reads the tile ranges.  Both
+// sum a block's partials in tile order.
+template <typename TD, int TPB>
+__global__ __launch_bounds__(256) void k_fused_combine(FusedCombineArgs<TD> a) {
+  constexpr int U = 4;
+  __shared__ double part[8][32];
+  __shared__ double xb[32];
+  const int lane = threadIdx.x & 31;
+  const int bl = threadIdx.x >> 5;
+  const int64_t j = static_cast<int64_t>(blockIdx.x) * 32 + lane;
+  const TD* pp = a.part;
+  double* x = a.x;
+  double s = 0.0;
+  if (j < a.n) {
+    const double xo = a.xbar[j];
+    for (int i0 = bl; i0 < a.m; i0 += 8 * U) {
+      double u[U], xi[U];
+#pragma unroll
+      for (int q = 0; q < U; ++q) {
+        const int i = i0 + 8 * q;
+        u[q] = 0.0;
+        xi[q] = 0.0;
+        if (i < a.m) {
+          if constexpr (TPB > 0) {
+            double v[TPB];
+#pragma unroll
+            for (int t = 0; t < TPB; ++t)
+              v[t] = static_cast<double>(pp[static_cast<int64_t>(i * TPB + t) * a.ldp + j]);
+#pragma unroll
+            for (int t = 0; t < TPB; ++t) u[q] += v[t];
+          } else {
+            for (int t = a.tile_first[i]; t < a.tile_first[i + 1]; ++t)
+              u[q] += static_cast<double>(pp[static_cast<int64_t>(t) * a.ldp + j]);
+          }
+          xi[q] = x[static_cast<int64_t>(i) * a.ldx + j];
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < U; ++q) {
+        const int i = i0 + 8 * q;
+        if (i < a.m) {
+          const double xn = xi[q] + a.gamma * ((xo - xi[q]) - u[q]);
+          x[static_cast<int64_t>(i) * a.ldx + j] = xn;
+          s += xn;
+        }
+      }
+    }
+  }
+  part[bl][lane] = s;
+  __syncthreads();
+  if (bl == 0 && j < a.n) {
+    const double tot = ((part[0][lane] + part[1][lane]) + (part[2][lane] + part[3][lane])) +
+                       ((part[4][lane] + part[5][lane]) + (part[6][lane] + part[7][lane]));
+    const double v = a.beta == 0.0 ? a.alpha * tot : a.alpha * tot + a.beta * a.xbar[j];
+    a.xbar[j] = v;
+    xb[lane] = v;
+  }
+  __syncthreads();
+  if (j < a.n) {
+    const double v = xb[lane];
+    for (int i0 = bl; i0 < a.m; i0 += 8 * U) {
+      double xi[U];
+#pragma unroll
+      for (int q = 0; q < U; ++q) {
+        const int i = i0 + 8 * q;
+        xi[q] = i < a.m ? x[static_cast<int64_t>(i) * a.ldx + j] : 0.0;
+      }
+#pragma unroll
+      for (int q = 0; q < U; ++q) {
+        const int i = i0 + 8 * q;
+        if (i < a.m) a.d[static_cast<int64_t>(i) * a.ldd + j] = static_cast<TD>(v - xi[q]);
+      }
+    }
+  }
+}
+
+// out[j] = alpha sum_t part[t][j] over all tiles (FP64, fixed order), j < n:
+// the sum over blocks of the normal operator after k_fused with one shared
+// vector.  32 columns per workgroup, 8 lanes per column, each lane four
+// independent running sums.
+__global__ __launch_bounds__(256) void k_fused_sum(const double* part, int64_t ldp, int32_t ntiles,
+                                                   int64_t n, double alpha, double* out) {
+  __shared__ double red[8][32];
+  const int lane = threadIdx.x & 31;
+  const int bl = threadIdx.x >> 5;
+  const int64_t j = static_cast<int64_t>(blockIdx.x) * 32 + lane;
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  if (j < n) {
+    for (int t0 = bl; t0 < ntiles; t0 += 32) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int t = t0 + 8 * q;
+        if (t < ntiles) acc[q] += part[static_cast<int64_t>(t) * ldp + j];
+      }
+    }
+  }
+  red[bl][lane] = (acc[0] + acc[1]) + (acc[2] + acc[3]);
+  __syncthreads();
+  if (bl == 0 && j < n)
+    out[j] = alpha * (((red[0][lane] + red[1][lane]) + (red[2][lane] + red[3][lane])) +
+                      ((red[4][lane] + red[5][lane]) + (red[6][lane] + red[7][lane])));
+}
+
 // ------------------------------------------------------------------ expand (FP64)
 
 // y_i = beta * y_i + alpha * sum_{r in block i} w_r C[r][:], FP64 accumulation.
@@ -987,6 +1212,101 @@ static hipError_t expand_impl(const ExpandArgs<TQ>& a, hipStream_t s) {
 }
 
 hipError_t launch_expand_f64(const ExpandArgs<double>& a, hipStream_t s) { return expand_impl(a, s); }
+
+int fused_cpt(int64_t ldc, int elem_bytes) {
+  const int64_t chunks = ldc * elem_bytes / 16;
+  for (int c = 1; c <= 16; c *= 2)
+    if (chunks <= static_cast<int64_t>(kThreads) * c) return c;
+  return 0;
+}
+
+template <typename TQ, typename TA, int CPT, int G>
+static hipError_t fused_launch(const FusedArgs<TQ, TA>& a, hipStream_t s) {
+  const unsigned grid = a.xcd_remap == 1
+                            ? static_cast<unsigned>((a.ntiles + kXcds - 1) / kXcds * kXcds)
+                            : static_cast<unsigned>(a.ntiles);
+  if (grid == 0) return hipSuccess;
+  APC_LAUNCH((k_fused<TQ, TA, CPT, G>), dim3(grid), dim3(kThreads), 0, s, a);
+  return hipGetLastError();
+}
+
+// Register estimate of a (cpt, g) shape per thread, in 32-bit registers: two
+// groups of g rows x cpt chunks of 16 bytes, plus d_blk and the partial sum
+// (cpt chunks of 16 / sizeof(TQ) elements of TA each).  Shapes over 256 spill
+// or leave no room for addresses, so launchers refuse them.
+constexpr int fused_regs(int q_bytes, int a_bytes, int cpt, int g) {
+  return 8 * g * cpt + 2 * cpt * (16 / q_bytes) * a_bytes / 4;
+}
+bool fused_shape_ok(int q_bytes, int a_bytes, int cpt, int g) {
+  return cpt >= 1 && (g == 1 || g == 2 || g == 4) && fused_regs(q_bytes, a_bytes, cpt, g) <= 256;
+}
+
+template <typename TQ, typename TA, int CPT>
+static hipError_t fused_g(const FusedArgs<TQ, TA>& a, int g, hipStream_t s) {
+  constexpr int q = sizeof(TQ), e = sizeof(TA);
+  switch (g) {
+    case 1:
+      if constexpr (fused_regs(q, e, CPT, 1) <= 256) return fused_launch<TQ, TA, CPT, 1>(a, s);
+      break;
+    case 2:
+      if constexpr (fused_regs(q, e, CPT, 2) <= 256) return fused_launch<TQ, TA, CPT, 2>(a, s);
+      break;
+    case 4:
+      if constexpr (fused_regs(q, e, CPT, 4) <= 256) return fused_launch<TQ, TA, CPT, 4>(a, s);
+      break;
+    default: break;
+  }
+  return hipErrorInvalidValue;
+}
+
+template <typename TQ, typename TA>
+static hipError_t fused_impl(const FusedArgs<TQ, TA>& a, int g, hipStream_t s) {
+  switch (fused_cpt(a.ldc, sizeof(TQ))) {
+    case 1: return fused_g<TQ, TA, 1>(a, g, s);
+    case 2: return fused_g<TQ, TA, 2>(a, g, s);
+    case 4: return fused_g<TQ, TA, 4>(a, g, s);
+    case 8: return fused_g<TQ, TA, 8>(a, g, s);
+    case 16: return fused_g<TQ, TA, 16>(a, g, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_fused_f32(const FusedArgs<float, float>& a, int g, hipStream_t s) {
+  return fused_impl(a, g, s);
+}
+hipError_t launch_fused_f64(const FusedArgs<double, double>& a, int g, hipStream_t s) {
+  return fused_impl(a, g, s);
+}
+hipError_t launch_fused_f32x64(const FusedArgs<float, double>& a, int g, hipStream_t s) {
+  return fused_impl(a, g, s);
+}
+
+hipError_t launch_fused_sum(const double* part, int64_t ldp, int32_t ntiles, int64_t n,
+                            double alpha, double* out, hipStream_t s) {
+  APC_LAUNCH(k_fused_sum, dim3(grid_for(n, 32)), dim3(256), 0, s, part, ldp, ntiles, n, alpha,
+             out);
+  return hipGetLastError();
+}
+
+template <typename TD>
+static hipError_t fused_combine_impl(const FusedCombineArgs<TD>& a, hipStream_t s) {
+  const dim3 grid(grid_for(a.n, 32));
+  switch (a.tpb) {
+    case 1: APC_LAUNCH((k_fused_combine<TD, 1>), grid, dim3(256), 0, s, a); break;
+    case 2: APC_LAUNCH((k_fused_combine<TD, 2>), grid, dim3(256), 0, s, a); break;
+    case 4: APC_LAUNCH((k_fused_combine<TD, 4>), grid, dim3(256), 0, s, a); break;
+    case 8: APC_LAUNCH((k_fused_combine<TD, 8>), grid, dim3(256), 0, s, a); break;
+    default: APC_LAUNCH((k_fused_combine<TD, 0>), grid, dim3(256), 0, s, a); break;
+  }
+  return hipGetLastError();
+}
+hipError_t launch_fused_combine_f32(const FusedCombineArgs<float>& a, hipStream_t s) {
+  return fused_combine_impl(a, s);
+}
+hipError_t launch_fused_combine_f64(const FusedCombineArgs<double>& a, hipStream_t s) {
+  return fused_combine_impl(a, s);
+}
+
 hipError_t launch_expand_f32(const ExpandArgs<float>& a, hipStream_t s) { return expand_impl(a, s); }
 
 hipError_t launch_linv_apply(const int64_t* off, const int64_t* goff, int32_t m, int64_t pmax,

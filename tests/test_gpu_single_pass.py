@@ -1,0 +1,168 @@
+"""GPU parity of the single-pass k = 1 update (one read of the factor per update):
+every launch shape against the FP64 oracle and against the two-pass update, on
+ragged blocks (tiles and register groups with short tails), row widths that
+leave part of a thread's chunks empty, and the widest rows the kernel holds.
+
+Bars: FP64 1e-10 and FP32 1e-5, as ||x_bar_gpu(t) - x_bar_oracle(t)|| / ||x*||."""
+
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import apc_oracle as O
+from paper_1708_01413_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"f64": 1e-10, "f32": 1e-5}
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _apc():
+    from paper_1708_01413_amd import apc
+    return apc
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def oracle_traj(S, T, gamma, eta):
+    Qt, R = O.factor(S.A, S.off)
+    x = O.init_local(Qt, R, S.B, S.off)
+    xbar = O.initial_average(x)
+    traj = [xbar[:, 0].copy()]
+    for _ in range(T):
+        x, xbar = O.apc_step(Qt, x, xbar, gamma, eta)
+        traj.append(xbar[:, 0].copy())
+    return np.stack(traj)
+
+
+def gpu_traj(plan, T):
+    torch = _torch()
+    snaps = [plan.xbar()]
+    for _ in range(T):
+        plan.iterate(1)
+        snaps.append(plan.xbar())
+    torch.cuda.synchronize()
+    return torch.stack(snaps).cpu().numpy()
+
+
+def dev(a, b, xstar):
+    return float(np.max(np.linalg.norm(a - b, axis=-1)) / np.linalg.norm(xstar))
+
+
+def make(N, n, m, seed, lo, hi, shift=0.0):
+    sizes = synth.renormalised_sizes(np.random.default_rng(seed), m, N, lo, hi)
+    return synth.gaussian_system(N, n, m, seed=seed, shift=shift, sizes=sizes,
+                                 scale=1.0 / math.sqrt(n))
+
+
+SHAPES = [("16", "1"), ("16", "4"), ("32", "2"), ("64", "4"), ("128", "1"), ("64", "1")]
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("rows,g", SHAPES)
+def test_single_pass_shapes_match_oracle(prec, rows, g, monkeypatch):
+    """N = n = 1000 (ldc 1024: the last chunk of a row is partly past n), 13 blocks of
+    40..120 rows, so every tile height and register group ends in a short tail."""
+    apc = _apc()
+    torch = _torch()
+    S = make(1000, 1000, 13, 2, 40, 120, shift=2.0)
+    g_opt, e_opt, _ = O.optimal_params(*O.spectrum(S.A, S.off))
+    T = 50
+    ref = oracle_traj(S, T, g_opt, e_opt)
+    A = torch.from_numpy(S.A).cuda()
+    b = torch.from_numpy(S.B).cuda()
+    monkeypatch.setenv("APC_FUSED_ROWS", rows)
+    monkeypatch.setenv("APC_FUSED_G", g)
+    plan = apc.Plan(A, b, S.off, prec, gamma=g_opt, eta=e_opt)
+    shape = plan.single_pass_shape()
+    say(f"case: single pass {prec} sizes={np.diff(S.off).tolist()} shape={shape}")
+    assert shape == {"rows_per_wg": int(rows), "rows_per_group": int(g)}
+    d = dev(gpu_traj(plan, T), ref, S.xstar)
+    say(f"max dev {d:.3e}")
+    assert d <= TOL[prec]
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_single_pass_matches_two_pass(prec, monkeypatch):
+    """The same plan arithmetic with one and with two reads of the factor per update."""
+    apc = _apc()
+    torch = _torch()
+    S = make(2048, 1536, 16, 5, 64, 192)
+    A = torch.from_numpy(S.A).cuda()
+    b = torch.from_numpy(S.B).cuda()
+    one = apc.Plan(A, b, S.off, prec)
+    assert one.single_pass_shape() is not None
+    monkeypatch.setenv("APC_FUSED", "0")
+    two = apc.Plan(A, b, S.off, prec, gamma=one.params()["gamma"], eta=one.params()["eta"])
+    assert two.single_pass_shape() is None
+    one.iterate(40)
+    two.iterate(40)
+    xs = np.linalg.norm(S.xstar)
+    d = float(torch.linalg.norm(one.xbar() - two.xbar())) / xs
+    err = float(torch.linalg.norm(one.xbar() - torch.from_numpy(S.xstar).cuda())) / xs
+    say(f"case: one vs two passes {prec}: dev {d:.3e}, error after 40 updates {err:.3e}")
+    assert d <= TOL[prec]
+
+
+def test_single_pass_widest_fp32_rows():
+    """n = 9000 in FP32: 16 chunks per thread (the widest the kernel holds), one row
+    per register group; gamma = eta = 1 so no spectrum is needed."""
+    apc = _apc()
+    torch = _torch()
+    N, n, m = 9000, 9000, 36
+    S = synth.gaussian_system(N, n, m, seed=11, shift=2.0, scale=1.0 / math.sqrt(n))
+    T = 6
+    ref = oracle_traj(S, T, 1.0, 1.0)
+    A = torch.from_numpy(S.A).cuda()
+    b = torch.from_numpy(S.B).cuda()
+    plan = apc.Plan(A, b, S.off, "f32", gamma=1.0, eta=1.0)
+    shape = plan.single_pass_shape()
+    say(f"case: widest FP32 rows n={n} shape={shape}")
+    assert shape is not None and shape["rows_per_group"] == 1
+    d = dev(gpu_traj(plan, T), ref, S.xstar)
+    say(f"max dev {d:.3e}")
+    assert d <= TOL["f32"]
+
+
+def test_single_pass_fp64_is_deterministic():
+    apc = _apc()
+    torch = _torch()
+    S = make(1024, 768, 12, 10, 40, 140)
+    A = torch.from_numpy(S.A).cuda()
+    b = torch.from_numpy(S.B).cuda()
+    runs = []
+    for _ in range(2):
+        plan = apc.Plan(A, b, S.off, "f64", gamma=1.05, eta=3.0)
+        plan.iterate(30)
+        runs.append(plan.xbar().cpu().numpy())
+    np.testing.assert_array_equal(runs[0], runs[1])
+
+
+def test_wide_fp64_rows_take_two_passes():
+    """FP64 rows wider than 8192 do not fit the single-pass registers: the plan falls
+    back to two passes and still matches the oracle."""
+    apc = _apc()
+    torch = _torch()
+    N, n, m = 8300, 8300, 10
+    S = synth.gaussian_system(N, n, m, seed=12, shift=2.0, scale=1.0 / math.sqrt(n))
+    T = 4
+    ref = oracle_traj(S, T, 1.0, 1.0)
+    A = torch.from_numpy(S.A).cuda()
+    b = torch.from_numpy(S.B).cuda()
+    plan = apc.Plan(A, b, S.off, "f64", gamma=1.0, eta=1.0)
+    assert plan.single_pass_shape() is None
+    d = dev(gpu_traj(plan, T), ref, S.xstar)
+    say(f"case: wide FP64 rows n={n}, two passes: max dev {d:.3e}")
+    assert d <= TOL["f64"]
