@@ -589,6 +589,7 @@ def main():
         prm = plan.params()
         plan_info = plan.info()
         single = plan.single_pass_shape()
+        qr = plan.setup_info()
         plan.close()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -704,6 +705,8 @@ def main():
             "setup_ms": round(float(np.mean(setup_ms)), 3),
             "iterate_ms": round(it_ms, 3),
             "total_ms": round(float(np.mean(setup_ms)) + it_ms, 3),
+            "qr_passes": qr["qr_passes"],
+            "qr_defect_after_first_pass": qr["qr_defect"],
         },
         "params": prm,
         "relres_at_end": relres,

@@ -199,6 +199,16 @@ apc_status apc_tridiag_extremes(const double* alpha, const double* beta, int32_t
 apc_status apc_get_info(apc_plan p, int32_t* lanczos_steps, int32_t* rows_per_tile,
                         int32_t* column_splits, int32_t* block_groups, int32_t* refinements);
 
+/* Host copies of what setup did for the thin QR of Sec. 3.1 (CholeskyQR):
+ * *qr_passes = 2, or 1 when a k = 1 APC_F32 plan skipped the second pass
+ * because the rows' measured departure from orthonormality after the first,
+ * max_i ||C_i C_i^T - I|| estimated with a random vector, was at most
+ * 1e-10 / sqrt(max p_i), far below the FP32 rounding the factor then takes;
+ * *qr_defect = that estimate (NaN when it was not measured: FP64 plans, the
+ * k-RHS forms, rows too wide for the single-pass kernel in FP64, or
+ * APC_QR_PASSES=2 in the environment).  Any pointer may be NULL. */
+apc_status apc_get_setup(apc_plan p, int32_t* qr_passes, double* qr_defect);
+
 /* Launch shape the k-RHS path chose for one of its contractions (which: 0 =
  * pass A, 1 = pass B, 2 = the FP64 start x_bar(0) = (1/m) C^T c, 3 = the FP64
  * residual): rows of the streamed operand per workgroup, split-K factor, and

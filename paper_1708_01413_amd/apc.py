@@ -36,7 +36,8 @@ EXPORTED = (
     "apc_workspace_bytes", "apc_setup", "apc_iterate", "apc_iterate_timed", "apc_residual",
     "apc_solve", "apc_get_xbar", "apc_get_local", "apc_project", "apc_get_params",
     "apc_iterations", "apc_destroy", "apc_last_error", "apc_optimal_params",
-    "apc_tridiag_extremes", "apc_get_info", "apc_get_launch", "apc_set_anchor", "apc_set_params",
+    "apc_tridiag_extremes", "apc_get_info", "apc_get_setup", "apc_get_launch", "apc_set_anchor",
+    "apc_set_params",
     "apc_restart", "apc_backward_workspace_bytes", "apc_backward",
     "apc_batch_workspace_bytes", "apc_batch_create", "apc_batch_iterate",
     "apc_batch_iterate_graph", "apc_batch_residuals", "apc_batch_activate", "apc_batch_solve",
@@ -96,6 +97,7 @@ def _load() -> ctypes.CDLL:
         "apc_get_params": (i32, [vp, Pd, Pd, Pd, Pd, Pd]),
         "apc_iterations": (i64, [vp]),
         "apc_get_info": (i32, [vp, Pi, Pi, Pi, Pi, Pi]),
+        "apc_get_setup": (i32, [vp, Pi, Pd]),
         "apc_get_launch": (i32, [vp, i32, Pi, Pi, Pf]),
         "apc_set_anchor": (i32, [vp, i32]),
         "apc_set_params": (i32, [vp, f64, f64]),
@@ -206,6 +208,12 @@ def apc_get_info(plan) -> dict:
     _check(lib.apc_get_info(plan, *[ctypes.byref(v) for v in vals]))
     return dict(zip(("lanczos_steps", "rows_per_tile", "column_splits", "block_groups",
                      "refinements"), (v.value for v in vals)))
+
+
+def apc_get_setup(plan) -> dict:
+    passes, defect = ctypes.c_int32(), ctypes.c_double()
+    _check(lib.apc_get_setup(plan, ctypes.byref(passes), ctypes.byref(defect)))
+    return {"qr_passes": passes.value, "qr_defect": defect.value}
 
 
 def apc_get_launch(plan, which: int) -> dict:
@@ -416,6 +424,11 @@ class Plan:
         """Launch shapes of the k-RHS contractions (pass A, pass B, start, residual)."""
         return {name: apc_get_launch(self.handle, w)
                 for w, name in enumerate(("pass_a", "pass_b", "start", "residual"))}
+
+    def setup_info(self) -> dict:
+        """CholeskyQR passes setup took and the measured orthogonality defect after the
+        first (NaN when not measured)."""
+        return apc_get_setup(self.handle)
 
     def single_pass_shape(self):
         """Rows per workgroup and rows per register group of the single-pass k = 1

@@ -399,6 +399,9 @@ struct apc_plan_s {
   bool fused = false;                  // k = 1: both halves of eq. (2a) in one pass over C
   int32_t fused_rows = 0, fused_g = 0, ntiles_f = 0;
   int32_t fused_tpb = 0;               // > 0: every block has this many single-pass tiles
+  int32_t qr_passes = 2;               // CholeskyQR passes setup took (1: see setup_impl)
+  double qr_defect = NAN;              // estimated ||Q_i^T Q_i - I|| after the first pass
+  int32_t op_g = 1;                    // rows per register group of the FP32 x FP64 operator
   int64_t since_start = 0;             // k-RHS updates since the last start
   int refinements = 0;
   std::vector<int32_t> tile_start;     // first pass-A tile of every block (m+1)
@@ -509,6 +512,47 @@ apc_status fused_combine(apc_plan_s* P, double alpha, double beta) {
                                P->fused_tpb};
     HIP_TRY(launch_fused_combine_f64(a, P->stream));
   }
+  return APC_OK;
+}
+
+// Departure from orthonormality of every block's rows of the FP64 factor C,
+// max_i ||C_i C_i^T - I||, estimated with one random vector z: with
+// C_i C_i^T = I + E_i, u_i = C_i^T C_i z and v_i = C_i^T C_i u_i differ by
+// C_i^T E_i C_i z, so ||v_i - u_i|| / ||u_i|| estimates ||E_i|| (within a factor
+// up to sqrt(p_i) when E_i is concentrated in one direction).  Two single passes
+// over C; synchronises the stream.  Uses the x, Y, vtmp and w slices as scratch.
+apc_status orthogonality_defect(apc_plan_s* P, const double* C, double* defect) {
+  const Layout& L = P->L;
+  hipStream_t st = P->stream;
+  std::vector<double> z(L.ldc, 0.0);
+  for (int64_t j = 0; j < P->n; ++j) {
+    const uint64_t r = splitmix64(0x0a7ull * 1000003ull + static_cast<uint64_t>(j));
+    z[j] = (static_cast<double>(r >> 11) * (1.0 / 9007199254740992.0)) - 0.5;
+  }
+  double* zd = P->at<double>(L.vtmp);
+  double* U = P->at<double>(L.Y);
+  double* V = P->x();
+  double* part = P->at<double>(L.fpart);
+  double* out = P->at<double>(L.w);
+  HIP_TRY(hipMemcpyAsync(zd, z.data(), L.ldc * sizeof(double), hipMemcpyHostToDevice, st));
+  const int g = fused_cpt(L.ldc, 8) >= 16 ? 1 : 2;
+  const int32_t remap = P->xcd_remap == 1 ? 1 : 0;
+  for (int app = 0; app < 2; ++app) {
+    FusedArgs<double, double> a{C, L.ldc, P->n, P->tf(0), P->tf(1), P->tf(2), P->ntiles_f,
+                                app == 0 ? zd : U, app == 0 ? 0 : L.ldc, part, L.ldc, remap};
+    HIP_TRY(launch_fused_f64(a, g, st));
+    HIP_TRY(launch_block_sum(part, L.ldc, P->tf(3), P->m, L.ldc, app == 0 ? U : V, L.ldc, st));
+  }
+  HIP_TRY(launch_defect(U, V, L.ldc, P->m, P->n, out, st));
+  std::vector<double> h(2 * static_cast<size_t>(P->m));
+  HIP_TRY(hipMemcpyAsync(h.data(), out, h.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  double worst = 0.0;
+  for (int i = 0; i < P->m; ++i) {
+    const double e = h[2 * i + 1] > 0.0 ? std::sqrt(h[2 * i] / h[2 * i + 1]) : INFINITY;
+    worst = std::isnan(e) ? INFINITY : std::max(worst, e);
+  }
+  *defect = worst;
   return APC_OK;
 }
 
@@ -852,13 +896,13 @@ apc_status normal_matvec(apc_plan_s* P, const NormalOp& op, const double* v, dou
   // One pass over C (the plan's single-pass tiles, v shared by every tile),
   // then the FP64 sum of the tiles' partial rows.
   const int cpt32 = fused_cpt(L.ldc, 4), cpt64 = fused_cpt(L.ldc, 8);
-  if (P->fused && (op.f32 ? fused_shape_ok(4, 8, cpt32, 1) : cpt64 > 0)) {
+  if (P->fused && (op.f32 ? fused_shape_ok(4, 8, cpt32, P->op_g) : cpt64 > 0)) {
     double* part = P->at<double>(L.fpart);
     const int32_t remap = P->xcd_remap == 1 ? 1 : 0;
     if (op.f32) {
       FusedArgs<float, double> a{static_cast<const float*>(op.C), L.ldc, P->n, P->tf(0),
                                  P->tf(1), P->tf(2), P->ntiles_f, v, 0, part, L.ldc, remap};
-      HIP_TRY(launch_fused_f32x64(a, 1, P->stream));
+      HIP_TRY(launch_fused_f32x64(a, P->op_g, P->stream));
     } else {
       FusedArgs<double, double> a{static_cast<const double*>(op.C), L.ldc, P->n, P->tf(0),
                                   P->tf(1), P->tf(2), P->ntiles_f, v, 0, part, L.ldc, remap};
@@ -1112,6 +1156,15 @@ apc_status setup_impl(apc_plan_s* P, const Tiles& T) {
   // (APC_SETUP_MFMA=0 selects the vector kernels).
   bool mfma = true;
   if (const char* e = std::getenv("APC_SETUP_MFMA")) mfma = std::atoi(e) != 0;
+  // A k = 1 FP32 plan rounds the factor to FP32 (relative 6e-8 per entry), so a
+  // second CholeskyQR pass, which takes the rows' departure from orthonormality
+  // from the first pass's ~kappa(A_i)^2 eps down to ~eps, changes nothing the
+  // iteration sees when that departure is already far below FP32 rounding.  The
+  // second pass (about a quarter of setup at 16384 x 8192) is skipped when the
+  // measured departure, times sqrt(p_max) for the estimate's worst case, is at
+  // most 1e-10; FP64 plans, the k-RHS forms and APC_QR_PASSES=2 always take two.
+  bool may_skip = !P->gemm && P->prec == APC_F32 && P->fused && fused_cpt(ldc, 8) > 0;
+  if (const char* e = std::getenv("APC_QR_PASSES")) may_skip = may_skip && std::atoi(e) != 2;
   for (int pass = 0; pass < 2; ++pass) {
     double* src = pass == 0 ? Ca : Cb;
     double* dst = pass == 0 ? Cb : Ca;
@@ -1126,7 +1179,7 @@ apc_status setup_impl(apc_plan_s* P, const Tiles& T) {
     // Both inverse factors are kept: refinement and apc_restart form
     // c = L2^{-1} L1^{-1} r, the adjoint applies L1^{-T} L2^{-T}.
     double* Li = pass == 1 ? P->at<double>(L.Linv2) : P->at<double>(L.Linv);
-    HIP_TRY(launch_chol_inv(P->doff(), P->at<int64_t>(L.goff), m, P->at<double>(L.G), Li,
+    HIP_TRY(launch_chol_inv(P->doff(), P->at<int64_t>(L.goff), m, P->pmax, P->at<double>(L.G), Li,
                             P->at<int>(L.flags), rank_tol, st));
     HIP_TRY(launch_linv_apply(P->doff(), P->at<int64_t>(L.goff), m, P->pmax, Li, cs, N, cd, N,
                               P->kp, 0, 1.0, st));
@@ -1135,6 +1188,19 @@ apc_status setup_impl(apc_plan_s* P, const Tiles& T) {
     else
       HIP_TRY(launch_trmm(src, dst, ldc, P->doff(), P->at<int32_t>(L.tiles_t), L.ntiles_t,
                           P->at<int64_t>(L.goff), Li, st));
+    if (pass == 0 && may_skip) {
+      ST_TRY(orthogonality_defect(P, dst, &P->qr_defect));
+      if (P->qr_defect * std::sqrt(static_cast<double>(pmax)) <= 1e-10) {
+        // The factor and c stay where the first pass left them: the plan's
+        // layout names those slices from here on.
+        P->qr_passes = 1;
+        std::swap(P->L.C64a, P->L.C64b);
+        std::swap(P->L.ca, P->L.cb);
+        std::swap(Ca, Cb);
+        std::swap(ca, cb);
+        break;
+      }
+    }
   }
   int flags[4] = {0, 0, 0, 0};
   HIP_TRY(hipMemcpyAsync(flags, P->at<int>(L.flags), sizeof flags, hipMemcpyDeviceToHost, st));
@@ -1305,6 +1371,10 @@ apc_status apc_setup(apc_plan* out, const double* A, int64_t lda, const double* 
   P->fused = fused;
   P->fused_rows = fused_rows;
   P->fused_g = fused_g;
+  if (const char* e = std::getenv("APC_FUSED_OP_G")) {
+    const int g = std::atoi(e);
+    if (g == 1 || g == 2 || g == 4) P->op_g = g;
+  }
   P->ntiles_f = static_cast<int32_t>(T.f_row0.size());
   if (fused) {
     const int32_t t0 = T.f_first[1];
@@ -1610,6 +1680,13 @@ apc_status apc_get_info(apc_plan p, int32_t* lanczos_steps, int32_t* rows_per_ti
   return APC_OK;
 }
 
+apc_status apc_get_setup(apc_plan p, int32_t* qr_passes, double* qr_defect) {
+  if (!p) return fail(APC_EINVAL, "plan is NULL");
+  if (qr_passes) *qr_passes = p->qr_passes;
+  if (qr_defect) *qr_defect = p->qr_defect;
+  return APC_OK;
+}
+
 apc_status apc_get_launch(apc_plan p, int32_t which, int32_t* rows_per_wg, int32_t* splits,
                           float* tuned_us) {
   if (!p) return fail(APC_EINVAL, "plan is NULL");
@@ -1651,8 +1728,8 @@ apc_status apc_set_params(apc_plan p, double gamma, double eta) {
 
 namespace {
 
-// New right-hand sides (or the stored ones): c = L2^{-1} L1^{-1} b per block,
-// then the start of Alg. 1 again.
+// New right-hand sides (or the stored ones): c = L2^{-1} L1^{-1} b per block
+// (L1^{-1} b after a one-pass setup), then the start of Alg. 1 again.
 apc_status restart_impl(apc_plan_s* P, const double* B, int64_t ldb) {
   const Layout& L = P->L;
   hipStream_t st = P->stream;
@@ -1665,9 +1742,11 @@ apc_status restart_impl(apc_plan_s* P, const double* B, int64_t ldb) {
     HIP_TRY(launch_tn_pack(kTnF64, B, ldb, P->N, P->k, 1, cb, P->N, P->kp, st));
     HIP_TRY(launch_linv_apply(P->doff(), P->at<int64_t>(L.goff), P->m, P->pmax,
                               P->at<double>(L.Linv), cb, P->N, ca, P->N, P->kp, 0, 1.0, st));
-    HIP_TRY(launch_linv_apply(P->doff(), P->at<int64_t>(L.goff), P->m, P->pmax,
-                              P->at<double>(L.Linv2), ca, P->N, cb, P->N, P->kp, 0, 1.0, st));
-    HIP_TRY(launch_copy_strided(cb, 1, ca, 1, static_cast<int64_t>(P->kp) * P->N, 1, st));
+    if (P->qr_passes == 2) {
+      HIP_TRY(launch_linv_apply(P->doff(), P->at<int64_t>(L.goff), P->m, P->pmax,
+                                P->at<double>(L.Linv2), ca, P->N, cb, P->N, P->kp, 0, 1.0, st));
+      HIP_TRY(launch_copy_strided(cb, 1, ca, 1, static_cast<int64_t>(P->kp) * P->N, 1, st));
+    }
     ST_TRY(residual_norm2(P, nullptr, P->at<double>(L.scal) + 1));
     double b2 = 0;
     HIP_TRY(hipMemcpyAsync(&b2, P->at<double>(L.scal) + 1, sizeof b2, hipMemcpyDeviceToHost, st));
@@ -2259,14 +2338,14 @@ apc_status hbm_update(apc_hbm_s* H) {
   // Single pass (the plan's tiles): every tile's partial of sum_r (C_r x - d_r) C_r,
   // their sum (the gradient), then the heavy-ball step.
   const int cpt32 = fused_cpt(L.ldc, 4), cpt64 = fused_cpt(L.ldc, 8);
-  if (P->fused && (f32 ? fused_shape_ok(4, 8, cpt32, 1) : cpt64 > 0)) {
+  if (P->fused && (f32 ? fused_shape_ok(4, 8, cpt32, P->op_g) : cpt64 > 0)) {
     double* part = P->at<double>(L.fpart);
     const int32_t remap = P->xcd_remap == 1 ? 1 : 0;
     if (f32) {
       FusedArgs<float, double> a{static_cast<const float*>(H->C), L.ldc, P->n, P->tf(0),
                                  P->tf(1), P->tf(2), P->ntiles_f, H->x, 0, part, L.ldc, remap,
                                  H->d};
-      HIP_TRY(launch_fused_f32x64(a, 1, P->stream));
+      HIP_TRY(launch_fused_f32x64(a, P->op_g, P->stream));
     } else {
       FusedArgs<double, double> a{static_cast<const double*>(H->C), L.ldc, P->n, P->tf(0),
                                   P->tf(1), P->tf(2), P->ntiles_f, H->x, 0, part, L.ldc, remap,

@@ -175,6 +175,14 @@ hipError_t launch_fused_f64(const FusedArgs<double, double>& a, int g, hipStream
 // FP32 factor, FP64 vector and sums (the normal operator of the eigenvalue
 // estimate).
 hipError_t launch_fused_f32x64(const FusedArgs<float, double>& a, int g, hipStream_t s);
+// out[i * ldo + j] = sum of block i's partial rows (tile_first[i] .. tile_first[i+1]-1,
+// in order), j < ncols, every block i < m (FP64).
+hipError_t launch_block_sum(const double* part, int64_t ldp, const int32_t* tile_first, int32_t m,
+                            int64_t ncols, double* out, int64_t ldo, hipStream_t s);
+// out[2i] = ||V_i - U_i||^2 and out[2i+1] = ||U_i||^2 over j < n, rows i < m of
+// stride ld (FP64).
+hipError_t launch_defect(const double* U, const double* V, int64_t ld, int32_t m, int64_t n,
+                         double* out, hipStream_t s);
 // out[j] = alpha * sum over all ntiles partial rows part[t][j] (FP64), j < n.
 hipError_t launch_fused_sum(const double* part, int64_t ldp, int32_t ntiles, int64_t n,
                             double alpha, double* out, hipStream_t s);
@@ -388,8 +396,8 @@ hipError_t launch_gram(const double* C, int64_t ldc, const int64_t* off, const i
 // Per block: Cholesky G_i = L L^T in place (lower triangle), Linv_i = L^{-1}
 // (zeros above the diagonal); flags[0] <- 1 + (first block whose pivot fails
 // the rank test).
-hipError_t launch_chol_inv(const int64_t* off, const int64_t* goff, int32_t m, double* G,
-                           double* Linv, int* flags, double rank_tol, hipStream_t s);
+hipError_t launch_chol_inv(const int64_t* off, const int64_t* goff, int32_t m, int64_t pmax,
+                           double* G, double* Linv, int* flags, double rank_tol, hipStream_t s);
 // Out_i = Linv_i In_i for every block (tiles: (blk, ta, tc)).
 // The same two products on the FP64 matrix cores (ldc a multiple of 32).
 hipError_t launch_gram_mfma(const double* C, int64_t ldc, const int64_t* off,

@@ -619,6 +619,45 @@ __global__ __launch_bounds__(256) void k_fused_sum(const double* part, int64_t l
                       ((red[4][lane] + red[5][lane]) + (red[6][lane] + red[7][lane])));
 }
 
+// out[i * ldo + j] = sum over block i's partial rows (tiles tile_first[i] ..
+// tile_first[i + 1] - 1, in order) of part[t][j], j < ncols.  Grid: (column
+// chunks of 256, blocks).
+__global__ __launch_bounds__(256) void k_block_sum(const double* part, int64_t ldp,
+                                                   const int32_t* tile_first, int64_t ncols,
+                                                   double* out, int64_t ldo) {
+  const int i = blockIdx.y;
+  const int64_t j = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+  if (j >= ncols) return;
+  double s = 0.0;
+  for (int t = tile_first[i]; t < tile_first[i + 1]; ++t) s += part[static_cast<int64_t>(t) * ldp + j];
+  out[static_cast<int64_t>(i) * ldo + j] = s;
+}
+
+// Per block i: out[2i] = ||V_i - U_i||^2, out[2i + 1] = ||U_i||^2 over j < n.
+__global__ __launch_bounds__(256) void k_defect(const double* U, const double* V, int64_t ld,
+                                                int64_t n, double* out) {
+  __shared__ double ra[4], rb[4];
+  const int i = blockIdx.x;
+  double a = 0.0, b = 0.0;
+  for (int64_t j = threadIdx.x; j < n; j += 256) {
+    const double u = U[static_cast<int64_t>(i) * ld + j];
+    const double d = V[static_cast<int64_t>(i) * ld + j] - u;
+    a += d * d;
+    b += u * u;
+  }
+  a = wave_sum(a);
+  b = wave_sum(b);
+  if ((threadIdx.x & 63) == 0) {
+    ra[threadIdx.x >> 6] = a;
+    rb[threadIdx.x >> 6] = b;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    out[2 * i] = (ra[0] + ra[1]) + (ra[2] + ra[3]);
+    out[2 * i + 1] = (rb[0] + rb[1]) + (rb[2] + rb[3]);
+  }
+}
+
 // ------------------------------------------------------------------ expand (FP64)
 
 // y_i = beta * y_i + alpha * sum_{r in block i} w_r C[r][:], FP64 accumulation.
@@ -732,14 +771,14 @@ __global__ __launch_bounds__(256) void k_gram(const double* C, int64_t ldc, cons
   }
 }
 
-// Blocked Cholesky G_i = L L^T and Linv_i = L^{-1}, one workgroup per block.
-// Panels of 32 columns: wave 0 factors and inverts the 32 x 32 diagonal block
-// in registers (lane i holds row i; broadcasts by shuffles), all threads then
-// solve the panel below it (rows times L_kk^{-T}) and update the trailing
-// lower triangle from an LDS copy of the panel.  Then Linv's block rows below
-// the diagonal: Linv[I, J] = -L_II^{-1} sum_{K=J}^{I-1} L[I, K] Linv[K, J].
+// Blocked Cholesky G_i = L L^T and the diagonal blocks of Linv_i = L^{-1}, one
+// workgroup per block.  Panels of 32 columns: wave 0 factors and inverts the
+// 32 x 32 diagonal block in registers (lane i holds row i; broadcasts by
+// shuffles), all threads then solve the panel below it (rows times L_kk^{-T})
+// and update the trailing lower triangle from an LDS copy of the panel.
 // Linv's strict upper triangle is written as zeros (the tiled products read
-// whole tiles).  flags[0] <- 1 + (first block whose pivot fails the rank test).
+// whole tiles); its blocks below the diagonal are k_tri_inv's.  flags[0] <-
+// 1 + (first block whose pivot fails the rank test).
 constexpr int kNB = 32;
 constexpr int kPanelRows = 384;  // panels of up to this many rows are kept in LDS
 
@@ -870,58 +909,73 @@ __global__ __launch_bounds__(512) void k_chol_inv(const int64_t* off, const int6
     __syncthreads();
   }
 
-  // Off-diagonal block rows of Linv, top to bottom, in 32 x 32 blocks through
-  // LDS: for block row I and block column J < I,
-  //   Linv[I][J] = -Linv_II sum_{K=J}^{I-1} L[I][K] Linv[K][J].
-  // Thread (i, c-pair): i = tid / 16, columns 2 (tid % 16) and 2 (tid % 16) + 1.
+  if (tid == 0 && bad) atomicCAS(flags, 0, blk + 1);
+}
+
+// Off-diagonal blocks of L^{-1} after k_chol_inv (which leaves L in the lower
+// triangle of G and the inverses of L's 32 x 32 diagonal blocks in Linv).  One
+// 512-thread workgroup per (block column J, block): block column J of L^{-1}
+// depends on no other column, so the columns of all blocks run in parallel.
+// Going down the column, for block row I > J,
+//   Linv[I][J] = -Linv_II sum_{K=J}^{I-1} L[I][K] Linv[K][J],
+// each term a 32 x 32 product through LDS; the Linv[K][J] it reads were written
+// by this workgroup earlier in the column (or are the diagonal block, K = J).
+// Thread (i, column pair): i = tid / 16, columns 2 (tid % 16) and 2 (tid % 16) + 1.
+__global__ __launch_bounds__(512) void k_tri_inv(const int64_t* off, const int64_t* goff,
+                                                 const double* G, double* Linv) {
+  const int blk = blockIdx.y;
+  const int p = static_cast<int>(off[blk + 1] - off[blk]);
+  const int J0 = static_cast<int>(blockIdx.x) * kNB;
+  if (J0 + kNB >= p) return;  // the last block column has no block below it
+  const double* Gb = G + goff[blk];
+  double* Lb = Linv + goff[blk];
+  const int tid = threadIdx.x;
   const int ti = tid >> 4, tc2 = (tid & 15) * 2;
-  for (int I0 = kNB; I0 < p; I0 += kNB) {
+  __shared__ double dl[kNB][kNB + 1];
+  __shared__ double di[kNB][kNB + 1];
+  __shared__ double pan[kNB][kNB + 1];
+  for (int I0 = J0 + kNB; I0 < p; I0 += kNB) {
     const int nbI = min(kNB, p - I0);
+    __syncthreads();
     // L_II^{-1} into LDS (zero-padded to 32 x 32).
-    for (int e = tid; e < kNB * kNB; e += nt) {
+    for (int e = tid; e < kNB * kNB; e += 512) {
       const int i = e / kNB, q = e % kNB;
       di[i][q] = (i < nbI && q <= i) ? Lb[static_cast<int64_t>(I0 + i) * p + I0 + q] : 0.0;
     }
-    for (int J0 = 0; J0 < I0; J0 += kNB) {
-      double t0 = 0.0, t1 = 0.0;
-      for (int K0 = J0; K0 < I0; K0 += kNB) {
-        __syncthreads();
-        // dl <- L[I0 + i][K0 + k], pan[0..31] <- Linv[K0 + k][J0 + c] (all in range:
-        // K0 + k < I0 <= p - 1 and J0 + c < I0).
-        for (int e = tid; e < kNB * kNB; e += nt) {
-          const int r = e / kNB, q = e % kNB;
-          dl[r][q] = r < nbI ? Gb[static_cast<int64_t>(I0 + r) * p + K0 + q] : 0.0;
-          pan[r][q] = Lb[static_cast<int64_t>(K0 + r) * p + J0 + q];
-        }
-        __syncthreads();
-        if (tid < 512) {
-#pragma unroll 8
-          for (int k = 0; k < kNB; ++k) {
-            const double l = dl[ti][k];
-            t0 = fma(l, pan[k][tc2], t0);
-            t1 = fma(l, pan[k][tc2 + 1], t1);
-          }
-        }
+    double t0 = 0.0, t1 = 0.0;
+    for (int K0 = J0; K0 < I0; K0 += kNB) {
+      __syncthreads();
+      // dl <- L[I0 + r][K0 + q], pan <- Linv[K0 + r][J0 + q]: K0 + r < I0 <= p - 1
+      // and J0 + q < J0 + kNB <= I0 (block column J is full).
+      for (int e = tid; e < kNB * kNB; e += 512) {
+        const int r = e / kNB, q = e % kNB;
+        dl[r][q] = r < nbI ? Gb[static_cast<int64_t>(I0 + r) * p + K0 + q] : 0.0;
+        pan[r][q] = Lb[static_cast<int64_t>(K0 + r) * p + J0 + q];
       }
       __syncthreads();
-      dl[ti][tc2] = t0;
-      dl[ti][tc2 + 1] = t1;
-      __syncthreads();
-      double o0 = 0.0, o1 = 0.0;
 #pragma unroll 8
-      for (int q = 0; q < kNB; ++q) {
-        const double d = di[ti][q];  // zero above the diagonal
-        o0 = fma(d, dl[q][tc2], o0);
-        o1 = fma(d, dl[q][tc2 + 1], o1);
-      }
-      if (ti < nbI) {
-        Lb[static_cast<int64_t>(I0 + ti) * p + J0 + tc2] = -o0;
-        Lb[static_cast<int64_t>(I0 + ti) * p + J0 + tc2 + 1] = -o1;
+      for (int k = 0; k < kNB; ++k) {
+        const double l = dl[ti][k];
+        t0 = fma(l, pan[k][tc2], t0);
+        t1 = fma(l, pan[k][tc2 + 1], t1);
       }
     }
     __syncthreads();
+    dl[ti][tc2] = t0;
+    dl[ti][tc2 + 1] = t1;
+    __syncthreads();
+    double o0 = 0.0, o1 = 0.0;
+#pragma unroll 8
+    for (int q = 0; q < kNB; ++q) {
+      const double d = di[ti][q];  // zero above the diagonal
+      o0 = fma(d, dl[q][tc2], o0);
+      o1 = fma(d, dl[q][tc2 + 1], o1);
+    }
+    if (ti < nbI) {
+      Lb[static_cast<int64_t>(I0 + ti) * p + J0 + tc2] = -o0;
+      Lb[static_cast<int64_t>(I0 + ti) * p + J0 + tc2 + 1] = -o1;
+    }
   }
-  if (tid == 0 && bad) atomicCAS(flags, 0, blk + 1);
 }
 
 // 64x64 tile of Out_i = Linv_i In_i (Linv lower triangular: K runs to the
@@ -1281,6 +1335,21 @@ hipError_t launch_fused_f32x64(const FusedArgs<float, double>& a, int g, hipStre
   return fused_impl(a, g, s);
 }
 
+hipError_t launch_block_sum(const double* part, int64_t ldp, const int32_t* tile_first, int32_t m,
+                            int64_t ncols, double* out, int64_t ldo, hipStream_t s) {
+  if (m <= 0 || ncols <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_block_sum, dim3(grid_for(ncols, 256), static_cast<unsigned>(m)), dim3(256),
+                     0, s, part, ldp, tile_first, ncols, out, ldo);
+  return hipGetLastError();
+}
+
+hipError_t launch_defect(const double* U, const double* V, int64_t ld, int32_t m, int64_t n,
+                         double* out, hipStream_t s) {
+  if (m <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_defect, dim3(static_cast<unsigned>(m)), dim3(256), 0, s, U, V, ld, n, out);
+  return hipGetLastError();
+}
+
 hipError_t launch_fused_sum(const double* part, int64_t ldp, int32_t ntiles, int64_t n,
                             double alpha, double* out, hipStream_t s) {
   APC_LAUNCH(k_fused_sum, dim3(grid_for(n, 32)), dim3(256), 0, s, part, ldp, ntiles, n, alpha,
@@ -1351,9 +1420,14 @@ hipError_t launch_gram(const double* C, int64_t ldc, const int64_t* off, const i
   return hipGetLastError();
 }
 
-hipError_t launch_chol_inv(const int64_t* off, const int64_t* goff, int32_t m, double* G,
-                           double* Linv, int* flags, double rank_tol, hipStream_t s) {
+hipError_t launch_chol_inv(const int64_t* off, const int64_t* goff, int32_t m, int64_t pmax,
+                           double* G, double* Linv, int* flags, double rank_tol, hipStream_t s) {
   hipLaunchKernelGGL(k_chol_inv, dim3(m), dim3(512), 0, s, off, goff, G, Linv, flags, rank_tol);
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const unsigned cols = static_cast<unsigned>((pmax + kNB - 1) / kNB);
+  hipLaunchKernelGGL(k_tri_inv, dim3(cols, static_cast<unsigned>(m)), dim3(512), 0, s, off, goff,
+                     G, Linv);
   return hipGetLastError();
 }
 
