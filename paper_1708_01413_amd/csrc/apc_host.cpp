@@ -66,7 +66,7 @@ struct Layout {
   int64_t ldc = 0, kmax = 0, S = 0;
   int32_t ntiles_a = 0, ntiles_g = 0, ntiles_t = 0, nparts = 0;
   int32_t ntiles_fmax = 0;  // single-pass row tiles the workspace holds (k = 1)
-  size_t tiles_f = 0, fpart = 0;
+  size_t tiles_f = 0, fpart = 0, v32 = 0;
   // k-RHS path: rows/K padding of its operands (N and n rounded up to kTnPad)
   int64_t Np = 0, np = 0;
   size_t Cq, CqT, C64T, Apad, yq, Wq, tnpart, x0, ys, c64p, Xs, Rb, cw, Linv2, ssq;
@@ -243,6 +243,7 @@ Layout make_layout(int64_t N, int64_t n, const int64_t* off, int32_t m, int32_t 
   L.tiles_f = take((3 * static_cast<int64_t>(L.ntiles_fmax) + m + 1) * 4);
   // FP64 entries: the normal operator of the eigenvalue estimate sums in FP64.
   L.fpart = take(static_cast<int64_t>(L.ntiles_fmax) * L.ldc * 8);
+  L.v32 = take(L.ntiles_fmax > 0 ? L.ldc * 4 : 0);  // FP32 copy of an operator's vector
   L.tiles_g = take(3 * static_cast<int64_t>(L.ntiles_g) * 4);
   L.tiles_t = take(3 * static_cast<int64_t>(L.ntiles_t) * 4);
   L.doff = take((m + 1) * 8);
@@ -401,7 +402,6 @@ struct apc_plan_s {
   int32_t fused_tpb = 0;               // > 0: every block has this many single-pass tiles
   int32_t qr_passes = 2;               // CholeskyQR passes setup took (1: see setup_impl)
   double qr_defect = NAN;              // estimated ||Q_i^T Q_i - I|| after the first pass
-  int32_t op_g = 1;                    // rows per register group of the FP32 x FP64 operator
   int64_t since_start = 0;             // k-RHS updates since the last start
   int refinements = 0;
   std::vector<int32_t> tile_start;     // first pass-A tile of every block (m+1)
@@ -894,15 +894,23 @@ NormalOp x_operator(const apc_plan_s* P) {
 apc_status normal_matvec(apc_plan_s* P, const NormalOp& op, const double* v, double* out) {
   const Layout& L = P->L;
   // One pass over C (the plan's single-pass tiles, v shared by every tile),
-  // then the FP64 sum of the tiles' partial rows.
-  const int cpt32 = fused_cpt(L.ldc, 4), cpt64 = fused_cpt(L.ldc, 8);
-  if (P->fused && (op.f32 ? fused_shape_ok(4, 8, cpt32, P->op_g) : cpt64 > 0)) {
+  // then the FP64 sum of the tiles' partial rows.  Through the FP32 factor the
+  // pass runs in FP32 like the iteration's (v rounded to FP32, FP32 partial
+  // rows): the operator then carries a relative error ~1e-7, far below the
+  // eigenvalue estimate's stopping tolerances (3e-4 and 1e-2).
+  const int cpt64 = fused_cpt(L.ldc, 8);
+  if (P->fused && (op.f32 || cpt64 > 0)) {
     double* part = P->at<double>(L.fpart);
     const int32_t remap = P->xcd_remap == 1 ? 1 : 0;
     if (op.f32) {
-      FusedArgs<float, double> a{static_cast<const float*>(op.C), L.ldc, P->n, P->tf(0),
-                                 P->tf(1), P->tf(2), P->ntiles_f, v, 0, part, L.ldc, remap};
-      HIP_TRY(launch_fused_f32x64(a, P->op_g, P->stream));
+      float* v32 = P->at<float>(L.v32);
+      float* part32 = P->at<float>(L.fpart);
+      HIP_TRY(launch_cast_f32(v, v32, L.ldc, P->stream));
+      FusedArgs<float, float> a{static_cast<const float*>(op.C), L.ldc, P->n, P->tf(0), P->tf(1),
+                                P->tf(2), P->ntiles_f, v32, 0, part32, L.ldc, remap};
+      HIP_TRY(launch_fused_f32(a, P->fused_g, P->stream));
+      HIP_TRY(launch_fused_sum_f32(part32, L.ldc, P->ntiles_f, L.ldc, op.scale, out, P->stream));
+      return APC_OK;
     } else {
       FusedArgs<double, double> a{static_cast<const double*>(op.C), L.ldc, P->n, P->tf(0),
                                   P->tf(1), P->tf(2), P->ntiles_f, v, 0, part, L.ldc, remap};
@@ -1147,15 +1155,21 @@ apc_status setup_impl(apc_plan_s* P, const Tiles& T) {
   double* Cb = P->at<double>(L.C64b);
   double* ca = P->at<double>(L.ca);
   double* cb = P->at<double>(L.cb);
-  HIP_TRY(launch_copy_pad(P->A, P->lda, P->B, P->ldb, N, n, Ca, ldc, ca, P->k, P->kp, st));
-  int64_t pmax = 1;
-  for (int i = 0; i < m; ++i) pmax = std::max(pmax, P->off[i + 1] - P->off[i]);
-  const double rank_tol = 32.0 * std::numeric_limits<double>::epsilon() *
-                          static_cast<double>(std::max<int64_t>(pmax, 32));
   // The Gram and triangular products run on the FP64 matrix cores
   // (APC_SETUP_MFMA=0 selects the vector kernels).
   bool mfma = true;
   if (const char* e = std::getenv("APC_SETUP_MFMA")) mfma = std::atoi(e) != 0;
+  // When A's rows are already the factor's padded rows (n a multiple of 64,
+  // lda = n, 16-byte aligned), the first pass reads A in place and only b is
+  // copied (the matrix-core kernels never read past a block's rows).
+  const bool in_place = mfma && n == ldc && P->lda == ldc &&
+                        reinterpret_cast<uintptr_t>(P->A) % 16 == 0;
+  HIP_TRY(launch_copy_pad(P->A, P->lda, P->B, P->ldb, N, n, in_place ? nullptr : Ca, ldc, ca,
+                          P->k, P->kp, st));
+  int64_t pmax = 1;
+  for (int i = 0; i < m; ++i) pmax = std::max(pmax, P->off[i + 1] - P->off[i]);
+  const double rank_tol = 32.0 * std::numeric_limits<double>::epsilon() *
+                          static_cast<double>(std::max<int64_t>(pmax, 32));
   // A k = 1 FP32 plan rounds the factor to FP32 (relative 6e-8 per entry), so a
   // second CholeskyQR pass, which takes the rows' departure from orthonormality
   // from the first pass's ~kappa(A_i)^2 eps down to ~eps, changes nothing the
@@ -1166,7 +1180,7 @@ apc_status setup_impl(apc_plan_s* P, const Tiles& T) {
   bool may_skip = !P->gemm && P->prec == APC_F32 && P->fused && fused_cpt(ldc, 8) > 0;
   if (const char* e = std::getenv("APC_QR_PASSES")) may_skip = may_skip && std::atoi(e) != 2;
   for (int pass = 0; pass < 2; ++pass) {
-    double* src = pass == 0 ? Ca : Cb;
+    const double* src = pass == 0 ? (in_place ? P->A : Ca) : Cb;
     double* dst = pass == 0 ? Cb : Ca;
     const double* cs = pass == 0 ? ca : cb;
     double* cd = pass == 0 ? cb : ca;
@@ -1183,8 +1197,10 @@ apc_status setup_impl(apc_plan_s* P, const Tiles& T) {
                             P->at<int>(L.flags), rank_tol, st));
     HIP_TRY(launch_linv_apply(P->doff(), P->at<int64_t>(L.goff), m, P->pmax, Li, cs, N, cd, N,
                               P->kp, 0, 1.0, st));
+    // An FP32 k = 1 plan's factor copy is written by the same launch.
+    float* dst32 = (P->prec == APC_F32 && !P->gemm) ? P->at<float>(L.C32) : nullptr;
     if (mfma)
-      HIP_TRY(launch_trmm_mfma(src, dst, ldc, P->doff(), m, P->at<int64_t>(L.goff), Li, st));
+      HIP_TRY(launch_trmm_mfma(src, dst, ldc, P->doff(), m, P->at<int64_t>(L.goff), Li, dst32, st));
     else
       HIP_TRY(launch_trmm(src, dst, ldc, P->doff(), P->at<int32_t>(L.tiles_t), L.ntiles_t,
                           P->at<int64_t>(L.goff), Li, st));
@@ -1248,7 +1264,7 @@ apc_status setup_impl(apc_plan_s* P, const Tiles& T) {
       HIP_TRY(launch_expand_f64(e, st));
     }
     ST_TRY(average(P, 1.0 / m, 0.0));
-    if (P->prec == APC_F32) HIP_TRY(launch_cast_f32(Ca, P->at<float>(L.C32), N * ldc, st));
+    if (P->prec == APC_F32 && !mfma) HIP_TRY(launch_cast_f32(Ca, P->at<float>(L.C32), N * ldc, st));
   }
 
   // Parameters: caller's, or Theorem 1's optimum from the estimated spectrum.
@@ -1371,10 +1387,6 @@ apc_status apc_setup(apc_plan* out, const double* A, int64_t lda, const double* 
   P->fused = fused;
   P->fused_rows = fused_rows;
   P->fused_g = fused_g;
-  if (const char* e = std::getenv("APC_FUSED_OP_G")) {
-    const int g = std::atoi(e);
-    if (g == 1 || g == 2 || g == 4) P->op_g = g;
-  }
   P->ntiles_f = static_cast<int32_t>(T.f_row0.size());
   if (fused) {
     const int32_t t0 = T.f_first[1];
@@ -2338,14 +2350,14 @@ apc_status hbm_update(apc_hbm_s* H) {
   // Single pass (the plan's tiles): every tile's partial of sum_r (C_r x - d_r) C_r,
   // their sum (the gradient), then the heavy-ball step.
   const int cpt32 = fused_cpt(L.ldc, 4), cpt64 = fused_cpt(L.ldc, 8);
-  if (P->fused && (f32 ? fused_shape_ok(4, 8, cpt32, P->op_g) : cpt64 > 0)) {
+  if (P->fused && (f32 ? fused_shape_ok(4, 8, cpt32, 1) : cpt64 > 0)) {
     double* part = P->at<double>(L.fpart);
     const int32_t remap = P->xcd_remap == 1 ? 1 : 0;
     if (f32) {
       FusedArgs<float, double> a{static_cast<const float*>(H->C), L.ldc, P->n, P->tf(0),
                                  P->tf(1), P->tf(2), P->ntiles_f, H->x, 0, part, L.ldc, remap,
                                  H->d};
-      HIP_TRY(launch_fused_f32x64(a, P->op_g, P->stream));
+      HIP_TRY(launch_fused_f32x64(a, 1, P->stream));
     } else {
       FusedArgs<double, double> a{static_cast<const double*>(H->C), L.ldc, P->n, P->tf(0),
                                   P->tf(1), P->tf(2), P->ntiles_f, H->x, 0, part, L.ldc, remap,

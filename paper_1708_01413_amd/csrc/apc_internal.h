@@ -186,6 +186,9 @@ hipError_t launch_defect(const double* U, const double* V, int64_t ld, int32_t m
 // out[j] = alpha * sum over all ntiles partial rows part[t][j] (FP64), j < n.
 hipError_t launch_fused_sum(const double* part, int64_t ldp, int32_t ntiles, int64_t n,
                             double alpha, double* out, hipStream_t s);
+// The same over FP32 partial rows (summed in FP64).
+hipError_t launch_fused_sum_f32(const float* part, int64_t ldp, int32_t ntiles, int64_t n,
+                                double alpha, double* out, hipStream_t s);
 
 // The rest of one update after the single-pass kernel, per column j < n:
 //   x_i[j] += gamma (x_bar[j] - x_i[j] - sum_{t in block i} part[t][j])   (eq. 2a)
@@ -403,8 +406,10 @@ hipError_t launch_chol_inv(const int64_t* off, const int64_t* goff, int32_t m, i
 hipError_t launch_gram_mfma(const double* C, int64_t ldc, const int64_t* off,
                             const int32_t* tiles, int32_t ntiles, const int64_t* goff, double* G,
                             hipStream_t s);
+// out32 (optional, same layout as Out): the result also rounded to FP32.
 hipError_t launch_trmm_mfma(const double* In, double* Out, int64_t ldc, const int64_t* off,
-                            int32_t m, const int64_t* goff, const double* Linv, hipStream_t s);
+                            int32_t m, const int64_t* goff, const double* Linv, float* out32,
+                            hipStream_t s);
 hipError_t launch_trmm(const double* In, double* Out, int64_t ldc, const int64_t* off,
                        const int32_t* tiles, int32_t ntiles, const int64_t* goff,
                        const double* Linv, hipStream_t s);

@@ -592,11 +592,12 @@ __global__ __launch_bounds__(256) void k_fused_combine(FusedCombineArgs<TD> a) {
   }
 }
 
-// out[j] = alpha sum_t part[t][j] over all tiles (FP64, fixed order), j < n:
+// out[j] = alpha sum_t part[t][j] over all tiles (summed in FP64, fixed order), j < n:
 // the sum over blocks of the normal operator after k_fused with one shared
 // vector.  32 columns per workgroup, 8 lanes per column, each lane four
 // independent running sums.
-__global__ __launch_bounds__(256) void k_fused_sum(const double* part, int64_t ldp, int32_t ntiles,
+template <typename TP>
+__global__ __launch_bounds__(256) void k_fused_sum(const TP* part, int64_t ldp, int32_t ntiles,
                                                    int64_t n, double alpha, double* out) {
   __shared__ double red[8][32];
   const int lane = threadIdx.x & 31;
@@ -608,7 +609,7 @@ __global__ __launch_bounds__(256) void k_fused_sum(const double* part, int64_t l
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const int t = t0 + 8 * q;
-        if (t < ntiles) acc[q] += part[static_cast<int64_t>(t) * ldp + j];
+        if (t < ntiles) acc[q] += static_cast<double>(part[static_cast<int64_t>(t) * ldp + j]);
       }
     }
   }
@@ -708,7 +709,8 @@ __global__ __launch_bounds__(kThreads) void k_expand(ExpandArgs<TQ> a) {
 __global__ void k_copy_pad(const double* A, int64_t lda, const double* B, int64_t ldb, int64_t N,
                            int64_t n, double* C, int64_t ldc, double* c, int32_t k, int32_t kp) {
   for (int64_t r = blockIdx.x; r < N; r += gridDim.x) {
-    for (int64_t j = threadIdx.x; j < ldc; j += blockDim.x) C[r * ldc + j] = j < n ? A[r * lda + j] : 0.0;
+    if (C)
+      for (int64_t j = threadIdx.x; j < ldc; j += blockDim.x) C[r * ldc + j] = j < n ? A[r * lda + j] : 0.0;
     for (int col = threadIdx.x; col < kp; col += blockDim.x)
       c[static_cast<int64_t>(col) * N + r] = col < k ? B[r * ldb + col] : 0.0;
   }
@@ -1352,8 +1354,14 @@ hipError_t launch_defect(const double* U, const double* V, int64_t ld, int32_t m
 
 hipError_t launch_fused_sum(const double* part, int64_t ldp, int32_t ntiles, int64_t n,
                             double alpha, double* out, hipStream_t s) {
-  APC_LAUNCH(k_fused_sum, dim3(grid_for(n, 32)), dim3(256), 0, s, part, ldp, ntiles, n, alpha,
-             out);
+  APC_LAUNCH(k_fused_sum<double>, dim3(grid_for(n, 32)), dim3(256), 0, s, part, ldp, ntiles, n,
+             alpha, out);
+  return hipGetLastError();
+}
+hipError_t launch_fused_sum_f32(const float* part, int64_t ldp, int32_t ntiles, int64_t n,
+                                double alpha, double* out, hipStream_t s) {
+  APC_LAUNCH(k_fused_sum<float>, dim3(grid_for(n, 32)), dim3(256), 0, s, part, ldp, ntiles, n,
+             alpha, out);
   return hipGetLastError();
 }
 
