@@ -402,6 +402,8 @@ struct apc_plan_s {
   int32_t fused_tpb = 0;               // > 0: every block has this many single-pass tiles
   int32_t qr_passes = 2;               // CholeskyQR passes setup took (1: see setup_impl)
   double qr_defect = NAN;              // estimated ||Q_i^T Q_i - I|| after the first pass
+  double* pinned = nullptr;            // pinned host copy of the Lanczos coefficients
+  hipEvent_t check_ev = nullptr;       // recorded after their copy
   int64_t since_start = 0;             // k-RHS updates since the last start
   int refinements = 0;
   std::vector<int32_t> tile_start;     // first pass-A tile of every block (m+1)
@@ -890,8 +892,10 @@ NormalOp x_operator(const apc_plan_s* P) {
                   f32, 1.0 / P->m};
 }
 
-// out = op(v), FP64 vectors and accumulation.
-apc_status normal_matvec(apc_plan_s* P, const NormalOp& op, const double* v, double* out) {
+// out = op(v), FP64 vectors and accumulation.  v32_ready: the plan's FP32
+// operator vector already holds v rounded to FP32.
+apc_status normal_matvec(apc_plan_s* P, const NormalOp& op, const double* v, double* out,
+                         bool v32_ready = false) {
   const Layout& L = P->L;
   // One pass over C (the plan's single-pass tiles, v shared by every tile),
   // then the FP64 sum of the tiles' partial rows.  Through the FP32 factor the
@@ -905,7 +909,7 @@ apc_status normal_matvec(apc_plan_s* P, const NormalOp& op, const double* v, dou
     if (op.f32) {
       float* v32 = P->at<float>(L.v32);
       float* part32 = P->at<float>(L.fpart);
-      HIP_TRY(launch_cast_f32(v, v32, L.ldc, P->stream));
+      if (!v32_ready) HIP_TRY(launch_cast_f32(v, v32, L.ldc, P->stream));
       FusedArgs<float, float> a{static_cast<const float*>(op.C), L.ldc, P->n, P->tf(0), P->tf(1),
                                 P->tf(2), P->ntiles_f, v32, 0, part32, L.ldc, remap};
       HIP_TRY(launch_fused_f32(a, P->fused_g, P->stream));
@@ -993,31 +997,25 @@ apc_status lanczos(apc_plan_s* P, const NormalOp& op, double cap, double* lo_out
   const int32_t ns = static_cast<int32_t>((ldc + scols - 1) / scols);
   const int32_t nslab = static_cast<int32_t>((ldc + expand_slab(8) - 1) / expand_slab(8));
 
-  std::vector<double> a, b;
   double th_lo = 0, th_hi = 0, bd_lo = INFINITY, bd_hi = INFINITY;
   double prev_lo = NAN, prev_hi = NAN, d_lo = INFINITY, d_hi = INFINITY;
-  bool done = false;
-  int steps = 0;
-  for (int j = 0; j < kmax && !done; ++j) {
-    ST_TRY(normal_matvec(P, op, V + static_cast<int64_t>(j) * ldc, vt));
-    for (int pass = 0; pass < 2; ++pass) {
-      double* hh = pass == 0 ? h : h2;
-      RowdotArgs<double> r{V, ldc, nullptr, nullptr, nullptr, (j + 1 + 7) / 8, j + 1, vt, nullptr,
-                           0, nullptr, 0, hh, hstride, ns, scols, 0, 8, 0};
-      HIP_TRY(launch_rowdot_f64(r, P->stream));
-      ExpandArgs<double> e{V, ldc, nullptr, 1, nslab, j + 1, hh, ns, hstride, vt, 0, -1.0, 1.0, 0};
-      HIP_TRY(launch_expand_f64(e, P->stream));
-    }
-    HIP_TRY(launch_lanczos_normalize(vt, ldc, h, h2, ns, hstride, j, al, be,
-                                     V + static_cast<int64_t>(j + 1) * ldc, P->stream));
-    const int k = j + 1;
-    steps = k;
-    if (k % kLanczosCheck != 0 && k != kmax) continue;
-    a.resize(k);
-    b.resize(k);
-    HIP_TRY(hipMemcpyAsync(a.data(), al, k * sizeof(double), hipMemcpyDeviceToHost, P->stream));
-    HIP_TRY(hipMemcpyAsync(b.data(), be, k * sizeof(double), hipMemcpyDeviceToHost, P->stream));
-    HIP_TRY(hipStreamSynchronize(P->stream));
+  // The coefficients of the first k steps, copied to pinned host memory, decide
+  // whether to stop after k steps.  The copy is issued after step k and read
+  // after step k + 1 has been enqueued, so the GPU runs that step while the host
+  // waits and decides; stopping then leaves one step unused.
+  if (!P->pinned) {
+    void* hp = nullptr;
+    HIP_TRY(hipHostMalloc(&hp, 2 * static_cast<size_t>(hstride) * sizeof(double), hipHostMallocDefault));
+    P->pinned = static_cast<double*>(hp);
+  }
+  if (!P->check_ev) HIP_TRY(hipEventCreateWithFlags(&P->check_ev, hipEventDisableTiming));
+  double* ha = P->pinned;
+  double* hb = P->pinned + hstride;
+  std::vector<double> a, b;
+  // Convergence test on T_k (alpha, beta of the first k steps in ha, hb).
+  auto converged = [&](int k) -> apc_status {
+    a.assign(ha, ha + k);
+    b.assign(hb, hb + k);
     for (int i = 0; i < k; ++i)
       if (!std::isfinite(a[i]) || !std::isfinite(b[i]))
         return fail(APC_EDIVERGED, "non-finite value in the Lanczos recurrence");
@@ -1054,7 +1052,57 @@ apc_status lanczos(apc_plan_s* P, const NormalOp& op, double cap, double* lo_out
     const bool lo_ok = bd_lo <= 1e-6 * th_lo || (d_lo <= 1e-2 * th_lo && bd_lo <= 0.5 * th_lo);
     prev_lo = th_lo;
     prev_hi = th_hi;
-    done = exhausted || (hi_ok && lo_ok);
+    return (exhausted || (hi_ok && lo_ok)) ? APC_OK : APC_ENOCONV;
+  };
+  auto issue_copy = [&](int k) -> apc_status {
+    HIP_TRY(hipMemcpyAsync(ha, al, k * sizeof(double), hipMemcpyDeviceToHost, P->stream));
+    HIP_TRY(hipMemcpyAsync(hb, be, k * sizeof(double), hipMemcpyDeviceToHost, P->stream));
+    HIP_TRY(hipEventRecord(P->check_ev, P->stream));
+    return APC_OK;
+  };
+  auto decide = [&](int k, bool* stop) -> apc_status {
+    HIP_TRY(hipEventSynchronize(P->check_ev));
+    const apc_status c = converged(k);
+    if (c != APC_OK && c != APC_ENOCONV) return c;
+    *stop = c == APC_OK;
+    return APC_OK;
+  };
+  // The FP32 operator reads the vector's FP32 copy, which the normalisation
+  // writes for the next step.
+  float* v32 = op.f32 && P->fused ? P->at<float>(P->L.v32) : nullptr;
+  if (v32) HIP_TRY(launch_cast_f32(V, v32, ldc, P->stream));
+  bool done = false;
+  int steps = 0, pending = 0;
+  for (int j = 0; j < kmax && !done; ++j) {
+    ST_TRY(normal_matvec(P, op, V + static_cast<int64_t>(j) * ldc, vt, v32 != nullptr));
+    for (int pass = 0; pass < 2; ++pass) {
+      double* hh = pass == 0 ? h : h2;
+      RowdotArgs<double> r{V, ldc, nullptr, nullptr, nullptr, (j + 1 + 7) / 8, j + 1, vt, nullptr,
+                           0, nullptr, 0, hh, hstride, ns, scols, 0, 8, 0};
+      HIP_TRY(launch_rowdot_f64(r, P->stream));
+      ExpandArgs<double> e{V, ldc, nullptr, 1, nslab, j + 1, hh, ns, hstride, vt, 0, -1.0, 1.0, 0};
+      HIP_TRY(launch_expand_f64(e, P->stream));
+    }
+    HIP_TRY(launch_lanczos_normalize(vt, ldc, h, h2, ns, hstride, j, al, be,
+                                     V + static_cast<int64_t>(j + 1) * ldc, v32, P->stream));
+    const int k = j + 1;
+    if (pending) {
+      ST_TRY(decide(pending, &done));
+      if (done) {
+        steps = pending;
+        break;
+      }
+      pending = 0;
+    }
+    steps = k;
+    if (k % kLanczosCheck == 0 || k == kmax) {
+      ST_TRY(issue_copy(k));
+      pending = k;
+      if (k == kmax) {
+        ST_TRY(decide(k, &done));
+        pending = 0;
+      }
+    }
   }
   *steps_out = steps;
   if (!done)
@@ -1949,6 +1997,8 @@ int64_t apc_iterations(apc_plan p) { return p ? p->iters : -1; }
 void apc_destroy(apc_plan p) {
   if (!p) return;
   for (hipEvent_t e : p->events) (void)hipEventDestroy(e);
+  if (p->check_ev) (void)hipEventDestroy(p->check_ev);
+  if (p->pinned) (void)hipHostFree(p->pinned);
   delete p;
 }
 

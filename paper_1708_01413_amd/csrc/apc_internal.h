@@ -428,10 +428,11 @@ hipError_t launch_copy_strided(const double* src, int64_t lds, double* dst, int6
                                int64_t rows, int64_t cols, hipStream_t s);
 
 // Lanczos helper: alpha[j] = sum_s h[s*hstride + j] + sum_s h2[s*hstride + j];
-// beta[j] = ||y||; V[j+1] = y / beta[j].
+// beta[j] = ||y||; V[j+1] = y / beta[j], and its FP32 rounding in vnext32 when
+// that is non-null.
 hipError_t launch_lanczos_normalize(const double* y, int64_t n, const double* h, const double* h2,
                                     int32_t nsplit, int64_t hstride, int32_t j, double* alpha,
-                                    double* beta, double* vnext, hipStream_t s);
+                                    double* beta, double* vnext, float* vnext32, hipStream_t s);
 
 // ---------------------------------------------------------------------------
 // Residual monitor (FP64)

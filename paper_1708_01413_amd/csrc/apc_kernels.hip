@@ -1110,7 +1110,8 @@ __global__ __launch_bounds__(1024) void k_lanczos_normalize(const double* y, int
                                                             const double* h, const double* h2,
                                                             int32_t nsplit, int64_t hstride,
                                                             int32_t j, double* alpha,
-                                                            double* beta, double* vnext) {
+                                                            double* beta, double* vnext,
+                                                            float* vnext32) {
   __shared__ double part[1024 / 64];
   __shared__ double bsh;
   double s = 0.0;
@@ -1134,7 +1135,11 @@ __global__ __launch_bounds__(1024) void k_lanczos_normalize(const double* y, int
   __syncthreads();
   const double b = bsh;
   const double inv = b > 0.0 ? 1.0 / b : 0.0;
-  for (int64_t e = threadIdx.x; e < n; e += blockDim.x) vnext[e] = y[e] * inv;
+  for (int64_t e = threadIdx.x; e < n; e += blockDim.x) {
+    const double v = y[e] * inv;
+    vnext[e] = v;
+    if (vnext32) vnext32[e] = static_cast<float>(v);
+  }
 }
 
 // ------------------------------------------------------------------ residual
@@ -1505,9 +1510,9 @@ hipError_t launch_copy_t(const double* src, int64_t lds, double* dst, int64_t ld
 
 hipError_t launch_lanczos_normalize(const double* y, int64_t n, const double* h, const double* h2,
                                     int32_t nsplit, int64_t hstride, int32_t j, double* alpha,
-                                    double* beta, double* vnext, hipStream_t s) {
+                                    double* beta, double* vnext, float* vnext32, hipStream_t s) {
   hipLaunchKernelGGL(k_lanczos_normalize, dim3(1), dim3(1024), 0, s, y, n, h, h2, nsplit, hstride,
-                     j, alpha, beta, vnext);
+                     j, alpha, beta, vnext, vnext32);
   return hipGetLastError();
 }
 
