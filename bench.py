@@ -258,8 +258,19 @@ def many_systems(apc, synth, dev, count=256):
         plans.append(apc.Plan(A, b, S.off, "f32", stream=stream))
     setup_s = time.perf_counter() - t0
     batch = apc.Batch(plans)
-    # Bytes an update must move, summed over systems (as the k = 1 FP32 path).
-    per_update = sum(2 * S.N * S.n * 4 + 3 * S.m * S.n * 8 for S in systems)
+    single = batch.launch()["items_b"] == 0
+    # Bytes an update moves, summed over systems (as the k = 1 FP32 path does:
+    # one read of each factor in the single pass, two in the two-pass form).
+    two_pass_bytes = sum(2 * S.N * S.n * 4 + 3 * S.m * S.n * 8 for S in systems)
+    if single:
+        # The batch cuts every block into row tiles of up to 64 rows, one partial
+        # row each.
+        per_update = 0
+        for S in systems:
+            tiles = int(sum(-(-int(q) // 64) for q in np.diff(S.off)))
+            per_update += algorithmic_bytes_single(S.N, S.n, S.m, tiles)[2]
+    else:
+        per_update = two_pass_bytes
     T = 20
 
     def timed(fn):
@@ -277,6 +288,16 @@ def many_systems(apc, synth, dev, count=256):
         for p in plans:
             p.iterate(T)
     t_seq = timed(one_by_one)
+    t_two = None
+    if single:
+        os.environ["APC_FUSED"] = "0"
+        try:
+            batch2 = apc.Batch(plans)
+        finally:
+            del os.environ["APC_FUSED"]
+        batch2.iterate(T, graph=True)
+        t_two = timed(lambda: batch2.iterate(T, graph=True))
+        batch2.close()
     # Fresh start, then per-system stopping at relative residual 1e-6.
     for p in plans:
         p.restart()
@@ -297,6 +318,8 @@ def many_systems(apc, synth, dev, count=256):
         "us_per_update_graph": round(t_graph * 1e6, 1),
         "us_per_update_eager": round(t_eager * 1e6, 1),
         "us_per_update_one_plan_at_a_time": round(t_seq * 1e6, 1),
+        "form": "single pass over each factor" if single else "two passes over each factor",
+        "two_pass_batch_us_per_update": round(t_two * 1e6, 1) if t_two else None,
         "algorithmic_bytes_per_update": per_update,
         "GBs_graph": round(per_update / t_graph / 1e9, 1),
         "solve_to_relres_1e-6": {"status": apc.STATUS_NAMES.get(st, st), "ms": round(solve_ms, 2),

@@ -328,11 +328,15 @@ apc_status apc_batch_solve(apc_batch b, double rtol, int32_t max_iters, int32_t 
                            int32_t use_graph, int32_t* iters_out, double* relres_out);
 
 /* Launch shape: workgroups per persistent launch, work items per pass, and the
- * measured pass-A time when the grid was chosen by timing.  Host pointers. */
+ * measured time of the pass over the factors when the grid was chosen by
+ * timing.  A batch whose plans all update in one pass over their factor (rows
+ * up to 1024 wide) does too: *items_a then counts its row tiles, *items_b is
+ * 0 and *items_avg counts the 32-column items of the update + average launch.
+ * Host pointers. */
 apc_status apc_batch_get_launch(apc_batch b, int32_t* grid, int32_t* items_a, int32_t* items_b,
                                 int32_t* items_avg, float* tuned_us);
 
-/* Release the batch (and its captured graphs). */
+/* Release the batch (and its captured graphs) after its stream has finished. */
 void apc_batch_destroy(apc_batch b);
 
 /* ---- Comparison methods on the same passes (Sec. 4.3, Sec. 6) -----------

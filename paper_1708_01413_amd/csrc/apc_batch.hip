@@ -7,7 +7,13 @@
 // blockIdx.x + gridDim.x, ...  Items of a system whose `active` flag is 0 are
 // skipped, so converged systems stop costing bandwidth.
 //
-// Per update (eq. (2a)-(2b) for every system):
+// Per update (eq. (2a)-(2b) for every system), when every plan updates in one
+// pass and rows are at most 1024 wide:
+//   single pass  items (system, row tile of one block): w_r = C_r . d_i and the
+//                tile's partial row sum_r w_r C_r, one read of the factor
+//   combine      items (system, 32 columns): x_i += gamma (x_bar - x_i - Q_i w_i),
+//                x_bar <- (eta/m) sum_i x_i + (1-eta) x_bar, d_i = x_bar - x_i
+// otherwise in two passes:
 //   pass A   items (system, 16-row tile of one block): w_r = C_r . d_i
 //   pass B   items (system, block, 256-column slab):   x_i += gamma (x_bar - x_i - Q_i w_i)
 //   average  items (system, 256-column chunk):          x_bar <- (eta/m) sum_i x_i + (1-eta) x_bar,
@@ -159,6 +165,144 @@ __global__ __launch_bounds__(256) void k_batch_average(const BatchSys* sys, cons
   }
 }
 
+// Single pass over one row tile of one system: w_r = C_r . d_blk for each row
+// and the tile's partial row sum_r w_r C_r.  Lane l holds the 16-byte chunks
+// l, l + 64, ... (CPL of them: rows up to 256 CPL wide), so a row's dot product
+// needs only a wave sum.  A wave takes RF = 16 / CPL rows at a time (rows
+// wv, wv + 4, ...), all their loads in flight, so short rows still keep 16
+// loads per lane in flight.  The four waves' partial rows are added in LDS.
+template <int CPL>
+__device__ inline void batch_tile_pass(const BatchSys& S, int t, float (&red)[4][kBatchFusedCols]) {
+  constexpr int RF = 16 / CPL;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int64_t row0 = S.tiles[t];
+  const int nrows = S.tiles[S.ntiles + t];
+  const int blk = S.tiles[2 * S.ntiles + t];
+  const float* C = static_cast<const float*>(S.C);
+  const float* d = static_cast<const float*>(S.d) + static_cast<int64_t>(blk) * S.ldc;
+  float dv[CPL][4], acc[CPL][4];
+#pragma unroll
+  for (int c = 0; c < CPL; ++c) {
+    const int64_t j = static_cast<int64_t>(lane + 64 * c) * 4;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      dv[c][e] = j + e < S.n ? d[j + e] : 0.f;
+      acc[c][e] = 0.f;
+    }
+  }
+  for (int r = wv; r < nrows; r += 4 * RF) {
+    float4 row[RF][CPL];
+#pragma unroll
+    for (int q = 0; q < RF; ++q)
+#pragma unroll
+      for (int c = 0; c < CPL; ++c) {
+        const int64_t j = static_cast<int64_t>(lane + 64 * c) * 4;
+        // C is zero from n to ldc (a multiple of 64), so a chunk that starts
+        // before n stays inside the row.
+        row[q][c] = (r + 4 * q < nrows && j < S.n) ? ld4_nt(C + (row0 + r + 4 * q) * S.ldc + j)
+                                                    : make_float4(0.f, 0.f, 0.f, 0.f);
+      }
+#pragma unroll
+    for (int q = 0; q < RF; ++q) {
+      float s = 0.f;
+#pragma unroll
+      for (int c = 0; c < CPL; ++c)
+        s += (row[q][c].x * dv[c][0] + row[q][c].y * dv[c][1]) +
+             (row[q][c].z * dv[c][2] + row[q][c].w * dv[c][3]);
+      s = wsum64(s);
+#pragma unroll
+      for (int c = 0; c < CPL; ++c) {
+        acc[c][0] = fmaf(s, row[q][c].x, acc[c][0]);
+        acc[c][1] = fmaf(s, row[q][c].y, acc[c][1]);
+        acc[c][2] = fmaf(s, row[q][c].z, acc[c][2]);
+        acc[c][3] = fmaf(s, row[q][c].w, acc[c][3]);
+      }
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < CPL; ++c)
+#pragma unroll
+    for (int e = 0; e < 4; ++e) red[wv][(lane + 64 * c) * 4 + e] = acc[c][e];
+}
+
+// Items (sys, row tile of the batch's tiles for that system): the tile's
+// partial row, for rows up to kBatchFusedCols wide.
+__global__ __launch_bounds__(256) void k_batch_fused(const BatchSys* sys, const int2* items,
+                                                     int32_t nitems, const int32_t* active) {
+  __shared__ float red[4][kBatchFusedCols];
+  for (int32_t it = blockIdx.x; it < nitems; it += gridDim.x) {
+    const int2 w = items[it];
+    if (!active[w.x]) continue;  // uniform per workgroup
+    const BatchSys& S = sys[w.x];
+    if (S.ldc <= 256) batch_tile_pass<1>(S, w.y, red);
+    else if (S.ldc <= 512) batch_tile_pass<2>(S, w.y, red);
+    else batch_tile_pass<4>(S, w.y, red);
+    __syncthreads();
+    float* out = S.part + static_cast<int64_t>(w.y) * S.ldc;
+    for (int64_t j = threadIdx.x; j < S.ldc; j += 256)
+      out[j] = (red[0][j] + red[1][j]) + (red[2][j] + red[3][j]);
+    __syncthreads();
+  }
+}
+
+// After k_batch_fused, items (sys, first of 32 columns): lanes (column,
+// block-lane) as in the single-system combine -- x_i += gamma (x_bar - x_i -
+// sum of block i's partial rows), x_bar <- (eta/m) sum_i x_i + (1 - eta) x_bar,
+// d_i = x_bar - x_i.  A block's partial rows are loaded four at a time, with
+// its x_i, before they are added.
+__global__ __launch_bounds__(256) void k_batch_fused_combine(const BatchSys* sys, const int2* items,
+                                                             int32_t nitems, const int32_t* active) {
+  __shared__ double part[8][32];
+  __shared__ double xb[32];
+  const int lane = threadIdx.x & 31;
+  const int bl = threadIdx.x >> 5;
+  for (int32_t it = blockIdx.x; it < nitems; it += gridDim.x) {
+    const int2 w = items[it];
+    if (!active[w.x]) continue;  // uniform per workgroup
+    const BatchSys& S = sys[w.x];
+    const int64_t j = w.y + lane;
+    double* x = S.x;
+    double s = 0.0;
+    if (j < S.n) {
+      const double xo = S.xbar[j];
+      for (int i = bl; i < S.m; i += 8) {
+        const int64_t o = static_cast<int64_t>(i) * S.ldc + j;
+        const double xi = x[o];
+        const int t1 = S.tile_first[i + 1];
+        double u = 0.0;
+        for (int t = S.tile_first[i]; t < t1; t += 4) {
+          float v[4];
+#pragma unroll
+          for (int k = 0; k < 4; ++k)
+            v[k] = t + k < t1 ? S.part[static_cast<int64_t>(t + k) * S.ldc + j] : 0.f;
+#pragma unroll
+          for (int k = 0; k < 4; ++k) u += static_cast<double>(v[k]);
+        }
+        const double xn = xi + S.gamma * ((xo - xi) - u);
+        x[o] = xn;
+        s += xn;
+      }
+    }
+    part[bl][lane] = s;
+    __syncthreads();
+    if (bl == 0 && j < S.n) {
+      const double tot = ((part[0][lane] + part[1][lane]) + (part[2][lane] + part[3][lane])) +
+                         ((part[4][lane] + part[5][lane]) + (part[6][lane] + part[7][lane]));
+      const double v = (S.eta / S.m) * tot + (1.0 - S.eta) * S.xbar[j];
+      S.xbar[j] = v;
+      xb[lane] = v;
+    }
+    __syncthreads();
+    if (j < S.n) {
+      float* d = static_cast<float*>(S.d);
+      for (int i = bl; i < S.m; i += 8)
+        d[static_cast<int64_t>(i) * S.ldc + j] =
+            static_cast<float>(xb[lane] - x[static_cast<int64_t>(i) * S.ldc + j]);
+    }
+    __syncthreads();
+  }
+}
+
 // Residual partials: partial[item] = sum over the tile's rows of (b_r - a_r . x_bar)^2.
 __global__ __launch_bounds__(256) void k_batch_resid(const BatchSys* sys, const int4* items,
                                                      int32_t nitems, const int32_t* active,
@@ -222,6 +366,18 @@ hipError_t launch_batch_average(int f64, int32_t grid, const BatchSys* sys, cons
                                 int32_t nitems, const int32_t* active, hipStream_t s) {
   if (f64) return hipErrorInvalidValue;
   k_batch_average<float><<<grid, 256, 0, s>>>(sys, items, nitems, active);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_fused(int32_t grid, const BatchSys* sys, const int2* items, int32_t nitems,
+                              const int32_t* active, hipStream_t s) {
+  k_batch_fused<<<grid, 256, 0, s>>>(sys, items, nitems, active);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_fused_combine(int32_t grid, const BatchSys* sys, const int2* items,
+                                      int32_t nitems, const int32_t* active, hipStream_t s) {
+  k_batch_fused_combine<<<grid, 256, 0, s>>>(sys, items, nitems, active);
   return hipGetLastError();
 }
 

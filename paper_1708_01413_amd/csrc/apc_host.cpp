@@ -2018,6 +2018,10 @@ struct apc_batch_s {
   int4* itemsB = nullptr;
   int2* itemsV = nullptr;
   int32_t nA = 0, nB = 0, nV = 0;
+  bool fused = false;                  // single pass: items F (sys, tile), W (sys, 32 columns)
+  int2* itemsF = nullptr;
+  int2* itemsW = nullptr;
+  int32_t nF = 0, nW = 0;
   int32_t* active = nullptr;
   int32_t* item_start = nullptr;
   double* partial = nullptr;
@@ -2033,8 +2037,26 @@ namespace {
 struct BatchPlanItems {
   std::vector<int4> A, B;
   std::vector<int2> V;
+  std::vector<int2> F, W;  // single pass (when every plan has it and rows fit)
+  // Single pass: every system's row tiles (up to kBatchTileRows rows of one
+  // block) as row0[t], nrows[t], blk[t], then first[i] (m + 1), concatenated;
+  // tile_at[s] is system s's offset in that array.
+  std::vector<int32_t> tiles;
+  std::vector<size_t> tile_at;
   std::vector<int32_t> start;
 };
+
+constexpr int kBatchTileRows = 64;
+
+// A batch updates in one pass over every factor when each plan does (k = 1
+// single-pass tiles) and every row fits the batch kernel's registers.
+bool batch_single_pass(const apc_plan* plans, int32_t count) {
+  if (const char* e = std::getenv("APC_FUSED"))
+    if (std::atoi(e) == 0) return false;
+  for (int32_t s = 0; s < count; ++s)
+    if (!plans[s]->fused || plans[s]->L.ldc > kBatchFusedCols) return false;
+  return true;
+}
 
 apc_status batch_items(const apc_plan* plans, int32_t count, BatchPlanItems* it) {
   it->start.push_back(0);
@@ -2049,11 +2071,30 @@ apc_status batch_items(const apc_plan* plans, int32_t count, BatchPlanItems* it)
     for (int64_t j = 0; j < P->n; j += 256) it->V.push_back(make_int2(s, static_cast<int>(j)));
     it->start.push_back(static_cast<int32_t>(it->A.size()));
   }
+  if (batch_single_pass(plans, count)) {
+    for (int32_t s = 0; s < count; ++s) {
+      const apc_plan_s* P = plans[s];
+      std::vector<int32_t> r0, nr, bk, first(1, 0);
+      for (int i = 0; i < P->m; ++i) {
+        const int64_t p = P->off[i + 1] - P->off[i];
+        for (int64_t r = 0; r < p; r += kBatchTileRows) {
+          r0.push_back(static_cast<int32_t>(P->off[i] + r));
+          nr.push_back(static_cast<int32_t>(std::min<int64_t>(kBatchTileRows, p - r)));
+          bk.push_back(i);
+        }
+        first.push_back(static_cast<int32_t>(r0.size()));
+      }
+      it->tile_at.push_back(it->tiles.size());
+      for (auto* v : {&r0, &nr, &bk, &first}) it->tiles.insert(it->tiles.end(), v->begin(), v->end());
+      for (size_t t = 0; t < r0.size(); ++t) it->F.push_back(make_int2(s, static_cast<int>(t)));
+      for (int64_t j = 0; j < P->n; j += 32) it->W.push_back(make_int2(s, static_cast<int>(j)));
+    }
+  }
   return APC_OK;
 }
 
 struct BatchLayout {
-  size_t sys, A, B, V, active, start, partial, relres, total;
+  size_t sys, A, B, V, F, W, T, active, start, partial, relres, total;
 };
 
 BatchLayout batch_layout(int32_t count, const BatchPlanItems& it) {
@@ -2068,6 +2109,9 @@ BatchLayout batch_layout(int32_t count, const BatchPlanItems& it) {
   L.A = take(static_cast<int64_t>(it.A.size()) * sizeof(int4));
   L.B = take(static_cast<int64_t>(it.B.size()) * sizeof(int4));
   L.V = take(static_cast<int64_t>(it.V.size()) * sizeof(int2));
+  L.F = take(static_cast<int64_t>(it.F.size()) * sizeof(int2));
+  L.W = take(static_cast<int64_t>(it.W.size()) * sizeof(int2));
+  L.T = take(static_cast<int64_t>(it.tiles.size()) * 4);
   L.active = take(static_cast<int64_t>(count) * 4);
   L.start = take(static_cast<int64_t>(count + 1) * 4);
   L.partial = take(static_cast<int64_t>(it.A.size()) * 8);
@@ -2090,6 +2134,11 @@ apc_status batch_check_plans(const apc_plan* plans, int32_t count) {
 }
 
 apc_status batch_update(apc_batch_s* B) {
+  if (B->fused) {
+    HIP_TRY(launch_batch_fused(B->gridA, B->sys, B->itemsF, B->nF, B->active, B->stream));
+    HIP_TRY(launch_batch_fused_combine(B->gridV, B->sys, B->itemsW, B->nW, B->active, B->stream));
+    return APC_OK;
+  }
   HIP_TRY(launch_batch_pass_a(0, B->gridA, B->sys, B->itemsA, B->nA, B->active, B->stream));
   HIP_TRY(launch_batch_pass_b(0, B->gridB, B->sys, B->itemsB, B->nB, B->active, B->stream));
   HIP_TRY(launch_batch_average(0, B->gridV, B->sys, B->itemsV, B->nV, B->active, B->stream));
@@ -2143,6 +2192,11 @@ apc_status apc_batch_create(apc_batch* out, const apc_plan* plans, int32_t count
   B->nA = static_cast<int32_t>(it.A.size());
   B->nB = static_cast<int32_t>(it.B.size());
   B->nV = static_cast<int32_t>(it.V.size());
+  B->fused = !it.F.empty();
+  B->itemsF = reinterpret_cast<int2*>(B->ws + L.F);
+  B->itemsW = reinterpret_cast<int2*>(B->ws + L.W);
+  B->nF = static_cast<int32_t>(it.F.size());
+  B->nW = static_cast<int32_t>(it.W.size());
   std::vector<BatchSys> hs(count);
   for (int32_t s = 0; s < count; ++s) {
     apc_plan_s* P = plans[s];
@@ -2164,6 +2218,18 @@ apc_status apc_batch_create(apc_batch* out, const apc_plan* plans, int32_t count
     d.gamma = P->gamma;
     d.eta = P->eta;
     d.bnorm = P->bnorm;
+    if (B->fused) {
+      // The plan's partial-row slice holds at least one FP64 row per 16 rows
+      // of a block, so one FP32 row per tile of up to 64 rows fits.
+      const int32_t* tl = reinterpret_cast<const int32_t*>(B->ws + L.T) + it.tile_at[s];
+      int32_t nt = 0;
+      for (int i = 0; i < P->m; ++i)
+        nt += static_cast<int32_t>((P->off[i + 1] - P->off[i] + kBatchTileRows - 1) / kBatchTileRows);
+      d.tiles = tl;
+      d.tile_first = tl + 3 * nt;
+      d.ntiles = nt;
+      d.part = P->at<float>(P->L.fpart);
+    }
   }
   B->h_active.assign(count, 1);
   hipStream_t st = B->stream;
@@ -2171,11 +2237,15 @@ apc_status apc_batch_create(apc_batch* out, const apc_plan* plans, int32_t count
   HIP_TRY(hipMemcpyAsync(B->itemsA, it.A.data(), it.A.size() * sizeof(int4), hipMemcpyHostToDevice, st));
   HIP_TRY(hipMemcpyAsync(B->itemsB, it.B.data(), it.B.size() * sizeof(int4), hipMemcpyHostToDevice, st));
   HIP_TRY(hipMemcpyAsync(B->itemsV, it.V.data(), it.V.size() * sizeof(int2), hipMemcpyHostToDevice, st));
+  if (B->fused) {
+    HIP_TRY(hipMemcpyAsync(B->ws + L.T, it.tiles.data(), it.tiles.size() * 4, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(B->itemsF, it.F.data(), it.F.size() * sizeof(int2), hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(B->itemsW, it.W.data(), it.W.size() * sizeof(int2), hipMemcpyHostToDevice, st));
+  }
   HIP_TRY(hipMemcpyAsync(B->active, B->h_active.data(), count * 4, hipMemcpyHostToDevice, st));
   HIP_TRY(hipMemcpyAsync(B->item_start, it.start.data(), it.start.size() * 4, hipMemcpyHostToDevice, st));
-  // Persistent grid: time pass A (it only writes the scratch w) for a few
-  // workgroup counts and use the fastest for all three passes, unless the
-  // environment fixes it.
+  // Persistent grid: time the pass over the factors for a few workgroup
+  // counts and use the fastest for every pass, unless the environment fixes it.
   if (const char* e = std::getenv("APC_BATCH_GRID")) {
     const int g = std::max(1, std::atoi(e));
     B->gridA = B->gridB = B->gridV = g;
@@ -2186,10 +2256,15 @@ apc_status apc_batch_create(apc_batch* out, const apc_plan* plans, int32_t count
     const int cands[5] = {256, 512, 1024, 2048, 4096};
     float best = 0.f;
     for (int c : cands) {
-      hipError_t err = launch_batch_pass_a(0, c, B->sys, B->itemsA, B->nA, B->active, st);
+      // The pass that streams the factors (it writes only scratch: w, or the
+      // partial rows).
+      auto stream_pass = [&]() {
+        return B->fused ? launch_batch_fused(c, B->sys, B->itemsF, B->nF, B->active, st)
+                        : launch_batch_pass_a(0, c, B->sys, B->itemsA, B->nA, B->active, st);
+      };
+      hipError_t err = stream_pass();
       if (err == hipSuccess) err = hipEventRecord(e0, st);
-      for (int r = 0; err == hipSuccess && r < 3; ++r)
-        err = launch_batch_pass_a(0, c, B->sys, B->itemsA, B->nA, B->active, st);
+      for (int r = 0; err == hipSuccess && r < 3; ++r) err = stream_pass();
       if (err == hipSuccess) err = hipEventRecord(e1, st);
       if (err == hipSuccess) err = hipEventSynchronize(e1);
       float ms = 0.f;
@@ -2298,15 +2373,16 @@ apc_status apc_batch_get_launch(apc_batch b, int32_t* grid, int32_t* items_a, in
                                 int32_t* items_avg, float* tuned_us) {
   if (!b) return fail(APC_EINVAL, "batch is NULL");
   if (grid) *grid = b->gridA;
-  if (items_a) *items_a = b->nA;
-  if (items_b) *items_b = b->nB;
-  if (items_avg) *items_avg = b->nV;
+  if (items_a) *items_a = b->fused ? b->nF : b->nA;
+  if (items_b) *items_b = b->fused ? 0 : b->nB;
+  if (items_avg) *items_avg = b->fused ? b->nW : b->nV;
   if (tuned_us) *tuned_us = b->tuned_us;
   return APC_OK;
 }
 
 void apc_batch_destroy(apc_batch b) {
   if (!b) return;
+  (void)hipStreamSynchronize(b->stream);  // no captured graph may still be running
   for (auto& kv : b->graphs) {
     (void)hipGraphExecDestroy(kv.second.second);
     (void)hipGraphDestroy(kv.second.first);

@@ -340,9 +340,25 @@ struct BatchSys {
   double gamma;
   double eta;
   double bnorm;
+  // Single-pass update: the system's row tiles in the batch (row0, nrows, blk
+  // at tiles, tiles + ntiles, tiles + 2 ntiles; block i's tiles from
+  // tile_first[i]) and one FP32 partial row of ldc entries per tile (in the
+  // plan's partial-row slice).
+  const int32_t* tiles = nullptr;
+  const int32_t* tile_first = nullptr;
+  int32_t ntiles = 0;
+  float* part = nullptr;
 };
 // Items: pass A (sys, first row, rows <= 8, block); pass B (sys, block, first
 // column of a 256-column slab, 0); average (sys, first column of 256).
+// Single pass (rows up to kBatchFusedCols wide): items (sys, tile) write the
+// tile's partial row; items (sys, first of 32 columns) then apply the x_i
+// update, the average and the next differences, as k = 1 single-system plans do.
+constexpr int kBatchFusedCols = 1024;
+hipError_t launch_batch_fused(int32_t grid, const BatchSys* sys, const int2* items, int32_t nitems,
+                              const int32_t* active, hipStream_t s);
+hipError_t launch_batch_fused_combine(int32_t grid, const BatchSys* sys, const int2* items,
+                                      int32_t nitems, const int32_t* active, hipStream_t s);
 hipError_t launch_batch_pass_a(int f64, int32_t grid, const BatchSys* sys, const int4* items,
                                int32_t nitems, const int32_t* active, hipStream_t s);
 hipError_t launch_batch_pass_b(int f64, int32_t grid, const BatchSys* sys, const int4* items,

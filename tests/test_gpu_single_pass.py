@@ -166,3 +166,75 @@ def test_wide_fp64_rows_take_two_passes():
     d = dev(gpu_traj(plan, T), ref, S.xstar)
     say(f"case: wide FP64 rows n={n}, two passes: max dev {d:.3e}")
     assert d <= TOL["f64"]
+
+
+def _plans(systems, stream):
+    apc = _apc()
+    torch = _torch()
+    plans, keep = [], []
+    for S in systems:
+        A = torch.from_numpy(S.A).cuda()
+        b = torch.from_numpy(S.B).cuda()
+        keep.append((A, b))
+        g, e, _ = O.optimal_params(*O.spectrum(S.A, S.off))
+        plans.append(apc.Plan(A, b, S.off, "f32", gamma=g, eta=e, stream=stream))
+    return plans, keep
+
+
+def test_batch_single_pass_matches_two_pass_and_oracle(monkeypatch):
+    """A batch of plans that all update in one pass runs one pass over every factor
+    (no pass-B items); the same plans batched with APC_FUSED=0 run two passes.  Both
+    follow the oracle to the FP32 bar and each other to FP32 rounding."""
+    apc = _apc()
+    torch = _torch()
+    systems = synth.many_small_systems(count=12, seed=84, lo=64, hi=1024)
+    stream = torch.cuda.Stream()
+    p1, k1 = _plans(systems, stream)
+    b1 = apc.Batch(p1)
+    monkeypatch.setenv("APC_FUSED", "0")
+    p2, k2 = _plans(systems, stream)
+    b2 = apc.Batch(p2)
+    monkeypatch.delenv("APC_FUSED")
+    l1, l2 = b1.launch(), b2.launch()
+    say(f"case: batch single pass {l1}, two passes {l2}, n = {[S.n for S in systems]}")
+    assert l1["items_b"] == 0 and l2["items_b"] > 0
+    T = 30
+    b1.iterate(T, graph=True)
+    b2.iterate(T)
+    stream.synchronize()
+    worst_o, worst_2 = 0.0, 0.0
+    for S, p, q in zip(systems, p1, p2):
+        g, e = p.params()["gamma"], p.params()["eta"]
+        ref = O.apc_run(S.A, S.B, S.off, T, g, e)["xbar"][:, 0]
+        x = p.xbar().cpu().numpy()
+        xs = np.linalg.norm(S.xstar)
+        worst_o = max(worst_o, np.linalg.norm(x - ref) / xs)
+        worst_2 = max(worst_2, np.linalg.norm(x - q.xbar().cpu().numpy()) / xs)
+    say(f"max dev vs oracle {worst_o:.2e}, vs two-pass batch {worst_2:.2e}")
+    assert worst_o <= TOL["f32"]
+    assert worst_2 <= 1e-6
+    b1.close()
+    b2.close()
+
+
+def test_batch_with_wide_rows_takes_two_passes():
+    """A system with rows wider than 1024 puts the whole batch on the two-pass kernels."""
+    apc = _apc()
+    torch = _torch()
+    systems = synth.many_small_systems(count=3, seed=85, lo=64, hi=512)
+    systems.append(synth.gaussian_system(1100, 1100, 4, seed=86, shift=2.0,
+                                         scale=1.0 / math.sqrt(1100)))
+    stream = torch.cuda.Stream()
+    plans, keep = _plans(systems, stream)
+    batch = apc.Batch(plans)
+    launch = batch.launch()
+    say(f"case: batch with a 1100-wide system: {launch}")
+    assert launch["items_b"] > 0
+    T = 20
+    batch.iterate(T)
+    stream.synchronize()
+    for S, p in zip(systems, plans):
+        g, e = p.params()["gamma"], p.params()["eta"]
+        ref = O.apc_run(S.A, S.B, S.off, T, g, e)["xbar"][:, 0]
+        assert np.linalg.norm(p.xbar().cpu().numpy() - ref) / np.linalg.norm(S.xstar) <= TOL["f32"]
+    batch.close()
