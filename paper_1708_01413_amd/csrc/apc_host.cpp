@@ -65,7 +65,7 @@ int64_t round_up(int64_t v, int64_t a) { return (v + a - 1) / a * a; }
 struct Layout {
   int64_t ldc = 0, kmax = 0, S = 0;
   int32_t ntiles_a = 0, ntiles_g = 0, ntiles_t = 0, nparts = 0;
-  int32_t ntiles_fmax = 0;  // single-pass row tiles the workspace holds (k = 1)
+  int32_t ntiles_fmax = 0;  // single-pass row tiles the workspace holds
   size_t tiles_f = 0, fpart = 0, v32 = 0;
   // k-RHS path: rows/K padding of its operands (N and n rounded up to kTnPad)
   int64_t Np = 0, np = 0;
@@ -235,7 +235,9 @@ Layout make_layout(int64_t N, int64_t n, const int64_t* off, int32_t m, int32_t 
   L.ssq = take(sumsq_parts() * d);
   L.tiles_a = take(3 * max_tiles_a * 4);
   // Single-pass k = 1 iteration: its tile lists and one partial row per tile.
-  if (!gemm && k == 1) {
+  // Also for FP32 / bf16 k-RHS plans, whose eigenvalue estimate runs the
+  // FP32 single-pass kernel on a temporary FP32 copy of the factor.
+  if ((!gemm && k == 1) || (gemm && prec != APC_F64)) {
     int64_t nf = 0;
     for (int i = 0; i < m; ++i) nf += (off[i + 1] - off[i] + kFusedMinRows - 1) / kFusedMinRows;
     L.ntiles_fmax = static_cast<int32_t>(nf);
@@ -903,7 +905,7 @@ apc_status normal_matvec(apc_plan_s* P, const NormalOp& op, const double* v, dou
   // rows): the operator then carries a relative error ~1e-7, far below the
   // eigenvalue estimate's stopping tolerances (3e-4 and 1e-2).
   const int cpt64 = fused_cpt(L.ldc, 8);
-  if (P->fused && (op.f32 || cpt64 > 0)) {
+  if (P->ntiles_f > 0 && (op.f32 || cpt64 > 0)) {
     double* part = P->at<double>(L.fpart);
     const int32_t remap = P->xcd_remap == 1 ? 1 : 0;
     if (op.f32) {
@@ -1069,7 +1071,7 @@ apc_status lanczos(apc_plan_s* P, const NormalOp& op, double cap, double* lo_out
   };
   // The FP32 operator reads the vector's FP32 copy, which the normalisation
   // writes for the next step.
-  float* v32 = op.f32 && P->fused ? P->at<float>(P->L.v32) : nullptr;
+  float* v32 = op.f32 && P->ntiles_f > 0 ? P->at<float>(P->L.v32) : nullptr;
   if (v32) HIP_TRY(launch_cast_f32(V, v32, ldc, P->stream));
   bool done = false;
   int steps = 0, pending = 0;
@@ -1183,7 +1185,7 @@ apc_status setup_impl(apc_plan_s* P, const Tiles& T) {
   HIP_TRY(hipMemcpyAsync(P->at<int32_t>(L.tiles_a), ta.data(), ta.size() * 4, hipMemcpyHostToDevice, st));
   HIP_TRY(hipMemcpyAsync(P->at<int32_t>(L.tiles_g), T.g.data(), T.g.size() * 4, hipMemcpyHostToDevice, st));
   std::vector<int32_t> tf;
-  if (P->fused) {
+  if (P->ntiles_f > 0) {
     tf.insert(tf.end(), T.f_row0.begin(), T.f_row0.end());
     tf.insert(tf.end(), T.f_nrows.begin(), T.f_nrows.end());
     tf.insert(tf.end(), T.f_blk.begin(), T.f_blk.end());
@@ -1277,6 +1279,18 @@ apc_status setup_impl(apc_plan_s* P, const Tiles& T) {
   P->bnorm = std::sqrt(scal[1]);
 
   if (P->gemm) {
+    // FP32 / bf16: the eigenvalue estimate through an FP32 copy of the factor
+    // in the slice the padded copy of A takes later (one single pass over
+    // 4 bytes per entry instead of two passes over 8).
+    if (P->ntiles_f > 0 && (std::isnan(P->gamma) || std::isnan(P->eta))) {
+      float* c32 = reinterpret_cast<float*>(P->ws + L.Apad);
+      HIP_TRY(launch_cast_f32(Ca, c32, N * ldc, st));
+      double lo = 0, hi = 0;
+      ST_TRY(lanczos(P, NormalOp{c32, true, 1.0 / m}, 1.0, &lo, &hi, &P->lanczos_steps));
+      P->mu_min = lo;
+      P->mu_max = hi;
+      optimum(lo, hi, &P->gamma, &P->eta, &P->rho);
+    }
     // Factor copies for the matrix cores (C and C^T in the iteration's
     // precision, C^T in FP64), the padded FP64 copy of A, zeroed operands.
     const int64_t Np = L.Np, np = L.np;
@@ -1315,7 +1329,8 @@ apc_status setup_impl(apc_plan_s* P, const Tiles& T) {
     if (P->prec == APC_F32 && !mfma) HIP_TRY(launch_cast_f32(Ca, P->at<float>(L.C32), N * ldc, st));
   }
 
-  // Parameters: caller's, or Theorem 1's optimum from the estimated spectrum.
+  // Parameters: caller's, or Theorem 1's optimum from the estimated spectrum
+  // (k-RHS FP32 / bf16 plans estimated it right after the QR).
   if (std::isnan(P->gamma) || std::isnan(P->eta)) {
     double lo = 0, hi = 0;
     ST_TRY(lanczos(P, x_operator(P), 1.0, &lo, &hi, &P->lanczos_steps));
@@ -1386,7 +1401,16 @@ apc_status apc_setup(apc_plan* out, const double* A, int64_t lda, const double* 
   const int cpt = fused_cpt(round_up(n, kLdAlign), elem);
   bool fused = !uses_gemm(k, precision) && k == 1 && cpt > 0;
   if (const char* e = std::getenv("APC_FUSED")) fused = fused && std::atoi(e) != 0;
+  // FP32 / bf16 k-RHS plans: single-pass tiles for the eigenvalue operator
+  // through an FP32 copy of the factor.
+  const int cpt32 = fused_cpt(round_up(n, kLdAlign), 4);
+  const bool op_tiles = uses_gemm(k, precision) && base_prec != APC_F64 && cpt32 > 0 &&
+                        fused_shape_ok(4, 4, cpt32, 1);
   int32_t fused_rows = 0, fused_g = 0;
+  if (op_tiles) {
+    fused_shape(N, 4, cpt32, &fused_rows, &fused_g);
+    build_fused_tiles(off, m, fused_rows, &T);
+  }
   if (fused) {
     fused_shape(N, elem, cpt, &fused_rows, &fused_g);
     if (const char* e = std::getenv("APC_FUSED_ROWS")) {
