@@ -157,8 +157,11 @@ __global__ __launch_bounds__(256) void k_tn(TnArgs a) {
       if (step < nsteps) {  // uniform across the workgroup
         const int buf = step & 1;
         const bool more = step + 1 < nsteps;
-        if (step + PF < nsteps) load_m(mr[(i + PF) % D], step + PF);
+        // V's next step is loaded before M's step + PF: loads complete in
+        // order, so the wait for V at the end of this step then does not also
+        // wait for the newest M loads, which keep PF steps in flight.
         if (more) load_v(step + 1);
+        if (step + PF < nsteps) load_m(mr[(i + PF) % D], step + PF);
 #pragma unroll
         for (int p = 0; p < 4; ++p) {
           u32x4 bf[NCT];
