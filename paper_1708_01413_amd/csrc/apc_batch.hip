@@ -209,7 +209,7 @@ __device__ inline void batch_tile_pass(const BatchSys& S, int t, float (&red)[4]
       for (int c = 0; c < CPL; ++c)
         s += (row[q][c].x * dv[c][0] + row[q][c].y * dv[c][1]) +
              (row[q][c].z * dv[c][2] + row[q][c].w * dv[c][3]);
-      s = wsum64(s);
+      s = wave_sum_dpp(s);
 #pragma unroll
       for (int c = 0; c < CPL; ++c) {
         acc[c][0] = fmaf(s, row[q][c].x, acc[c][0]);

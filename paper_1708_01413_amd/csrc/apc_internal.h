@@ -32,6 +32,50 @@ TimedLaunch& pending_timing();
 
 
 constexpr int kThreads = 256;       // threads per workgroup for streaming kernels
+
+// FP32 wave sum without LDS: DPP within each 16-lane row (pairs, quads, then
+// rotations by 4 and 8 lanes give every lane its row's sum), then the four row
+// sums read as scalars.  The result is uniform across the wave.
+template <int CTRL>
+__device__ inline float dpp_f32(float x) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, 0xf, 0xf, false));
+}
+__device__ inline float wave_sum_dpp(float v) {
+  v += dpp_f32<0xB1>(v);   // quad_perm(1, 0, 3, 2)
+  v += dpp_f32<0x4E>(v);   // quad_perm(2, 3, 0, 1)
+  v += dpp_f32<0x124>(v);  // row_ror:4
+  v += dpp_f32<0x128>(v);  // row_ror:8
+  const float r0 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 0));
+  const float r1 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 16));
+  const float r2 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 32));
+  const float r3 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 48));
+  return (r0 + r1) + (r2 + r3);
+}
+// The same for FP64: each DPP move carries the two 32-bit halves.
+template <int CTRL>
+__device__ inline double dpp_f64(double x) {
+  const long long b = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_update_dpp(0, static_cast<int>(b), CTRL, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, static_cast<int>(b >> 32), CTRL, 0xf, 0xf, false);
+  return __longlong_as_double((static_cast<long long>(hi) << 32) |
+                              static_cast<long long>(static_cast<unsigned>(lo)));
+}
+__device__ inline double lane_f64(double x, int l) {
+  const long long b = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_readlane(static_cast<int>(b), l);
+  const int hi = __builtin_amdgcn_readlane(static_cast<int>(b >> 32), l);
+  return __longlong_as_double((static_cast<long long>(hi) << 32) |
+                              static_cast<long long>(static_cast<unsigned>(lo)));
+}
+__device__ inline double wave_sum_dpp(double v) {
+  v += dpp_f64<0xB1>(v);
+  v += dpp_f64<0x4E>(v);
+  v += dpp_f64<0x124>(v);
+  v += dpp_f64<0x128>(v);
+  return (lane_f64(v, 0) + lane_f64(v, 16)) + (lane_f64(v, 32) + lane_f64(v, 48));
+}
+
+
 constexpr int kRowTile = 16;        // rows per pass-A workgroup
 constexpr int kLdAlign = 64;        // padded row stride of the internal factor (elements)
 constexpr int kGramTile = 64;       // FP64 setup GEMM tile edge

@@ -479,7 +479,7 @@ __global__ __launch_bounds__(kThreads) void k_fused(FusedArgs<TQ, TA> a) {
     }
 #pragma unroll
     for (int r = 0; r < G; ++r) {
-      const TA v = wave_sum(sum[r]);
+      const TA v = wave_sum_dpp(sum[r]);
       if (lane == 0) red[slot][wv][r] = v;
     }
     __syncthreads();
