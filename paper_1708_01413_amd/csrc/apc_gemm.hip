@@ -658,83 +658,117 @@ __global__ __launch_bounds__(256) void k_gram_mfma(const double* C, int64_t ldc,
       }
 }
 
-// Out_i[r][c] = sum_{k <= r} Linv_i[r][k] In_i[k][c].  One workgroup per
-// (block i, 64-column slab) covers all p_i rows, in groups of 256: wave w owns
-// the 16-row tiles 4 j + w (j < 4) of the group, so the triangular work is
-// spread evenly.  In's K index runs along its rows: each 32-row chunk of the
-// slab is staged in LDS once and read by every row tile (its B fragments),
-// while Linv_i (zero above the diagonal) is read from L2 element-wise; chunks
-// entirely above a row tile's diagonal are skipped.
-// Two workgroups per CU: without the bound the FP32 output's extra registers
-// left room for one, and the product took 2.35 ms instead of 1.6 at 16384 x 8192.
-constexpr int kTrmmRowsPerGroup = 256;
-__global__ __launch_bounds__(256, 2) void k_trmm_mfma(const double* In, double* Out, int64_t ldc,
-                                                   const int64_t* off, int32_t nslab, int32_t m,
-                                                   const int64_t* goff, const double* Linv,
-                                                   float* Out32) {
-  const int q = xcd_contiguous(static_cast<int>(blockIdx.x), m * nslab);
-  if (q >= m * nslab) return;
-  const int blk = q / nslab;
-  const int slab = q % nslab;
+// Out_i = Linv_i In_i as 128 x 128 output tiles on the FP64 matrix cores,
+// one workgroup per (block, 128-row tile, 128-column tile).  K (the block's
+// rows, cut at the tile's last row since Linv is lower triangular) goes in
+// chunks of 32: both operands are staged in LDS K-major -- As[k][r] =
+// Linv[R0 + r][kc + k], Bs[k][c] = In[kc + k][C0 + c] -- and each of the four
+// waves multiplies its 64 x 64 quadrant as 4 x 4 MFMA 16x16x4 tiles.  The next
+// chunk is loaded into registers while the current one is multiplied.  Row
+// tiles entirely above the chunk's diagonal are skipped.  The LDS row stride
+// (144 doubles, 1152 bytes) puts the two half-waves of a fragment read on
+// different banks.
+constexpr int kTT = 128;
+constexpr int kTK = 32;
+constexpr int kTS = kTT + 16;
+__global__ __launch_bounds__(256, 2) void k_trmm_lds(const double* In, double* Out, int64_t ldc,
+                                                  const int64_t* off, int32_t m, int32_t nrt,
+                                                  int32_t nct, const int64_t* goff,
+                                                  const double* Linv, float* Out32) {
+  const int total = m * nrt * nct;
+  const int q = xcd_contiguous(static_cast<int>(blockIdx.x), total);
+  if (q >= total) return;
+  const int blk = q / (nrt * nct);
+  const int rem = q - blk * nrt * nct;
+  const int rt = rem / nct, ct = rem - rt * nct;
   const int64_t r0 = off[blk];
   const int p = static_cast<int>(off[blk + 1] - r0);
+  const int R0 = rt * kTT;
+  if (R0 >= p) return;  // uniform per workgroup
+  const int64_t C0 = static_cast<int64_t>(ct) * kTT;
   const double* Lb = Linv + goff[blk];
-  const int64_t c0 = static_cast<int64_t>(slab) * 64;
+  const int kend = min(p, R0 + kTT);
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int li = lane & 15, g = lane >> 4;
-  const double* inb = In + r0 * ldc + c0;
-  __shared__ double sB[32][65];
-  for (int grp = 0; grp * kTrmmRowsPerGroup < p; ++grp) {
-    f64x4 acc[4][4];
+  const int wr = wv >> 1, wc = wv & 1;
+  __shared__ __align__(16) double As[kTK][kTS];
+  __shared__ __align__(16) double Bs[kTK][kTS];
+
+  // Staging: A -- thread t takes row t / 2 and 16 consecutive k (scalar loads:
+  // Linv rows have stride p, which may be odd); B -- thread t takes row t / 8
+  // of the chunk and 16 consecutive columns (16-byte loads: ldc is a multiple
+  // of 64).  Entries past the block, past kend or past ldc are zero.
+  const int ar = threadIdx.x >> 1, ak = (threadIdx.x & 1) * 16;
+  const int bk = threadIdx.x >> 3, bc = (threadIdx.x & 7) * 16;
+  const bool a_row_ok = R0 + ar < p;
+  const bool b_col_ok = C0 + bc < ldc;
+  double pa[16];
+  f64x2 pb[8];
+  auto load_chunk = [&](int kc) {
 #pragma unroll
-    for (int jt = 0; jt < 4; ++jt)
+    for (int j = 0; j < 16; ++j) {
+      const int k = kc + ak + j;
+      pa[j] = (a_row_ok && k < kend) ? Lb[static_cast<int64_t>(R0 + ar) * p + k] : 0.0;
+    }
+    const bool brow = kc + bk < kend && b_col_ok;
+    const double* src = In + (r0 + kc + bk) * ldc + C0 + bc;
 #pragma unroll
-      for (int u = 0; u < 4; ++u) acc[jt][u] = f64x4{};
-    const int kend = min(p, (grp + 1) * kTrmmRowsPerGroup);
-    for (int kc = 0; kc < kend; kc += 32) {
-      __syncthreads();
-      for (int e = threadIdx.x; e < 32 * 64; e += 256) {
-        const int r = e >> 6, c = e & 63;
-        sB[r][c] = kc + r < kend ? inb[static_cast<int64_t>(kc + r) * ldc + c] : 0.0;
-      }
-      __syncthreads();
-      double bf[4][8];
+    for (int j = 0; j < 8; ++j)
+      pb[j] = brow ? *reinterpret_cast<const f64x2*>(src + 2 * j) : f64x2{0.0, 0.0};
+  };
+  auto store_chunk = [&]() {
 #pragma unroll
-      for (int u = 0; u < 4; ++u)
+    for (int j = 0; j < 16; ++j) As[ak + j][ar] = pa[j];
 #pragma unroll
-        for (int j = 0; j < 8; ++j) bf[u][j] = sB[8 * g + j][16 * u + li];
+    for (int j = 0; j < 8; ++j) *reinterpret_cast<f64x2*>(&Bs[bk][bc + 2 * j]) = pb[j];
+  };
+
+  f64x4 acc[4][4];
 #pragma unroll
-      for (int jt = 0; jt < 4; ++jt) {
-        const int rt = grp * (kTrmmRowsPerGroup / 16) + 4 * jt + wv;
-        if (16 * rt >= p || kc >= 16 * (rt + 1)) continue;  // uniform per wave
-        const int row = 16 * rt + li;
-        double a[8];
+  for (int t = 0; t < 4; ++t)
 #pragma unroll
-        for (int j = 0; j < 8; ++j) {
-          const int k = kc + 8 * g + j;
-          a[j] = (row < p && k < p) ? Lb[static_cast<int64_t>(row) * p + k] : 0.0;
-        }
+    for (int u = 0; u < 4; ++u) acc[t][u] = f64x4{};
+  load_chunk(0);
+  store_chunk();
+  __syncthreads();
+  for (int kc = 0; kc < kend; kc += kTK) {
+    const bool more = kc + kTK < kend;
+    if (more) load_chunk(kc + kTK);
 #pragma unroll
-        for (int j = 0; j < 8; ++j)
+    for (int kk = 0; kk < kTK / 4; ++kk) {
+      const int k = 4 * kk + g;
+      double b[4];
 #pragma unroll
-          for (int u = 0; u < 4; ++u)
-            acc[jt][u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[j], bf[u][j], acc[jt][u], 0, 0, 0);
+      for (int u = 0; u < 4; ++u) b[u] = Bs[k][wc * 64 + u * 16 + li];
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        // Rows of this 16-row tile all lie above column kc + 4 kk: zero.
+        if (kc + 4 * kk > R0 + wr * 64 + t * 16 + 15) continue;  // uniform per wave
+        const double a = As[k][wr * 64 + t * 16 + li];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+          acc[t][u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b[u], acc[t][u], 0, 0, 0);
       }
     }
-#pragma unroll
-    for (int jt = 0; jt < 4; ++jt)
-#pragma unroll
-      for (int u = 0; u < 4; ++u)
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const int row = 16 * (grp * (kTrmmRowsPerGroup / 16) + 4 * jt + wv) + g + 4 * q;
-          if (row < p) {
-            const int64_t o = (r0 + row) * ldc + c0 + 16 * u + li;
-            Out[o] = acc[jt][u][q];
-            if (Out32) Out32[o] = static_cast<float>(acc[jt][u][q]);
-          }
-        }
+    __syncthreads();
+    if (more) store_chunk();
+    __syncthreads();
   }
+  // acc[t][u][q] = D[g + 4 q][li] of the 16 x 16 tile (t, u).
+#pragma unroll
+  for (int t = 0; t < 4; ++t)
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int qq = 0; qq < 4; ++qq) {
+        const int row = R0 + wr * 64 + t * 16 + g + 4 * qq;
+        const int64_t col = C0 + wc * 64 + u * 16 + li;
+        if (row < p && col < ldc) {
+          const int64_t o = (r0 + row) * ldc + col;
+          Out[o] = acc[t][u][qq];
+          if (Out32) Out32[o] = static_cast<float>(acc[t][u][qq]);
+        }
+      }
 }
 
 }  // namespace
@@ -749,16 +783,17 @@ hipError_t launch_gram_mfma(const double* C, int64_t ldc, const int64_t* off,
   return hipGetLastError();
 }
 
-hipError_t launch_trmm_mfma(const double* In, double* Out, int64_t ldc, const int64_t* off,
-                            int32_t m, const int64_t* goff, const double* Linv, float* out32,
-                            hipStream_t s) {
+hipError_t launch_trmm_lds(const double* In, double* Out, int64_t ldc, const int64_t* off,
+                           int32_t m, int64_t pmax, const int64_t* goff, const double* Linv,
+                           float* out32, hipStream_t s) {
   if (m <= 0) return hipSuccess;
   if (ldc % 64 != 0) return hipErrorInvalidValue;
-  const int32_t nslab = static_cast<int32_t>(ldc / 64);
-  const int64_t items = static_cast<int64_t>(m) * nslab;
+  const int64_t nrt = (pmax + kTT - 1) / kTT, nct = (ldc + kTT - 1) / kTT;
+  const int64_t items = static_cast<int64_t>(m) * nrt * nct;
   if (items > std::numeric_limits<int32_t>::max() / 2) return hipErrorInvalidValue;
   const unsigned grid = static_cast<unsigned>((items + kXcds - 1) / kXcds * kXcds);
-  k_trmm_mfma<<<grid, 256, 0, s>>>(In, Out, ldc, off, nslab, m, goff, Linv, out32);
+  k_trmm_lds<<<grid, 256, 0, s>>>(In, Out, ldc, off, m, static_cast<int32_t>(nrt),
+                                  static_cast<int32_t>(nct), goff, Linv, out32);
   return hipGetLastError();
 }
 

@@ -1250,7 +1250,8 @@ apc_status setup_impl(apc_plan_s* P, const Tiles& T) {
     // An FP32 k = 1 plan's factor copy is written by the same launch.
     float* dst32 = (P->prec == APC_F32 && !P->gemm) ? P->at<float>(L.C32) : nullptr;
     if (mfma)
-      HIP_TRY(launch_trmm_mfma(src, dst, ldc, P->doff(), m, P->at<int64_t>(L.goff), Li, dst32, st));
+      HIP_TRY(launch_trmm_lds(src, dst, ldc, P->doff(), m, P->pmax, P->at<int64_t>(L.goff), Li,
+                              dst32, st));
     else
       HIP_TRY(launch_trmm(src, dst, ldc, P->doff(), P->at<int32_t>(L.tiles_t), L.ntiles_t,
                           P->at<int64_t>(L.goff), Li, st));

@@ -461,15 +461,18 @@ hipError_t launch_gram(const double* C, int64_t ldc, const int64_t* off, const i
 // the rank test).
 hipError_t launch_chol_inv(const int64_t* off, const int64_t* goff, int32_t m, int64_t pmax,
                            double* G, double* Linv, int* flags, double rank_tol, hipStream_t s);
-// Out_i = Linv_i In_i for every block (tiles: (blk, ta, tc)).
-// The same two products on the FP64 matrix cores (ldc a multiple of 32).
+// G_i = C_i C_i^T on the FP64 matrix cores (ldc a multiple of 32).
 hipError_t launch_gram_mfma(const double* C, int64_t ldc, const int64_t* off,
                             const int32_t* tiles, int32_t ntiles, const int64_t* goff, double* G,
                             hipStream_t s);
-// out32 (optional, same layout as Out): the result also rounded to FP32.
-hipError_t launch_trmm_mfma(const double* In, double* Out, int64_t ldc, const int64_t* off,
-                            int32_t m, const int64_t* goff, const double* Linv, float* out32,
-                            hipStream_t s);
+// Out_i = Linv_i In_i on the FP64 matrix cores as 128 x 128 tiles with both
+// operands staged in LDS (ldc a multiple of 64, pmax the largest block's rows,
+// In and Out distinct).  out32 (optional, same layout as Out): the result also
+// rounded to FP32.
+hipError_t launch_trmm_lds(const double* In, double* Out, int64_t ldc, const int64_t* off,
+                           int32_t m, int64_t pmax, const int64_t* goff, const double* Linv,
+                           float* out32, hipStream_t s);
+// Out_i = Linv_i In_i for every block on the vector units (tiles: (blk, ta, tc)).
 hipError_t launch_trmm(const double* In, double* Out, int64_t ldc, const int64_t* off,
                        const int32_t* tiles, int32_t ntiles, const int64_t* goff,
                        const double* Linv, hipStream_t s);
