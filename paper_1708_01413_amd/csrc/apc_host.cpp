@@ -55,6 +55,7 @@ apc_status fail(apc_status st, const char* fmt, ...) {
 
 constexpr int64_t kAlign = 256;
 constexpr int kLanczosMax = 1024;   // Lanczos steps cap (full reorthogonalisation)
+static_assert(kLanczosMax <= kLzMaxRows, "a Lanczos step reorthogonalises against at most kLzMaxRows rows");
 constexpr int kLanczosCheck = 4;    // steps between convergence checks (host syncs)
 constexpr int kAnchorEvery = 16;    // default anchor spacing of the FP32 k-RHS iteration
 
@@ -71,7 +72,7 @@ struct Layout {
   int64_t Np = 0, np = 0;
   size_t Cq, CqT, C64T, Apad, yq, Wq, tnpart, x0, ys, c64p, Xs, Rb, cw, Linv2, ssq;
   size_t C64p, yref, uref, W64;  // FP64 anchor of the FP32 / bf16 k-RHS iteration
-  size_t C64a, C64b, C32, x, xbar, dv, w, ca, cb, Y, vtmp, V, h, h2, alpha, beta, G, Linv, flags, scal, partial, tiles_a, tiles_g, tiles_t, doff, goff, total;
+  size_t C64a, C64b, C32, x, xbar, dv, w, ca, cb, Y, vtmp, V, h, alpha, beta, G, Linv, flags, scal, partial, tiles_a, tiles_g, tiles_t, doff, goff, total;
 };
 
 struct Tiles {
@@ -194,8 +195,9 @@ Layout make_layout(int64_t N, int64_t n, const int64_t* off, int32_t m, int32_t 
   L.Y = take(m * L.ldc * d);
   L.vtmp = take(L.ldc * d);
   L.V = take((L.kmax + 1) * L.ldc * d);
-  L.h = take(kMaxSplit * (L.kmax + 1) * d);
-  L.h2 = take(kMaxSplit * (L.kmax + 1) * d);
+  // Lanczos step: two passes' dot partials per column slab, then the slab norms.
+  const int64_t nlz = (L.ldc + kLzSlab - 1) / kLzSlab;
+  L.h = take((2 * nlz * (L.kmax + 1) + nlz) * d);
   L.alpha = take((L.kmax + 1) * d);
   L.beta = take((L.kmax + 1) * d);
   L.G = take(L.S * d);
@@ -896,8 +898,18 @@ NormalOp x_operator(const apc_plan_s* P) {
 
 // out = op(v), FP64 vectors and accumulation.  v32_ready: the plan's FP32
 // operator vector already holds v rounded to FP32.
+// The single pass's partial rows, left for the caller to sum (the Lanczos step
+// sums them in its first launch).
+struct DeferredSum {
+  const void* part = nullptr;
+  bool f32 = false;
+  int64_t ldp = 0;
+  int32_t ntiles = 0;
+  double scale = 1.0;
+};
+
 apc_status normal_matvec(apc_plan_s* P, const NormalOp& op, const double* v, double* out,
-                         bool v32_ready = false) {
+                         bool v32_ready = false, DeferredSum* defer = nullptr) {
   const Layout& L = P->L;
   // One pass over C (the plan's single-pass tiles, v shared by every tile),
   // then the FP64 sum of the tiles' partial rows.  Through the FP32 factor the
@@ -915,12 +927,20 @@ apc_status normal_matvec(apc_plan_s* P, const NormalOp& op, const double* v, dou
       FusedArgs<float, float> a{static_cast<const float*>(op.C), L.ldc, P->n, P->tf(0), P->tf(1),
                                 P->tf(2), P->ntiles_f, v32, 0, part32, L.ldc, remap};
       HIP_TRY(launch_fused_f32(a, P->fused_g, P->stream));
+      if (defer) {
+        *defer = DeferredSum{part32, true, L.ldc, P->ntiles_f, op.scale};
+        return APC_OK;
+      }
       HIP_TRY(launch_fused_sum_f32(part32, L.ldc, P->ntiles_f, L.ldc, op.scale, out, P->stream));
       return APC_OK;
     } else {
       FusedArgs<double, double> a{static_cast<const double*>(op.C), L.ldc, P->n, P->tf(0),
                                   P->tf(1), P->tf(2), P->ntiles_f, v, 0, part, L.ldc, remap};
       HIP_TRY(launch_fused_f64(a, cpt64 >= 16 ? 1 : 2, P->stream));
+    }
+    if (defer) {
+      *defer = DeferredSum{part, false, L.ldc, P->ntiles_f, op.scale};
+      return APC_OK;
     }
     HIP_TRY(launch_fused_sum(part, L.ldc, P->ntiles_f, L.ldc, op.scale, out, P->stream));
     return APC_OK;
@@ -974,30 +994,12 @@ apc_status lanczos(apc_plan_s* P, const NormalOp& op, double cap, double* lo_out
   const int64_t hstride = P->L.kmax + 1;
   double* V = P->at<double>(P->L.V);
   double* vt = P->at<double>(P->L.vtmp);
-  double* h = P->at<double>(P->L.h);
-  double* h2 = P->at<double>(P->L.h2);
+  double* hp = P->at<double>(P->L.h);
   double* al = P->at<double>(P->L.alpha);
   double* be = P->at<double>(P->L.beta);
 
-  std::vector<double> v0(ldc, 0.0);
-  double nrm = 0.0;
-  for (int64_t j = 0; j < n; ++j) {
-    const uint64_t r = splitmix64(0x5eedull * 1000003ull + static_cast<uint64_t>(j));
-    v0[j] = (static_cast<double>(r >> 11) * (1.0 / 9007199254740992.0)) - 0.5;
-    nrm += v0[j] * v0[j];
-  }
-  nrm = std::sqrt(nrm);
-  for (int64_t j = 0; j < n; ++j) v0[j] /= nrm;
-  HIP_TRY(hipMemcpyAsync(V, v0.data(), ldc * sizeof(double), hipMemcpyHostToDevice, P->stream));
-  HIP_TRY(hipStreamSynchronize(P->stream));
-
-  // Reorthogonalisation GEMVs against V (j+1 rows) use column splits so that
-  // enough workgroups run even for a few rows.
-  const int64_t chunk = rowdot_chunk<double>();
-  const int64_t want = std::min<int64_t>(kMaxSplit, std::max<int64_t>(1, (ldc + chunk - 1) / chunk));
-  const int64_t scols = round_up((ldc + want - 1) / want, chunk);
-  const int32_t ns = static_cast<int32_t>((ldc + scols - 1) / scols);
-  const int32_t nslab = static_cast<int32_t>((ldc + expand_slab(8) - 1) / expand_slab(8));
+  const int32_t nlz = static_cast<int32_t>((ldc + kLzSlab - 1) / kLzSlab);
+  double* np = hp + 2 * static_cast<int64_t>(nlz) * hstride;
 
   double th_lo = 0, th_hi = 0, bd_lo = INFINITY, bd_hi = INFINITY;
   double prev_lo = NAN, prev_hi = NAN, d_lo = INFINITY, d_hi = INFINITY;
@@ -1072,21 +1074,15 @@ apc_status lanczos(apc_plan_s* P, const NormalOp& op, double cap, double* lo_out
   // The FP32 operator reads the vector's FP32 copy, which the normalisation
   // writes for the next step.
   float* v32 = op.f32 && P->ntiles_f > 0 ? P->at<float>(P->L.v32) : nullptr;
-  if (v32) HIP_TRY(launch_cast_f32(V, v32, ldc, P->stream));
+  HIP_TRY(launch_lanczos_start(0x5eedull * 1000003ull, n, ldc, V, v32, P->stream));
   bool done = false;
   int steps = 0, pending = 0;
   for (int j = 0; j < kmax && !done; ++j) {
-    ST_TRY(normal_matvec(P, op, V + static_cast<int64_t>(j) * ldc, vt, v32 != nullptr));
-    for (int pass = 0; pass < 2; ++pass) {
-      double* hh = pass == 0 ? h : h2;
-      RowdotArgs<double> r{V, ldc, nullptr, nullptr, nullptr, (j + 1 + 7) / 8, j + 1, vt, nullptr,
-                           0, nullptr, 0, hh, hstride, ns, scols, 0, 8, 0};
-      HIP_TRY(launch_rowdot_f64(r, P->stream));
-      ExpandArgs<double> e{V, ldc, nullptr, 1, nslab, j + 1, hh, ns, hstride, vt, 0, -1.0, 1.0, 0};
-      HIP_TRY(launch_expand_f64(e, P->stream));
-    }
-    HIP_TRY(launch_lanczos_normalize(vt, ldc, h, h2, ns, hstride, j, al, be,
-                                     V + static_cast<int64_t>(j + 1) * ldc, v32, P->stream));
+    DeferredSum ds;
+    ST_TRY(normal_matvec(P, op, V + static_cast<int64_t>(j) * ldc, vt, v32 != nullptr, &ds));
+    const LanczosArgs la{V,  ldc, j,  nlz, vt, hp, hstride, np, al, be,
+                         V + static_cast<int64_t>(j + 1) * ldc, v32};
+    HIP_TRY(launch_lanczos_step(la, ds.part, ds.f32, ds.ldp, ds.ntiles, ds.scale, P->stream));
     const int k = j + 1;
     if (pending) {
       ST_TRY(decide(pending, &done));

@@ -490,12 +490,32 @@ hipError_t launch_fill_u32(unsigned* p, int64_t count, unsigned v, hipStream_t s
 hipError_t launch_copy_strided(const double* src, int64_t lds, double* dst, int64_t ldd,
                                int64_t rows, int64_t cols, hipStream_t s);
 
-// Lanczos helper: alpha[j] = sum_s h[s*hstride + j] + sum_s h2[s*hstride + j];
-// beta[j] = ||y||; V[j+1] = y / beta[j], and its FP32 rounding in vnext32 when
-// that is non-null.
-hipError_t launch_lanczos_normalize(const double* y, int64_t n, const double* h, const double* h2,
-                                    int32_t nsplit, int64_t hstride, int32_t j, double* alpha,
-                                    double* beta, double* vnext, float* vnext32, hipStream_t s);
+// One Lanczos step after the operator (twice classical Gram-Schmidt of w
+// against V's rows 0..j, alpha_j, beta_j, V[j + 1] = w / beta_j), over column
+// slabs of kLzSlab.  w is the operator's output, or, when part is non-null,
+// scale * (the sum of ntiles partial rows of stride ldp, FP32 when part32).
+constexpr int kLzSlab = 64;
+constexpr int kLzMaxRows = 1024;  // basis rows a step can reorthogonalise against
+struct LanczosArgs {
+  const double* V;  // basis rows 0..j, row stride ldc
+  int64_t ldc;
+  int32_t j;
+  int32_t nslab;    // ceil(ldc / kLzSlab)
+  double* w;        // ldc entries, overwritten by the reorthogonalised vector
+  double* hp;       // dot partials: pass q, slab s, row r at hp[(q * nslab + s) * hstride + r]
+  int64_t hstride;  // >= j + 1
+  double* np;       // nslab norm partials
+  double* alpha;
+  double* beta;
+  double* vnext;    // V's row j + 1
+  float* vnext32;   // optional FP32 copy of vnext
+};
+hipError_t launch_lanczos_step(const LanczosArgs& a, const void* part, bool part32, int64_t ldp,
+                               int32_t ntiles, double scale, hipStream_t s);
+// v = the normalised splitmix64 start vector of n entries (zero up to ldc),
+// and its FP32 rounding in v32 when non-null.
+hipError_t launch_lanczos_start(uint64_t seed, int64_t n, int64_t ldc, double* v, float* v32,
+                                hipStream_t s);
 
 // ---------------------------------------------------------------------------
 // Residual monitor (FP64)

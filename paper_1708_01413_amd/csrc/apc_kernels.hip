@@ -1106,39 +1106,191 @@ __global__ void k_copy_t(const double* src, int64_t lds, double* dst, int64_t ld
   }
 }
 
-__global__ __launch_bounds__(1024) void k_lanczos_normalize(const double* y, int64_t n,
-                                                            const double* h, const double* h2,
-                                                            int32_t nsplit, int64_t hstride,
-                                                            int32_t j, double* alpha,
-                                                            double* beta, double* vnext,
-                                                            float* vnext32) {
+// ------------------------------------------------------------------ Lanczos step
+
+// One Lanczos step after the operator: twice classical Gram-Schmidt of w
+// against the basis rows V[0..j], then beta_j = ||w||, V[j + 1] = w / beta_j,
+// in four launches over column slabs of kLzSlab = 64 columns, one workgroup
+// of four waves per slab.  Lane l of every wave owns the slab's column l; the
+// waves split the rows (or the partial-row tiles) r = wv, wv + 4, ...  Every
+// step local to a column -- the operator's sum over partial rows, w -=
+// sum_r h_r V[r], the scaling -- runs in the slab that owns it; only the dot
+// products and the norm cross slabs, as per-slab partials that every
+// workgroup of the next launch sums in slab order (so nothing depends on
+// scheduling).  All lanes take part in every wave sum; columns past ldc
+// contribute zero.
+
+// hp[blockIdx.x * hstride + r] = sum over the slab's columns of V[r][c] x,
+// r <= j; wave wv takes rows r = wv (mod 4).
+__device__ inline void lz_dots(const LanczosArgs& a, int64_t c, bool ok, double x, double* hp) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  for (int r = wv; r <= a.j; r += 4) {
+    const double v = ok ? a.V[static_cast<int64_t>(r) * a.ldc + c] : 0.0;
+    const double t = wave_sum_dpp(v * x);
+    if (lane == 0) hp[static_cast<int64_t>(blockIdx.x) * a.hstride + r] = t;
+  }
+}
+
+// hs[r] = sum over the slabs of hp[s * hstride + r], r <= j: wave wv takes
+// rows r = wv (mod 4), lane l the slabs s = l (mod 64), then a wave sum.
+__device__ inline void lz_gather(const LanczosArgs& a, const double* hp, double* hs) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  for (int r = wv; r <= a.j; r += 4) {
+    double t = 0.0;
+    for (int sl = lane; sl < a.nslab; sl += 64) t += hp[static_cast<int64_t>(sl) * a.hstride + r];
+    t = wave_sum_dpp(t);
+    if (lane == 0) hs[r] = t;
+  }
+  __syncthreads();
+}
+
+// w - sum_{r <= j} hs[r] V[r][c]: each wave sums its rows, the four partial
+// sums meet in LDS (acc, 4 x 64).  Returns the new w of the lane's column in
+// every wave.
+__device__ inline double lz_subtract(const LanczosArgs& a, int64_t c, bool ok, double w,
+                                     const double* hs, double (*acc)[64]) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  double s0 = 0.0, s1 = 0.0;
+  if (ok) {
+    int r = wv;
+    for (; r + 4 <= a.j; r += 8) {
+      s0 = fma(hs[r], a.V[static_cast<int64_t>(r) * a.ldc + c], s0);
+      s1 = fma(hs[r + 4], a.V[static_cast<int64_t>(r + 4) * a.ldc + c], s1);
+    }
+    if (r <= a.j) s0 = fma(hs[r], a.V[static_cast<int64_t>(r) * a.ldc + c], s0);
+  }
+  acc[wv][lane] = s0 + s1;
+  __syncthreads();
+  return w - ((acc[0][lane] + acc[1][lane]) + (acc[2][lane] + acc[3][lane]));
+}
+
+// Launch 1: w (the operator's output, or first its sum scale * sum_t part[t]
+// over the single pass's partial rows, in FP64: wave wv takes tiles t = wv
+// (mod 4)) and the first Gram-Schmidt pass's dot partials.
+template <typename TP>
+__global__ __launch_bounds__(256) void k_lz_first(LanczosArgs a, const TP* part, int64_t ldp,
+                                                  int32_t ntiles, double scale) {
+  __shared__ double acc[4][64];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int64_t c = static_cast<int64_t>(blockIdx.x) * kLzSlab + lane;
+  const bool ok = c < a.ldc;
+  double w = 0.0;
+  if (part) {
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    if (ok) {
+      int t = wv;
+      for (; t + 12 < ntiles; t += 16) {
+        s0 += static_cast<double>(part[static_cast<int64_t>(t) * ldp + c]);
+        s1 += static_cast<double>(part[static_cast<int64_t>(t + 4) * ldp + c]);
+        s2 += static_cast<double>(part[static_cast<int64_t>(t + 8) * ldp + c]);
+        s3 += static_cast<double>(part[static_cast<int64_t>(t + 12) * ldp + c]);
+      }
+      for (; t < ntiles; t += 4) s0 += static_cast<double>(part[static_cast<int64_t>(t) * ldp + c]);
+    }
+    acc[wv][lane] = (s0 + s1) + (s2 + s3);
+    __syncthreads();
+    w = scale * ((acc[0][lane] + acc[1][lane]) + (acc[2][lane] + acc[3][lane]));
+    if (ok && wv == 0) a.w[c] = w;
+  } else if (ok) {
+    w = a.w[c];
+  }
+  lz_dots(a, c, ok, w, a.hp);
+}
+
+// Launch 2: w -= V^T h (first pass), then the second pass's dot partials.
+__global__ __launch_bounds__(256) void k_lz_second(LanczosArgs a) {
+  __shared__ double hs[kLzMaxRows];
+  __shared__ double acc[4][64];
+  lz_gather(a, a.hp, hs);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int64_t c = static_cast<int64_t>(blockIdx.x) * kLzSlab + lane;
+  const bool ok = c < a.ldc;
+  const double w = lz_subtract(a, c, ok, ok ? a.w[c] : 0.0, hs, acc);
+  lz_dots(a, c, ok, w, a.hp + static_cast<int64_t>(a.nslab) * a.hstride);
+  __syncthreads();  // every wave has read w[c] before wave 0 replaces it
+  if (ok && wv == 0) a.w[c] = w;
+}
+
+// Launch 3: w -= V^T h (second pass) and the slab's part of ||w||^2.
+__global__ __launch_bounds__(256) void k_lz_third(LanczosArgs a) {
+  __shared__ double hs[kLzMaxRows];
+  __shared__ double acc[4][64];
+  lz_gather(a, a.hp + static_cast<int64_t>(a.nslab) * a.hstride, hs);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int64_t c = static_cast<int64_t>(blockIdx.x) * kLzSlab + lane;
+  const bool ok = c < a.ldc;
+  const double w = lz_subtract(a, c, ok, ok ? a.w[c] : 0.0, hs, acc);
+  __syncthreads();  // every wave has read w[c] before wave 0 replaces it
+  if (wv == 0) {
+    if (ok) a.w[c] = w;
+    const double t = wave_sum_dpp(w * w);
+    if (lane == 0) a.np[blockIdx.x] = t;
+  }
+}
+
+// Launch 4: beta_j = ||w|| (every workgroup sums the slab norms in order),
+// alpha_j = both passes' coefficients of V[j] (workgroup 0), V[j + 1] =
+// w / beta_j and its FP32 rounding when vnext32 is non-null.  One wave.
+__global__ __launch_bounds__(64) void k_lz_normalize(LanczosArgs a) {
+  const int lane = threadIdx.x;
+  double t = 0.0;
+  for (int sl = lane; sl < a.nslab; sl += 64) t += a.np[sl];
+  const double b = sqrt(wave_sum_dpp(t));
+  if (blockIdx.x == 0) {
+    double a1 = 0.0, a2 = 0.0;
+    for (int sl = lane; sl < a.nslab; sl += 64) {
+      a1 += a.hp[static_cast<int64_t>(sl) * a.hstride + a.j];
+      a2 += a.hp[static_cast<int64_t>(a.nslab + sl) * a.hstride + a.j];
+    }
+    a1 = wave_sum_dpp(a1);
+    a2 = wave_sum_dpp(a2);
+    if (lane == 0) {
+      a.beta[a.j] = b;
+      a.alpha[a.j] = a1 + a2;
+    }
+  }
+  const double inv = b > 0.0 ? 1.0 / b : 0.0;
+  const int64_t c = static_cast<int64_t>(blockIdx.x) * kLzSlab + lane;
+  if (c < a.ldc) {
+    const double v = a.w[c] * inv;
+    a.vnext[c] = v;
+    if (a.vnext32) a.vnext32[c] = static_cast<float>(v);
+  }
+}
+
+// The Lanczos start vector: v[c] = u_c - 1/2 for c < n, u_c the top 53 bits of
+// splitmix64(seed + c) as a fraction of 2^53, zero for n <= c < ldc; then
+// v /= ||v||.  One workgroup (the norm in a fixed order).
+__device__ inline double lz_start_value(uint64_t seed, int64_t c) {
+  uint64_t x = seed + static_cast<uint64_t>(c) + 0x9E3779B97F4A7C15ull;
+  x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ull;
+  x = (x ^ (x >> 27)) * 0x94D049BB133111EBull;
+  x ^= x >> 31;
+  return static_cast<double>(x >> 11) * (1.0 / 9007199254740992.0) - 0.5;
+}
+__global__ __launch_bounds__(1024) void k_lz_start(uint64_t seed, int64_t n, int64_t ldc, double* v,
+                                                   float* v32) {
   __shared__ double part[1024 / 64];
-  __shared__ double bsh;
+  __shared__ double inv_sh;
   double s = 0.0;
-  for (int64_t e = threadIdx.x; e < n; e += blockDim.x) s = fma(y[e], y[e], s);
-  s = wave_sum(s);
+  for (int64_t c = threadIdx.x; c < n; c += 1024) {
+    const double x = lz_start_value(seed, c);
+    s = fma(x, x, s);
+  }
+  s = wave_sum_dpp(s);
   if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = s;
   __syncthreads();
   if (threadIdx.x == 0) {
     double t = 0.0;
-    for (int w = 0; w < static_cast<int>(blockDim.x / 64); ++w) t += part[w];
-    const double b = sqrt(t);
-    bsh = b;
-    beta[j] = b;
-    double a1 = 0.0, a2 = 0.0;
-    for (int sp = 0; sp < nsplit; ++sp) {
-      a1 += h[sp * hstride + j];
-      a2 += h2[sp * hstride + j];
-    }
-    alpha[j] = a1 + a2;
+    for (int w = 0; w < 1024 / 64; ++w) t += part[w];
+    inv_sh = 1.0 / sqrt(t);
   }
   __syncthreads();
-  const double b = bsh;
-  const double inv = b > 0.0 ? 1.0 / b : 0.0;
-  for (int64_t e = threadIdx.x; e < n; e += blockDim.x) {
-    const double v = y[e] * inv;
-    vnext[e] = v;
-    if (vnext32) vnext32[e] = static_cast<float>(v);
+  const double inv = inv_sh;
+  for (int64_t c = threadIdx.x; c < ldc; c += 1024) {
+    const double x = c < n ? lz_start_value(seed, c) * inv : 0.0;
+    v[c] = x;
+    if (v32) v32[c] = static_cast<float>(x);
   }
 }
 
@@ -1508,11 +1660,26 @@ hipError_t launch_copy_t(const double* src, int64_t lds, double* dst, int64_t ld
   return hipGetLastError();
 }
 
-hipError_t launch_lanczos_normalize(const double* y, int64_t n, const double* h, const double* h2,
-                                    int32_t nsplit, int64_t hstride, int32_t j, double* alpha,
-                                    double* beta, double* vnext, float* vnext32, hipStream_t s) {
-  hipLaunchKernelGGL(k_lanczos_normalize, dim3(1), dim3(1024), 0, s, y, n, h, h2, nsplit, hstride,
-                     j, alpha, beta, vnext, vnext32);
+hipError_t launch_lanczos_step(const LanczosArgs& a, const void* part, bool part32, int64_t ldp,
+                               int32_t ntiles, double scale, hipStream_t s) {
+  if (a.j < 0 || a.j >= kLzMaxRows || a.nslab != (a.ldc + kLzSlab - 1) / kLzSlab)
+    return hipErrorInvalidValue;
+  const dim3 grid(static_cast<unsigned>(a.nslab)), block(256);
+  if (part && part32)
+    hipLaunchKernelGGL(k_lz_first<float>, grid, block, 0, s, a, static_cast<const float*>(part),
+                       ldp, ntiles, scale);
+  else
+    hipLaunchKernelGGL(k_lz_first<double>, grid, block, 0, s, a, static_cast<const double*>(part),
+                       ldp, ntiles, scale);
+  hipLaunchKernelGGL(k_lz_second, grid, block, 0, s, a);
+  hipLaunchKernelGGL(k_lz_third, grid, block, 0, s, a);
+  hipLaunchKernelGGL(k_lz_normalize, grid, dim3(64), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_lanczos_start(uint64_t seed, int64_t n, int64_t ldc, double* v, float* v32,
+                                hipStream_t s) {
+  hipLaunchKernelGGL(k_lz_start, dim3(1), dim3(1024), 0, s, seed, n, ldc, v, v32);
   return hipGetLastError();
 }
 
