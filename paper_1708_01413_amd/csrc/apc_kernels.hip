@@ -36,6 +36,7 @@ namespace {
 // ~7.0 TB/s this way against ~6.3 TB/s with ordinary loads.
 typedef float f32x4_t __attribute__((ext_vector_type(4)));
 typedef double f64x2_t __attribute__((ext_vector_type(2)));
+typedef double f64x4 __attribute__((ext_vector_type(4)));
 template <typename T>
 struct V16;
 template <>
@@ -795,7 +796,7 @@ __global__ __launch_bounds__(512) void k_chol_inv(const int64_t* off, const int6
   const int lane = tid & 63, wv = tid >> 6;
   __shared__ double dl[kNB][kNB + 1];   // L_kk, then (column-solve input)
   __shared__ double di[kNB][kNB + 1];   // L_kk^{-1}
-  __shared__ double pan[kPanelRows][kNB + 1];
+  __shared__ double pan[kPanelRows][kNB + 2];  // stride 34: conflict-free MFMA fragment reads
   __shared__ double red[1024 / 64];  // per-wave maxima (up to 16 waves)
   __shared__ int bad;
 
@@ -806,17 +807,15 @@ __global__ __launch_bounds__(512) void k_chol_inv(const int64_t* off, const int6
   for (int o = 32; o > 0; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o, 64));
   if (lane == 0) red[wv] = mx;
   if (tid == 0) bad = 0;
-  for (int64_t e = tid; e < static_cast<int64_t>(p) * p; e += nt) {
-    const int r = static_cast<int>(e / p), c = static_cast<int>(e % p);
-    if (c > r) Lb[e] = 0.0;
-  }
+  for (int r = wv; r < p; r += nt / 64)
+    for (int c = r + 1 + lane; c < p; c += 64) Lb[static_cast<int64_t>(r) * p + c] = 0.0;
   __syncthreads();
   double maxdiag = 0.0;
   for (int w = 0; w < nt / 64; ++w) maxdiag = fmax(maxdiag, red[w]);
 
   for (int kb = 0; kb < p; kb += kNB) {
     const int nb = min(kNB, p - kb);
-    // (1) diagonal block: Cholesky and inverse in wave 0's registers.
+    // (1) diagonal block: Cholesky and its inverse in wave 0's registers.
     if (wv == 0) {
       double a[kNB];
 #pragma unroll
@@ -825,9 +824,11 @@ __global__ __launch_bounds__(512) void k_chol_inv(const int64_t* off, const int6
         if (lane < nb && j < nb && j <= lane) v = Gb[static_cast<int64_t>(kb + lane) * p + kb + j];
         a[j] = v;
       }
+      // Column j and the pivot pass between lanes by lane reads (scalar
+      // broadcasts: the source lanes are compile-time constants).
 #pragma unroll
       for (int j = 0; j < kNB; ++j) {
-        double piv = __shfl(a[j], j, 64);
+        double piv = lane_f64(a[j], j);
         if (j < nb && !(piv > rank_tol * maxdiag)) {  // also catches NaN
           if (lane == 0) bad = 1;
           piv = maxdiag > 0.0 ? maxdiag : 1.0;
@@ -837,7 +838,7 @@ __global__ __launch_bounds__(512) void k_chol_inv(const int64_t* off, const int6
         if (lane == j) a[j] = d;
 #pragma unroll
         for (int jj = j + 1; jj < kNB; ++jj) {
-          const double ljj = __shfl(a[j], jj, 64);
+          const double ljj = lane_f64(a[j], jj);
           if (lane >= jj) a[jj] -= a[j] * ljj;
         }
       }
@@ -845,21 +846,25 @@ __global__ __launch_bounds__(512) void k_chol_inv(const int64_t* off, const int6
 #pragma unroll
         for (int j = 0; j < kNB; ++j) dl[lane][j] = (j <= lane) ? a[j] : 0.0;
       }
-    }
-    __syncthreads();
-    // Inverse of L_kk, lane c of wave 0 builds column c by forward substitution.
-    if (wv == 0 && lane < kNB) {
-      const int c = lane;
-      double x[kNB];
+      __builtin_amdgcn_wave_barrier();
+      // Inverse of L_kk: lane c forms column c by right-looking forward
+      // substitution, x_i = s_i / L_ii and then s_k -= L_ki x_i for k > i
+      // (L's entries broadcast from LDS: a wave's LDS accesses complete in
+      // order).  The dependent chain is one multiply and one FMA per step.
+      double sv[kNB];
+#pragma unroll
+      for (int k = 0; k < kNB; ++k) sv[k] = (lane == k) ? 1.0 : 0.0;
 #pragma unroll
       for (int i = 0; i < kNB; ++i) {
-        double sacc = (i == c) ? 1.0 : 0.0;
+        const double x = sv[i] * (1.0 / dl[i][i]);
+        sv[i] = x;
 #pragma unroll
-        for (int q = 0; q < i; ++q) sacc -= dl[i][q] * x[q];
-        x[i] = (i < c) ? 0.0 : sacc / dl[i][i];
+        for (int k = i + 1; k < kNB; ++k) sv[k] -= dl[k][i] * x;
       }
+      if (lane < kNB) {
 #pragma unroll
-      for (int i = 0; i < kNB; ++i) di[i][c] = x[i];
+        for (int i = 0; i < kNB; ++i) di[i][lane] = (i < lane) ? 0.0 : sv[i];
+      }
     }
     __syncthreads();
     // Write L_kk and L_kk^{-1} back.
@@ -870,43 +875,99 @@ __global__ __launch_bounds__(512) void k_chol_inv(const int64_t* off, const int6
         Lb[static_cast<int64_t>(kb + i) * p + kb + j] = di[i][j];
       }
     }
-    // (2) panel below: rows times L_kk^{-T}.
+    // (2) panel below: P = rows times L_kk^{-T} (a panel exists only below a
+    // full 32-column block) on the FP64 matrix cores.  Wave w takes the
+    // 16-row tiles I = w (mod 8) and both 16-column output tiles of each:
+    // lane (li, g) supplies A[li][g] = G[row 16 I + li][4 kk + g] (all eight K
+    // steps loaded before anything is written: the result replaces those
+    // rows) and B[g][li] = Linv_kk[16 J + li][4 kk + g], and receives
+    // P[16 I + g + 4 q][16 J + li].
     const int T = p - kb - nb;
     const bool in_lds = T <= kPanelRows;
-    for (int t = tid; t < T; t += nt) {
-      const int r = kb + nb + t;
-      double* row = Gb + static_cast<int64_t>(r) * p + kb;
-      double o[kNB];
+    if (T > 0) {
+      const int nT = (T + 15) / 16;
+      const int li = lane & 15, g = lane >> 4;
+      for (int I = wv; I < nT; I += nt / 64) {
+        const int ra = 16 * I + li;
+        const double* arow = Gb + static_cast<int64_t>(kb + nb + min(ra, T - 1)) * p + kb;
+        double av[kNB / 4];
 #pragma unroll
-      for (int j = 0; j < kNB; ++j) o[j] = 0.0;
-#pragma unroll 1
-      for (int q = 0; q < nb; ++q) {  // o[j] = sum_{q <= j} row[q] Linv_kk[j][q]
-        const double sq = row[q];
+        for (int kk = 0; kk < kNB / 4; ++kk) {
+          const double v = arow[4 * kk + g];
+          av[kk] = ra < T ? v : 0.0;
+        }
+        f64x4 acc0 = f64x4{}, acc1 = f64x4{};
 #pragma unroll
-        for (int j = 0; j < kNB; ++j) o[j] += (j >= q) ? sq * di[j][q] : 0.0;
-      }
+        for (int kk = 0; kk < kNB / 4; ++kk) {
+          acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(av[kk], di[li][4 * kk + g], acc0, 0, 0, 0);
+          acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(av[kk], di[16 + li][4 * kk + g], acc1, 0, 0, 0);
+        }
 #pragma unroll
-      for (int j = 0; j < kNB; ++j) {
-        if (j < nb) {
-          row[j] = o[j];
-          if (in_lds) pan[t][j] = o[j];
+        for (int q = 0; q < 4; ++q) {
+          const int row = 16 * I + g + 4 * q;
+          if (row < T) {
+            double* orow = Gb + static_cast<int64_t>(kb + nb + row) * p + kb;
+            orow[li] = acc0[q];
+            orow[16 + li] = acc1[q];
+            if (in_lds) {
+              pan[row][li] = acc0[q];
+              pan[row][16 + li] = acc1[q];
+            }
+          }
         }
       }
     }
     __syncthreads();
-    // (3) trailing update of the lower triangle.
-    for (int64_t e = tid; e < static_cast<int64_t>(T) * T; e += nt) {
-      const int rr = static_cast<int>(e / T), cc = static_cast<int>(e % T);
-      if (cc > rr) continue;
-      double sacc = 0.0;
-      if (in_lds) {
-        for (int q = 0; q < nb; ++q) sacc += pan[rr][q] * pan[cc][q];
-      } else {
+    // (3) trailing update G22 -= P P^T of the lower triangle.  With the panel
+    // in LDS: 16 x 16 tiles (I >= J) on the FP64 matrix cores, dealt to the
+    // waves round-robin, 8 MFMA 16x16x4 per tile (K = nb = 32: a trailing
+    // block exists only after a full panel).  Lane (li, g) supplies
+    // A[li][g] = -P[16 I + li][k] and B[g][li] = P[16 J + li][k] and holds
+    // D[g + 4 q][li]; rows past T read a clamped row and are zeroed.
+    if (in_lds) {
+      const int nT = (T + 15) / 16;
+      const int li = lane & 15, g = lane >> 4;
+      int tc = 0;
+      for (int I = 0; I < nT; ++I) {
+        for (int J = 0; J <= I; ++J, ++tc) {
+          if (tc % (nt / 64) != wv) continue;  // uniform per wave
+          const int col = 16 * J + li;
+          f64x4 acc;
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const int row = 16 * I + g + 4 * q;
+            const double v = Gb[static_cast<int64_t>(kb + nb + min(row, T - 1)) * p + kb + nb +
+                                min(col, T - 1)];
+            acc[q] = (row < T && col <= row) ? v : 0.0;
+          }
+          const int ra = 16 * I + li, rb = 16 * J + li;
+          const int ca = min(ra, T - 1), cb = min(rb, T - 1);
+#pragma unroll
+          for (int kk = 0; kk < kNB / 4; ++kk) {
+            const int k = 4 * kk + g;
+            const double av = pan[ca][k], bv = pan[cb][k];
+            const double a = ra < T ? -av : 0.0;
+            const double b = rb < T ? bv : 0.0;
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+          }
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const int row = 16 * I + g + 4 * q;
+            if (row < T && col <= row)
+              Gb[static_cast<int64_t>(kb + nb + row) * p + kb + nb + col] = acc[q];
+          }
+        }
+      }
+    } else {
+      for (int64_t e = tid; e < static_cast<int64_t>(T) * T; e += nt) {
+        const int rr = static_cast<int>(e / T), cc = static_cast<int>(e % T);
+        if (cc > rr) continue;
         const double* pr = Gb + static_cast<int64_t>(kb + nb + rr) * p + kb;
         const double* pc = Gb + static_cast<int64_t>(kb + nb + cc) * p + kb;
+        double sacc = 0.0;
         for (int q = 0; q < nb; ++q) sacc += pr[q] * pc[q];
+        Gb[static_cast<int64_t>(kb + nb + rr) * p + kb + nb + cc] -= sacc;
       }
-      Gb[static_cast<int64_t>(kb + nb + rr) * p + kb + nb + cc] -= sacc;
     }
     __syncthreads();
   }
