@@ -353,12 +353,6 @@ void optimum(double lo, double hi, double* gamma, double* eta, double* rho) {
   *rho = r;
 }
 
-uint64_t splitmix64(uint64_t x) {
-  x += 0x9E3779B97F4A7C15ull;
-  x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ull;
-  x = (x ^ (x >> 27)) * 0x94D049BB133111EBull;
-  return x ^ (x >> 31);
-}
 
 }  // namespace
 
@@ -406,7 +400,8 @@ struct apc_plan_s {
   int32_t fused_tpb = 0;               // > 0: every block has this many single-pass tiles
   int32_t qr_passes = 2;               // CholeskyQR passes setup took (1: see setup_impl)
   double qr_defect = NAN;              // estimated ||Q_i^T Q_i - I|| after the first pass
-  double* pinned = nullptr;            // pinned host copy of the Lanczos coefficients
+  double* pinned = nullptr;            // pinned host staging (Lanczos coefficients, setup readbacks)
+  size_t pinned_n = 0;                 // its size in doubles
   hipEvent_t check_ev = nullptr;       // recorded after their copy
   int64_t since_start = 0;             // k-RHS updates since the last start
   int refinements = 0;
@@ -522,25 +517,40 @@ apc_status fused_combine(apc_plan_s* P, double alpha, double beta) {
 }
 
 // Departure from orthonormality of every block's rows of the FP64 factor C,
+// Pinned host staging of at least n doubles, kept for the plan's life.
+apc_status pinned_at_least(apc_plan_s* P, size_t n) {
+  if (P->pinned && P->pinned_n >= n) return APC_OK;
+  if (P->pinned) {
+    HIP_TRY(hipHostFree(P->pinned));
+    P->pinned = nullptr;
+    P->pinned_n = 0;
+  }
+  void* hp = nullptr;
+  HIP_TRY(hipHostMalloc(&hp, n * sizeof(double), hipHostMallocDefault));
+  P->pinned = static_cast<double*>(hp);
+  P->pinned_n = n;
+  return APC_OK;
+}
+
 // max_i ||C_i C_i^T - I||, estimated with one random vector z: with
 // C_i C_i^T = I + E_i, u_i = C_i^T C_i z and v_i = C_i^T C_i u_i differ by
 // C_i^T E_i C_i z, so ||v_i - u_i|| / ||u_i|| estimates ||E_i|| (within a factor
 // up to sqrt(p_i) when E_i is concentrated in one direction).  Two single passes
 // over C; synchronises the stream.  Uses the x, Y, vtmp and w slices as scratch.
-apc_status orthogonality_defect(apc_plan_s* P, const double* C, double* defect) {
+// flags (4 ints) and scal (2 doubles), when non-null, are read back from the
+// plan's slices in the same synchronisation.
+apc_status orthogonality_defect(apc_plan_s* P, const double* C, double* defect, int* flags = nullptr,
+                                double* scal = nullptr) {
   const Layout& L = P->L;
   hipStream_t st = P->stream;
-  std::vector<double> z(L.ldc, 0.0);
-  for (int64_t j = 0; j < P->n; ++j) {
-    const uint64_t r = splitmix64(0x0a7ull * 1000003ull + static_cast<uint64_t>(j));
-    z[j] = (static_cast<double>(r >> 11) * (1.0 / 9007199254740992.0)) - 0.5;
-  }
   double* zd = P->at<double>(L.vtmp);
+  // z: the splitmix64 vector of the Lanczos start, normalised (the estimate is
+  // a ratio), generated on the GPU.
+  HIP_TRY(launch_lanczos_start(0x0a7ull * 1000003ull, P->n, L.ldc, zd, nullptr, st));
   double* U = P->at<double>(L.Y);
   double* V = P->x();
   double* part = P->at<double>(L.fpart);
   double* out = P->at<double>(L.w);
-  HIP_TRY(hipMemcpyAsync(zd, z.data(), L.ldc * sizeof(double), hipMemcpyHostToDevice, st));
   const int g = fused_cpt(L.ldc, 8) >= 16 ? 1 : 2;
   const int32_t remap = P->xcd_remap == 1 ? 1 : 0;
   for (int app = 0; app < 2; ++app) {
@@ -550,9 +560,16 @@ apc_status orthogonality_defect(apc_plan_s* P, const double* C, double* defect) 
     HIP_TRY(launch_block_sum(part, L.ldc, P->tf(3), P->m, L.ldc, app == 0 ? U : V, L.ldc, st));
   }
   HIP_TRY(launch_defect(U, V, L.ldc, P->m, P->n, out, st));
-  std::vector<double> h(2 * static_cast<size_t>(P->m));
-  HIP_TRY(hipMemcpyAsync(h.data(), out, h.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+  const size_t nh = 2 * static_cast<size_t>(P->m);
+  // (sized for the Lanczos coefficients too, which come next)
+  ST_TRY(pinned_at_least(P, std::max<size_t>(nh + 4, 2 * static_cast<size_t>(L.kmax + 1))));
+  double* h = P->pinned;
+  HIP_TRY(hipMemcpyAsync(h, out, nh * sizeof(double), hipMemcpyDeviceToHost, st));
+  if (flags) HIP_TRY(hipMemcpyAsync(h + nh, P->at<int>(L.flags), 4 * sizeof(int), hipMemcpyDeviceToHost, st));
+  if (scal) HIP_TRY(hipMemcpyAsync(h + nh + 2, P->at<double>(L.scal), 2 * sizeof(double), hipMemcpyDeviceToHost, st));
   HIP_TRY(hipStreamSynchronize(st));
+  if (flags) std::memcpy(flags, h + nh, 4 * sizeof(int));
+  if (scal) std::memcpy(scal, h + nh + 2, 2 * sizeof(double));
   double worst = 0.0;
   for (int i = 0; i < P->m; ++i) {
     const double e = h[2 * i + 1] > 0.0 ? std::sqrt(h[2 * i] / h[2 * i + 1]) : INFINITY;
@@ -1007,11 +1024,7 @@ apc_status lanczos(apc_plan_s* P, const NormalOp& op, double cap, double* lo_out
   // whether to stop after k steps.  The copy is issued after step k and read
   // after step k + 1 has been enqueued, so the GPU runs that step while the host
   // waits and decides; stopping then leaves one step unused.
-  if (!P->pinned) {
-    void* hp = nullptr;
-    HIP_TRY(hipHostMalloc(&hp, 2 * static_cast<size_t>(hstride) * sizeof(double), hipHostMallocDefault));
-    P->pinned = static_cast<double*>(hp);
-  }
+  ST_TRY(pinned_at_least(P, 2 * static_cast<size_t>(hstride)));
   if (!P->check_ev) HIP_TRY(hipEventCreateWithFlags(&P->check_ev, hipEventDisableTiming));
   double* ha = P->pinned;
   double* hb = P->pinned + hstride;
@@ -1224,6 +1237,9 @@ apc_status setup_impl(apc_plan_s* P, const Tiles& T) {
   // measured departure, times sqrt(p_max) for the estimate's worst case, is at
   // most 1e-10; FP64 plans, the k-RHS forms and APC_QR_PASSES=2 always take two.
   bool may_skip = !P->gemm && P->prec == APC_F32 && P->fused && fused_cpt(ldc, 8) > 0;
+  int flags[4] = {0, 0, 0, 0};
+  double scal[2] = {0, 0};
+  bool have_flags = false;  // read with the orthogonality estimate
   if (const char* e = std::getenv("APC_QR_PASSES")) may_skip = may_skip && std::atoi(e) != 2;
   for (int pass = 0; pass < 2; ++pass) {
     const double* src = pass == 0 ? (in_place ? P->A : Ca) : Cb;
@@ -1252,8 +1268,9 @@ apc_status setup_impl(apc_plan_s* P, const Tiles& T) {
       HIP_TRY(launch_trmm(src, dst, ldc, P->doff(), P->at<int32_t>(L.tiles_t), L.ntiles_t,
                           P->at<int64_t>(L.goff), Li, st));
     if (pass == 0 && may_skip) {
-      ST_TRY(orthogonality_defect(P, dst, &P->qr_defect));
+      ST_TRY(orthogonality_defect(P, dst, &P->qr_defect, flags, scal));
       if (P->qr_defect * std::sqrt(static_cast<double>(pmax)) <= 1e-10) {
+        have_flags = true;
         // The factor and c stay where the first pass left them: the plan's
         // layout names those slices from here on.
         P->qr_passes = 1;
@@ -1265,11 +1282,11 @@ apc_status setup_impl(apc_plan_s* P, const Tiles& T) {
       }
     }
   }
-  int flags[4] = {0, 0, 0, 0};
-  HIP_TRY(hipMemcpyAsync(flags, P->at<int>(L.flags), sizeof flags, hipMemcpyDeviceToHost, st));
-  double scal[2] = {0, 0};
-  HIP_TRY(hipMemcpyAsync(scal, P->at<double>(L.scal), sizeof scal, hipMemcpyDeviceToHost, st));
-  HIP_TRY(hipStreamSynchronize(st));
+  if (!have_flags) {
+    HIP_TRY(hipMemcpyAsync(flags, P->at<int>(L.flags), sizeof flags, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(scal, P->at<double>(L.scal), sizeof scal, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+  }
   if (flags[0] != 0)
     return fail(APC_ERANK, "block %d is not of full row rank (Cholesky pivot below %g of the largest)",
                 flags[0] - 1, rank_tol);
