@@ -583,18 +583,17 @@ __global__ __launch_bounds__(256) void k_gram_mfma(const double* C, int64_t ldc,
   const int li = lane & 15, g = lane >> 4;
   const int qa = wv >> 1, qb = wv & 1;
   // Operand rows of this lane: two 16-row tiles of the A quadrant, two of the B
-  // quadrant.  Rows past the block read its first row and are zeroed.
+  // quadrant.  Rows past the block read its first row: they only reach
+  // entries of G past the block, which are not stored, so they need no
+  // zeroing (which would make every load wait as soon as it was issued).
   const double* pa[2];
   const double* pb[2];
-  bool va[2], vb[2];
 #pragma unroll
   for (int t = 0; t < 2; ++t) {
     const int ra = ta * 64 + qa * 32 + 16 * t + li;
     const int rb = tb * 64 + qb * 32 + 16 * t + li;
-    va[t] = ra < p;
-    vb[t] = rb < p;
-    pa[t] = C + (r0 + (va[t] ? ra : 0)) * ldc + 8 * g;
-    pb[t] = C + (r0 + (vb[t] ? rb : 0)) * ldc + 8 * g;
+    pa[t] = C + (r0 + (ra < p ? ra : 0)) * ldc + 8 * g;
+    pb[t] = C + (r0 + (rb < p ? rb : 0)) * ldc + 8 * g;
   }
   f64x2 ar[3][2][4], br[3][2][4];  // ring of three K steps: two loaded ahead
   f64x4 acc[2][2];
@@ -608,10 +607,8 @@ __global__ __launch_bounds__(256) void k_gram_mfma(const double* C, int64_t ldc,
     for (int t = 0; t < 2; ++t)
 #pragma unroll
       for (int pc = 0; pc < 4; ++pc) {
-        const f64x2 x = *reinterpret_cast<const f64x2*>(pa[t] + o + 2 * pc);
-        const f64x2 y = *reinterpret_cast<const f64x2*>(pb[t] + o + 2 * pc);
-        a[t][pc] = va[t] ? x : f64x2{};
-        b[t][pc] = vb[t] ? y : f64x2{};
+        a[t][pc] = *reinterpret_cast<const f64x2*>(pa[t] + o + 2 * pc);
+        b[t][pc] = *reinterpret_cast<const f64x2*>(pb[t] + o + 2 * pc);
       }
   };
   auto compute = [&](const f64x2 (&a)[2][4], const f64x2 (&b)[2][4]) {
@@ -626,20 +623,21 @@ __global__ __launch_bounds__(256) void k_gram_mfma(const double* C, int64_t ldc,
             acc[t][u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[t][pc][e], b[u][pc][e], acc[t][u],
                                                              0, 0, 0);
   };
+  // Every load is issued unconditionally (steps past the end reload the last
+  // one, unused): a load behind a branch leaves the compiler unable to count
+  // the loads in flight where the paths join, and it then waits for all of
+  // them, which serialises the prefetch with the products.
   const int nsteps = static_cast<int>(ldc / 32);
-  if (nsteps > 0) load(ar[0], br[0], 0);
-  if (nsteps > 1) load(ar[1], br[1], 1);
+  const int last = nsteps - 1;
+  load(ar[0], br[0], 0);
+  load(ar[1], br[1], min(1, last));
   for (int s0 = 0; s0 < nsteps; s0 += 3) {
-    if (s0 + 2 < nsteps) load(ar[2], br[2], s0 + 2);
+    load(ar[2], br[2], min(s0 + 2, last));
     compute(ar[0], br[0]);
-    if (s0 + 1 < nsteps) {
-      if (s0 + 3 < nsteps) load(ar[0], br[0], s0 + 3);
-      compute(ar[1], br[1]);
-    }
-    if (s0 + 2 < nsteps) {
-      if (s0 + 4 < nsteps) load(ar[1], br[1], s0 + 4);
-      compute(ar[2], br[2]);
-    }
+    load(ar[0], br[0], min(s0 + 3, last));
+    if (s0 + 1 < nsteps) compute(ar[1], br[1]);
+    load(ar[1], br[1], min(s0 + 4, last));
+    if (s0 + 2 < nsteps) compute(ar[2], br[2]);
   }
   // acc[t][u][q] = G[row base + g + 4 q][column base + li].
   double* Gb = G + goff[blk];
@@ -698,29 +696,35 @@ __global__ __launch_bounds__(256, 2) void k_trmm_lds(const double* In, double* O
   // Linv rows have stride p, which may be odd); B -- thread t takes row t / 8
   // of the chunk and 16 consecutive columns (16-byte loads: ldc is a multiple
   // of 64).  Entries past the block, past kend or past ldc are zero.
+  // Loads read clamped in-range addresses unconditionally and the entries
+  // outside the block are zeroed when stored to LDS, after the products: a
+  // load behind a branch, or one whose value is selected at once, makes the
+  // compiler wait for every load in flight there.
   const int ar = threadIdx.x >> 1, ak = (threadIdx.x & 1) * 16;
   const int bk = threadIdx.x >> 3, bc = (threadIdx.x & 7) * 16;
   const bool a_row_ok = R0 + ar < p;
   const bool b_col_ok = C0 + bc < ldc;
+  const int64_t a_row = static_cast<int64_t>(a_row_ok ? R0 + ar : p - 1) * p;
+  const int64_t b_col = b_col_ok ? C0 + bc : 0;
   double pa[16];
   f64x2 pb[8];
+  int kc_loaded = 0;
   auto load_chunk = [&](int kc) {
+    kc_loaded = kc;
 #pragma unroll
-    for (int j = 0; j < 16; ++j) {
-      const int k = kc + ak + j;
-      pa[j] = (a_row_ok && k < kend) ? Lb[static_cast<int64_t>(R0 + ar) * p + k] : 0.0;
-    }
-    const bool brow = kc + bk < kend && b_col_ok;
-    const double* src = In + (r0 + kc + bk) * ldc + C0 + bc;
+    for (int j = 0; j < 16; ++j) pa[j] = Lb[a_row + min(kc + ak + j, p - 1)];
+    const double* src = In + (r0 + min(kc + bk, p - 1)) * ldc + b_col;
 #pragma unroll
-    for (int j = 0; j < 8; ++j)
-      pb[j] = brow ? *reinterpret_cast<const f64x2*>(src + 2 * j) : f64x2{0.0, 0.0};
+    for (int j = 0; j < 8; ++j) pb[j] = *reinterpret_cast<const f64x2*>(src + 2 * j);
   };
   auto store_chunk = [&]() {
+    const int kc = kc_loaded;
 #pragma unroll
-    for (int j = 0; j < 16; ++j) As[ak + j][ar] = pa[j];
+    for (int j = 0; j < 16; ++j) As[ak + j][ar] = (a_row_ok && kc + ak + j < kend) ? pa[j] : 0.0;
+    const bool brow = kc + bk < kend && b_col_ok;
 #pragma unroll
-    for (int j = 0; j < 8; ++j) *reinterpret_cast<f64x2*>(&Bs[bk][bc + 2 * j]) = pb[j];
+    for (int j = 0; j < 8; ++j)
+      *reinterpret_cast<f64x2*>(&Bs[bk][bc + 2 * j]) = brow ? pb[j] : f64x2{0.0, 0.0};
   };
 
   f64x4 acc[4][4];
@@ -733,7 +737,7 @@ __global__ __launch_bounds__(256, 2) void k_trmm_lds(const double* In, double* O
   __syncthreads();
   for (int kc = 0; kc < kend; kc += kTK) {
     const bool more = kc + kTK < kend;
-    if (more) load_chunk(kc + kTK);
+    load_chunk(more ? kc + kTK : kc);  // the last chunk reloads itself, unused
 #pragma unroll
     for (int kk = 0; kk < kTK / 4; ++kk) {
       const int k = 4 * kk + g;

@@ -56,7 +56,7 @@ apc_status fail(apc_status st, const char* fmt, ...) {
 constexpr int64_t kAlign = 256;
 constexpr int kLanczosMax = 1024;   // Lanczos steps cap (full reorthogonalisation)
 static_assert(kLanczosMax <= kLzMaxRows, "a Lanczos step reorthogonalises against at most kLzMaxRows rows");
-constexpr int kLanczosCheck = 4;    // steps between convergence checks (host syncs)
+constexpr int kLanczosWindow = 4;   // steps over which a Ritz value's change is measured
 constexpr int kAnchorEvery = 16;    // default anchor spacing of the FP32 k-RHS iteration
 
 int64_t round_up(int64_t v, int64_t a) { return (v + a - 1) / a * a; }
@@ -526,7 +526,8 @@ apc_status pinned_at_least(apc_plan_s* P, size_t n) {
     P->pinned_n = 0;
   }
   void* hp = nullptr;
-  HIP_TRY(hipHostMalloc(&hp, n * sizeof(double), hipHostMallocDefault));
+  // Coherent: the Lanczos step's kernel writes its coefficients here directly.
+  HIP_TRY(hipHostMalloc(&hp, n * sizeof(double), hipHostMallocCoherent));
   P->pinned = static_cast<double*>(hp);
   P->pinned_n = n;
   return APC_OK;
@@ -1019,11 +1020,15 @@ apc_status lanczos(apc_plan_s* P, const NormalOp& op, double cap, double* lo_out
   double* np = hp + 2 * static_cast<int64_t>(nlz) * hstride;
 
   double th_lo = 0, th_hi = 0, bd_lo = INFINITY, bd_hi = INFINITY;
-  double prev_lo = NAN, prev_hi = NAN, d_lo = INFINITY, d_hi = INFINITY;
-  // The coefficients of the first k steps, copied to pinned host memory, decide
-  // whether to stop after k steps.  The copy is issued after step k and read
-  // after step k + 1 has been enqueued, so the GPU runs that step while the host
-  // waits and decides; stopping then leaves one step unused.
+  double d_lo = INFINITY, d_hi = INFINITY;
+  // The extreme Ritz values after each step (index k - 1), for their change
+  // over the last kLanczosWindow steps.
+  std::vector<double> hist_lo, hist_hi;
+  // The coefficients of the first k steps, in pinned host memory, decide
+  // whether to stop after k steps.  The event after step k is awaited after
+  // step k + 1 has been enqueued, so the GPU runs that step while the host
+  // waits and decides; stopping then leaves one step unused.  Every step is
+  // checked.
   ST_TRY(pinned_at_least(P, 2 * static_cast<size_t>(hstride)));
   if (!P->check_ev) HIP_TRY(hipEventCreateWithFlags(&P->check_ev, hipEventDisableTiming));
   double* ha = P->pinned;
@@ -1063,17 +1068,24 @@ apc_status lanczos(apc_plan_s* P, const NormalOp& op, double cap, double* lo_out
     // and ~10 % below mu_min, which raises rho by O(width) only: at the
     // 16384 x 8192 benchmark shape 40 steps (each costs about 1.3 updates)
     // instead of 76 for about two more updates to 1e-6.
+    hist_lo.resize(k, NAN);
+    hist_hi.resize(k, NAN);
+    hist_lo[k - 1] = th_lo;
+    hist_hi[k - 1] = th_hi;
+    const int kw = k - kLanczosWindow;
+    const double prev_lo = kw >= 1 ? hist_lo[kw - 1] : NAN;
+    const double prev_hi = kw >= 1 ? hist_hi[kw - 1] : NAN;
     d_lo = std::isnan(prev_lo) ? INFINITY : std::fabs(th_lo - prev_lo);
     d_hi = std::isnan(prev_hi) ? INFINITY : std::fabs(th_hi - prev_hi);
     const bool hi_ok = bd_hi <= 1e-10 * th_hi || (d_hi <= 3e-4 * th_hi && bd_hi <= 1e-2 * th_hi);
     const bool lo_ok = bd_lo <= 1e-6 * th_lo || (d_lo <= 1e-2 * th_lo && bd_lo <= 0.5 * th_lo);
-    prev_lo = th_lo;
-    prev_hi = th_hi;
     return (exhausted || (hi_ok && lo_ok)) ? APC_OK : APC_ENOCONV;
   };
-  auto issue_copy = [&](int k) -> apc_status {
-    HIP_TRY(hipMemcpyAsync(ha, al, k * sizeof(double), hipMemcpyDeviceToHost, P->stream));
-    HIP_TRY(hipMemcpyAsync(hb, be, k * sizeof(double), hipMemcpyDeviceToHost, P->stream));
+  // The normalisation kernel also stores alpha_j, beta_j in the pinned buffer
+  // (coherent host memory), so a check needs only an event, no copy.
+  double* hab = nullptr;
+  HIP_TRY(hipHostGetDevicePointer(reinterpret_cast<void**>(&hab), P->pinned, 0));
+  auto issue_copy = [&](int) -> apc_status {
     HIP_TRY(hipEventRecord(P->check_ev, P->stream));
     return APC_OK;
   };
@@ -1094,7 +1106,7 @@ apc_status lanczos(apc_plan_s* P, const NormalOp& op, double cap, double* lo_out
     DeferredSum ds;
     ST_TRY(normal_matvec(P, op, V + static_cast<int64_t>(j) * ldc, vt, v32 != nullptr, &ds));
     const LanczosArgs la{V,  ldc, j,  nlz, vt, hp, hstride, np, al, be,
-                         V + static_cast<int64_t>(j + 1) * ldc, v32};
+                         V + static_cast<int64_t>(j + 1) * ldc, v32, hab};
     HIP_TRY(launch_lanczos_step(la, ds.part, ds.f32, ds.ldp, ds.ntiles, ds.scale, P->stream));
     const int k = j + 1;
     if (pending) {
@@ -1106,7 +1118,7 @@ apc_status lanczos(apc_plan_s* P, const NormalOp& op, double cap, double* lo_out
       pending = 0;
     }
     steps = k;
-    if (k % kLanczosCheck == 0 || k == kmax) {
+    {
       ST_TRY(issue_copy(k));
       pending = k;
       if (k == kmax) {

@@ -509,6 +509,7 @@ struct LanczosArgs {
   double* beta;
   double* vnext;    // V's row j + 1
   float* vnext32;   // optional FP32 copy of vnext
+  double* host_ab;  // optional (host memory the device can write): alpha_j at [j], beta_j at [hstride + j]
 };
 hipError_t launch_lanczos_step(const LanczosArgs& a, const void* part, bool part32, int64_t ldp,
                                int32_t ntiles, double scale, hipStream_t s);

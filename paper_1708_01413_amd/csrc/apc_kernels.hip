@@ -1308,6 +1308,10 @@ __global__ __launch_bounds__(64) void k_lz_normalize(LanczosArgs a) {
     if (lane == 0) {
       a.beta[a.j] = b;
       a.alpha[a.j] = a1 + a2;
+      if (a.host_ab) {
+        a.host_ab[a.j] = a1 + a2;
+        a.host_ab[a.hstride + a.j] = b;
+      }
     }
   }
   const double inv = b > 0.0 ? 1.0 / b : 0.0;
