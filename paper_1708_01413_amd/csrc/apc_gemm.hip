@@ -669,7 +669,7 @@ __global__ __launch_bounds__(256) void k_gram_mfma(const double* C, int64_t ldc,
 constexpr int kTT = 128;
 constexpr int kTK = 32;
 constexpr int kTS = kTT + 16;
-__global__ __launch_bounds__(256, 2) void k_trmm_lds(const double* In, double* Out, int64_t ldc,
+__global__ __launch_bounds__(512, 2) void k_trmm_lds(const double* In, double* Out, int64_t ldc,
                                                   const int64_t* off, int32_t m, int32_t nrt,
                                                   int32_t nct, const int64_t* goff,
                                                   const double* Linv, float* Out32) {
@@ -688,7 +688,7 @@ __global__ __launch_bounds__(256, 2) void k_trmm_lds(const double* In, double* O
   const int kend = min(p, R0 + kTT);
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int li = lane & 15, g = lane >> 4;
-  const int wr = wv >> 1, wc = wv & 1;
+  const int wr = wv >> 1, wc = wv & 1;  // eight waves: 4 x 2 quadrants of 32 x 64
   __shared__ __align__(16) double As[kTK][kTS];
   __shared__ __align__(16) double Bs[kTK][kTS];
 
@@ -700,36 +700,36 @@ __global__ __launch_bounds__(256, 2) void k_trmm_lds(const double* In, double* O
   // outside the block are zeroed when stored to LDS, after the products: a
   // load behind a branch, or one whose value is selected at once, makes the
   // compiler wait for every load in flight there.
-  const int ar = threadIdx.x >> 1, ak = (threadIdx.x & 1) * 16;
-  const int bk = threadIdx.x >> 3, bc = (threadIdx.x & 7) * 16;
+  const int ar = threadIdx.x >> 2, ak = (threadIdx.x & 3) * 8;
+  const int bk = threadIdx.x >> 4, bc = (threadIdx.x & 15) * 8;
   const bool a_row_ok = R0 + ar < p;
   const bool b_col_ok = C0 + bc < ldc;
   const int64_t a_row = static_cast<int64_t>(a_row_ok ? R0 + ar : p - 1) * p;
   const int64_t b_col = b_col_ok ? C0 + bc : 0;
-  double pa[16];
-  f64x2 pb[8];
+  double pa[8];
+  f64x2 pb[4];
   int kc_loaded = 0;
   auto load_chunk = [&](int kc) {
     kc_loaded = kc;
 #pragma unroll
-    for (int j = 0; j < 16; ++j) pa[j] = Lb[a_row + min(kc + ak + j, p - 1)];
+    for (int j = 0; j < 8; ++j) pa[j] = Lb[a_row + min(kc + ak + j, p - 1)];
     const double* src = In + (r0 + min(kc + bk, p - 1)) * ldc + b_col;
 #pragma unroll
-    for (int j = 0; j < 8; ++j) pb[j] = *reinterpret_cast<const f64x2*>(src + 2 * j);
+    for (int j = 0; j < 4; ++j) pb[j] = *reinterpret_cast<const f64x2*>(src + 2 * j);
   };
   auto store_chunk = [&]() {
     const int kc = kc_loaded;
 #pragma unroll
-    for (int j = 0; j < 16; ++j) As[ak + j][ar] = (a_row_ok && kc + ak + j < kend) ? pa[j] : 0.0;
+    for (int j = 0; j < 8; ++j) As[ak + j][ar] = (a_row_ok && kc + ak + j < kend) ? pa[j] : 0.0;
     const bool brow = kc + bk < kend && b_col_ok;
 #pragma unroll
-    for (int j = 0; j < 8; ++j)
+    for (int j = 0; j < 4; ++j)
       *reinterpret_cast<f64x2*>(&Bs[bk][bc + 2 * j]) = brow ? pb[j] : f64x2{0.0, 0.0};
   };
 
-  f64x4 acc[4][4];
+  f64x4 acc[2][4];
 #pragma unroll
-  for (int t = 0; t < 4; ++t)
+  for (int t = 0; t < 2; ++t)
 #pragma unroll
     for (int u = 0; u < 4; ++u) acc[t][u] = f64x4{};
   load_chunk(0);
@@ -745,10 +745,10 @@ __global__ __launch_bounds__(256, 2) void k_trmm_lds(const double* In, double* O
 #pragma unroll
       for (int u = 0; u < 4; ++u) b[u] = Bs[k][wc * 64 + u * 16 + li];
 #pragma unroll
-      for (int t = 0; t < 4; ++t) {
+      for (int t = 0; t < 2; ++t) {
         // Rows of this 16-row tile all lie above column kc + 4 kk: zero.
-        if (kc + 4 * kk > R0 + wr * 64 + t * 16 + 15) continue;  // uniform per wave
-        const double a = As[k][wr * 64 + t * 16 + li];
+        if (kc + 4 * kk > R0 + wr * 32 + t * 16 + 15) continue;  // uniform per wave
+        const double a = As[k][wr * 32 + t * 16 + li];
 #pragma unroll
         for (int u = 0; u < 4; ++u)
           acc[t][u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b[u], acc[t][u], 0, 0, 0);
@@ -760,12 +760,12 @@ __global__ __launch_bounds__(256, 2) void k_trmm_lds(const double* In, double* O
   }
   // acc[t][u][q] = D[g + 4 q][li] of the 16 x 16 tile (t, u).
 #pragma unroll
-  for (int t = 0; t < 4; ++t)
+  for (int t = 0; t < 2; ++t)
 #pragma unroll
     for (int u = 0; u < 4; ++u)
 #pragma unroll
       for (int qq = 0; qq < 4; ++qq) {
-        const int row = R0 + wr * 64 + t * 16 + g + 4 * qq;
+        const int row = R0 + wr * 32 + t * 16 + g + 4 * qq;
         const int64_t col = C0 + wc * 64 + u * 16 + li;
         if (row < p && col < ldc) {
           const int64_t o = (r0 + row) * ldc + col;
@@ -796,7 +796,7 @@ hipError_t launch_trmm_lds(const double* In, double* Out, int64_t ldc, const int
   const int64_t items = static_cast<int64_t>(m) * nrt * nct;
   if (items > std::numeric_limits<int32_t>::max() / 2) return hipErrorInvalidValue;
   const unsigned grid = static_cast<unsigned>((items + kXcds - 1) / kXcds * kXcds);
-  k_trmm_lds<<<grid, 256, 0, s>>>(In, Out, ldc, off, m, static_cast<int32_t>(nrt),
+  k_trmm_lds<<<grid, 512, 0, s>>>(In, Out, ldc, off, m, static_cast<int32_t>(nrt),
                                   static_cast<int32_t>(nct), goff, Linv, out32);
   return hipGetLastError();
 }
