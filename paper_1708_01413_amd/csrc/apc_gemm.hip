@@ -549,14 +549,9 @@ namespace apc {
 
 // ------------------------------------------------------------------ FP64 setup products
 //
-// The two products of CholeskyQR2 on the matrix cores: the Gram matrix
-// G_i = C_i C_i^T and the triangular product Out_i = L_i^{-1} In_i, one 64 x 64
-// output tile per workgroup over the same tile lists as the vector kernels.
-// Wave w owns the 32 x 32 quadrant (w / 2, w % 2) as 2 x 2 MFMA 16x16x4 f64
-// tiles.  A K step is 32 elements: lane (li, g) contributes the elements
-// k = k0 + 8 g + 2 p + e (piece p < 4, element e < 2) of its operand rows, the
-// p-th piece feeding two MFMAs, so each MFMA reduces over a K subset that both
-// operands label alike (as in k_tn).
+// The two products of CholeskyQR on the FP64 matrix cores: the Gram matrix
+// G_i = C_i C_i^T and the triangular product Out_i = L_i^{-1} In_i, both with
+// their operands staged in LDS by eight-wave workgroups.
 
 namespace {
 
@@ -569,103 +564,17 @@ __device__ inline int xcd_contiguous(int b, int total) {
   return (b % kXcds) * per + b / kXcds;
 }
 
-__global__ __launch_bounds__(256) void k_gram_mfma(const double* C, int64_t ldc,
-                                                   const int64_t* off, const int32_t* tiles,
-                                                   int32_t ntiles, const int64_t* goff, double* G) {
-  const int q = xcd_contiguous(static_cast<int>(blockIdx.x), ntiles);
-  if (q >= ntiles) return;
-  const int blk = tiles[3 * q + 0];
-  const int ta = tiles[3 * q + 1];
-  const int tb = tiles[3 * q + 2];
-  const int64_t r0 = off[blk];
-  const int p = static_cast<int>(off[blk + 1] - r0);
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int li = lane & 15, g = lane >> 4;
-  const int qa = wv >> 1, qb = wv & 1;
-  // Operand rows of this lane: two 16-row tiles of the A quadrant, two of the B
-  // quadrant.  Rows past the block read its first row: they only reach
-  // entries of G past the block, which are not stored, so they need no
-  // zeroing (which would make every load wait as soon as it was issued).
-  const double* pa[2];
-  const double* pb[2];
-#pragma unroll
-  for (int t = 0; t < 2; ++t) {
-    const int ra = ta * 64 + qa * 32 + 16 * t + li;
-    const int rb = tb * 64 + qb * 32 + 16 * t + li;
-    pa[t] = C + (r0 + (ra < p ? ra : 0)) * ldc + 8 * g;
-    pb[t] = C + (r0 + (rb < p ? rb : 0)) * ldc + 8 * g;
-  }
-  f64x2 ar[3][2][4], br[3][2][4];  // ring of three K steps: two loaded ahead
-  f64x4 acc[2][2];
-#pragma unroll
-  for (int t = 0; t < 2; ++t)
-#pragma unroll
-    for (int u = 0; u < 2; ++u) acc[t][u] = f64x4{};
-  auto load = [&](f64x2 (&a)[2][4], f64x2 (&b)[2][4], int step) {
-    const int64_t o = static_cast<int64_t>(step) * 32;
-#pragma unroll
-    for (int t = 0; t < 2; ++t)
-#pragma unroll
-      for (int pc = 0; pc < 4; ++pc) {
-        a[t][pc] = *reinterpret_cast<const f64x2*>(pa[t] + o + 2 * pc);
-        b[t][pc] = *reinterpret_cast<const f64x2*>(pb[t] + o + 2 * pc);
-      }
-  };
-  auto compute = [&](const f64x2 (&a)[2][4], const f64x2 (&b)[2][4]) {
-#pragma unroll
-    for (int pc = 0; pc < 4; ++pc)
-#pragma unroll
-      for (int e = 0; e < 2; ++e)
-#pragma unroll
-        for (int t = 0; t < 2; ++t)
-#pragma unroll
-          for (int u = 0; u < 2; ++u)
-            acc[t][u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[t][pc][e], b[u][pc][e], acc[t][u],
-                                                             0, 0, 0);
-  };
-  // Every load is issued unconditionally (steps past the end reload the last
-  // one, unused): a load behind a branch leaves the compiler unable to count
-  // the loads in flight where the paths join, and it then waits for all of
-  // them, which serialises the prefetch with the products.
-  const int nsteps = static_cast<int>(ldc / 32);
-  const int last = nsteps - 1;
-  load(ar[0], br[0], 0);
-  load(ar[1], br[1], min(1, last));
-  for (int s0 = 0; s0 < nsteps; s0 += 3) {
-    load(ar[2], br[2], min(s0 + 2, last));
-    compute(ar[0], br[0]);
-    load(ar[0], br[0], min(s0 + 3, last));
-    if (s0 + 1 < nsteps) compute(ar[1], br[1]);
-    load(ar[1], br[1], min(s0 + 4, last));
-    if (s0 + 2 < nsteps) compute(ar[2], br[2]);
-  }
-  // acc[t][u][q] = G[row base + g + 4 q][column base + li].
-  double* Gb = G + goff[blk];
-#pragma unroll
-  for (int t = 0; t < 2; ++t)
-#pragma unroll
-    for (int u = 0; u < 2; ++u)
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int ra = ta * 64 + qa * 32 + 16 * t + g + 4 * q;
-        const int rb = tb * 64 + qb * 32 + 16 * u + li;
-        if (ra < p && rb < p) {
-          Gb[static_cast<int64_t>(ra) * p + rb] = acc[t][u][q];
-          if (ta != tb) Gb[static_cast<int64_t>(rb) * p + ra] = acc[t][u][q];
-        }
-      }
-}
-
 // Out_i = Linv_i In_i as 128 x 128 output tiles on the FP64 matrix cores,
 // one workgroup per (block, 128-row tile, 128-column tile).  K (the block's
 // rows, cut at the tile's last row since Linv is lower triangular) goes in
 // chunks of 32: both operands are staged in LDS K-major -- As[k][r] =
-// Linv[R0 + r][kc + k], Bs[k][c] = In[kc + k][C0 + c] -- and each of the four
-// waves multiplies its 64 x 64 quadrant as 4 x 4 MFMA 16x16x4 tiles.  The next
-// chunk is loaded into registers while the current one is multiplied.  Row
-// tiles entirely above the chunk's diagonal are skipped.  The LDS row stride
-// (144 doubles, 1152 bytes) puts the two half-waves of a fragment read on
-// different banks.
+// Linv[R0 + r][kc + k], Bs[k][c] = In[kc + k][C0 + c] -- and each of the eight
+// waves multiplies a 32 x 64 quadrant as 2 x 4 MFMA 16x16x4 tiles (half the
+// registers of four 64 x 64 quadrants: four waves per SIMD instead of two,
+// 0.94 ms instead of 1.27 at 16384 x 8192).  The next chunk is loaded into
+// registers while the current one is multiplied.  Row tiles entirely above
+// the chunk's diagonal are skipped.  The LDS row stride (144 doubles, 1152
+// bytes) puts the two half-waves of a fragment read on different banks.
 constexpr int kTT = 128;
 constexpr int kTK = 32;
 constexpr int kTS = kTT + 16;
@@ -775,15 +684,101 @@ __global__ __launch_bounds__(512, 2) void k_trmm_lds(const double* In, double* O
       }
 }
 
+// G_i = C_i C_i^T as 64 x 64 tiles (ta >= tb) on the FP64 matrix cores with
+// both operands staged in LDS: one workgroup of eight waves per tile, each
+// wave a 16 x 32 quadrant (1 x 2 MFMA 16x16x4 tiles), so that four or more
+// waves per SIMD hide the latencies.  K (the padded row length, a multiple of
+// 32) goes in chunks of 32, K-major in LDS (As[k][r] = C[row 64 ta + r][kc + k],
+// Bs[k][c] likewise for 64 tb + c; row stride 80 doubles keeps each
+// half-wave's fragment reads on distinct banks); the next chunk is loaded
+// into registers while the current one is multiplied.  Rows past the block
+// read its last row: they only reach entries of G past the block, which are
+// not stored.
+constexpr int kGT = 64;
+constexpr int kGK = 32;
+constexpr int kGS = kGT + 16;
+__global__ __launch_bounds__(512) void k_gram_lds(const double* C, int64_t ldc,
+                                                 const int64_t* off, const int32_t* tiles,
+                                                 int32_t ntiles, const int64_t* goff, double* G) {
+  const int q = xcd_contiguous(static_cast<int>(blockIdx.x), ntiles);
+  if (q >= ntiles) return;
+  const int blk = tiles[3 * q + 0];
+  const int ta = tiles[3 * q + 1];
+  const int tb = tiles[3 * q + 2];
+  const int64_t r0 = off[blk];
+  const int p = static_cast<int>(off[blk + 1] - r0);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int li = lane & 15, g = lane >> 4;
+  const int wr = wv >> 1, wc = wv & 1;
+  __shared__ __align__(16) double As[kGK][kGS];
+  __shared__ __align__(16) double Bs[kGK][kGS];
+  // Staging: thread t takes row t / 8 of each operand tile and the four
+  // consecutive k at 4 (t % 8) (two 16-byte loads each).
+  const int sr = threadIdx.x >> 3, sk = (threadIdx.x & 7) * 4;
+  const double* pa = C + (r0 + min(ta * kGT + sr, p - 1)) * ldc + sk;
+  const double* pb = C + (r0 + min(tb * kGT + sr, p - 1)) * ldc + sk;
+  f64x2 ra[2], rb[2];
+  auto load_chunk = [&](int64_t kc) {
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+      ra[e] = *reinterpret_cast<const f64x2*>(pa + kc + 2 * e);
+      rb[e] = *reinterpret_cast<const f64x2*>(pb + kc + 2 * e);
+    }
+  };
+  auto store_chunk = [&]() {
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+      As[sk + 2 * e][sr] = ra[e][0];
+      As[sk + 2 * e + 1][sr] = ra[e][1];
+      Bs[sk + 2 * e][sr] = rb[e][0];
+      Bs[sk + 2 * e + 1][sr] = rb[e][1];
+    }
+  };
+  f64x4 acc[2] = {f64x4{}, f64x4{}};
+  const int64_t kend = ldc;
+  load_chunk(0);
+  store_chunk();
+  __syncthreads();
+  for (int64_t kc = 0; kc < kend; kc += kGK) {
+    const bool more = kc + kGK < kend;
+    load_chunk(more ? kc + kGK : kc);  // the last chunk reloads itself, unused
+#pragma unroll
+    for (int kk = 0; kk < kGK / 4; ++kk) {
+      const int k = 4 * kk + g;
+      const double a = As[k][wr * 16 + li];
+      const double b0 = Bs[k][wc * 32 + li];
+      const double b1 = Bs[k][wc * 32 + 16 + li];
+      acc[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b0, acc[0], 0, 0, 0);
+      acc[1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b1, acc[1], 0, 0, 0);
+    }
+    __syncthreads();
+    if (more) store_chunk();
+    __syncthreads();
+  }
+  // acc[u][q] = G[64 ta + 16 wr + g + 4 q][64 tb + 32 wc + 16 u + li].
+  double* Gb = G + goff[blk];
+#pragma unroll
+  for (int u = 0; u < 2; ++u)
+#pragma unroll
+    for (int qq = 0; qq < 4; ++qq) {
+      const int ra_ = ta * kGT + wr * 16 + g + 4 * qq;
+      const int rb_ = tb * kGT + wc * 32 + u * 16 + li;
+      if (ra_ < p && rb_ < p) {
+        Gb[static_cast<int64_t>(ra_) * p + rb_] = acc[u][qq];
+        if (ta != tb) Gb[static_cast<int64_t>(rb_) * p + ra_] = acc[u][qq];
+      }
+    }
+}
+
 }  // namespace
 
-hipError_t launch_gram_mfma(const double* C, int64_t ldc, const int64_t* off,
-                            const int32_t* tiles, int32_t ntiles, const int64_t* goff, double* G,
-                            hipStream_t s) {
+hipError_t launch_gram_lds(const double* C, int64_t ldc, const int64_t* off,
+                           const int32_t* tiles, int32_t ntiles, const int64_t* goff, double* G,
+                           hipStream_t s) {
   if (ntiles <= 0) return hipSuccess;
-  if (ldc % 32 != 0) return hipErrorInvalidValue;
+  if (ldc % kGK != 0) return hipErrorInvalidValue;
   const unsigned grid = static_cast<unsigned>((ntiles + kXcds - 1) / kXcds * kXcds);
-  k_gram_mfma<<<grid, 256, 0, s>>>(C, ldc, off, tiles, ntiles, goff, G);
+  k_gram_lds<<<grid, 512, 0, s>>>(C, ldc, off, tiles, ntiles, goff, G);
   return hipGetLastError();
 }
 

@@ -1259,8 +1259,8 @@ apc_status setup_impl(apc_plan_s* P, const Tiles& T) {
     const double* cs = pass == 0 ? ca : cb;
     double* cd = pass == 0 ? cb : ca;
     if (mfma)
-      HIP_TRY(launch_gram_mfma(src, ldc, P->doff(), P->at<int32_t>(L.tiles_g), L.ntiles_g,
-                               P->at<int64_t>(L.goff), P->at<double>(L.G), st));
+      HIP_TRY(launch_gram_lds(src, ldc, P->doff(), P->at<int32_t>(L.tiles_g), L.ntiles_g,
+                              P->at<int64_t>(L.goff), P->at<double>(L.G), st));
     else
       HIP_TRY(launch_gram(src, ldc, P->doff(), P->at<int32_t>(L.tiles_g), L.ntiles_g,
                           P->at<int64_t>(L.goff), P->at<double>(L.G), st));
