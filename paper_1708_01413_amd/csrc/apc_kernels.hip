@@ -997,47 +997,81 @@ __global__ __launch_bounds__(512) void k_tri_inv(const int64_t* off, const int64
   __shared__ double dl[kNB][kNB + 1];
   __shared__ double di[kNB][kNB + 1];
   __shared__ double pan[kNB][kNB + 1];
-  for (int I0 = J0 + kNB; I0 < p; I0 += kNB) {
+  // The steps (I0, K0) -- row blocks I0 = J0 + 32, ..., K0 = J0 .. I0 - 32 --
+  // run in order; the next step's two blocks are loaded into registers while
+  // the current one is multiplied (thread t stages entries t and t + 512 of
+  // each: row e / 32, column e % 32).  A step reads Linv[K0][J0] with K0 < I0,
+  // written by this workgroup at the end of an earlier row; the last step of
+  // a row, which reads the block the previous row wrote, is loaded during the
+  // step before it, after that write.
+  const int sr = tid >> 5, sq = tid & 31;
+  double vl[2], vp[2];
+  auto load_step = [&](int I, int K) {
+    const int nb = min(kNB, p - I);
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int r = sr + 16 * u;
+      vl[u] = Gb[static_cast<int64_t>(I + min(r, nb - 1)) * p + K + sq];
+      vp[u] = Lb[static_cast<int64_t>(K + r) * p + J0 + sq];
+    }
+  };
+  int I0 = J0 + kNB, K0 = J0;
+  load_step(I0, K0);
+  double t0 = 0.0, t1 = 0.0;
+  for (;;) {
     const int nbI = min(kNB, p - I0);
     __syncthreads();
-    // L_II^{-1} into LDS (zero-padded to 32 x 32).
-    for (int e = tid; e < kNB * kNB; e += 512) {
-      const int i = e / kNB, q = e % kNB;
-      di[i][q] = (i < nbI && q <= i) ? Lb[static_cast<int64_t>(I0 + i) * p + I0 + q] : 0.0;
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int r = sr + 16 * u;
+      dl[r][sq] = r < nbI ? vl[u] : 0.0;
+      pan[r][sq] = vp[u];
     }
-    double t0 = 0.0, t1 = 0.0;
-    for (int K0 = J0; K0 < I0; K0 += kNB) {
-      __syncthreads();
-      // dl <- L[I0 + r][K0 + q], pan <- Linv[K0 + r][J0 + q]: K0 + r < I0 <= p - 1
-      // and J0 + q < J0 + kNB <= I0 (block column J is full).
+    if (K0 == J0) {
+      // L_II^{-1} into LDS (zero-padded to 32 x 32).
       for (int e = tid; e < kNB * kNB; e += 512) {
-        const int r = e / kNB, q = e % kNB;
-        dl[r][q] = r < nbI ? Gb[static_cast<int64_t>(I0 + r) * p + K0 + q] : 0.0;
-        pan[r][q] = Lb[static_cast<int64_t>(K0 + r) * p + J0 + q];
+        const int i = e / kNB, q = e % kNB;
+        di[i][q] = (i < nbI && q <= i) ? Lb[static_cast<int64_t>(I0 + i) * p + I0 + q] : 0.0;
       }
+    }
+    __syncthreads();
+    int nI = I0, nK = K0 + kNB;
+    const bool row_end = nK >= I0;
+    if (row_end) {
+      nI = I0 + kNB;
+      nK = J0;
+    }
+    const bool more = nI < p;
+    load_step(more ? nI : I0, more ? nK : K0);  // past the end: reload, unused
+#pragma unroll 8
+    for (int k = 0; k < kNB; ++k) {
+      const double l = dl[ti][k];
+      t0 = fma(l, pan[k][tc2], t0);
+      t1 = fma(l, pan[k][tc2 + 1], t1);
+    }
+    if (row_end) {
+      // Linv[I][J] = -L_II^{-1} (the row's sum).
       __syncthreads();
+      dl[ti][tc2] = t0;
+      dl[ti][tc2 + 1] = t1;
+      __syncthreads();
+      double o0 = 0.0, o1 = 0.0;
 #pragma unroll 8
-      for (int k = 0; k < kNB; ++k) {
-        const double l = dl[ti][k];
-        t0 = fma(l, pan[k][tc2], t0);
-        t1 = fma(l, pan[k][tc2 + 1], t1);
+      for (int q = 0; q < kNB; ++q) {
+        const double d = di[ti][q];  // zero above the diagonal
+        o0 = fma(d, dl[q][tc2], o0);
+        o1 = fma(d, dl[q][tc2 + 1], o1);
       }
+      if (ti < nbI) {
+        Lb[static_cast<int64_t>(I0 + ti) * p + J0 + tc2] = -o0;
+        Lb[static_cast<int64_t>(I0 + ti) * p + J0 + tc2 + 1] = -o1;
+      }
+      t0 = 0.0;
+      t1 = 0.0;
+      if (!more) break;
     }
-    __syncthreads();
-    dl[ti][tc2] = t0;
-    dl[ti][tc2 + 1] = t1;
-    __syncthreads();
-    double o0 = 0.0, o1 = 0.0;
-#pragma unroll 8
-    for (int q = 0; q < kNB; ++q) {
-      const double d = di[ti][q];  // zero above the diagonal
-      o0 = fma(d, dl[q][tc2], o0);
-      o1 = fma(d, dl[q][tc2 + 1], o1);
-    }
-    if (ti < nbI) {
-      Lb[static_cast<int64_t>(I0 + ti) * p + J0 + tc2] = -o0;
-      Lb[static_cast<int64_t>(I0 + ti) * p + J0 + tc2 + 1] = -o1;
-    }
+    I0 = nI;
+    K0 = nK;
   }
 }
 
