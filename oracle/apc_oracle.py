@@ -31,7 +31,10 @@ design notes):
                     from the (m-1)n eigenvalues equal to 1-gamma in App. A, and
                     gamma in [0, 2] from the definition of S, eq. (6)).
   R5 metric      -- relative l2 error ||x_bar - x*|| / ||x*|| (Sec. 5); with k
-                    right-hand sides, per column, and the maximum over columns.
+                    right-hand sides the paper is silent: the error of each
+                    column, and the maximum over columns is the figure that
+                    tolerances gate on (rel_error); the Frobenius form over all
+                    columns (rel_error_fro) is reported beside it.
   R6 rank        -- a block is rank deficient when min|diag R_i| <=
                     n * eps * max|diag R_i| (thin QR of A_i^T).
   R7 singular    -- no unique solution when mu_min <= n * eps (App. A, steady
@@ -236,15 +239,27 @@ def apc_step(Qt, x: np.ndarray, xbar: np.ndarray, gamma: float, eta: float):
 
 
 def rel_error(xbar: np.ndarray, xstar: np.ndarray) -> float:
-    """Relative l2 error ||x_bar - x*|| / ||x*|| (Sec. 5), max over columns (R5)."""
+    """Relative l2 error ||x_bar - x*|| / ||x*|| (Sec. 5).  With k columns:
+    the error of every column on its own, and the largest of them (R5)."""
     xb, xs = _as_cols(xbar), _as_cols(xstar)
-    return float(np.max(np.linalg.norm(xb - xs, axis=0) / np.linalg.norm(xs, axis=0)))
+    per_col = [np.sqrt(np.sum((xb[:, c] - xs[:, c]) ** 2)) / np.sqrt(np.sum(xs[:, c] ** 2))
+               for c in range(xs.shape[1])]
+    return float(max(per_col))
+
+
+def rel_error_fro(xbar: np.ndarray, xstar: np.ndarray) -> float:
+    """The same error taken over all k columns at once, ||X_bar - X*||_F / ||X*||_F
+    (the figure reported beside rel_error, R5).  Equal to rel_error for k = 1."""
+    xb, xs = _as_cols(xbar), _as_cols(xstar)
+    return float(np.sqrt(np.sum((xb - xs) ** 2)) / np.sqrt(np.sum(xs ** 2)))
 
 
 def residual(A: np.ndarray, B: np.ndarray, X: np.ndarray) -> float:
-    """||B - A X||_F / ||B||_F, the residual of eq. (1)."""
+    """Relative residual of eq. (1) over all k columns, ||B - A X||_F / ||B||_F
+    (the convergence monitor a solver can evaluate without knowing x*)."""
     B = _as_cols(B)
-    return float(np.linalg.norm(B - np.asarray(A) @ _as_cols(X)) / np.linalg.norm(B))
+    R = B - np.asarray(A, dtype=np.float64) @ _as_cols(X)
+    return float(np.sqrt(np.sum(R ** 2)) / np.sqrt(np.sum(B ** 2)))
 
 
 def apc_run(A, B, off, T: int, gamma: float | None = None, eta: float | None = None,

@@ -4,11 +4,15 @@ Calls only the FP64 oracle and the seeded input generators.  Outputs:
 
 * tall_gauss_16384x8192_m64.npz: the oracle's spectrum (mu_min, mu_max),
   Theorem 1's parameters, the relative error curve err(t) for t = 0..T and
-  x_bar(t) at every 8th coordinate for a few t;
+  the whole vector x_bar(t) for a few t;
 * shifted_uneven_8192_k64.npz: the same for N = n = 8192, A = G/sqrt(n) + 2I,
-  64 uneven blocks, 64 right-hand sides (every 64th coordinate of 8 columns);
+  64 uneven blocks, 64 right-hand sides: the error curve as the largest
+  column error (err, the figure tolerances gate on) and in Frobenius form
+  (err_fro), and the whole n x 64 x_bar(t) for three t;
 * many_small_systems_256.npz: for each of the 256 independent systems, its
-  parameters and x_bar(T) at every 16th coordinate after T updates.
+  parameters and the whole x_bar(T) after T updates.
+
+Every error figure comes from the oracle's own rel_error / rel_error_fro.
 
 Run:  python tests/golden/make_golden.py [tall|batched|many]   (a few minutes)
 """
@@ -27,7 +31,6 @@ from paper_1708_01413_amd import synth  # noqa: E402
 
 T = 60
 CHECK_T = [0, 1, 2, 5, 10, 20, 30, 33, 40, 50, 60]
-STRIDE = 8
 
 
 def main():
@@ -41,26 +44,23 @@ def main():
     g, e, rho = O.optimal_params(mu_min, mu_max)
     print(f"spectrum {time.time() - t0:.1f}s mu=[{mu_min:.6g}, {mu_max:.6g}] gamma={g:.9g} "
           f"eta={e:.9g} rho={rho:.6g}", flush=True)
-    idx = np.arange(0, S.n, STRIDE)
     err = [O.rel_error(xbar, S.xstar)]
-    samples = {0: xbar[idx, 0].copy()}
+    full = {0: xbar[:, 0].copy()}
     for t in range(1, T + 1):
         x, xbar = O.apc_step(Qt, x, xbar, g, e)
         err.append(O.rel_error(xbar, S.xstar))
         if t in CHECK_T:
-            samples[t] = xbar[idx, 0].copy()
+            full[t] = xbar[:, 0].copy()
     print(f"iterate {time.time() - t0:.1f}s err(T)={err[-1]:.3e}", flush=True)
     out = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tall_gauss_16384x8192_m64.npz")
     np.savez(out, mu_min=mu_min, mu_max=mu_max, gamma=g, eta=e, rho=rho, err=np.array(err),
-             check_t=np.array(CHECK_T), idx=idx,
-             samples=np.stack([samples[t] for t in CHECK_T]), xstar_norm=np.linalg.norm(S.xstar))
+             check_t=np.array(CHECK_T), xbar=np.stack([full[t] for t in CHECK_T]),
+             xstar_norm=np.linalg.norm(S.xstar), xstar_max=np.max(np.abs(S.xstar)))
     print("wrote", out)
 
 
 BATCHED_T = 56
-BATCHED_CHECK = [0, 1, 2, 5, 10, 20, 34, 45, 56]
-BATCHED_COLS = [0, 1, 7, 13, 21, 34, 55, 63]
-BATCHED_STRIDE = 64
+BATCHED_CHECK = [5, 20, 56]
 
 
 def batched():
@@ -73,29 +73,25 @@ def batched():
     g, e, rho = O.optimal_params(mu_min, mu_max)
     print(f"batched: setup {time.time() - t0:.1f}s mu=[{mu_min:.6g}, {mu_max:.6g}] rho={rho:.6g}",
           flush=True)
-    idx = np.arange(0, S.n, BATCHED_STRIDE)
-    cols = np.array(BATCHED_COLS)
     xs = S.xstar
-    def err_of(xb):   # Frobenius norm over all columns, relative to ||X*||_F
-        return float(np.linalg.norm(xb - xs) / np.linalg.norm(xs))
-    err = [err_of(xbar)]
-    samples = {0: xbar[np.ix_(idx, cols)].copy()}
+    err, err_fro = [O.rel_error(xbar, xs)], [O.rel_error_fro(xbar, xs)]
+    full = {}
     for t in range(1, BATCHED_T + 1):
         x, xbar = O.apc_step(Qt, x, xbar, g, e)
-        err.append(err_of(xbar))
+        err.append(O.rel_error(xbar, xs))
+        err_fro.append(O.rel_error_fro(xbar, xs))
         if t in BATCHED_CHECK:
-            samples[t] = xbar[np.ix_(idx, cols)].copy()
+            full[t] = xbar.copy()
     print(f"batched: iterate {time.time() - t0:.1f}s err(T)={err[-1]:.3e}", flush=True)
     out = os.path.join(os.path.dirname(os.path.abspath(__file__)), "shifted_uneven_8192_k64.npz")
     np.savez(out, mu_min=mu_min, mu_max=mu_max, gamma=g, eta=e, rho=rho, err=np.array(err),
-             check_t=np.array(BATCHED_CHECK), idx=idx, cols=cols,
-             samples=np.stack([samples[t] for t in BATCHED_CHECK]),
-             xstar_norm=np.linalg.norm(xs))
+             err_fro=np.array(err_fro), check_t=np.array(BATCHED_CHECK),
+             xbar=np.stack([full[t] for t in BATCHED_CHECK]),
+             xstar_norm=np.linalg.norm(xs, axis=0), xstar_max=np.max(np.abs(xs), axis=0))
     print("wrote", out)
 
 
 MANY_T = 20
-MANY_STRIDE = 16
 
 
 def many():
@@ -109,13 +105,13 @@ def many():
         xb = out["xbar"][:, 0]
         gam.append(g)
         eta.append(e)
-        vals.append(xb[::MANY_STRIDE])
+        vals.append(xb)
         starts.append(starts[-1] + len(vals[-1]))
-        errs.append(np.linalg.norm(xb - S.xstar) / np.linalg.norm(S.xstar))
+        errs.append(O.rel_error(xb, S.xstar))
     print(f"many: {time.time() - t0:.1f}s, err(T) in [{min(errs):.2e}, {max(errs):.2e}]", flush=True)
     out = os.path.join(os.path.dirname(os.path.abspath(__file__)), "many_small_systems_256.npz")
-    np.savez(out, gamma=np.array(gam), eta=np.array(eta), T=MANY_T, stride=MANY_STRIDE,
-             starts=np.array(starts), samples=np.concatenate(vals), err=np.array(errs))
+    np.savez(out, gamma=np.array(gam), eta=np.array(eta), T=MANY_T,
+             starts=np.array(starts), xbar=np.concatenate(vals), err=np.array(errs))
     print("wrote", out)
 
 

@@ -408,6 +408,67 @@ def test_rejects_block_wider_than_n():
         O.factor(S.A, S.off)
 
 
+# --------------------------------------------------------------------------- Sec. 5 metric, eq. (1) residual
+
+
+def test_error_metrics_on_a_hand_worked_case():
+    """Sec. 5's relative error, worked by hand.  Columns of X*: (3, 4) and (0, 2), norms 5
+    and 2.  X_bar differs by (0, 0.5) in column 0 and by (0.1, 0) in column 1, so the
+    column errors are 0.5/5 = 0.1 and 0.1/2 = 0.05; the largest is 0.1 (R5's gate) and the
+    Frobenius form is sqrt(0.25 + 0.01)/sqrt(25 + 4) = sqrt(0.26/29)."""
+    xs = np.array([[3.0, 0.0], [4.0, 2.0]])
+    xb = np.array([[3.0, 0.1], [4.5, 2.0]])
+    assert O.rel_error(xb, xs) == pytest.approx(0.1, rel=1e-15)
+    assert O.rel_error_fro(xb, xs) == pytest.approx(np.sqrt(0.26 / 29.0), rel=1e-15)
+    # one column only, as a 1-D vector: both forms are the plain l2 ratio
+    assert O.rel_error(xb[:, 1], xs[:, 1]) == pytest.approx(0.05, rel=1e-15)
+    assert O.rel_error_fro(xb[:, 0], xs[:, 0]) == pytest.approx(0.1, rel=1e-15)
+
+
+def test_error_metrics_invariances():
+    """The per-column gate does not change when each column (of both X_bar and X*) is
+    scaled by its own factor; the Frobenius form does, and it never exceeds the gate.
+    A column that is exact does not lower the gate."""
+    rng = np.random.default_rng(3)
+    xs = rng.standard_normal((40, 5))
+    xb = xs + 1e-3 * rng.standard_normal((40, 5)) * np.array([1, 10, 0.1, 3, 0.5])
+    D = np.array([1e-3, 7.0, 0.2, 1e4, 1.0])
+    assert O.rel_error(xb * D, xs * D) == pytest.approx(O.rel_error(xb, xs), rel=1e-13)
+    assert O.rel_error_fro(xb * D, xs * D) != pytest.approx(O.rel_error_fro(xb, xs), rel=1e-3)
+    assert O.rel_error_fro(xb, xs) <= O.rel_error(xb, xs) * (1 + 1e-15)
+    worst = np.argmax(np.linalg.norm(xb - xs, axis=0) / np.linalg.norm(xs, axis=0))
+    xb2 = xb.copy()
+    xb2[:, (worst + 1) % 5] = xs[:, (worst + 1) % 5]
+    assert O.rel_error(xb2, xs) == pytest.approx(O.rel_error(xb, xs), rel=1e-15)
+
+
+def test_residual_of_a_perturbed_direct_solve():
+    """Eq. (1): with X = A^{-1}(B + E) from LAPACK, B - A X = -E exactly up to rounding,
+    so the relative residual is ||E||_F / ||B||_F; for X = X* it vanishes."""
+    S = synth.shifted_square(60, 4, k=3, shift=2.0, seed=24)
+    E = 1e-4 * np.random.default_rng(25).standard_normal(S.B.shape)
+    X = np.linalg.solve(S.A, S.B + E)
+    want = np.sqrt(np.sum(E ** 2) / np.sum(S.B ** 2))
+    assert O.residual(S.A, S.B, X) == pytest.approx(want, rel=1e-8)
+    assert O.residual(S.A, S.B, S.xstar) < 1e-14
+    # one column carries the whole perturbation: the residual spans all columns
+    E1 = np.zeros_like(S.B)
+    E1[:, 1] = E[:, 1]
+    X1 = np.linalg.solve(S.A, S.B + E1)
+    assert O.residual(S.A, S.B, X1) == pytest.approx(
+        np.linalg.norm(E[:, 1]) / np.linalg.norm(S.B), rel=1e-8)
+
+
+def test_residual_with_orthonormal_columns_is_the_error():
+    """A tall A with orthonormal columns keeps lengths, so ||B - A X|| = ||X* - X|| and
+    ||B|| = ||X*||: the residual equals the Frobenius error."""
+    rng = np.random.default_rng(26)
+    Qm, _ = np.linalg.qr(rng.standard_normal((50, 12)))
+    xs = rng.standard_normal((12, 2))
+    xb = xs + 1e-2 * rng.standard_normal((12, 2))
+    assert O.residual(Qm, Qm @ xs, xb) == pytest.approx(O.rel_error_fro(xb, xs), rel=1e-12)
+
+
 # --------------------------------------------------------------------------- Table 2 context
 
 

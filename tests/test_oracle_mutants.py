@@ -72,6 +72,32 @@ def _X_missing_inverse(A, off):
     return sum(Ai.T @ Ai for Ai in O.blocks(A, off)) / m        # (A_i A_i^T)^{-1} dropped
 
 
+def _rel_error_mean(xbar, xstar):
+    xb, xs = O._as_cols(xbar), O._as_cols(xstar)
+    return float(np.mean(np.linalg.norm(xb - xs, axis=0) / np.linalg.norm(xs, axis=0)))  # mean, not max
+
+
+def _rel_error_as_fro(xbar, xstar):
+    xb, xs = O._as_cols(xbar), O._as_cols(xstar)
+    return float(np.linalg.norm(xb - xs) / np.linalg.norm(xs))  # Frobenius in place of the gate
+
+
+def _rel_error_fro_unnormalised(xbar, xstar):
+    xb, xs = O._as_cols(xbar), O._as_cols(xstar)
+    return float(np.linalg.norm(xb - xs))                        # ||X*|| dropped
+
+
+def _residual_max_column(A, B, X):
+    B = O._as_cols(B)
+    R = B - np.asarray(A) @ O._as_cols(X)
+    return float(np.max(np.linalg.norm(R, axis=0)) / np.linalg.norm(B))  # max column, not F-norm
+
+
+def _residual_sign(A, B, X):
+    B = O._as_cols(B)
+    return float(np.linalg.norm(B + np.asarray(A) @ O._as_cols(X)) / np.linalg.norm(B))  # B + AX
+
+
 _orig_params = O.optimal_params
 _orig_adjoint = O.apc_adjoint
 
@@ -172,6 +198,15 @@ MUTANTS = [
                                               "test_apc_average_is_preconditioned_heavy_ball"]),
     ("dhbm_step", _dhbm_step_wrong_sign, ["test_dhbm_step_is_the_heavy_ball_recursion",
                                           "test_dhbm_converges_to_direct_solve"]),
+    ("rel_error", _rel_error_mean, ["test_error_metrics_on_a_hand_worked_case",
+                                    "test_error_metrics_invariances"]),
+    ("rel_error", _rel_error_as_fro, ["test_error_metrics_on_a_hand_worked_case",
+                                      "test_error_metrics_invariances"]),
+    ("rel_error_fro", _rel_error_fro_unnormalised, ["test_error_metrics_on_a_hand_worked_case",
+                                                    "test_residual_with_orthonormal_columns_is_the_error"]),
+    ("residual", _residual_max_column, ["test_residual_of_a_perturbed_direct_solve"]),
+    ("residual", _residual_sign, ["test_residual_of_a_perturbed_direct_solve",
+                                  "test_residual_with_orthonormal_columns_is_the_error"]),
 ]
 
 
