@@ -477,12 +477,16 @@ class UnrolledAPC:
                     plan.iterate(T)
                     ctx.plan, ctx.T, ctx.ckpt = plan, T, ckpt_every
                     ctx.params = (float(gamma), float(eta))
+                    ctx.b = b.detach().clone()
                     return plan.xbar()
 
                 @staticmethod
                 def backward(ctx, gx):
+                    # The adjoint re-runs the forward from the plan's last restart;
+                    # another forward on the same plan may have restarted it since.
                     plan = ctx.plan
                     plan.set_params(*ctx.params)
+                    plan.restart(ctx.b)
                     dB, dg, de = plan.backward(gx, ctx.T, ctx.ckpt)
                     return (dB, torch.tensor(dg, dtype=torch.float64),
                             torch.tensor(de, dtype=torch.float64), None, None, None)

@@ -331,7 +331,8 @@ __global__ __launch_bounds__(256) void k_batch_resid(const BatchSys* sys, const 
 }
 
 // Per system: relres = sqrt(sum of its items' partials) / ||b||; a system whose
-// relres <= rtol (or is not finite) is deactivated.  One thread per system.
+// relres <= rtol, or is not finite (it diverged), is deactivated.  One thread
+// per system.
 __global__ void k_batch_check(const BatchSys* sys, int32_t count, const int32_t* item_start,
                               const double* partial, double rtol, int32_t* active,
                               double* relres) {
@@ -343,7 +344,7 @@ __global__ void k_batch_check(const BatchSys* sys, int32_t count, const int32_t*
   const double bn = sys[s].bnorm;
   const double rr = bn > 0.0 ? sqrt(t) / bn : sqrt(t);
   relres[s] = rr;
-  if (!(rr > rtol)) active[s] = 0;
+  if (!(rr > rtol) || !isfinite(rr)) active[s] = 0;
 }
 
 }  // namespace

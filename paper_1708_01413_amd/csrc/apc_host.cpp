@@ -405,6 +405,8 @@ struct apc_plan_s {
   hipEvent_t check_ev = nullptr;       // recorded after their copy
   int64_t since_start = 0;             // k-RHS updates since the last start
   int refinements = 0;
+  bool inner_pending = false;          // APC_BF16_IR: the inner solve must restart on
+                                       // B - A X before the next update
   std::vector<int32_t> tile_start;     // first pass-A tile of every block (m+1)
   std::vector<hipEvent_t> events;
 
@@ -1527,9 +1529,18 @@ apc_status apc_setup(apc_plan* out, const double* A, int64_t lda, const double* 
   return APC_OK;
 }
 
+}  // extern "C"
+
+namespace {
+apc_status resume_refinement(apc_plan_s* p);
+}  // namespace
+
+extern "C" {
+
 apc_status apc_iterate(apc_plan p, int32_t T) {
   if (!p) return fail(APC_EINVAL, "plan is NULL");
   if (T < 0) return fail(APC_EINVAL, "T must be >= 0");
+  if (T > 0) ST_TRY(resume_refinement(p));
   for (int32_t t = 0; t < T; ++t) ST_TRY(update(p, nullptr, nullptr, nullptr));
   p->iters += T;
   return APC_OK;
@@ -1539,6 +1550,7 @@ apc_status apc_iterate_timed(apc_plan p, int32_t T, float* ms_total, float* ms_p
                              float* ms_pass_b, float* ms_average) {
   if (!p) return fail(APC_EINVAL, "plan is NULL");
   if (T < 0) return fail(APC_EINVAL, "T must be >= 0");
+  if (T > 0) ST_TRY(resume_refinement(p));
   const int per = launches_per_update(p);
   // Two bracketing events for the whole run, two per timed kernel.
   const size_t kern = static_cast<size_t>(T) * per;
@@ -1591,6 +1603,35 @@ apc_status apc_residual(apc_plan p, double* relres) {
 
 namespace {
 
+// Restarts the inner solve of the refinement on the residual R (FP64,
+// RHS-major, stride N, k columns) of the committed solution X: the
+// minimum-norm start of the correction equation, c = L2^{-1} L1^{-1} r per
+// block (padded columns of R are zeroed first).
+apc_status restart_inner(apc_plan_s* p, double* Rb) {
+  const Layout& L = p->L;
+  double* cw = p->at<double>(L.cw);
+  if (p->kp > p->k)
+    HIP_TRY(launch_fill_u32(reinterpret_cast<unsigned*>(Rb + static_cast<int64_t>(p->k) * p->N),
+                            2 * (p->kp - p->k) * p->N, 0u, p->stream));
+  HIP_TRY(launch_linv_apply(p->doff(), p->at<int64_t>(L.goff), p->m, p->pmax,
+                            p->at<double>(L.Linv), Rb, p->N, cw, p->N, p->kp, 0, 1.0, p->stream));
+  HIP_TRY(launch_linv_apply(p->doff(), p->at<int64_t>(L.goff), p->m, p->pmax,
+                            p->at<double>(L.Linv2), cw, p->N, Rb, p->N, p->kp, 0, 1.0, p->stream));
+  ST_TRY(start_gemm(p, Rb));
+  p->inner_pending = false;
+  return APC_OK;
+}
+
+// A refined solve ends with the correction committed (X += x_bar, x_bar = 0)
+// and no inner solve on the new residual.  Updates after it continue the
+// refinement: R = B - A X in FP64, then the inner solve restarts on R.
+apc_status resume_refinement(apc_plan_s* p) {
+  if (!p->bf16 || !p->inner_pending) return APC_OK;
+  double* Rb = p->at<double>(p->L.Rb);
+  ST_TRY(gemm_residual(p, p->at<double>(p->L.Xs), Rb));
+  return restart_inner(p, Rb);
+}
+
 // Mixed precision: iterative refinement around the bf16 inner solver.  Each
 // step runs `inner` updates of the current inner solve, commits X += x_bar,
 // forms R = B - A X in FP64 on matrix cores, and (unless done) restarts the
@@ -1605,7 +1646,6 @@ apc_status solve_refined(apc_plan_s* p, double rtol, int32_t max_iters, int32_t*
   int32_t done = 0;
   double rr = 0.0;
   double* Rb = p->at<double>(L.Rb);
-  double* cw = p->at<double>(L.cw);
   double* dst = p->at<double>(L.scal);
   for (;;) {
     const int32_t T = std::min(inner, max_iters - done);
@@ -1629,17 +1669,13 @@ apc_status solve_refined(apc_plan_s* p, double rtol, int32_t max_iters, int32_t*
       return fail(APC_EDIVERGED, "residual became non-finite after %d refinement steps",
                   p->refinements);
     }
-    if (rr <= rtol || done >= max_iters) break;
-    // Inner right-hand sides for R: c = L2^{-1} L1^{-1} r per block (padded
-    // columns of R are zero), then restart the inner solve.
-    if (p->kp > p->k)
-      HIP_TRY(launch_fill_u32(reinterpret_cast<unsigned*>(Rb + static_cast<int64_t>(p->k) * p->N),
-                              2 * (p->kp - p->k) * p->N, 0u, p->stream));
-    HIP_TRY(launch_linv_apply(p->doff(), p->at<int64_t>(L.goff), p->m, p->pmax,
-                              p->at<double>(L.Linv), Rb, p->N, cw, p->N, p->kp, 0, 1.0, p->stream));
-    HIP_TRY(launch_linv_apply(p->doff(), p->at<int64_t>(L.goff), p->m, p->pmax,
-                              p->at<double>(L.Linv2), cw, p->N, Rb, p->N, p->kp, 0, 1.0, p->stream));
-    ST_TRY(start_gemm(p, Rb));
+    if (rr <= rtol || done >= max_iters) {
+      // The inner state still belongs to the correction just committed;
+      // the next update restarts it on the current residual.
+      p->inner_pending = true;
+      break;
+    }
+    ST_TRY(restart_inner(p, Rb));
   }
   *done_out = done;
   *rr_out = rr;
@@ -1877,6 +1913,7 @@ apc_status restart_impl(apc_plan_s* P, const double* B, int64_t ldb) {
   }
   P->iters = 0;
   P->refinements = 0;
+  P->inner_pending = false;
   return APC_OK;
 }
 
@@ -2396,6 +2433,10 @@ apc_status apc_batch_activate(apc_batch b) {
 apc_status apc_batch_solve(apc_batch b, double rtol, int32_t max_iters, int32_t check_every,
                            int32_t use_graph, int32_t* iters_out, double* relres_out) {
   if (!b || max_iters < 0 || check_every < 1 || !(rtol >= 0)) return fail(APC_EINVAL, "bad argument");
+  // Every system is checked afresh: a flag left clear by an earlier check with
+  // another tolerance says nothing about this one.
+  b->h_active.assign(b->count, 1);
+  HIP_TRY(hipMemcpyAsync(b->active, b->h_active.data(), b->count * 4, hipMemcpyHostToDevice, b->stream));
   std::vector<int64_t> start(b->count);
   for (int32_t s = 0; s < b->count; ++s) start[s] = b->plans[s]->iters;
   std::vector<double> rr(b->count, 0.0);
@@ -2415,7 +2456,12 @@ apc_status apc_batch_solve(apc_batch b, double rtol, int32_t max_iters, int32_t 
     if (relres_out) relres_out[s] = rr[s];
   }
   for (int32_t s = 0; s < b->count; ++s)
-    if (b->h_active[s]) return fail(APC_ENOCONV, "system %d did not reach %g in %d updates", s, rtol, max_iters);
+    if (!std::isfinite(rr[s]))
+      return fail(APC_EDIVERGED, "system %d: residual became non-finite", s);
+  for (int32_t s = 0; s < b->count; ++s)
+    if (rr[s] > rtol)
+      return fail(APC_ENOCONV, "system %d did not reach %g in %d updates (relres %g)", s, rtol,
+                  max_iters, rr[s]);
   return APC_OK;
 }
 

@@ -5,9 +5,9 @@ the FP64 oracle and the seeded generators; where the oracle cannot run the full
 trajectory in reasonable time the test checks properties that hold at any size
 (the error against the known solution X*).
 
-Bars: FP64 1e-10 and FP32 1e-5 relative to ||X*|| (Frobenius over the right-hand
-sides for k > 1), on sampled coordinates as sqrt(n_total / n_sampled) times the
-sampled norm."""
+Bars: FP64 1e-10 and FP32 1e-5, per right-hand side c, both norm-wise
+(||x_gpu[:, c] - x_oracle[:, c]|| / ||x*[:, c]||) and element by element
+(|x_gpu[j, c] - x_oracle[j, c]| / max_j |x*[j, c]|), on whole vectors."""
 
 import math
 import os
@@ -44,7 +44,8 @@ def say(*a):
 @pytest.mark.parametrize("prec", ["f32", "f64"])
 def test_full_size_batched_8k_k64(prec):
     """N = n = 8192, A = G/sqrt(n) + 2I, 64 uneven blocks, k = 64: the error curve
-    t = 0..56 and x_bar(t) on every 64th coordinate of 8 columns at 9 values of t."""
+    t = 0..56 (largest column error, and the Frobenius form) and the whole n x 64 x_bar(t)
+    at t = 5, 20, 56, element by element."""
     torch = _torch()
     apc = _apc()
     g = np.load(os.path.join(GOLDEN, "shifted_uneven_8192_k64.npz"), allow_pickle=False)
@@ -56,33 +57,39 @@ def test_full_size_batched_8k_k64(prec):
     off = S.off
     del S
     plan = apc.Plan(A, b, off, prec, gamma=float(g["gamma"]), eta=float(g["eta"]))
-    idx = torch.from_numpy(g["idx"]).cuda()
-    cols = torch.from_numpy(g["cols"]).cuda()
     check = [int(t) for t in g["check_t"]]
-    xn = float(g["xstar_norm"])
-    errs, samples = [], {}
+    xn = torch.from_numpy(g["xstar_norm"]).cuda()          # per column
+    xmax = g["xstar_max"]                                  # per column
+    errs, errs_f, full = [], [], {}
+    xs_f = float(torch.linalg.norm(xs))
     for t in range(check[-1] + 1):
         if t:
             plan.iterate(1)
         xb = plan.xbar()
-        errs.append(float(torch.linalg.norm(xb - xs)) / xn)
+        errs.append(float(torch.max(torch.linalg.norm(xb - xs, dim=0) / xn)))
+        errs_f.append(float(torch.linalg.norm(xb - xs)) / xs_f)
         if t in check:
-            samples[t] = xb[idx][:, cols].cpu().numpy()
-    errs = np.array(errs)
-    say("err gpu ", " ".join(f"{e:.3e}" for e in errs[[5, 20, 34, 56]]))
-    say("err orc ", " ".join(f"{e:.3e}" for e in g["err"][[5, 20, 34, 56]]))
+            full[t] = xb.cpu().numpy()
+    errs, errs_f = np.array(errs), np.array(errs_f)
+    say("err gpu ", " ".join(f"{e:.3e}" for e in errs[[5, 20, 34, 56]]),
+        " Frobenius ", " ".join(f"{e:.3e}" for e in errs_f[[5, 20, 34, 56]]))
+    say("err orc ", " ".join(f"{e:.3e}" for e in g["err"][[5, 20, 34, 56]]),
+        " Frobenius ", " ".join(f"{e:.3e}" for e in g["err_fro"][[5, 20, 34, 56]]))
     assert np.max(np.abs(errs - g["err"])) <= TOL[prec]
-    n_total = 8192 * 64
+    assert np.max(np.abs(errs_f - g["err_fro"])) <= TOL[prec]
+    xn_np = g["xstar_norm"]
     for k, t in enumerate(check):
-        d = samples[t] - g["samples"][k]
-        est = math.sqrt(n_total / d.size * float(np.sum(d * d))) / xn
-        assert est <= TOL[prec], (t, est)
+        d = full[t] - g["xbar"][k]
+        col = float(np.max(np.linalg.norm(d, axis=0) / xn_np))
+        elem = float(np.max(np.abs(d) / xmax))
+        say(f"t = {t}: largest column deviation {col:.3e}, element-wise {elem:.3e}")
+        assert col <= TOL[prec] and elem <= TOL[prec], (t, col, elem)
 
 
 def test_full_size_many_systems_batch():
     """256 independent systems (n in [64, 1024], m in {4, 8, 16}), FP32, one persistent
-    launch per pass captured in a hipGraph: x_bar of every system after 20 updates on
-    every 16th coordinate against the oracle's."""
+    launch per pass captured in a hipGraph: the whole x_bar of every system after 20
+    updates against the oracle's, norm-wise and element by element."""
     torch = _torch()
     apc = _apc()
     g = np.load(os.path.join(GOLDEN, "many_small_systems_256.npz"), allow_pickle=False)
@@ -100,18 +107,17 @@ def test_full_size_many_systems_batch():
     T = int(g["T"])
     batch.iterate(T, graph=True)
     stream.synchronize()
-    stride = int(g["stride"])
-    worst = 0.0
+    worst, worst_e = 0.0, 0.0
     for s, (p, S) in enumerate(zip(plans, systems)):
         xb = p.xbar()                    # enqueued on the plans' stream
         stream.synchronize()
-        got = xb.cpu().numpy()[::stride]
-        ref = g["samples"][g["starts"][s]:g["starts"][s + 1]]
+        got = xb.cpu().numpy()
+        ref = g["xbar"][g["starts"][s]:g["starts"][s + 1]]
         d = got - ref
-        est = math.sqrt(S.n / d.size * float(np.sum(d * d))) / np.linalg.norm(S.xstar)
-        worst = max(worst, est)
-    say(f"worst sampled deviation over 256 systems: {worst:.3e}")
-    assert worst <= TOL["f32"]
+        worst = max(worst, float(np.linalg.norm(d) / np.linalg.norm(S.xstar)))
+        worst_e = max(worst_e, float(np.max(np.abs(d)) / np.max(np.abs(S.xstar))))
+    say(f"worst deviation over 256 systems: norm-wise {worst:.3e}, element-wise {worst_e:.3e}")
+    assert worst <= TOL["f32"] and worst_e <= TOL["f32"]
     batch.close()
     for p in plans:
         p.close()

@@ -1,7 +1,8 @@
 """GPU parity: the HIP path (through the C ABI) against the FP64 oracle.
 
-Tolerances (written per test): FP64 mode 1e-10 and FP32 mode 1e-5, both as
-||x_bar_gpu(t) - x_bar_oracle(t)||_2 / ||x*||_2 at every checked t.
+Tolerances (written per test): FP64 mode 1e-10 and FP32 mode 1e-5, as
+||x_bar_gpu(t) - x_bar_oracle(t)||_2 / ||x*||_2 at every checked t and, where
+stated, element by element as |x_bar_gpu(t)[j] - x_bar_oracle(t)[j]| / max_j |x*[j]|.
 """
 
 import math
@@ -67,19 +68,28 @@ def rel_dev(a, b, xstar):
     return float(np.max(np.linalg.norm(a - b, axis=-1)) / np.linalg.norm(xstar))
 
 
+def elem_dev(a, b, xstar):
+    """max over entries (and over t) of |a - b| / max_j |x*[j]|."""
+    return float(np.max(np.abs(a - b)) / np.max(np.abs(xstar)))
+
+
 # ---------------------------------------------------------------- the FP64 workload
 
 
-def cholqr2_factor(S):
-    """A second backward-stable FP64 factorization of every A_i^T (CholeskyQR2 in NumPy),
-    used only to measure how strongly a trajectory reacts to rounding in the projectors."""
+def householder_permuted_factor(S, seed):
+    """The oracle's own factorisation (LAPACK Householder QR of A_i^T) applied to A_i^T
+    with its n coordinates permuted, then permuted back: another valid thin QR of every
+    block, with different rounding.  Used only to measure how strongly the oracle's
+    trajectory reacts to rounding in its projectors."""
+    rng = np.random.default_rng(seed)
     Qt, R = [], []
     for Ai in O.blocks(S.A, S.off):
-        L1 = np.linalg.cholesky(Ai @ Ai.T)
-        Q1 = np.linalg.solve(L1, Ai)
-        L2 = np.linalg.cholesky(Q1 @ Q1.T)
-        Qt.append(np.linalg.solve(L2, Q1))
-        R.append(Qt[-1] @ Ai.T)
+        pi = rng.permutation(Ai.shape[1])
+        Q, Ri = np.linalg.qr(Ai.T[pi], mode="reduced")
+        Qf = np.empty_like(Q)
+        Qf[pi] = Q
+        Qt.append(Qf.T.copy())
+        R.append(Ri)
     return Qt, R
 
 
@@ -89,24 +99,30 @@ def square512():
     mn, mx = O.spectrum(S.A, S.off)
     g, e, rho = O.optimal_params(mn, mx)
     traj, _ = oracle_traj(S, 2000, g, e)
-    # Sensitivity scale s(t): the same oracle iteration on a CholeskyQR2 factor.
-    Qc, Rc = cholqr2_factor(S)
-    x = O.init_local(Qc, Rc, S.B, S.off)
-    xbar = O.initial_average(x)
-    alt = [xbar[:, 0].copy()]
-    for _ in range(2000):
-        x, xbar = O.apc_step(Qc, x, xbar, g, e)
-        alt.append(xbar[:, 0].copy())
-    sens = np.linalg.norm(np.stack(alt) - traj, axis=1) / np.linalg.norm(S.xstar)
+    # Sensitivity scale s(t): the largest drift of the oracle iteration run on four
+    # coordinate-permuted Householder factors from the oracle's own trajectory.
+    sens = np.zeros(2001)
+    for seed in range(4):
+        Qp, Rp = householder_permuted_factor(S, seed)
+        x = O.init_local(Qp, Rp, S.B, S.off)
+        xbar = O.initial_average(x)
+        alt = [xbar[:, 0].copy()]
+        for _ in range(2000):
+            x, xbar = O.apc_step(Qp, x, xbar, g, e)
+            alt.append(xbar[:, 0].copy())
+        sens = np.maximum(sens, np.linalg.norm(np.stack(alt) - traj, axis=1)
+                          / np.linalg.norm(S.xstar))
     return S, dict(mu_min=mn, mu_max=mx, gamma=g, eta=e, rho=rho), traj, sens
 
 
 def test_fp64_square512_trajectory_2000(square512):
     """N = n = 512, m = 8, FP64, optimal (gamma, eta) from the oracle, 2000 updates through
     the transient growth (error peaks at ~31 ||x*||).  kappa(X) = 5.5e6 makes this
-    trajectory amplify ~1e-16 differences between two valid projectors: an oracle run on a
-    CholeskyQR2 factor drifts from the Householder-based oracle by s(t) ~ 8e-11 at t = 300
-    and ~5.6e-9 at t = 2000.  Bar: 1e-10 for t <= 300, and 1e-10 + 2 s(t) for every t."""
+    trajectory amplify ~1e-16 differences between two valid projectors: the oracle run on
+    its own Householder QR of coordinate-permuted blocks drifts from the unpermuted oracle
+    by s(t) ~ 6e-11 at t = 300 and ~4e-9 at t = 2000 (largest of four permutations).
+    Bar: 1e-10 for t <= 300, and 1e-10 + 2 s(t) for every t, i.e. at most twice the
+    spread between two equally valid runs of the oracle itself."""
     apc = _apc()
     S, prm, ref, sens = square512
     say("case: square512 f64 trajectory T=2000")
@@ -115,9 +131,12 @@ def test_fp64_square512_trajectory_2000(square512):
     got = gpu_traj(plan, 2000)
     dev_t = np.linalg.norm(got - ref, axis=1) / np.linalg.norm(S.xstar)
     err = np.linalg.norm(got - S.xstar, axis=1) / np.linalg.norm(S.xstar)
-    say(f"dev(300)={dev_t[300]:.3e} dev(2000)={dev_t[-1]:.3e} s(2000)={sens[-1]:.3e}; "
+    say(f"dev(300)={dev_t[300]:.3e} dev(2000)={dev_t[-1]:.3e} against the oracle's own "
+        f"spread s(300)={sens[300]:.3e} s(2000)={sens[-1]:.3e} (ratio {dev_t[-1] / sens[-1]:.2f}); "
+        f"element-wise dev(t<=300) {elem_dev(got[:301], ref[:301], S.xstar):.3e}; "
         f"err(1)={err[1]:.3f} peak={err.max():.2f} err(2000)={err[-1]:.2f}")
     assert dev_t[:301].max() <= TOL["f64"]
+    assert elem_dev(got[:301], ref[:301], S.xstar) <= TOL["f64"]
     assert np.all(dev_t <= TOL["f64"] + 2.0 * sens)
     assert plan.iterations == 2000
 
@@ -338,34 +357,36 @@ def tall16k():
 @pytest.mark.parametrize("prec", ["f32", "f64"])
 def test_full_size_tall16k_trajectory(tall16k, prec):
     """N = 16384, n = 8192, m = 64 (the benchmark workload) in the launch configuration
-    the benchmark times: relative-error curve and every-8th-coordinate samples of x_bar(t)
-    against the oracle's stored values (tests/golden/make_golden.py)."""
+    the benchmark times: the relative-error curve t = 0..60 and the whole vector x_bar(t)
+    at 11 values of t against the oracle's stored values (tests/golden/make_golden.py),
+    norm-wise and element by element."""
     torch = _torch()
     apc = _apc()
     A, b, xs, off, g = tall16k
     say(f"case: full-size tall16k {prec}")
     plan = apc.Plan(A, b, off, prec, gamma=float(g["gamma"]), eta=float(g["eta"]))
-    idx = torch.from_numpy(g["idx"]).cuda()
     check = list(g["check_t"])
-    xn = float(g["xstar_norm"])
-    errs, samples = [], {}
+    xn, xmax = float(g["xstar_norm"]), float(g["xstar_max"])
+    errs, full = [], {}
     for t in range(int(check[-1]) + 1):
         if t:
             plan.iterate(1)
         xb = plan.xbar()
         errs.append(float(torch.linalg.norm(xb - xs)) / xn)
         if t in check:
-            samples[t] = xb[idx].cpu().numpy()
+            full[t] = xb.cpu().numpy()
     errs = np.array(errs)
     ref_err = g["err"]
     say("err gpu ", " ".join(f"{e:.3e}" for e in errs[[10, 20, 30, 40, 60]]))
     say("err orc ", " ".join(f"{e:.3e}" for e in ref_err[[10, 20, 30, 40, 60]]))
     assert np.max(np.abs(errs - ref_err)) <= TOL[prec]
-    n = 8192
+    worst_n, worst_e = 0.0, 0.0
     for k, t in enumerate(check):
-        d = samples[t] - g["samples"][k]
-        est = math.sqrt(n / d.size * float(np.sum(d * d))) / xn   # sampled estimate of ||dx||/||x*||
-        assert est <= TOL[prec], (t, est)
+        d = full[t] - g["xbar"][k]
+        worst_n = max(worst_n, float(np.linalg.norm(d)) / xn)
+        worst_e = max(worst_e, float(np.max(np.abs(d))) / xmax)
+    say(f"x_bar(t) vs oracle at t = {check}: norm-wise {worst_n:.3e}, element-wise {worst_e:.3e}")
+    assert worst_n <= TOL[prec] and worst_e <= TOL[prec]
     first = lambda e, lvl: int(np.argmax(e <= lvl))
     assert abs(first(errs, 1e-5) - first(ref_err, 1e-5)) <= 1
     assert errs[-1] <= (1e-6 if prec == "f32" else 1e-9)
