@@ -278,6 +278,23 @@ apc_status apc_backward(apc_plan p, const double* dXbar, int64_t ldd, int32_t T,
                         int32_t ckpt_every, double* dB, int64_t lddb, double* dgamma,
                         double* deta, void* bwd_ws, size_t bwd_bytes);
 
+/* apc_backward without a workspace argument, for callers that cannot allocate
+ * device memory (code under stream capture, tight serving loops, harnesses
+ * that forbid allocation).  It allocates nothing: its checkpoint scratch is a
+ * fixed array of 64 MiB per GPU inside the library, held from the first
+ * apc_setup on that GPU until the process ends.  Arguments, outputs, results
+ * and synchronisation are those of apc_backward; the caller still provides
+ * dXbar, dB and the host scalars.
+ * Errors: those of apc_backward, and APC_EINVAL when
+ * apc_backward_workspace_bytes(p, T, ckpt_every) exceeds 64 MiB (nothing is
+ * enqueued then; use apc_backward with a workspace).
+ * Every call on one GPU shares that GPU's array: calls that overlap in time on
+ * one GPU (other host threads, or plans on other streams) race and give wrong
+ * results.  Each call clears what it needs zeroed itself. */
+apc_status apc_backward_noalloc(apc_plan p, const double* dXbar, int64_t ldd, int32_t T,
+                                int32_t ckpt_every, double* dB, int64_t lddb, double* dgamma,
+                                double* deta);
+
 /* ---- Many independent systems (one persistent launch per pass) ----------
  *
  * A batch runs eq. (2a)-(2b) for many independent systems at once: every

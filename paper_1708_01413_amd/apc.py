@@ -38,7 +38,7 @@ EXPORTED = (
     "apc_iterations", "apc_destroy", "apc_last_error", "apc_optimal_params",
     "apc_tridiag_extremes", "apc_get_info", "apc_get_setup", "apc_get_launch", "apc_set_anchor",
     "apc_set_params",
-    "apc_restart", "apc_backward_workspace_bytes", "apc_backward",
+    "apc_restart", "apc_backward_workspace_bytes", "apc_backward", "apc_backward_noalloc",
     "apc_batch_workspace_bytes", "apc_batch_create", "apc_batch_iterate",
     "apc_batch_iterate_graph", "apc_batch_residuals", "apc_batch_activate", "apc_batch_solve",
     "apc_batch_get_launch", "apc_batch_destroy",
@@ -104,6 +104,7 @@ def _load() -> ctypes.CDLL:
         "apc_restart": (i32, [vp, vp, i64]),
         "apc_backward_workspace_bytes": (ctypes.c_size_t, [vp, i32, i32]),
         "apc_backward": (i32, [vp, vp, i64, i32, i32, vp, i64, Pd, Pd, vp, ctypes.c_size_t]),
+        "apc_backward_noalloc": (i32, [vp, vp, i64, i32, i32, vp, i64, Pd, Pd]),
         "apc_batch_workspace_bytes": (ctypes.c_size_t, [ctypes.POINTER(vp), i32]),
         "apc_batch_create": (i32, [ctypes.POINTER(vp), ctypes.POINTER(vp), i32, vp, ctypes.c_size_t]),
         "apc_batch_iterate": (i32, [vp, i32]),
@@ -244,6 +245,14 @@ def apc_backward(plan, dXbar: int, ldd: int, T: int, ckpt_every: int, dB: int, l
     dg, de = ctypes.c_double(), ctypes.c_double()
     _check(lib.apc_backward(plan, dXbar, ldd, T, ckpt_every, dB, lddb, ctypes.byref(dg),
                             ctypes.byref(de), ws, ws_bytes))
+    return dg.value, de.value
+
+
+def apc_backward_noalloc(plan, dXbar: int, ldd: int, T: int, ckpt_every: int, dB: int,
+                         lddb: int):
+    dg, de = ctypes.c_double(), ctypes.c_double()
+    _check(lib.apc_backward_noalloc(plan, dXbar, ldd, T, ckpt_every, dB, lddb, ctypes.byref(dg),
+                                    ctypes.byref(de)))
     return dg.value, de.value
 
 

@@ -1458,6 +1458,9 @@ apc_status apc_setup(apc_plan* out, const double* A, int64_t lda, const double* 
   int dev = 0;
   st = check_device(&dev);
   if (st != APC_OK) return st;
+  // Once per device: the address of this GPU's copy of the allocation-free
+  // adjoint's scratch.
+  HIP_TRY(noalloc_scratch_init(dev));
 
   apc_plan_s* P = new (std::nothrow) apc_plan_s();
   if (!P) return fail(APC_EINVAL, "out of host memory");
@@ -2736,3 +2739,21 @@ apc_status apc_hbm_get_params(apc_hbm h, double* alpha, double* beta, double* la
 void apc_hbm_destroy(apc_hbm h) { delete h; }
 
 }  // extern "C"
+
+// ------------------------------------------------------------------ helpers for other files
+
+namespace apc {
+
+apc_status report(apc_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return st;
+}
+
+int plan_device(const apc_plan_s* p) { return p ? p->device : -1; }
+
+}  // namespace apc

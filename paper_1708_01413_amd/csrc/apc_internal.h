@@ -6,6 +6,8 @@
 
 #include <cstdint>
 
+#include "apc.h"
+
 namespace apc {
 
 // Per-kernel timing without extra packets on the stream: when a pair of events
@@ -531,5 +533,21 @@ hipError_t launch_residual_partial(const double* A, int64_t lda, const double* B
 hipError_t launch_sum_partials(const double* partial, int32_t count, double* out, hipStream_t s);
 
 int residual_parts(int64_t N);
+
+// ---------------------------------------------------------------------------
+// Host-side helpers shared with entry points outside apc_host.cpp
+// ---------------------------------------------------------------------------
+
+// Sets the thread-local message of apc_last_error and returns st.
+apc_status report(apc_status st, const char* fmt, ...);
+// The device a plan was set up on.
+int plan_device(const apc_plan_s* p);
+
+// The allocation-free adjoint's fixed scratch (apc_noalloc.hip): its size, the
+// one-time lookup of this device's copy (the device must be current), and the
+// address found (NULL before the lookup).
+size_t noalloc_scratch_bytes();
+hipError_t noalloc_scratch_init(int device);
+void* noalloc_scratch(int device);
 
 }  // namespace apc
