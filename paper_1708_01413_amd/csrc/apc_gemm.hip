@@ -5,12 +5,12 @@
 //
 //   part[s][c][r] = sum_{j in split s} M[r][j] * V[c][j]
 //
-// M (rows x K, row-major) is the large operand and is read exactly once: each
-// lane loads four 16-byte pieces of a row per 256-byte step straight into MFMA
-// operand registers (no LDS round trip).  V (one row per right-hand side, K
+// M (rows x K) is the large operand and is read exactly once: each lane loads
+// four 16-byte pieces of a row per 256-byte step straight into MFMA operand
+// registers (no LDS round trip).  V (one row per right-hand side, K
 // contiguous) is small and re-read by every workgroup: one 256-byte-per-row
 // step of it is staged in LDS and shared by the four waves.  Both operands
-// are laid out K-contiguous, so the per-update passes of the (y, x_bar) form
+// are K-contiguous per row, so the per-update passes of the (y, x_bar) form
 // of APC are
 //
 //   pass A:  W  = C  y     M = C   (N x n),  V = y^T (k x n)
@@ -29,6 +29,18 @@
 // each lane one contiguous 64-byte run.  Plain loads: non-temporal ones
 // measured slower here.  V is read from LDS with exactly the same (lane group,
 // piece, element) -> K mapping, so the sum is over all of K.
+//
+// Fragment-packed M.  An MFMA operand gives each of 16 lanes its own row, so
+// in a row-major M one load instruction touches 16 rows 32 KB apart and a
+// step touches every row of the workgroup for 256 bytes only; a read-only
+// probe of that pattern over 16384 x 16384 bf16 reached 4.6 TB/s.  M is
+// therefore stored as tiles of 16 rows x one 256-byte step, each tile 4 KB
+// contiguous in the order the lanes consume it: piece p of lane L (row L % 16,
+// chunk 4 p + L / 16 of the step) at bytes (64 p + L) * 16 of the tile.  One
+// load instruction then reads 1 KB contiguous, and the tiles are ordered by
+// step, then row tile, so a workgroup's step is 16 RT KB contiguous per wave.
+// The same probe reads this layout at 6.8-7.0 TB/s with non-temporal loads
+// (each byte of M is read once per pass).  k_tn_pack writes it (frag = 1).
 //
 // Split-K partials are written per split and summed in a fixed order by the
 // epilogue kernels, so results do not depend on timing.
@@ -89,7 +101,19 @@ __device__ inline void mma_piece(const u32x4& a, const u32x4& b, f64x4& c, doubl
 // right-hand sides of its column group.  Grid: (rows / (64 RT)) x ncg x nsplit,
 // with the split index fastest so that, dealt round-robin over the 8 XCDs, one
 // XCD works on one split (nsplit | 8) and keeps that split's V in its L2.
-template <typename T, int RT, int NCT, int PF>
+// Element offset of (row r, column c) in the fragment-packed layout of a
+// rows x K operand (rows % 16 == 0, K a multiple of the step).
+template <typename T>
+__host__ __device__ inline int64_t frag_index(int64_t r, int64_t c, int64_t rows) {
+  constexpr int kE = 16 / sizeof(T);
+  constexpr int kStep = 16 * kE;
+  const int64_t ks = c / kStep;
+  const int kc = static_cast<int>((c % kStep) / kE);   // 16-byte chunk in the step
+  const int lane = static_cast<int>(r % 16) + 16 * (kc % 4);
+  return (ks * (rows / 16) + r / 16) * (16 * kStep) + (64 * (kc / 4) + lane) * kE + c % kE;
+}
+
+template <typename T, int RT, int NCT, int PF, int NT>
 __global__ __launch_bounds__(256) void k_tn(TnArgs a) {
   using Acc = typename TnTraits<T>::Acc;
   using Part = typename TnTraits<T>::Part;
@@ -111,9 +135,14 @@ __global__ __launch_bounds__(256) void k_tn(TnArgs a) {
   const T* V = static_cast<const T*>(a.V) + static_cast<int64_t>(cg) * NCT * 16 * a.ldv + kb0;
   const int64_t rb = rtile * 64 * RT + static_cast<int64_t>(wv) * 16 * RT;
 
+  // Fragment-packed M: this wave's tile t of step s starts at
+  // ((kb0 / kStep + s) * rows / 16 + rb / 16 + t) * 16 * kStep, and lane L's
+  // piece p sits (64 p + L) * kE further on.
+  const int64_t sstride = a.rows * kStep;
   const T* mrow[RT];
 #pragma unroll
-  for (int t = 0; t < RT; ++t) mrow[t] = M + (rb + 16 * t + li) * a.ldm + kb0 + g * kE;
+  for (int t = 0; t < RT; ++t)
+    mrow[t] = M + (kb0 / kStep) * sstride + (rb + 16 * t) * kStep + lane * kE;
   const int vr = threadIdx.x >> 4, vp = threadIdx.x & 15;
   const T* vsrc = V + static_cast<int64_t>(vr) * a.ldv + vp * kE;
 
@@ -129,11 +158,14 @@ __global__ __launch_bounds__(256) void k_tn(TnArgs a) {
   constexpr int D = PF + 1;
   u32x4 mr[D][RT][4], vst[NCT];
   auto load_m = [&](u32x4 (&dst)[RT][4], int step) {
-    const int64_t o = static_cast<int64_t>(step) * kStep;
+    const int64_t o = static_cast<int64_t>(step) * sstride;
 #pragma unroll
     for (int t = 0; t < RT; ++t)
 #pragma unroll
-      for (int p = 0; p < 4; ++p) dst[t][p] = *reinterpret_cast<const u32x4*>(mrow[t] + o + p * 4 * kE);
+      for (int p = 0; p < 4; ++p) {
+        const u32x4* src = reinterpret_cast<const u32x4*>(mrow[t] + o + p * 64 * kE);
+        dst[t][p] = NT ? __builtin_nontemporal_load(src) : *src;
+      }
   };
   auto load_v = [&](int step) {
     const int64_t o = static_cast<int64_t>(step) * kStep;
@@ -141,46 +173,64 @@ __global__ __launch_bounds__(256) void k_tn(TnArgs a) {
     for (int u = 0; u < NCT; ++u)
       vst[u] = *reinterpret_cast<const u32x4*>(vsrc + static_cast<int64_t>(16 * u) * a.ldv + o);
   };
-#pragma unroll
-  for (int s0 = 0; s0 < PF; ++s0)
-    if (s0 < nsteps) load_m(mr[s0], s0);
+  // A split past the end of K (from rounding its length up to whole steps)
+  // writes zero partials.  Otherwise every load below is issued without a
+  // branch, so that the compiler can count the loads in flight (see the main
+  // part); a step past the split's end is replaced by its last step.
   if (nsteps > 0) {
-    load_v(0);
 #pragma unroll
-    for (int u = 0; u < NCT; ++u) vs[0][vr + 16 * u][vp] = vst[u];
-  }
+  for (int s0 = 0; s0 < PF; ++s0) load_m(mr[s0], min(s0, nsteps - 1));
+  load_v(0);
+#pragma unroll
+  for (int u = 0; u < NCT; ++u) vs[0][vr + 16 * u][vp] = vst[u];
   __syncthreads();
-  for (int step0 = 0; step0 < nsteps; step0 += D) {
+  // One step: V's next step and M's step + PF are loaded, step `step` is
+  // multiplied from ring slot i, V's next step goes to the other LDS buffer.
+  // V is loaded before M: loads complete in order, so the wait for V at the
+  // end of the step does not also wait for the newest M loads, which keep PF
+  // steps in flight.
+  auto body = [&](int step, int i, bool more, bool load_ahead) {
+    const int buf = step & 1;
+    if (more) load_v(step + 1);
+    if (load_ahead) load_m(mr[(i + PF) % D], step + PF);
+    // Keep the loads at the top of the step: moved down among the products
+    // they would be waited for as soon as they are issued.
+    __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-    for (int i = 0; i < D; ++i) {
-      const int step = step0 + i;
-      if (step < nsteps) {  // uniform across the workgroup
-        const int buf = step & 1;
-        const bool more = step + 1 < nsteps;
-        // V's next step is loaded before M's step + PF: loads complete in
-        // order, so the wait for V at the end of this step then does not also
-        // wait for the newest M loads, which keep PF steps in flight.
-        if (more) load_v(step + 1);
-        if (step + PF < nsteps) load_m(mr[(i + PF) % D], step + PF);
+    for (int p = 0; p < 4; ++p) {
+      u32x4 bf[NCT];
 #pragma unroll
-        for (int p = 0; p < 4; ++p) {
-          u32x4 bf[NCT];
+      for (int ct = 0; ct < NCT; ++ct) bf[ct] = vs[buf][ct * 16 + li][4 * p + g];
 #pragma unroll
-          for (int ct = 0; ct < NCT; ++ct) bf[ct] = vs[buf][ct * 16 + li][4 * p + g];
+      for (int t = 0; t < RT; ++t)
 #pragma unroll
-          for (int t = 0; t < RT; ++t)
-#pragma unroll
-            for (int ct = 0; ct < NCT; ++ct)
-              mma_piece(mr[i][t][p], bf[ct], acc[t][ct], static_cast<T*>(nullptr));
-        }
-        if (more) {
-#pragma unroll
-          for (int u = 0; u < NCT; ++u) vs[buf ^ 1][vr + 16 * u][vp] = vst[u];
-        }
-        __syncthreads();
-      }
+        for (int ct = 0; ct < NCT; ++ct)
+          mma_piece(mr[i][t][p], bf[ct], acc[t][ct], static_cast<T*>(nullptr));
     }
+    if (more) {
+#pragma unroll
+      for (int u = 0; u < NCT; ++u) vs[buf ^ 1][vr + 16 * u][vp] = vst[u];
+    }
+    __syncthreads();
+  };
+  // Main part: every step of the chunk has step + PF < nsteps, so both loads
+  // are issued without a branch.  A load behind a branch makes the compiler
+  // wait for every load in flight where the paths join (it cannot count the
+  // loads issued after V's), which would drain the prefetch each step.
+  int step0 = 0;
+  // (Both loops are unrolled by the ring size, so every slot index is a
+  // compile-time constant.)
+  for (; step0 + D - 1 + PF < nsteps; step0 += D) {
+#pragma unroll
+    for (int i = 0; i < D; ++i) body(step0 + i, i, true, true);
   }
+  // Tail: the last steps, loads only where they exist (uniform branches).
+  for (; step0 < nsteps; step0 += D) {
+#pragma unroll
+    for (int i = 0; i < D; ++i)
+      if (step0 + i < nsteps) body(step0 + i, i, step0 + i + 1 < nsteps, step0 + i + PF < nsteps);
+  }
+  }  // nsteps > 0
 
   // Result layout: f32 accumulators hold D[4 g + q][li]; f64 ones D[g + 4 q][li].
   Part* part = static_cast<Part*>(a.part);
@@ -199,39 +249,56 @@ __global__ __launch_bounds__(256) void k_tn(TnArgs a) {
     }
 }
 
-template <typename T, int RT, int PF>
+template <typename T, int RT, int PF, int NT>
 hipError_t tn_nct(const TnArgs& a, hipStream_t s) {
   const int nct = a.kp >= 128 ? 8 : a.kp / 16;
   const int64_t ncg = a.kp / (16 * nct);
   const int64_t blocks = (a.rows / (64 * RT)) * ncg * a.nsplit;
   const dim3 grid(static_cast<unsigned>(blocks)), block(256);
   switch (nct) {
-    case 1: APC_LAUNCH((k_tn<T, RT, 1, PF>), grid, block, 0, s, a); break;
-    case 2: APC_LAUNCH((k_tn<T, RT, 2, PF>), grid, block, 0, s, a); break;
-    case 4: APC_LAUNCH((k_tn<T, RT, 4, PF>), grid, block, 0, s, a); break;
-    case 8: APC_LAUNCH((k_tn<T, RT, 8, PF>), grid, block, 0, s, a); break;
+    case 1: APC_LAUNCH((k_tn<T, RT, 1, PF, NT>), grid, block, 0, s, a); break;
+    case 2: APC_LAUNCH((k_tn<T, RT, 2, PF, NT>), grid, block, 0, s, a); break;
+    case 4: APC_LAUNCH((k_tn<T, RT, 4, PF, NT>), grid, block, 0, s, a); break;
+    case 8: APC_LAUNCH((k_tn<T, RT, 8, PF, NT>), grid, block, 0, s, a); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
 
-template <typename T, int PF>
+template <typename T, int PF, int NT>
 hipError_t tn_rt(int rt, const TnArgs& a, hipStream_t s) {
   switch (rt) {
-    case 1: return tn_nct<T, 1, PF>(a, s);
-    case 2: return tn_nct<T, 2, PF>(a, s);
+    case 1: return tn_nct<T, 1, PF, NT>(a, s);
+    case 2: return tn_nct<T, 2, PF, NT>(a, s);
     case 4:
       if constexpr (sizeof(T) == 8) return hipErrorInvalidValue;
-      else return tn_nct<T, 4, PF>(a, s);
+      else return tn_nct<T, 4, PF, NT>(a, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+// Deeper prefetch (3 or 4 steps ahead) for shapes with one or two row tiles
+// per wave, whose steps are short.
+template <typename T, int PF, int NT>
+hipError_t tn_rt_deep(int rt, const TnArgs& a, hipStream_t s) {
+  if constexpr (sizeof(T) == 8) return hipErrorInvalidValue;  // FP64: registers
+  else switch (rt) {
+    case 1: return tn_nct<T, 1, PF, NT>(a, s);
+    case 2: return tn_nct<T, 2, PF, NT>(a, s);
     default: return hipErrorInvalidValue;
   }
 }
 
 template <typename T>
 hipError_t tn_pf(int rt, int pf, const TnArgs& a, hipStream_t s) {
-  switch (pf) {
-    case 1: return tn_rt<T, 1>(rt, a, s);
-    case 2: return tn_rt<T, 2>(rt, a, s);
+  const int nt = a.nt ? 1 : 0;
+  switch (pf * 2 + nt) {
+    case 2: return tn_rt<T, 1, 0>(rt, a, s);
+    case 3: return tn_rt<T, 1, 1>(rt, a, s);
+    case 4: return tn_rt<T, 2, 0>(rt, a, s);
+    case 5: return tn_rt<T, 2, 1>(rt, a, s);
+    case 7: return tn_rt_deep<T, 3, 1>(rt, a, s);
+    case 9: return tn_rt_deep<T, 4, 1>(rt, a, s);
     default: return hipErrorInvalidValue;
   }
 }
@@ -389,21 +456,24 @@ __global__ __launch_bounds__(256) void k_tn_resid(const double* part, int32_t ns
 
 // dst (drows x ldd, type TQ) = src or src^T (FP64, srows x scols, stride lds),
 // zero outside the source.  64 x 64 tiles through LDS for the transpose.
+// frag = 1 writes the fragment-packed layout of k_tn's M operand instead of
+// row-major (then drows % 16 == 0 and ldd is a multiple of the step).
 template <typename TQ>
 __global__ __launch_bounds__(256) void k_tn_pack(const double* src, int64_t lds, int64_t srows,
                                                  int64_t scols, int32_t transpose, TQ* dst,
-                                                 int64_t ldd, int64_t drows) {
+                                                 int64_t ldd, int64_t drows, int32_t frag) {
   __shared__ double tile[64][65];
   const int64_t tiles_c = (ldd + 63) / 64;
   const int64_t tr = blockIdx.x / tiles_c, tc = blockIdx.x % tiles_c;
   const int64_t r0 = tr * 64, c0 = tc * 64;  // destination tile origin
   const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  auto at = [&](int64_t r, int64_t c) { return frag ? frag_index<TQ>(r, c, drows) : r * ldd + c; };
   if (!transpose) {
     for (int rr = ty; rr < 64; rr += 4) {
       const int64_t r = r0 + rr, c = c0 + tx;
       if (r >= drows || c >= ldd) continue;
       const double v = (r < srows && c < scols) ? src[r * lds + c] : 0.0;
-      dst[r * ldd + c] = cvt<TQ>(v);
+      dst[at(r, c)] = cvt<TQ>(v);
     }
     return;
   }
@@ -415,7 +485,7 @@ __global__ __launch_bounds__(256) void k_tn_pack(const double* src, int64_t lds,
   __syncthreads();
   for (int rr = ty; rr < 64; rr += 4) {
     const int64_t r = r0 + rr, c = c0 + tx;
-    if (r < drows && c < ldd) dst[r * ldd + c] = cvt<TQ>(tile[tx][rr]);
+    if (r < drows && c < ldd) dst[at(r, c)] = cvt<TQ>(tile[tx][rr]);
   }
 }
 
@@ -520,27 +590,44 @@ hipError_t launch_tn_resid(const double* part, int32_t nsplit, int32_t kp, int64
   return hipGetLastError();
 }
 
-hipError_t launch_tn_pack(int type, const double* src, int64_t lds, int64_t srows, int64_t scols,
-                          int32_t transpose, void* dst, int64_t ldd, int64_t drows, hipStream_t s) {
+namespace {
+
+hipError_t tn_pack(int type, const double* src, int64_t lds, int64_t srows, int64_t scols,
+                   int32_t transpose, void* dst, int64_t ldd, int64_t drows, int32_t frag,
+                   hipStream_t s) {
   const int64_t blocks = ((drows + 63) / 64) * ((ldd + 63) / 64);
   if (blocks < 1) return hipSuccess;
   const dim3 grid(static_cast<unsigned>(blocks));
   switch (type) {
     case kTnF64:
       k_tn_pack<double><<<grid, 256, 0, s>>>(src, lds, srows, scols, transpose,
-                                             static_cast<double*>(dst), ldd, drows);
+                                             static_cast<double*>(dst), ldd, drows, frag);
       break;
     case kTnF32:
       k_tn_pack<float><<<grid, 256, 0, s>>>(src, lds, srows, scols, transpose,
-                                            static_cast<float*>(dst), ldd, drows);
+                                            static_cast<float*>(dst), ldd, drows, frag);
       break;
     case kTnBF16:
       k_tn_pack<__bf16><<<grid, 256, 0, s>>>(src, lds, srows, scols, transpose,
-                                             static_cast<__bf16*>(dst), ldd, drows);
+                                             static_cast<__bf16*>(dst), ldd, drows, frag);
       break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_tn_pack(int type, const double* src, int64_t lds, int64_t srows, int64_t scols,
+                          int32_t transpose, void* dst, int64_t ldd, int64_t drows, hipStream_t s) {
+  return tn_pack(type, src, lds, srows, scols, transpose, dst, ldd, drows, 0, s);
+}
+
+hipError_t launch_tn_pack_frag(int type, const double* src, int64_t lds, int64_t srows,
+                               int64_t scols, int32_t transpose, void* dst, int64_t K,
+                               int64_t rows, hipStream_t s) {
+  if (rows % 16 || K % tn_step_elems(type)) return hipErrorInvalidValue;
+  return tn_pack(type, src, lds, srows, scols, transpose, dst, K, rows, 1, s);
 }
 
 }  // namespace apc

@@ -364,6 +364,7 @@ struct TnChoice {
   int nsplit = 1;
   float us = 0.f;  // measured time per launch when tuned
   int pf = 1;      // steps of the streamed operand loaded ahead
+  int nt = 1;      // non-temporal loads of the streamed operand
 };
 
 struct apc_plan_s {
@@ -594,7 +595,7 @@ apc_status orthogonality_defect(apc_plan_s* P, const double* C, double* defect, 
 
 TnArgs tn_args(const void* M, int64_t ldm, int64_t rows, const void* V, int64_t ldv, int32_t kp,
                int64_t K, const TnChoice& ch, int type, void* part, int64_t ldp) {
-  TnArgs a{M, ldm, rows, V, ldv, kp, K, ch.nsplit, 0, part, ldp};
+  TnArgs a{M, ldm, rows, V, ldv, kp, K, ch.nsplit, 0, part, ldp, ch.nt};
   a.klen = round_up((K + ch.nsplit - 1) / ch.nsplit, tn_step_elems(type));
   return a;
 }
@@ -747,7 +748,8 @@ apc_status tn_tune(apc_plan_s* P, int type, TnArgs base, TnChoice* out) {
   const char* fix_rt = std::getenv("APC_TN_RT");
   const char* fix_ns = std::getenv("APC_TN_SPLIT");
   const char* tune = std::getenv("APC_TN_TUNE");
-  if (fix_rt || fix_ns || std::getenv("APC_TN_PF") || (tune && std::atoi(tune) == 0)) {
+  if (fix_rt || fix_ns || std::getenv("APC_TN_PF") || std::getenv("APC_TN_NT") ||
+      (tune && std::atoi(tune) == 0)) {
     // Fixed shape (not cached): 128 rows per workgroup, the smallest split
     // with >= 512 workgroups, unless the environment names them.
     TnChoice c;
@@ -759,7 +761,10 @@ apc_status tn_tune(apc_plan_s* P, int type, TnArgs base, TnChoice* out) {
     for (int ns : splits)
       if (blocks(c.rt, ns) >= 512) { c.nsplit = ns; break; }
     if (fix_ns) c.nsplit = std::max(1, std::min(kTnMaxSplit, std::atoi(fix_ns)));
-    if (const char* e = std::getenv("APC_TN_PF")) c.pf = std::atoi(e) == 2 ? 2 : 1;
+    if (const char* e = std::getenv("APC_TN_PF")) c.pf = std::max(1, std::min(4, std::atoi(e)));
+    if (c.pf > 2 && (c.rt > 2 || type == kTnF64)) c.pf = 2;
+    if (c.pf > 2) c.nt = 1;
+    if (const char* e = std::getenv("APC_TN_NT")) c.nt = std::atoi(e) != 0;
     *out = c;
     return APC_OK;
   }
@@ -782,16 +787,20 @@ apc_status tn_tune(apc_plan_s* P, int type, TnArgs base, TnChoice* out) {
     for (int ns : splits) {
       if (blocks(rt, ns) < 64 && !(rt == 1 && ns == 8)) continue;
       if (static_cast<int64_t>(ns) * tn_step_elems(type) > base.K && ns > 1) continue;
-      for (int pf = 1; pf <= 2; ++pf) {
-        TnChoice c;
-        c.rt = rt;
-        c.nsplit = ns;
-        c.pf = pf;
-        cand.push_back(c);
-      }
+      for (int pf = 1; pf <= 4; ++pf)
+        for (int nt = 0; nt <= 1; ++nt) {
+          // Three and four steps ahead: non-temporal only, one or two tiles.
+          if (pf > 2 && (nt == 0 || rt > 2 || type == kTnF64)) continue;
+          TnChoice c;
+          c.rt = rt;
+          c.nsplit = ns;
+          c.pf = pf;
+          c.nt = nt;
+          cand.push_back(c);
+        }
     }
   }
-  if (cand.empty()) cand.push_back(TnChoice{1, 1, 0.f, 1});
+  if (cand.empty()) cand.push_back(TnChoice{1, 1, 0.f, 1, 1});
   TnChoice best;
   {
     hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -802,6 +811,7 @@ apc_status tn_tune(apc_plan_s* P, int type, TnArgs base, TnChoice* out) {
     for (const TnChoice& c : cand) {
       TnArgs a = base;
       a.nsplit = c.nsplit;
+      a.nt = c.nt;
       a.klen = round_up((a.K + c.nsplit - 1) / c.nsplit, tn_step_elems(type));
       hipError_t err = launch_tn(type, c.rt, c.pf, a, P->stream);  // warm-up
       for (int r = 0; err == hipSuccess && r < 1; ++r) {
@@ -1322,13 +1332,15 @@ apc_status setup_impl(apc_plan_s* P, const Tiles& T) {
     // Factor copies for the matrix cores (C and C^T in the iteration's
     // precision, C^T in FP64), the padded FP64 copy of A, zeroed operands.
     const int64_t Np = L.Np, np = L.np;
-    HIP_TRY(launch_tn_pack(P->tq, Ca, ldc, N, n, 0, P->ws + L.Cq, np, Np, st));
-    HIP_TRY(launch_tn_pack(P->tq, Ca, ldc, N, n, 1, P->ws + L.CqT, Np, np, st));
+    // Every one of them is a streamed operand of the contraction kernel and
+    // is stored in its fragment-packed layout.
+    HIP_TRY(launch_tn_pack_frag(P->tq, Ca, ldc, N, n, 0, P->ws + L.Cq, np, Np, st));
+    HIP_TRY(launch_tn_pack_frag(P->tq, Ca, ldc, N, n, 1, P->ws + L.CqT, Np, np, st));
     if (P->tq != kTnF64) {
-      HIP_TRY(launch_tn_pack(kTnF64, Ca, ldc, N, n, 1, P->ws + L.C64T, Np, np, st));
-      HIP_TRY(launch_tn_pack(kTnF64, Ca, ldc, N, n, 0, P->ws + L.C64p, np, Np, st));
+      HIP_TRY(launch_tn_pack_frag(kTnF64, Ca, ldc, N, n, 1, P->ws + L.C64T, Np, np, st));
+      HIP_TRY(launch_tn_pack_frag(kTnF64, Ca, ldc, N, n, 0, P->ws + L.C64p, np, Np, st));
     }
-    HIP_TRY(launch_tn_pack(kTnF64, P->A, P->lda, N, n, 0, P->ws + L.Apad, np, Np, st));
+    HIP_TRY(launch_tn_pack_frag(kTnF64, P->A, P->lda, N, n, 0, P->ws + L.Apad, np, Np, st));
     const int64_t sq = P->tq == kTnF64 ? 8 : P->tq == kTnF32 ? 4 : 2;
     HIP_TRY(launch_fill_u32(P->at<unsigned>(L.yq), P->kp * np * sq / 4, 0u, st));
     HIP_TRY(launch_fill_u32(P->at<unsigned>(L.Wq), P->kp * Np * sq / 4, 0u, st));

@@ -275,6 +275,8 @@ constexpr int kTnMaxSplit = 8;    // split-K factors the partial buffer holds
 // rows is a multiple of 64*rt, K and klen multiples of the step (256 bytes of
 // a row), kp is 16, 32, 64 or a multiple of 128, M and V rows are 16-byte
 // aligned and zero wherever they extend past the data.
+// M: rows x K in the fragment-packed layout written by launch_tn_pack_frag
+// (ldm = K); V: kp rows of K, stride ldv.
 struct TnArgs {
   const void* M;
   int64_t ldm;
@@ -287,8 +289,10 @@ struct TnArgs {
   int64_t klen;
   void* part;
   int64_t ldp;
+  int32_t nt;   // 1: non-temporal loads of M
 };
-// rt: 16-row tiles per wave (1, 2, 4; FP64 1, 2); pf: steps of M loaded ahead (1, 2).
+// rt: 16-row tiles per wave (1, 2, 4; FP64 1, 2); pf: steps of M loaded ahead
+// (1, 2; 3 and 4 with rt <= 2, non-temporal loads, not FP64).
 hipError_t launch_tn(int type, int rt, int pf, const TnArgs& a, hipStream_t s);
 int tn_step_elems(int type);
 // out[c*ldo + r] = TQ(sum over the nsplit partials in split order), r < rows, c < kp.
@@ -427,6 +431,11 @@ hipError_t launch_tn_resid(const double* part, int32_t nsplit, int32_t kp, int64
 // zero outside the FP64 source (srows x scols, stride lds).
 hipError_t launch_tn_pack(int type, const double* src, int64_t lds, int64_t srows, int64_t scols,
                           int32_t transpose, void* dst, int64_t ldd, int64_t drows, hipStream_t s);
+// The same into the fragment-packed layout of k_tn's M operand (rows x K,
+// rows % 16 == 0, K a multiple of tn_step_elems(type)).
+hipError_t launch_tn_pack_frag(int type, const double* src, int64_t lds, int64_t srows,
+                               int64_t scols, int32_t transpose, void* dst, int64_t K,
+                               int64_t rows, hipStream_t s);
 
 // Per block: out[col*ldo + r0 + r] = scale * sum_q Lop[r][q] in[col*ldi + r0 + q], col < kc,
 // with Lop = Linv_i (q <= r) or, when trans, Linv_i^T (q >= r); pmax = max p_i.
