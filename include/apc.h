@@ -123,6 +123,17 @@ apc_status apc_setup(apc_plan* out, const double* A, int64_t lda, const double* 
  * x_bar <- eta (x_bar(0) + y - Z/m) + (1 - eta) x_bar.  Returns at once. */
 apc_status apc_iterate(apc_plan p, int32_t T);
 
+/* As apc_iterate, replayed from a captured HIP graph: the first call for a
+ * given T (and, in the k-RHS form with anchor updates, a given position in
+ * the anchor cycle) captures the T updates' launches on the plan's stream;
+ * later calls replay the graph, which removes the host's per-launch cost.
+ * Results are those of apc_iterate, bit for bit.  The plan's stream must not
+ * be the default (NULL) stream, and must not be under capture by the caller.
+ * apc_set_params and apc_set_anchor drop the cached graphs (their launches
+ * carry gamma and eta by value).  Asynchronous, like apc_iterate.
+ * Errors: APC_EINVAL (NULL plan, T < 0, default stream), APC_EHIP. */
+apc_status apc_iterate_graph(apc_plan p, int32_t T);
+
 /* As apc_iterate, and also times every launch with a pair of HIP events that
  * the launch itself records at its start and end: *ms_total receives the span
  * of the T updates; *ms_pass_a, *ms_pass_b and *ms_average the summed

@@ -33,7 +33,8 @@ APC_OK, APC_EINVAL, APC_ERANK, APC_ESINGULAR, APC_EDIVERGED, APC_ENOCONV, APC_EN
     APC_EHIP, APC_EUNSUPPORTED = range(9)
 
 EXPORTED = (
-    "apc_workspace_bytes", "apc_setup", "apc_iterate", "apc_iterate_timed", "apc_residual",
+    "apc_workspace_bytes", "apc_setup", "apc_iterate", "apc_iterate_graph", "apc_iterate_timed",
+    "apc_residual",
     "apc_solve", "apc_get_xbar", "apc_get_local", "apc_project", "apc_get_params",
     "apc_iterations", "apc_destroy", "apc_last_error", "apc_optimal_params",
     "apc_tridiag_extremes", "apc_get_info", "apc_get_setup", "apc_get_launch", "apc_set_anchor",
@@ -88,6 +89,7 @@ def _load() -> ctypes.CDLL:
         "apc_setup": (i32, [ctypes.POINTER(vp), vp, i64, vp, i64, i64, i64, P64, i32, i32, i32,
                             f64, f64, vp, ctypes.c_size_t, vp]),
         "apc_iterate": (i32, [vp, i32]),
+        "apc_iterate_graph": (i32, [vp, i32]),
         "apc_iterate_timed": (i32, [vp, i32, Pf, Pf, Pf, Pf]),
         "apc_residual": (i32, [vp, Pd]),
         "apc_solve": (i32, [vp, f64, i32, vp, i64, Pi, Pd]),
@@ -165,6 +167,10 @@ def apc_setup(A: int, lda: int, B: int, ldb: int, N: int, n: int, off, m: int, k
 
 def apc_iterate(plan, T: int):
     _check(lib.apc_iterate(plan, T))
+
+
+def apc_iterate_graph(plan, T: int):
+    _check(lib.apc_iterate_graph(plan, T))
 
 
 def apc_iterate_timed(plan, T: int):
@@ -344,8 +350,10 @@ class Plan:
             apc_set_anchor(self.handle, int(anchor_every))
 
     # -- iteration
-    def iterate(self, T: int):
-        apc_iterate(self.handle, T)
+    def iterate(self, T: int, graph: bool = False):
+        """T updates; graph=True replays a captured HIP graph of them (needs a plan on a
+        non-default stream)."""
+        (apc_iterate_graph if graph else apc_iterate)(self.handle, T)
 
     def iterate_timed(self, T: int):
         """(ms_total, ms_pass_a, ms_pass_b, ms_average) of T updates, timed with HIP events."""

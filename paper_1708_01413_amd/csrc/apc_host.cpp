@@ -410,6 +410,17 @@ struct apc_plan_s {
                                        // B - A X before the next update
   std::vector<int32_t> tile_start;     // first pass-A tile of every block (m+1)
   std::vector<hipEvent_t> events;
+  // Captured graphs of T updates (apc_iterate_graph), keyed by (T, the anchor
+  // phase of the k-RHS form); their launches carry gamma and eta by value, so
+  // apc_set_params and apc_set_anchor drop them.
+  std::map<std::pair<int32_t, int32_t>, std::pair<hipGraph_t, hipGraphExec_t>> graphs;
+  void drop_graphs() {
+    for (auto& kv : graphs) {
+      (void)hipGraphExecDestroy(kv.second.second);
+      (void)hipGraphDestroy(kv.second.first);
+    }
+    graphs.clear();
+  }
 
   template <typename T>
   T* at(size_t o) const { return reinterpret_cast<T*>(ws + o); }
@@ -1561,6 +1572,45 @@ apc_status apc_iterate(apc_plan p, int32_t T) {
   return APC_OK;
 }
 
+apc_status apc_iterate_graph(apc_plan p, int32_t T) {
+  if (!p) return fail(APC_EINVAL, "plan is NULL");
+  if (T < 0) return fail(APC_EINVAL, "T must be >= 0");
+  if (T == 0) return APC_OK;
+  if (p->stream == nullptr) return fail(APC_EINVAL, "graph capture needs a non-default stream");
+  ST_TRY(resume_refinement(p));
+  const int32_t phase = p->gemm && p->anchor_every > 0
+                            ? static_cast<int32_t>(p->since_start % p->anchor_every) : 0;
+  const auto key = std::make_pair(T, phase);
+  auto itg = p->graphs.find(key);
+  if (itg == p->graphs.end()) {
+    // Capture T updates.  Nothing runs during capture: the update counter of
+    // the k-RHS form (which places the anchor updates) is put back after it.
+    const int64_t since = p->since_start;
+    hipGraph_t g = nullptr;
+    HIP_TRY(hipStreamBeginCapture(p->stream, hipStreamCaptureModeThreadLocal));
+    apc_status st = APC_OK;
+    for (int32_t t = 0; t < T && st == APC_OK; ++t) st = update(p, nullptr, nullptr, nullptr);
+    const hipError_t e = hipStreamEndCapture(p->stream, &g);
+    p->since_start = since;
+    if (st != APC_OK) {
+      if (g) (void)hipGraphDestroy(g);
+      return st;
+    }
+    HIP_TRY(e);
+    hipGraphExec_t ex = nullptr;
+    const hipError_t ei = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    if (ei != hipSuccess) {
+      (void)hipGraphDestroy(g);
+      HIP_TRY(ei);
+    }
+    itg = p->graphs.emplace(key, std::make_pair(g, ex)).first;
+  }
+  HIP_TRY(hipGraphLaunch(itg->second.second, p->stream));
+  if (p->gemm) p->since_start += T;
+  p->iters += T;
+  return APC_OK;
+}
+
 apc_status apc_iterate_timed(apc_plan p, int32_t T, float* ms_total, float* ms_pass_a,
                              float* ms_pass_b, float* ms_average) {
   if (!p) return fail(APC_EINVAL, "plan is NULL");
@@ -1874,6 +1924,10 @@ apc_status apc_set_anchor(apc_plan p, int32_t every) {
     return fail(APC_EUNSUPPORTED, "anchor updates exist for FP32 / bf16 plans with the k-RHS form");
   if (p->since_start != 0)
     return fail(APC_EINVAL, "set the anchor spacing before the first update after setup");
+  if (every != p->anchor_every) {
+    (void)hipStreamSynchronize(p->stream);  // no captured graph may still be running
+    p->drop_graphs();
+  }
   p->anchor_every = every;
   return APC_OK;
 }
@@ -1882,6 +1936,10 @@ apc_status apc_set_params(apc_plan p, double gamma, double eta) {
   if (!p) return fail(APC_EINVAL, "plan is NULL");
   if (!std::isfinite(gamma) || !std::isfinite(eta))
     return fail(APC_EINVAL, "gamma and eta must be finite");
+  if (gamma != p->gamma || eta != p->eta) {
+    (void)hipStreamSynchronize(p->stream);  // no captured graph may still be running
+    p->drop_graphs();
+  }
   p->gamma = gamma;
   p->eta = eta;
   return APC_OK;
@@ -2098,6 +2156,10 @@ int64_t apc_iterations(apc_plan p) { return p ? p->iters : -1; }
 
 void apc_destroy(apc_plan p) {
   if (!p) return;
+  if (!p->graphs.empty()) {
+    (void)hipStreamSynchronize(p->stream);
+    p->drop_graphs();
+  }
   for (hipEvent_t e : p->events) (void)hipEventDestroy(e);
   if (p->check_ev) (void)hipEventDestroy(p->check_ev);
   if (p->pinned) (void)hipHostFree(p->pinned);
