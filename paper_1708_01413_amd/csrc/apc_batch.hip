@@ -23,6 +23,7 @@
 #include <hip/hip_runtime.h>
 
 #include "apc_internal.h"
+#include "apc_tn.h"
 
 namespace apc {
 
@@ -225,6 +226,18 @@ __device__ inline void batch_tile_pass(const BatchSys& S, int t, float (&red)[4]
     for (int e = 0; e < 4; ++e) red[wv][(lane + 64 * c) * 4 + e] = acc[c][e];
 }
 
+// One single-pass item: tile t of system S, its partial row written.
+__device__ inline void fused_item(const BatchSys& S, int t, float (&red)[4][kBatchFusedCols]) {
+  if (S.ldc <= 256) batch_tile_pass<1>(S, t, red);
+  else if (S.ldc <= 512) batch_tile_pass<2>(S, t, red);
+  else batch_tile_pass<4>(S, t, red);
+  __syncthreads();
+  float* out = S.part + static_cast<int64_t>(t) * S.ldc;
+  for (int64_t j = threadIdx.x; j < S.ldc; j += 256)
+    out[j] = (red[0][j] + red[1][j]) + (red[2][j] + red[3][j]);
+  __syncthreads();
+}
+
 // Items (sys, row tile of the batch's tiles for that system): the tile's
 // partial row, for rows up to kBatchFusedCols wide.
 __global__ __launch_bounds__(256) void k_batch_fused(const BatchSys* sys, const int2* items,
@@ -233,15 +246,7 @@ __global__ __launch_bounds__(256) void k_batch_fused(const BatchSys* sys, const 
   for (int32_t it = blockIdx.x; it < nitems; it += gridDim.x) {
     const int2 w = items[it];
     if (!active[w.x]) continue;  // uniform per workgroup
-    const BatchSys& S = sys[w.x];
-    if (S.ldc <= 256) batch_tile_pass<1>(S, w.y, red);
-    else if (S.ldc <= 512) batch_tile_pass<2>(S, w.y, red);
-    else batch_tile_pass<4>(S, w.y, red);
-    __syncthreads();
-    float* out = S.part + static_cast<int64_t>(w.y) * S.ldc;
-    for (int64_t j = threadIdx.x; j < S.ldc; j += 256)
-      out[j] = (red[0][j] + red[1][j]) + (red[2][j] + red[3][j]);
-    __syncthreads();
+    fused_item(sys[w.x], w.y, red);
   }
 }
 
@@ -250,56 +255,60 @@ __global__ __launch_bounds__(256) void k_batch_fused(const BatchSys* sys, const 
 // sum of block i's partial rows), x_bar <- (eta/m) sum_i x_i + (1 - eta) x_bar,
 // d_i = x_bar - x_i.  A block's partial rows are loaded four at a time, with
 // its x_i, before they are added.
+__device__ inline void combine_item(const BatchSys& S, int col, double (&part)[8][32],
+                                    double (&xb)[32]) {
+  const int lane = threadIdx.x & 31;
+  const int bl = threadIdx.x >> 5;
+  const int64_t j = col + lane;
+  double* x = S.x;
+  double s = 0.0;
+  if (j < S.n) {
+    const double xo = S.xbar[j];
+    for (int i = bl; i < S.m; i += 8) {
+      const int64_t o = static_cast<int64_t>(i) * S.ldc + j;
+      const double xi = x[o];
+      const int t1 = S.tile_first[i + 1];
+      double u = 0.0;
+      for (int t = S.tile_first[i]; t < t1; t += 4) {
+        float v[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+          v[k] = t + k < t1 ? S.part[static_cast<int64_t>(t + k) * S.ldc + j] : 0.f;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) u += static_cast<double>(v[k]);
+      }
+      const double xn = xi + S.gamma * ((xo - xi) - u);
+      x[o] = xn;
+      s += xn;
+    }
+  }
+  part[bl][lane] = s;
+  __syncthreads();
+  if (bl == 0 && j < S.n) {
+    const double tot = ((part[0][lane] + part[1][lane]) + (part[2][lane] + part[3][lane])) +
+                       ((part[4][lane] + part[5][lane]) + (part[6][lane] + part[7][lane]));
+    const double v = (S.eta / S.m) * tot + (1.0 - S.eta) * S.xbar[j];
+    S.xbar[j] = v;
+    xb[lane] = v;
+  }
+  __syncthreads();
+  if (j < S.n) {
+    float* d = static_cast<float*>(S.d);
+    for (int i = bl; i < S.m; i += 8)
+      d[static_cast<int64_t>(i) * S.ldc + j] =
+          static_cast<float>(xb[lane] - x[static_cast<int64_t>(i) * S.ldc + j]);
+  }
+  __syncthreads();
+}
+
 __global__ __launch_bounds__(256) void k_batch_fused_combine(const BatchSys* sys, const int2* items,
                                                              int32_t nitems, const int32_t* active) {
   __shared__ double part[8][32];
   __shared__ double xb[32];
-  const int lane = threadIdx.x & 31;
-  const int bl = threadIdx.x >> 5;
   for (int32_t it = blockIdx.x; it < nitems; it += gridDim.x) {
     const int2 w = items[it];
     if (!active[w.x]) continue;  // uniform per workgroup
-    const BatchSys& S = sys[w.x];
-    const int64_t j = w.y + lane;
-    double* x = S.x;
-    double s = 0.0;
-    if (j < S.n) {
-      const double xo = S.xbar[j];
-      for (int i = bl; i < S.m; i += 8) {
-        const int64_t o = static_cast<int64_t>(i) * S.ldc + j;
-        const double xi = x[o];
-        const int t1 = S.tile_first[i + 1];
-        double u = 0.0;
-        for (int t = S.tile_first[i]; t < t1; t += 4) {
-          float v[4];
-#pragma unroll
-          for (int k = 0; k < 4; ++k)
-            v[k] = t + k < t1 ? S.part[static_cast<int64_t>(t + k) * S.ldc + j] : 0.f;
-#pragma unroll
-          for (int k = 0; k < 4; ++k) u += static_cast<double>(v[k]);
-        }
-        const double xn = xi + S.gamma * ((xo - xi) - u);
-        x[o] = xn;
-        s += xn;
-      }
-    }
-    part[bl][lane] = s;
-    __syncthreads();
-    if (bl == 0 && j < S.n) {
-      const double tot = ((part[0][lane] + part[1][lane]) + (part[2][lane] + part[3][lane])) +
-                         ((part[4][lane] + part[5][lane]) + (part[6][lane] + part[7][lane]));
-      const double v = (S.eta / S.m) * tot + (1.0 - S.eta) * S.xbar[j];
-      S.xbar[j] = v;
-      xb[lane] = v;
-    }
-    __syncthreads();
-    if (j < S.n) {
-      float* d = static_cast<float*>(S.d);
-      for (int i = bl; i < S.m; i += 8)
-        d[static_cast<int64_t>(i) * S.ldc + j] =
-            static_cast<float>(xb[lane] - x[static_cast<int64_t>(i) * S.ldc + j]);
-    }
-    __syncthreads();
+    combine_item(sys[w.x], w.y, part, xb);
   }
 }
 
@@ -347,7 +356,81 @@ __global__ void k_batch_check(const BatchSys* sys, int32_t count, const int32_t*
   if (!(rr > rtol) || !isfinite(rr)) active[s] = 0;
 }
 
+// One launch of a mixed batch: every workgroup loops over the work list and
+// runs each item with the matching device function (the contraction tile of
+// k_tn with 64-row tiles, two steps of prefetch; the k = 1 single-pass tile
+// and combine of the batch kernels above; the elementwise epilogues).  The
+// item kinds share one LDS buffer.
+template <int NCT>
+__global__ __launch_bounds__(256) void k_batch_mixed(const BatchSys* sys, const BatchGemm* gemm,
+                                                     const int4* items, int32_t nitems,
+                                                     const int32_t* active) {
+  constexpr size_t kTn = sizeof(TnStage<NCT>);
+  constexpr size_t kRed = sizeof(float) * 4 * kBatchFusedCols;
+  constexpr size_t kBytes = kTn > kRed ? kTn : kRed;
+  __shared__ __attribute__((aligned(16))) unsigned char lds[kBytes];
+  for (int32_t it = blockIdx.x; it < nitems; it += gridDim.x) {
+    const int4 w = items[it];
+    if (!active[w.x >> 8]) continue;  // uniform per workgroup
+    const int kind = w.x & 0xff;
+    if (kind == kItemFused) {
+      fused_item(sys[w.y], w.z, *reinterpret_cast<float(*)[4][kBatchFusedCols]>(lds));
+    } else if (kind == kItemCombine) {
+      combine_item(sys[w.y], w.z, *reinterpret_cast<double(*)[8][32]>(lds),
+                   *reinterpret_cast<double(*)[32]>(lds + sizeof(double) * 8 * 32));
+    } else if (kind == kItemTn32 || kind == kItemTn64) {
+      const TnArgs a = gemm[w.y].tn[w.z];
+      if (kind == kItemTn32)
+        tn_block<float, 1, NCT, 2, 1>(a, w.w, *reinterpret_cast<TnStage<NCT>*>(lds));
+      else
+        tn_block<double, 1, NCT, 2, 0>(a, w.w, *reinterpret_cast<TnStage<NCT>*>(lds));
+      __syncthreads();
+    } else {
+      const BatchGemm& G = gemm[w.y];
+      const int64_t e0 = static_cast<int64_t>(w.w) * kBatchChunk;
+      if (kind == kItemSum32 || kind == kItemSum64) {
+        const int64_t total = static_cast<int64_t>(G.kp) * G.sum_rows;
+        const int64_t e1 = min(total, e0 + kBatchChunk);
+        const int64_t stride = static_cast<int64_t>(G.kp) * G.sum_ldp;
+        for (int64_t e = e0 + threadIdx.x; e < e1; e += 256) {
+          if (kind == kItemSum32)
+            sum_cast_elem(static_cast<const float*>(G.sum_part), G.sum_nsplit[0], G.sum_ldp,
+                          G.sum_rows, stride, static_cast<float*>(G.sum_out[0]), G.sum_ldo, e);
+          else
+            sum_cast_elem(static_cast<const double*>(G.sum_part), G.sum_nsplit[1], G.sum_ldp,
+                          G.sum_rows, stride, static_cast<double*>(G.sum_out[1]), G.sum_ldo, e);
+        }
+      } else if (kind == kItemUpd32 || kind == kItemUpd64) {
+        const TnUpdateArgs& u = G.upd[kind == kItemUpd64 ? 1 : 0];
+        const int64_t e1 = min(static_cast<int64_t>(u.kp) * u.n, e0 + kBatchChunk);
+        for (int64_t e = e0 + threadIdx.x; e < e1; e += 256) {
+          if (kind == kItemUpd32) update_elem<float, float>(u, e);
+          else update_elem<double, float>(u, e);
+        }
+      } else if (kind == kItemAnchorVec) {
+        const int64_t e1 = min(G.state_count, e0 + kBatchChunk);
+        for (int64_t e = e0 + threadIdx.x; e < e1; e += 256)
+          G.yref[e] = (1.0 - G.gamma) * G.y[e] + G.gamma * G.xbar[e];
+      }
+    }
+  }
+}
+
 }  // namespace
+
+hipError_t launch_batch_mixed(int32_t grid, int32_t nct, const BatchSys* sys, const BatchGemm* gemm,
+                              const int4* items, int32_t nitems, const int32_t* active,
+                              hipStream_t s) {
+  if (nitems <= 0) return hipSuccess;
+  switch (nct) {
+    case 1: k_batch_mixed<1><<<grid, 256, 0, s>>>(sys, gemm, items, nitems, active); break;
+    case 2: k_batch_mixed<2><<<grid, 256, 0, s>>>(sys, gemm, items, nitems, active); break;
+    case 4: k_batch_mixed<4><<<grid, 256, 0, s>>>(sys, gemm, items, nitems, active); break;
+    case 8: k_batch_mixed<8><<<grid, 256, 0, s>>>(sys, gemm, items, nitems, active); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
 
 hipError_t launch_batch_pass_a(int f64, int32_t grid, const BatchSys* sys, const int4* items,
                                int32_t nitems, const int32_t* active, hipStream_t s) {

@@ -2193,7 +2193,21 @@ struct apc_batch_s {
   int32_t gridA = 1024, gridB = 1024, gridV = 1024;
   float tuned_us = 0.f;
   std::vector<int32_t> h_active;
-  std::map<int32_t, std::pair<hipGraph_t, hipGraphExec_t>> graphs;
+  std::map<std::pair<int32_t, int32_t>, std::pair<hipGraph_t, hipGraphExec_t>> graphs;
+  // Mixed batch (k-RHS plans with k = 1 systems): per-update work lists of
+  // the four launches, for ordinary [0] and anchor [1] updates, and the
+  // anchor prologue; the k-RHS plans' descriptors and their anchor cycle.
+  bool mixed = false;
+  BatchGemm* gemm = nullptr;
+  std::vector<int32_t> gemm_sys;       // system index of each k-RHS plan
+  std::vector<int32_t> gemm_slot;      // its residual slot in `partial`
+  int4* itemsL[2][4] = {};
+  int32_t nL[2][4] = {};
+  int4* itemsL0 = nullptr;
+  int32_t nL0 = 0;
+  int32_t nct = 1;
+  int32_t anchor_every = 0;
+  int64_t since = 0;                   // updates of the k-RHS plans' anchor cycle
 };
 
 namespace {
@@ -2202,6 +2216,9 @@ struct BatchPlanItems {
   std::vector<int4> A, B;
   std::vector<int2> V;
   std::vector<int2> F, W;  // single pass (when every plan has it and rows fit)
+  std::vector<int4> L[2][4], L0;  // mixed batch work lists
+  std::vector<BatchGemm> gemm;
+  std::vector<int32_t> gemm_sys, gemm_slot;
   // Single pass: every system's row tiles (up to kBatchTileRows rows of one
   // block) as row0[t], nrows[t], blk[t], then first[i] (m + 1), concatenated;
   // tile_at[s] is system s's offset in that array.
@@ -2217,15 +2234,59 @@ constexpr int kBatchTileRows = 64;
 bool batch_single_pass(const apc_plan* plans, int32_t count) {
   if (const char* e = std::getenv("APC_FUSED"))
     if (std::atoi(e) == 0) return false;
-  for (int32_t s = 0; s < count; ++s)
+  for (int32_t s = 0; s < count; ++s) {
+    if (plans[s]->gemm) continue;
     if (!plans[s]->fused || plans[s]->L.ldc > kBatchFusedCols) return false;
+  }
   return true;
+}
+
+// The descriptor of a k-RHS plan in a mixed batch: its four contractions
+// (arguments as update_gemm forms them), split sums and updates.
+BatchGemm batch_gemm_desc(apc_plan_s* P) {
+  const Layout& L = P->L;
+  void* part = P->ws + L.tnpart;
+  BatchGemm G{};
+  G.tn[0] = pass_a_args(P);
+  G.tn[1] = pass_b_args(P);
+  G.tn[2] = tn_args(P->ws + L.C64p, L.np, L.Np, P->ws + L.yref, L.np, P->kp, L.np, P->tnR, kTnF64,
+                    part, L.Np);
+  G.tn[3] = tn_args(P->ws + L.C64T, L.Np, L.np, P->ws + L.W64, L.Np, P->kp, L.Np, P->tnX0, kTnF64,
+                    part, L.np);
+  for (int q = 0; q < 4; ++q)
+    G.tn_blocks[q] = static_cast<int32_t>((G.tn[q].rows / 64) * (P->kp / (16 * std::min(8, P->kp / 16))) *
+                                          G.tn[q].nsplit);
+  G.sum_part = part;
+  G.sum_nsplit[0] = P->tnA.nsplit;
+  G.sum_nsplit[1] = P->tnR.nsplit;
+  G.sum_ldp = L.Np;
+  G.sum_rows = L.Np;
+  G.sum_out[0] = P->ws + L.Wq;
+  G.sum_out[1] = P->ws + L.W64;
+  G.sum_ldo = L.Np;
+  G.kp = P->kp;
+  G.upd[0] = update_args(P, P->tnB, 0);
+  G.upd[1] = update_args(P, P->tnX0, 2);
+  G.y = P->at<double>(L.ys);
+  G.xbar = P->xbar();
+  G.yref = P->anchor_every > 0 ? P->at<double>(L.yref) : nullptr;
+  G.state_count = static_cast<int64_t>(P->kp) * L.np;
+  G.gamma = P->gamma;
+  return G;
 }
 
 apc_status batch_items(const apc_plan* plans, int32_t count, BatchPlanItems* it) {
   it->start.push_back(0);
   for (int32_t s = 0; s < count; ++s) {
     const apc_plan_s* P = plans[s];
+    if (P->gemm) {
+      // One residual slot, filled by the plan's own FP64 residual (an empty
+      // pass-A item keeps the slot's index in the per-system ranges).
+      it->gemm_slot.push_back(static_cast<int32_t>(it->A.size()));
+      it->A.push_back(make_int4(s, 0, 0, 0));
+      it->start.push_back(static_cast<int32_t>(it->A.size()));
+      continue;
+    }
     for (int i = 0; i < P->m; ++i) {
       const int64_t r0 = P->off[i], p = P->off[i + 1] - r0;
       for (int64_t r = 0; r < p; r += 16)
@@ -2238,6 +2299,10 @@ apc_status batch_items(const apc_plan* plans, int32_t count, BatchPlanItems* it)
   if (batch_single_pass(plans, count)) {
     for (int32_t s = 0; s < count; ++s) {
       const apc_plan_s* P = plans[s];
+      if (P->gemm) {
+        it->tile_at.push_back(it->tiles.size());
+        continue;
+      }
       std::vector<int32_t> r0, nr, bk, first(1, 0);
       for (int i = 0; i < P->m; ++i) {
         const int64_t p = P->off[i + 1] - P->off[i];
@@ -2254,11 +2319,42 @@ apc_status batch_items(const apc_plan* plans, int32_t count, BatchPlanItems* it)
       for (int64_t j = 0; j < P->n; j += 32) it->W.push_back(make_int2(s, static_cast<int>(j)));
     }
   }
+  // Mixed batch: the k-RHS plans' contraction tiles and epilogue chunks next
+  // to the k = 1 items, one list per launch.  Contraction tiles first (they
+  // take longest), then the k = 1 work.
+  bool any_gemm = false;
+  for (int32_t s = 0; s < count; ++s) any_gemm = any_gemm || plans[s]->gemm;
+  if (!any_gemm) return APC_OK;
+  auto item = [](int kind, int sys, int desc, int z, int w) { return make_int4(kind | (sys << 8), desc, z, w); };
+  for (int32_t s = 0; s < count; ++s) {
+    apc_plan_s* P = plans[s];
+    if (!P->gemm) continue;
+    const int g = static_cast<int>(it->gemm.size());
+    it->gemm.push_back(batch_gemm_desc(P));
+    it->gemm_sys.push_back(s);
+    const BatchGemm& G = it->gemm.back();
+    auto chunks = [](int64_t total) { return static_cast<int>((total + kBatchChunk - 1) / kBatchChunk); };
+    for (int v = 0; v < 2; ++v) {
+      const int tnk = v ? kItemTn64 : kItemTn32;
+      for (int b = 0; b < G.tn_blocks[v ? 2 : 0]; ++b) it->L[v][0].push_back(item(tnk, s, g, v ? 2 : 0, b));
+      const int nsum = chunks(static_cast<int64_t>(G.kp) * G.sum_rows);
+      for (int c = 0; c < nsum; ++c) it->L[v][1].push_back(item(v ? kItemSum64 : kItemSum32, s, g, v, c));
+      for (int b = 0; b < G.tn_blocks[v ? 3 : 1]; ++b) it->L[v][2].push_back(item(tnk, s, g, v ? 3 : 1, b));
+      const int nupd = chunks(static_cast<int64_t>(G.upd[v].kp) * G.upd[v].n);
+      for (int c = 0; c < nupd; ++c) it->L[v][3].push_back(item(v ? kItemUpd64 : kItemUpd32, s, g, v, c));
+    }
+    if (G.yref)
+      for (int c = 0; c < chunks(G.state_count); ++c) it->L0.push_back(item(kItemAnchorVec, s, g, 0, c));
+  }
+  for (int v = 0; v < 2; ++v) {
+    for (const int2& f : it->F) it->L[v][0].push_back(item(kItemFused, f.x, f.x, f.y, 0));
+    for (const int2& w : it->W) it->L[v][1].push_back(item(kItemCombine, w.x, w.x, w.y, 0));
+  }
   return APC_OK;
 }
 
 struct BatchLayout {
-  size_t sys, A, B, V, F, W, T, active, start, partial, relres, total;
+  size_t sys, A, B, V, F, W, T, active, start, partial, relres, gemm, L[2][4], L0, total;
 };
 
 BatchLayout batch_layout(int32_t count, const BatchPlanItems& it) {
@@ -2280,6 +2376,10 @@ BatchLayout batch_layout(int32_t count, const BatchPlanItems& it) {
   L.start = take(static_cast<int64_t>(count + 1) * 4);
   L.partial = take(static_cast<int64_t>(it.A.size()) * 8);
   L.relres = take(static_cast<int64_t>(count) * 8);
+  L.gemm = take(static_cast<int64_t>(it.gemm.size()) * sizeof(BatchGemm));
+  for (int v = 0; v < 2; ++v)
+    for (int q = 0; q < 4; ++q) L.L[v][q] = take(static_cast<int64_t>(it.L[v][q].size()) * sizeof(int4));
+  L.L0 = take(static_cast<int64_t>(it.L0.size()) * sizeof(int4));
   L.total = cur;
   return L;
 }
@@ -2289,15 +2389,43 @@ apc_status batch_check_plans(const apc_plan* plans, int32_t count) {
   for (int32_t s = 0; s < count; ++s) {
     const apc_plan_s* P = plans[s];
     if (!P) return fail(APC_EINVAL, "plan %d is NULL", s);
-    if (P->gemm || P->k != 1 || P->prec != APC_F32)
-      return fail(APC_EUNSUPPORTED, "plan %d: batches take k = 1 FP32 plans in the per-block form", s);
+    if (P->prec != APC_F32 || P->bf16 || (P->gemm && P->tq != kTnF32) || (!P->gemm && P->k != 1))
+      return fail(APC_EUNSUPPORTED, "plan %d: batches take FP32 plans (k = 1 per-block form, or the "
+                  "k-RHS form with FP32 products)", s);
+    if (P->gemm && P->kp > 128)
+      return fail(APC_EUNSUPPORTED, "plan %d: k-RHS plans in a batch need k <= 128", s);
+    if (s >= (1 << 23)) return fail(APC_EINVAL, "too many plans");
     if (P->stream != plans[0]->stream) return fail(APC_EINVAL, "plans must share one stream");
     if (P->n > (1 << 30) || P->N > (1 << 30)) return fail(APC_EINVAL, "plan %d too large", s);
   }
+  // k-RHS plans share one launch shape and one anchor cycle, and k = 1 plans
+  // next to them must update in one pass.
+  const apc_plan_s* first = nullptr;
+  for (int32_t s = 0; s < count; ++s) {
+    const apc_plan_s* P = plans[s];
+    if (!P->gemm) continue;
+    if (!first) { first = P; continue; }
+    if (P->kp != first->kp || P->anchor_every != first->anchor_every || P->since_start != first->since_start)
+      return fail(APC_EUNSUPPORTED, "k-RHS plans in one batch need the same padded k, anchor spacing "
+                  "and number of updates since their start");
+  }
+  if (first && !batch_single_pass(plans, count))
+    return fail(APC_EUNSUPPORTED, "k = 1 plans next to k-RHS plans must update in one pass "
+                "(rows up to %d wide)", kBatchFusedCols);
   return APC_OK;
 }
 
 apc_status batch_update(apc_batch_s* B) {
+  if (B->mixed) {
+    const int v = B->anchor_every > 0 && B->since % B->anchor_every == 0 ? 1 : 0;
+    if (v) HIP_TRY(launch_batch_mixed(B->gridA, B->nct, B->sys, B->gemm, B->itemsL0, B->nL0, B->active,
+                                      B->stream));
+    for (int q = 0; q < 4; ++q)
+      HIP_TRY(launch_batch_mixed(B->gridA, B->nct, B->sys, B->gemm, B->itemsL[v][q], B->nL[v][q],
+                                 B->active, B->stream));
+    ++B->since;
+    return APC_OK;
+  }
   if (B->fused) {
     HIP_TRY(launch_batch_fused(B->gridA, B->sys, B->itemsF, B->nF, B->active, B->stream));
     HIP_TRY(launch_batch_fused_combine(B->gridV, B->sys, B->itemsW, B->nW, B->active, B->stream));
@@ -2311,7 +2439,10 @@ apc_status batch_update(apc_batch_s* B) {
 
 void batch_count(apc_batch_s* B, int32_t T) {
   for (int32_t s = 0; s < B->count; ++s)
-    if (B->h_active[s]) B->plans[s]->iters += T;
+    if (B->h_active[s]) {
+      B->plans[s]->iters += T;
+      if (B->plans[s]->gemm) B->plans[s]->since_start += T;
+    }
 }
 
 }  // namespace
@@ -2357,6 +2488,23 @@ apc_status apc_batch_create(apc_batch* out, const apc_plan* plans, int32_t count
   B->nB = static_cast<int32_t>(it.B.size());
   B->nV = static_cast<int32_t>(it.V.size());
   B->fused = !it.F.empty();
+  B->mixed = !it.gemm.empty();
+  if (B->mixed) {
+    B->gemm = reinterpret_cast<BatchGemm*>(B->ws + L.gemm);
+    B->gemm_sys = it.gemm_sys;
+    B->gemm_slot = it.gemm_slot;
+    for (int v = 0; v < 2; ++v)
+      for (int q = 0; q < 4; ++q) {
+        B->itemsL[v][q] = reinterpret_cast<int4*>(B->ws + L.L[v][q]);
+        B->nL[v][q] = static_cast<int32_t>(it.L[v][q].size());
+      }
+    B->itemsL0 = reinterpret_cast<int4*>(B->ws + L.L0);
+    B->nL0 = static_cast<int32_t>(it.L0.size());
+    const apc_plan_s* G0 = plans[it.gemm_sys[0]];
+    B->nct = std::min(8, G0->kp / 16);
+    B->anchor_every = G0->anchor_every;
+    B->since = G0->since_start;
+  }
   B->itemsF = reinterpret_cast<int2*>(B->ws + L.F);
   B->itemsW = reinterpret_cast<int2*>(B->ws + L.W);
   B->nF = static_cast<int32_t>(it.F.size());
@@ -2382,7 +2530,7 @@ apc_status apc_batch_create(apc_batch* out, const apc_plan* plans, int32_t count
     d.gamma = P->gamma;
     d.eta = P->eta;
     d.bnorm = P->bnorm;
-    if (B->fused) {
+    if (B->fused && !P->gemm) {
       // The plan's partial-row slice holds at least one FP64 row per 16 rows
       // of a block, so one FP32 row per tile of up to 64 rows fits.
       const int32_t* tl = reinterpret_cast<const int32_t*>(B->ws + L.T) + it.tile_at[s];
@@ -2406,6 +2554,15 @@ apc_status apc_batch_create(apc_batch* out, const apc_plan* plans, int32_t count
     HIP_TRY(hipMemcpyAsync(B->itemsF, it.F.data(), it.F.size() * sizeof(int2), hipMemcpyHostToDevice, st));
     HIP_TRY(hipMemcpyAsync(B->itemsW, it.W.data(), it.W.size() * sizeof(int2), hipMemcpyHostToDevice, st));
   }
+  if (B->mixed) {
+    HIP_TRY(hipMemcpyAsync(B->gemm, it.gemm.data(), it.gemm.size() * sizeof(BatchGemm),
+                           hipMemcpyHostToDevice, st));
+    for (int v = 0; v < 2; ++v)
+      for (int q = 0; q < 4; ++q)
+        HIP_TRY(hipMemcpyAsync(B->itemsL[v][q], it.L[v][q].data(), it.L[v][q].size() * sizeof(int4),
+                               hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(B->itemsL0, it.L0.data(), it.L0.size() * sizeof(int4), hipMemcpyHostToDevice, st));
+  }
   HIP_TRY(hipMemcpyAsync(B->active, B->h_active.data(), count * 4, hipMemcpyHostToDevice, st));
   HIP_TRY(hipMemcpyAsync(B->item_start, it.start.data(), it.start.size() * 4, hipMemcpyHostToDevice, st));
   // Persistent grid: time the pass over the factors for a few workgroup
@@ -2423,6 +2580,9 @@ apc_status apc_batch_create(apc_batch* out, const apc_plan* plans, int32_t count
       // The pass that streams the factors (it writes only scratch: w, or the
       // partial rows).
       auto stream_pass = [&]() {
+        if (B->mixed)
+          return launch_batch_mixed(c, B->nct, B->sys, B->gemm, B->itemsL[0][0], B->nL[0][0],
+                                    B->active, st);
         return B->fused ? launch_batch_fused(c, B->sys, B->itemsF, B->nF, B->active, st)
                         : launch_batch_pass_a(0, c, B->sys, B->itemsA, B->nA, B->active, st);
       };
@@ -2463,14 +2623,23 @@ apc_status apc_batch_iterate_graph(apc_batch b, int32_t T) {
   if (!b || T < 0) return fail(APC_EINVAL, "bad argument");
   if (T == 0) return APC_OK;
   if (b->stream == nullptr) return fail(APC_EINVAL, "graph capture needs a non-default stream");
-  auto itg = b->graphs.find(T);
+  const int32_t phase = b->mixed && b->anchor_every > 0
+                            ? static_cast<int32_t>(b->since % b->anchor_every) : 0;
+  const auto key = std::make_pair(T, phase);
+  auto itg = b->graphs.find(key);
   if (itg == b->graphs.end()) {
+    // Nothing runs during capture: the anchor cycle is put back after it.
+    const int64_t since = b->since;
     hipGraph_t g = nullptr;
     HIP_TRY(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
     apc_status st = APC_OK;
     for (int32_t t = 0; t < T && st == APC_OK; ++t) st = batch_update(b);
     hipError_t e = hipStreamEndCapture(b->stream, &g);
-    if (st != APC_OK) return st;
+    b->since = since;
+    if (st != APC_OK) {
+      if (g) (void)hipGraphDestroy(g);
+      return st;
+    }
     HIP_TRY(e);
     hipGraphExec_t ex = nullptr;
     e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
@@ -2478,9 +2647,10 @@ apc_status apc_batch_iterate_graph(apc_batch b, int32_t T) {
       (void)hipGraphDestroy(g);
       HIP_TRY(e);
     }
-    itg = b->graphs.emplace(T, std::make_pair(g, ex)).first;
+    itg = b->graphs.emplace(key, std::make_pair(g, ex)).first;
   }
   HIP_TRY(hipGraphLaunch(itg->second.second, b->stream));
+  b->since += T;
   batch_count(b, T);
   return APC_OK;
 }
@@ -2488,6 +2658,16 @@ apc_status apc_batch_iterate_graph(apc_batch b, int32_t T) {
 apc_status apc_batch_residuals(apc_batch b, double rtol, double* relres, int32_t* active) {
   if (!b) return fail(APC_EINVAL, "batch is NULL");
   HIP_TRY(launch_batch_resid(b->gridA, b->sys, b->itemsA, b->nA, b->active, b->partial, b->stream));
+  // k-RHS plans: ||B - A X_bar||_F^2 in FP64 by the plan's own residual, into
+  // the system's slot.
+  for (size_t g = 0; g < b->gemm_sys.size(); ++g) {
+    apc_plan_s* P = b->plans[b->gemm_sys[g]];
+    double* Rb = P->at<double>(P->L.Rb);
+    ST_TRY(gemm_residual(P, P->xbar(), Rb));
+    HIP_TRY(launch_sumsq(Rb, static_cast<int64_t>(P->k) * P->N, P->at<double>(P->L.ssq), b->stream));
+    HIP_TRY(launch_sum_partials(P->at<double>(P->L.ssq), sumsq_parts(), b->partial + b->gemm_slot[g],
+                                b->stream));
+  }
   HIP_TRY(launch_batch_check(b->sys, b->count, b->item_start, b->partial, rtol, b->active,
                              b->relres, b->stream));
   std::vector<double> rr(b->count);
@@ -2546,9 +2726,17 @@ apc_status apc_batch_get_launch(apc_batch b, int32_t* grid, int32_t* items_a, in
                                 int32_t* items_avg, float* tuned_us) {
   if (!b) return fail(APC_EINVAL, "batch is NULL");
   if (grid) *grid = b->gridA;
-  if (items_a) *items_a = b->fused ? b->nF : b->nA;
-  if (items_b) *items_b = b->fused ? 0 : b->nB;
-  if (items_avg) *items_avg = b->fused ? b->nW : b->nV;
+  if (b->mixed) {
+    // Items of the launches of an ordinary update: pass A with the k = 1
+    // single pass, pass B, and the split sums with the k = 1 combine.
+    if (items_a) *items_a = b->nL[0][0];
+    if (items_b) *items_b = b->nL[0][2];
+    if (items_avg) *items_avg = b->nL[0][1];
+  } else {
+    if (items_a) *items_a = b->fused ? b->nF : b->nA;
+    if (items_b) *items_b = b->fused ? 0 : b->nB;
+    if (items_avg) *items_avg = b->fused ? b->nW : b->nV;
+  }
   if (tuned_us) *tuned_us = b->tuned_us;
   return APC_OK;
 }

@@ -409,6 +409,45 @@ hipError_t launch_batch_fused(int32_t grid, const BatchSys* sys, const int2* ite
                               const int32_t* active, hipStream_t s);
 hipError_t launch_batch_fused_combine(int32_t grid, const BatchSys* sys, const int2* items,
                                       int32_t nitems, const int32_t* active, hipStream_t s);
+
+// Mixed batches: k-RHS plans (the (y, x_bar) form with FP32 products and
+// optional FP64 anchor updates) run in the same persistent launches as k = 1
+// single-pass systems.  Per update four launches, each over one work list:
+//   1. pass-A contraction tiles (W = C y; FP64 C with y_ref on anchor updates)
+//      and the k = 1 single-pass tiles
+//   2. split sums of W (W64 on anchor updates) and the k = 1 combine items
+//   3. pass-B contraction tiles (Z = C^T W)
+//   4. (y, x_bar) update chunks (anchor update on anchor updates)
+// preceded on anchor updates by one launch of y_ref chunks.
+// Items: int4 {kind | system << 8, descriptor (BatchSys or BatchGemm index),
+// which / tile / column, block or chunk}.
+struct BatchGemm {
+  TnArgs tn[4];           // pass A, pass B (FP32 factor), anchor pass A, anchor pass B (FP64)
+  int32_t tn_blocks[4];   // 64-row tiles x splits of each contraction
+  const void* sum_part;   // split sums: partials, split count (FP32, FP64 anchor),
+  int32_t sum_nsplit[2];  // stride, rows, outputs (W FP32, W64 FP64)
+  int64_t sum_ldp;
+  int64_t sum_rows;
+  void* sum_out[2];
+  int64_t sum_ldo;
+  int32_t kp;
+  TnUpdateArgs upd[2];    // update (FP32 partials), anchor update (FP64 partials)
+  const double* y;        // y_ref = (1 - gamma) y + gamma x_bar before an anchor update
+  const double* xbar;
+  double* yref;
+  int64_t state_count;    // kp * np
+  double gamma;
+};
+enum BatchItemKind {
+  kItemFused = 0, kItemCombine = 1, kItemTn32 = 2, kItemTn64 = 3, kItemSum32 = 4,
+  kItemSum64 = 5, kItemUpd32 = 6, kItemUpd64 = 7, kItemAnchorVec = 8
+};
+constexpr int kBatchChunk = 2048;  // elements per split-sum / update / y_ref item
+// nct = kp / 16 of the k-RHS plans (1, 2, 4 or 8).
+hipError_t launch_batch_mixed(int32_t grid, int32_t nct, const BatchSys* sys, const BatchGemm* gemm,
+                              const int4* items, int32_t nitems, const int32_t* active,
+                              hipStream_t s);
+
 hipError_t launch_batch_pass_a(int f64, int32_t grid, const BatchSys* sys, const int4* items,
                                int32_t nitems, const int32_t* active, hipStream_t s);
 hipError_t launch_batch_pass_b(int f64, int32_t grid, const BatchSys* sys, const int4* items,
