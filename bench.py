@@ -105,14 +105,18 @@ def chunks_per_thread(n, elem):
     return c
 
 
-def cpu_baseline(S, per_iter_bytes, budget_iters=8):
+def cpu_baseline(S, per_iter_bytes, gamma, eta, updates_to_target, budget_iters=8,
+                 single_iters=2):
     """The FP64 oracle, as it stands, on the same system: factor + init once, then a few
-    updates; reported in the benchmark's unit (the GPU path's bytes per update)."""
+    updates on all host threads and a few on one thread; reported in the benchmark's
+    unit (the GPU path's bytes per update), with the oracle's time to the target error
+    (its setup plus the updates the GPU path needed, with the same gamma and eta)."""
     from oracle import apc_oracle as O
     try:
-        from threadpoolctl import threadpool_info
+        from threadpoolctl import threadpool_info, threadpool_limits
         cores = max([p.get("num_threads", 1) for p in threadpool_info()] or [1])
     except Exception:
+        threadpool_limits = None
         cores = os.cpu_count() or 1
     t0 = time.perf_counter()
     Qt, R = O.factor(S.A, S.off)
@@ -121,18 +125,32 @@ def cpu_baseline(S, per_iter_bytes, budget_iters=8):
     t_setup = time.perf_counter() - t0
     t1 = time.perf_counter()
     for _ in range(budget_iters):
-        x, xbar = O.apc_step(Qt, x, xbar, 1.0158, 32.03)
+        x, xbar = O.apc_step(Qt, x, xbar, gamma, eta)
     t_iter = (time.perf_counter() - t1) / budget_iters
+    t_one = None
+    if threadpool_limits is not None:
+        with threadpool_limits(limits=1):
+            t2 = time.perf_counter()
+            for _ in range(single_iters):
+                x, xbar = O.apc_step(Qt, x, xbar, gamma, eta)
+            t_one = (time.perf_counter() - t2) / single_iters
     return {
         "value": per_iter_bytes / t_iter / 1e9,
         "unit": "GB/s",
         "cores": int(cores),
         "kind": "oracle",
         "sample": (f"FP64 NumPy oracle on the same 16384x8192 m=64 system: QR factor + init "
-                   f"({t_setup:.1f} s) then {budget_iters} updates at {t_iter * 1e3:.1f} ms each; "
-                   "value = GPU-path algorithmic bytes per update / oracle time per update"),
+                   f"({t_setup:.1f} s) then {budget_iters} updates at {t_iter * 1e3:.1f} ms each "
+                   f"on {cores} threads and {single_iters} on one thread; value = GPU-path "
+                   "algorithmic bytes per update / oracle time per update"),
         "ms_per_iter": t_iter * 1e3,
+        "ms_per_iter_1_thread": None if t_one is None else t_one * 1e3,
+        "value_1_thread": None if t_one is None else per_iter_bytes / t_one / 1e9,
         "setup_s": t_setup,
+        f"time_to_target_s": t_setup + updates_to_target * t_iter,
+        "time_to_target_note": (f"oracle setup (QR + init) + {updates_to_target} updates (the "
+                                "count the GPU path needed) on all threads; gamma and eta are "
+                                "given to it (its dense spectrum, ~30-50 s here, is not timed)"),
     }
 
 
@@ -150,8 +168,13 @@ def plain_updates_ms(plan, T):
 
 
 def _err(plan, xs, xs_norm):
+    """Relative error of x_bar against x*; with k columns the largest column error (the
+    figure the tolerances gate on)."""
     import torch
-    return float(torch.linalg.norm(plan.xbar() - xs)) / xs_norm
+    x = plan.xbar()
+    if x.dim() == 1:
+        return float(torch.linalg.norm(x - xs)) / xs_norm
+    return float(torch.max(torch.linalg.norm(x - xs, dim=0) / torch.linalg.norm(xs, dim=0)))
 
 
 MFMA_PEAK_TFLOPS = {"f32": 157.3, "bf16": 2500.0, "f64": 78.6}
@@ -215,7 +238,7 @@ def time_refined(apc, A, b, off, xs, rtol, ws, anchor=None):
     x, it, rr, st = plan.solve(rtol, 5000)
     torch.cuda.synchronize()
     t2 = time.perf_counter()
-    err = float(torch.linalg.norm(x - xs)) / xs_norm
+    err = float(torch.max(torch.linalg.norm(x - xs, dim=0) / torch.linalg.norm(xs, dim=0)))
     info = plan.info()
     plan.close()
     return {"rtol": rtol, "status": apc.STATUS_NAMES.get(st, st), "err": err, "updates": it,
@@ -332,6 +355,74 @@ def many_systems(apc, synth, dev, count=256):
         "solve_to_relres_1e-6": {"status": apc.STATUS_NAMES.get(st, st), "ms": round(solve_ms, 2),
                                  "updates_min": int(iters.min()), "updates_max": int(iters.max()),
                                  "max_rel_err": max(errs)},
+    }
+    batch.close()
+    for p in plans:
+        p.close()
+    return res
+
+
+def config3_one_batch(apc, synth, dev):
+    """Both parts of the batched workload in ONE batch: N = n = 8192, A = G/sqrt(n) + 2I,
+    k = 64, 64 uneven blocks (FP32 products, FP64 anchor every 16 updates) and the 256
+    independent k = 1 systems; every update is four launches of one persistent kernel over
+    work lists that cover both parts, replayed from a hipGraph."""
+    import torch
+    big = synth.shifted_uneven_8k(k=64)
+    many = synth.many_small_systems(count=256, seed=0)
+    stream = torch.cuda.Stream(device=dev)
+    plans, keep = [], []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for S in [big] + many:
+        A = torch.from_numpy(S.A).to(dev)
+        b = torch.from_numpy(np.ascontiguousarray(S.B)).to(dev)
+        keep.append((A, b))
+        plans.append(apc.Plan(A, b, S.off, "f32", stream=stream))
+    stream.synchronize()
+    setup_s = time.perf_counter() - t0
+    batch = apc.Batch(plans)
+    T = 16                                  # one anchor update per replay
+
+    def timed(fn, reps=3):
+        stream.synchronize()
+        t = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        stream.synchronize()
+        return (time.perf_counter() - t) / (reps * T)
+
+    batch.iterate(T, graph=True)            # capture + warm
+    t_graph = timed(lambda: batch.iterate(T, graph=True))
+    t_eager = timed(lambda: batch.iterate(T, graph=False))
+    for p in plans:
+        p.restart()
+    batch.activate()
+    stream.synchronize()
+    t = time.perf_counter()
+    iters, rr, st = batch.solve(1e-6, 400, check_every=8, graph=True)
+    stream.synchronize()
+    solve_ms = (time.perf_counter() - t) * 1e3
+    with torch.cuda.stream(stream):
+        xs = [p.xbar().cpu().numpy() for p in plans]
+    stream.synchronize()
+    errs = [float(np.max(np.linalg.norm((x - S.xstar).reshape(S.n, -1), axis=0)
+                         / np.linalg.norm(S.xstar.reshape(S.n, -1), axis=0)))
+            for x, S in zip(xs, [big] + many)]
+    res = {
+        "workload": "one batch: N=n=8192, A=G/sqrt(n)+2I, k=64, 64 uneven blocks (FP32, FP64 "
+                    "anchor every 16) + 256 systems n in [64, 1024], k = 1 (FP32)",
+        "launch": batch.launch(),
+        "launches_per_update": "4 (+1 y_ref prologue on anchor updates)",
+        "setup_s_all_plans": round(setup_s, 2),
+        "us_per_update_graph": round(t_graph * 1e6, 1),
+        "us_per_update_eager": round(t_eager * 1e6, 1),
+        "solve_to_relres_1e-6": {"status": apc.STATUS_NAMES.get(st, st), "ms": round(solve_ms, 2),
+                                 "updates_k64_system": int(iters[0]),
+                                 "updates_256_systems_min": int(iters[1:].min()),
+                                 "updates_256_systems_max": int(iters[1:].max()),
+                                 "max_rel_err_k64_system": errs[0],
+                                 "max_rel_err_256_systems": max(errs[1:])},
     }
     batch.close()
     for p in plans:
@@ -481,11 +572,14 @@ def secondary(apc, synth, dev):
         "plain_fp32_time_to_1e-6": time_plain(apc, A, b, S.off, xs, "f32", 1e-6, ws, anchor=0),
         "kernels": krhs_rates(apc, A, b, S.off, "f32", ws),
         "note": "FP32 projections on matrix cores with an FP64 anchor update every 16 updates "
-                "(default); plain_fp32 = every update in FP32",
+                "(default); plain_fp32 = every update's products in FP32 (the state y, x_bar "
+                "stays FP64 in every mode)",
     }
     del A, b, xs, ws, S
     torch.cuda.empty_cache()
     out["many_systems_fp32"] = many_systems(apc, synth, dev)
+    torch.cuda.empty_cache()
+    out["batched_one_launch"] = config3_one_batch(apc, synth, dev)
     torch.cuda.empty_cache()
     out["adjoint_fp32"] = adjoint_workload(apc, synth, dev)
     out["comparison_methods"] = comparison_methods(apc, synth, dev)
@@ -499,7 +593,11 @@ def secondary(apc, synth, dev):
     ws32 = torch.empty(apc.Plan.workspace_bytes(n, n, off, "f32", k=k), dtype=torch.uint8, device=dev)
     ws16 = torch.empty(apc.Plan.workspace_bytes(n, n, off, "bf16_ir", k=k), dtype=torch.uint8,
                        device=dev)
-    mixed = {"workload": "N=n=16384, A=G/sqrt(n)+alpha I, k=128, m=64 blocks of 256"}
+    mixed = {"workload": "N=n=16384, A=G/sqrt(n)+alpha I, k=128, m=64 blocks of 256",
+             "note": "plain_fp32: FP32 products on matrix cores with the state (y, x_bar) kept "
+                     "in FP64, no anchor updates; fp32_anchored: the same with an FP64 anchor "
+                     "update every 16; bf16_ir: bf16 products inside FP64 iterative refinement; "
+                     "errors are the largest column error against X* (B = A X* in FP64)"}
     for alpha in (3.0, 1.5):
         A = G.clone()
         A.diagonal().add_(alpha)
@@ -740,13 +838,22 @@ def main():
         },
         "params": prm,
         "relres_at_end": relres,
+        "paper_context": {
+            "note": "context only, not a target: the paper reports optimal convergence times "
+                    "T = 1/(-log rho) in iterations (Table 2), not wall-clock figures",
+            "table2_row": "standard tall Gaussian 1000 x 500, APC",
+            "table2_T_APC": 2.34,
+            "T_this_system_from_rho": round(1.0 / -math.log(prm["rho"]), 3),
+            "rho_estimated": prm["rho"],
+            f"updates_to_{args.target:g}": T,
+        },
     }
     if not args.main_only:
         del A, b, xs, ws
         torch.cuda.empty_cache()
         out.update(secondary(apc, synth, dev))
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(S, per_iter)
+        out["cpu_baseline"] = cpu_baseline(S, per_iter, prm["gamma"], prm["eta"], T)
     print(json.dumps(out), flush=True)
 
 

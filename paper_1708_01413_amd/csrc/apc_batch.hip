@@ -172,9 +172,9 @@ __global__ __launch_bounds__(256) void k_batch_average(const BatchSys* sys, cons
 // needs only a wave sum.  A wave takes RF = 16 / CPL rows at a time (rows
 // wv, wv + 4, ...), all their loads in flight, so short rows still keep 16
 // loads per lane in flight.  The four waves' partial rows are added in LDS.
-template <int CPL>
+template <int CPL, int INFLIGHT = 16>
 __device__ inline void batch_tile_pass(const BatchSys& S, int t, float (&red)[4][kBatchFusedCols]) {
-  constexpr int RF = 16 / CPL;
+  constexpr int RF = INFLIGHT / CPL;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int64_t row0 = S.tiles[t];
   const int nrows = S.tiles[S.ntiles + t];
@@ -226,11 +226,15 @@ __device__ inline void batch_tile_pass(const BatchSys& S, int t, float (&red)[4]
     for (int e = 0; e < 4; ++e) red[wv][(lane + 64 * c) * 4 + e] = acc[c][e];
 }
 
-// One single-pass item: tile t of system S, its partial row written.
+// One single-pass item: tile t of system S, its partial row written, with
+// INFLIGHT 16-byte loads per lane in flight (16 measured best, also in the
+// mixed kernel: 8 lowered its registers but took 342 against 326 us per update
+// of the 8192^2 k = 64 system with the 256 systems).
+template <int INFLIGHT = 16>
 __device__ inline void fused_item(const BatchSys& S, int t, float (&red)[4][kBatchFusedCols]) {
-  if (S.ldc <= 256) batch_tile_pass<1>(S, t, red);
-  else if (S.ldc <= 512) batch_tile_pass<2>(S, t, red);
-  else batch_tile_pass<4>(S, t, red);
+  if (S.ldc <= 256) batch_tile_pass<1, INFLIGHT>(S, t, red);
+  else if (S.ldc <= 512) batch_tile_pass<2, INFLIGHT>(S, t, red);
+  else batch_tile_pass<4, INFLIGHT>(S, t, red);
   __syncthreads();
   float* out = S.part + static_cast<int64_t>(t) * S.ldc;
   for (int64_t j = threadIdx.x; j < S.ldc; j += 256)
@@ -360,9 +364,11 @@ __global__ void k_batch_check(const BatchSys* sys, int32_t count, const int32_t*
 // runs each item with the matching device function (the contraction tile of
 // k_tn with 64-row tiles, two steps of prefetch; the k = 1 single-pass tile
 // and combine of the batch kernels above; the elementwise epilogues).  The
-// item kinds share one LDS buffer.
+// item kinds share one LDS buffer.  Registers are capped for two workgroups
+// per CU (one otherwise: 326 against 338 us per update for the 8192^2 k = 64
+// system with the 256 systems; four steps of prefetch took 345).
 template <int NCT>
-__global__ __launch_bounds__(256) void k_batch_mixed(const BatchSys* sys, const BatchGemm* gemm,
+__global__ __launch_bounds__(256, 2) void k_batch_mixed(const BatchSys* sys, const BatchGemm* gemm,
                                                      const int4* items, int32_t nitems,
                                                      const int32_t* active) {
   constexpr size_t kTn = sizeof(TnStage<NCT>);

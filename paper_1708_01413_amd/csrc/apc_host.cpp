@@ -2346,9 +2346,26 @@ apc_status batch_items(const apc_plan* plans, int32_t count, BatchPlanItems* it)
     if (G.yref)
       for (int c = 0; c < chunks(G.state_count); ++c) it->L0.push_back(item(kItemAnchorVec, s, g, 0, c));
   }
+  // The k = 1 systems are split between the two contraction launches (single
+  // pass with pass A, combine with the split sums; or single pass with pass B,
+  // combine with the update), balanced by the bytes of their factors, so that
+  // neither launch carries all of them next to a full contraction.
+  std::vector<int> side(count, 0);
+  int64_t load[2] = {0, 0};
+  std::vector<int32_t> order;
+  for (int32_t s = 0; s < count; ++s)
+    if (!plans[s]->gemm) order.push_back(s);
+  std::sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
+    return plans[a]->N * plans[a]->L.ldc > plans[b]->N * plans[b]->L.ldc;
+  });
+  for (int32_t s : order) {
+    const int q = load[0] <= load[1] ? 0 : 1;
+    side[s] = q;
+    load[q] += plans[s]->N * plans[s]->L.ldc;
+  }
   for (int v = 0; v < 2; ++v) {
-    for (const int2& f : it->F) it->L[v][0].push_back(item(kItemFused, f.x, f.x, f.y, 0));
-    for (const int2& w : it->W) it->L[v][1].push_back(item(kItemCombine, w.x, w.x, w.y, 0));
+    for (const int2& f : it->F) it->L[v][side[f.x] ? 2 : 0].push_back(item(kItemFused, f.x, f.x, f.y, 0));
+    for (const int2& w : it->W) it->L[v][side[w.x] ? 3 : 1].push_back(item(kItemCombine, w.x, w.x, w.y, 0));
   }
   return APC_OK;
 }

@@ -414,11 +414,12 @@ hipError_t launch_batch_fused_combine(int32_t grid, const BatchSys* sys, const i
 // optional FP64 anchor updates) run in the same persistent launches as k = 1
 // single-pass systems.  Per update four launches, each over one work list:
 //   1. pass-A contraction tiles (W = C y; FP64 C with y_ref on anchor updates)
-//      and the k = 1 single-pass tiles
-//   2. split sums of W (W64 on anchor updates) and the k = 1 combine items
+//   2. split sums of W (W64 on anchor updates)
 //   3. pass-B contraction tiles (Z = C^T W)
 //   4. (y, x_bar) update chunks (anchor update on anchor updates)
-// preceded on anchor updates by one launch of y_ref chunks.
+// preceded on anchor updates by one launch of y_ref chunks.  Each k = 1
+// system's single-pass tiles go with launch 1 and its combine with launch 2,
+// or with launches 3 and 4 (the systems are split between the two pairs).
 // Items: int4 {kind | system << 8, descriptor (BatchSys or BatchGemm index),
 // which / tile / column, block or chunk}.
 struct BatchGemm {
