@@ -308,16 +308,32 @@ apc_status apc_backward_noalloc(apc_plan p, const double* dXbar, int64_t ldd, in
 
 /* ---- Many independent systems (one persistent launch per pass) ----------
  *
- * A batch runs eq. (2a)-(2b) for many independent systems at once: every
- * system is a plan from apc_setup (k = 1, APC_F32, per-block form; all plans
- * on one stream), keeping its own factor and state in its own workspace.  Per
- * update a batch enqueues three launches for all systems together -- pass A
- * over a work list of (system, 16-row tile) items, pass B over (system, block,
- * column slab) items, the average over (system, column chunk) items -- each a
- * persistent grid of a fixed number of workgroups looping over the list.  The
- * grid is chosen at creation by timing pass A (APC_BATCH_GRID fixes it).  Each
- * system's gamma, eta and ||b|| are captured at creation.  The plans must
- * outlive the batch; apc_get_xbar etc. on a plan see the batch's updates. */
+ * A batch runs eq. (2a)-(2b) for many independent systems at once (Sec. 2's
+ * machines, Alg. 1, for many problems): every system is a plan from
+ * apc_setup, all plans on one stream, each keeping its own factor and state in
+ * its own workspace.  Two kinds of plans can be batched:
+ *   - k = 1, APC_F32, per-block form;
+ *   - the k-RHS (y, x_bar) form with FP32 products (k > 1 or APC_REDUCED_FORM,
+ *     k <= 128), with or without FP64 anchor updates.
+ * Every launch is a persistent grid of a fixed number of workgroups looping
+ * over a work list that covers all systems; items of inactive systems are
+ * skipped.  Per update:
+ *   - k = 1 plans only, single pass (every row at most 1024 wide): one launch
+ *     of (system, row tile) items that form each tile's partial row of
+ *     Q_i w_i, one of (system, column chunk) items for the x_i update, the
+ *     average and the next differences; otherwise three launches (pass A over
+ *     16-row tiles, pass B over (block, column slab) items, the average);
+ *   - with k-RHS plans: four launches -- pass-A contraction tiles (W = C y),
+ *     split sums of W, pass-B tiles (Z = C^T W), (y, x_bar) update chunks,
+ *     preceded on anchor updates by one launch of y_ref chunks -- and the
+ *     k = 1 plans' single-pass tiles and combine items ride in launches 1-2
+ *     or 3-4 (split between the two by factor size).  All k-RHS plans of one
+ *     batch must share k (padded), the anchor spacing and their count of
+ *     updates since the start; the batch follows one anchor cycle for them.
+ * The grid is chosen at creation by timing the first launch of an update
+ * (APC_BATCH_GRID fixes it).  Each system's gamma, eta and ||b|| are captured
+ * at creation.  The plans must outlive the batch; apc_get_xbar etc. on a plan
+ * see the batch's updates. */
 typedef struct apc_batch_s* apc_batch;
 
 /* Bytes of device workspace (descriptors and work lists) for a batch of these
@@ -325,8 +341,10 @@ typedef struct apc_batch_s* apc_batch;
 size_t apc_batch_workspace_bytes(const apc_plan* plans, int32_t count);
 
 /* Build the batch (host array of count plans; workspace device, 256-byte
- * aligned, caller-owned).  Synchronises.  APC_EUNSUPPORTED for plans other than
- * k = 1 FP32 per-block form, APC_EINVAL for mixed streams or a small workspace. */
+ * aligned, caller-owned).  Synchronises.  APC_EUNSUPPORTED for plans of other
+ * kinds (FP64, bf16, k-RHS with k > 128) or k-RHS plans that differ in k,
+ * anchor spacing or update count, or k = 1 plans that do not update in one
+ * pass next to k-RHS plans; APC_EINVAL for mixed streams or a small workspace. */
 apc_status apc_batch_create(apc_batch* out, const apc_plan* plans, int32_t count, void* workspace,
                             size_t ws_bytes);
 
@@ -334,11 +352,12 @@ apc_status apc_batch_create(apc_batch* out, const apc_plan* plans, int32_t count
 apc_status apc_batch_iterate(apc_batch b, int32_t T);
 
 /* The same T updates through a hipGraph: captured on the batch's stream at the
- * first call for this T (the stream must not be the default stream), replayed
- * after.  Results are identical to apc_batch_iterate. */
+ * first call for this T (and position in the k-RHS plans' anchor cycle; the
+ * stream must not be the default stream), replayed after.  Results are
+ * identical to apc_batch_iterate. */
 apc_status apc_batch_iterate_graph(apc_batch b, int32_t T);
 
-/* FP64 relative residual ||b_s - A_s x_bar_s|| / ||b_s|| of every active system
+/* FP64 relative residual ||B_s - A_s X_bar_s||_F / ||B_s||_F of every active system
  * into relres (host, count; inactive systems keep their last value), and
  * deactivate each system whose residual is <= rtol or not finite (rtol < 0:
  * none).  active (host, count, may be NULL) receives the flags.  Synchronises. */
@@ -347,11 +366,13 @@ apc_status apc_batch_residuals(apc_batch b, double rtol, double* relres, int32_t
 /* Mark every system active again. */
 apc_status apc_batch_activate(apc_batch b);
 
-/* Per-system stopping: check residuals every check_every updates, stop each
- * system once its residual is <= rtol, until none is left or max_iters updates
- * were applied.  use_graph != 0 runs the updates through apc_batch_iterate_graph.
- * iters_out, relres_out: host arrays of count (may be NULL).  APC_ENOCONV if
- * some system did not reach rtol.  Synchronises. */
+/* Per-system stopping: every system is checked afresh at entry, then
+ * residuals every check_every updates; each system stops once its residual is
+ * <= rtol (or not finite), until none is left or max_iters updates were
+ * applied.  use_graph != 0 runs the updates through apc_batch_iterate_graph.
+ * iters_out, relres_out: host arrays of count (may be NULL).  APC_EDIVERGED if
+ * some system's residual became non-finite, else APC_ENOCONV if some system
+ * did not reach rtol.  Synchronises. */
 apc_status apc_batch_solve(apc_batch b, double rtol, int32_t max_iters, int32_t check_every,
                            int32_t use_graph, int32_t* iters_out, double* relres_out);
 
@@ -360,7 +381,8 @@ apc_status apc_batch_solve(apc_batch b, double rtol, int32_t max_iters, int32_t 
  * timing.  A batch whose plans all update in one pass over their factor (rows
  * up to 1024 wide) does too: *items_a then counts its row tiles, *items_b is
  * 0 and *items_avg counts the 32-column items of the update + average launch.
- * Host pointers. */
+ * With k-RHS plans: the items of an ordinary update's first (pass A),
+ * third (pass B) and second (split sums) launches.  Host pointers. */
 apc_status apc_batch_get_launch(apc_batch b, int32_t* grid, int32_t* items_a, int32_t* items_b,
                                 int32_t* items_avg, float* tuned_us);
 
