@@ -47,8 +47,8 @@ typedef enum {
                   /* accumulation, iterates and update arithmetic in FP64          */
   APC_BF16_IR = 2, /* iterative refinement: inner APC on a bf16 Q_i (matrix cores, */
                    /* FP32 accumulation, FP64 state), FP64 residual B - A X and    */
-                   /* FP64 start x_bar(0) on matrix cores; setup QR and eigenvalue */
-                   /* estimate in FP64                                             */
+                   /* FP64 start x_bar(0) on matrix cores; setup QR in FP64, the  */
+                   /* eigenvalue estimate's recurrence in FP64 (see apc_setup)     */
   APC_REDUCED_FORM = 16 /* flag, OR'ed into APC_F64 / APC_F32: use the (y, x_bar)    */
                         /* form below also for k = 1 (needed by apc_backward)      */
 } apc_precision;
@@ -93,8 +93,13 @@ size_t apc_workspace_bytes(int64_t N, int64_t n, const int64_t* off, int32_t m, 
  *   gamma, eta  the parameters of eq. (2).  If either is NaN, both are set to
  *          Theorem 1's optimum from the extreme eigenvalues of
  *          X = (1/m) sum_i A_i^T (A_i A_i^T)^{-1} A_i (eq. (3)), estimated on
- *          the GPU in FP64 by Lanczos on X v = (1/m) sum_i Q_i Q_i^T v and
- *          widened to an interval that encloses the spectrum.
+ *          the GPU by Lanczos on X v = (1/m) sum_i Q_i Q_i^T v (recurrence,
+ *          reorthogonalisation and Ritz values in FP64; the product X v reads
+ *          the FP64 factor in APC_F64 plans and an FP32 copy of it otherwise,
+ *          with FP64 sums: relative error ~1e-7, far below the stopping
+ *          tolerances) and widened to an interval that encloses the spectrum:
+ *          mu_max by the top Ritz value's residual bound, mu_min by a margin
+ *          of up to 20 times the bottom Ritz value's last change.
  *   workspace  device, >= apc_workspace_bytes(...) bytes, 256-byte aligned,
  *          owned by the caller, used exclusively by this plan until destroy.
  *

@@ -1158,8 +1158,13 @@ apc_status lanczos(apc_plan_s* P, const NormalOp& op, double cap, double* lo_out
   if (!(th_lo > n * std::numeric_limits<double>::epsilon() * th_hi))
     return fail(APC_ESINGULAR, "smallest eigenvalue ~ 0 (Ritz value %g, largest %g): no unique "
                 "solution", th_lo, th_hi);
+  // The top end, where an underestimate of mu_max is the divergent side of
+  // Theorem 1, takes the whole residual bound |beta_k s_k| (some eigenvalue
+  // lies within it of the top Ritz value, which approaches mu_max from
+  // below).  The bottom end, where an overestimate only slows the iteration,
+  // takes at most 20 times its last change.
   const double m_lo = std::max(std::min(bd_lo, 20.0 * d_lo), 1e-13 * th_hi);
-  const double m_hi = std::max(std::min(bd_hi, 20.0 * d_hi), 1e-13 * th_hi);
+  const double m_hi = std::max(bd_hi, 1e-13 * th_hi);
   *lo_out = std::max(th_lo - m_lo, 0.5 * th_lo);
   *hi_out = std::min(th_hi + m_hi, cap);
   return APC_OK;
