@@ -1089,7 +1089,7 @@ apc_status lanczos(apc_plan_s* P, const NormalOp& op, double cap, double* lo_out
     // the convergence rates seen at the spectral edges here) with a factor of
     // 4 to spare.  The enclosing interval is then a few 1e-3 wide above mu_max
     // and ~10 % below mu_min, which raises rho by O(width) only: at the
-    // 16384 x 8192 benchmark shape 40 steps (each costs about 1.3 updates)
+    // 16384 x 8192 benchmark shape 37 steps (each costs about 1.2 updates)
     // instead of 76 for about two more updates to 1e-6.
     hist_lo.resize(k, NAN);
     hist_hi.resize(k, NAN);
