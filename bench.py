@@ -633,6 +633,9 @@ def main():
     ap.add_argument("--bf16-contraction-only", action="store_true",
                     help="only the mixed-precision system (16384^2, k = 128, alpha = 3): setup and "
                          "8 bf16 updates, for counter runs of the matrix-core contraction")
+    ap.add_argument("--f32-contraction-only", action="store_true",
+                    help="only the batched system (8192^2, k = 64, uneven blocks): setup and 8 "
+                         "FP32 updates without anchors, for counter runs of the FP32 contraction")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: sharding the blocks over several GPUs (one "
@@ -664,6 +667,17 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"workload": "N=n=16384, A=G/sqrt(n)+3I, k=128, m=64, bf16 contraction",
                           "updates": 8, "launch_shapes": plan.launch_shapes()}), flush=True)
+        return
+    if args.f32_contraction_only:
+        Sb = synth.shifted_uneven_8k(k=64)
+        Ab = torch.from_numpy(Sb.A).to(dev)
+        Bb = torch.from_numpy(np.ascontiguousarray(Sb.B)).to(dev)
+        plan = apc.Plan(Ab, Bb, Sb.off, "f32", gamma=1.0, eta=1.0, anchor_every=0)
+        plan.iterate(8)
+        torch.cuda.synchronize()
+        print(json.dumps({"workload": "N=n=8192, A=G/sqrt(n)+2I, k=64, 64 uneven blocks, FP32 "
+                          "contraction", "updates": 8, "launch_shapes": plan.launch_shapes()}),
+              flush=True)
         return
     S = synth.tall_gaussian_16k()
     N, n, m = S.N, S.n, S.m
