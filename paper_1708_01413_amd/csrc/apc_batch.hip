@@ -172,8 +172,16 @@ __global__ __launch_bounds__(256) void k_batch_average(const BatchSys* sys, cons
 // needs only a wave sum.  A wave takes RF = 16 / CPL rows at a time (rows
 // wv, wv + 4, ...), all their loads in flight, so short rows still keep 16
 // loads per lane in flight.  The four waves' partial rows are added in LDS.
+// Global-address-space view of a pointer read from a descriptor (its address
+// space is otherwise unknown and the loads become flat loads).
+typedef float g_f32x4 __attribute__((ext_vector_type(4)));
+__device__ inline const __attribute__((address_space(1))) g_f32x4* gptr4(const float* p) {
+  return reinterpret_cast<const __attribute__((address_space(1))) g_f32x4*>(
+      reinterpret_cast<uintptr_t>(p));
+}
+
 template <int CPL, int INFLIGHT = 16>
-__device__ inline void batch_tile_pass(const BatchSys& S, int t, float (&red)[4][kBatchFusedCols]) {
+__device__ __attribute__((always_inline)) inline void batch_tile_pass(const BatchSys& S, int t, float (&red)[4][kBatchFusedCols]) {
   constexpr int RF = INFLIGHT / CPL;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int64_t row0 = S.tiles[t];
@@ -181,43 +189,46 @@ __device__ inline void batch_tile_pass(const BatchSys& S, int t, float (&red)[4]
   const int blk = S.tiles[2 * S.ntiles + t];
   const float* C = static_cast<const float*>(S.C);
   const float* d = static_cast<const float*>(S.d) + static_cast<int64_t>(blk) * S.ldc;
+  // Every load below is issued without a branch: a chunk past the row (the
+  // row stride ldc is a multiple of 64, so only lanes past ldc) reads the
+  // row's last chunk, a row past the tile reads the tile's first row, and
+  // their contributions are zeroed by selects (entries of d past n, the dot
+  // products of such rows).  A load behind a branch makes the compiler wait
+  // for every load in flight where the paths join.
+  int64_t jc[CPL];
   float dv[CPL][4], acc[CPL][4];
 #pragma unroll
   for (int c = 0; c < CPL; ++c) {
     const int64_t j = static_cast<int64_t>(lane + 64 * c) * 4;
+    jc[c] = j < S.ldc ? j : S.ldc - 4;
+    const g_f32x4 v = *gptr4(d + jc[c]);
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
-      dv[c][e] = j + e < S.n ? d[j + e] : 0.f;
+      dv[c][e] = j + e < S.n ? v[e] : 0.f;
       acc[c][e] = 0.f;
     }
   }
   for (int r = wv; r < nrows; r += 4 * RF) {
-    float4 row[RF][CPL];
+    g_f32x4 row[RF][CPL];
 #pragma unroll
-    for (int q = 0; q < RF; ++q)
+    for (int q = 0; q < RF; ++q) {
+      const int64_t rr = row0 + (r + 4 * q < nrows ? r + 4 * q : 0);
 #pragma unroll
-      for (int c = 0; c < CPL; ++c) {
-        const int64_t j = static_cast<int64_t>(lane + 64 * c) * 4;
-        // C is zero from n to ldc (a multiple of 64), so a chunk that starts
-        // before n stays inside the row.
-        row[q][c] = (r + 4 * q < nrows && j < S.n) ? ld4_nt(C + (row0 + r + 4 * q) * S.ldc + j)
-                                                    : make_float4(0.f, 0.f, 0.f, 0.f);
-      }
+      for (int c = 0; c < CPL; ++c) row[q][c] = __builtin_nontemporal_load(gptr4(C + rr * S.ldc + jc[c]));
+    }
 #pragma unroll
     for (int q = 0; q < RF; ++q) {
       float s = 0.f;
 #pragma unroll
       for (int c = 0; c < CPL; ++c)
-        s += (row[q][c].x * dv[c][0] + row[q][c].y * dv[c][1]) +
-             (row[q][c].z * dv[c][2] + row[q][c].w * dv[c][3]);
+        s += (row[q][c][0] * dv[c][0] + row[q][c][1] * dv[c][1]) +
+             (row[q][c][2] * dv[c][2] + row[q][c][3] * dv[c][3]);
       s = wave_sum_dpp(s);
+      s = r + 4 * q < nrows ? s : 0.f;
 #pragma unroll
-      for (int c = 0; c < CPL; ++c) {
-        acc[c][0] = fmaf(s, row[q][c].x, acc[c][0]);
-        acc[c][1] = fmaf(s, row[q][c].y, acc[c][1]);
-        acc[c][2] = fmaf(s, row[q][c].z, acc[c][2]);
-        acc[c][3] = fmaf(s, row[q][c].w, acc[c][3]);
-      }
+      for (int c = 0; c < CPL; ++c)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) acc[c][e] = fmaf(s, row[q][c][e], acc[c][e]);
     }
   }
 #pragma unroll
@@ -228,10 +239,10 @@ __device__ inline void batch_tile_pass(const BatchSys& S, int t, float (&red)[4]
 
 // One single-pass item: tile t of system S, its partial row written, with
 // INFLIGHT 16-byte loads per lane in flight (16 measured best, also in the
-// mixed kernel: 8 lowered its registers but took 342 against 326 us per update
-// of the 8192^2 k = 64 system with the 256 systems).
+// mixed kernel: 8 took 342 against 333 us per update of the 8192^2 k = 64
+// system with the 256 systems).
 template <int INFLIGHT = 16>
-__device__ inline void fused_item(const BatchSys& S, int t, float (&red)[4][kBatchFusedCols]) {
+__device__ __attribute__((always_inline)) inline void fused_item(const BatchSys& S, int t, float (&red)[4][kBatchFusedCols]) {
   if (S.ldc <= 256) batch_tile_pass<1, INFLIGHT>(S, t, red);
   else if (S.ldc <= 512) batch_tile_pass<2, INFLIGHT>(S, t, red);
   else batch_tile_pass<4, INFLIGHT>(S, t, red);
@@ -259,7 +270,7 @@ __global__ __launch_bounds__(256) void k_batch_fused(const BatchSys* sys, const 
 // sum of block i's partial rows), x_bar <- (eta/m) sum_i x_i + (1 - eta) x_bar,
 // d_i = x_bar - x_i.  A block's partial rows are loaded four at a time, with
 // its x_i, before they are added.
-__device__ inline void combine_item(const BatchSys& S, int col, double (&part)[8][32],
+__device__ __attribute__((always_inline)) inline void combine_item(const BatchSys& S, int col, double (&part)[8][32],
                                     double (&xb)[32]) {
   const int lane = threadIdx.x & 31;
   const int bl = threadIdx.x >> 5;
@@ -366,7 +377,8 @@ __global__ void k_batch_check(const BatchSys* sys, int32_t count, const int32_t*
 // and combine of the batch kernels above; the elementwise epilogues).  The
 // item kinds share one LDS buffer.  Registers are capped for two workgroups
 // per CU (one otherwise: 326 against 338 us per update for the 8192^2 k = 64
-// system with the 256 systems; four steps of prefetch took 345).
+// system with the 256 systems; four steps of prefetch took 345; the k = 1
+// tile as a called function instead of inlined, 395).
 template <int NCT>
 __global__ __launch_bounds__(256, 2) void k_batch_mixed(const BatchSys* sys, const BatchGemm* gemm,
                                                      const int4* items, int32_t nitems,
