@@ -545,17 +545,24 @@ def secondary(apc, synth, dev):
     plan = apc.Plan(A, b, S.off, "f64")
     plan.iterate(50)
     tot = plain_updates_ms(plan, 2000)
+    plan.iterate(2000)
     err = float(torch.linalg.norm(plan.xbar() - torch.from_numpy(S.xstar).to(dev))) / float(
         np.linalg.norm(S.xstar))
-    _, pa, pb, pv = plan.iterate_timed(2000)
+    # The same updates launched one kernel pair per update (iterate_timed always takes
+    # that path), for comparison with the single launch of all T updates above.
+    tt, pa, pb, pv = plan.iterate_timed(2000)
     single = plan.single_pass_shape()
     kern = ({"single_pass_us": round(pa * 1e3 / 2000, 2), "combine_us": round(pv * 1e3 / 2000, 2),
              "single_pass_shape": single} if single is not None else
             {"pass_a_us": round(pa * 1e3 / 2000, 2), "pass_b_us": round(pb * 1e3 / 2000, 2),
              "average_us": round(pv * 1e3 / 2000, 2)})
+    kern["per_update_launches_us_per_update"] = round(tt * 1e3 / 2000, 2)
+    resident = plan.resident_shape()
     out["square512_fp64"] = dict({"workload": "N=n=512, A, x* iid N(0,1), m=8 blocks of 64, FP64",
                                   "updates": 2000, "us_per_update": round(tot * 1e3 / 2000, 2),
-                                  "err_after_2050": err, "params": plan.params()}, **kern)
+                                  "path": ("one launch for all updates, factor held in registers "
+                                           f"({resident})" if resident else "launches per update"),
+                                  "err_after_4050": err, "params": plan.params()}, **kern)
     plan.close()
     del A, b, S
     # Batched: N = n = 8192, A = G/sqrt(n) + 2I, k = 64, 64 blocks of uneven size.

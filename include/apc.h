@@ -114,8 +114,17 @@ apc_status apc_setup(apc_plan* out, const double* A, int64_t lda, const double* 
                      int32_t precision, double gamma, double eta, void* workspace,
                      size_t ws_bytes, void* stream);
 
-/* Apply T updates of eq. (2a)-(2b) (T >= 0).  Asynchronous: per update it
- * enqueues, k = 1 with n <= 16384 (FP32) or 8192 (FP64): one pass over the
+/* Apply T updates of eq. (2a)-(2b) (T >= 0).  Asynchronous.  k = 1 FP64 with
+ * every block of at most 64 rows and n <= 1024 (32 rows when n > 512), and m
+ * no larger than the device's CU count (unless APC_RESIDENT=0 in the
+ * environment at setup): ONE launch for all T updates, in which workgroup i
+ * holds block i's rows of the factor in registers, and the m workgroups meet
+ * at a device-wide barrier once per update to form x_bar (the updates of
+ * eq. (2a)-(2b) unchanged; only sums are ordered differently from the
+ * per-update kernels).  Its wait is bounded: if the device cannot hold all m
+ * workgroups at once for seconds, the launch stops, x_bar becomes NaN and the
+ * next apc_residual (and so apc_solve) returns APC_EHIP.  Otherwise per update
+ * it enqueues, k = 1 with n <= 16384 (FP32) or 8192 (FP64): one pass over the
  * factor that forms w_i = Q_i^T (x_bar - x_i) row by row and adds each row's
  * share of Q_i w_i while the row is in registers, then one launch for
  * x_i += gamma (x_bar - x_i - Q_i w_i), the momentum average
@@ -232,8 +241,11 @@ apc_status apc_get_setup(apc_plan p, int32_t* qr_passes, double* qr_defect);
  * APC_TN_TUNE=0 / APC_TN_RT / APC_TN_SPLIT).  Shapes are timed once per
  * problem shape and process.  which = 4: the single-pass k = 1 update, rows
  * per workgroup and rows per register group (in *splits), *tuned_us = 0.
+ * which = 5: the single-launch k = 1 update of apc_iterate, the block rows and
+ * columns one workgroup holds (in *splits), *tuned_us = 0.
  * Host pointers, any may be NULL.  APC_EUNSUPPORTED for which 0..3 on a k = 1
- * FP64/FP32 plan and for which = 4 on a plan that updates in two passes. */
+ * FP64/FP32 plan, for which = 4 on a plan that updates in two passes and for
+ * which = 5 on a plan without the single-launch update. */
 apc_status apc_get_launch(apc_plan p, int32_t which, int32_t* rows_per_wg, int32_t* splits,
                           float* tuned_us);
 

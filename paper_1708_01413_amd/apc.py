@@ -458,6 +458,17 @@ class Plan:
         _check(st)
         return {"rows_per_wg": rows.value, "rows_per_group": g.value}
 
+    def resident_shape(self):
+        """Block rows and columns one workgroup holds in the single-launch k = 1 update
+        (T updates in one launch), or None when the plan launches per update."""
+        rows, cols, us = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_float()
+        st = lib.apc_get_launch(self.handle, 5, ctypes.byref(rows), ctypes.byref(cols),
+                                ctypes.byref(us))
+        if st == APC_EUNSUPPORTED:
+            return None
+        _check(st)
+        return {"rows_per_wg": rows.value, "cols_per_wg": cols.value}
+
     @property
     def iterations(self) -> int:
         return apc_iterations(self.handle)

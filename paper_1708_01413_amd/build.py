@@ -18,7 +18,7 @@ LIB = os.path.join(HERE, "libapc.so")
 OBJDIR = os.path.join(ROOT, "_build")
 SOURCES = [os.path.join(CSRC, "apc_kernels.hip"), os.path.join(CSRC, "apc_gemm.hip"),
            os.path.join(CSRC, "apc_batch.hip"), os.path.join(CSRC, "apc_noalloc.hip"),
-           os.path.join(CSRC, "apc_host.cpp")]
+           os.path.join(CSRC, "apc_resident.hip"), os.path.join(CSRC, "apc_host.cpp")]
 
 HIPCC_FLAGS = [
     "-O3", "-std=c++17", "-fPIC",

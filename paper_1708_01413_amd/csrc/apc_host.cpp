@@ -73,6 +73,7 @@ struct Layout {
   size_t Cq, CqT, C64T, Apad, yq, Wq, tnpart, x0, ys, c64p, Xs, Rb, cw, Linv2, ssq;
   size_t C64p, yref, uref, W64;  // FP64 anchor of the FP32 / bf16 k-RHS iteration
   size_t C64a, C64b, C32, x, xbar, dv, w, ca, cb, Y, vtmp, V, h, alpha, beta, G, Linv, flags, scal, partial, tiles_a, tiles_g, tiles_t, doff, goff, total;
+  size_t xch, rsync;  // single-launch k = 1 path: exchange buffer, epoch and time-out words
 };
 
 struct Tiles {
@@ -158,6 +159,18 @@ int32_t padded_rhs(int32_t k, int32_t prec) {
   if (k <= 32) return 32;
   if (k <= 64) return 64;
   return static_cast<int32_t>(round_up(k, 128));
+}
+
+// k = 1 FP64 plans whose blocks fit one workgroup's registers can run T
+// updates in one launch (k_resident); the workspace then holds its exchange
+// buffer.  Whether a plan uses it also depends on the device (m workgroups
+// resident at once), which the workspace size does not.
+bool resident_candidate(const int64_t* off, int32_t m, int64_t ldc, int32_t k, int32_t flags,
+                        int* rpw, int* cpl) {
+  if (k != 1 || uses_gemm(k, flags) || base_precision(flags) != APC_F64) return false;
+  int64_t pmax = 0;
+  for (int i = 0; i < m; ++i) pmax = std::max(pmax, off[i + 1] - off[i]);
+  return resident_shape(pmax, ldc, rpw, cpl);
 }
 
 Layout make_layout(int64_t N, int64_t n, const int64_t* off, int32_t m, int32_t k, int32_t flags,
@@ -252,6 +265,12 @@ Layout make_layout(int64_t N, int64_t n, const int64_t* off, int32_t m, int32_t 
   L.tiles_t = take(3 * static_cast<int64_t>(L.ntiles_t) * 4);
   L.doff = take((m + 1) * 8);
   L.goff = take(m * 8);
+  {
+    int rpw = 0, cpl = 0;
+    const bool res = resident_candidate(off, m, L.ldc, k, flags, &rpw, &cpl);
+    L.xch = take(res ? 2 * m * L.ldc * 16 : 0);  // two tagged 64-bit words per double
+    L.rsync = take(4 * 4);
+  }
   L.total = cur;
   return L;
 }
@@ -399,6 +418,9 @@ struct apc_plan_s {
   bool fused = false;                  // k = 1: both halves of eq. (2a) in one pass over C
   int32_t fused_rows = 0, fused_g = 0, ntiles_f = 0;
   int32_t fused_tpb = 0;               // > 0: every block has this many single-pass tiles
+  bool resident = false;               // k = 1 FP64: T updates in one launch (k_resident)
+  int32_t res_rpw = 0, res_cpl = 0, res_stride = 1;
+  uint32_t res_spin = 1u << 22;        // polls of one exchanged word before it gives up
   int32_t qr_passes = 2;               // CholeskyQR passes setup took (1: see setup_impl)
   double qr_defect = NAN;              // estimated ||Q_i^T Q_i - I|| after the first pass
   double* pinned = nullptr;            // pinned host staging (Lanczos coefficients, setup readbacks)
@@ -893,6 +915,23 @@ apc_status update(apc_plan_s* P, hipEvent_t* ev, int* kinds, int* nev) {
   return APC_OK;
 }
 
+// T updates: one k_resident launch when the plan has that path, else T
+// updates of the kernels above.
+apc_status advance(apc_plan_s* P, int32_t T) {
+  if (T <= 0) return APC_OK;
+  if (P->resident) {
+    const int64_t ld = P->state_ld();
+    ResidentArgs a{P->C64(), P->L.ldc, static_cast<int32_t>(P->n), P->doff(), P->m, P->x(), ld,
+                   P->xbar(), P->at<double>(P->L.dv), ld, P->gamma, P->eta / P->m,
+                   1.0 - P->eta, T, P->at<uint64_t>(P->L.xch), P->at<uint32_t>(P->L.rsync),
+                   P->res_stride, P->res_spin};
+    HIP_TRY(launch_resident_f64(a, P->res_rpw, P->res_cpl, P->stream));
+    return APC_OK;
+  }
+  for (int32_t t = 0; t < T; ++t) ST_TRY(update(P, nullptr, nullptr, nullptr));
+  return APC_OK;
+}
+
 int launches_per_update(const apc_plan_s* P) {
   if (P->gemm) return 4;
   if (P->fused) return 2;
@@ -1245,6 +1284,9 @@ apc_status setup_impl(apc_plan_s* P, const Tiles& T) {
   HIP_TRY(hipMemcpyAsync(P->doff(), P->off.data(), (m + 1) * 8, hipMemcpyHostToDevice, st));
   HIP_TRY(hipMemcpyAsync(P->at<int64_t>(L.goff), T.goff.data(), m * 8, hipMemcpyHostToDevice, st));
   HIP_TRY(launch_fill_u32(P->at<unsigned>(L.flags), 4, 0u, st));
+  HIP_TRY(launch_fill_u32(P->at<unsigned>(L.rsync), 4, 0u, st));
+  if (P->resident)
+    HIP_TRY(launch_fill_u32(P->at<unsigned>(L.xch), 8 * P->m * L.ldc, 0u, st));
 
   // ||b||^2 for the residual monitor.
   ST_TRY(residual_norm2(P, nullptr, P->at<double>(L.scal) + 1));
@@ -1525,6 +1567,26 @@ apc_status apc_setup(apc_plan* out, const double* A, int64_t lda, const double* 
     for (int i = 0; i < m; ++i) same = same && T.f_first[i + 1] - T.f_first[i] == t0;
     if (same && (t0 == 1 || t0 == 2 || t0 == 4 || t0 == 8)) P->fused_tpb = t0;
   }
+  {
+    // One launch for T updates when every block fits one workgroup and the
+    // device holds all m workgroups at once (one per CU).
+    int rpw = 0, cpl = 0, cus = 0;
+    HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    bool res = resident_candidate(off, m, L.ldc, k, precision, &rpw, &cpl) && m <= cus;
+    if (const char* e = std::getenv("APC_RESIDENT")) res = res && std::atoi(e) != 0;
+    P->resident = res;
+    P->res_rpw = rpw;
+    P->res_cpl = cpl;
+    // Stride 8 launches 8 workgroups per block and keeps every eighth, which
+    // the dispatcher deals to one XCD; all m must then fit that XCD's CUs.
+    if (const char* e = std::getenv("APC_RESIDENT_STRIDE")) {
+      const int s = std::atoi(e);
+      if (s == 1 || (s == kXcds && m <= cus / kXcds)) P->res_stride = s;
+    }
+    // Failure-path tests shorten the bounded wait from the host.
+    if (const char* e = std::getenv("APC_RESIDENT_SPIN"))
+      P->res_spin = static_cast<uint32_t>(std::strtoul(e, nullptr, 10));
+  }
   P->tile_start.assign(1, 0);
   for (int i = 0; i < m; ++i)
     P->tile_start.push_back(P->tile_start.back() +
@@ -1572,7 +1634,7 @@ apc_status apc_iterate(apc_plan p, int32_t T) {
   if (!p) return fail(APC_EINVAL, "plan is NULL");
   if (T < 0) return fail(APC_EINVAL, "T must be >= 0");
   if (T > 0) ST_TRY(resume_refinement(p));
-  for (int32_t t = 0; t < T; ++t) ST_TRY(update(p, nullptr, nullptr, nullptr));
+  ST_TRY(advance(p, T));
   p->iters += T;
   return APC_OK;
 }
@@ -1593,8 +1655,7 @@ apc_status apc_iterate_graph(apc_plan p, int32_t T) {
     const int64_t since = p->since_start;
     hipGraph_t g = nullptr;
     HIP_TRY(hipStreamBeginCapture(p->stream, hipStreamCaptureModeThreadLocal));
-    apc_status st = APC_OK;
-    for (int32_t t = 0; t < T && st == APC_OK; ++t) st = update(p, nullptr, nullptr, nullptr);
+    const apc_status st = advance(p, T);
     const hipError_t e = hipStreamEndCapture(p->stream, &g);
     p->since_start = since;
     if (st != APC_OK) {
@@ -1665,9 +1726,16 @@ apc_status apc_residual(apc_plan p, double* relres) {
   ST_TRY(current_solution(p, &x));
   ST_TRY(residual_norm2(p, x, dst));
   double r2 = 0;
+  uint32_t timed_out = 0;
   HIP_TRY(hipMemcpyAsync(&r2, dst, sizeof r2, hipMemcpyDeviceToHost, p->stream));
+  if (p->resident)
+    HIP_TRY(hipMemcpyAsync(&timed_out, p->at<uint32_t>(p->L.rsync) + 2, sizeof timed_out,
+                           hipMemcpyDeviceToHost, p->stream));
   HIP_TRY(hipStreamSynchronize(p->stream));
   *relres = p->bnorm > 0 ? std::sqrt(r2) / p->bnorm : std::sqrt(r2);
+  if (timed_out)
+    return fail(APC_EHIP, "the single-launch update gave up waiting for its %d workgroups "
+                "(the device did not hold them all at once); x_bar is NaN", p->m);
   return APC_OK;
 }
 
@@ -1913,8 +1981,15 @@ apc_status apc_get_launch(apc_plan p, int32_t which, int32_t* rows_per_wg, int32
     if (tuned_us) *tuned_us = 0.f;
     return APC_OK;
   }
+  if (which == 5) {
+    if (!p->resident) return fail(APC_EUNSUPPORTED, "the plan does not use the single-launch update");
+    if (rows_per_wg) *rows_per_wg = 8 * p->res_rpw;
+    if (splits) *splits = 128 * p->res_cpl;
+    if (tuned_us) *tuned_us = 0.f;
+    return APC_OK;
+  }
+  if (which < 0 || which > 3) return fail(APC_EINVAL, "which must be 0..5");
   if (!p->gemm) return fail(APC_EUNSUPPORTED, "launch shapes are reported for the k-RHS path only");
-  if (which < 0 || which > 3) return fail(APC_EINVAL, "which must be 0..4");
   const TnChoice& c = which == 0 ? p->tnA : which == 1 ? p->tnB : which == 2 ? p->tnX0 : p->tnR;
   if (rows_per_wg) *rows_per_wg = 64 * c.rt;
   if (splits) *splits = c.nsplit;

@@ -262,6 +262,37 @@ struct FusedCombineArgs {
 hipError_t launch_fused_combine_f32(const FusedCombineArgs<float>& a, hipStream_t s);
 hipError_t launch_fused_combine_f64(const FusedCombineArgs<double>& a, hipStream_t s);
 
+// T updates of eq. (2a)-(2b) for k = 1 in ONE launch (FP64, small blocks): one
+// workgroup per block keeps its rows of C in registers for the whole launch,
+// and the m workgroups exchange their x_i once per update through tagged
+// words to form x_bar.  The state (x, x_bar, d) is read at the start and written at the end
+// in the layout the two-kernel update uses, so the two paths interleave.
+// Needs every block to fit one workgroup's registers (resident_shape) and all
+// m workgroups resident at once (m at most the device's CU count).
+struct ResidentArgs {
+  const double* C;
+  int64_t ldc;
+  int32_t n;
+  const int64_t* off;         // m + 1 row offsets of the blocks in C
+  int32_t m;
+  double* x;                  // x_i at x + i*ldx
+  int64_t ldx;
+  double* xbar;
+  double* d;                  // d_i = x_bar - x_i at d + i*ldd
+  int64_t ldd;
+  double gamma, alpha, beta;  // x_bar <- alpha sum_i x_i + beta x_bar
+  int32_t T;
+  uint64_t* xch;              // 2 parities x m x ldc x 2 tagged words (zero at setup)
+  uint32_t* sync;             // [1] epoch base, [2] a poll timed out (zero at setup)
+  int32_t stride;             // launched workgroups per block (the others exit at once)
+  uint32_t spin_limit;        // polls of one exchanged word before the launch gives up
+};
+constexpr int kResidentThreads = 512;
+// Register shape (rows per wave, 16-byte chunks per lane and row) for blocks
+// of at most max_rows rows and a row stride of ldc doubles; false if none.
+bool resident_shape(int64_t max_rows, int64_t ldc, int* rpw, int* cpl);
+hipError_t launch_resident_f64(const ResidentArgs& a, int rpw, int cpl, hipStream_t s);
+
 // ---------------------------------------------------------------------------
 // k right-hand sides: streaming contractions on the matrix cores (apc_gemm.hip)
 // ---------------------------------------------------------------------------

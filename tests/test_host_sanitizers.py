@@ -33,7 +33,8 @@ def _run(cmd):
 
 @pytest.mark.skipif(not os.path.exists(HIPCC), reason="hipcc not available")
 def test_host_layer_under_asan_and_ubsan(tmp_path):
-    kernels = ["apc_kernels.hip", "apc_gemm.hip", "apc_batch.hip", "apc_noalloc.hip"]
+    kernels = ["apc_kernels.hip", "apc_gemm.hip", "apc_batch.hip", "apc_noalloc.hip",
+               "apc_resident.hip"]
     jobs = [[HIPCC, *COMMON, "-c", os.path.join(CSRC, k), "-o", str(tmp_path / (k + ".o"))]
             for k in kernels]
     jobs.append([HIPCC, *COMMON, *SAN, "-c", os.path.join(CSRC, "apc_host.cpp"),
