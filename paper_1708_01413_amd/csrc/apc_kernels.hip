@@ -1206,85 +1206,141 @@ __global__ void k_copy_t(const double* src, int64_t lds, double* dst, int64_t ld
 // One Lanczos step after the operator: twice classical Gram-Schmidt of w
 // against the basis rows V[0..j], then beta_j = ||w||, V[j + 1] = w / beta_j,
 // in four launches over column slabs of kLzSlab = 64 columns, one workgroup
-// of four waves per slab.  Lane l of every wave owns the slab's column l; the
-// waves split the rows (or the partial-row tiles) r = wv, wv + 4, ...  Every
-// step local to a column -- the operator's sum over partial rows, w -=
-// sum_r h_r V[r], the scaling -- runs in the slab that owns it; only the dot
-// products and the norm cross slabs, as per-slab partials that every
+// of kLzWaves waves per slab.  Lane l of every wave owns the slab's column l;
+// the waves split the rows (or the partial-row tiles) r = wv, wv + 8, ...
+// Every step local to a column -- the operator's sum over partial rows,
+// w -= sum_r h_r V[r], the scaling -- runs in the slab that owns it; only the
+// dot products and the norm cross slabs, as per-slab partials that every
 // workgroup of the next launch sums in slab order (so nothing depends on
-// scheduling).  All lanes take part in every wave sum; columns past ldc
+// scheduling).  Rows go eight per wave at a time: their loads are issued
+// together and their eight wave sums reduced at once (row_sums), so a step
+// costs a few memory round trips instead of one per row.  Columns past ldc
 // contribute zero.
+constexpr int kLzWaves = 8;
+constexpr int kLzRows = 8 * kLzWaves;  // basis rows one pass over the workgroup covers
 
-// hp[blockIdx.x * hstride + r] = sum over the slab's columns of V[r][c] x,
-// r <= j; wave wv takes rows r = wv (mod 4).
+// hp[blockIdx.x * hstride + r] = sum over the slab's columns of V[r][c] x, r <= j.
 __device__ inline void lz_dots(const LanczosArgs& a, int64_t c, bool ok, double x, double* hp) {
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  for (int r = wv; r <= a.j; r += 4) {
-    const double v = ok ? a.V[static_cast<int64_t>(r) * a.ldc + c] : 0.0;
-    const double t = wave_sum_dpp(v * x);
-    if (lane == 0) hp[static_cast<int64_t>(blockIdx.x) * a.hstride + r] = t;
+  const int64_t cc = ok ? c : 0;
+  for (int r0 = 0; r0 <= a.j; r0 += kLzRows) {
+    double p[8], t[8];
+    // Clamped addresses and a select after the load keep the eight loads
+    // free of branches, so they are all in flight at once.
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const int r = r0 + wv + kLzWaves * k;
+      p[k] = a.V[static_cast<int64_t>(r <= a.j ? r : a.j) * a.ldc + cc];
+    }
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const int r = r0 + wv + kLzWaves * k;
+      p[k] = ok && r <= a.j ? p[k] * x : 0.0;
+    }
+    row_sums<8>(p, t, lane);
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const int r = r0 + wv + kLzWaves * k;
+      if (lane == k && r <= a.j) hp[static_cast<int64_t>(blockIdx.x) * a.hstride + r] = t[k];
+    }
   }
 }
 
-// hs[r] = sum over the slabs of hp[s * hstride + r], r <= j: wave wv takes
-// rows r = wv (mod 4), lane l the slabs s = l (mod 64), then a wave sum.
+// hs[r] = sum over the slabs of hp[s * hstride + r], r <= j: lane l takes the
+// slabs s = l (mod 64) of eight rows at a time, then one row_sums.
 __device__ inline void lz_gather(const LanczosArgs& a, const double* hp, double* hs) {
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  for (int r = wv; r <= a.j; r += 4) {
-    double t = 0.0;
-    for (int sl = lane; sl < a.nslab; sl += 64) t += hp[static_cast<int64_t>(sl) * a.hstride + r];
-    t = wave_sum_dpp(t);
-    if (lane == 0) hs[r] = t;
+  for (int r0 = 0; r0 <= a.j; r0 += kLzRows) {
+    double p[8], t[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) p[k] = 0.0;
+    for (int sl = lane; sl < a.nslab; sl += 64) {
+      double v[8];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        const int r = r0 + wv + kLzWaves * k;
+        v[k] = hp[static_cast<int64_t>(sl) * a.hstride + (r <= a.j ? r : a.j)];
+      }
+#pragma unroll
+      for (int k = 0; k < 8; ++k) p[k] += r0 + wv + kLzWaves * k <= a.j ? v[k] : 0.0;
+    }
+    row_sums<8>(p, t, lane);
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const int r = r0 + wv + kLzWaves * k;
+      if (lane == k && r <= a.j) hs[r] = t[k];
+    }
   }
   __syncthreads();
 }
 
-// w - sum_{r <= j} hs[r] V[r][c]: each wave sums its rows, the four partial
-// sums meet in LDS (acc, 4 x 64).  Returns the new w of the lane's column in
-// every wave.
+__device__ inline double lz_tree(const double (*acc)[64], int lane) {
+  return ((acc[0][lane] + acc[1][lane]) + (acc[2][lane] + acc[3][lane])) +
+         ((acc[4][lane] + acc[5][lane]) + (acc[6][lane] + acc[7][lane]));
+}
+
+// w - sum_{r <= j} hs[r] V[r][c]: each wave sums its rows (eight loads in
+// flight), the eight partial sums meet in LDS (acc, 8 x 64).  Returns the new
+// w of the lane's column in every wave.
 __device__ inline double lz_subtract(const LanczosArgs& a, int64_t c, bool ok, double w,
                                      const double* hs, double (*acc)[64]) {
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  double s0 = 0.0, s1 = 0.0;
-  if (ok) {
-    int r = wv;
-    for (; r + 4 <= a.j; r += 8) {
-      s0 = fma(hs[r], a.V[static_cast<int64_t>(r) * a.ldc + c], s0);
-      s1 = fma(hs[r + 4], a.V[static_cast<int64_t>(r + 4) * a.ldc + c], s1);
+  const int64_t cc = ok ? c : 0;
+  double s = 0.0;
+  for (int r0 = 0; r0 <= a.j; r0 += kLzRows) {
+    double v[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const int r = r0 + wv + kLzWaves * k;
+      v[k] = a.V[static_cast<int64_t>(r <= a.j ? r : a.j) * a.ldc + cc];
     }
-    if (r <= a.j) s0 = fma(hs[r], a.V[static_cast<int64_t>(r) * a.ldc + c], s0);
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const int r = r0 + wv + kLzWaves * k;
+      const int rc = r <= a.j ? r : a.j;
+      s = fma(r <= a.j ? hs[rc] : 0.0, ok ? v[k] : 0.0, s);
+    }
   }
-  acc[wv][lane] = s0 + s1;
+  acc[wv][lane] = s;
   __syncthreads();
-  return w - ((acc[0][lane] + acc[1][lane]) + (acc[2][lane] + acc[3][lane]));
+  return w - lz_tree(acc, lane);
 }
 
 // Launch 1: w (the operator's output, or first its sum scale * sum_t part[t]
 // over the single pass's partial rows, in FP64: wave wv takes tiles t = wv
-// (mod 4)) and the first Gram-Schmidt pass's dot partials.
+// (mod 8), sixteen loads in flight) and the first Gram-Schmidt pass's dot
+// partials.
 template <typename TP>
-__global__ __launch_bounds__(256) void k_lz_first(LanczosArgs a, const TP* part, int64_t ldp,
-                                                  int32_t ntiles, double scale) {
-  __shared__ double acc[4][64];
+__global__ __launch_bounds__(64 * kLzWaves) void k_lz_first(LanczosArgs a, const TP* part,
+                                                            int64_t ldp, int32_t ntiles,
+                                                            double scale) {
+  __shared__ double acc[kLzWaves][64];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int64_t c = static_cast<int64_t>(blockIdx.x) * kLzSlab + lane;
   const bool ok = c < a.ldc;
   double w = 0.0;
   if (part) {
-    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-    if (ok) {
-      int t = wv;
-      for (; t + 12 < ntiles; t += 16) {
-        s0 += static_cast<double>(part[static_cast<int64_t>(t) * ldp + c]);
-        s1 += static_cast<double>(part[static_cast<int64_t>(t + 4) * ldp + c]);
-        s2 += static_cast<double>(part[static_cast<int64_t>(t + 8) * ldp + c]);
-        s3 += static_cast<double>(part[static_cast<int64_t>(t + 12) * ldp + c]);
+    double s = 0.0;
+    const int64_t cc = ok ? c : 0;
+    if (ntiles > 0) {
+      for (int t0 = wv; t0 < ntiles; t0 += 16 * kLzWaves) {
+        double v[16];
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+          const int t = t0 + kLzWaves * q;
+          v[q] = static_cast<double>(part[static_cast<int64_t>(t < ntiles ? t : ntiles - 1) * ldp + cc]);
+        }
+#pragma unroll
+        for (int q = 0; q < 16; ++q) v[q] = ok && t0 + kLzWaves * q < ntiles ? v[q] : 0.0;
+        double u[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) u[q] = (v[4 * q] + v[4 * q + 1]) + (v[4 * q + 2] + v[4 * q + 3]);
+        s += (u[0] + u[1]) + (u[2] + u[3]);
       }
-      for (; t < ntiles; t += 4) s0 += static_cast<double>(part[static_cast<int64_t>(t) * ldp + c]);
     }
-    acc[wv][lane] = (s0 + s1) + (s2 + s3);
+    acc[wv][lane] = s;
     __syncthreads();
-    w = scale * ((acc[0][lane] + acc[1][lane]) + (acc[2][lane] + acc[3][lane]));
+    w = scale * lz_tree(acc, lane);
     if (ok && wv == 0) a.w[c] = w;
   } else if (ok) {
     w = a.w[c];
@@ -1293,9 +1349,9 @@ __global__ __launch_bounds__(256) void k_lz_first(LanczosArgs a, const TP* part,
 }
 
 // Launch 2: w -= V^T h (first pass), then the second pass's dot partials.
-__global__ __launch_bounds__(256) void k_lz_second(LanczosArgs a) {
+__global__ __launch_bounds__(64 * kLzWaves) void k_lz_second(LanczosArgs a) {
   __shared__ double hs[kLzMaxRows];
-  __shared__ double acc[4][64];
+  __shared__ double acc[kLzWaves][64];
   lz_gather(a, a.hp, hs);
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int64_t c = static_cast<int64_t>(blockIdx.x) * kLzSlab + lane;
@@ -1307,9 +1363,9 @@ __global__ __launch_bounds__(256) void k_lz_second(LanczosArgs a) {
 }
 
 // Launch 3: w -= V^T h (second pass) and the slab's part of ||w||^2.
-__global__ __launch_bounds__(256) void k_lz_third(LanczosArgs a) {
+__global__ __launch_bounds__(64 * kLzWaves) void k_lz_third(LanczosArgs a) {
   __shared__ double hs[kLzMaxRows];
-  __shared__ double acc[4][64];
+  __shared__ double acc[kLzWaves][64];
   lz_gather(a, a.hp + static_cast<int64_t>(a.nslab) * a.hstride, hs);
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int64_t c = static_cast<int64_t>(blockIdx.x) * kLzSlab + lane;
@@ -1763,7 +1819,7 @@ hipError_t launch_lanczos_step(const LanczosArgs& a, const void* part, bool part
                                int32_t ntiles, double scale, hipStream_t s) {
   if (a.j < 0 || a.j >= kLzMaxRows || a.nslab != (a.ldc + kLzSlab - 1) / kLzSlab)
     return hipErrorInvalidValue;
-  const dim3 grid(static_cast<unsigned>(a.nslab)), block(256);
+  const dim3 grid(static_cast<unsigned>(a.nslab)), block(64 * kLzWaves);
   if (part && part32)
     hipLaunchKernelGGL(k_lz_first<float>, grid, block, 0, s, a, static_cast<const float*>(part),
                        ldp, ntiles, scale);

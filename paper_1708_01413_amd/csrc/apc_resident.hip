@@ -60,91 +60,6 @@ __device__ inline double untag(uint64_t lo, uint64_t hi) {
   return __longlong_as_double(static_cast<long long>((hi << 32) | (lo & 0xffffffffull)));
 }
 
-// Row sums of R rows at once, each row's partial spread over the 64 lanes of
-// the wave (v[k] in every lane).  Instead of R separate wave sums, the rows are
-// halved between lane halves: v_permlane32_swap pairs lane l with l ^ 32, which
-// keeps rows k < R/2 in the low half and the others in the high half (one swap
-// and one add per pair of rows, no selects); v_permlane16_swap does the same
-// for l ^ 16, and for R = 8 a DPP rotate by 8 within each 16-lane row (with
-// selects) for l ^ 8.  Each lane then holds one row's partial, summed within
-// groups of 8 or 16 lanes by DPP, and the R results are read out with
-// v_readlane.  The order of the additions is fixed, so results are
-// reproducible.
-__device__ inline double swap_add32(double& a, double& b) {
-  const uint64_t ua = static_cast<uint64_t>(__double_as_longlong(a));
-  const uint64_t ub = static_cast<uint64_t>(__double_as_longlong(b));
-  const auto lo = __builtin_amdgcn_permlane32_swap(static_cast<unsigned>(ua), static_cast<unsigned>(ub),
-                                                   false, false);
-  const auto hi = __builtin_amdgcn_permlane32_swap(static_cast<unsigned>(ua >> 32),
-                                                   static_cast<unsigned>(ub >> 32), false, false);
-  const double na = __longlong_as_double(static_cast<long long>(
-      (static_cast<uint64_t>(hi[0]) << 32) | static_cast<uint64_t>(lo[0])));
-  const double nb = __longlong_as_double(static_cast<long long>(
-      (static_cast<uint64_t>(hi[1]) << 32) | static_cast<uint64_t>(lo[1])));
-  return na + nb;
-}
-__device__ inline double swap_add16(double& a, double& b) {
-  const uint64_t ua = static_cast<uint64_t>(__double_as_longlong(a));
-  const uint64_t ub = static_cast<uint64_t>(__double_as_longlong(b));
-  const auto lo = __builtin_amdgcn_permlane16_swap(static_cast<unsigned>(ua), static_cast<unsigned>(ub),
-                                                   false, false);
-  const auto hi = __builtin_amdgcn_permlane16_swap(static_cast<unsigned>(ua >> 32),
-                                                   static_cast<unsigned>(ub >> 32), false, false);
-  const double na = __longlong_as_double(static_cast<long long>(
-      (static_cast<uint64_t>(hi[0]) << 32) | static_cast<uint64_t>(lo[0])));
-  const double nb = __longlong_as_double(static_cast<long long>(
-      (static_cast<uint64_t>(hi[1]) << 32) | static_cast<uint64_t>(lo[1])));
-  return na + nb;
-}
-
-template <int R>
-__device__ inline void row_sums(double (&v)[R], double (&w)[R], int lane) {
-  static_assert(R == 1 || R == 2 || R == 4 || R == 8, "rows per wave");
-  double r;
-  if constexpr (R == 1) {
-    r = v[0];
-  } else {
-    // l ^ 32: the low half keeps rows [0, R/2), the high half [R/2, R).
-    double h[R / 2];
-#pragma unroll
-    for (int k = 0; k < R / 2; ++k) h[k] = swap_add32(v[k], v[k + R / 2]);
-    if constexpr (R == 2) {
-      r = h[0];
-    } else {
-      // l ^ 16 within each half: even rows of 16 lanes keep the lower quarter.
-      double g[R / 4];
-#pragma unroll
-      for (int k = 0; k < R / 4; ++k) g[k] = swap_add16(h[k], h[k + R / 4]);
-      if constexpr (R == 4) {
-        r = g[0];
-      } else {
-        // l ^ 8 (a rotate by 8 within 16 lanes): lanes with bit 3 clear keep g[0].
-        const bool up = (lane & 8) != 0;
-        const double send = up ? g[0] : g[1];
-        const double keep = up ? g[1] : g[0];
-        r = keep + dpp_f64<0x128>(send);
-      }
-    }
-  }
-  // Plain sums within groups of 8 lanes (R = 8) or 16 lanes (R < 8).
-  r += dpp_f64<0xB1>(r);   // quad_perm(1, 0, 3, 2)
-  r += dpp_f64<0x4E>(r);   // quad_perm(2, 3, 0, 1)
-  r += dpp_f64<0x141>(r);  // row_half_mirror
-  if constexpr (R < 8) r += dpp_f64<0x128>(r);  // row_ror:8
-  if constexpr (R == 8) {
-#pragma unroll
-    for (int k = 0; k < 8; ++k) w[k] = lane_f64(r, 8 * k);
-  } else if constexpr (R == 4) {
-#pragma unroll
-    for (int k = 0; k < 4; ++k) w[k] = lane_f64(r, 16 * k);
-  } else if constexpr (R == 2) {
-#pragma unroll
-    for (int k = 0; k < 2; ++k) w[k] = lane_f64(r, 32 * k) + lane_f64(r, 32 * k + 16);
-  } else {
-    w[0] = (lane_f64(r, 0) + lane_f64(r, 16)) + (lane_f64(r, 32) + lane_f64(r, 48));
-  }
-}
-
 // RPW rows per wave (rows wave + 8k of the block), CPL 16-byte chunks per lane
 // and row (chunk lane + 64c, i.e. columns 2(lane + 64c) and the next one).
 // The owner layout for x_i, x_bar and the column sums: thread t owns columns
