@@ -56,26 +56,43 @@ namespace apc {
 
 namespace {
 
-template <typename T, int RT, int NCT, int PF, int NT>
-__global__ __launch_bounds__(256) void k_tn(TnArgs a) {
+template <typename T, int RT, int NCT, int PF, int NT, int W>
+__global__ __launch_bounds__(64 * W) void k_tn(TnArgs a) {
   __shared__ TnStage<NCT> vs;
-  tn_block<T, RT, NCT, PF, NT>(a, blockIdx.x, vs);
+  tn_block<T, RT, NCT, PF, NT, W>(a, blockIdx.x, vs);
 }
 
-template <typename T, int RT, int PF, int NT>
-hipError_t tn_nct(const TnArgs& a, hipStream_t s) {
+template <typename T, int RT, int PF, int NT, int W>
+hipError_t tn_nct_w(const TnArgs& a, hipStream_t s) {
   const int nct = a.kp >= 128 ? 8 : a.kp / 16;
   const int64_t ncg = a.kp / (16 * nct);
-  const int64_t blocks = (a.rows / (64 * RT)) * ncg * a.nsplit;
-  const dim3 grid(static_cast<unsigned>(blocks)), block(256);
+  const int64_t blocks = (a.rows / (16 * W * RT)) * ncg * a.nsplit;
+  const dim3 grid(static_cast<unsigned>(blocks)), block(64 * W);
   switch (nct) {
-    case 1: APC_LAUNCH((k_tn<T, RT, 1, PF, NT>), grid, block, 0, s, a); break;
-    case 2: APC_LAUNCH((k_tn<T, RT, 2, PF, NT>), grid, block, 0, s, a); break;
-    case 4: APC_LAUNCH((k_tn<T, RT, 4, PF, NT>), grid, block, 0, s, a); break;
-    case 8: APC_LAUNCH((k_tn<T, RT, 8, PF, NT>), grid, block, 0, s, a); break;
+    case 1:
+      if constexpr (W == 4) APC_LAUNCH((k_tn<T, RT, 1, PF, NT, W>), grid, block, 0, s, a);
+      else return hipErrorInvalidValue;
+      break;
+    case 2: APC_LAUNCH((k_tn<T, RT, 2, PF, NT, W>), grid, block, 0, s, a); break;
+    case 4: APC_LAUNCH((k_tn<T, RT, 4, PF, NT, W>), grid, block, 0, s, a); break;
+    case 8: APC_LAUNCH((k_tn<T, RT, 8, PF, NT, W>), grid, block, 0, s, a); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
+}
+
+// Eight-wave workgroups (two waves per SIMD where the registers allow) for
+// bf16 / FP32 with one or two row tiles per wave, non-temporal loads and one or
+// two steps of prefetch: twice the rows share each staged step of V.
+template <typename T, int RT, int PF, int NT>
+hipError_t tn_nct(const TnArgs& a, hipStream_t s) {
+  if (a.waves == 8) {
+    if constexpr (sizeof(T) <= 4 && RT <= 2 && PF <= 2 && NT == 1)
+      return tn_nct_w<T, RT, PF, NT, 8>(a, s);
+    else
+      return hipErrorInvalidValue;
+  }
+  return tn_nct_w<T, RT, PF, NT, 4>(a, s);
 }
 
 template <typename T, int PF, int NT>
@@ -255,7 +272,8 @@ unsigned grid_stride_blocks(int64_t total) {
 
 hipError_t launch_tn(int type, int rt, int pf, const TnArgs& a, hipStream_t s) {
   if (a.kp < 16 || (a.kp > 128 && a.kp % 128) || (a.kp <= 128 && (a.kp & (a.kp - 1))) ||
-      a.rows % (64 * rt) || a.nsplit < 1 || a.nsplit > kTnMaxSplit)
+      a.rows % (16 * (a.waves == 8 ? 8 : 4) * rt) || a.nsplit < 1 || a.nsplit > kTnMaxSplit ||
+      (a.waves != 4 && a.waves != 8))
     return hipErrorInvalidValue;
   switch (type) {
     case kTnF64: return tn_pf<double>(rt, pf, a, s);

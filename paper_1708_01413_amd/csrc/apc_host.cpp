@@ -384,6 +384,7 @@ struct TnChoice {
   float us = 0.f;  // measured time per launch when tuned
   int pf = 1;      // steps of the streamed operand loaded ahead
   int nt = 1;      // non-temporal loads of the streamed operand
+  int waves = 4;   // waves per workgroup (rows per workgroup = 16 waves rt)
 };
 
 struct apc_plan_s {
@@ -628,7 +629,7 @@ apc_status orthogonality_defect(apc_plan_s* P, const double* C, double* defect, 
 
 TnArgs tn_args(const void* M, int64_t ldm, int64_t rows, const void* V, int64_t ldv, int32_t kp,
                int64_t K, const TnChoice& ch, int type, void* part, int64_t ldp) {
-  TnArgs a{M, ldm, rows, V, ldv, kp, K, ch.nsplit, 0, part, ldp, ch.nt};
+  TnArgs a{M, ldm, rows, V, ldv, kp, K, ch.nsplit, 0, part, ldp, ch.nt, ch.waves};
   a.klen = round_up((K + ch.nsplit - 1) / ch.nsplit, tn_step_elems(type));
   return a;
 }
@@ -776,7 +777,7 @@ apc_status tn_tune(apc_plan_s* P, int type, TnArgs base, TnChoice* out) {
     }
   };
   const int64_t ncg = base.kp >= 128 ? base.kp / 128 : 1;
-  auto blocks = [&](int rt, int ns) { return (base.rows / (64 * rt)) * ncg * ns; };
+  auto blocks = [&](int rt, int ns, int w = 4) { return (base.rows / (16 * w * rt)) * ncg * ns; };
   const int splits[4] = {1, 2, 4, 8};
   const char* fix_rt = std::getenv("APC_TN_RT");
   const char* fix_ns = std::getenv("APC_TN_SPLIT");
@@ -798,6 +799,10 @@ apc_status tn_tune(apc_plan_s* P, int type, TnArgs base, TnChoice* out) {
     if (c.pf > 2 && (c.rt > 2 || type == kTnF64)) c.pf = 2;
     if (c.pf > 2) c.nt = 1;
     if (const char* e = std::getenv("APC_TN_NT")) c.nt = std::atoi(e) != 0;
+    if (const char* e = std::getenv("APC_TN_WAVES"))
+      if (std::atoi(e) == 8 && type != kTnF64 && c.rt <= 2 && c.pf <= 2 && c.nt &&
+          base.rows % (128 * c.rt) == 0)
+        c.waves = 8;
     *out = c;
     return APC_OK;
   }
@@ -830,6 +835,13 @@ apc_status tn_tune(apc_plan_s* P, int type, TnArgs base, TnChoice* out) {
           c.pf = pf;
           c.nt = nt;
           cand.push_back(c);
+          // The same with eight waves per workgroup.
+          // (Two tiles, two steps ahead and 128 right-hand sides spill there.)
+          if (type != kTnF64 && rt <= 2 && pf <= 2 && nt == 1 && base.rows % (128 * rt) == 0 &&
+              base.kp >= 32 && blocks(rt, ns, 8) >= 32 && !(rt == 2 && pf == 2 && base.kp >= 128)) {
+            c.waves = 8;
+            cand.push_back(c);
+          }
         }
     }
   }
@@ -845,6 +857,7 @@ apc_status tn_tune(apc_plan_s* P, int type, TnArgs base, TnChoice* out) {
       TnArgs a = base;
       a.nsplit = c.nsplit;
       a.nt = c.nt;
+      a.waves = c.waves;
       a.klen = round_up((a.K + c.nsplit - 1) / c.nsplit, tn_step_elems(type));
       hipError_t err = launch_tn(type, c.rt, c.pf, a, P->stream);  // warm-up
       for (int r = 0; err == hipSuccess && r < 1; ++r) {
@@ -1991,7 +2004,7 @@ apc_status apc_get_launch(apc_plan p, int32_t which, int32_t* rows_per_wg, int32
   if (which < 0 || which > 3) return fail(APC_EINVAL, "which must be 0..5");
   if (!p->gemm) return fail(APC_EUNSUPPORTED, "launch shapes are reported for the k-RHS path only");
   const TnChoice& c = which == 0 ? p->tnA : which == 1 ? p->tnB : which == 2 ? p->tnX0 : p->tnR;
-  if (rows_per_wg) *rows_per_wg = 64 * c.rt;
+  if (rows_per_wg) *rows_per_wg = 16 * c.waves * c.rt;
   if (splits) *splits = c.nsplit;
   if (tuned_us) *tuned_us = c.us;
   return APC_OK;
@@ -2333,9 +2346,12 @@ BatchGemm batch_gemm_desc(apc_plan_s* P) {
                     part, L.Np);
   G.tn[3] = tn_args(P->ws + L.C64T, L.Np, L.np, P->ws + L.W64, L.Np, P->kp, L.Np, P->tnX0, kTnF64,
                     part, L.np);
-  for (int q = 0; q < 4; ++q)
+  // The batch kernel runs one 16-row tile per wave in four-wave workgroups.
+  for (int q = 0; q < 4; ++q) {
+    G.tn[q].waves = 4;
     G.tn_blocks[q] = static_cast<int32_t>((G.tn[q].rows / 64) * (P->kp / (16 * std::min(8, P->kp / 16))) *
                                           G.tn[q].nsplit);
+  }
   G.sum_part = part;
   G.sum_nsplit[0] = P->tnA.nsplit;
   G.sum_nsplit[1] = P->tnR.nsplit;

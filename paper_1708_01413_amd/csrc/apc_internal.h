@@ -406,9 +406,11 @@ struct TnArgs {
   void* part;
   int64_t ldp;
   int32_t nt;   // 1: non-temporal loads of M
+  int32_t waves = 4;  // waves per workgroup: 4, or 8 (bf16 / FP32, rt <= 2, nt, pf <= 2)
 };
 // rt: 16-row tiles per wave (1, 2, 4; FP64 1, 2); pf: steps of M loaded ahead
-// (1, 2; 3 and 4 with rt <= 2, non-temporal loads, not FP64).
+// (1, 2; 3 and 4 with rt <= 2, non-temporal loads, not FP64).  A workgroup
+// covers 16 * waves * rt rows.
 hipError_t launch_tn(int type, int rt, int pf, const TnArgs& a, hipStream_t s);
 int tn_step_elems(int type);
 // out[c*ldo + r] = TQ(sum over the nsplit partials in split order), r < rows, c < kp.

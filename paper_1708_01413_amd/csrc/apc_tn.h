@@ -76,12 +76,14 @@ __host__ __device__ inline int64_t frag_index(int64_t r, int64_t c, int64_t rows
   return (ks * (rows / 16) + r / 16) * (16 * kStep) + (64 * (kc / 4) + lane) * kE + c % kE;
 }
 
-// Workgroup: 4 waves, wave w owns RT consecutive 16-row tiles, all 16*NCT
-// right-hand sides of its column group.  Grid: (rows / (64 RT)) x ncg x nsplit,
+// Workgroup: W waves (4 or 8), wave w owns RT consecutive 16-row tiles, all
+// 16*NCT right-hand sides of its column group.  Grid: (rows / (16 W RT)) x ncg x nsplit,
 // with the split index fastest so that, dealt round-robin over the 8 XCDs, one
 // XCD works on one split (nsplit | 8) and keeps that split's V in its L2.
-template <typename T, int RT, int NCT, int PF, int NT>
+template <typename T, int RT, int NCT, int PF, int NT, int W = 4>
 __device__ inline void tn_block(const TnArgs& a, int bid, TnStage<NCT>& vs) {
+  static_assert((W == 4 || W == 8) && (4 * NCT) % W == 0, "waves per workgroup");
+  constexpr int VU = 4 * NCT / W;     // V rows each thread stages per step: 4 W rows at a time
   using Acc = typename TnTraits<T>::Acc;
   using Part = typename TnTraits<T>::Part;
   constexpr int kE = 16 / sizeof(T);  // elements per 16-byte piece
@@ -100,7 +102,7 @@ __device__ inline void tn_block(const TnArgs& a, int bid, TnStage<NCT>& vs) {
   const int nsteps = kend > kb0 ? static_cast<int>((kend - kb0) / kStep) : 0;
   const T* M = static_cast<const T*>(a.M);
   const T* V = static_cast<const T*>(a.V) + static_cast<int64_t>(cg) * NCT * 16 * a.ldv + kb0;
-  const int64_t rb = rtile * 64 * RT + static_cast<int64_t>(wv) * 16 * RT;
+  const int64_t rb = rtile * 16 * W * RT + static_cast<int64_t>(wv) * 16 * RT;
 
   // Fragment-packed M: this wave's tile t of step s starts at
   // ((kb0 / kStep + s) * rows / 16 + rb / 16 + t) * 16 * kStep, and lane L's
@@ -122,7 +124,7 @@ __device__ inline void tn_block(const TnArgs& a, int bid, TnStage<NCT>& vs) {
   // while step s computes.  The step loop is unrolled by the ring size so that
   // every slot index is a compile-time constant.
   constexpr int D = PF + 1;
-  u32x4 mr[D][RT][4], vst[NCT];
+  u32x4 mr[D][RT][4], vst[VU];
   auto load_m = [&](u32x4 (&dst)[RT][4], int step) {
     const int64_t o = static_cast<int64_t>(step) * sstride;
 #pragma unroll
@@ -136,8 +138,8 @@ __device__ inline void tn_block(const TnArgs& a, int bid, TnStage<NCT>& vs) {
   auto load_v = [&](int step) {
     const int64_t o = static_cast<int64_t>(step) * kStep;
 #pragma unroll
-    for (int u = 0; u < NCT; ++u)
-      vst[u] = *reinterpret_cast<const u32x4*>(vsrc + static_cast<int64_t>(16 * u) * a.ldv + o);
+    for (int u = 0; u < VU; ++u)
+      vst[u] = *reinterpret_cast<const u32x4*>(vsrc + static_cast<int64_t>(4 * W * u) * a.ldv + o);
   };
   // A split past the end of K (from rounding its length up to whole steps)
   // writes zero partials.  Otherwise every load below is issued without a
@@ -148,7 +150,7 @@ __device__ inline void tn_block(const TnArgs& a, int bid, TnStage<NCT>& vs) {
   for (int s0 = 0; s0 < PF; ++s0) load_m(mr[s0], min(s0, nsteps - 1));
   load_v(0);
 #pragma unroll
-  for (int u = 0; u < NCT; ++u) vs[0][vr + 16 * u][vp] = vst[u];
+  for (int u = 0; u < VU; ++u) vs[0][vr + 4 * W * u][vp] = vst[u];
   __syncthreads();
   // One step: V's next step and M's step + PF are loaded, step `step` is
   // multiplied from ring slot i, V's next step goes to the other LDS buffer.
@@ -175,7 +177,7 @@ __device__ inline void tn_block(const TnArgs& a, int bid, TnStage<NCT>& vs) {
     }
     if (more) {
 #pragma unroll
-      for (int u = 0; u < NCT; ++u) vs[buf ^ 1][vr + 16 * u][vp] = vst[u];
+      for (int u = 0; u < VU; ++u) vs[buf ^ 1][vr + 4 * W * u][vp] = vst[u];
     }
     __syncthreads();
   };
