@@ -2393,6 +2393,8 @@ apc_status batch_items(const apc_plan* plans, int32_t count, BatchPlanItems* it)
     it->start.push_back(static_cast<int32_t>(it->A.size()));
   }
   if (batch_single_pass(plans, count)) {
+    // (weight, item) pairs, ordered below.
+    std::vector<std::pair<int64_t, int2>> fw, ww;
     for (int32_t s = 0; s < count; ++s) {
       const apc_plan_s* P = plans[s];
       if (P->gemm) {
@@ -2411,9 +2413,23 @@ apc_status batch_items(const apc_plan* plans, int32_t count, BatchPlanItems* it)
       }
       it->tile_at.push_back(it->tiles.size());
       for (auto* v : {&r0, &nr, &bk, &first}) it->tiles.insert(it->tiles.end(), v->begin(), v->end());
-      for (size_t t = 0; t < r0.size(); ++t) it->F.push_back(make_int2(s, static_cast<int>(t)));
-      for (int64_t j = 0; j < P->n; j += 32) it->W.push_back(make_int2(s, static_cast<int>(j)));
+      for (size_t t = 0; t < r0.size(); ++t)
+        fw.emplace_back(static_cast<int64_t>(nr[t]) * P->L.ldc, make_int2(s, static_cast<int>(t)));
+      for (int64_t j = 0; j < P->n; j += 32)
+        ww.emplace_back(static_cast<int64_t>(r0.size()) + P->m, make_int2(s, static_cast<int>(j)));
     }
+    // Largest items first: workgroups take items in launch order, so the big
+    // tiles start early and small ones fill the end of the pass, instead of a
+    // few big tiles running alone at its end.  Every item writes only its own
+    // partial row or columns (partial rows are summed later in tile order), so
+    // the order changes no result.
+    auto by_weight = [](const std::pair<int64_t, int2>& a, const std::pair<int64_t, int2>& b) {
+      return a.first > b.first;
+    };
+    std::stable_sort(fw.begin(), fw.end(), by_weight);
+    std::stable_sort(ww.begin(), ww.end(), by_weight);
+    for (const auto& f : fw) it->F.push_back(f.second);
+    for (const auto& w : ww) it->W.push_back(w.second);
   }
   // Mixed batch: the k-RHS plans' contraction tiles and epilogue chunks next
   // to the k = 1 items, one list per launch.  Contraction tiles first (they
