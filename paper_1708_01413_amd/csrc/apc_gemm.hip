@@ -24,11 +24,11 @@
 // label.  A step's 256 bytes of a row are sixteen 16-byte chunks; lane group g
 // (lanes 16 g .. 16 g + 15) holds chunks g, 4 + g, 8 + g, 12 + g as pieces
 // p = 0..3, and piece p feeds the p-th MFMA of the step (bf16: one 16x16x32,
-// f32: four 16x16x4, f64: two 16x16x4).  So one load instruction reads 64
-// contiguous bytes of each of 16 rows, which measured 2-5 % faster than giving
-// each lane one contiguous 64-byte run.  Plain loads: non-temporal ones
-// measured slower here.  V is read from LDS with exactly the same (lane group,
-// piece, element) -> K mapping, so the sum is over all of K.
+// f32: four 16x16x4, f64: two 16x16x4).  In a row-major M one load instruction
+// then reads 64 contiguous bytes of each of 16 rows, which measured 2-5 %
+// faster than giving each lane one contiguous 64-byte run.  V is read from LDS
+// with exactly the same (lane group, piece, element) -> K mapping, so the sum
+// is over all of K.
 //
 // Fragment-packed M.  An MFMA operand gives each of 16 lanes its own row, so
 // in a row-major M one load instruction touches 16 rows 32 KB apart and a
@@ -40,7 +40,8 @@
 // load instruction then reads 1 KB contiguous, and the tiles are ordered by
 // step, then row tile, so a workgroup's step is 16 RT KB contiguous per wave.
 // The same probe reads this layout at 6.8-7.0 TB/s with non-temporal loads
-// (each byte of M is read once per pass).  k_tn_pack writes it (frag = 1).
+// (each byte of M is read once per pass), which are the default for it; the
+// tuner also times plain loads.  k_tn_pack writes it (frag = 1).
 //
 // Split-K partials are written per split and summed in a fixed order by the
 // epilogue kernels, so results do not depend on timing.
