@@ -341,6 +341,7 @@ class Plan:
         base = self.workspace.data_ptr()
         self._ws_ptr = (base + 255) // 256 * 256
         self.A, self.b = A, b
+        self._streams_in()
         g = math.nan if gamma is None else float(gamma)
         e = math.nan if eta is None else float(eta)
         self.handle = apc_setup(A.data_ptr(), A.stride(0), b.data_ptr(), b.stride(0), self.N,
@@ -348,6 +349,22 @@ class Plan:
                                 self._ws_ptr, ws, self.stream.cuda_stream)
         if anchor_every is not None:
             apc_set_anchor(self.handle, int(anchor_every))
+
+    # -- stream order between torch and the library
+    def _streams_in(self):
+        """Make the plan's stream wait for what is queued on the caller's current stream:
+        the tensors a call reads, and memory the caching allocator just handed out (it
+        orders reuse on the current stream only)."""
+        cur = self._torch.cuda.current_stream(self.device)
+        if cur.cuda_stream != self.stream.cuda_stream:
+            self.stream.wait_stream(cur)
+
+    def _streams_out(self):
+        """Make the caller's current stream wait for the plan's stream, so that torch work
+        on the tensors a call wrote (and later reuse of their memory) comes after it."""
+        cur = self._torch.cuda.current_stream(self.device)
+        if cur.cuda_stream != self.stream.cuda_stream:
+            cur.wait_stream(self.stream)
 
     # -- iteration
     def iterate(self, T: int, graph: bool = False):
@@ -373,7 +390,9 @@ class Plan:
 
     def solve(self, rtol: float, max_iters: int):
         x = self._torch.empty(self._xshape(), dtype=self._torch.float64, device=self.device)
+        self._streams_in()
         st, it, rr = apc_solve(self.handle, rtol, max_iters, x.data_ptr(), 1 if self.k == 1 else self.k)
+        self._streams_out()
         if st not in (APC_OK, APC_ENOCONV):
             _check(st)
         return x, it, rr, st
@@ -390,6 +409,7 @@ class Plan:
             raise ValueError("b must be a float64 CUDA tensor shaped like the plan's b")
         b = b.contiguous()
         self.b = b
+        self._streams_in()
         apc_restart(self.handle, b.data_ptr(), 1 if self.k == 1 else self.k)
 
     def backward(self, dxbar, T: int, ckpt_every: int | None = None):
@@ -408,27 +428,35 @@ class Plan:
         wp = (ws.data_ptr() + 255) // 256 * 256
         dB = torch.empty(self.b.shape, dtype=torch.float64, device=self.device)
         ld = 1 if self.k == 1 else self.k
+        self._streams_in()
         dg, de = apc_backward(self.handle, dxbar.data_ptr(), ld, T, ckpt_every, dB.data_ptr(), ld,
                               wp, nb)
+        self._streams_out()
         return dB, dg, de
 
     # -- state access
     def xbar(self):
         x = self._torch.empty(self._xshape(), dtype=self._torch.float64, device=self.device)
+        self._streams_in()
         apc_get_xbar(self.handle, x.data_ptr(), 1 if self.k == 1 else self.k)
+        self._streams_out()
         return x
 
     def local(self):
         shape = (self.m, self.n) if self.k == 1 else (self.m, self.n, self.k)
         X = self._torch.empty(shape, dtype=self._torch.float64, device=self.device)
+        self._streams_in()
         apc_get_local(self.handle, X.data_ptr(), self.n if self.k == 1 else self.k)
+        self._streams_out()
         return X
 
     def project(self, V):
         if V.shape != (self.m, self.n) or V.dtype != self._torch.float64 or not V.is_contiguous():
             raise ValueError("V must be a contiguous (m, n) float64 tensor")
         out = self._torch.empty_like(V)
+        self._streams_in()
         apc_project(self.handle, V.data_ptr(), out.data_ptr(), self.n)
+        self._streams_out()
         return out
 
     def params(self) -> dict:
@@ -551,6 +579,7 @@ class Batch:
         dev = self.plans[0].device
         self.workspace = torch.empty(nb + 256, dtype=torch.uint8, device=dev)
         wp = (self.workspace.data_ptr() + 255) // 256 * 256
+        self.plans[0]._streams_in()
         h = ctypes.c_void_p()
         _check(lib.apc_batch_create(ctypes.byref(h), arr, self.count, wp, nb))
         self.handle = h.value
@@ -610,6 +639,7 @@ class HeavyBall:
             raise ApcError(APC_EUNSUPPORTED, lib.apc_last_error().decode(errors="replace"))
         self.workspace = torch.empty(nb + 256, dtype=torch.uint8, device=plan.device)
         wp = (self.workspace.data_ptr() + 255) // 256 * 256
+        plan._streams_in()
         nan = float("nan")
         h = ctypes.c_void_p()
         _check(lib.apc_hbm_create(ctypes.byref(h), plan.handle, kind,
@@ -625,7 +655,9 @@ class HeavyBall:
 
     def x(self):
         out = self._torch.empty(self.plan.n, dtype=self._torch.float64, device=self.plan.device)
+        self.plan._streams_in()
         _check(lib.apc_hbm_get_x(self.handle, out.data_ptr(), 1))
+        self.plan._streams_out()
         return out
 
     def residual(self) -> float:

@@ -83,12 +83,13 @@ hipError_t tn_nct_w(const TnArgs& a, hipStream_t s) {
 }
 
 // Eight-wave workgroups (two waves per SIMD where the registers allow) for
-// bf16 / FP32 with one or two row tiles per wave, non-temporal loads and one or
-// two steps of prefetch: twice the rows share each staged step of V.
+// bf16 / FP32 with non-temporal loads and one row tile per wave (up to four
+// steps of prefetch) or two (up to two): twice the rows share each staged step
+// of V.
 template <typename T, int RT, int PF, int NT>
 hipError_t tn_nct(const TnArgs& a, hipStream_t s) {
   if (a.waves == 8) {
-    if constexpr (sizeof(T) <= 4 && RT <= 2 && PF <= 2 && NT == 1)
+    if constexpr (sizeof(T) <= 4 && (RT == 1 || (RT == 2 && PF <= 2)) && NT == 1)
       return tn_nct_w<T, RT, PF, NT, 8>(a, s);
     else
       return hipErrorInvalidValue;

@@ -800,7 +800,7 @@ apc_status tn_tune(apc_plan_s* P, int type, TnArgs base, TnChoice* out) {
     if (c.pf > 2) c.nt = 1;
     if (const char* e = std::getenv("APC_TN_NT")) c.nt = std::atoi(e) != 0;
     if (const char* e = std::getenv("APC_TN_WAVES"))
-      if (std::atoi(e) == 8 && type != kTnF64 && c.rt <= 2 && c.pf <= 2 && c.nt &&
+      if (std::atoi(e) == 8 && type != kTnF64 && (c.rt == 1 || (c.rt == 2 && c.pf <= 2)) && c.nt &&
           base.rows % (128 * c.rt) == 0)
         c.waves = 8;
     *out = c;
@@ -837,7 +837,8 @@ apc_status tn_tune(apc_plan_s* P, int type, TnArgs base, TnChoice* out) {
           cand.push_back(c);
           // The same with eight waves per workgroup.
           // (Two tiles, two steps ahead and 128 right-hand sides spill there.)
-          if (type != kTnF64 && rt <= 2 && pf <= 2 && nt == 1 && base.rows % (128 * rt) == 0 &&
+          if (type != kTnF64 && (rt == 1 || (rt == 2 && pf <= 2)) && nt == 1 &&
+              base.rows % (128 * rt) == 0 &&
               base.kp >= 32 && blocks(rt, ns, 8) >= 32 && !(rt == 2 && pf == 2 && base.kp >= 128)) {
             c.waves = 8;
             cand.push_back(c);

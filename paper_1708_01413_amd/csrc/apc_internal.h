@@ -406,7 +406,7 @@ struct TnArgs {
   void* part;
   int64_t ldp;
   int32_t nt;   // 1: non-temporal loads of M
-  int32_t waves = 4;  // waves per workgroup: 4, or 8 (bf16 / FP32, rt <= 2, nt, pf <= 2)
+  int32_t waves = 4;  // waves per workgroup: 4, or 8 (bf16 / FP32, nt; rt 1, or rt 2 with pf <= 2)
 };
 // rt: 16-row tiles per wave (1, 2, 4; FP64 1, 2); pf: steps of M loaded ahead
 // (1, 2; 3 and 4 with rt <= 2, non-temporal loads, not FP64).  A workgroup

@@ -554,12 +554,14 @@ def test_launch_shapes_change_rounding_only(rt, split, monkeypatch):
     assert dev <= 1e-12
 
 
-@pytest.mark.parametrize("rt,pf,nt,split", [("1", "4", "1", "1"), ("2", "3", "1", "2"),
-                                           ("4", "2", "0", "4"), ("2", "1", "1", "8")])
-def test_fp32_launch_shapes_match_oracle(rt, pf, nt, split, monkeypatch):
+@pytest.mark.parametrize("rt,pf,nt,split,waves", [("1", "4", "1", "1", "4"), ("2", "3", "1", "2", "4"),
+                                                 ("4", "2", "0", "4", "4"), ("2", "1", "1", "8", "4"),
+                                                 ("1", "2", "1", "4", "8"), ("2", "1", "1", "2", "8")])
+def test_fp32_launch_shapes_match_oracle(rt, pf, nt, split, waves, monkeypatch):
     """FP32 k-RHS plans with forced contraction shapes (row tiles per wave, prefetch depth,
-    non-temporal loads, split-K), including the deep-prefetch ones, against the oracle's
-    trajectory at the FP32 bar (plain FP32 updates, no anchors)."""
+    non-temporal loads, split-K, waves per workgroup), including the deep-prefetch and
+    eight-wave ones, against the oracle's trajectory at the FP32 bar (plain FP32 updates,
+    no anchors)."""
     apc = _apc()
     torch = _torch()
     S = synth.gaussian_system(1536, 1024, 12, k=24, seed=39, scale=1 / math.sqrt(1024))
@@ -573,17 +575,19 @@ def test_fp32_launch_shapes_match_oracle(rt, pf, nt, split, monkeypatch):
         x, xbar = O.apc_step(Qt, x, xbar, g, e)
         ref.append(xbar.copy())
     A, b = upload(S)
-    for var, val in (("APC_TN_RT", rt), ("APC_TN_PF", pf), ("APC_TN_NT", nt), ("APC_TN_SPLIT", split)):
+    for var, val in (("APC_TN_RT", rt), ("APC_TN_PF", pf), ("APC_TN_NT", nt), ("APC_TN_SPLIT", split),
+                     ("APC_TN_WAVES", waves)):
         monkeypatch.setenv(var, val)
     plan = apc.Plan(A, b, S.off, "f32", gamma=g, eta=e, anchor_every=0)
     shapes = plan.launch_shapes()
+    assert shapes["pass_a"]["rows_per_wg"] == 16 * int(waves) * int(rt)
     snaps = [plan.xbar()]
     for _ in range(T):
         plan.iterate(1)
         snaps.append(plan.xbar())
     got = torch.stack(snaps).cpu().numpy()
     dev = max(np.linalg.norm(got[t] - ref[t]) for t in range(T + 1)) / np.linalg.norm(S.xstar)
-    say(f"case: fp32 forced shape rt={rt} pf={pf} nt={nt} split={split} {shapes['pass_a']}: "
+    say(f"case: fp32 forced shape rt={rt} pf={pf} nt={nt} split={split} waves={waves} {shapes['pass_a']}: "
         f"dev {dev:.2e}")
     assert shapes["pass_a"]["splits"] == int(split)
     assert dev <= TOL["f32"]
