@@ -20,7 +20,11 @@
  *     outputs and the workspace; sizes come from apc_workspace_bytes.
  *   - All GPU work is enqueued on the stream given to apc_setup (a
  *     hipStream_t passed as void*, NULL = default stream).  Entry points that
- *     return host values synchronise that stream; they say so below.
+ *     return host values synchronise that stream; they say so below.  Device
+ *     buffers a call reads must be ready in that stream's order, and buffers
+ *     it writes are valid in that stream's order only: a caller producing or
+ *     consuming them on another stream orders the two streams (events), as
+ *     the Python binding does around every call.
  *   - No C++ exception crosses this boundary.  A non-OK status leaves a
  *     message for apc_last_error() (thread-local).  Argument errors are
  *     detected on the host before any GPU work is enqueued.
