@@ -412,6 +412,7 @@ struct apc_plan_s {
   int tq = kTnF64;                     // element type of the k-RHS factor copies
   TnChoice tnA, tnB, tnX0, tnR;        // launch shapes: pass A, pass B, x_bar(0), residual
   int anchor_every = 0;                // k-RHS FP32/bf16: every this many updates one in FP64
+  bool c64p_ready = false;             // the FP64 factor in pass-A orientation is packed
   int64_t pmax = 1;                    // largest block
   int32_t passb_nt = 1;                // k = 1 pass B: non-temporal loads of C
   int32_t passb_rows = 1;              // k = 1 pass B: waves split the block's rows
@@ -570,13 +571,21 @@ apc_status pinned_at_least(apc_plan_s* P, size_t n) {
   return APC_OK;
 }
 
+apc_status expand_blocks(apc_plan_s* P, const double* w, double* y, double alpha, double beta,
+                         const double* C = nullptr);
+apc_status rowdot64(apc_plan_s* P, const double* va, const double* vb, int64_t ldvb, double* out,
+                    const double* C = nullptr);
+
 // max_i ||C_i C_i^T - I||, estimated with one random vector z: with
 // C_i C_i^T = I + E_i, u_i = C_i^T C_i z and v_i = C_i^T C_i u_i differ by
 // C_i^T E_i C_i z, so ||v_i - u_i|| / ||u_i|| estimates ||E_i|| (within a factor
 // up to sqrt(p_i) when E_i is concentrated in one direction).  Two single passes
-// over C; synchronises the stream.  Uses the x, Y, vtmp and w slices as scratch.
-// flags (4 ints) and scal (2 doubles), when non-null, are read back from the
-// plan's slices in the same synchronisation.
+// over C when its rows fit the single-pass kernel (k = 1 plans), else two
+// row-dot and two expansion passes; synchronises the stream.  Scratch: the Y
+// and vtmp slices, and for the second vector the x slice (k = 1) or the padded
+// copy of A's slice (k-RHS plans, before setup fills it), plus w.  flags (4
+// ints) and scal (2 doubles), when non-null, are read back from the plan's
+// slices in the same synchronisation.
 apc_status orthogonality_defect(apc_plan_s* P, const double* C, double* defect, int* flags = nullptr,
                                 double* scal = nullptr) {
   const Layout& L = P->L;
@@ -586,16 +595,24 @@ apc_status orthogonality_defect(apc_plan_s* P, const double* C, double* defect, 
   // a ratio), generated on the GPU.
   HIP_TRY(launch_lanczos_start(0x0a7ull * 1000003ull, P->n, L.ldc, zd, nullptr, st));
   double* U = P->at<double>(L.Y);
-  double* V = P->x();
-  double* part = P->at<double>(L.fpart);
+  double* V = P->gemm ? P->at<double>(L.Apad) : P->x();
   double* out = P->at<double>(L.w);
-  const int g = fused_cpt(L.ldc, 8) >= 16 ? 1 : 2;
-  const int32_t remap = P->xcd_remap == 1 ? 1 : 0;
-  for (int app = 0; app < 2; ++app) {
-    FusedArgs<double, double> a{C, L.ldc, P->n, P->tf(0), P->tf(1), P->tf(2), P->ntiles_f,
-                                app == 0 ? zd : U, app == 0 ? 0 : L.ldc, part, L.ldc, remap};
-    HIP_TRY(launch_fused_f64(a, g, st));
-    HIP_TRY(launch_block_sum(part, L.ldc, P->tf(3), P->m, L.ldc, app == 0 ? U : V, L.ldc, st));
+  if (!P->gemm && fused_cpt(L.ldc, 8) > 0) {
+    double* part = P->at<double>(L.fpart);
+    const int g = fused_cpt(L.ldc, 8) >= 16 ? 1 : 2;
+    const int32_t remap = P->xcd_remap == 1 ? 1 : 0;
+    for (int app = 0; app < 2; ++app) {
+      FusedArgs<double, double> a{C, L.ldc, P->n, P->tf(0), P->tf(1), P->tf(2), P->ntiles_f,
+                                  app == 0 ? zd : U, app == 0 ? 0 : L.ldc, part, L.ldc, remap};
+      HIP_TRY(launch_fused_f64(a, g, st));
+      HIP_TRY(launch_block_sum(part, L.ldc, P->tf(3), P->m, L.ldc, app == 0 ? U : V, L.ldc, st));
+    }
+  } else {
+    // w = C z, U_i = C_i^T w_i; then w = C (0 - U_blk) = -C_i U_i, V_i = -C_i^T w_i.
+    ST_TRY(rowdot64(P, zd, nullptr, 0, out, C));
+    ST_TRY(expand_blocks(P, out, U, 1.0, 0.0, C));
+    ST_TRY(rowdot64(P, nullptr, U, L.ldc, out, C));
+    ST_TRY(expand_blocks(P, out, V, -1.0, 0.0, C));
   }
   HIP_TRY(launch_defect(U, V, L.ldc, P->m, P->n, out, st));
   const size_t nh = 2 * static_cast<size_t>(P->m);
@@ -654,6 +671,17 @@ TnArgs resid_args(const apc_plan_s* P, const double* X) {
   const Layout& L = P->L;
   return tn_args(P->ws + L.Apad, L.np, L.Np, X, L.np, P->kp, L.np, P->tnR, kTnF64,
                  P->ws + L.tnpart, L.Np);
+}
+
+// The FP64 factor C (from the plan's FP64 slice) in the fragment-packed pass-A
+// layout (C64p), once.
+apc_status pack_c64p(apc_plan_s* P) {
+  if (P->c64p_ready || P->tq == kTnF64) return APC_OK;
+  const Layout& L = P->L;
+  HIP_TRY(launch_tn_pack_frag(kTnF64, P->C64(), L.ldc, P->N, P->n, 0, P->ws + L.C64p, L.np, L.Np,
+                              P->stream));
+  P->c64p_ready = true;
+  return APC_OK;
 }
 
 TnUpdateArgs update_args(const apc_plan_s* P, const TnChoice& ch, int mode) {
@@ -953,20 +981,23 @@ int launches_per_update(const apc_plan_s* P) {
   return 2 * ((P->m + g - 1) / g) + 1;
 }
 
-// y_i = alpha * Q_i w_i + beta * y_i over all blocks of the FP64 factor.
-apc_status expand_blocks(apc_plan_s* P, const double* w, double* y, double alpha, double beta) {
-  ExpandArgs<double> e{P->C64(), P->L.ldc, P->doff(), P->m,
+// y_i = alpha * C_i^T w_i + beta * y_i over all blocks of an FP64 factor C
+// (the plan's, unless given).
+apc_status expand_blocks(apc_plan_s* P, const double* w, double* y, double alpha, double beta,
+                         const double* C) {
+  ExpandArgs<double> e{C ? C : P->C64(), P->L.ldc, P->doff(), P->m,
                        static_cast<int32_t>((P->L.ldc + expand_slab(8) - 1) / expand_slab(8)),
                        P->N, w, 1, 0, y, P->L.ldc, alpha, beta, 0};
   HIP_TRY(launch_expand_f64(e, P->stream));
   return APC_OK;
 }
 
-// FP64 out = C d over the block tiles, d_i = va - vb_i (va or vb may be null).
+// FP64 out = C d over the block tiles, d_i = va - vb_i (va or vb may be null),
+// for an FP64 factor C (the plan's, unless given).
 apc_status rowdot64(apc_plan_s* P, const double* va, const double* vb, int64_t ldvb,
-                    double* out) {
-  RowdotArgs<double> a{P->C64(), P->L.ldc, P->ta(0), P->ta(1), P->ta(2), P->L.ntiles_a, 0, va,
-                       vb, ldvb, nullptr, 0, out, 0, 1, P->L.ldc, 0, P->passa_rows, 0};
+                    double* out, const double* C) {
+  RowdotArgs<double> a{C ? C : P->C64(), P->L.ldc, P->ta(0), P->ta(1), P->ta(2), P->L.ntiles_a, 0,
+                       va, vb, ldvb, nullptr, 0, out, 0, 1, P->L.ldc, 0, P->passa_rows, 0};
   HIP_TRY(launch_rowdot_f64(a, P->stream));
   return APC_OK;
 }
@@ -1236,6 +1267,14 @@ apc_status residual_norm2(apc_plan_s* P, const double* x, double* out_dev) {
     HIP_TRY(launch_sum_partials(P->at<double>(P->L.ssq), sumsq_parts(), out_dev, P->stream));
     return APC_OK;
   }
+  if (!x && P->ldb == P->k) {
+    // ||B||_F^2 of a contiguous B: one sum of squares instead of a launch per
+    // right-hand side.
+    HIP_TRY(launch_sumsq(P->B, static_cast<int64_t>(P->k) * P->N, P->at<double>(P->L.ssq),
+                         P->stream));
+    HIP_TRY(launch_sum_partials(P->at<double>(P->L.ssq), sumsq_parts(), out_dev, P->stream));
+    return APC_OK;
+  }
   for (int col = 0; col < P->k; ++col)
     HIP_TRY(launch_residual_partial(P->A, P->lda, P->B + col, P->ldb, P->N, P->n,
                                     x ? x + static_cast<int64_t>(col) * P->L.ldc : nullptr,
@@ -1325,14 +1364,17 @@ apc_status setup_impl(apc_plan_s* P, const Tiles& T) {
   for (int i = 0; i < m; ++i) pmax = std::max(pmax, P->off[i + 1] - P->off[i]);
   const double rank_tol = 32.0 * std::numeric_limits<double>::epsilon() *
                           static_cast<double>(std::max<int64_t>(pmax, 32));
-  // A k = 1 FP32 plan rounds the factor to FP32 (relative 6e-8 per entry), so a
-  // second CholeskyQR pass, which takes the rows' departure from orthonormality
-  // from the first pass's ~kappa(A_i)^2 eps down to ~eps, changes nothing the
-  // iteration sees when that departure is already far below FP32 rounding.  The
-  // second pass (about a quarter of setup at 16384 x 8192) is skipped when the
+  // An FP32 or bf16 plan rounds the factor to FP32 / bf16 for its products
+  // (relative 6e-8 / 4e-3 per entry), so a second CholeskyQR pass, which takes
+  // the rows' departure from orthonormality from the first pass's
+  // ~kappa(A_i)^2 eps down to ~eps, changes nothing those products see when
+  // that departure is already far below their rounding; the FP64 uses of the
+  // factor (anchor updates, the k-RHS start, refinement restarts) then carry a
+  // departure of at most the same 1e-10, below their tolerances.  The second
+  // pass (about a quarter of setup at 16384 x 8192) is skipped when the
   // measured departure, times sqrt(p_max) for the estimate's worst case, is at
-  // most 1e-10; FP64 plans, the k-RHS forms and APC_QR_PASSES=2 always take two.
-  bool may_skip = !P->gemm && P->prec == APC_F32 && P->fused && fused_cpt(ldc, 8) > 0;
+  // most 1e-10; FP64 plans and APC_QR_PASSES=2 always take two.
+  bool may_skip = P->prec != APC_F64 && (P->gemm || P->fused);
   int flags[4] = {0, 0, 0, 0};
   double scal[2] = {0, 0};
   bool have_flags = false;  // read with the orthogonality estimate
@@ -1410,7 +1452,10 @@ apc_status setup_impl(apc_plan_s* P, const Tiles& T) {
     HIP_TRY(launch_tn_pack_frag(P->tq, Ca, ldc, N, n, 1, P->ws + L.CqT, Np, np, st));
     if (P->tq != kTnF64) {
       HIP_TRY(launch_tn_pack_frag(kTnF64, Ca, ldc, N, n, 1, P->ws + L.C64T, Np, np, st));
-      HIP_TRY(launch_tn_pack_frag(kTnF64, Ca, ldc, N, n, 0, P->ws + L.C64p, np, Np, st));
+      // The FP64 factor in pass-A orientation serves the anchor updates and the
+      // FP32 adjoint only; a bf16 plan without anchors packs it when
+      // apc_set_anchor turns them on.
+      if (P->anchor_every > 0 || !P->bf16) ST_TRY(pack_c64p(P));
     }
     HIP_TRY(launch_tn_pack_frag(kTnF64, P->A, P->lda, N, n, 0, P->ws + L.Apad, np, Np, st));
     const int64_t sq = P->tq == kTnF64 ? 8 : P->tq == kTnF32 ? 4 : 2;
@@ -1767,8 +1812,11 @@ apc_status restart_inner(apc_plan_s* p, double* Rb) {
                             2 * (p->kp - p->k) * p->N, 0u, p->stream));
   HIP_TRY(launch_linv_apply(p->doff(), p->at<int64_t>(L.goff), p->m, p->pmax,
                             p->at<double>(L.Linv), Rb, p->N, cw, p->N, p->kp, 0, 1.0, p->stream));
-  HIP_TRY(launch_linv_apply(p->doff(), p->at<int64_t>(L.goff), p->m, p->pmax,
-                            p->at<double>(L.Linv2), cw, p->N, Rb, p->N, p->kp, 0, 1.0, p->stream));
+  if (p->qr_passes == 2)
+    HIP_TRY(launch_linv_apply(p->doff(), p->at<int64_t>(L.goff), p->m, p->pmax,
+                              p->at<double>(L.Linv2), cw, p->N, Rb, p->N, p->kp, 0, 1.0, p->stream));
+  else
+    HIP_TRY(launch_copy_strided(cw, 1, Rb, 1, static_cast<int64_t>(p->kp) * p->N, 1, p->stream));
   ST_TRY(start_gemm(p, Rb));
   p->inner_pending = false;
   return APC_OK;
@@ -2018,6 +2066,7 @@ apc_status apc_set_anchor(apc_plan p, int32_t every) {
     return fail(APC_EUNSUPPORTED, "anchor updates exist for FP32 / bf16 plans with the k-RHS form");
   if (p->since_start != 0)
     return fail(APC_EINVAL, "set the anchor spacing before the first update after setup");
+  if (every > 0) ST_TRY(pack_c64p(p));
   if (every != p->anchor_every) {
     (void)hipStreamSynchronize(p->stream);  // no captured graph may still be running
     p->drop_graphs();
@@ -2224,10 +2273,15 @@ apc_status apc_backward(apc_plan p, const double* dXbar, int64_t ldd, int32_t T,
   HIP_TRY(launch_tn_sum_cast(kTnF64, part, P->tnR.nsplit, P->kp, L.Np, L.Np, W64, L.Np, st));
   double* t1b = P->at<double>(L.Rb);
   double* t2b = P->at<double>(L.cb);
-  HIP_TRY(launch_linv_apply(P->doff(), P->at<int64_t>(L.goff), P->m, P->pmax,
-                            P->at<double>(L.Linv2), W64, L.Np, t1b, P->N, P->kp, 1, 1.0 / P->m, st));
-  HIP_TRY(launch_linv_apply(P->doff(), P->at<int64_t>(L.goff), P->m, P->pmax,
-                            P->at<double>(L.Linv), t1b, P->N, t2b, P->N, P->kp, 1, 1.0, st));
+  if (P->qr_passes == 2) {
+    HIP_TRY(launch_linv_apply(P->doff(), P->at<int64_t>(L.goff), P->m, P->pmax,
+                              P->at<double>(L.Linv2), W64, L.Np, t1b, P->N, P->kp, 1, 1.0 / P->m, st));
+    HIP_TRY(launch_linv_apply(P->doff(), P->at<int64_t>(L.goff), P->m, P->pmax,
+                              P->at<double>(L.Linv), t1b, P->N, t2b, P->N, P->kp, 1, 1.0, st));
+  } else {  // one CholeskyQR pass: c = L1^{-1} b only
+    HIP_TRY(launch_linv_apply(P->doff(), P->at<int64_t>(L.goff), P->m, P->pmax,
+                              P->at<double>(L.Linv), W64, L.Np, t2b, P->N, P->kp, 1, 1.0 / P->m, st));
+  }
   HIP_TRY(launch_copy_t(t2b, P->N, dB, lddb, P->N, P->k, st));
   // The plan is left at x_bar(T) of the forward run.
   ST_TRY(restore_state(P, ck(nck), ck(nck) + cnt));

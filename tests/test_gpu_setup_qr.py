@@ -1,7 +1,8 @@
-"""GPU checks of the thin QR at setup (Sec. 3.1, CholeskyQR): a k = 1 FP32 plan skips
-the second CholeskyQR pass only when the first pass's rows are orthonormal far below
-FP32 rounding, and takes both passes otherwise; either way the trajectory matches the
-FP64 oracle (Householder QR) to the FP32 bar 1e-5.
+"""GPU checks of the thin QR at setup (Sec. 3.1, CholeskyQR): an FP32 or bf16 plan (k = 1
+or the k-RHS form) skips the second CholeskyQR pass only when the first pass's rows are
+orthonormal far below FP32 rounding, and takes both passes otherwise; either way the
+trajectory matches the FP64 oracle (Householder QR) to the FP32 bar 1e-5, and bf16
+refinement still reaches the FP64 solution.
 
 The ill-conditioned case mixes each block's rows by a p x p matrix whose singular values
 span five orders of magnitude.  That leaves every row space, so every projector P_i and
@@ -154,3 +155,81 @@ def test_restart_after_one_pass_setup():
     d = float(torch.linalg.norm(plan.xbar() - fresh.xbar()) / torch.linalg.norm(fresh.xbar()))
     say(f"case: restart after one-pass setup, dev {d:.2e}")
     assert d <= 1e-12
+
+
+# ---------------------------------------------------------------- k right-hand sides
+
+
+def oracle_traj_k(S, T, gamma, eta):
+    Qt, R = O.factor(S.A, S.off)
+    x = O.init_local(Qt, R, S.B, S.off)
+    xbar = O.initial_average(x)
+    traj = [xbar.copy()]
+    for _ in range(T):
+        x, xbar = O.apc_step(Qt, x, xbar, gamma, eta)
+        traj.append(xbar.copy())
+    return np.stack(traj)
+
+
+def gpu_traj_k(plan, T):
+    torch = _torch()
+    snaps = [plan.xbar()]
+    for _ in range(T):
+        plan.iterate(1)
+        snaps.append(plan.xbar())
+    torch.cuda.synchronize()
+    return torch.stack(snaps).cpu().numpy()
+
+
+def dev_k(a, b, xstar):
+    """Largest column error over t: max_t max_c ||a_t[:, c] - b_t[:, c]|| / ||x*[:, c]||."""
+    return float(np.max(np.linalg.norm(a - b, axis=1) / np.linalg.norm(xstar, axis=0)))
+
+
+def test_krhs_fp32_plan_takes_one_pass_and_keeps_the_anchored_bar():
+    """A well-conditioned FP32 plan with k = 12 (the (y, x_bar) form, FP64 anchor every
+    16 updates) skips the second pass: its anchored trajectory, whose FP64 anchor
+    products run on the one-pass FP64 factor, stays within the FP32 bar of the oracle
+    over 40 updates (anchors at 0, 16, 32)."""
+    S = synth.gaussian_system(1536, 1024, 8, k=12, seed=64, scale=1 / math.sqrt(1024))
+    plan, g, e = run(S, "f32", 0)
+    info = plan.setup_info()
+    say(f"case: k = 12 FP32 setup {info}")
+    assert info["qr_passes"] == 1
+    assert info["qr_defect"] <= 1e-10 / math.sqrt(192)
+    T = 40
+    d = dev_k(gpu_traj_k(plan, T), oracle_traj_k(S, T, g, e), S.xstar)
+    say(f"max column dev {d:.3e}")
+    assert d <= TOL32
+
+
+def test_ill_conditioned_krhs_fp32_plan_takes_two_passes():
+    S = mixed_rows(synth.gaussian_system(1536, 1024, 8, k=12, seed=65, scale=1 / math.sqrt(1024)), 5)
+    plan, g, e = run(S, "f32", 0)
+    info = plan.setup_info()
+    say(f"case: mixed-row k = 12 FP32 setup {info}")
+    assert info["qr_passes"] == 2
+    T = 40
+    d = dev_k(gpu_traj_k(plan, T), oracle_traj_k(S, T, g, e), S.xstar)
+    say(f"max column dev {d:.3e}")
+    assert d <= TOL32
+
+
+@pytest.mark.parametrize("anchor", [0, 4])
+def test_bf16_plan_one_pass_refines_to_fp64(anchor):
+    """bf16 refinement on a one-pass factor reaches the FP64 solution; with anchor
+    updates turned on after setup (the FP64 pass-A factor copy is packed then)."""
+    apc = _apc()
+    torch = _torch()
+    S = synth.shifted_square(1024, 8, k=6, shift=3.0, seed=66)
+    A = torch.from_numpy(S.A).cuda()
+    b = torch.from_numpy(np.ascontiguousarray(S.B)).cuda()
+    plan = apc.Plan(A, b, S.off, "bf16_ir", anchor_every=anchor)
+    info = plan.setup_info()
+    x, it, rr, st = plan.solve(1e-11, 4000)
+    ref = np.linalg.solve(S.A, S.B)
+    err = float(np.max(np.linalg.norm(x.cpu().numpy() - ref, axis=0) / np.linalg.norm(ref, axis=0)))
+    say(f"case: bf16 anchor={anchor} setup {info}: status {st} updates {it} relres {rr:.2e} "
+        f"err {err:.2e}")
+    assert info["qr_passes"] == 1
+    assert st == apc.APC_OK and err <= 1e-9
