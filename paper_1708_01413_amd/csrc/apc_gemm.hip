@@ -265,6 +265,154 @@ __global__ __launch_bounds__(256) void k_tn_pack(const double* src, int64_t lds,
   }
 }
 
+// One destination row's eight consecutive entries (columns c0 .. c0 + 7,
+// c0 % 8 == 0) as whole 16-byte pieces of the fragment-packed layout: one
+// piece in bf16, two in FP32, four in FP64.
+template <typename TQ>
+__device__ inline void store_frag8(TQ* dst, int64_t r, int64_t c0, int64_t rows, const double (&v)[8]) {
+  constexpr int kE = 16 / sizeof(TQ);
+#pragma unroll
+  for (int h = 0; h < 8 / kE; ++h) {
+    TQ w[kE];
+#pragma unroll
+    for (int e = 0; e < kE; ++e) w[e] = cvt<TQ>(v[kE * h + e]);
+    u32x4 piece;
+    __builtin_memcpy(&piece, w, 16);
+    *reinterpret_cast<u32x4*>(dst + frag_index<TQ>(r, c0 + kE * h, rows)) = piece;
+  }
+}
+
+struct PackMultiArgs {
+  const double* src;
+  int64_t lds, srows, scols;
+  int32_t transpose;
+  int32_t vec;     // 16-byte source loads: src 16-byte aligned, lds and scols even
+  void* dq;        // fragment-packed, element type of the kernel
+  double* d64;     // fragment-packed FP64 (null: none)
+  float* r32;      // row-major FP32, non-transposed packs only (null: none)
+  int64_t ldr, r32rows, r32cols;
+  int64_t K, rows;  // packed outputs: rows x K, rows % 16 == 0, K % 128 == 0
+};
+
+// Fragment-packed copies of an FP64 matrix (or of its transpose) from a single
+// read of it: dq in the element type TQ, optionally d64 in FP64, and for a
+// non-transposed pack optionally the row-major FP32 copy r32[r * ldr + c] of
+// rows < r32rows and columns < r32cols (r32cols % 8 == 0).  Entries outside
+// the source are zero.  A workgroup takes units of 16 destination rows x 128
+// destination columns: the unit's source block goes to LDS through loads that
+// are contiguous across lanes (16 bytes each when vec, 8 otherwise; addresses
+// clamped into the source and the value selected afterwards, so that no load
+// sits behind a branch), then thread (r, o) writes entries (r, 8 o .. 8 o + 7)
+// of the unit as whole 16-byte pieces of every packed output, sixteen
+// consecutive threads filling 256 contiguous bytes.
+constexpr int kPkPitch = 128 + 2;  // LDS row pitch in doubles (16-byte aligned rows)
+template <typename TQ>
+__global__ __launch_bounds__(256) void k_tn_pack_multi(PackMultiArgs a) {
+  __shared__ __align__(16) double tile[16][kPkPitch];
+  const int t = threadIdx.x;
+  const int64_t ucols = a.K / 128;
+  const int64_t units = (a.rows / 16) * ucols;
+  for (int64_t u = blockIdx.x; u < units; u += gridDim.x) {
+    const int64_t R0 = (u / ucols) * 16, C0 = (u % ucols) * 128;
+    // tile[r][c] = dest (R0 + r, C0 + c) = src[R0 + r][C0 + c] or src[C0 + c][R0 + r].
+    if (!a.transpose) {
+      const int r = t >> 4;
+      const int64_t sr = R0 + r;
+      const bool rok = sr < a.srows;
+      const double* row = a.src + (rok ? sr : 0) * a.lds;
+      if (a.vec) {
+        f64x2 v[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int64_t c = C0 + 2 * ((t & 15) + 16 * e);
+          v[e] = *reinterpret_cast<const f64x2*>(row + (c < a.scols ? c : 0));
+        }
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int cl = 2 * ((t & 15) + 16 * e);
+          const bool ok = rok && C0 + cl < a.scols;
+          *reinterpret_cast<f64x2*>(&tile[r][cl]) = ok ? v[e] : f64x2{0.0, 0.0};
+        }
+      } else {
+        double v[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          const int64_t c = C0 + (t & 15) + 16 * e;
+          v[e] = row[c < a.scols ? c : 0];
+        }
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          const int cl = (t & 15) + 16 * e;
+          tile[r][cl] = rok && C0 + cl < a.scols ? v[e] : 0.0;
+        }
+      }
+    } else if (a.vec) {
+      // Thread: source rows C0 + t / 8 + 32 e, columns R0 + 2 (t % 8) + {0, 1}
+      // (scols even: both or neither inside).
+      const int64_t sc = R0 + 2 * (t & 7);
+      const bool cok = sc < a.scols;
+      f64x2 v[4];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int64_t sr = C0 + (t >> 3) + 32 * e;
+        v[e] = *reinterpret_cast<const f64x2*>(a.src + (sr < a.srows ? sr : 0) * a.lds + (cok ? sc : 0));
+      }
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int cl = (t >> 3) + 32 * e;
+        const bool ok = cok && C0 + cl < a.srows;
+        tile[2 * (t & 7)][cl] = ok ? v[e][0] : 0.0;
+        tile[2 * (t & 7) + 1][cl] = ok ? v[e][1] : 0.0;
+      }
+    } else {
+      // Thread: source rows C0 + t / 16 + 16 e, column R0 + t % 16.
+      const int64_t sc = R0 + (t & 15);
+      const bool cok = sc < a.scols;
+      double v[8];
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const int64_t sr = C0 + (t >> 4) + 16 * e;
+        v[e] = a.src[(sr < a.srows ? sr : 0) * a.lds + (cok ? sc : 0)];
+      }
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const int cl = (t >> 4) + 16 * e;
+        tile[t & 15][cl] = cok && C0 + cl < a.srows ? v[e] : 0.0;
+      }
+    }
+    __syncthreads();
+    {
+      const int r = t & 15, o = t >> 4;
+      double v[8];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const f64x2 w = *reinterpret_cast<const f64x2*>(&tile[r][8 * o + 2 * e]);
+        v[2 * e] = w[0];
+        v[2 * e + 1] = w[1];
+      }
+      store_frag8(static_cast<TQ*>(a.dq), R0 + r, C0 + 8 * o, a.rows, v);
+      if (a.d64) store_frag8(a.d64, R0 + r, C0 + 8 * o, a.rows, v);
+    }
+    if (a.r32) {
+      // Row-major: thread (r = t / 16, o = t % 16), 32 contiguous bytes each.
+      const int r = t >> 4, o = t & 15;
+      const int64_t gr = R0 + r, gc = C0 + 8 * o;
+      if (gr < a.r32rows && gc < a.r32cols) {
+        f32x4 lo, hi;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          lo[e] = static_cast<float>(tile[r][8 * o + e]);
+          hi[e] = static_cast<float>(tile[r][8 * o + 4 + e]);
+        }
+        float* d = a.r32 + gr * a.ldr + gc;
+        *reinterpret_cast<f32x4*>(d) = lo;
+        *reinterpret_cast<f32x4*>(d + 4) = hi;
+      }
+    }
+    __syncthreads();
+  }
+}
+
 unsigned grid_stride_blocks(int64_t total) {
   int64_t b = (total + 255) / 256;
   return static_cast<unsigned>(std::max<int64_t>(1, std::min<int64_t>(b, 8192)));
@@ -403,8 +551,39 @@ hipError_t launch_tn_pack(int type, const double* src, int64_t lds, int64_t srow
 hipError_t launch_tn_pack_frag(int type, const double* src, int64_t lds, int64_t srows,
                                int64_t scols, int32_t transpose, void* dst, int64_t K,
                                int64_t rows, hipStream_t s) {
+  return launch_tn_pack_frag_multi(type, src, lds, srows, scols, transpose, dst, K, rows, nullptr,
+                                   nullptr, 0, 0, 0, s);
+}
+
+hipError_t launch_tn_pack_frag_multi(int type, const double* src, int64_t lds, int64_t srows,
+                                     int64_t scols, int32_t transpose, void* dst, int64_t K,
+                                     int64_t rows, double* d64, float* r32, int64_t ldr,
+                                     int64_t r32rows, int64_t r32cols, hipStream_t s) {
   if (rows % 16 || K % tn_step_elems(type)) return hipErrorInvalidValue;
-  return tn_pack(type, src, lds, srows, scols, transpose, dst, K, rows, 1, s);
+  if ((d64 && type == kTnF64) || (r32 && (transpose || r32cols % 8 || ldr % 4 ||
+                                          reinterpret_cast<uintptr_t>(r32) % 16 ||
+                                          r32rows > rows || r32cols > K)))
+    return hipErrorInvalidValue;
+  if (K % 128 || srows < 1 || scols < 1) {
+    // Shapes the unit kernel does not take: the element-wise kernel, once per output.
+    if (r32) return hipErrorInvalidValue;
+    const hipError_t e = tn_pack(type, src, lds, srows, scols, transpose, dst, K, rows, 1, s);
+    if (e != hipSuccess || !d64) return e;
+    return tn_pack(kTnF64, src, lds, srows, scols, transpose, d64, K, rows, 1, s);
+  }
+  PackMultiArgs a{src, lds, srows, scols, transpose, 0, dst, d64, r32, ldr, r32rows, r32cols, K, rows};
+  a.vec = reinterpret_cast<uintptr_t>(src) % 16 == 0 && lds % 2 == 0 && scols % 2 == 0;
+  const int64_t units = (rows / 16) * (K / 128);
+  if (units < 1) return hipSuccess;
+  // Eight 256-thread workgroups per CU (16.6 KB of LDS each), grid-stride over the units.
+  const unsigned grid = static_cast<unsigned>(std::min<int64_t>(units, 256 * 8));
+  switch (type) {
+    case kTnF64: k_tn_pack_multi<double><<<grid, 256, 0, s>>>(a); break;
+    case kTnF32: k_tn_pack_multi<float><<<grid, 256, 0, s>>>(a); break;
+    case kTnBF16: k_tn_pack_multi<__bf16><<<grid, 256, 0, s>>>(a); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
 }
 
 }  // namespace apc

@@ -597,7 +597,8 @@ apc_status orthogonality_defect(apc_plan_s* P, const double* C, double* defect, 
   double* U = P->at<double>(L.Y);
   double* V = P->gemm ? P->at<double>(L.Apad) : P->x();
   double* out = P->at<double>(L.w);
-  if (!P->gemm && fused_cpt(L.ldc, 8) > 0) {
+  // (k-RHS FP32 / bf16 plans have single-pass tiles for their eigenvalue estimate.)
+  if (fused_cpt(L.ldc, 8) > 0 && (!P->gemm || P->ntiles_f > 0)) {
     double* part = P->at<double>(L.fpart);
     const int g = fused_cpt(L.ldc, 8) >= 16 ? 1 : 2;
     const int32_t remap = P->xcd_remap == 1 ? 1 : 0;
@@ -1431,31 +1432,34 @@ apc_status setup_impl(apc_plan_s* P, const Tiles& T) {
   P->bnorm = std::sqrt(scal[1]);
 
   if (P->gemm) {
-    // FP32 / bf16: the eigenvalue estimate through an FP32 copy of the factor
-    // in the slice the padded copy of A takes later (one single pass over
-    // 4 bytes per entry instead of two passes over 8).
-    if (P->ntiles_f > 0 && (std::isnan(P->gamma) || std::isnan(P->eta))) {
-      float* c32 = reinterpret_cast<float*>(P->ws + L.Apad);
-      HIP_TRY(launch_cast_f32(Ca, c32, N * ldc, st));
+    // Factor copies for the matrix cores (C and C^T in the iteration's
+    // precision, C^T in FP64, C in FP64 for the anchor updates and the FP32
+    // adjoint), the padded FP64 copy of A, zeroed operands.  Every one of them
+    // is a streamed operand of the contraction kernel and is stored in its
+    // fragment-packed layout; the copies of one orientation are written from a
+    // single read of the FP64 factor.  A bf16 plan without anchors packs the
+    // FP64 C when apc_set_anchor turns them on.
+    const int64_t Np = L.Np, np = L.np;
+    // FP32 / bf16: the eigenvalue estimate runs through a row-major FP32 copy
+    // of the factor, written by the same read into the slice the padded copy
+    // of A takes afterwards (one single pass over 4 bytes per entry per step
+    // instead of two passes over 8).
+    const bool est = P->ntiles_f > 0 && (std::isnan(P->gamma) || std::isnan(P->eta));
+    float* c32 = est ? reinterpret_cast<float*>(P->ws + L.Apad) : nullptr;
+    const bool pack64 = P->tq != kTnF64 && (P->anchor_every > 0 || !P->bf16) && !P->c64p_ready;
+    HIP_TRY(launch_tn_pack_frag_multi(P->tq, Ca, ldc, N, n, 0, P->ws + L.Cq, np, Np,
+                                      pack64 ? P->at<double>(L.C64p) : nullptr, c32, ldc, N, ldc,
+                                      st));
+    if (pack64) P->c64p_ready = true;
+    HIP_TRY(launch_tn_pack_frag_multi(P->tq, Ca, ldc, N, n, 1, P->ws + L.CqT, Np, np,
+                                      P->tq != kTnF64 ? P->at<double>(L.C64T) : nullptr, nullptr,
+                                      0, 0, 0, st));
+    if (est) {
       double lo = 0, hi = 0;
       ST_TRY(lanczos(P, NormalOp{c32, true, 1.0 / m}, 1.0, &lo, &hi, &P->lanczos_steps));
       P->mu_min = lo;
       P->mu_max = hi;
       optimum(lo, hi, &P->gamma, &P->eta, &P->rho);
-    }
-    // Factor copies for the matrix cores (C and C^T in the iteration's
-    // precision, C^T in FP64), the padded FP64 copy of A, zeroed operands.
-    const int64_t Np = L.Np, np = L.np;
-    // Every one of them is a streamed operand of the contraction kernel and
-    // is stored in its fragment-packed layout.
-    HIP_TRY(launch_tn_pack_frag(P->tq, Ca, ldc, N, n, 0, P->ws + L.Cq, np, Np, st));
-    HIP_TRY(launch_tn_pack_frag(P->tq, Ca, ldc, N, n, 1, P->ws + L.CqT, Np, np, st));
-    if (P->tq != kTnF64) {
-      HIP_TRY(launch_tn_pack_frag(kTnF64, Ca, ldc, N, n, 1, P->ws + L.C64T, Np, np, st));
-      // The FP64 factor in pass-A orientation serves the anchor updates and the
-      // FP32 adjoint only; a bf16 plan without anchors packs it when
-      // apc_set_anchor turns them on.
-      if (P->anchor_every > 0 || !P->bf16) ST_TRY(pack_c64p(P));
     }
     HIP_TRY(launch_tn_pack_frag(kTnF64, P->A, P->lda, N, n, 0, P->ws + L.Apad, np, Np, st));
     const int64_t sq = P->tq == kTnF64 ? 8 : P->tq == kTnF32 ? 4 : 2;
