@@ -742,9 +742,16 @@ constexpr int kGK = 32;
 constexpr int kGS = kGT + 16;
 __global__ __launch_bounds__(512) void k_gram_lds(const double* C, int64_t ldc,
                                                  const int64_t* off, const int32_t* tiles,
-                                                 int32_t ntiles, const int64_t* goff, double* G) {
-  const int q = xcd_contiguous(static_cast<int>(blockIdx.x), ntiles);
-  if (q >= ntiles) return;
+                                                 int32_t ntiles, const int64_t* goff, double* G,
+                                                 int32_t nsplit, int64_t klen, double* part,
+                                                 int64_t pstride) {
+  // Work item u = split * ntiles + tile: consecutive items (one XCD's share)
+  // are tiles of the same blocks over the same K range, which share rows.
+  const int total = ntiles * nsplit;
+  const int item = xcd_contiguous(static_cast<int>(blockIdx.x), total);
+  if (item >= total) return;
+  const int split = item / ntiles;
+  const int q = item - split * ntiles;
   const int blk = tiles[3 * q + 0];
   const int ta = tiles[3 * q + 1];
   const int tb = tiles[3 * q + 2];
@@ -778,11 +785,12 @@ __global__ __launch_bounds__(512) void k_gram_lds(const double* C, int64_t ldc,
     }
   };
   f64x4 acc[2] = {f64x4{}, f64x4{}};
-  const int64_t kend = ldc;
-  load_chunk(0);
+  const int64_t k0 = static_cast<int64_t>(split) * klen;
+  const int64_t kend = min(ldc, k0 + klen);  // > k0: the host sizes the splits
+  load_chunk(k0);
   store_chunk();
   __syncthreads();
-  for (int64_t kc = 0; kc < kend; kc += kGK) {
+  for (int64_t kc = k0; kc < kend; kc += kGK) {
     const bool more = kc + kGK < kend;
     load_chunk(more ? kc + kGK : kc);  // the last chunk reloads itself, unused
 #pragma unroll
@@ -798,8 +806,9 @@ __global__ __launch_bounds__(512) void k_gram_lds(const double* C, int64_t ldc,
     if (more) store_chunk();
     __syncthreads();
   }
-  // acc[u][q] = G[64 ta + 16 wr + g + 4 q][64 tb + 32 wc + 16 u + li].
-  double* Gb = G + goff[blk];
+  // acc[u][q] = G[64 ta + 16 wr + g + 4 q][64 tb + 32 wc + 16 u + li] (this
+  // split's share; split s > 0 writes the same layout at part + (s - 1) pstride).
+  double* Gb = (split == 0 ? G : part + (split - 1) * pstride) + goff[blk];
 #pragma unroll
   for (int u = 0; u < 2; ++u)
 #pragma unroll
@@ -813,15 +822,39 @@ __global__ __launch_bounds__(512) void k_gram_lds(const double* C, int64_t ldc,
     }
 }
 
+// G += part[0] + part[1] + ... (split s > 0 at part + (s - 1) pstride), in
+// split order, so the sum does not depend on scheduling.
+__global__ __launch_bounds__(256) void k_gram_split_sum(double* G, const double* part,
+                                                       int64_t pstride, int32_t nsplit) {
+  for (int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; e < pstride;
+       e += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    double v = G[e];
+    for (int sp = 1; sp < nsplit; ++sp) v += part[(sp - 1) * pstride + e];
+    G[e] = v;
+  }
+}
+
 }  // namespace
 
 hipError_t launch_gram_lds(const double* C, int64_t ldc, const int64_t* off,
                            const int32_t* tiles, int32_t ntiles, const int64_t* goff, double* G,
-                           hipStream_t s) {
+                           int32_t nsplit, double* part, int64_t pstride, hipStream_t s) {
   if (ntiles <= 0) return hipSuccess;
-  if (ldc % kGK != 0) return hipErrorInvalidValue;
-  const unsigned grid = static_cast<unsigned>((ntiles + kXcds - 1) / kXcds * kXcds);
-  k_gram_lds<<<grid, 512, 0, s>>>(C, ldc, off, tiles, ntiles, goff, G);
+  if (ldc % kGK != 0 || nsplit < 1 || (nsplit > 1 && !part)) return hipErrorInvalidValue;
+  // Every split non-empty: klen a whole number of chunks, (nsplit - 1) klen < ldc
+  // (fewer splits where the chunks do not divide so).
+  int64_t klen = 0;
+  for (;; --nsplit) {
+    klen = (ldc / kGK + nsplit - 1) / nsplit * kGK;
+    if (nsplit == 1 || (nsplit - 1) * klen < ldc) break;
+  }
+  const int64_t total = static_cast<int64_t>(ntiles) * nsplit;
+  if (total > std::numeric_limits<int32_t>::max() / 2) return hipErrorInvalidValue;
+  const unsigned grid = static_cast<unsigned>((total + kXcds - 1) / kXcds * kXcds);
+  k_gram_lds<<<grid, 512, 0, s>>>(C, ldc, off, tiles, ntiles, goff, G, nsplit, klen, part, pstride);
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess || nsplit == 1) return e;
+  k_gram_split_sum<<<grid_stride_blocks(pstride), 256, 0, s>>>(G, part, pstride, nsplit);
   return hipGetLastError();
 }
 

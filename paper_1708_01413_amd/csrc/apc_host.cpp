@@ -1357,6 +1357,17 @@ apc_status setup_impl(apc_plan_s* P, const Tiles& T) {
   // When A's rows are already the factor's padded rows (n a multiple of 64,
   // lda = n, 16-byte aligned), the first pass reads A in place and only b is
   // copied (the matrix-core kernels never read past a block's rows).
+  // The Gram product's K range is split so that the launch has about 2048
+  // workgroups (four per CU fit at once) when the blocks alone give few
+  // tiles, each range keeping at least 1024 columns (shorter rows gain
+  // nothing); the partial Grams go to the factor slice the pass writes next,
+  // which is free until the triangular product.
+  int64_t gsize = 0;
+  for (int i = 0; i < m; ++i) gsize += (P->off[i + 1] - P->off[i]) * (P->off[i + 1] - P->off[i]);
+  int32_t gsplit = static_cast<int32_t>((2048 + L.ntiles_g - 1) / std::max(1, L.ntiles_g));
+  if (const char* e = std::getenv("APC_GRAM_SPLIT")) gsplit = std::atoi(e);
+  gsplit = static_cast<int32_t>(std::max<int64_t>(
+      1, std::min<int64_t>({gsplit, 8, ldc / 1024, 1 + N * ldc / std::max<int64_t>(1, gsize)})));
   const bool in_place = mfma && n == ldc && P->lda == ldc &&
                         reinterpret_cast<uintptr_t>(P->A) % 16 == 0;
   HIP_TRY(launch_copy_pad(P->A, P->lda, P->B, P->ldb, N, n, in_place ? nullptr : Ca, ldc, ca,
@@ -1387,7 +1398,7 @@ apc_status setup_impl(apc_plan_s* P, const Tiles& T) {
     double* cd = pass == 0 ? cb : ca;
     if (mfma)
       HIP_TRY(launch_gram_lds(src, ldc, P->doff(), P->at<int32_t>(L.tiles_g), L.ntiles_g,
-                              P->at<int64_t>(L.goff), P->at<double>(L.G), st));
+                              P->at<int64_t>(L.goff), P->at<double>(L.G), gsplit, dst, gsize, st));
     else
       HIP_TRY(launch_gram(src, ldc, P->doff(), P->at<int32_t>(L.tiles_g), L.ntiles_g,
                           P->at<int64_t>(L.goff), P->at<double>(L.G), st));

@@ -639,10 +639,13 @@ hipError_t launch_gram(const double* C, int64_t ldc, const int64_t* off, const i
 hipError_t launch_chol_inv(const int64_t* off, const int64_t* goff, int32_t m, int64_t pmax,
                            double* G, double* Linv, int* flags, double rank_tol, hipStream_t s);
 // G_i = C_i C_i^T on the FP64 matrix cores, both operands staged in LDS
-// (512 threads per 64 x 64 tile of `tiles`; ldc a multiple of 32).
+// (512 threads per 64 x 64 tile of `tiles` and K range; ldc a multiple of 32).
+// nsplit > 1 splits K into that many ranges: ranges 1.. write partial Grams
+// into part (pstride = the total size of G, nsplit - 1 copies), then a second
+// launch adds them to G in range order.
 hipError_t launch_gram_lds(const double* C, int64_t ldc, const int64_t* off,
                            const int32_t* tiles, int32_t ntiles, const int64_t* goff, double* G,
-                           hipStream_t s);
+                           int32_t nsplit, double* part, int64_t pstride, hipStream_t s);
 // Out_i = Linv_i In_i on the FP64 matrix cores as 128 x 128 tiles with both
 // operands staged in LDS (ldc a multiple of 64, pmax the largest block's rows,
 // In and Out distinct).  out32 (optional, same layout as Out): the result also
