@@ -1205,7 +1205,7 @@ __global__ void k_copy_t(const double* src, int64_t lds, double* dst, int64_t ld
 
 // One Lanczos step after the operator: twice classical Gram-Schmidt of w
 // against the basis rows V[0..j], then beta_j = ||w||, V[j + 1] = w / beta_j,
-// in four launches over column slabs of kLzSlab = 64 columns, one workgroup
+// in three launches over column slabs of kLzSlab = 64 columns, one workgroup
 // of kLzWaves waves per slab.  Lane l of every wave owns the slab's column l;
 // the waves split the rows (or the partial-row tiles) r = wv, wv + 8, ...
 // Every step local to a column -- the operator's sum over partial rows,
@@ -1214,23 +1214,47 @@ __global__ void k_copy_t(const double* src, int64_t lds, double* dst, int64_t ld
 // workgroup of the next launch sums in slab order (so nothing depends on
 // scheduling).  Rows go eight per wave at a time: their loads are issued
 // together and their eight wave sums reduced at once (row_sums), so a step
-// costs a few memory round trips instead of one per row.  Columns past ldc
-// contribute zero.
+// costs a few memory round trips instead of one per row; each thread's
+// entries of the first 64 basis rows are loaded once per launch, before the
+// loads they do not depend on have returned.  Columns past ldc contribute
+// zero.  The norm after the second pass is taken by Pythagoras: with V's rows
+// orthonormal, ||w1 - V^T h2||^2 = ||w1||^2 - ||h2||^2 for h2 = V w1 (to
+// rounding, h2 being of the order of the first pass's rounding), so the
+// second pass and the normalisation share a launch.
 constexpr int kLzWaves = 8;
 constexpr int kLzRows = 8 * kLzWaves;  // basis rows one pass over the workgroup covers
 
+// v[k] = V[r][c] for the first kLzRows rows this wave takes (r = wv + 8 k,
+// clamped to j; rows past j are never used).
+__device__ inline void lz_first_rows(const LanczosArgs& a, int64_t c, bool ok, double (&v)[8]) {
+  const int wv = threadIdx.x >> 6;
+  const int64_t cc = ok ? c : 0;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    const int r = wv + kLzWaves * k;
+    v[k] = a.V[static_cast<int64_t>(r <= a.j ? r : a.j) * a.ldc + cc];
+  }
+}
+
 // hp[blockIdx.x * hstride + r] = sum over the slab's columns of V[r][c] x, r <= j.
-__device__ inline void lz_dots(const LanczosArgs& a, int64_t c, bool ok, double x, double* hp) {
+// v0: the thread's entries of the first kLzRows rows (lz_first_rows).
+__device__ inline void lz_dots(const LanczosArgs& a, int64_t c, bool ok, double x, double* hp,
+                               const double (&v0)[8]) {
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int64_t cc = ok ? c : 0;
   for (int r0 = 0; r0 <= a.j; r0 += kLzRows) {
     double p[8], t[8];
-    // Clamped addresses and a select after the load keep the eight loads
-    // free of branches, so they are all in flight at once.
+    if (r0 == 0) {
 #pragma unroll
-    for (int k = 0; k < 8; ++k) {
-      const int r = r0 + wv + kLzWaves * k;
-      p[k] = a.V[static_cast<int64_t>(r <= a.j ? r : a.j) * a.ldc + cc];
+      for (int k = 0; k < 8; ++k) p[k] = v0[k];
+    } else {
+      // Clamped addresses and a select after the load keep the eight loads
+      // free of branches, so they are all in flight at once.
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        const int r = r0 + wv + kLzWaves * k;
+        p[k] = a.V[static_cast<int64_t>(r <= a.j ? r : a.j) * a.ldc + cc];
+      }
     }
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
@@ -1281,18 +1305,23 @@ __device__ inline double lz_tree(const double (*acc)[64], int lane) {
 
 // w - sum_{r <= j} hs[r] V[r][c]: each wave sums its rows (eight loads in
 // flight), the eight partial sums meet in LDS (acc, 8 x 64).  Returns the new
-// w of the lane's column in every wave.
+// w of the lane's column in every wave.  v0 as in lz_dots.
 __device__ inline double lz_subtract(const LanczosArgs& a, int64_t c, bool ok, double w,
-                                     const double* hs, double (*acc)[64]) {
+                                     const double* hs, double (*acc)[64], const double (&v0)[8]) {
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int64_t cc = ok ? c : 0;
   double s = 0.0;
   for (int r0 = 0; r0 <= a.j; r0 += kLzRows) {
     double v[8];
+    if (r0 == 0) {
 #pragma unroll
-    for (int k = 0; k < 8; ++k) {
-      const int r = r0 + wv + kLzWaves * k;
-      v[k] = a.V[static_cast<int64_t>(r <= a.j ? r : a.j) * a.ldc + cc];
+      for (int k = 0; k < 8; ++k) v[k] = v0[k];
+    } else {
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        const int r = r0 + wv + kLzWaves * k;
+        v[k] = a.V[static_cast<int64_t>(r <= a.j ? r : a.j) * a.ldc + cc];
+      }
     }
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
@@ -1304,6 +1333,14 @@ __device__ inline double lz_subtract(const LanczosArgs& a, int64_t c, bool ok, d
   acc[wv][lane] = s;
   __syncthreads();
   return w - lz_tree(acc, lane);
+}
+
+// Sum of nslab per-slab values in slab order (wave 0 of the workgroup; the
+// same order in every workgroup).
+__device__ inline double lz_slab_sum(const double* v, int32_t nslab, int lane) {
+  double t = 0.0;
+  for (int sl = lane; sl < nslab; sl += 64) t += v[sl];
+  return wave_sum_dpp(t);
 }
 
 // Launch 1: w (the operator's output, or first its sum scale * sum_t part[t]
@@ -1318,6 +1355,8 @@ __global__ __launch_bounds__(64 * kLzWaves) void k_lz_first(LanczosArgs a, const
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int64_t c = static_cast<int64_t>(blockIdx.x) * kLzSlab + lane;
   const bool ok = c < a.ldc;
+  double v0[8];
+  lz_first_rows(a, c, ok, v0);
   double w = 0.0;
   if (part) {
     double s = 0.0;
@@ -1345,69 +1384,73 @@ __global__ __launch_bounds__(64 * kLzWaves) void k_lz_first(LanczosArgs a, const
   } else if (ok) {
     w = a.w[c];
   }
-  lz_dots(a, c, ok, w, a.hp);
+  lz_dots(a, c, ok, w, a.hp, v0);
 }
 
-// Launch 2: w -= V^T h (first pass), then the second pass's dot partials.
+// Launch 2: w1 = w - V^T h (first pass), the second pass's dot partials and
+// the slab's part of ||w1||^2.
 __global__ __launch_bounds__(64 * kLzWaves) void k_lz_second(LanczosArgs a) {
   __shared__ double hs[kLzMaxRows];
   __shared__ double acc[kLzWaves][64];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int64_t c = static_cast<int64_t>(blockIdx.x) * kLzSlab + lane;
+  const bool ok = c < a.ldc;
+  double v0[8];
+  lz_first_rows(a, c, ok, v0);
+  const double wc = ok ? a.w[c] : 0.0;
   lz_gather(a, a.hp, hs);
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int64_t c = static_cast<int64_t>(blockIdx.x) * kLzSlab + lane;
-  const bool ok = c < a.ldc;
-  const double w = lz_subtract(a, c, ok, ok ? a.w[c] : 0.0, hs, acc);
-  lz_dots(a, c, ok, w, a.hp + static_cast<int64_t>(a.nslab) * a.hstride);
-  __syncthreads();  // every wave has read w[c] before wave 0 replaces it
-  if (ok && wv == 0) a.w[c] = w;
-}
-
-// Launch 3: w -= V^T h (second pass) and the slab's part of ||w||^2.
-__global__ __launch_bounds__(64 * kLzWaves) void k_lz_third(LanczosArgs a) {
-  __shared__ double hs[kLzMaxRows];
-  __shared__ double acc[kLzWaves][64];
-  lz_gather(a, a.hp + static_cast<int64_t>(a.nslab) * a.hstride, hs);
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int64_t c = static_cast<int64_t>(blockIdx.x) * kLzSlab + lane;
-  const bool ok = c < a.ldc;
-  const double w = lz_subtract(a, c, ok, ok ? a.w[c] : 0.0, hs, acc);
-  __syncthreads();  // every wave has read w[c] before wave 0 replaces it
+  const double w = lz_subtract(a, c, ok, wc, hs, acc, v0);
+  lz_dots(a, c, ok, w, a.hp + static_cast<int64_t>(a.nslab) * a.hstride, v0);
   if (wv == 0) {
     if (ok) a.w[c] = w;
-    const double t = wave_sum_dpp(w * w);
+    const double t = wave_sum_dpp(ok ? w * w : 0.0);
     if (lane == 0) a.np[blockIdx.x] = t;
   }
 }
 
-// Launch 4: beta_j = ||w|| (every workgroup sums the slab norms in order),
-// alpha_j = both passes' coefficients of V[j] (workgroup 0), V[j + 1] =
-// w / beta_j and its FP32 rounding when vnext32 is non-null.  One wave.
-__global__ __launch_bounds__(64) void k_lz_normalize(LanczosArgs a) {
-  const int lane = threadIdx.x;
-  double t = 0.0;
-  for (int sl = lane; sl < a.nslab; sl += 64) t += a.np[sl];
-  const double b = sqrt(wave_sum_dpp(t));
-  if (blockIdx.x == 0) {
-    double a1 = 0.0, a2 = 0.0;
-    for (int sl = lane; sl < a.nslab; sl += 64) {
-      a1 += a.hp[static_cast<int64_t>(sl) * a.hstride + a.j];
-      a2 += a.hp[static_cast<int64_t>(a.nslab + sl) * a.hstride + a.j];
-    }
-    a1 = wave_sum_dpp(a1);
-    a2 = wave_sum_dpp(a2);
-    if (lane == 0) {
-      a.beta[a.j] = b;
-      a.alpha[a.j] = a1 + a2;
-      if (a.host_ab) {
-        a.host_ab[a.j] = a1 + a2;
-        a.host_ab[a.hstride + a.j] = b;
+// Launch 3: w2 = w1 - V^T h2 (second pass), beta_j = sqrt(||w1||^2 - ||h2||^2)
+// (every workgroup sums the slab norms and h2 in the same order), alpha_j =
+// both passes' coefficients of V[j] (workgroup 0), V[j + 1] = w2 / beta_j and
+// its FP32 rounding when vnext32 is non-null.
+__global__ __launch_bounds__(64 * kLzWaves) void k_lz_third(LanczosArgs a) {
+  __shared__ double hs[kLzMaxRows];
+  __shared__ double acc[kLzWaves][64];
+  __shared__ double beta_sh;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int64_t c = static_cast<int64_t>(blockIdx.x) * kLzSlab + lane;
+  const bool ok = c < a.ldc;
+  double v0[8];
+  lz_first_rows(a, c, ok, v0);
+  const double wc = ok ? a.w[c] : 0.0;
+  lz_gather(a, a.hp + static_cast<int64_t>(a.nslab) * a.hstride, hs);
+  if (wv == 0) {
+    double h2 = 0.0;
+    for (int r = lane; r <= a.j; r += 64) h2 = fma(hs[r], hs[r], h2);
+    h2 = wave_sum_dpp(h2);
+    const double n1 = lz_slab_sum(a.np, a.nslab, lane);
+    const double b = sqrt(fmax(n1 - h2, 0.0));
+    if (lane == 0) beta_sh = b;
+    if (blockIdx.x == 0) {
+      double a1 = 0.0;
+      for (int sl = lane; sl < a.nslab; sl += 64) a1 += a.hp[static_cast<int64_t>(sl) * a.hstride + a.j];
+      a1 = wave_sum_dpp(a1);
+      if (lane == 0) {
+        const double al = a1 + hs[a.j];
+        a.beta[a.j] = b;
+        a.alpha[a.j] = al;
+        if (a.host_ab) {
+          a.host_ab[a.j] = al;
+          a.host_ab[a.hstride + a.j] = b;
+        }
       }
     }
   }
+  // (lz_subtract's barrier also publishes beta_sh.)
+  const double w = lz_subtract(a, c, ok, wc, hs, acc, v0);
+  const double b = beta_sh;
   const double inv = b > 0.0 ? 1.0 / b : 0.0;
-  const int64_t c = static_cast<int64_t>(blockIdx.x) * kLzSlab + lane;
-  if (c < a.ldc) {
-    const double v = a.w[c] * inv;
+  if (wv == 0 && ok) {
+    const double v = w * inv;
     a.vnext[c] = v;
     if (a.vnext32) a.vnext32[c] = static_cast<float>(v);
   }
@@ -1828,7 +1871,6 @@ hipError_t launch_lanczos_step(const LanczosArgs& a, const void* part, bool part
                        ldp, ntiles, scale);
   hipLaunchKernelGGL(k_lz_second, grid, block, 0, s, a);
   hipLaunchKernelGGL(k_lz_third, grid, block, 0, s, a);
-  hipLaunchKernelGGL(k_lz_normalize, grid, dim3(64), 0, s, a);
   return hipGetLastError();
 }
 
