@@ -157,6 +157,27 @@ __global__ __launch_bounds__(256) void k_tn_update(TnUpdateArgs a) {
     update_elem<P, TQ>(a, e);
 }
 
+// The same four entries per thread (every row length and stride a multiple of 4).
+template <typename P, typename TQ>
+__global__ __launch_bounds__(256) void k_tn_update4(TnUpdateArgs a) {
+  const int64_t total = static_cast<int64_t>(a.kp) * a.n / 4;
+  for (int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; e < total;
+       e += static_cast<int64_t>(gridDim.x) * blockDim.x)
+    update4<P, TQ>(a, 4 * e);
+}
+
+template <typename P, typename TQ>
+__global__ __launch_bounds__(256) void k_tn_sum_cast4(const P* part, int32_t nsplit, int32_t kp,
+                                                      int64_t ldp, int64_t rows, TQ* out, int64_t ldo) {
+  const int64_t total = static_cast<int64_t>(kp) * rows / 4;
+  const int64_t stride = static_cast<int64_t>(kp) * ldp;
+  for (int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; e < total;
+       e += static_cast<int64_t>(gridDim.x) * blockDim.x)
+    sum_cast4(part, nsplit, ldp, rows, stride, out, ldo, 4 * e);
+}
+
+inline bool quad_ok(const void* p) { return reinterpret_cast<uintptr_t>(p) % 16 == 0; }
+
 // y_ref = (1 - gamma) y + gamma x_bar (the vector the next update multiplies), FP64.
 __global__ __launch_bounds__(256) void k_tn_anchor_vec(const double* y, const double* xb, int64_t count,
                                                        double gamma, double* yref) {
@@ -437,44 +458,54 @@ int tn_step_elems(int type) { return type == kTnF64 ? 32 : type == kTnF32 ? 64 :
 
 hipError_t launch_tn_sum_cast(int type, const void* part, int32_t nsplit, int32_t kp, int64_t ldp,
                               int64_t rows, void* out, int64_t ldo, hipStream_t s) {
-  const unsigned g = grid_stride_blocks(static_cast<int64_t>(kp) * rows);
+  // Four entries per thread where every row starts 16-byte aligned.
+  const bool four = rows % 4 == 0 && ldp % 4 == 0 && ldo % 4 == 0 && quad_ok(part) &&
+                    reinterpret_cast<uintptr_t>(out) % 16 == 0;
+  const unsigned g = grid_stride_blocks(static_cast<int64_t>(kp) * rows / (four ? 4 : 1));
+#define APC_SUM_CAST(P, TQ)                                                                      \
+  do {                                                                                           \
+    if (four)                                                                                    \
+      APC_LAUNCH((k_tn_sum_cast4<P, TQ>), dim3(g), dim3(256), 0, s, static_cast<const P*>(part), \
+                 nsplit, kp, ldp, rows, static_cast<TQ*>(out), ldo);                             \
+    else                                                                                         \
+      APC_LAUNCH((k_tn_sum_cast<P, TQ>), dim3(g), dim3(256), 0, s, static_cast<const P*>(part),  \
+                 nsplit, kp, ldp, rows, static_cast<TQ*>(out), ldo);                             \
+  } while (0)
   switch (type) {
-    case kTnF64:
-      APC_LAUNCH((k_tn_sum_cast<double, double>), dim3(g), dim3(256), 0, s,
-                 static_cast<const double*>(part), nsplit, kp, ldp, rows, static_cast<double*>(out),
-                 ldo);
-      break;
-    case kTnF32:
-      APC_LAUNCH((k_tn_sum_cast<float, float>), dim3(g), dim3(256), 0, s,
-                 static_cast<const float*>(part), nsplit, kp, ldp, rows, static_cast<float*>(out),
-                 ldo);
-      break;
-    case kTnBF16:
-      APC_LAUNCH((k_tn_sum_cast<float, __bf16>), dim3(g), dim3(256), 0, s,
-                 static_cast<const float*>(part), nsplit, kp, ldp, rows, static_cast<__bf16*>(out),
-                 ldo);
-      break;
+    case kTnF64: APC_SUM_CAST(double, double); break;
+    case kTnF32: APC_SUM_CAST(float, float); break;
+    case kTnBF16: APC_SUM_CAST(float, __bf16); break;
     default: return hipErrorInvalidValue;
   }
+#undef APC_SUM_CAST
   return hipGetLastError();
 }
 
 hipError_t launch_tn_update(int type, int part_f64, const TnUpdateArgs& a, hipStream_t s) {
-  const unsigned g = grid_stride_blocks(static_cast<int64_t>(a.kp) * a.n);
+  const bool four = a.n % 4 == 0 && a.ldp % 4 == 0 && a.ldx % 4 == 0 && a.ldq % 4 == 0 &&
+                    quad_ok(a.part) && quad_ok(a.x0) && quad_ok(a.y) && quad_ok(a.xb) &&
+                    quad_ok(a.yq) && (!a.yref || (quad_ok(a.yref) && quad_ok(a.uref)));
+  const unsigned g = grid_stride_blocks(static_cast<int64_t>(a.kp) * a.n / (four ? 4 : 1));
+#define APC_UPDATE(P, TQ)                                                            \
+  do {                                                                               \
+    if (four) APC_LAUNCH((k_tn_update4<P, TQ>), dim3(g), dim3(256), 0, s, a);        \
+    else APC_LAUNCH((k_tn_update<P, TQ>), dim3(g), dim3(256), 0, s, a);              \
+  } while (0)
   if (part_f64) {
     switch (type) {
-      case kTnF64: APC_LAUNCH((k_tn_update<double, double>), dim3(g), dim3(256), 0, s, a); break;
-      case kTnF32: APC_LAUNCH((k_tn_update<double, float>), dim3(g), dim3(256), 0, s, a); break;
-      case kTnBF16: APC_LAUNCH((k_tn_update<double, __bf16>), dim3(g), dim3(256), 0, s, a); break;
+      case kTnF64: APC_UPDATE(double, double); break;
+      case kTnF32: APC_UPDATE(double, float); break;
+      case kTnBF16: APC_UPDATE(double, __bf16); break;
       default: return hipErrorInvalidValue;
     }
   } else {
     switch (type) {
-      case kTnF32: APC_LAUNCH((k_tn_update<float, float>), dim3(g), dim3(256), 0, s, a); break;
-      case kTnBF16: APC_LAUNCH((k_tn_update<float, __bf16>), dim3(g), dim3(256), 0, s, a); break;
+      case kTnF32: APC_UPDATE(float, float); break;
+      case kTnBF16: APC_UPDATE(float, __bf16); break;
       default: return hipErrorInvalidValue;
     }
   }
+#undef APC_UPDATE
   return hipGetLastError();
 }
 

@@ -796,7 +796,17 @@ apc_status gemm_residual(apc_plan_s* P, const double* X, double* R) {
 // plan's operands (the partial buffer is scratch here).  Shapes are cached per
 // (type, rows, K, kp) for the life of the process, so repeated plans of one
 // shape launch identically and give identical results.
-apc_status tn_tune(apc_plan_s* P, int type, TnArgs base, TnChoice* out) {
+// scrub (optional): a contraction launched before each timed one, so that the
+// candidate streams its operand the way an update does, right after the other
+// orientation's pass has streamed its own (in a loop over one operand alone,
+// part of it would still be in the 256 MB last-level cache).
+struct TnScrub {
+  TnArgs args;
+  int type;
+  TnChoice choice;
+};
+apc_status tn_tune(apc_plan_s* P, int type, TnArgs base, TnChoice* out,
+                   const TnScrub* scrub = nullptr) {
   struct Key {
     int type;
     int64_t rows, K;
@@ -878,9 +888,17 @@ apc_status tn_tune(apc_plan_s* P, int type, TnArgs base, TnChoice* out) {
   if (cand.empty()) cand.push_back(TnChoice{1, 1, 0.f, 1, 1});
   TnChoice best;
   {
-    hipEvent_t e0 = nullptr, e1 = nullptr;
-    HIP_TRY(hipEventCreate(&e0));
-    HIP_TRY(hipEventCreate(&e1));
+    // Each timed launch takes a pair of events recorded from its own dispatch.
+    constexpr int kReps = 3;
+    hipEvent_t ev[2 * kReps] = {};
+    for (hipEvent_t& e : ev) HIP_TRY(hipEventCreate(&e));
+    auto destroy = [&]() {
+      for (hipEvent_t& e : ev) (void)hipEventDestroy(e);
+    };
+    auto run_scrub = [&]() -> hipError_t {
+      if (!scrub) return hipSuccess;
+      return launch_tn(scrub->type, scrub->choice.rt, scrub->choice.pf, scrub->args, P->stream);
+    };
     float best_ms = 0.f;
     bool have = false;
     for (const TnChoice& c : cand) {
@@ -889,29 +907,38 @@ apc_status tn_tune(apc_plan_s* P, int type, TnArgs base, TnChoice* out) {
       a.nt = c.nt;
       a.waves = c.waves;
       a.klen = round_up((a.K + c.nsplit - 1) / c.nsplit, tn_step_elems(type));
-      hipError_t err = launch_tn(type, c.rt, c.pf, a, P->stream);  // warm-up
-      for (int r = 0; err == hipSuccess && r < 1; ++r) {
-        err = hipEventRecord(e0, P->stream);
-        for (int q = 0; err == hipSuccess && q < 3; ++q) err = launch_tn(type, c.rt, c.pf, a, P->stream);
-        if (err == hipSuccess) err = hipEventRecord(e1, P->stream);
+      hipError_t err = run_scrub();
+      if (err == hipSuccess) err = launch_tn(type, c.rt, c.pf, a, P->stream);  // warm-up
+      for (int r = 0; err == hipSuccess && r < kReps; ++r) {
+        err = run_scrub();
+        if (err != hipSuccess) break;
+        pending_timing() = TimedLaunch{ev[2 * r], ev[2 * r + 1]};
+        err = launch_tn(type, c.rt, c.pf, a, P->stream);
+        if (pending_timing().start) {  // not taken: record back to back (never expected)
+          pending_timing() = TimedLaunch{};
+          err = hipErrorInvalidValue;
+        }
       }
       float ms = 0.f;
-      if (err == hipSuccess) err = hipEventSynchronize(e1);
-      if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
+      if (err == hipSuccess) err = hipEventSynchronize(ev[2 * kReps - 1]);
+      for (int r = 0; err == hipSuccess && r < kReps; ++r) {
+        float t = 0.f;
+        err = hipEventElapsedTime(&t, ev[2 * r], ev[2 * r + 1]);
+        ms += t;
+      }
       if (err != hipSuccess) {
-        (void)hipEventDestroy(e0);
-        (void)hipEventDestroy(e1);
+        pending_timing() = TimedLaunch{};
+        destroy();
         return fail(APC_EHIP, "tuning launch failed: %s", hipGetErrorString(err));
       }
-      ms /= 3.f;
+      ms /= static_cast<float>(kReps);
       if (!have || ms < best_ms) {
         best = c;
         best_ms = ms;
         have = true;
       }
     }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
+    destroy();
     best.us = best_ms * 1e3f;
   }
   std::lock_guard<std::mutex> lk(mu);
@@ -1483,8 +1510,19 @@ apc_status setup_impl(apc_plan_s* P, const Tiles& T) {
       HIP_TRY(launch_fill_u32(P->at<unsigned>(L.cw), 2 * P->kp * N, 0u, st));
       HIP_TRY(launch_fill_u32(P->at<unsigned>(L.Xs), 2 * P->kp * np, 0u, st));
     }
-    ST_TRY(tn_tune(P, P->tq, pass_a_args(P), &P->tnA));
-    ST_TRY(tn_tune(P, P->tq, pass_b_args(P), &P->tnB));
+    // The two passes alternate in an update: each is tuned right after the
+    // other has streamed its operand (pass B first in a default shape).
+    {
+      TnChoice dflt;
+      dflt.rt = 1;
+      dflt.nsplit = 4;
+      TnScrub sb{tn_args(P->ws + L.CqT, L.Np, L.np, P->ws + L.Wq, L.Np, P->kp, L.Np, dflt, P->tq,
+                         P->ws + L.tnpart, L.np),
+                 P->tq, dflt};
+      ST_TRY(tn_tune(P, P->tq, pass_a_args(P), &P->tnA, &sb));
+      const TnScrub sa{pass_a_args(P), P->tq, P->tnA};
+      ST_TRY(tn_tune(P, P->tq, pass_b_args(P), &P->tnB, &sa));
+    }
     ST_TRY(tn_tune(P, kTnF64, x0_args(P), &P->tnX0));
     ST_TRY(tn_tune(P, kTnF64, resid_args(P, P->xbar()), &P->tnR));
   } else {

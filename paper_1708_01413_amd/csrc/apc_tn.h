@@ -244,6 +244,58 @@ __device__ inline void sum_cast_elem(const P* part, int32_t nsplit, int64_t ldp,
   out[c * ldo + r] = static_cast<TQ>(s);
 }
 
+// Four consecutive entries as one or two 16-byte accesses (8 bytes for bf16);
+// the address is a multiple of four entries, 16-byte aligned.
+template <typename T>
+__device__ inline void load4(const T* p, T (&v)[4]) {
+  if constexpr (sizeof(T) == 4) {
+    const f32x4 w = *reinterpret_cast<const f32x4*>(p);
+    __builtin_memcpy(v, &w, 16);
+  } else {
+    const f64x2 w0 = reinterpret_cast<const f64x2*>(p)[0];
+    const f64x2 w1 = reinterpret_cast<const f64x2*>(p)[1];
+    v[0] = w0[0];
+    v[1] = w0[1];
+    v[2] = w1[0];
+    v[3] = w1[1];
+  }
+}
+template <typename T>
+__device__ inline void store4(T* p, const T (&v)[4]) {
+  if constexpr (sizeof(T) == 2) {
+    uint2 w;
+    __builtin_memcpy(&w, v, 8);
+    *reinterpret_cast<uint2*>(p) = w;
+  } else if constexpr (sizeof(T) == 4) {
+    f32x4 w;
+    __builtin_memcpy(&w, v, 16);
+    *reinterpret_cast<f32x4*>(p) = w;
+  } else {
+    reinterpret_cast<f64x2*>(p)[0] = f64x2{v[0], v[1]};
+    reinterpret_cast<f64x2*>(p)[1] = f64x2{v[2], v[3]};
+  }
+}
+
+// sum_cast_elem for the four entries e .. e + 3 (e, rows, ldp and ldo
+// multiples of 4: the four share one right-hand side).
+template <typename P, typename TQ>
+__device__ inline void sum_cast4(const P* part, int32_t nsplit, int64_t ldp, int64_t rows,
+                                 int64_t stride, TQ* out, int64_t ldo, int64_t e) {
+  const int64_t c = e / rows, r = e - c * rows;
+  P s[4];
+  load4(part + c * ldp + r, s);
+  for (int sp = 1; sp < nsplit; ++sp) {
+    P t[4];
+    load4(part + sp * stride + c * ldp + r, t);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) s[q] += t[q];
+  }
+  TQ o[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) o[q] = static_cast<TQ>(s[q]);
+  store4(out + c * ldo + r, o);
+}
+
 // The (y, x_bar) update, its start, or an anchor update (see TnUpdateArgs)
 // for element e = c * n + j.
 template <typename P, typename TQ>
@@ -284,6 +336,79 @@ __device__ inline void update_elem(const TnUpdateArgs& a, int64_t e) {
   a.y[i] = y1;
   a.xb[i] = xn;
   yq[c * a.ldq + j] = cvt<TQ>(omg * y1 + g * xn - ref);
+}
+
+// update_elem for the four entries e .. e + 3 (e, n, ldp, ldx and ldq
+// multiples of 4), the same arithmetic per entry.
+template <typename P, typename TQ>
+__device__ inline void update4(const TnUpdateArgs& a, int64_t e) {
+  const int64_t stride = static_cast<int64_t>(a.kp) * a.ldp;
+  const P* part = static_cast<const P*>(a.part);
+  TQ* yq = static_cast<TQ*>(a.yq);
+  const double g = a.gamma, omg = 1.0 - a.gamma, eta = a.eta, ome = 1.0 - a.eta;
+  const int64_t c = e / a.n, j = e - c * a.n;
+  P zs[4];
+  load4(part + c * a.ldp + j, zs);
+  for (int sp = 1; sp < a.nsplit; ++sp) {
+    P t[4];
+    load4(part + sp * stride + c * a.ldp + j, t);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) zs[q] += t[q];
+  }
+  const int64_t i = c * a.ldx + j;
+  TQ qv[4];
+  if (a.mode == 1) {
+    double x0[4], zero[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      x0[q] = static_cast<double>(zs[q]) * a.inv_m;
+      qv[q] = cvt<TQ>(g * x0[q]);
+    }
+    store4(a.x0 + i, x0);
+    store4(a.xb + i, x0);
+    store4(a.y + i, zero);
+    if (a.yref) {
+      store4(a.yref + i, zero);
+      store4(a.uref + i, zero);
+    }
+    store4(yq + c * a.ldq + j, qv);
+    return;
+  }
+  double xb[4], x0[4], y[4] = {0.0, 0.0, 0.0, 0.0}, yr[4] = {0.0, 0.0, 0.0, 0.0},
+         ur[4] = {0.0, 0.0, 0.0, 0.0};
+  load4(a.xb + i, xb);
+  load4(a.x0 + i, x0);
+  if (a.mode == 2) {
+    load4(a.yref + i, yr);
+  } else {
+    load4(a.y + i, y);
+    if (a.yref) {
+      load4(a.yref + i, yr);
+      load4(a.uref + i, ur);
+    }
+  }
+  double yo[4], xo[4], uo[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const double y1 = a.mode == 2 ? yr[q] : omg * y[q] + g * xb[q];
+    double u = static_cast<double>(zs[q]) * a.inv_m;
+    double ref = 0.0;
+    if (a.mode == 2) {
+      uo[q] = u;
+      ref = y1;
+    } else if (a.yref) {
+      u += ur[q];
+      ref = yr[q];
+    }
+    const double xn = eta * (x0[q] + y1 - u) + ome * xb[q];
+    yo[q] = y1;
+    xo[q] = xn;
+    qv[q] = cvt<TQ>(omg * y1 + g * xn - ref);
+  }
+  if (a.mode == 2) store4(a.uref + i, uo);
+  store4(a.y + i, yo);
+  store4(a.xb + i, xo);
+  store4(yq + c * a.ldq + j, qv);
 }
 
 }  // namespace

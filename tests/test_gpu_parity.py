@@ -446,6 +446,7 @@ MULTI = [
     (1000, 800, 9, (40, 160), 20, 32),      # k padded to 32; 128-row tiles + tails
     (2048, 2048, 16, (64, 192), 64, 33),    # full 64-wide tile, square, shifted
     (512, 512, 4, (96, 160), 130, 35),      # k > 128: two 128-wide column groups
+    (301, 201, 5, (40, 80), 8, 42),         # odd n and lda: element-wise operand packing
 ]
 
 
