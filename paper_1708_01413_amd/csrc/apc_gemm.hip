@@ -309,14 +309,15 @@ struct PackMultiArgs {
   int32_t transpose;
   int32_t vec;     // 16-byte source loads: src 16-byte aligned, lds and scols even
   void* dq;        // fragment-packed, element type of the kernel
-  double* d64;     // fragment-packed FP64 (null: none)
+  void* d2;        // a second fragment-packed copy (null: none), FP64 or FP32
+  int32_t d2_f64;  // its element type: 1 FP64, 0 FP32
   float* r32;      // row-major FP32, non-transposed packs only (null: none)
   int64_t ldr, r32rows, r32cols;
   int64_t K, rows;  // packed outputs: rows x K, rows % 16 == 0, K % 128 == 0
 };
 
 // Fragment-packed copies of an FP64 matrix (or of its transpose) from a single
-// read of it: dq in the element type TQ, optionally d64 in FP64, and for a
+// read of it: dq in the element type TQ, optionally d2 in FP64 or FP32, and for a
 // non-transposed pack optionally the row-major FP32 copy r32[r * ldr + c] of
 // rows < r32rows and columns < r32cols (r32cols % 8 == 0).  Entries outside
 // the source are zero.  A workgroup takes units of 16 destination rows x 128
@@ -412,7 +413,10 @@ __global__ __launch_bounds__(256) void k_tn_pack_multi(PackMultiArgs a) {
         v[2 * e + 1] = w[1];
       }
       store_frag8(static_cast<TQ*>(a.dq), R0 + r, C0 + 8 * o, a.rows, v);
-      if (a.d64) store_frag8(a.d64, R0 + r, C0 + 8 * o, a.rows, v);
+      if (a.d2) {
+        if (a.d2_f64) store_frag8(static_cast<double*>(a.d2), R0 + r, C0 + 8 * o, a.rows, v);
+        else store_frag8(static_cast<float*>(a.d2), R0 + r, C0 + 8 * o, a.rows, v);
+      }
     }
     if (a.r32) {
       // Row-major: thread (r = t / 16, o = t % 16), 32 contiguous bytes each.
@@ -583,15 +587,17 @@ hipError_t launch_tn_pack_frag(int type, const double* src, int64_t lds, int64_t
                                int64_t scols, int32_t transpose, void* dst, int64_t K,
                                int64_t rows, hipStream_t s) {
   return launch_tn_pack_frag_multi(type, src, lds, srows, scols, transpose, dst, K, rows, nullptr,
-                                   nullptr, 0, 0, 0, s);
+                                   0, nullptr, 0, 0, 0, s);
 }
 
 hipError_t launch_tn_pack_frag_multi(int type, const double* src, int64_t lds, int64_t srows,
                                      int64_t scols, int32_t transpose, void* dst, int64_t K,
-                                     int64_t rows, double* d64, float* r32, int64_t ldr,
+                                     int64_t rows, void* d2, int type2, float* r32, int64_t ldr,
                                      int64_t r32rows, int64_t r32cols, hipStream_t s) {
   if (rows % 16 || K % tn_step_elems(type)) return hipErrorInvalidValue;
-  if ((d64 && type == kTnF64) || (r32 && (transpose || r32cols % 8 || ldr % 4 ||
+  if (d2 && (type2 == type || (type2 != kTnF64 && type2 != kTnF32) || K % tn_step_elems(type2)))
+    return hipErrorInvalidValue;
+  if ((r32 && (transpose || r32cols % 8 || ldr % 4 ||
                                           reinterpret_cast<uintptr_t>(r32) % 16 ||
                                           r32rows > rows || r32cols > K)))
     return hipErrorInvalidValue;
@@ -599,10 +605,11 @@ hipError_t launch_tn_pack_frag_multi(int type, const double* src, int64_t lds, i
     // Shapes the unit kernel does not take: the element-wise kernel, once per output.
     if (r32) return hipErrorInvalidValue;
     const hipError_t e = tn_pack(type, src, lds, srows, scols, transpose, dst, K, rows, 1, s);
-    if (e != hipSuccess || !d64) return e;
-    return tn_pack(kTnF64, src, lds, srows, scols, transpose, d64, K, rows, 1, s);
+    if (e != hipSuccess || !d2) return e;
+    return tn_pack(type2, src, lds, srows, scols, transpose, d2, K, rows, 1, s);
   }
-  PackMultiArgs a{src, lds, srows, scols, transpose, 0, dst, d64, r32, ldr, r32rows, r32cols, K, rows};
+  PackMultiArgs a{src, lds, srows, scols, transpose, 0, dst, d2, type2 == kTnF64 ? 1 : 0,
+                  r32, ldr, r32rows, r32cols, K, rows};
   a.vec = reinterpret_cast<uintptr_t>(src) % 16 == 0 && lds % 2 == 0 && scols % 2 == 0;
   const int64_t units = (rows / 16) * (K / 128);
   if (units < 1) return hipSuccess;

@@ -70,7 +70,7 @@ struct Layout {
   size_t tiles_f = 0, fpart = 0, v32 = 0;
   // k-RHS path: rows/K padding of its operands (N and n rounded up to kTnPad)
   int64_t Np = 0, np = 0;
-  size_t Cq, CqT, C64T, Apad, yq, Wq, tnpart, x0, ys, c64p, Xs, Rb, cw, Linv2, ssq;
+  size_t Cq, CqT, C64T, C32T, Apad, yq, Wq, tnpart, x0, ys, c64p, Xs, Rb, cw, Linv2, ssq;
   size_t C64p, yref, uref, W64;  // FP64 anchor of the FP32 / bf16 k-RHS iteration
   size_t C64a, C64b, C32, x, xbar, dv, w, ca, cb, Y, vtmp, V, h, alpha, beta, G, Linv, flags, scal, partial, tiles_a, tiles_g, tiles_t, doff, goff, total;
   size_t xch, rsync;  // single-launch k = 1 path: exchange buffer, epoch and time-out words
@@ -229,6 +229,8 @@ Layout make_layout(int64_t N, int64_t n, const int64_t* off, int32_t m, int32_t 
   L.Cq = take(gemm ? L.Np * L.np * sq : 0);
   L.CqT = take(gemm ? L.np * L.Np * sq : 0);
   L.C64T = take(gemm && prec != APC_F64 ? L.np * L.Np * d : 0);
+  // bf16: C^T in FP32 for the inner solves' starts (x_bar(0) = (1/m) C^T c).
+  L.C32T = take(bf ? L.np * L.Np * 4 : 0);
   L.Apad = take(gemm ? L.Np * L.np * d : 0);
   L.yq = take(gemm ? kp * L.np * sq : 0);
   L.Wq = take(gemm ? kp * L.Np * sq : 0);
@@ -413,6 +415,7 @@ struct apc_plan_s {
   TnChoice tnA, tnB, tnX0, tnR;        // launch shapes: pass A, pass B, x_bar(0), residual
   int anchor_every = 0;                // k-RHS FP32/bf16: every this many updates one in FP64
   bool c64p_ready = false;             // the FP64 factor in pass-A orientation is packed
+  bool c64t_ready = false;             // ... and in pass-B orientation (FP32 / bf16 plans)
   int64_t pmax = 1;                    // largest block
   int32_t passb_nt = 1;                // k = 1 pass B: non-temporal loads of C
   int32_t passb_rows = 1;              // k = 1 pass B: waves split the block's rows
@@ -662,10 +665,16 @@ TnArgs pass_b_args(const apc_plan_s* P) {
   return tn_args(P->ws + L.CqT, L.Np, L.np, P->ws + L.Wq, L.Np, P->kp, L.Np, P->tnB, P->tq,
                  P->ws + L.tnpart, L.np);
 }
+// The start's contraction x_bar(0) = (1/m) C^T c: FP64 (the FP32 and FP64
+// iterations), FP32 in the mixed-precision mode, whose inner solves only
+// need the start to a relative 1e-7 or so (the FP64 residual of the
+// refinement corrects the rest); its operand c then sits in the same slice
+// as FP32.
+int x0_type(const apc_plan_s* P) { return P->bf16 ? kTnF32 : kTnF64; }
 TnArgs x0_args(const apc_plan_s* P) {
   const Layout& L = P->L;
-  const void* Mt = P->tq == kTnF64 ? P->ws + L.CqT : P->ws + L.C64T;
-  return tn_args(Mt, L.Np, L.np, P->ws + L.c64p, L.Np, P->kp, L.Np, P->tnX0, kTnF64,
+  const void* Mt = P->tq == kTnF64 ? P->ws + L.CqT : P->bf16 ? P->ws + L.C32T : P->ws + L.C64T;
+  return tn_args(Mt, L.Np, L.np, P->ws + L.c64p, L.Np, P->kp, L.Np, P->tnX0, x0_type(P),
                  P->ws + L.tnpart, L.np);
 }
 TnArgs resid_args(const apc_plan_s* P, const double* X) {
@@ -677,11 +686,17 @@ TnArgs resid_args(const apc_plan_s* P, const double* X) {
 // The FP64 factor C (from the plan's FP64 slice) in the fragment-packed pass-A
 // layout (C64p), once.
 apc_status pack_c64p(apc_plan_s* P) {
-  if (P->c64p_ready || P->tq == kTnF64) return APC_OK;
+  if (P->tq == kTnF64) return APC_OK;
   const Layout& L = P->L;
-  HIP_TRY(launch_tn_pack_frag(kTnF64, P->C64(), L.ldc, P->N, P->n, 0, P->ws + L.C64p, L.np, L.Np,
-                              P->stream));
+  if (!P->c64p_ready)
+    HIP_TRY(launch_tn_pack_frag(kTnF64, P->C64(), L.ldc, P->N, P->n, 0, P->ws + L.C64p, L.np, L.Np,
+                                P->stream));
   P->c64p_ready = true;
+  // (A bf16 plan's anchor updates also need C^T in FP64.)
+  if (!P->c64t_ready)
+    HIP_TRY(launch_tn_pack_frag(kTnF64, P->C64(), L.ldc, P->N, P->n, 1, P->ws + L.C64T, L.Np, L.np,
+                                P->stream));
+  P->c64t_ready = true;
   return APC_OK;
 }
 
@@ -742,13 +757,15 @@ apc_status update_gemm(apc_plan_s* P, hipEvent_t* ev, int* kinds, int* nev) {
     HIP_TRY(launch_tn_sum_cast(kTnF64, part, P->tnR.nsplit, P->kp, L.Np, L.Np, P->ws + L.W64,
                                L.Np, P->stream));
     ST_TRY(timed_done(P, ev, e));
-    TnArgs b = tn_args(P->ws + L.C64T, L.Np, L.np, P->ws + L.W64, L.Np, P->kp, L.Np, P->tnX0,
-                       kTnF64, part, L.np);
+    // (A bf16 plan's start shape is an FP32 one: its anchors take the residual's.)
+    const TnChoice& cb = P->bf16 ? P->tnR : P->tnX0;
+    TnArgs b = tn_args(P->ws + L.C64T, L.Np, L.np, P->ws + L.W64, L.Np, P->kp, L.Np, cb, kTnF64,
+                       part, L.np);
     time_next(P, ev, kinds, &e, 1);
-    HIP_TRY(launch_tn(kTnF64, P->tnX0.rt, P->tnX0.pf, b, P->stream));
+    HIP_TRY(launch_tn(kTnF64, cb.rt, cb.pf, b, P->stream));
     ST_TRY(timed_done(P, ev, e));
     time_next(P, ev, kinds, &e, 2);
-    HIP_TRY(launch_tn_update(P->tq, 1, update_args(P, P->tnX0, 2), P->stream));
+    HIP_TRY(launch_tn_update(P->tq, 1, update_args(P, cb, 2), P->stream));
     ST_TRY(timed_done(P, ev, e));
   } else {
     time_next(P, ev, kinds, &e, 0);
@@ -775,10 +792,10 @@ apc_status update_gemm(apc_plan_s* P, hipEvent_t* ev, int* kinds, int* nev) {
 // x_bar(0) = (1/m) C^T c in FP64, y(0) = 0.
 apc_status start_gemm(apc_plan_s* P, const double* c_rhs) {
   const Layout& L = P->L;
-  HIP_TRY(launch_tn_pack(kTnF64, c_rhs, P->N, P->kp, P->N, 0, P->ws + L.c64p, L.Np, P->kp,
-                         P->stream));
-  HIP_TRY(launch_tn(kTnF64, P->tnX0.rt, P->tnX0.pf, x0_args(P), P->stream));
-  HIP_TRY(launch_tn_update(P->tq, 1, update_args(P, P->tnX0, 1), P->stream));
+  const int t = x0_type(P);
+  HIP_TRY(launch_tn_pack(t, c_rhs, P->N, P->kp, P->N, 0, P->ws + L.c64p, L.Np, P->kp, P->stream));
+  HIP_TRY(launch_tn(t, P->tnX0.rt, P->tnX0.pf, x0_args(P), P->stream));
+  HIP_TRY(launch_tn_update(P->tq, t == kTnF64, update_args(P, P->tnX0, 1), P->stream));
   P->since_start = 0;
   return APC_OK;
 }
@@ -1486,12 +1503,16 @@ apc_status setup_impl(apc_plan_s* P, const Tiles& T) {
     float* c32 = est ? reinterpret_cast<float*>(P->ws + L.Apad) : nullptr;
     const bool pack64 = P->tq != kTnF64 && (P->anchor_every > 0 || !P->bf16) && !P->c64p_ready;
     HIP_TRY(launch_tn_pack_frag_multi(P->tq, Ca, ldc, N, n, 0, P->ws + L.Cq, np, Np,
-                                      pack64 ? P->at<double>(L.C64p) : nullptr, c32, ldc, N, ldc,
-                                      st));
+                                      pack64 ? P->at<double>(L.C64p) : nullptr, kTnF64, c32, ldc,
+                                      N, ldc, st));
     if (pack64) P->c64p_ready = true;
-    HIP_TRY(launch_tn_pack_frag_multi(P->tq, Ca, ldc, N, n, 1, P->ws + L.CqT, Np, np,
-                                      P->tq != kTnF64 ? P->at<double>(L.C64T) : nullptr, nullptr,
-                                      0, 0, 0, st));
+    // C^T: FP64 beside an FP32 iteration's copy; FP32 beside a bf16 one (its
+    // starts), the FP64 one then packed with the anchors' operands if asked for.
+    void* t2 = P->tq == kTnF64 ? nullptr : P->bf16 ? P->ws + L.C32T : P->ws + L.C64T;
+    HIP_TRY(launch_tn_pack_frag_multi(P->tq, Ca, ldc, N, n, 1, P->ws + L.CqT, Np, np, t2,
+                                      P->bf16 ? kTnF32 : kTnF64, nullptr, 0, 0, 0, st));
+    if (P->tq != kTnF64 && !P->bf16) P->c64t_ready = true;
+    if (P->bf16 && P->anchor_every > 0) ST_TRY(pack_c64p(P));
     if (est) {
       double lo = 0, hi = 0;
       ST_TRY(lanczos(P, NormalOp{c32, true, 1.0 / m}, 1.0, &lo, &hi, &P->lanczos_steps));
@@ -1523,7 +1544,7 @@ apc_status setup_impl(apc_plan_s* P, const Tiles& T) {
       const TnScrub sa{pass_a_args(P), P->tq, P->tnA};
       ST_TRY(tn_tune(P, P->tq, pass_b_args(P), &P->tnB, &sa));
     }
-    ST_TRY(tn_tune(P, kTnF64, x0_args(P), &P->tnX0));
+    ST_TRY(tn_tune(P, x0_type(P), x0_args(P), &P->tnX0));
     ST_TRY(tn_tune(P, kTnF64, resid_args(P, P->xbar()), &P->tnR));
   } else {
     // Alg. 1 initialisation: x_i(0) = Q_i c_i (minimum-norm local solutions),

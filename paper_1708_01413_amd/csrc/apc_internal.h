@@ -594,13 +594,13 @@ hipError_t launch_tn_pack(int type, const double* src, int64_t lds, int64_t srow
 hipError_t launch_tn_pack_frag(int type, const double* src, int64_t lds, int64_t srows,
                                int64_t scols, int32_t transpose, void* dst, int64_t K,
                                int64_t rows, hipStream_t s);
-// The same from one read of the source, also writing (when non-null) the FP64
-// fragment-packed copy d64 (type != FP64) and, for a non-transposed pack, the
-// row-major FP32 copy r32 (r32rows x r32cols of it, stride ldr; r32cols % 8 ==
-// 0, r32 16-byte aligned).
+// The same from one read of the source, also writing (when non-null) a second
+// fragment-packed copy d2 of element type type2 (kTnF64 or kTnF32, not type)
+// and, for a non-transposed pack, the row-major FP32 copy r32 (r32rows x
+// r32cols of it, stride ldr; r32cols % 8 == 0, r32 16-byte aligned).
 hipError_t launch_tn_pack_frag_multi(int type, const double* src, int64_t lds, int64_t srows,
                                      int64_t scols, int32_t transpose, void* dst, int64_t K,
-                                     int64_t rows, double* d64, float* r32, int64_t ldr,
+                                     int64_t rows, void* d2, int type2, float* r32, int64_t ldr,
                                      int64_t r32rows, int64_t r32cols, hipStream_t s);
 
 // Per block: out[col*ldo + r0 + r] = scale * sum_q Lop[r][q] in[col*ldi + r0 + q], col < kc,
