@@ -650,11 +650,12 @@ __device__ inline int xcd_contiguous(int b, int total) {
 // rows, cut at the tile's last row since Linv is lower triangular) goes in
 // chunks of 32: both operands are staged in LDS K-major -- As[k][r] =
 // Linv[R0 + r][kc + k], Bs[k][c] = In[kc + k][C0 + c] -- and each of the eight
-// waves multiplies a 32 x 64 quadrant as 2 x 4 MFMA 16x16x4 tiles (half the
+// waves multiplies 32 rows x 64 columns as 2 x 4 MFMA 16x16x4 tiles (half the
 // registers of four 64 x 64 quadrants: four waves per SIMD instead of two,
 // 0.94 ms instead of 1.27 at 16384 x 8192).  The next chunk is loaded into
 // registers while the current one is multiplied.  Row tiles entirely above
-// the chunk's diagonal are skipped.  The LDS row stride (144 doubles, 1152
+// the chunk's diagonal are skipped; a wave takes the 16-row tiles w and 7 - w
+// of the 128 (not 32 contiguous rows), so every wave skips as many.  The LDS row stride (144 doubles, 1152
 // bytes) puts the two half-waves of a fragment read on different banks.
 constexpr int kTT = 128;
 constexpr int kTK = 32;
@@ -678,7 +679,10 @@ __global__ __launch_bounds__(512, 2) void k_trmm_lds(const double* In, double* O
   const int kend = min(p, R0 + kTT);
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int li = lane & 15, g = lane >> 4;
-  const int wr = wv >> 1, wc = wv & 1;  // eight waves: 4 x 2 quadrants of 32 x 64
+  const int wr = wv >> 1, wc = wv & 1;  // eight waves: 4 row pairs x 2 column halves of 64
+  // The wave's two 16-row tiles of the 128: wr and 7 - wr, so that the
+  // products skipped above the diagonal are spread evenly over the waves.
+  const int tr16[2] = {wr, 7 - wr};
   __shared__ __align__(16) double As[kTK][kTS];
   __shared__ __align__(16) double Bs[kTK][kTS];
 
@@ -737,8 +741,8 @@ __global__ __launch_bounds__(512, 2) void k_trmm_lds(const double* In, double* O
 #pragma unroll
       for (int t = 0; t < 2; ++t) {
         // Rows of this 16-row tile all lie above column kc + 4 kk: zero.
-        if (kc + 4 * kk > R0 + wr * 32 + t * 16 + 15) continue;  // uniform per wave
-        const double a = As[k][wr * 32 + t * 16 + li];
+        if (kc + 4 * kk > R0 + tr16[t] * 16 + 15) continue;  // uniform per wave
+        const double a = As[k][tr16[t] * 16 + li];
 #pragma unroll
         for (int u = 0; u < 4; ++u)
           acc[t][u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b[u], acc[t][u], 0, 0, 0);
@@ -755,7 +759,7 @@ __global__ __launch_bounds__(512, 2) void k_trmm_lds(const double* In, double* O
     for (int u = 0; u < 4; ++u)
 #pragma unroll
       for (int qq = 0; qq < 4; ++qq) {
-        const int row = R0 + wr * 32 + t * 16 + g + 4 * qq;
+        const int row = R0 + tr16[t] * 16 + g + 4 * qq;
         const int64_t col = C0 + wc * 64 + u * 16 + li;
         if (row < p && col < ldc) {
           const int64_t o = (r0 + row) * ldc + col;
