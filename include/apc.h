@@ -51,8 +51,9 @@ typedef enum {
                   /* accumulation, iterates and update arithmetic in FP64          */
   APC_BF16_IR = 2, /* iterative refinement: inner APC on a bf16 Q_i (matrix cores, */
                    /* FP32 accumulation, FP64 state), FP64 residual B - A X and    */
-                   /* FP64 start x_bar(0) on matrix cores; setup QR in FP64, the  */
-                   /* eigenvalue estimate's recurrence in FP64 (see apc_setup)     */
+                   /* FP32 inner starts x_bar(0) on matrix cores; setup QR in      */
+                   /* FP64, the eigenvalue estimate's recurrence in FP64 (see      */
+                   /* apc_setup)                                                   */
   APC_REDUCED_FORM = 16 /* flag, OR'ed into APC_F64 / APC_F32: use the (y, x_bar)    */
                         /* form below also for k = 1 (needed by apc_backward)      */
 } apc_precision;
@@ -229,17 +230,19 @@ apc_status apc_get_info(apc_plan p, int32_t* lanczos_steps, int32_t* rows_per_ti
                         int32_t* column_splits, int32_t* block_groups, int32_t* refinements);
 
 /* Host copies of what setup did for the thin QR of Sec. 3.1 (CholeskyQR):
- * *qr_passes = 2, or 1 when a k = 1 APC_F32 plan skipped the second pass
- * because the rows' measured departure from orthonormality after the first,
+ * *qr_passes = 2, or 1 when an APC_F32 / APC_BF16_IR plan (k = 1 with the
+ * single-pass update, or the k-RHS form) skipped the second pass because the
+ * rows' measured departure from orthonormality after the first,
  * max_i ||C_i C_i^T - I|| estimated with a random vector, was at most
- * 1e-10 / sqrt(max p_i), far below the FP32 rounding the factor then takes;
- * *qr_defect = that estimate (NaN when it was not measured: FP64 plans, the
- * k-RHS forms, rows too wide for the single-pass kernel in FP64, or
- * APC_QR_PASSES=2 in the environment).  Any pointer may be NULL. */
+ * 1e-10 / sqrt(max p_i), far below the rounding the factor then takes;
+ * *qr_defect = that estimate (NaN when it was not measured: FP64 plans, k = 1
+ * plans updated in two passes, or APC_QR_PASSES=2 in the environment).  Any
+ * pointer may be NULL. */
 apc_status apc_get_setup(apc_plan p, int32_t* qr_passes, double* qr_defect);
 
 /* Launch shape the k-RHS path chose for one of its contractions (which: 0 =
- * pass A, 1 = pass B, 2 = the FP64 start x_bar(0) = (1/m) C^T c, 3 = the FP64
+ * pass A, 1 = pass B, 2 = the start x_bar(0) = (1/m) C^T c (FP64; FP32 with
+ * APC_BF16_IR), 3 = the FP64
  * residual): rows of the streamed operand per workgroup, split-K factor, and
  * the measured time per launch when it was chosen by timing (0 when fixed by
  * APC_TN_TUNE=0 / APC_TN_RT / APC_TN_SPLIT).  Shapes are timed once per

@@ -789,7 +789,8 @@ apc_status update_gemm(apc_plan_s* P, hipEvent_t* ev, int* kinds, int* nev) {
 
 // Starts the (y, x_bar) iteration for the right-hand sides whose transformed
 // values c = R^{-T} b (RHS-major, stride N, zero past k) are given:
-// x_bar(0) = (1/m) C^T c in FP64, y(0) = 0.
+// x_bar(0) = (1/m) C^T c (FP64, or FP32 in the mixed-precision mode, see
+// x0_args), y(0) = 0.
 apc_status start_gemm(apc_plan_s* P, const double* c_rhs) {
   const Layout& L = P->L;
   const int t = x0_type(P);
