@@ -404,31 +404,40 @@ __global__ __launch_bounds__(256, 2) void k_batch_mixed(const BatchSys* sys, con
         tn_block<double, 1, NCT, 2, 0>(a, w.w, *reinterpret_cast<TnStage<NCT>*>(lds));
       __syncthreads();
     } else {
+      // Elementwise items, four consecutive entries per thread: every row
+      // length and stride of a k-RHS plan's operands is a multiple of 256
+      // and every slice 256-byte aligned.
       const BatchGemm& G = gemm[w.y];
       const int64_t e0 = static_cast<int64_t>(w.w) * kBatchChunk;
       if (kind == kItemSum32 || kind == kItemSum64) {
         const int64_t total = static_cast<int64_t>(G.kp) * G.sum_rows;
         const int64_t e1 = min(total, e0 + kBatchChunk);
         const int64_t stride = static_cast<int64_t>(G.kp) * G.sum_ldp;
-        for (int64_t e = e0 + threadIdx.x; e < e1; e += 256) {
+        for (int64_t e = e0 + 4 * threadIdx.x; e < e1; e += 4 * 256) {
           if (kind == kItemSum32)
-            sum_cast_elem(static_cast<const float*>(G.sum_part), G.sum_nsplit[0], G.sum_ldp,
-                          G.sum_rows, stride, static_cast<float*>(G.sum_out[0]), G.sum_ldo, e);
+            sum_cast4(static_cast<const float*>(G.sum_part), G.sum_nsplit[0], G.sum_ldp, G.sum_rows,
+                      stride, static_cast<float*>(G.sum_out[0]), G.sum_ldo, e);
           else
-            sum_cast_elem(static_cast<const double*>(G.sum_part), G.sum_nsplit[1], G.sum_ldp,
-                          G.sum_rows, stride, static_cast<double*>(G.sum_out[1]), G.sum_ldo, e);
+            sum_cast4(static_cast<const double*>(G.sum_part), G.sum_nsplit[1], G.sum_ldp,
+                      G.sum_rows, stride, static_cast<double*>(G.sum_out[1]), G.sum_ldo, e);
         }
       } else if (kind == kItemUpd32 || kind == kItemUpd64) {
         const TnUpdateArgs& u = G.upd[kind == kItemUpd64 ? 1 : 0];
         const int64_t e1 = min(static_cast<int64_t>(u.kp) * u.n, e0 + kBatchChunk);
-        for (int64_t e = e0 + threadIdx.x; e < e1; e += 256) {
-          if (kind == kItemUpd32) update_elem<float, float>(u, e);
-          else update_elem<double, float>(u, e);
+        for (int64_t e = e0 + 4 * threadIdx.x; e < e1; e += 4 * 256) {
+          if (kind == kItemUpd32) update4<float, float>(u, e);
+          else update4<double, float>(u, e);
         }
       } else if (kind == kItemAnchorVec) {
         const int64_t e1 = min(G.state_count, e0 + kBatchChunk);
-        for (int64_t e = e0 + threadIdx.x; e < e1; e += 256)
-          G.yref[e] = (1.0 - G.gamma) * G.y[e] + G.gamma * G.xbar[e];
+        for (int64_t e = e0 + 4 * threadIdx.x; e < e1; e += 4 * 256) {
+          double y[4], xb[4], r[4];
+          load4(G.y + e, y);
+          load4(G.xbar + e, xb);
+#pragma unroll
+          for (int q = 0; q < 4; ++q) r[q] = (1.0 - G.gamma) * y[q] + G.gamma * xb[q];
+          store4(G.yref + e, r);
+        }
       }
     }
   }
