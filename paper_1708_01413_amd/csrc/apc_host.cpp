@@ -1695,6 +1695,19 @@ apc_status apc_setup(apc_plan* out, const double* A, int64_t lda, const double* 
   P->fused_rows = fused_rows;
   P->fused_g = fused_g;
   P->ntiles_f = static_cast<int32_t>(T.f_row0.size());
+  {
+    // At eight or more 16-byte chunks per thread, two-row register groups
+    // take every register of a wave, one workgroup per CU: tiles beyond the
+    // CU count then run as a second round of their own.  Between one and two
+    // tiles per CU, one-row groups (two workgroups per CU) run them at once.
+    int cus = 0;
+    HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    const int ce = fused ? elem : 4, cc = fused ? cpt : cpt32;
+    const bool fixed = std::getenv("APC_FUSED_G") != nullptr;
+    if (!fixed && P->fused_g == 2 && cc >= 8 && P->ntiles_f > cus && P->ntiles_f <= 2 * cus &&
+        fused_shape_ok(ce, ce, cc, 1))
+      P->fused_g = 1;
+  }
   if (fused) {
     const int32_t t0 = T.f_first[1];
     bool same = true;
