@@ -398,10 +398,12 @@ __global__ __launch_bounds__(256, 2) void k_batch_mixed(const BatchSys* sys, con
                    *reinterpret_cast<double(*)[32]>(lds + sizeof(double) * 8 * 32));
     } else if (kind == kItemTn32 || kind == kItemTn64) {
       const TnArgs a = gemm[w.y].tn[w.z];
+      // (The FP64 contraction, an anchor update's, loads one step ahead: with
+      // two the kernel's union of work kinds spilled registers.)
       if (kind == kItemTn32)
         tn_block<float, 1, NCT, 2, 1>(a, w.w, *reinterpret_cast<TnStage<NCT>*>(lds));
       else
-        tn_block<double, 1, NCT, 2, 0>(a, w.w, *reinterpret_cast<TnStage<NCT>*>(lds));
+        tn_block<double, 1, NCT, 1, 0>(a, w.w, *reinterpret_cast<TnStage<NCT>*>(lds));
       __syncthreads();
     } else {
       // Elementwise items, four consecutive entries per thread: every row
