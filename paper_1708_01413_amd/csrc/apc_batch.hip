@@ -265,61 +265,90 @@ __global__ __launch_bounds__(256) void k_batch_fused(const BatchSys* sys, const 
   }
 }
 
-// After k_batch_fused, items (sys, first of 32 columns): lanes (column,
-// block-lane) as in the single-system combine -- x_i += gamma (x_bar - x_i -
-// sum of block i's partial rows), x_bar <- (eta/m) sum_i x_i + (1 - eta) x_bar,
-// d_i = x_bar - x_i.  A block's partial rows are loaded four at a time, with
-// its x_i, before they are added.
-__device__ __attribute__((always_inline)) inline void combine_item(const BatchSys& S, int col, double (&part)[8][32],
-                                    double (&xb)[32]) {
-  const int lane = threadIdx.x & 31;
-  const int bl = threadIdx.x >> 5;
+// After k_batch_fused, items (sys, first of 64 columns): lane l of wave w
+// takes column l and the blocks i = w (mod 4) -- x_i += gamma (x_bar - x_i -
+// sum of block i's partial rows), x_bar <- (eta/m) sum_i x_i + (1 - eta)
+// x_bar, d_i = x_bar - x_i.  A lane's blocks are loaded four at a time (their
+// x_i and first four partial rows, clamped addresses and selects), and with
+// m <= 16 their new x_i stay in registers for the differences.  A block's
+// partial rows are added in tile order.
+__device__ __attribute__((always_inline)) inline void combine_item(const BatchSys& S, int col,
+                                                                   double (&part)[4][64],
+                                                                   double (&xb)[64]) {
+  constexpr int U = 4;
+  const int lane = threadIdx.x & 63;
+  const int bl = threadIdx.x >> 6;
   const int64_t j = col + lane;
+  const bool ok = j < S.n;
+  const int64_t jc = ok ? j : col;  // col < n
   double* x = S.x;
+  const double xo = S.xbar[jc];
+  const bool one = S.m <= 4 * U;
+  double keep[U];
   double s = 0.0;
-  if (j < S.n) {
-    const double xo = S.xbar[j];
-    for (int i = bl; i < S.m; i += 8) {
-      const int64_t o = static_cast<int64_t>(i) * S.ldc + j;
-      const double xi = x[o];
-      const int t1 = S.tile_first[i + 1];
-      double u = 0.0;
-      for (int t = S.tile_first[i]; t < t1; t += 4) {
-        float v[4];
+  for (int i0 = bl; i0 < S.m; i0 += 4 * U) {
+    double xi[U];
+    float v[U][4];
+    int t0[U], t1[U];
 #pragma unroll
-        for (int k = 0; k < 4; ++k)
-          v[k] = t + k < t1 ? S.part[static_cast<int64_t>(t + k) * S.ldc + j] : 0.f;
+    for (int q = 0; q < U; ++q) {
+      const int i = i0 + 4 * q;
+      const int ic = i < S.m ? i : i0;
+      t0[q] = S.tile_first[ic];
+      t1[q] = S.tile_first[ic + 1];
+      xi[q] = x[static_cast<int64_t>(ic) * S.ldc + jc];
 #pragma unroll
-        for (int k = 0; k < 4; ++k) u += static_cast<double>(v[k]);
+      for (int k = 0; k < 4; ++k) {
+        const int t = min(t0[q] + k, t1[q] - 1);  // every block has a tile
+        v[q][k] = S.part[static_cast<int64_t>(t) * S.ldc + jc];
       }
-      const double xn = xi + S.gamma * ((xo - xi) - u);
-      x[o] = xn;
-      s += xn;
+    }
+#pragma unroll
+    for (int q = 0; q < U; ++q) {
+      const int i = i0 + 4 * q;
+      double u = 0.0;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) u += t0[q] + k < t1[q] ? static_cast<double>(v[q][k]) : 0.0;
+      for (int t = t0[q] + 4; t < t1[q]; ++t)  // blocks of more than four tiles
+        u += static_cast<double>(S.part[static_cast<int64_t>(t) * S.ldc + jc]);
+      const double xn = xi[q] + S.gamma * ((xo - xi[q]) - u);
+      keep[q] = xn;
+      if (i < S.m && ok) {
+        x[static_cast<int64_t>(i) * S.ldc + j] = xn;
+        s += xn;
+      }
     }
   }
   part[bl][lane] = s;
   __syncthreads();
-  if (bl == 0 && j < S.n) {
-    const double tot = ((part[0][lane] + part[1][lane]) + (part[2][lane] + part[3][lane])) +
-                       ((part[4][lane] + part[5][lane]) + (part[6][lane] + part[7][lane]));
+  if (bl == 0 && ok) {
+    const double tot = (part[0][lane] + part[1][lane]) + (part[2][lane] + part[3][lane]);
     const double v = (S.eta / S.m) * tot + (1.0 - S.eta) * S.xbar[j];
     S.xbar[j] = v;
     xb[lane] = v;
   }
   __syncthreads();
-  if (j < S.n) {
+  if (ok) {
     float* d = static_cast<float*>(S.d);
-    for (int i = bl; i < S.m; i += 8)
-      d[static_cast<int64_t>(i) * S.ldc + j] =
-          static_cast<float>(xb[lane] - x[static_cast<int64_t>(i) * S.ldc + j]);
+    const double v = xb[lane];
+    for (int i0 = bl; i0 < S.m; i0 += 4 * U) {
+#pragma unroll
+      for (int q = 0; q < U; ++q) {
+        const int i = i0 + 4 * q;
+        if (i < S.m) {
+          const double xi = one ? keep[q] : x[static_cast<int64_t>(i) * S.ldc + j];
+          d[static_cast<int64_t>(i) * S.ldc + j] = static_cast<float>(v - xi);
+        }
+      }
+    }
   }
   __syncthreads();
 }
 
 __global__ __launch_bounds__(256) void k_batch_fused_combine(const BatchSys* sys, const int2* items,
                                                              int32_t nitems, const int32_t* active) {
-  __shared__ double part[8][32];
-  __shared__ double xb[32];
+  __shared__ double part[4][64];
+  __shared__ double xb[64];
   for (int32_t it = blockIdx.x; it < nitems; it += gridDim.x) {
     const int2 w = items[it];
     if (!active[w.x]) continue;  // uniform per workgroup
@@ -394,8 +423,8 @@ __global__ __launch_bounds__(256, 2) void k_batch_mixed(const BatchSys* sys, con
     if (kind == kItemFused) {
       fused_item(sys[w.y], w.z, *reinterpret_cast<float(*)[4][kBatchFusedCols]>(lds));
     } else if (kind == kItemCombine) {
-      combine_item(sys[w.y], w.z, *reinterpret_cast<double(*)[8][32]>(lds),
-                   *reinterpret_cast<double(*)[32]>(lds + sizeof(double) * 8 * 32));
+      combine_item(sys[w.y], w.z, *reinterpret_cast<double(*)[4][64]>(lds),
+                   *reinterpret_cast<double(*)[64]>(lds + sizeof(double) * 4 * 64));
     } else if (kind == kItemTn32 || kind == kItemTn64) {
       const TnArgs a = gemm[w.y].tn[w.z];
       // (The FP64 contraction, an anchor update's, loads one step ahead: with

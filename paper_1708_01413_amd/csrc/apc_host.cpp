@@ -2418,7 +2418,7 @@ struct apc_batch_s {
   int4* itemsB = nullptr;
   int2* itemsV = nullptr;
   int32_t nA = 0, nB = 0, nV = 0;
-  bool fused = false;                  // single pass: items F (sys, tile), W (sys, 32 columns)
+  bool fused = false;                  // single pass: items F (sys, tile), W (sys, 64 columns)
   int2* itemsF = nullptr;
   int2* itemsW = nullptr;
   int32_t nF = 0, nW = 0;
@@ -2558,7 +2558,7 @@ apc_status batch_items(const apc_plan* plans, int32_t count, BatchPlanItems* it)
       for (auto* v : {&r0, &nr, &bk, &first}) it->tiles.insert(it->tiles.end(), v->begin(), v->end());
       for (size_t t = 0; t < r0.size(); ++t)
         fw.emplace_back(static_cast<int64_t>(nr[t]) * P->L.ldc, make_int2(s, static_cast<int>(t)));
-      for (int64_t j = 0; j < P->n; j += 32)
+      for (int64_t j = 0; j < P->n; j += 64)
         ww.emplace_back(static_cast<int64_t>(r0.size()) + P->m, make_int2(s, static_cast<int>(j)));
     }
     // Largest items first: workgroups take items in launch order, so the big

@@ -520,7 +520,7 @@ struct BatchSys {
 // Items: pass A (sys, first row, rows <= 8, block); pass B (sys, block, first
 // column of a 256-column slab, 0); average (sys, first column of 256).
 // Single pass (rows up to kBatchFusedCols wide): items (sys, tile) write the
-// tile's partial row; items (sys, first of 32 columns) then apply the x_i
+// tile's partial row; items (sys, first of 64 columns) then apply the x_i
 // update, the average and the next differences, as k = 1 single-system plans do.
 constexpr int kBatchFusedCols = 1024;
 hipError_t launch_batch_fused(int32_t grid, const BatchSys* sys, const int2* items, int32_t nitems,
