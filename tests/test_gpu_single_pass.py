@@ -238,3 +238,29 @@ def test_batch_with_wide_rows_takes_two_passes():
         ref = O.apc_run(S.A, S.B, S.off, T, g, e)["xbar"][:, 0]
         assert np.linalg.norm(p.xbar().cpu().numpy() - ref) / np.linalg.norm(S.xstar) <= TOL["f32"]
     batch.close()
+
+
+def test_one_row_groups_when_tiles_just_exceed_the_cus():
+    """8192^2 FP32 with 64 uneven blocks (sizes drawn from [32, 256]): the single pass's
+    tiles outnumber the CUs by less than a second round, and two-row register groups fit
+    one workgroup per CU, so the plan takes one-row groups (two workgroups per CU); the
+    update still matches the oracle."""
+    apc = _apc()
+    torch = _torch()
+    S = synth.shifted_uneven_8k(seed=5, k=1)
+    T = 8
+    ref = oracle_traj(S, T, 1.0, 1.0)
+    A = torch.from_numpy(S.A).cuda()
+    b = torch.from_numpy(np.ascontiguousarray(S.B[:, 0])).cuda()
+    plan = apc.Plan(A, b, S.off, "f32", gamma=1.0, eta=1.0)
+    shape = plan.single_pass_shape()
+    tiles = sum(-(-int(p) // shape["rows_per_wg"]) for p in np.diff(S.off))
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    say(f"case: uneven 8192^2 FP32, {tiles} tiles on {cus} CUs, shape {shape}")
+    if not cus < tiles <= 2 * cus:
+        pytest.skip(f"{tiles} tiles on {cus} CUs: not between one and two per CU")
+    assert shape["rows_per_group"] == 1
+    d = dev(gpu_traj(plan, T), ref, S.xstar[:, 0])
+    say(f"max dev {d:.3e}")
+    assert d <= TOL["f32"]
+    plan.close()
