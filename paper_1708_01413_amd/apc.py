@@ -69,8 +69,9 @@ def _hip_runtimes() -> set:
 
 def _load() -> ctypes.CDLL:
     if not os.path.exists(LIB_PATH):
-        raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
-                          "(hipcc --offload-arch=gfx950); there is no fallback path")
+        raise ImportError(f"{LIB_PATH} is missing: build it with "
+                          "python paper_1708_01413_amd/build.py (hipcc --offload-arch=gfx950); "
+                          "there is no fallback path")
     # torch ships its own HIP runtime with the same soname as the system one.
     # Load it first so libapc binds to it: two HIP runtimes in one process
     # cannot share the device (HIP then reports no device to one of them).
