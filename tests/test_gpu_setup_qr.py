@@ -233,3 +233,24 @@ def test_bf16_plan_one_pass_refines_to_fp64(anchor):
         f"err {err:.2e}")
     assert info["qr_passes"] == 1
     assert st == apc.APC_OK and err <= 1e-9
+
+
+@pytest.mark.parametrize("n", [2048, 2050])
+def test_split_gram_in_both_passes_fp64(n):
+    """Rows of 2048 or more columns split the Gram product's K range (partial Grams in
+    the factor slice the pass writes next); an FP64 plan takes both CholeskyQR passes,
+    so both write their partials there: in place (n = 2048, the first pass reads A
+    itself) and through the padded copy (n = 2050).  Mixed rows (kappa(A_i) ~ 1e4) make
+    the second pass matter.  FP64 bar 1e-10 against the oracle's trajectory."""
+    sizes = synth.renormalised_sizes(np.random.default_rng(62), 9, 2304, 160, 352)
+    S = mixed_rows(synth.gaussian_system(2304, n, 9, seed=62, sizes=sizes,
+                                         scale=1 / math.sqrt(n)), 4)
+    plan, g, e = run(S, "f64", 0)
+    info = plan.setup_info()
+    say(f"case: split Gram, FP64, n={n}, blocks {np.diff(S.off).tolist()}, {info}")
+    assert info["qr_passes"] == 2
+    T = 30
+    d = dev(gpu_traj(plan, T), oracle_traj(S, T, g, e), S.xstar)
+    say(f"max dev {d:.3e}")
+    assert d <= 1e-10
+    plan.close()
