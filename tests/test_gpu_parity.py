@@ -632,6 +632,30 @@ def test_bf16_refinement_reaches_fp64_accuracy(alpha, k, anchor):
     assert info["refinements"] >= 2      # the inner bf16 solve alone cannot reach 1e-10
 
 
+def test_bf16_restart_with_new_rhs_reaches_fp64_accuracy():
+    """A refined bf16 solve, then apc_restart with new right-hand sides and a second solve
+    (the inner solves start from x_bar(0) formed on the FP32 matrix cores): both
+    solutions match the LAPACK solve of their right-hand sides to 1e-10."""
+    apc = _apc()
+    torch = _torch()
+    S = synth.shifted_square(2048, 8, k=16, shift=3.0, seed=45)
+    A, b = upload(S)
+    b2 = torch.from_numpy(np.random.default_rng(46).standard_normal(S.B.shape)).to(A.device)
+    plan = apc.Plan(A, b, S.off, "bf16_ir")
+    x1, it1, rr1, st1 = plan.solve(1e-12, 2000)
+    ref1 = np.linalg.solve(S.A, S.B)
+    d1 = np.linalg.norm(x1.cpu().numpy() - ref1) / np.linalg.norm(ref1)
+    plan.restart(b2)
+    x2, it2, rr2, st2 = plan.solve(1e-12, 2000)
+    ref2 = np.linalg.solve(S.A, b2.cpu().numpy())
+    d2 = np.linalg.norm(x2.cpu().numpy() - ref2) / np.linalg.norm(ref2)
+    say(f"case: bf16 restart: first solve {it1} updates dev {d1:.2e}, after restart {it2} "
+        f"updates dev {d2:.2e}")
+    assert st1 == apc.APC_OK and st2 == apc.APC_OK
+    assert d1 <= 1e-10 and d2 <= 1e-10
+    plan.close()
+
+
 def test_bf16_inner_solve_contracts():
     """One inner solve on the bf16 factor (no refinement) cuts the residual by > 100x."""
     apc = _apc()
