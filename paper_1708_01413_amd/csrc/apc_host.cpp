@@ -2463,7 +2463,11 @@ struct BatchPlanItems {
   std::vector<int32_t> start;
 };
 
-constexpr int kBatchTileRows = 64;
+// (128 rows: each item streams long enough to cover the chain of dependent
+// loads that starts it; the 256-system pass took 72 us with 64-row items,
+// 67 with 128, 65 with 256, where the mixed batch with its contraction tiles
+// balanced worse.)
+constexpr int kBatchTileRows = 128;
 
 // A batch updates in one pass over every factor when each plan does (k = 1
 // single-pass tiles) and every row fits the batch kernel's registers.
@@ -2804,7 +2808,7 @@ apc_status apc_batch_create(apc_batch* out, const apc_plan* plans, int32_t count
     d.bnorm = P->bnorm;
     if (B->fused && !P->gemm) {
       // The plan's partial-row slice holds at least one FP64 row per 16 rows
-      // of a block, so one FP32 row per tile of up to 64 rows fits.
+      // of a block, so one FP32 row per tile of up to 128 rows fits.
       const int32_t* tl = reinterpret_cast<const int32_t*>(B->ws + L.T) + it.tile_at[s];
       int32_t nt = 0;
       for (int i = 0; i < P->m; ++i)
