@@ -181,12 +181,11 @@ __device__ inline const __attribute__((address_space(1))) g_f32x4* gptr4(const f
 }
 
 template <int CPL, int INFLIGHT = 16>
-__device__ __attribute__((always_inline)) inline void batch_tile_pass(const BatchSys& S, int t, float (&red)[4][kBatchFusedCols]) {
+__device__ __attribute__((always_inline)) inline void batch_tile_pass(const BatchSys& S, int64_t row0,
+                                                                      int nrows, int blk,
+                                                                      float (&red)[4][kBatchFusedCols]) {
   constexpr int RF = INFLIGHT / CPL;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int64_t row0 = S.tiles[t];
-  const int nrows = S.tiles[S.ntiles + t];
-  const int blk = S.tiles[2 * S.ntiles + t];
   const float* C = static_cast<const float*>(S.C);
   const float* d = static_cast<const float*>(S.d) + static_cast<int64_t>(blk) * S.ldc;
   // Every load below is issued without a branch: a chunk past the row (the
@@ -242,10 +241,12 @@ __device__ __attribute__((always_inline)) inline void batch_tile_pass(const Batc
 // mixed kernel: 8 took 342 against 333 us per update of the 8192^2 k = 64
 // system with the 256 systems).
 template <int INFLIGHT = 16>
-__device__ __attribute__((always_inline)) inline void fused_item(const BatchSys& S, int t, float (&red)[4][kBatchFusedCols]) {
-  if (S.ldc <= 256) batch_tile_pass<1, INFLIGHT>(S, t, red);
-  else if (S.ldc <= 512) batch_tile_pass<2, INFLIGHT>(S, t, red);
-  else batch_tile_pass<4, INFLIGHT>(S, t, red);
+__device__ __attribute__((always_inline)) inline void fused_item(const BatchSys& S, int t, int64_t row0,
+                                                                 int nrows, int blk,
+                                                                 float (&red)[4][kBatchFusedCols]) {
+  if (S.ldc <= 256) batch_tile_pass<1, INFLIGHT>(S, row0, nrows, blk, red);
+  else if (S.ldc <= 512) batch_tile_pass<2, INFLIGHT>(S, row0, nrows, blk, red);
+  else batch_tile_pass<4, INFLIGHT>(S, row0, nrows, blk, red);
   __syncthreads();
   float* out = S.part + static_cast<int64_t>(t) * S.ldc;
   for (int64_t j = threadIdx.x; j < S.ldc; j += 256)
@@ -253,15 +254,24 @@ __device__ __attribute__((always_inline)) inline void fused_item(const BatchSys&
   __syncthreads();
 }
 
-// Items (sys, row tile of the batch's tiles for that system): the tile's
-// partial row, for rows up to kBatchFusedCols wide.
-__global__ __launch_bounds__(256) void k_batch_fused(const BatchSys* sys, const int2* items,
+// The same with the tile's rows and block read from the system's tile lists.
+template <int INFLIGHT = 16>
+__device__ __attribute__((always_inline)) inline void fused_item(const BatchSys& S, int t,
+                                                                 float (&red)[4][kBatchFusedCols]) {
+  fused_item<INFLIGHT>(S, t, S.tiles[t], S.tiles[S.ntiles + t], S.tiles[2 * S.ntiles + t], red);
+}
+
+// Items (sys, row tile of the batch's tiles for that system, the tile's first
+// row, rows | block << 8): the tile's partial row, for rows up to
+// kBatchFusedCols wide.  The item carries the tile so that its rows' loads
+// wait only for the item and the system's descriptor.
+__global__ __launch_bounds__(256) void k_batch_fused(const BatchSys* sys, const int4* items,
                                                      int32_t nitems, const int32_t* active) {
   __shared__ float red[4][kBatchFusedCols];
   for (int32_t it = blockIdx.x; it < nitems; it += gridDim.x) {
-    const int2 w = items[it];
+    const int4 w = items[it];
     if (!active[w.x]) continue;  // uniform per workgroup
-    fused_item(sys[w.x], w.y, red);
+    fused_item(sys[w.x], w.y, w.z, w.w & 0xff, static_cast<int>(static_cast<uint32_t>(w.w) >> 8), red);
   }
 }
 
@@ -511,7 +521,7 @@ hipError_t launch_batch_average(int f64, int32_t grid, const BatchSys* sys, cons
   return hipGetLastError();
 }
 
-hipError_t launch_batch_fused(int32_t grid, const BatchSys* sys, const int2* items, int32_t nitems,
+hipError_t launch_batch_fused(int32_t grid, const BatchSys* sys, const int4* items, int32_t nitems,
                               const int32_t* active, hipStream_t s) {
   k_batch_fused<<<grid, 256, 0, s>>>(sys, items, nitems, active);
   return hipGetLastError();

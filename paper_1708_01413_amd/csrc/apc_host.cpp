@@ -2419,7 +2419,7 @@ struct apc_batch_s {
   int2* itemsV = nullptr;
   int32_t nA = 0, nB = 0, nV = 0;
   bool fused = false;                  // single pass: items F (sys, tile), W (sys, 64 columns)
-  int2* itemsF = nullptr;
+  int4* itemsF = nullptr;
   int2* itemsW = nullptr;
   int32_t nF = 0, nW = 0;
   int32_t* active = nullptr;
@@ -2451,7 +2451,9 @@ namespace {
 struct BatchPlanItems {
   std::vector<int4> A, B;
   std::vector<int2> V;
-  std::vector<int2> F, W;  // single pass (when every plan has it and rows fit)
+  std::vector<int4> F;     // single pass (when every plan has it and rows fit):
+                           // (sys, tile, first row, rows | block << 8)
+  std::vector<int2> W;
   std::vector<int4> L[2][4], L0;  // mixed batch work lists
   std::vector<BatchGemm> gemm;
   std::vector<int32_t> gemm_sys, gemm_slot;
@@ -2476,7 +2478,8 @@ bool batch_single_pass(const apc_plan* plans, int32_t count) {
     if (std::atoi(e) == 0) return false;
   for (int32_t s = 0; s < count; ++s) {
     if (plans[s]->gemm) continue;
-    if (!plans[s]->fused || plans[s]->L.ldc > kBatchFusedCols) return false;
+    // The single-pass items carry the block index in 24 bits.
+    if (!plans[s]->fused || plans[s]->L.ldc > kBatchFusedCols || plans[s]->m >= (1 << 24)) return false;
   }
   return true;
 }
@@ -2541,7 +2544,8 @@ apc_status batch_items(const apc_plan* plans, int32_t count, BatchPlanItems* it)
   }
   if (batch_single_pass(plans, count)) {
     // (weight, item) pairs, ordered below.
-    std::vector<std::pair<int64_t, int2>> fw, ww;
+    std::vector<std::pair<int64_t, int4>> fw;
+    std::vector<std::pair<int64_t, int2>> ww;
     for (int32_t s = 0; s < count; ++s) {
       const apc_plan_s* P = plans[s];
       if (P->gemm) {
@@ -2561,7 +2565,8 @@ apc_status batch_items(const apc_plan* plans, int32_t count, BatchPlanItems* it)
       it->tile_at.push_back(it->tiles.size());
       for (auto* v : {&r0, &nr, &bk, &first}) it->tiles.insert(it->tiles.end(), v->begin(), v->end());
       for (size_t t = 0; t < r0.size(); ++t)
-        fw.emplace_back(static_cast<int64_t>(nr[t]) * P->L.ldc, make_int2(s, static_cast<int>(t)));
+        fw.emplace_back(static_cast<int64_t>(nr[t]) * P->L.ldc,
+                        make_int4(s, static_cast<int>(t), r0[t], nr[t] | (bk[t] << 8)));
       for (int64_t j = 0; j < P->n; j += 64)
         ww.emplace_back(static_cast<int64_t>(r0.size()) + P->m, make_int2(s, static_cast<int>(j)));
     }
@@ -2570,9 +2575,7 @@ apc_status batch_items(const apc_plan* plans, int32_t count, BatchPlanItems* it)
     // few big tiles running alone at its end.  Every item writes only its own
     // partial row or columns (partial rows are summed later in tile order), so
     // the order changes no result.
-    auto by_weight = [](const std::pair<int64_t, int2>& a, const std::pair<int64_t, int2>& b) {
-      return a.first > b.first;
-    };
+    auto by_weight = [](const auto& a, const auto& b) { return a.first > b.first; };
     std::stable_sort(fw.begin(), fw.end(), by_weight);
     std::stable_sort(ww.begin(), ww.end(), by_weight);
     for (const auto& f : fw) it->F.push_back(f.second);
@@ -2623,7 +2626,7 @@ apc_status batch_items(const apc_plan* plans, int32_t count, BatchPlanItems* it)
     load[q] += plans[s]->N * plans[s]->L.ldc;
   }
   for (int v = 0; v < 2; ++v) {
-    for (const int2& f : it->F) it->L[v][side[f.x] ? 2 : 0].push_back(item(kItemFused, f.x, f.x, f.y, 0));
+    for (const int4& f : it->F) it->L[v][side[f.x] ? 2 : 0].push_back(item(kItemFused, f.x, f.x, f.y, 0));
     for (const int2& w : it->W) it->L[v][side[w.x] ? 3 : 1].push_back(item(kItemCombine, w.x, w.x, w.y, 0));
   }
   return APC_OK;
@@ -2645,7 +2648,7 @@ BatchLayout batch_layout(int32_t count, const BatchPlanItems& it) {
   L.A = take(static_cast<int64_t>(it.A.size()) * sizeof(int4));
   L.B = take(static_cast<int64_t>(it.B.size()) * sizeof(int4));
   L.V = take(static_cast<int64_t>(it.V.size()) * sizeof(int2));
-  L.F = take(static_cast<int64_t>(it.F.size()) * sizeof(int2));
+  L.F = take(static_cast<int64_t>(it.F.size()) * sizeof(int4));
   L.W = take(static_cast<int64_t>(it.W.size()) * sizeof(int2));
   L.T = take(static_cast<int64_t>(it.tiles.size()) * 4);
   L.active = take(static_cast<int64_t>(count) * 4);
@@ -2781,7 +2784,7 @@ apc_status apc_batch_create(apc_batch* out, const apc_plan* plans, int32_t count
     B->anchor_every = G0->anchor_every;
     B->since = G0->since_start;
   }
-  B->itemsF = reinterpret_cast<int2*>(B->ws + L.F);
+  B->itemsF = reinterpret_cast<int4*>(B->ws + L.F);
   B->itemsW = reinterpret_cast<int2*>(B->ws + L.W);
   B->nF = static_cast<int32_t>(it.F.size());
   B->nW = static_cast<int32_t>(it.W.size());
@@ -2827,7 +2830,7 @@ apc_status apc_batch_create(apc_batch* out, const apc_plan* plans, int32_t count
   HIP_TRY(hipMemcpyAsync(B->itemsV, it.V.data(), it.V.size() * sizeof(int2), hipMemcpyHostToDevice, st));
   if (B->fused) {
     HIP_TRY(hipMemcpyAsync(B->ws + L.T, it.tiles.data(), it.tiles.size() * 4, hipMemcpyHostToDevice, st));
-    HIP_TRY(hipMemcpyAsync(B->itemsF, it.F.data(), it.F.size() * sizeof(int2), hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(B->itemsF, it.F.data(), it.F.size() * sizeof(int4), hipMemcpyHostToDevice, st));
     HIP_TRY(hipMemcpyAsync(B->itemsW, it.W.data(), it.W.size() * sizeof(int2), hipMemcpyHostToDevice, st));
   }
   if (B->mixed) {

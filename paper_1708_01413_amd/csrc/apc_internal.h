@@ -523,7 +523,7 @@ struct BatchSys {
 // tile's partial row; items (sys, first of 64 columns) then apply the x_i
 // update, the average and the next differences, as k = 1 single-system plans do.
 constexpr int kBatchFusedCols = 1024;
-hipError_t launch_batch_fused(int32_t grid, const BatchSys* sys, const int2* items, int32_t nitems,
+hipError_t launch_batch_fused(int32_t grid, const BatchSys* sys, const int4* items, int32_t nitems,
                               const int32_t* active, hipStream_t s);
 hipError_t launch_batch_fused_combine(int32_t grid, const BatchSys* sys, const int2* items,
                                       int32_t nitems, const int32_t* active, hipStream_t s);
