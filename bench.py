@@ -293,12 +293,17 @@ def many_systems(apc, synth, dev, count=256):
     # one read of each factor in the single pass, two in the two-pass form).
     two_pass_bytes = sum(2 * S.N * S.n * 4 + 3 * S.m * S.n * 8 for S in systems)
     if single:
-        # The batch cuts every block into row tiles of up to 64 rows, one partial
-        # row each.
-        per_update = 0
+        # A batch of k = 1 systems alone cuts every block into row tiles of up
+        # to 256 rows, one partial row each (the launch's item count is the
+        # number of tiles).
+        per_update, ntiles = 0, 0
         for S in systems:
-            tiles = int(sum(-(-int(q) // 64) for q in np.diff(S.off)))
+            tiles = int(sum(-(-int(q) // 256) for q in np.diff(S.off)))
+            ntiles += tiles
             per_update += algorithmic_bytes_single(S.N, S.n, S.m, tiles)[2]
+        if ntiles != batch.launch()["items_a"]:
+            raise RuntimeError(f"tile count {ntiles} differs from the batch's "
+                               f"{batch.launch()['items_a']} items")
     else:
         per_update = two_pass_bytes
     T = 20

@@ -262,7 +262,7 @@ __device__ __attribute__((always_inline)) inline void fused_item(const BatchSys&
 }
 
 // Items (sys, row tile of the batch's tiles for that system, the tile's first
-// row, rows | block << 8): the tile's partial row, for rows up to
+// row, (rows - 1) | block << 8): the tile's partial row, for rows up to
 // kBatchFusedCols wide.  The item carries the tile so that its rows' loads
 // wait only for the item and the system's descriptor.
 __global__ __launch_bounds__(256) void k_batch_fused(const BatchSys* sys, const int4* items,
@@ -271,7 +271,7 @@ __global__ __launch_bounds__(256) void k_batch_fused(const BatchSys* sys, const 
   for (int32_t it = blockIdx.x; it < nitems; it += gridDim.x) {
     const int4 w = items[it];
     if (!active[w.x]) continue;  // uniform per workgroup
-    fused_item(sys[w.x], w.y, w.z, w.w & 0xff, static_cast<int>(static_cast<uint32_t>(w.w) >> 8), red);
+    fused_item(sys[w.x], w.y, w.z, (w.w & 0xff) + 1, static_cast<int>(static_cast<uint32_t>(w.w) >> 8), red);
   }
 }
 

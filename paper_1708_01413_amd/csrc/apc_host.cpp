@@ -2452,24 +2452,27 @@ struct BatchPlanItems {
   std::vector<int4> A, B;
   std::vector<int2> V;
   std::vector<int4> F;     // single pass (when every plan has it and rows fit):
-                           // (sys, tile, first row, rows | block << 8)
+                           // (sys, tile, first row, (rows - 1) | block << 8)
   std::vector<int2> W;
   std::vector<int4> L[2][4], L0;  // mixed batch work lists
   std::vector<BatchGemm> gemm;
   std::vector<int32_t> gemm_sys, gemm_slot;
-  // Single pass: every system's row tiles (up to kBatchTileRows rows of one
+  // Single pass: every system's row tiles (up to tile_rows rows of one
   // block) as row0[t], nrows[t], blk[t], then first[i] (m + 1), concatenated;
-  // tile_at[s] is system s's offset in that array.
+  // tile_at[s] is system s's offset in that array, tile_n[s] its tile count.
   std::vector<int32_t> tiles;
   std::vector<size_t> tile_at;
+  std::vector<int32_t> tile_n;
+  int tile_rows = 0;
   std::vector<int32_t> start;
 };
 
-// (128 rows: each item streams long enough to cover the chain of dependent
-// loads that starts it; the 256-system pass took 72 us with 64-row items,
-// 67 with 128, 65 with 256, where the mixed batch with its contraction tiles
-// balanced worse.)
-constexpr int kBatchTileRows = 128;
+// Rows per single-pass tile: each item streams long enough to cover the
+// chain of dependent loads that starts it (the 256-system pass took 72 us
+// with 64-row items, 67 with 128, 65 with 256).  Next to contraction tiles in
+// a mixed batch the shorter items balance better, so 128 there.
+constexpr int kBatchTileRows = 256;
+constexpr int kBatchTileRowsMixed = 128;
 
 // A batch updates in one pass over every factor when each plan does (k = 1
 // single-pass tiles) and every row fits the batch kernel's registers.
@@ -2542,7 +2545,11 @@ apc_status batch_items(const apc_plan* plans, int32_t count, BatchPlanItems* it)
     for (int64_t j = 0; j < P->n; j += 256) it->V.push_back(make_int2(s, static_cast<int>(j)));
     it->start.push_back(static_cast<int32_t>(it->A.size()));
   }
+  bool any_gemm = false;
+  for (int32_t s = 0; s < count; ++s) any_gemm = any_gemm || plans[s]->gemm;
   if (batch_single_pass(plans, count)) {
+    const int tr = any_gemm ? kBatchTileRowsMixed : kBatchTileRows;
+    it->tile_rows = tr;
     // (weight, item) pairs, ordered below.
     std::vector<std::pair<int64_t, int4>> fw;
     std::vector<std::pair<int64_t, int2>> ww;
@@ -2550,23 +2557,25 @@ apc_status batch_items(const apc_plan* plans, int32_t count, BatchPlanItems* it)
       const apc_plan_s* P = plans[s];
       if (P->gemm) {
         it->tile_at.push_back(it->tiles.size());
+        it->tile_n.push_back(0);
         continue;
       }
       std::vector<int32_t> r0, nr, bk, first(1, 0);
       for (int i = 0; i < P->m; ++i) {
         const int64_t p = P->off[i + 1] - P->off[i];
-        for (int64_t r = 0; r < p; r += kBatchTileRows) {
+        for (int64_t r = 0; r < p; r += tr) {
           r0.push_back(static_cast<int32_t>(P->off[i] + r));
-          nr.push_back(static_cast<int32_t>(std::min<int64_t>(kBatchTileRows, p - r)));
+          nr.push_back(static_cast<int32_t>(std::min<int64_t>(tr, p - r)));
           bk.push_back(i);
         }
         first.push_back(static_cast<int32_t>(r0.size()));
       }
       it->tile_at.push_back(it->tiles.size());
+      it->tile_n.push_back(static_cast<int32_t>(r0.size()));
       for (auto* v : {&r0, &nr, &bk, &first}) it->tiles.insert(it->tiles.end(), v->begin(), v->end());
       for (size_t t = 0; t < r0.size(); ++t)
         fw.emplace_back(static_cast<int64_t>(nr[t]) * P->L.ldc,
-                        make_int4(s, static_cast<int>(t), r0[t], nr[t] | (bk[t] << 8)));
+                        make_int4(s, static_cast<int>(t), r0[t], (nr[t] - 1) | (bk[t] << 8)));
       for (int64_t j = 0; j < P->n; j += 64)
         ww.emplace_back(static_cast<int64_t>(r0.size()) + P->m, make_int2(s, static_cast<int>(j)));
     }
@@ -2584,8 +2593,6 @@ apc_status batch_items(const apc_plan* plans, int32_t count, BatchPlanItems* it)
   // Mixed batch: the k-RHS plans' contraction tiles and epilogue chunks next
   // to the k = 1 items, one list per launch.  Contraction tiles first (they
   // take longest), then the k = 1 work.
-  bool any_gemm = false;
-  for (int32_t s = 0; s < count; ++s) any_gemm = any_gemm || plans[s]->gemm;
   if (!any_gemm) return APC_OK;
   auto item = [](int kind, int sys, int desc, int z, int w) { return make_int4(kind | (sys << 8), desc, z, w); };
   for (int32_t s = 0; s < count; ++s) {
@@ -2811,11 +2818,9 @@ apc_status apc_batch_create(apc_batch* out, const apc_plan* plans, int32_t count
     d.bnorm = P->bnorm;
     if (B->fused && !P->gemm) {
       // The plan's partial-row slice holds at least one FP64 row per 16 rows
-      // of a block, so one FP32 row per tile of up to 128 rows fits.
+      // of a block, so one FP32 row per tile of 128 or more rows fits.
       const int32_t* tl = reinterpret_cast<const int32_t*>(B->ws + L.T) + it.tile_at[s];
-      int32_t nt = 0;
-      for (int i = 0; i < P->m; ++i)
-        nt += static_cast<int32_t>((P->off[i + 1] - P->off[i] + kBatchTileRows - 1) / kBatchTileRows);
+      const int32_t nt = it.tile_n[s];
       d.tiles = tl;
       d.tile_first = tl + 3 * nt;
       d.ntiles = nt;

@@ -217,6 +217,52 @@ def test_batch_single_pass_matches_two_pass_and_oracle(monkeypatch):
     b2.close()
 
 
+def test_batch_single_pass_blocks_over_several_tiles(monkeypatch):
+    """Tall systems whose blocks span several single-pass row tiles (a tile holds up to
+    256 rows of one block): blocks of 1, 255, 256, 257, 520 and 700 rows, rows of 700
+    and 1024 columns (two and four 16-byte chunks per lane).  The batch's one pass
+    follows the oracle to the FP32 bar and the two-pass batch to FP32 rounding."""
+    apc = _apc()
+    torch = _torch()
+    systems = [
+        synth.gaussian_system(1400, 700, sizes=[520, 257, 256, 1, 366], seed=91,
+                              shift=2.0, scale=1.0 / math.sqrt(700)),
+        synth.gaussian_system(1279, 1024, sizes=[700, 324, 255], seed=92,
+                              shift=2.0, scale=1.0 / math.sqrt(1024)),
+        synth.many_small_systems(count=1, seed=93, lo=300, hi=400)[0],
+    ]
+    stream = torch.cuda.Stream()
+    p1, k1 = _plans(systems, stream)
+    b1 = apc.Batch(p1)
+    monkeypatch.setenv("APC_FUSED", "0")
+    p2, k2 = _plans(systems, stream)
+    b2 = apc.Batch(p2)
+    monkeypatch.delenv("APC_FUSED")
+    l1, l2 = b1.launch(), b2.launch()
+    tiles = sum(-(-int(q) // 256) for S in systems for q in np.diff(S.off))
+    say(f"case: batch single pass over multi-tile blocks {l1}, two passes {l2}, "
+        f"tiles {tiles}")
+    assert l1["items_b"] == 0 and l1["items_a"] == tiles and l2["items_b"] > 0
+    T = 25
+    b1.iterate(T, graph=True)
+    b2.iterate(T)
+    stream.synchronize()
+    worst_o, worst_2 = 0.0, 0.0
+    for S, p, q in zip(systems, p1, p2):
+        g, e = p.params()["gamma"], p.params()["eta"]
+        ref = O.apc_run(S.A, S.B, S.off, T, g, e)["xbar"][:, 0]
+        x = p.xbar().cpu().numpy()
+        xs = np.max(np.abs(S.xstar))
+        # element by element, relative to the largest entry of x*
+        worst_o = max(worst_o, np.max(np.abs(x - ref)) / xs)
+        worst_2 = max(worst_2, np.max(np.abs(x - q.xbar().cpu().numpy())) / xs)
+    say(f"max element dev vs oracle {worst_o:.2e}, vs two-pass batch {worst_2:.2e}")
+    assert worst_o <= TOL["f32"]
+    assert worst_2 <= 1e-6
+    b1.close()
+    b2.close()
+
+
 def test_batch_with_wide_rows_takes_two_passes():
     """A system with rows wider than 1024 puts the whole batch on the two-pass kernels."""
     apc = _apc()
