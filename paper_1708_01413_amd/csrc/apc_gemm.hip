@@ -656,14 +656,18 @@ __device__ inline int xcd_contiguous(int b, int total) {
 // registers while the current one is multiplied.  Row tiles entirely above
 // the chunk's diagonal are skipped; a wave takes the 16-row tiles w and 7 - w
 // of the 128 (not 32 contiguous rows), so every wave skips as many.  The LDS row stride (144 doubles, 1152
-// bytes) puts the two half-waves of a fragment read on different banks.
-constexpr int kTT = 128;
+// bytes) puts the two half-waves of a fragment read on different banks.  The
+// launch bounds ask for four waves per SIMD (at most 128 registers), which the
+// optional row sums after the product would otherwise exceed.
+constexpr int kTT = kTrmmTile;
 constexpr int kTK = 32;
 constexpr int kTS = kTT + 16;
-__global__ __launch_bounds__(512, 2) void k_trmm_lds(const double* In, double* Out, int64_t ldc,
+__global__ __launch_bounds__(512, 4) void k_trmm_lds(const double* In, double* Out, int64_t ldc,
                                                   const int64_t* off, int32_t m, int32_t nrt,
                                                   int32_t nct, const int64_t* goff,
-                                                  const double* Linv, float* Out32) {
+                                                  const double* Linv, float* Out32,
+                                                  const double* cx, const double* cy,
+                                                  const int64_t* toff, double* tpart) {
   const int total = m * nrt * nct;
   const int q = xcd_contiguous(static_cast<int>(blockIdx.x), total);
   if (q >= total) return;
@@ -767,6 +771,48 @@ __global__ __launch_bounds__(512, 2) void k_trmm_lds(const double* In, double* O
           if (Out32) Out32[o] = static_cast<float>(acc[t][u][qq]);
         }
       }
+  if (!tpart) return;  // uniform per workgroup
+  // Row sums of the tile for the vectors given: each lane weights its eight
+  // rows (rows past the block have zero products and weight 0), the four lane
+  // groups of a column are added by shuffles, the four row-pair waves of a
+  // column half in LDS, in wave order.  As is free: every wave has passed the
+  // loop's last barrier.
+  double* red = &As[0][0];  // [2 vectors][4 waves][kTT columns]
+  const int64_t T = toff[m];
+#pragma unroll
+  for (int v = 0; v < 2; ++v) {
+    const double* cv = v == 0 ? cx : cy;
+    if (!cv) continue;  // uniform
+    double wgt[2][4];
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+#pragma unroll
+      for (int qq = 0; qq < 4; ++qq) {
+        const int row = R0 + tr16[t] * 16 + g + 4 * qq;
+        const double c = cv[r0 + min(row, p - 1)];
+        wgt[t][qq] = row < p ? c : 0.0;
+      }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      double sum = 0.0;
+#pragma unroll
+      for (int t = 0; t < 2; ++t)
+#pragma unroll
+        for (int qq = 0; qq < 4; ++qq) sum = fma(wgt[t][qq], acc[t][u][qq], sum);
+      sum += __shfl_xor(sum, 16);
+      sum += __shfl_xor(sum, 32);
+      if (g == 0) red[(v * 4 + wr) * kTT + wc * 64 + u * 16 + li] = sum;
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x < 2 * kTT) {
+    const int v = threadIdx.x / kTT, c = threadIdx.x % kTT;
+    if ((v == 0 ? cx : cy) && C0 + c < ldc) {
+      const double* rv = red + v * 4 * kTT + c;
+      const double sum = (rv[0] + rv[kTT]) + (rv[2 * kTT] + rv[3 * kTT]);
+      tpart[(v * T + toff[blk] + rt) * ldc + C0 + c] = sum;
+    }
+  }
 }
 
 // G_i = C_i C_i^T as 64 x 64 tiles (ta >= tb) on the FP64 matrix cores with
@@ -864,6 +910,19 @@ __global__ __launch_bounds__(512) void k_gram_lds(const double* C, int64_t ldc,
     }
 }
 
+// Per-block sums of the triangular product's row-tile sums, in tile order.
+__global__ __launch_bounds__(256) void k_tile_sum(const double* part, const int64_t* toff,
+                                                 int32_t m, int64_t ldc, double* out,
+                                                 int64_t ldo) {
+  const int64_t c = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+  if (c >= ldc) return;
+  for (int32_t i = blockIdx.y; i < m; i += gridDim.y) {
+    double v = 0.0;
+    for (int64_t t = toff[i]; t < toff[i + 1]; ++t) v += part[t * ldc + c];
+    out[static_cast<int64_t>(i) * ldo + c] = v;
+  }
+}
+
 // G += part[0] + part[1] + ... (split s > 0 at part + (s - 1) pstride), in
 // split order, so the sum does not depend on scheduling.
 __global__ __launch_bounds__(256) void k_gram_split_sum(double* G, const double* part,
@@ -902,15 +961,28 @@ hipError_t launch_gram_lds(const double* C, int64_t ldc, const int64_t* off,
 
 hipError_t launch_trmm_lds(const double* In, double* Out, int64_t ldc, const int64_t* off,
                            int32_t m, int64_t pmax, const int64_t* goff, const double* Linv,
-                           float* out32, hipStream_t s) {
+                           float* out32, const double* cx, const double* cy, const int64_t* toff,
+                           double* tpart, hipStream_t s) {
   if (m <= 0) return hipSuccess;
   if (ldc % 64 != 0) return hipErrorInvalidValue;
+  if (tpart && (!toff || (!cx && !cy))) return hipErrorInvalidValue;
   const int64_t nrt = (pmax + kTT - 1) / kTT, nct = (ldc + kTT - 1) / kTT;
   const int64_t items = static_cast<int64_t>(m) * nrt * nct;
   if (items > std::numeric_limits<int32_t>::max() / 2) return hipErrorInvalidValue;
   const unsigned grid = static_cast<unsigned>((items + kXcds - 1) / kXcds * kXcds);
   k_trmm_lds<<<grid, 512, 0, s>>>(In, Out, ldc, off, m, static_cast<int32_t>(nrt),
-                                  static_cast<int32_t>(nct), goff, Linv, out32);
+                                  static_cast<int32_t>(nct), goff, Linv, out32, cx, cy, toff,
+                                  tpart);
+  return hipGetLastError();
+}
+
+hipError_t launch_tile_sum(const double* part, const int64_t* toff, int32_t m, int64_t ldc,
+                           double* out, int64_t ldo, hipStream_t s) {
+  if (m <= 0 || ldc <= 0) return hipSuccess;
+  const int64_t gx = (ldc + 255) / 256;
+  if (gx > std::numeric_limits<int32_t>::max()) return hipErrorInvalidValue;
+  const dim3 grid(static_cast<unsigned>(gx), static_cast<unsigned>(std::min<int32_t>(m, 65535)));
+  k_tile_sum<<<grid, 256, 0, s>>>(part, toff, m, ldc, out, ldo);
   return hipGetLastError();
 }
 

@@ -73,6 +73,7 @@ struct Layout {
   size_t Cq, CqT, C64T, C32T, Apad, yq, Wq, tnpart, x0, ys, c64p, Xs, Rb, cw, Linv2, ssq;
   size_t C64p, yref, uref, W64;  // FP64 anchor of the FP32 / bf16 k-RHS iteration
   size_t C64a, C64b, C32, x, xbar, dv, w, ca, cb, Y, vtmp, V, h, alpha, beta, G, Linv, flags, scal, partial, tiles_a, tiles_g, tiles_t, doff, goff, total;
+  size_t toff, tpart;  // triangular product's row-tile sums (setup)
   size_t xch, rsync;  // single-launch k = 1 path: exchange buffer, epoch and time-out words
 };
 
@@ -81,6 +82,7 @@ struct Tiles {
   std::vector<int32_t> g;                        // Gram tiles (blk, ta, tb), ta >= tb
   std::vector<int32_t> t;                        // TRMM tiles (blk, ta, tc)
   std::vector<int64_t> goff;                     // offset of G_i in the packed Gram storage
+  std::vector<int64_t> toff;                     // triangular-product row tiles before block i (m+1)
   std::vector<int32_t> f_row0, f_nrows, f_blk;  // single-pass row tiles (k = 1)
   std::vector<int32_t> f_first;                 // first single-pass tile of every block (m+1)
 };
@@ -142,6 +144,9 @@ void build_tiles(const int64_t* off, int32_t m, int64_t ldc, int rows_per_tile, 
     T->goff.push_back(g);
     g += p * p;
   }
+  T->toff.assign(1, 0);
+  for (int i = 0; i < m; ++i)
+    T->toff.push_back(T->toff.back() + (off[i + 1] - off[i] + kTrmmTile - 1) / kTrmmTile);
 }
 
 // k > 1 (and the mixed-precision mode) run the (y, x_bar) form on the matrix
@@ -267,6 +272,10 @@ Layout make_layout(int64_t N, int64_t n, const int64_t* off, int32_t m, int32_t 
   L.tiles_t = take(3 * static_cast<int64_t>(L.ntiles_t) * 4);
   L.doff = take((m + 1) * 8);
   L.goff = take(m * 8);
+  // The triangular product's row-tile sums (two N-vectors' worth: the start
+  // x_i(0) = C_i^T c_i and the orthogonality estimate's C_i^T y_i).
+  L.toff = take((m + 1) * 8);
+  L.tpart = take(2 * T.toff.back() * L.ldc * 8);
   {
     int rpw = 0, cpl = 0;
     const bool res = resident_candidate(off, m, L.ldc, k, flags, &rpw, &cpl);
@@ -422,6 +431,7 @@ struct apc_plan_s {
   int32_t passa_nt = 1;                // k = 1 pass A: non-temporal loads of C
   bool fused = false;                  // k = 1: both halves of eq. (2a) in one pass over C
   int32_t fused_rows = 0, fused_g = 0, ntiles_f = 0;
+  int64_t ntiles_tr = 0;               // triangular-product row tiles over all blocks
   int32_t fused_tpb = 0;               // > 0: every block has this many single-pass tiles
   bool resident = false;               // k = 1 FP64: T updates in one launch (k_resident)
   int32_t res_rpw = 0, res_cpl = 0, res_stride = 1;
@@ -589,6 +599,8 @@ apc_status rowdot64(apc_plan_s* P, const double* va, const double* vb, int64_t l
 // copy of A's slice (k-RHS plans, before setup fills it), plus w.  flags (4
 // ints) and scal (2 doubles), when non-null, are read back from the plan's
 // slices in the same synchronisation.
+apc_status read_defect(apc_plan_s* P, const double* out, double* defect, int* flags,
+                       double* scal);
 apc_status orthogonality_defect(apc_plan_s* P, const double* C, double* defect, int* flags = nullptr,
                                 double* scal = nullptr) {
   const Layout& L = P->L;
@@ -619,6 +631,36 @@ apc_status orthogonality_defect(apc_plan_s* P, const double* C, double* defect, 
     ST_TRY(expand_blocks(P, out, V, -1.0, 0.0, C));
   }
   HIP_TRY(launch_defect(U, V, L.ldc, P->m, P->n, out, st));
+  return read_defect(P, out, defect, flags, scal);
+}
+
+// The same estimate from the other side, when the triangular product that
+// wrote C also left the row-tile sums of C_i^T y_i for a random N-vector y
+// (row toff[m] + t of the tpart slice): s_i = C_i^T y_i, then one row-dot
+// pass w = -C s, and C_i C_i^T y_i - y_i = -(w_i + y_i), so
+// ||w_i + y_i|| / ||y_i|| estimates ||E_i|| within the same factor.  One pass
+// over C instead of two; y sits at w + N, the norms at w + 2 N.
+apc_status orthogonality_defect_rows(apc_plan_s* P, const double* C, const double* y,
+                                     double* defect, int* flags, double* scal) {
+  const Layout& L = P->L;
+  hipStream_t st = P->stream;
+  double* U = P->at<double>(L.Y);
+  double* out = P->at<double>(L.w);
+  double* h = out + 2 * P->N;
+  const int64_t* toff = P->at<int64_t>(L.toff);
+  const int64_t ntt = P->ntiles_tr;
+  HIP_TRY(launch_tile_sum(P->at<double>(L.tpart) + ntt * L.ldc, toff, P->m, L.ldc, U, L.ldc, st));
+  ST_TRY(rowdot64(P, nullptr, U, L.ldc, out, C));
+  HIP_TRY(launch_defect_rows(out, y, P->doff(), P->m, h, st));
+  return read_defect(P, h, defect, flags, scal);
+}
+
+// Reads the per-block norms (and flags, scal) back in one synchronisation;
+// defect = max_i sqrt(h[2 i] / h[2 i + 1]).
+apc_status read_defect(apc_plan_s* P, const double* out, double* defect, int* flags,
+                       double* scal) {
+  const Layout& L = P->L;
+  hipStream_t st = P->stream;
   const size_t nh = 2 * static_cast<size_t>(P->m);
   // (sized for the Lanczos coefficients too, which come next)
   ST_TRY(pinned_at_least(P, std::max<size_t>(nh + 4, 2 * static_cast<size_t>(L.kmax + 1))));
@@ -1382,6 +1424,7 @@ apc_status setup_impl(apc_plan_s* P, const Tiles& T) {
   HIP_TRY(hipMemcpyAsync(P->at<int32_t>(L.tiles_t), T.t.data(), T.t.size() * 4, hipMemcpyHostToDevice, st));
   HIP_TRY(hipMemcpyAsync(P->doff(), P->off.data(), (m + 1) * 8, hipMemcpyHostToDevice, st));
   HIP_TRY(hipMemcpyAsync(P->at<int64_t>(L.goff), T.goff.data(), m * 8, hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(P->at<int64_t>(L.toff), T.toff.data(), (m + 1) * 8, hipMemcpyHostToDevice, st));
   HIP_TRY(launch_fill_u32(P->at<unsigned>(L.flags), 4, 0u, st));
   HIP_TRY(launch_fill_u32(P->at<unsigned>(L.rsync), 4, 0u, st));
   if (P->resident)
@@ -1436,6 +1479,15 @@ apc_status setup_impl(apc_plan_s* P, const Tiles& T) {
   double scal[2] = {0, 0};
   bool have_flags = false;  // read with the orthogonality estimate
   if (const char* e = std::getenv("APC_QR_PASSES")) may_skip = may_skip && std::atoi(e) != 2;
+  // On the matrix-core path the triangular product also sums its rows: the
+  // k = 1 start x_i(0) = C_i^T c_i (each pass; the last one's is used) and,
+  // in a first pass that may be the only one, C_i^T y_i for the orthogonality
+  // estimate's random N-vector y (the splitmix64 vector of the Lanczos start,
+  // normalised; the estimate is a ratio), so that neither needs a pass of its
+  // own over the factor.
+  const bool x0_rows = mfma && !P->gemm && P->k == 1;
+  double* yv = P->at<double>(L.w) + N;
+  if (mfma && may_skip) HIP_TRY(launch_lanczos_start(0x0a7ull * 1000003ull, N, N, yv, nullptr, st));
   for (int pass = 0; pass < 2; ++pass) {
     const double* src = pass == 0 ? (in_place ? P->A : Ca) : Cb;
     double* dst = pass == 0 ? Cb : Ca;
@@ -1456,14 +1508,22 @@ apc_status setup_impl(apc_plan_s* P, const Tiles& T) {
                               P->kp, 0, 1.0, st));
     // An FP32 k = 1 plan's factor copy is written by the same launch.
     float* dst32 = (P->prec == APC_F32 && !P->gemm) ? P->at<float>(L.C32) : nullptr;
-    if (mfma)
+    const bool est_rows = mfma && pass == 0 && may_skip;
+    if (mfma) {
+      const double* cx = x0_rows ? cd : nullptr;
+      const double* cy = est_rows ? yv : nullptr;
       HIP_TRY(launch_trmm_lds(src, dst, ldc, P->doff(), m, P->pmax, P->at<int64_t>(L.goff), Li,
-                              dst32, st));
-    else
+                              dst32, cx, cy, P->at<int64_t>(L.toff),
+                              cx || cy ? P->at<double>(L.tpart) : nullptr, st));
+    } else {
       HIP_TRY(launch_trmm(src, dst, ldc, P->doff(), P->at<int32_t>(L.tiles_t), L.ntiles_t,
                           P->at<int64_t>(L.goff), Li, st));
+    }
     if (pass == 0 && may_skip) {
-      ST_TRY(orthogonality_defect(P, dst, &P->qr_defect, flags, scal));
+      if (est_rows)
+        ST_TRY(orthogonality_defect_rows(P, dst, yv, &P->qr_defect, flags, scal));
+      else
+        ST_TRY(orthogonality_defect(P, dst, &P->qr_defect, flags, scal));
       if (P->qr_defect * std::sqrt(static_cast<double>(pmax)) <= 1e-10) {
         have_flags = true;
         // The factor and c stay where the first pass left them: the plan's
@@ -1549,8 +1609,12 @@ apc_status setup_impl(apc_plan_s* P, const Tiles& T) {
     ST_TRY(tn_tune(P, kTnF64, resid_args(P, P->xbar()), &P->tnR));
   } else {
     // Alg. 1 initialisation: x_i(0) = Q_i c_i (minimum-norm local solutions),
-    // x_bar(0) = (1/m) sum_i x_i(0).
-    for (int col = 0; col < P->k; ++col) {
+    // x_bar(0) = (1/m) sum_i x_i(0).  The matrix-core triangular product left
+    // x_i(0)'s row-tile sums.
+    if (x0_rows)
+      HIP_TRY(launch_tile_sum(P->at<double>(L.tpart), P->at<int64_t>(L.toff), m, ldc, P->x(),
+                              P->state_ld(), st));
+    for (int col = 0; col < (x0_rows ? 0 : P->k); ++col) {
       ExpandArgs<double> e{Ca, ldc, P->doff(), m,
                            static_cast<int32_t>((ldc + expand_slab(8) - 1) / expand_slab(8)), N,
                            ca + static_cast<int64_t>(col) * N, 1, 0,
@@ -1695,6 +1759,7 @@ apc_status apc_setup(apc_plan* out, const double* A, int64_t lda, const double* 
   P->fused_rows = fused_rows;
   P->fused_g = fused_g;
   P->ntiles_f = static_cast<int32_t>(T.f_row0.size());
+  P->ntiles_tr = T.toff.back();
   {
     // At eight or more 16-byte chunks per thread, two-row register groups
     // take every register of a wave, one workgroup per CU: tiles beyond the

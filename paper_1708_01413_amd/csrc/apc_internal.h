@@ -314,6 +314,10 @@ hipError_t launch_block_sum(const double* part, int64_t ldp, const int32_t* tile
 // stride ld (FP64).
 hipError_t launch_defect(const double* U, const double* V, int64_t ld, int32_t m, int64_t n,
                          double* out, hipStream_t s);
+// h[2 i] = sum over block i's rows r of (w[r] + y[r])^2, h[2 i + 1] = sum of
+// y[r]^2 (rows off[i] .. off[i + 1]; fixed summation order).
+hipError_t launch_defect_rows(const double* w, const double* y, const int64_t* off, int32_t m,
+                              double* h, hipStream_t s);
 // out[j] = alpha * sum over all ntiles partial rows part[t][j] (FP64), j < n.
 hipError_t launch_fused_sum(const double* part, int64_t ldp, int32_t ntiles, int64_t n,
                             double alpha, double* out, hipStream_t s);
@@ -646,13 +650,23 @@ hipError_t launch_chol_inv(const int64_t* off, const int64_t* goff, int32_t m, i
 hipError_t launch_gram_lds(const double* C, int64_t ldc, const int64_t* off,
                            const int32_t* tiles, int32_t ntiles, const int64_t* goff, double* G,
                            int32_t nsplit, double* part, int64_t pstride, hipStream_t s);
-// Out_i = Linv_i In_i on the FP64 matrix cores as 128 x 128 tiles with both
-// operands staged in LDS (ldc a multiple of 64, pmax the largest block's rows,
-// In and Out distinct).  out32 (optional, same layout as Out): the result also
-// rounded to FP32.
+// Out_i = Linv_i In_i on the FP64 matrix cores as kTrmmTile x kTrmmTile
+// tiles with both operands staged in LDS (ldc a multiple of 64, pmax the
+// largest block's rows, In and Out distinct).  out32 (optional, same layout as
+// Out): the result also rounded to FP32.  Row sums (optional, tpart non-null):
+// for an N-vector cx (and / or cy), the tile (block i, row tile t) writes
+// sum over its rows r of cx[r] Out[r][:] to row toff[i] + t of tpart (cy: row
+// toff[m] + toff[i] + t), toff[i] = the row tiles of the blocks before i;
+// launch_tile_sum adds them up per block.
+constexpr int kTrmmTile = 128;
 hipError_t launch_trmm_lds(const double* In, double* Out, int64_t ldc, const int64_t* off,
                            int32_t m, int64_t pmax, const int64_t* goff, const double* Linv,
-                           float* out32, hipStream_t s);
+                           float* out32, const double* cx, const double* cy, const int64_t* toff,
+                           double* tpart, hipStream_t s);
+// out[i * ldo + c] = sum over t in [toff[i], toff[i + 1]) of part[t * ldc + c],
+// in t order, for every block i < m and c < ldc.
+hipError_t launch_tile_sum(const double* part, const int64_t* toff, int32_t m, int64_t ldc,
+                           double* out, int64_t ldo, hipStream_t s);
 // Out_i = Linv_i In_i for every block on the vector units (tiles: (blk, ta, tc)).
 hipError_t launch_trmm(const double* In, double* Out, int64_t ldc, const int64_t* off,
                        const int32_t* tiles, int32_t ntiles, const int64_t* goff,

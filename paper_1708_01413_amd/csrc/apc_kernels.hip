@@ -660,6 +660,33 @@ __global__ __launch_bounds__(256) void k_defect(const double* U, const double* V
   }
 }
 
+// Per block: ||w_i + y_i||^2 and ||y_i||^2 over the block's rows (w = -C s
+// with s_i = C_i^T y_i, so w_i + y_i = -(C_i C_i^T - I) y_i).
+__global__ __launch_bounds__(256) void k_defect_rows(const double* w, const double* y,
+                                                     const int64_t* off, int32_t m, double* h) {
+  __shared__ double ra[4], rb[4];
+  for (int32_t i = blockIdx.x; i < m; i += gridDim.x) {
+    double a = 0.0, b = 0.0;
+    for (int64_t r = off[i] + threadIdx.x; r < off[i + 1]; r += 256) {
+      const double e = w[r] + y[r];
+      a = fma(e, e, a);
+      b = fma(y[r], y[r], b);
+    }
+    a = wave_sum(a);
+    b = wave_sum(b);
+    if ((threadIdx.x & 63) == 0) {
+      ra[threadIdx.x >> 6] = a;
+      rb[threadIdx.x >> 6] = b;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      h[2 * i] = (ra[0] + ra[1]) + (ra[2] + ra[3]);
+      h[2 * i + 1] = (rb[0] + rb[1]) + (rb[2] + rb[3]);
+    }
+    __syncthreads();
+  }
+}
+
 // ------------------------------------------------------------------ expand (FP64)
 
 // y_i = beta * y_i + alpha * sum_{r in block i} w_r C[r][:], FP64 accumulation.
@@ -1704,6 +1731,14 @@ hipError_t launch_defect(const double* U, const double* V, int64_t ld, int32_t m
                          double* out, hipStream_t s) {
   if (m <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_defect, dim3(static_cast<unsigned>(m)), dim3(256), 0, s, U, V, ld, n, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_defect_rows(const double* w, const double* y, const int64_t* off, int32_t m,
+                              double* h, hipStream_t s) {
+  if (m <= 0) return hipSuccess;
+  const unsigned grid = static_cast<unsigned>(std::min<int32_t>(m, 65536));
+  hipLaunchKernelGGL(k_defect_rows, dim3(grid), dim3(256), 0, s, w, y, off, m, h);
   return hipGetLastError();
 }
 
