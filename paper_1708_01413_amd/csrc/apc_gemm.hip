@@ -689,6 +689,14 @@ __global__ __launch_bounds__(512, 4) void k_trmm_lds(const double* In, double* O
   const int tr16[2] = {wr, 7 - wr};
   __shared__ __align__(16) double As[kTK][kTS];
   __shared__ __align__(16) double Bs[kTK][kTS];
+  // The row sums' weights for the tile's rows (0 past the block), loaded
+  // before the product so that the sums after it wait on no global load.
+  __shared__ double wts[2][kTT];
+  if (tpart && threadIdx.x < 2 * kTT) {
+    const int v = threadIdx.x / kTT, row = R0 + threadIdx.x % kTT;
+    const double* cv = v == 0 ? cx : cy;
+    wts[v][threadIdx.x % kTT] = cv && row < p ? cv[r0 + row] : 0.0;
+  }
 
   // Staging: A -- thread t takes row t / 2 and 16 consecutive k (scalar loads:
   // Linv rows have stride p, which may be odd); B -- thread t takes row t / 8
@@ -773,10 +781,10 @@ __global__ __launch_bounds__(512, 4) void k_trmm_lds(const double* In, double* O
       }
   if (!tpart) return;  // uniform per workgroup
   // Row sums of the tile for the vectors given: each lane weights its eight
-  // rows (rows past the block have zero products and weight 0), the four lane
-  // groups of a column are added by shuffles, the four row-pair waves of a
-  // column half in LDS, in wave order.  As is free: every wave has passed the
-  // loop's last barrier.
+  // rows (weights from LDS; rows past the block have zero products and
+  // weight 0), the four lane groups of a column are added by shuffles, the
+  // four row-pair waves of a column half in LDS, in wave order.  As is free:
+  // every wave has passed the loop's last barrier.
   double* red = &As[0][0];  // [2 vectors][4 waves][kTT columns]
   const int64_t T = toff[m];
 #pragma unroll
@@ -787,11 +795,7 @@ __global__ __launch_bounds__(512, 4) void k_trmm_lds(const double* In, double* O
 #pragma unroll
     for (int t = 0; t < 2; ++t)
 #pragma unroll
-      for (int qq = 0; qq < 4; ++qq) {
-        const int row = R0 + tr16[t] * 16 + g + 4 * qq;
-        const double c = cv[r0 + min(row, p - 1)];
-        wgt[t][qq] = row < p ? c : 0.0;
-      }
+      for (int qq = 0; qq < 4; ++qq) wgt[t][qq] = wts[v][tr16[t] * 16 + g + 4 * qq];
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       double sum = 0.0;
