@@ -272,10 +272,11 @@ Layout make_layout(int64_t N, int64_t n, const int64_t* off, int32_t m, int32_t 
   L.tiles_t = take(3 * static_cast<int64_t>(L.ntiles_t) * 4);
   L.doff = take((m + 1) * 8);
   L.goff = take(m * 8);
-  // The triangular product's row-tile sums (two N-vectors' worth: the start
-  // x_i(0) = C_i^T c_i and the orthogonality estimate's C_i^T y_i).
+  // The triangular product's row-tile sums (the start x_i(0) = C_i^T c_i and
+  // the orthogonality estimate's C_i^T y_i), then the estimate's random
+  // N-vector y and its per-block norms (2 m).
   L.toff = take((m + 1) * 8);
-  L.tpart = take(2 * T.toff.back() * L.ldc * 8);
+  L.tpart = take((2 * T.toff.back() * L.ldc + N + 2 * m) * 8);
   {
     int rpw = 0, cpl = 0;
     const bool res = resident_candidate(off, m, L.ldc, k, flags, &rpw, &cpl);
@@ -637,21 +638,29 @@ apc_status orthogonality_defect(apc_plan_s* P, const double* C, double* defect, 
 // The same estimate from the other side, when the triangular product that
 // wrote C also left the row-tile sums of C_i^T y_i for a random N-vector y
 // (row toff[m] + t of the tpart slice): s_i = C_i^T y_i, then one row-dot
-// pass w = -C s, and C_i C_i^T y_i - y_i = -(w_i + y_i), so
-// ||w_i + y_i|| / ||y_i|| estimates ||E_i|| within the same factor.  One pass
-// over C instead of two; y sits at w + N, the norms at w + 2 N.
-apc_status orthogonality_defect_rows(apc_plan_s* P, const double* C, const double* y,
-                                     double* defect, int* flags, double* scal) {
+// pass w = -C s (in the plan's pass-A column splits, summed in split order),
+// and C_i C_i^T y_i - y_i = -(w_i + y_i), so ||w_i + y_i|| / ||y_i||
+// estimates ||E_i|| within the same factor.  One pass over C instead of two.
+// y and the norms sit after the row sums in the tpart slice.
+double* defect_vector(apc_plan_s* P) {
+  return P->at<double>(P->L.tpart) + 2 * P->ntiles_tr * P->L.ldc;
+}
+apc_status orthogonality_defect_rows(apc_plan_s* P, const double* C, double* defect, int* flags,
+                                     double* scal) {
   const Layout& L = P->L;
   hipStream_t st = P->stream;
   double* U = P->at<double>(L.Y);
   double* out = P->at<double>(L.w);
-  double* h = out + 2 * P->N;
+  const double* y = defect_vector(P);
+  double* h = defect_vector(P) + P->N;
   const int64_t* toff = P->at<int64_t>(L.toff);
-  const int64_t ntt = P->ntiles_tr;
-  HIP_TRY(launch_tile_sum(P->at<double>(L.tpart) + ntt * L.ldc, toff, P->m, L.ldc, U, L.ldc, st));
-  ST_TRY(rowdot64(P, nullptr, U, L.ldc, out, C));
-  HIP_TRY(launch_defect_rows(out, y, P->doff(), P->m, h, st));
+  HIP_TRY(launch_tile_sum(P->at<double>(L.tpart) + P->ntiles_tr * L.ldc, toff, P->m, L.ldc, U,
+                          L.ldc, st));
+  RowdotArgs<double> a{C, L.ldc, P->ta(0), P->ta(1), P->ta(2), L.ntiles_a, 0, nullptr, U, L.ldc,
+                       nullptr, 0, out, P->N, P->nsplit, P->split_cols, P->xcd_remap,
+                       P->passa_rows, 0};
+  HIP_TRY(launch_rowdot_f64(a, st));
+  HIP_TRY(launch_defect_rows(out, P->nsplit, P->N, y, P->doff(), P->m, h, st));
   return read_defect(P, h, defect, flags, scal);
 }
 
@@ -1486,7 +1495,7 @@ apc_status setup_impl(apc_plan_s* P, const Tiles& T) {
   // normalised; the estimate is a ratio), so that neither needs a pass of its
   // own over the factor.
   const bool x0_rows = mfma && !P->gemm && P->k == 1;
-  double* yv = P->at<double>(L.w) + N;
+  double* yv = defect_vector(P);
   if (mfma && may_skip) HIP_TRY(launch_lanczos_start(0x0a7ull * 1000003ull, N, N, yv, nullptr, st));
   for (int pass = 0; pass < 2; ++pass) {
     const double* src = pass == 0 ? (in_place ? P->A : Ca) : Cb;
@@ -1521,7 +1530,7 @@ apc_status setup_impl(apc_plan_s* P, const Tiles& T) {
     }
     if (pass == 0 && may_skip) {
       if (est_rows)
-        ST_TRY(orthogonality_defect_rows(P, dst, yv, &P->qr_defect, flags, scal));
+        ST_TRY(orthogonality_defect_rows(P, dst, &P->qr_defect, flags, scal));
       else
         ST_TRY(orthogonality_defect(P, dst, &P->qr_defect, flags, scal));
       if (P->qr_defect * std::sqrt(static_cast<double>(pmax)) <= 1e-10) {

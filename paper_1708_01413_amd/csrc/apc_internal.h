@@ -315,9 +315,10 @@ hipError_t launch_block_sum(const double* part, int64_t ldp, const int32_t* tile
 hipError_t launch_defect(const double* U, const double* V, int64_t ld, int32_t m, int64_t n,
                          double* out, hipStream_t s);
 // h[2 i] = sum over block i's rows r of (w[r] + y[r])^2, h[2 i + 1] = sum of
-// y[r]^2 (rows off[i] .. off[i + 1]; fixed summation order).
-hipError_t launch_defect_rows(const double* w, const double* y, const int64_t* off, int32_t m,
-                              double* h, hipStream_t s);
+// y[r]^2 (rows off[i] .. off[i + 1]), where w[r] adds the nsplit partials
+// w + s * wstride in split order (fixed summation order throughout).
+hipError_t launch_defect_rows(const double* w, int32_t nsplit, int64_t wstride, const double* y,
+                              const int64_t* off, int32_t m, double* h, hipStream_t s);
 // out[j] = alpha * sum over all ntiles partial rows part[t][j] (FP64), j < n.
 hipError_t launch_fused_sum(const double* part, int64_t ldp, int32_t ntiles, int64_t n,
                             double alpha, double* out, hipStream_t s);

@@ -660,15 +660,19 @@ __global__ __launch_bounds__(256) void k_defect(const double* U, const double* V
   }
 }
 
-// Per block: ||w_i + y_i||^2 and ||y_i||^2 over the block's rows (w = -C s
-// with s_i = C_i^T y_i, so w_i + y_i = -(C_i C_i^T - I) y_i).
-__global__ __launch_bounds__(256) void k_defect_rows(const double* w, const double* y,
+// Per block: ||w_i + y_i||^2 and ||y_i||^2 over the block's rows (w = -C s,
+// the sum of nsplit column-split partials, with s_i = C_i^T y_i, so
+// w_i + y_i = -(C_i C_i^T - I) y_i).
+__global__ __launch_bounds__(256) void k_defect_rows(const double* w, int32_t nsplit,
+                                                     int64_t wstride, const double* y,
                                                      const int64_t* off, int32_t m, double* h) {
   __shared__ double ra[4], rb[4];
   for (int32_t i = blockIdx.x; i < m; i += gridDim.x) {
     double a = 0.0, b = 0.0;
     for (int64_t r = off[i] + threadIdx.x; r < off[i + 1]; r += 256) {
-      const double e = w[r] + y[r];
+      double wr = w[r];
+      for (int32_t sp = 1; sp < nsplit; ++sp) wr += w[sp * wstride + r];
+      const double e = wr + y[r];
       a = fma(e, e, a);
       b = fma(y[r], y[r], b);
     }
@@ -1734,11 +1738,13 @@ hipError_t launch_defect(const double* U, const double* V, int64_t ld, int32_t m
   return hipGetLastError();
 }
 
-hipError_t launch_defect_rows(const double* w, const double* y, const int64_t* off, int32_t m,
-                              double* h, hipStream_t s) {
+hipError_t launch_defect_rows(const double* w, int32_t nsplit, int64_t wstride, const double* y,
+                              const int64_t* off, int32_t m, double* h, hipStream_t s) {
   if (m <= 0) return hipSuccess;
+  if (nsplit < 1) return hipErrorInvalidValue;
   const unsigned grid = static_cast<unsigned>(std::min<int32_t>(m, 65536));
-  hipLaunchKernelGGL(k_defect_rows, dim3(grid), dim3(256), 0, s, w, y, off, m, h);
+  hipLaunchKernelGGL(k_defect_rows, dim3(grid), dim3(256), 0, s, w, nsplit, wstride, y, off, m,
+                     h);
   return hipGetLastError();
 }
 
