@@ -135,6 +135,35 @@ def test_two_passes_forced_and_fp64_plans(monkeypatch):
     say(f"case: forced two passes {i32}, FP64 {i64}")
 
 
+def test_vector_unit_setup_takes_the_same_decisions(monkeypatch):
+    """The vector-unit setup (APC_SETUP_MFMA=0: its own Gram and triangular product, the
+    start by an expansion pass, the two-pass orthogonality estimate) against the
+    matrix-core one (the start and the estimate from the triangular product's row
+    sums): the same one-pass / two-pass decisions, estimates of the same order, and both
+    trajectories within the FP32 bar of the oracle."""
+    good = synth.gaussian_system(1536, 1024, 8, seed=61, scale=1 / math.sqrt(1024))
+    bad = mixed_rows(good, 5)
+    T = 30
+    for S, passes in ((good, 1), (bad, 2)):
+        ref = oracle_traj(S, T, *O.optimal_params(*O.spectrum(S.A, S.off))[:2])
+        infos = []
+        for mfma in ("1", "0"):
+            monkeypatch.setenv("APC_SETUP_MFMA", mfma)
+            plan, g, e = run(S, "f32", 0)
+            info = plan.setup_info()
+            d = dev(gpu_traj(plan, T), ref, S.xstar)
+            say(f"case: APC_SETUP_MFMA={mfma}, expected passes {passes}: {info}, max dev {d:.3e}")
+            assert info["qr_passes"] == passes
+            assert d <= TOL32
+            infos.append(info["qr_defect"])
+        monkeypatch.delenv("APC_SETUP_MFMA")
+        if passes == 1:
+            assert max(infos) < 1e-13
+        else:
+            lo, hi = min(infos), max(infos)
+            assert lo > 1e-10 / math.sqrt(192) and hi / lo < 200
+
+
 def test_restart_after_one_pass_setup():
     """apc_restart on a one-pass plan applies only the first inverse factor: a restart
     with new right-hand sides follows a fresh plan's trajectory."""
