@@ -956,21 +956,39 @@ __global__ __launch_bounds__(512) void k_chol_inv(const int64_t* off, const int6
     // A[li][g] = -P[16 I + li][k] and B[g][li] = P[16 J + li][k] and holds
     // D[g + 4 q][li]; rows past T read a clamped row and are zeroed.
     if (in_lds) {
+      // Tile t = I (I + 1) / 2 + J goes to wave t mod (waves); a wave loads
+      // the G entries of kTrail of its tiles before it multiplies any, so the
+      // loads' latencies overlap instead of adding up tile after tile.
       const int nT = (T + 15) / 16;
+      const int ntile = nT * (nT + 1) / 2;
+      const int nw = nt / 64;
       const int li = lane & 15, g = lane >> 4;
-      int tc = 0;
-      for (int I = 0; I < nT; ++I) {
-        for (int J = 0; J <= I; ++J, ++tc) {
-          if (tc % (nt / 64) != wv) continue;  // uniform per wave
-          const int col = 16 * J + li;
-          f64x4 acc;
+      constexpr int kTrail = 8;
+      for (int t0 = wv; t0 < ntile; t0 += kTrail * nw) {
+        f64x4 acc[kTrail];
+        int tI[kTrail], tJ[kTrail];
+#pragma unroll
+        for (int u = 0; u < kTrail; ++u) {
+          const int t = t0 + u * nw;
+          int I = static_cast<int>((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
+          while ((I + 1) * (I + 2) / 2 <= t) ++I;
+          while (I * (I + 1) / 2 > t) --I;
+          tI[u] = I;
+          tJ[u] = t - I * (I + 1) / 2;
+          const int col = 16 * tJ[u] + li;
 #pragma unroll
           for (int q = 0; q < 4; ++q) {
             const int row = 16 * I + g + 4 * q;
             const double v = Gb[static_cast<int64_t>(kb + nb + min(row, T - 1)) * p + kb + nb +
                                 min(col, T - 1)];
-            acc[q] = (row < T && col <= row) ? v : 0.0;
+            acc[u][q] = (t < ntile && row < T && col <= row) ? v : 0.0;
           }
+        }
+#pragma unroll
+        for (int u = 0; u < kTrail; ++u) {
+          if (t0 + u * nw >= ntile) break;  // uniform per wave
+          const int I = tI[u], J = tJ[u];
+          const int col = 16 * J + li;
           const int ra = 16 * I + li, rb = 16 * J + li;
           const int ca = min(ra, T - 1), cb = min(rb, T - 1);
 #pragma unroll
@@ -979,13 +997,13 @@ __global__ __launch_bounds__(512) void k_chol_inv(const int64_t* off, const int6
             const double av = pan[ca][k], bv = pan[cb][k];
             const double a = ra < T ? -av : 0.0;
             const double b = rb < T ? bv : 0.0;
-            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+            acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[u], 0, 0, 0);
           }
 #pragma unroll
           for (int q = 0; q < 4; ++q) {
             const int row = 16 * I + g + 4 * q;
             if (row < T && col <= row)
-              Gb[static_cast<int64_t>(kb + nb + row) * p + kb + nb + col] = acc[q];
+              Gb[static_cast<int64_t>(kb + nb + row) * p + kb + nb + col] = acc[u][q];
           }
         }
       }
