@@ -648,6 +648,9 @@ def main():
     ap.add_argument("--f32-contraction-only", action="store_true",
                     help="only the batched system (8192^2, k = 64, uneven blocks): setup and 8 "
                          "FP32 updates without anchors, for counter runs of the FP32 contraction")
+    ap.add_argument("--setup-only", action="store_true",
+                    help="only the benchmark system's setup (tall Gaussian 16384 x 8192, FP32), "
+                         "three times, for counter runs of the setup kernels")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: sharding the blocks over several GPUs (one "
@@ -679,6 +682,23 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"workload": "N=n=16384, A=G/sqrt(n)+3I, k=128, m=64, bf16 contraction",
                           "updates": 8, "launch_shapes": plan.launch_shapes()}), flush=True)
+        return
+    if args.setup_only:
+        S = synth.tall_gaussian_16k()
+        A = torch.from_numpy(S.A).to(dev)
+        b = torch.from_numpy(S.B).to(dev)
+        ws = torch.empty(apc.Plan.workspace_bytes(S.N, S.n, S.off, "f32"), dtype=torch.uint8,
+                         device=dev)
+        times = []
+        for _ in range(3):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            plan = apc.Plan(A, b, S.off, "f32", workspace=ws)
+            torch.cuda.synchronize()
+            times.append(round((time.perf_counter() - t0) * 1e3, 3))
+            plan.close()
+        print(json.dumps({"workload": "tall Gaussian N=16384 n=8192, m=64, FP32 plan setup",
+                          "setup_ms": times}), flush=True)
         return
     if args.f32_contraction_only:
         Sb = synth.shifted_uneven_8k(k=64)
