@@ -530,39 +530,50 @@ __global__ __launch_bounds__(256) void k_fused_combine(FusedCombineArgs<TD> a) {
   const TD* pp = a.part;
   double* x = a.x;
   double s = 0.0;
+  // The first two rounds' new x_i stay in registers for the differences
+  // below (m <= 64 needs no re-read); later rounds read them back.
+  double keep[2][U];
+  auto round = [&](int i0, double xo, double (&kx)[U]) {
+    double u[U], xi[U];
+#pragma unroll
+    for (int q = 0; q < U; ++q) {
+      const int i = i0 + 8 * q;
+      u[q] = 0.0;
+      xi[q] = 0.0;
+      if (i < a.m) {
+        if constexpr (TPB > 0) {
+          double v[TPB];
+#pragma unroll
+          for (int t = 0; t < TPB; ++t)
+            v[t] = static_cast<double>(pp[static_cast<int64_t>(i * TPB + t) * a.ldp + j]);
+#pragma unroll
+          for (int t = 0; t < TPB; ++t) u[q] += v[t];
+        } else {
+          for (int t = a.tile_first[i]; t < a.tile_first[i + 1]; ++t)
+            u[q] += static_cast<double>(pp[static_cast<int64_t>(t) * a.ldp + j]);
+        }
+        xi[q] = x[static_cast<int64_t>(i) * a.ldx + j];
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < U; ++q) {
+      const int i = i0 + 8 * q;
+      kx[q] = 0.0;
+      if (i < a.m) {
+        const double xn = xi[q] + a.gamma * ((xo - xi[q]) - u[q]);
+        x[static_cast<int64_t>(i) * a.ldx + j] = xn;
+        s += xn;
+        kx[q] = xn;
+      }
+    }
+  };
   if (j < a.n) {
     const double xo = a.xbar[j];
-    for (int i0 = bl; i0 < a.m; i0 += 8 * U) {
-      double u[U], xi[U];
-#pragma unroll
-      for (int q = 0; q < U; ++q) {
-        const int i = i0 + 8 * q;
-        u[q] = 0.0;
-        xi[q] = 0.0;
-        if (i < a.m) {
-          if constexpr (TPB > 0) {
-            double v[TPB];
-#pragma unroll
-            for (int t = 0; t < TPB; ++t)
-              v[t] = static_cast<double>(pp[static_cast<int64_t>(i * TPB + t) * a.ldp + j]);
-#pragma unroll
-            for (int t = 0; t < TPB; ++t) u[q] += v[t];
-          } else {
-            for (int t = a.tile_first[i]; t < a.tile_first[i + 1]; ++t)
-              u[q] += static_cast<double>(pp[static_cast<int64_t>(t) * a.ldp + j]);
-          }
-          xi[q] = x[static_cast<int64_t>(i) * a.ldx + j];
-        }
-      }
-#pragma unroll
-      for (int q = 0; q < U; ++q) {
-        const int i = i0 + 8 * q;
-        if (i < a.m) {
-          const double xn = xi[q] + a.gamma * ((xo - xi[q]) - u[q]);
-          x[static_cast<int64_t>(i) * a.ldx + j] = xn;
-          s += xn;
-        }
-      }
+    if (bl < a.m) round(bl, xo, keep[0]);
+    if (bl + 8 * U < a.m) round(bl + 8 * U, xo, keep[1]);
+    for (int i0 = bl + 16 * U; i0 < a.m; i0 += 8 * U) {
+      double tmp[U];
+      round(i0, xo, tmp);
     }
   }
   part[bl][lane] = s;
@@ -577,7 +588,15 @@ __global__ __launch_bounds__(256) void k_fused_combine(FusedCombineArgs<TD> a) {
   __syncthreads();
   if (j < a.n) {
     const double v = xb[lane];
-    for (int i0 = bl; i0 < a.m; i0 += 8 * U) {
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+#pragma unroll
+      for (int q = 0; q < U; ++q) {
+        const int i = bl + 8 * U * r + 8 * q;
+        if (i < a.m) a.d[static_cast<int64_t>(i) * a.ldd + j] = static_cast<TD>(v - keep[r][q]);
+      }
+    }
+    for (int i0 = bl + 16 * U; i0 < a.m; i0 += 8 * U) {
       double xi[U];
 #pragma unroll
       for (int q = 0; q < U; ++q) {
