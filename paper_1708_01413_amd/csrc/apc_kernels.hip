@@ -521,7 +521,7 @@ __global__ __launch_bounds__(kThreads) void k_fused(FusedArgs<TQ, TA> a) {
 // sum a block's partials in tile order.
 template <typename TD, int TPB>
 __global__ __launch_bounds__(256) void k_fused_combine(FusedCombineArgs<TD> a) {
-  constexpr int U = 4;
+  constexpr int U = 8;
   __shared__ double part[8][32];
   __shared__ double xb[32];
   const int lane = threadIdx.x & 31;
@@ -531,7 +531,7 @@ __global__ __launch_bounds__(256) void k_fused_combine(FusedCombineArgs<TD> a) {
   double* x = a.x;
   double s = 0.0;
   // The first two rounds' new x_i stay in registers for the differences
-  // below (m <= 64 needs no re-read); later rounds read them back.
+  // below (m <= 128 needs no re-read); later rounds read them back.
   double keep[2][U];
   auto round = [&](int i0, double xo, double (&kx)[U]) {
     double u[U], xi[U];
