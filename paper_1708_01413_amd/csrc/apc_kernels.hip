@@ -514,30 +514,35 @@ __global__ __launch_bounds__(kThreads) void k_fused(FusedArgs<TQ, TA> a) {
 }
 
 // The x_i update, the average and the next differences after k_fused.  A
-// workgroup owns 32 columns; its 8 lanes per column take every eighth block,
-// U blocks at a time with all their loads issued before any store.  TPB > 0:
-// every block has exactly TPB tiles (tile t of block i is i TPB + t), so a
-// block's partials are loaded together; TPB = 0 reads the tile ranges.  Both
-// sum a block's partials in tile order.
+// workgroup owns kCombineCols = 16 columns; its 16 lanes per column take every
+// sixteenth block, U blocks at a time with all their loads issued before any
+// store.  16 columns rather than 32 give twice the workgroups, two waves per
+// SIMD at 16384 x 8192 (5.8 -> 5.3 us there; 8 columns, with 32-byte pieces
+// of the partial rows per load, took 9.1).  TPB > 0: every block has exactly
+// TPB tiles (tile t of block i is i TPB + t), so a block's partials are
+// loaded together; TPB = 0 reads the tile ranges.  Both sum a block's
+// partials in tile order.
+constexpr int kCombineCols = 16;
 template <typename TD, int TPB>
 __global__ __launch_bounds__(256) void k_fused_combine(FusedCombineArgs<TD> a) {
-  constexpr int U = 8;
-  __shared__ double part[8][32];
-  __shared__ double xb[32];
-  const int lane = threadIdx.x & 31;
-  const int bl = threadIdx.x >> 5;
-  const int64_t j = static_cast<int64_t>(blockIdx.x) * 32 + lane;
+  constexpr int U = 4;
+  constexpr int CL = kCombineCols, BL = 256 / kCombineCols;
+  __shared__ double part[BL][CL];
+  __shared__ double xb[CL];
+  const int lane = threadIdx.x % CL;
+  const int bl = threadIdx.x / CL;
+  const int64_t j = static_cast<int64_t>(blockIdx.x) * CL + lane;
   const TD* pp = a.part;
   double* x = a.x;
   double s = 0.0;
   // The first two rounds' new x_i stay in registers for the differences
-  // below (m <= 128 needs no re-read); later rounds read them back.
+  // below (m <= 2 BL U = 128 needs no re-read); later rounds read them back.
   double keep[2][U];
   auto round = [&](int i0, double xo, double (&kx)[U]) {
     double u[U], xi[U];
 #pragma unroll
     for (int q = 0; q < U; ++q) {
-      const int i = i0 + 8 * q;
+      const int i = i0 + BL * q;
       u[q] = 0.0;
       xi[q] = 0.0;
       if (i < a.m) {
@@ -557,7 +562,7 @@ __global__ __launch_bounds__(256) void k_fused_combine(FusedCombineArgs<TD> a) {
     }
 #pragma unroll
     for (int q = 0; q < U; ++q) {
-      const int i = i0 + 8 * q;
+      const int i = i0 + BL * q;
       kx[q] = 0.0;
       if (i < a.m) {
         const double xn = xi[q] + a.gamma * ((xo - xi[q]) - u[q]);
@@ -570,8 +575,8 @@ __global__ __launch_bounds__(256) void k_fused_combine(FusedCombineArgs<TD> a) {
   if (j < a.n) {
     const double xo = a.xbar[j];
     if (bl < a.m) round(bl, xo, keep[0]);
-    if (bl + 8 * U < a.m) round(bl + 8 * U, xo, keep[1]);
-    for (int i0 = bl + 16 * U; i0 < a.m; i0 += 8 * U) {
+    if (bl + BL * U < a.m) round(bl + BL * U, xo, keep[1]);
+    for (int i0 = bl + 2 * BL * U; i0 < a.m; i0 += BL * U) {
       double tmp[U];
       round(i0, xo, tmp);
     }
@@ -579,8 +584,9 @@ __global__ __launch_bounds__(256) void k_fused_combine(FusedCombineArgs<TD> a) {
   part[bl][lane] = s;
   __syncthreads();
   if (bl == 0 && j < a.n) {
-    const double tot = ((part[0][lane] + part[1][lane]) + (part[2][lane] + part[3][lane])) +
-                       ((part[4][lane] + part[5][lane]) + (part[6][lane] + part[7][lane]));
+    double tot = part[0][lane];
+#pragma unroll
+    for (int b = 1; b < BL; ++b) tot += part[b][lane];  // block-lane order
     const double v = a.beta == 0.0 ? a.alpha * tot : a.alpha * tot + a.beta * a.xbar[j];
     a.xbar[j] = v;
     xb[lane] = v;
@@ -592,20 +598,20 @@ __global__ __launch_bounds__(256) void k_fused_combine(FusedCombineArgs<TD> a) {
     for (int r = 0; r < 2; ++r) {
 #pragma unroll
       for (int q = 0; q < U; ++q) {
-        const int i = bl + 8 * U * r + 8 * q;
+        const int i = bl + BL * U * r + BL * q;
         if (i < a.m) a.d[static_cast<int64_t>(i) * a.ldd + j] = static_cast<TD>(v - keep[r][q]);
       }
     }
-    for (int i0 = bl + 16 * U; i0 < a.m; i0 += 8 * U) {
+    for (int i0 = bl + 2 * BL * U; i0 < a.m; i0 += BL * U) {
       double xi[U];
 #pragma unroll
       for (int q = 0; q < U; ++q) {
-        const int i = i0 + 8 * q;
+        const int i = i0 + BL * q;
         xi[q] = i < a.m ? x[static_cast<int64_t>(i) * a.ldx + j] : 0.0;
       }
 #pragma unroll
       for (int q = 0; q < U; ++q) {
-        const int i = i0 + 8 * q;
+        const int i = i0 + BL * q;
         if (i < a.m) a.d[static_cast<int64_t>(i) * a.ldd + j] = static_cast<TD>(v - xi[q]);
       }
     }
@@ -1800,7 +1806,7 @@ hipError_t launch_fused_sum_f32(const float* part, int64_t ldp, int32_t ntiles, 
 
 template <typename TD>
 static hipError_t fused_combine_impl(const FusedCombineArgs<TD>& a, hipStream_t s) {
-  const dim3 grid(grid_for(a.n, 32));
+  const dim3 grid(grid_for(a.n, kCombineCols));
   switch (a.tpb) {
     case 1: APC_LAUNCH((k_fused_combine<TD, 1>), grid, dim3(256), 0, s, a); break;
     case 2: APC_LAUNCH((k_fused_combine<TD, 2>), grid, dim3(256), 0, s, a); break;
