@@ -245,6 +245,28 @@ def test_single_row_blocks(prec):
     assert rel_dev(gpu_traj(plan, 40), ref, S.xstar) <= TOL[prec]
 
 
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("m", [129, 200, 260])
+def test_many_blocks_single_pass(prec, m):
+    """More blocks than the combine keeps in registers (a lane holds its first
+    2 x 4 blocks' new x_i, 16 lanes per column: m <= 128 needs no read-back), so the
+    later blocks' differences take the read-back path; blocks of 1 to 4 rows."""
+    apc = _apc()
+    rng = np.random.default_rng(40 + m)
+    sizes = [int(v) for v in rng.integers(1, 5, size=m)]
+    N = sum(sizes)
+    n = N - 20  # tall: X has full rank
+    S = synth.gaussian_system(N, n, sizes=sizes, seed=41 + m, shift=2.0, scale=1 / math.sqrt(n))
+    say(f"case: many blocks {prec} m={m} N={N} n={n}")
+    g, e, _ = O.optimal_params(*O.spectrum(S.A, S.off))
+    ref, _ = oracle_traj(S, 30, g, e)
+    A, b = upload(S)
+    plan = apc.Plan(A, b, S.off, prec, gamma=g, eta=e)
+    d = rel_dev(gpu_traj(plan, 30), ref, S.xstar)
+    say(f"max dev {d:.3e}")
+    assert d <= TOL[prec]
+
+
 @pytest.mark.parametrize("N,n,m", [(64, 64, 1), (128, 64, 2), (3, 1, 3)])
 def test_full_blocks_converge_in_one_step(N, n, m):
     """Every p_i = n: X = I, so gamma* = eta* = 1 and x_bar(1) = x* (Theorem 1).  Also
